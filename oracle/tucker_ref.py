@@ -1,0 +1,516 @@
+"""Plain FP64 CPU oracle for the ridge-leverage-score-sampled Tucker core update.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or link
+this module: only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` use it.  It shares no code with the HIP library.
+
+Conventions (the paper's elementwise Tucker model, eq.
+tucker_decomposition_elementwise in Sec. 2, is order-free; the paper's ``vec``
+stacks columns first, which would pair with the reversed Kronecker order, so the
+elementwise definition decides):
+
+* Tensors are row-major (C order): X[i1, ..., iN] with iN fastest.
+* The core G is R1 x ... x RN row-major, vec(G) is its C-order flattening.
+* Factor A(n) is In x Rn row-major.
+* The design row of multi-index i is k_i = a(1)[i1,:] (x) ... (x) a(N)[iN,:]
+  (row-major Kronecker), so K = A(1) (x) ... (x) A(N) and K vec(G) = vec(Xhat).
+
+Every routine works in float64 (uint64 for the integer sampling tables).
+Inputs of lower precision are converted exactly to float64 first.
+"""
+import math
+
+import numpy as np
+
+from .philox import philox4x64, mulhi64
+
+#: Fixed-point bits of the integer sampling weights w_i = ceil(l_i * 2^Q).
+Q_BITS = 24
+
+
+# --------------------------------------------------------------------------
+# Tensor algebra (Sec. 2, "Tensor Products")
+# --------------------------------------------------------------------------
+
+def mode_product(T, M, n):
+    """n-mode product T x_n M for M of shape (J, I_n) (Sec. 2, elementwise form)."""
+    out = np.tensordot(M, T, axes=([1], [n]))  # J first
+    return np.moveaxis(out, 0, n)
+
+
+def unfold(T, n):
+    """Mode-n unfolding, columns ordered row-major over the remaining modes."""
+    return np.moveaxis(T, n, 0).reshape(T.shape[n], -1)
+
+
+def reconstruct(G, factors):
+    """Xhat = G x_1 A(1) x_2 ... x_N A(N) (Sec. 2, Tucker decomposition)."""
+    T = np.asarray(G, dtype=np.float64)
+    for n, A in enumerate(factors):
+        T = mode_product(T, np.asarray(A, dtype=np.float64), n)
+    return T
+
+
+def kron_matrix(factors):
+    """Explicit K = A(1) (x) ... (x) A(N) (tiny shapes only)."""
+    K = np.ones((1, 1))
+    for A in factors:
+        K = np.kron(K, np.asarray(A, dtype=np.float64))
+    return K
+
+
+def kron_rows(factors, idx):
+    """Rows k_t of K for multi-indices idx[:, t], formed from factor rows only.
+
+    This is the implicit design-matrix query of Alg. 3 (initialise a structure
+    that answers entries of K without forming it): row t is the Kronecker
+    product of the sampled factor rows, in mode order.
+    """
+    idx = np.asarray(idx)
+    s = idx.shape[1]
+    rows = np.ones((s, 1))
+    for n, A in enumerate(factors):
+        a = np.asarray(A, dtype=np.float64)[idx[n]]
+        rows = (rows[:, :, None] * a[:, None, :]).reshape(s, -1)
+    return rows
+
+
+def flat_index(idx, dims):
+    """Row-major linear offsets of the multi-indices idx[:, t]."""
+    return np.ravel_multi_index(tuple(np.asarray(idx, dtype=np.int64)), dims)
+
+
+def mask_lookup(mask_words, flat):
+    """Observed flags of linear offsets from an LSB-first uint32 bit mask."""
+    words = np.asarray(mask_words, dtype=np.uint32)[flat >> 5]
+    return ((words >> (flat & 31).astype(np.uint32)) & 1).astype(bool)
+
+
+def unpack_mask(mask_words, dims):
+    """Dense boolean observed-mask from LSB-first uint32 words."""
+    n = int(np.prod(dims))
+    return mask_lookup(mask_words, np.arange(n, dtype=np.int64)).reshape(dims)
+
+
+# --------------------------------------------------------------------------
+# Ridge leverage scores (Sec. 2, eqs. ridge_leverage_score_def,
+# ridge_leverage_score_svd_def, d_eff_def)
+# --------------------------------------------------------------------------
+
+def ridge_leverage_scores(A, lam=0.0):
+    """l_i^lam(A) = a_i (A^T A + lam I)^+ a_i^T, the definition written out."""
+    A = np.asarray(A, dtype=np.float64)
+    M = np.linalg.pinv(A.T @ A + lam * np.eye(A.shape[1]), hermitian=True)
+    return np.einsum("ij,jk,ik->i", A, M, A)
+
+
+def leverage_scores(A):
+    """Statistical leverage scores: the ridge scores at lam = 0 (Sec. 2)."""
+    return ridge_leverage_scores(A, 0.0)
+
+
+def cross_ridge_scores(A, lam=0.0):
+    """Matrix of cross ridge scores A (A^T A + lam I)^+ A^T (Sec. 2)."""
+    A = np.asarray(A, dtype=np.float64)
+    M = np.linalg.pinv(A.T @ A + lam * np.eye(A.shape[1]), hermitian=True)
+    return A @ M @ A.T
+
+
+def ridge_scores_svd(A, lam=0.0):
+    """Ridge scores from the compact SVD: sum_k s_k^2/(s_k^2+lam) u_ik^2."""
+    A = np.asarray(A, dtype=np.float64)
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    tol = max(A.shape) * np.finfo(np.float64).eps * (s[0] if s.size else 0.0)
+    keep = s > tol
+    U, s = U[:, keep], s[keep]
+    f = s ** 2 / (s ** 2 + lam)
+    return (U ** 2) @ f
+
+
+def effective_dimension(A, lam):
+    """d_eff = sum_i l_i^lam(A) (eq. d_eff_def)."""
+    return float(ridge_leverage_scores(A, lam).sum())
+
+
+def is_rank_deficient(A):
+    """True if A has numerically dependent columns."""
+    A = np.asarray(A, dtype=np.float64)
+    return np.linalg.matrix_rank(A) < A.shape[1]
+
+
+# --------------------------------------------------------------------------
+# Sample count (Alg. 1, Cor. 3.3)
+# --------------------------------------------------------------------------
+
+def s_theory(d, eps, delta, beta_prime=0.5):
+    """Number of row samples of Alg. 1: ceil(4d/beta' max{420 ln(4d/delta), 1/(delta eps)}).
+
+    With the factor leverage scores as the overestimate and d'_eff = 0, Cor. 3.3
+    gives beta' = 1/2 for a full-rank design (Sec. 3).
+    """
+    return int(math.ceil(4.0 * d / beta_prime
+                         * max(420.0 * math.log(4.0 * d / delta), 1.0 / (delta * eps))))
+
+
+# --------------------------------------------------------------------------
+# Integer CDF tables and product-distribution sampling
+# (Lemma 4.1 product law; Alg. 3 sampler; proof of Thm 4.2: per-mode CDFs
+#  and one binary search per mode)
+# --------------------------------------------------------------------------
+
+def cdf_table(scores, q_bits=Q_BITS):
+    """Integer weights w_i = ceil(max(l_i, 0) * 2^Q) and their inclusive prefix sums.
+
+    The paper asks for a CDF per factor; integer weights make the table exact
+    and independent of summation order.  The sampled distribution is q = w / W
+    and the rescaling below uses the same q, so this is Alg. 1 run with the
+    overestimate w (every row with a nonzero score keeps a nonzero weight).
+    """
+    sc = np.maximum(np.asarray(scores, dtype=np.float64), 0.0)
+    w = np.ceil(sc * float(2 ** q_bits)).astype(np.uint64)
+    C = np.cumsum(w, dtype=np.uint64)
+    return w, C
+
+
+def sample(tables, s, seed, counter, problem=0):
+    """Draw s multi-indices i.i.d. from the product of the per-mode distributions.
+
+    tables : list of (w, C) per mode from ``cdf_table``.
+    Random words: Philox4x64-10 with key (seed, 0) and counter
+    (t, counter, problem, block); word j of block b drives mode 4b + j.
+    Mode n draws u = floor(r * W_n / 2^64) and takes the first row j with
+    C_j > u (inverse-CDF by binary search).  Draws are with replacement (Alg. 1).
+
+    Returns idx (N, s) int32 and weight (s,) float64, where
+    weight_t = (prod_n W_n / w_{i_n}) / s  = 1 / (s * P(row t))
+    so that sum_t weight_t k_t k_t^T is the sketched Gram (S K)^T (S K) of Alg. 1
+    (sketch entries 1/sqrt(P(j) s)).  The product is taken in mode order,
+    one IEEE operation at a time.
+    """
+    N = len(tables)
+    t = np.arange(s, dtype=np.uint64)
+    idx = np.empty((N, s), dtype=np.int32)
+    for b in range((N + 3) // 4):
+        words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(b),
+                           seed, 0)
+        for j in range(4):
+            n = 4 * b + j
+            if n >= N:
+                break
+            w, C = tables[n]
+            u = mulhi64(words[j], np.uint64(C[-1]))
+            idx[n] = np.searchsorted(C, u, side="right").astype(np.int32)
+    acc = np.ones(s, dtype=np.float64)
+    for n in range(N):
+        w, C = tables[n]
+        W = np.float64(C[-1])
+        acc = acc * (W / w[idx[n]].astype(np.float64))
+    weight = acc / np.float64(s)
+    return idx, weight
+
+
+def sampling_probabilities(tables, idx):
+    """P(row t) = prod_n w_{i_n} / W_n, the probability each sample was drawn with."""
+    p = np.ones(np.asarray(idx).shape[1])
+    for n, (w, C) in enumerate(tables):
+        p = p * (w[idx[n]].astype(np.float64) / np.float64(C[-1]))
+    return p
+
+
+# --------------------------------------------------------------------------
+# Sketched core update (Alg. 3 -> Alg. 1, normal equations as in the proof
+# of Thm 4.2; ridge handled as Gram + lam I)
+# --------------------------------------------------------------------------
+
+def sampled_entries(X, idx, mask=None):
+    """x_t = X[idx_t] and the observed flag of each sample."""
+    X = np.asarray(X)
+    flat = flat_index(idx, X.shape)
+    x = X.reshape(-1)[flat].astype(np.float64)
+    obs = np.ones(flat.shape, dtype=bool) if mask is None else mask_lookup(mask, flat)
+    return x, obs
+
+
+def sketched_normal_equations(X, factors, idx, weight, mask=None, chunk=8192):
+    """Sketched Gram sum_t w_t k_t k_t^T and right side sum_t w_t x_t k_t.
+
+    Samples that hit a missing entry contribute nothing (they keep their
+    weight, so both sums stay unbiased for the observed-only design).
+    """
+    x, obs = sampled_entries(X, idx, mask)
+    idx = np.asarray(idx)
+    weight = np.asarray(weight, dtype=np.float64)
+    d = int(np.prod([A.shape[1] for A in factors]))
+    gram = np.zeros((d, d))
+    rhs = np.zeros(d)
+    s = idx.shape[1]
+    for a in range(0, s, chunk):
+        b = min(s, a + chunk)
+        keep = obs[a:b]
+        rows = kron_rows(factors, idx[:, a:b][:, keep])
+        wk = weight[a:b][keep]
+        gram += (rows * wk[:, None]).T @ rows
+        rhs += rows.T @ (wk * x[a:b][keep])
+    return gram, rhs
+
+
+def core_update_sketched(X, factors, lam, idx, weight, mask=None):
+    """Sketched ridge solve (Gram + lam I) g = rhs by Cholesky; returns G (R1..RN)."""
+    gram, rhs = sketched_normal_equations(X, factors, idx, weight, mask)
+    d = gram.shape[0]
+    L = np.linalg.cholesky(gram + lam * np.eye(d))
+    g = np.linalg.solve(L.T, np.linalg.solve(L, rhs))
+    return g.reshape([A.shape[1] for A in factors])
+
+
+def fast_core_tensor_update(X, factors, lam, s, seed, counter, mask=None, problem=0):
+    """Alg. 3 end to end: factor leverage scores, product sampler, sketched solve."""
+    tables = [cdf_table(leverage_scores(A)) for A in factors]
+    idx, weight = sample(tables, s, seed, counter, problem)
+    G = core_update_sketched(X, factors, lam, idx, weight, mask)
+    return G, idx, weight, tables
+
+
+def sketched_objective_excess(g, g_star, factors, lam):
+    """(g - g*)^T (K^T K + lam I) (g - g*), computed through the Kronecker Gram.
+
+    For a ridge problem f(g) - f(g*) equals exactly this quadratic form, so the
+    (1+eps) bound of Thm 3.4 can be checked without cancellation.
+    """
+    e = np.asarray(g, dtype=np.float64) - np.asarray(g_star, dtype=np.float64)
+    Ce = e
+    for n, A in enumerate(factors):
+        A = np.asarray(A, dtype=np.float64)
+        Ce = mode_product(Ce, A.T @ A, n)
+    return float(np.sum(e * Ce) + lam * np.sum(e * e))
+
+
+def ridge_objective(X, G, factors, lam, mask=None):
+    """||K vec G - vec X||^2 (observed entries) + lam ||G||^2 (Alg. 2 core step)."""
+    R = np.asarray(X, dtype=np.float64) - reconstruct(G, factors)
+    if mask is not None:
+        R = R * unpack_mask(mask, R.shape)
+    return float(np.sum(R * R) + lam * np.sum(np.asarray(G, dtype=np.float64) ** 2))
+
+
+# --------------------------------------------------------------------------
+# Exact core update (Alg. 2 core step), eigen form from the proof of Lemma 4.1:
+#   K^T K + lam I = (x V_n) ((x) Lambda_n + lam I) (x V_n)^T
+# --------------------------------------------------------------------------
+
+def _kron_eigs(factors):
+    evals, vecs = [], []
+    for A in factors:
+        A = np.asarray(A, dtype=np.float64)
+        e, V = np.linalg.eigh(A.T @ A)
+        evals.append(e)
+        vecs.append(V)
+    D = np.ones(())
+    for e in evals:
+        D = np.multiply.outer(D, e)
+    return D, vecs
+
+
+def apply_inverse_kron_gram(T, factors, lam):
+    """(K^T K + lam I)^{-1} applied to a core-shaped tensor T."""
+    D, vecs = _kron_eigs(factors)
+    B = np.asarray(T, dtype=np.float64)
+    for n, V in enumerate(vecs):
+        B = mode_product(B, V.T, n)
+    B = B / (D + lam)
+    for n, V in enumerate(vecs):
+        B = mode_product(B, V, n)
+    return B
+
+
+def core_update_exact(X, factors, lam):
+    """argmin_G ||K vec G - vec X||^2 + lam ||G||^2 for a fully observed X."""
+    B = np.asarray(X, dtype=np.float64)
+    for n, A in enumerate(factors):
+        B = mode_product(B, np.asarray(A, dtype=np.float64).T, n)  # K^T vec X
+    return apply_inverse_kron_gram(B, factors, lam)
+
+
+def core_update_exact_masked(X, factors, lam, mask, tol=1e-12, maxit=1000):
+    """Exact core update over observed entries only.
+
+    The paper's experiments are fully observed; for a masked tensor this solves
+    (K~^T K~ + lam I) g = K~^T x~ by conjugate gradients with the matrix-free
+    product v -> K^T (M o (K v)) + lam v, preconditioned by the unmasked
+    (K^T K + lam I)^{-1}.
+    """
+    Mk = unpack_mask(mask, np.asarray(X).shape).astype(np.float64)
+    Xm = np.asarray(X, dtype=np.float64) * Mk
+
+    def KT(T):
+        for n, A in enumerate(factors):
+            T = mode_product(T, np.asarray(A, dtype=np.float64).T, n)
+        return T
+
+    def op(v):
+        return KT(reconstruct(v, factors) * Mk) + lam * v
+
+    b = KT(Xm)
+    x = apply_inverse_kron_gram(b, factors, lam)
+    r = b - op(x)
+    z = apply_inverse_kron_gram(r, factors, lam)
+    p = z.copy()
+    rz = np.sum(r * z)
+    bn = np.linalg.norm(b)
+    for _ in range(maxit):
+        if np.linalg.norm(r) <= tol * bn:
+            break
+        Ap = op(p)
+        alpha = rz / np.sum(p * Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = apply_inverse_kron_gram(r, factors, lam)
+        rz_new = np.sum(r * z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x
+
+
+# --------------------------------------------------------------------------
+# Factor update (Alg. 2 inner loop): row-wise ridge with
+#   K_n = G_(n) (x_{m != n} A(m))^T,   A(n) = X_(n) K_n^T (K_n K_n^T + lam I)^{-1}
+# --------------------------------------------------------------------------
+
+def factor_update(X, G, factors, n, lam):
+    """New A(n) for a fully observed X; X_(n) K_n^T and K_n K_n^T via mode products."""
+    W = np.asarray(X, dtype=np.float64)
+    C = np.ones((1, 1))
+    for m, A in enumerate(factors):
+        if m == n:
+            continue
+        A = np.asarray(A, dtype=np.float64)
+        W = mode_product(W, A.T, m)
+        C = np.kron(C, A.T @ A)
+    Gn = unfold(np.asarray(G, dtype=np.float64), n)
+    rhs = unfold(W, n) @ Gn.T              # X_(n) K_n^T  (I_n x R_n)
+    KKt = Gn @ C @ Gn.T                    # K_n K_n^T    (R_n x R_n)
+    Rn = KKt.shape[0]
+    return np.linalg.solve(KKt + lam * np.eye(Rn), rhs.T).T
+
+
+# --------------------------------------------------------------------------
+# Loss (Sec. 2) and RMSE
+# --------------------------------------------------------------------------
+
+def loss(X, G, factors, lam, mask=None):
+    """(L, rmse): L = ||X - Xhat||_F^2 + lam(||G||^2 + sum ||A(n)||^2); rmse over observed entries."""
+    R = np.asarray(X, dtype=np.float64) - reconstruct(G, factors)
+    count = R.size
+    if mask is not None:
+        Mk = unpack_mask(mask, R.shape)
+        R = R * Mk
+        count = int(Mk.sum())
+    sq = float(np.sum(R * R))
+    reg = float(np.sum(np.asarray(G, dtype=np.float64) ** 2))
+    reg += sum(float(np.sum(np.asarray(A, dtype=np.float64) ** 2)) for A in factors)
+    return sq + lam * reg, math.sqrt(sq / max(count, 1))
+
+
+# --------------------------------------------------------------------------
+# ALS (Alg. 2), exact or with the sampled core update of Alg. 3
+# --------------------------------------------------------------------------
+
+def als(X, G0, factors0, lam, iters, core="exact", s=None, seed=0, record=None):
+    """Alg. 2 from a given initial state; ``core`` is "exact" or "sketched".
+
+    Per iteration: update A(1)..A(N) in order, then the core.  The sketched core
+    update of iteration k uses sampling counter k.  Returns (G, factors, history)
+    where history holds (loss, rmse) after every core update.
+    """
+    G = np.asarray(G0, dtype=np.float64).copy()
+    factors = [np.asarray(A, dtype=np.float64).copy() for A in factors0]
+    hist = []
+    for it in range(iters):
+        for n in range(len(factors)):
+            factors[n] = factor_update(X, G, factors, n, lam)
+            if record is not None:
+                record.append(("factor", it, n, loss(X, G, factors, lam)))
+        if core == "exact":
+            G = core_update_exact(X, factors, lam)
+        else:
+            G, _, _, _ = fast_core_tensor_update(X, factors, lam, s, seed, it)
+        hist.append(loss(X, G, factors, lam))
+        if record is not None:
+            record.append(("core", it, -1, hist[-1]))
+    return G, factors, hist
+
+
+# --------------------------------------------------------------------------
+# Adjoint of the sketched solve with the sample set frozen (not in the paper)
+# --------------------------------------------------------------------------
+
+def sketched_adjoint(X, factors, lam, idx, weight, g_bar, mask=None):
+    """Gradients of <g_bar, g> w.r.t. the factors and the tensor entries.
+
+    g solves (sum_t w_t k_t k_t^T + lam I) g = sum_t w_t x_t k_t with (idx, w)
+    held fixed (the sketch is treated as a constant operator).  With
+    v = M^{-1} g_bar:
+      d/dx_t = w_t (k_t . v)                       (observed samples, summed over duplicates)
+      d/dk_t = w_t [ (x_t - k_t . g) v - (k_t . v) g ]
+    and d/dA(n)[i_n, :] collects d/dk_t contracted with the other modes' rows.
+    Returns (factor_bars, X_bar dense, g).
+    """
+    X = np.asarray(X)
+    gram, rhs = sketched_normal_equations(X, factors, idx, weight, mask)
+    d = gram.shape[0]
+    M = gram + lam * np.eye(d)
+    g = np.linalg.solve(M, rhs)
+    v = np.linalg.solve(M, np.asarray(g_bar, dtype=np.float64).reshape(-1))
+    x, obs = sampled_entries(X, idx, mask)
+    idx = np.asarray(idx)
+    rows_all = kron_rows(factors, idx)
+    w = np.asarray(weight, dtype=np.float64) * obs
+    kv = rows_all @ v
+    kg = rows_all @ g
+    Xbar = np.zeros(X.size)
+    np.add.at(Xbar, flat_index(idx, X.shape), w * kv)
+    kbar = w[:, None] * ((x - kg)[:, None] * v[None, :] - kv[:, None] * g[None, :])
+    ranks = [A.shape[1] for A in factors]
+    T = kbar.reshape([idx.shape[1]] + ranks)
+    rows = [np.asarray(A, dtype=np.float64)[idx[m]] for m, A in enumerate(factors)]
+    bars = []
+    for n, A in enumerate(factors):
+        Tn = T
+        # contract modes m != n, highest first, so lower axis numbers are unchanged
+        for m in reversed(range(len(factors))):
+            if m == n:
+                continue
+            Tn = np.einsum("t...r,tr->t...", np.moveaxis(Tn, 1 + m, -1), rows[m])
+        # Tn now has shape (s, R_n)
+        Ab = np.zeros(np.asarray(A).shape)
+        np.add.at(Ab, idx[n], Tn)
+        bars.append(Ab)
+    return bars, Xbar.reshape(X.shape), g.reshape(ranks)
+
+
+def exact_adjoint(X, factors, lam, g_bar):
+    """Gradients of <g_bar, g*> for the exact solve g* = (K^T K + lam I)^{-1} K^T x.
+
+    With v = (K^T K + lam I)^{-1} g_bar:  X_bar = K v (a full tensor) and
+    A_bar(n) = X_(n) (x_{m!=n} A(m)) V_(n)^T
+               - A(n) [G_(n) (x_{m!=n} C_m) V_(n)^T + V_(n) (x_{m!=n} C_m) G_(n)^T],
+    C_m = A(m)^T A(m), G = g*, V = v as core-shaped tensors.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    G = core_update_exact(X, factors, lam)
+    V = apply_inverse_kron_gram(np.asarray(g_bar, dtype=np.float64).reshape(G.shape), factors, lam)
+    Xbar = reconstruct(V, factors)
+    bars = []
+    for n, A in enumerate(factors):
+        A = np.asarray(A, dtype=np.float64)
+        W = X
+        C = np.ones((1, 1))
+        for m, B in enumerate(factors):
+            if m == n:
+                continue
+            B = np.asarray(B, dtype=np.float64)
+            W = mode_product(W, B.T, m)
+            C = np.kron(C, B.T @ B)
+        Gn, Vn = unfold(G, n), unfold(V, n)
+        bars.append(unfold(W, n) @ Vn.T - A @ (Gn @ C @ Vn.T + Vn @ C @ Gn.T))
+    return bars, Xbar, G
