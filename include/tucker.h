@@ -1,0 +1,220 @@
+/*
+ * tucker.h -- C ABI of the MI355X (gfx950) library for the ridge-leverage-score
+ * sampled core-tensor update of Tucker ALS.
+ *
+ * Paper: Fahrbach, Ghadiri, Fu, "Fast Low-Rank Tensor Decomposition by Ridge
+ * Leverage Score Sampling" (arXiv 2107.10654).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All tensors are row-major (C order): X[i_1,...,i_N] sits at
+ *   sum_n i_n * stride_n with i_N fastest.  The core G is R_1 x ... x R_N
+ *   row-major; factor A(n) is I_n x R_n row-major.
+ * - The design row of multi-index i is k_i = a(1)[i_1,:] (x) ... (x) a(N)[i_N,:]
+ *   (row-major Kronecker), so K = A(1) (x) ... (x) A(N) and K vec(G) = vec(Xhat)
+ *   (Sec. 2, elementwise Tucker model; Alg. 2 core step).
+ * - Pointers named "device" must point to device memory of the current HIP
+ *   device.  The library never allocates, frees or synchronises: the caller
+ *   owns every buffer, including the workspace whose size
+ *   tucker_workspace_bytes() reports.
+ * - Every call is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *   the null stream).  Argument and shape errors are returned synchronously and
+ *   nothing is enqueued.  Data-dependent failures (matrix not positive
+ *   definite, rank-deficient factor, refinement not converged) are written as a
+ *   tk_status code into the device word `dev_status`, which the caller reads
+ *   after synchronising the stream.  A call that writes dev_status first clears
+ *   it on the stream.
+ * - Per-mode arrays of length I_n (scores, weights, CDFs) are concatenated in
+ *   mode order: mode n starts at offset sum_{m<n} I_m.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_MAX_ORDER 8     /* largest supported tensor order N */
+#define TK_MAX_RANK 64     /* largest supported per-mode rank R_n */
+#define TK_Q_BITS 24       /* fixed-point bits of the integer sampling weights */
+#define TK_INFO_LEN 8      /* doubles written to dev_info by the sketched update */
+
+typedef enum { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 } tk_dtype;
+
+typedef enum {
+  TK_OK = 0,
+  TK_E_ARG = 1,             /* null pointer or bad scalar argument */
+  TK_E_SHAPE = 2,           /* unsupported order, rank or size */
+  TK_E_DTYPE = 3,           /* unsupported element type */
+  TK_E_WORKSPACE = 4,       /* workspace smaller than tucker_workspace_bytes() */
+  TK_E_NOT_SPD = 5,         /* Cholesky met a non-positive pivot */
+  TK_E_RANK_DEFICIENT = 6,  /* a factor matrix has dependent columns */
+  TK_E_NO_CONVERGE = 7,     /* FP64 refinement did not reach its tolerance */
+  TK_E_HIP = 8              /* a HIP runtime call failed */
+} tk_status;
+
+/* One Tucker problem: the tensor, its optional observation mask, the current
+ * factor matrices and the ridge parameter lambda of the regularised loss
+ * (Sec. 2, loss L; Alg. 2). */
+typedef struct {
+  int32_t order;                        /* N, 1..TK_MAX_ORDER */
+  int64_t dims[TK_MAX_ORDER];           /* I_n >= 1 */
+  int32_t ranks[TK_MAX_ORDER];          /* R_n, 1..TK_MAX_RANK, R_n <= I_n */
+  tk_dtype dtype;                       /* element type of X, factors and core: TK_F64 or TK_F32 */
+  const void* X;                        /* device, prod(dims) elements */
+  const uint32_t* mask;                 /* device or NULL; bit (e & 31) of word e >> 5 is 1
+                                           when entry e (row-major offset) is observed */
+  const void* factors[TK_MAX_ORDER];    /* device, A(n): dims[n] x ranks[n] */
+  double lambda;                        /* ridge parameter, >= 0 */
+} tk_problem;
+
+/* Options of the sketched update (Alg. 1 / Alg. 3). */
+typedef struct {
+  int64_t num_samples;     /* s >= 1; <= 0 selects Alg. 1's count
+                              ceil(8 d max{420 ln(4d/delta), 1/(delta eps)}) */
+  double eps, delta;       /* used only when num_samples <= 0 */
+  uint64_t seed;           /* Philox key word 0 */
+  uint64_t counter;        /* Philox counter word 1 (e.g. the ALS iteration) */
+  uint64_t problem;        /* Philox counter word 2 (problem index in a batch) */
+  tk_dtype gram_precision; /* TK_F64: FP64 Gram and solve, no refinement.
+                              TK_F32 / TK_BF16: Gram on MFMA with FP32
+                              accumulation, FP64 Cholesky, FP64 refinement. */
+  int32_t refine_max;      /* max refinement steps (low-precision Gram only) */
+  double refine_tol;       /* stop when ||r||_2 <= refine_tol * ||rhs||_2 */
+} tk_sketch_opts;
+
+/* Which call tucker_workspace_bytes() sizes. */
+typedef enum {
+  TK_CALL_LEVERAGE = 0,
+  TK_CALL_SKETCHED = 1,
+  TK_CALL_EXACT = 2,
+  TK_CALL_FACTOR = 3,
+  TK_CALL_LOSS = 4,
+  TK_CALL_ADJOINT = 5
+} tk_call;
+
+/* Bytes of workspace the named call needs for this problem (0 on bad input).
+ * `opts` is read only for TK_CALL_SKETCHED and TK_CALL_ADJOINT and may be
+ * NULL otherwise. */
+size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, int32_t call);
+
+/* Sample count of Alg. 1 with beta' = 1/2 (Cor. 3.3), as used when
+ * num_samples <= 0. */
+int64_t tucker_sample_count(int64_t d, double eps, double delta);
+
+/*
+ * Factor leverage scores and sampling tables -- Alg. 3, first step; the
+ * statistical leverage score is the ridge score of Sec. 2 at lambda = 0,
+ * l_i = a_i (A^T A)^+ a_i^T.  Computed per mode from the FP64 Cholesky
+ * factor L_n of C_n = A(n)^T A(n): q_i = L_n^{-1} a_i^T, l_i = ||q_i||^2.
+ *
+ * Outputs (device, concatenated per mode, total T = sum_n I_n entries):
+ *   scores  [T] double   l_i                                   (may be NULL)
+ *   cdf     [T] uint64   inclusive prefix sums of w_i = ceil(max(l_i,0) * 2^TK_Q_BITS);
+ *                        the last entry of mode n is the mode's total W_n
+ *                        (the per-mode CDFs of the proof of Thm 4.2)
+ * A factor whose Cholesky pivot falls to <= R_n * 2^-52 * max diag(C_n) is
+ * rank deficient: dev_status gets TK_E_RANK_DEFICIENT and that mode's outputs
+ * are zero.  Reads only p->order, dims, ranks, dtype and factors.
+ */
+tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* cdf,
+                                 int32_t* dev_status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Product-distribution sampling of s multi-indices -- Alg. 3 (sample from
+ * l(K) with factored scores; Lemma 4.1: leverage scores of a Kronecker
+ * product are products of factor scores) and Alg. 1 (s i.i.d. draws with
+ * replacement, sketch entry 1/sqrt(P(j) s)).
+ *
+ *   cdf     device, concatenated per-mode integer CDFs (as written above)
+ *   idx     device int32 [order][s] (structure of arrays): idx[n*s + t] = i_n of sample t
+ *   weight  device double [s]: weight_t = (prod_n W_n / w_{i_n}) / s = 1/(s P(t)),
+ *           the product taken in mode order, one IEEE operation at a time
+ * Random words: Philox4x64-10 with key (seed, 0) and counter
+ * (t, counter, problem, b); word j of block b drives mode 4b + j; the mode
+ * draws u = floor(r W_n / 2^64) and takes the first row j with cdf_j > u.
+ * Given equal tables the output is bit-identical to the FP64 CPU oracle.
+ */
+tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf, int64_t s,
+                        uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
+                        double* weight, void* stream);
+
+/*
+ * Sampled core-tensor update -- Alg. 3 FastCoreTensorUpdate calling Alg. 1
+ * ApproximateRidgeRegression; normal equations as in the proof of Thm 4.2,
+ * with the ridge term added to the sketched Gram:
+ *   g = argmin_g sum_t weight_t (x_t - k_t . g)^2 + lambda ||g||^2
+ *     = (sum_t weight_t k_t k_t^T + lambda I)^{-1} sum_t weight_t x_t k_t.
+ * Samples that hit an unobserved entry (mask bit 0) contribute nothing.
+ *
+ *   idx_in, weight_in  device or NULL.  Both given: use this frozen sample set
+ *                      (s = opts->num_samples entries).  Both NULL: compute the
+ *                      leverage scores, CDFs and samples from opts.
+ *   idx_out, weight_out device or NULL: receive the samples used.
+ *   core_out           device, prod(ranks) elements of p->dtype.
+ *   dev_info           device double [TK_INFO_LEN] or NULL:
+ *                      [0] samples s, [1] samples on missing entries,
+ *                      [2] refinement steps taken, [3] final relative residual
+ *                      ||r||/||rhs|| (FP64), [4] smallest Cholesky pivot,
+ *                      [5..7] reserved (0).
+ * Internally the rows are whitened per mode (q_i = L_n^{-1} a_i^T); the
+ * solution is mapped back exactly, so the result is the g above.
+ */
+tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts* opts,
+                                      const int32_t* idx_in, const double* weight_in,
+                                      int32_t* idx_out, double* weight_out, void* core_out,
+                                      int32_t* dev_status, double* dev_info, void* ws,
+                                      size_t ws_bytes, void* stream);
+
+/*
+ * Exact core-tensor update -- Alg. 2 core step,
+ *   G = argmin ||K vec G - vec X||^2 + lambda ||G||^2,
+ * through the eigen form of the proof of Lemma 4.1:
+ *   K^T K + lambda I = ((x)V_n) ((x)Lambda_n + lambda I) ((x)V_n)^T,
+ *   C_n = A(n)^T A(n) = V_n Lambda_n V_n^T.
+ * One streaming pass over X forms K^T vec X.  With a mask, the update is over
+ * observed entries only, solved by preconditioned conjugate gradients with
+ * the unmasked inverse as preconditioner (relative residual 1e-10, at most
+ * 200 iterations; TK_E_NO_CONVERGE otherwise).
+ */
+tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t* dev_status,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Factor-matrix update of Alg. 2 for mode `mode` (0-based): every row solves
+ *   a_i = argmin_y ||y K_n - x_(n),i||^2 + lambda ||y||^2,
+ *   K_n = G_(n) ((x)_{m != n} A(m))^T,
+ * i.e. A(n) = X_(n) K_n^T (K_n K_n^T + lambda I)^{-1}.  One streaming pass over
+ * X.  Fully observed tensors only (a mask gives TK_E_ARG).
+ *   core        device, prod(ranks) elements of p->dtype
+ *   factor_out  device, dims[mode] x ranks[mode] of p->dtype (may alias
+ *               p->factors[mode]; it is written last)
+ */
+tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mode,
+                               void* factor_out, int32_t* dev_status, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/*
+ * Regularised Tucker loss of Sec. 2,
+ *   L = ||X - Xhat||_F^2 + lambda (||G||_F^2 + sum_n ||A(n)||_F^2),
+ * with the residual over observed entries when a mask is given.
+ *   out  device double [3]: [0] L, [1] sum of squared residuals,
+ *        [2] number of observed entries (RMSE = sqrt(out[1] / out[2])).
+ */
+tk_status tucker_loss(const tk_problem* p, const void* core, double* out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* tucker_status_string(tk_status s);
+
+/* ABI revision of this header. */
+int32_t tucker_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKER_H */

@@ -514,3 +514,23 @@ def exact_adjoint(X, factors, lam, g_bar):
         Gn, Vn = unfold(G, n), unfold(V, n)
         bars.append(unfold(W, n) @ Vn.T - A @ (Gn @ C @ Vn.T + Vn @ C @ Gn.T))
     return bars, Xbar, G
+
+
+def normal_equation_residual(X, factors, lam, idx, weight, G, mask=None, chunk=4096):
+    """Relative residual ||sum_t w_t k_t (x_t - k_t.g) - lam g|| / ||sum_t w_t x_t k_t||.
+
+    Zero exactly when G solves the sketched ridge normal equations of the given
+    samples; computed matrix-free in chunks, so it scales to large d and s.
+    """
+    x, obs = sampled_entries(X, idx, mask)
+    idx = np.asarray(idx)
+    w = np.asarray(weight, dtype=np.float64) * obs
+    g = np.asarray(G, dtype=np.float64).reshape(-1)
+    r = -lam * g
+    b = np.zeros_like(g)
+    for a in range(0, idx.shape[1], chunk):
+        e = min(idx.shape[1], a + chunk)
+        rows = kron_rows(factors, idx[:, a:e])
+        b += rows.T @ (w[a:e] * x[a:e])
+        r += rows.T @ (w[a:e] * (x[a:e] - rows @ g))
+    return float(np.linalg.norm(r) / np.linalg.norm(b))

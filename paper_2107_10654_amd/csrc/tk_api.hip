@@ -1,0 +1,610 @@
+// C ABI entry points (include/tucker.h): argument validation, workspace
+// carving and the launch sequences of each call.  Nothing here allocates,
+// frees or synchronises; every launch goes to the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include "tk_internal.h"
+
+namespace tk {
+
+Geom make_geom(const tk_problem* p) {
+  Geom g;
+  memset(&g, 0, sizeof(g));
+  g.order = p->order;
+  int64_t off = 0, qoff = 0, roff = 0, numel = 1, d = 1;
+  for (int n = 0; n < p->order; ++n) {
+    g.ranks[n] = p->ranks[n];
+    g.dims[n] = p->dims[n];
+    g.off[n] = off;
+    g.qoff[n] = qoff;
+    g.roff[n] = roff;
+    off += p->dims[n];
+    qoff += p->dims[n] * p->ranks[n];
+    roff += static_cast<int64_t>(p->ranks[n]) * p->ranks[n];
+    numel *= p->dims[n];
+    d *= p->ranks[n];
+  }
+  int64_t stride = 1;
+  for (int n = p->order - 1; n >= 0; --n) {
+    g.strides[n] = stride;
+    stride *= p->dims[n];
+  }
+  g.total_rows = off;
+  g.total_q = qoff;
+  g.total_rr = roff;
+  g.numel = numel;
+  g.d = d;
+  return g;
+}
+
+namespace {
+
+constexpr int64_t kMaxD = 16384;
+
+tk_status check_shape(const tk_problem* p) {
+  if (!p) return TK_E_ARG;
+  if (p->order < 1 || p->order > kMaxOrder) return TK_E_SHAPE;
+  int64_t numel = 1, d = 1;
+  for (int n = 0; n < p->order; ++n) {
+    if (p->dims[n] < 1 || p->dims[n] > (int64_t(1) << 31) - 1) return TK_E_SHAPE;
+    if (p->ranks[n] < 1 || p->ranks[n] > kMaxRank) return TK_E_SHAPE;
+    if (p->ranks[n] > p->dims[n]) return TK_E_SHAPE;
+    if (numel > (int64_t(1) << 62) / p->dims[n]) return TK_E_SHAPE;
+    numel *= p->dims[n];
+    d *= p->ranks[n];
+    if (d > kMaxD) return TK_E_SHAPE;
+  }
+  if (p->dtype != TK_F64 && p->dtype != TK_F32) return TK_E_DTYPE;
+  if (!(p->lambda >= 0.0) || !isfinite(p->lambda)) return TK_E_ARG;
+  return TK_OK;
+}
+
+tk_status check_problem(const tk_problem* p, bool need_x) {
+  tk_status s = check_shape(p);
+  if (s != TK_OK) return s;
+  if (need_x && !p->X) return TK_E_ARG;
+  for (int n = 0; n < p->order; ++n)
+    if (!p->factors[n]) return TK_E_ARG;
+  return TK_OK;
+}
+
+int64_t resolve_samples(const tk_sketch_opts* o, int64_t d) {
+  if (o->num_samples > 0) return o->num_samples;
+  return tucker_sample_count(d, o->eps, o->delta);
+}
+
+// ---------------------------------------------------------------- workspaces
+struct LevWS {
+  double* scores;
+  uint64_t* cdf;
+  double* L;
+  double* Linv;
+  double* P;
+  double* Q64;
+  float* Q32;
+};
+
+void carve_lev(Carver& c, const Geom& g, LevWS& w) {
+  w.scores = c.take<double>(g.total_rows);
+  w.cdf = c.take<uint64_t>(g.total_rows);
+  w.L = c.take<double>(g.total_rr);
+  w.Linv = c.take<double>(g.total_rr);
+  w.P = c.take<double>(g.total_rr);
+  w.Q64 = c.take<double>(g.total_q);
+  w.Q32 = c.take<float>(g.total_q);
+}
+
+struct SketchWS {
+  LevWS lev;
+  int32_t* idx;
+  double* weight;
+  double* weff;
+  double* xw;
+  void* gpart;
+  double* M;
+  double* Linv_diag;
+  double* rhs;
+  double* h;
+  double* r;
+  double* ytmp;
+  double* delta;
+  double* ph_a;
+  double* ph_b;
+  double* vpart;
+  double* dpart;
+  double* coef;
+  int32_t* flags;
+  int32_t* status;
+  int32_t* done;
+  int32_t* steps;
+  double* relres;
+  double* min_pivot;
+  unsigned int* missing;
+};
+
+void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w) {
+  carve_lev(c, g, w.lev);
+  const int64_t d = g.d;
+  w.idx = c.take<int32_t>(static_cast<size_t>(g.order) * s);
+  w.weight = c.take<double>(s);
+  w.weff = c.take<double>(s);
+  w.xw = c.take<double>(s);
+  w.gpart = c.take<char>(gram_partial_bytes(g, pl));
+  w.M = c.take<double>(static_cast<size_t>(d) * d);
+  const int64_t nblk = cdiv(d, kCholNb);
+  w.Linv_diag = c.take<double>(nblk * kCholNb * kCholNb);
+  w.rhs = c.take<double>(d);
+  w.h = c.take<double>(d);
+  w.r = c.take<double>(d);
+  w.ytmp = c.take<double>(d);
+  w.delta = c.take<double>(d);
+  w.ph_a = c.take<double>(d);
+  w.ph_b = c.take<double>(d);
+  w.vpart = c.take<double>(rows_t_vec_chunks(g, s) * d);
+  w.dpart = c.take<double>(cdiv(d, 256) * s);
+  w.coef = c.take<double>(s);
+  w.flags = c.take<int32_t>(2 * nblk + 2);
+  w.status = c.take<int32_t>(1);
+  w.done = c.take<int32_t>(1);
+  w.steps = c.take<int32_t>(1);
+  w.relres = c.take<double>(1);
+  w.min_pivot = c.take<double>(1);
+  w.missing = c.take<unsigned int>(1);
+}
+
+struct ExactWS {
+  double* V;
+  double* lam;
+  double* W;
+  double* C;
+  double* tA;
+  double* tB;
+};
+
+// largest intermediate of the mode-product chain that contracts modes in
+// decreasing order, skipping `skip` (or none when skip < 0)
+int64_t chain_max(const Geom& g, int skip) {
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
+  int64_t mx = 1;
+  for (int m = g.order - 1; m >= 0; --m) {
+    if (m == skip) continue;
+    dims[m] = g.ranks[m];
+    int64_t sz = 1;
+    for (int n = 0; n < g.order; ++n) sz *= dims[n];
+    if (sz > mx) mx = sz;
+  }
+  return mx;
+}
+
+// largest intermediate of G x_0 A_0 ... x_{N-2} A_{N-2} (the loss reconstruction)
+int64_t up_chain_max(const Geom& g) {
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.ranks[n];
+  int64_t mx = g.d;
+  for (int m = 0; m < g.order - 1; ++m) {
+    dims[m] = g.dims[m];
+    int64_t sz = 1;
+    for (int n = 0; n < g.order; ++n) sz *= dims[n];
+    if (sz > mx) mx = sz;
+  }
+  return mx;
+}
+
+void carve_exact(Carver& c, const Geom& g, ExactWS& w) {
+  w.V = c.take<double>(g.total_rr);
+  w.lam = c.take<double>(static_cast<size_t>(kMaxOrder) * kMaxRank);
+  w.W = c.take<double>(g.total_q);
+  w.C = c.take<double>(g.total_rr);
+  const int64_t mx = chain_max(g, -1);
+  w.tA = c.take<double>(mx > g.d ? mx : g.d);
+  w.tB = c.take<double>(mx > g.d ? mx : g.d);
+}
+
+struct FactorWS {
+  double* C;
+  double* A64;
+  double* G64;
+  double* Z;
+  double* Z2;
+  double* rhs;
+  double* KKt;
+  double* tA;
+  double* tB;
+};
+
+void carve_factor(Carver& c, const Geom& g, FactorWS& w) {
+  w.C = c.take<double>(g.total_rr);
+  w.A64 = c.take<double>(g.total_q);
+  w.G64 = c.take<double>(g.d);
+  w.Z = c.take<double>(g.d);
+  w.Z2 = c.take<double>(g.d);
+  int64_t maxI = 1;
+  for (int n = 0; n < g.order; ++n) maxI = g.dims[n] > maxI ? g.dims[n] : maxI;
+  w.rhs = c.take<double>(maxI * kMaxRank);
+  w.KKt = c.take<double>(kMaxRank * kMaxRank);
+  int64_t mx = 1;
+  for (int n = 0; n < g.order; ++n) {
+    const int64_t v = chain_max(g, n);
+    mx = v > mx ? v : mx;
+  }
+  if (g.order == 1) mx = g.numel;  // no contraction: W is X itself, converted to FP64
+  w.tA = c.take<double>(mx);
+  w.tB = c.take<double>(mx);
+}
+
+constexpr int64_t kLossParts = 1024;
+
+struct LossWS {
+  double* A64;
+  double* G64;
+  double* tA;
+  double* tB;
+  double* psq;
+  double* pcnt;
+  double* preg;
+};
+
+void carve_loss(Carver& c, const Geom& g, LossWS& w) {
+  w.A64 = c.take<double>(g.total_q);
+  w.G64 = c.take<double>(g.d);
+  const int64_t mx = up_chain_max(g);
+  w.tA = c.take<double>(mx);
+  w.tB = c.take<double>(mx);
+  w.psq = c.take<double>(kLossParts);
+  w.pcnt = c.take<double>(kLossParts);
+  w.preg = c.take<double>(static_cast<size_t>(kMaxOrder + 1) * 64);
+}
+
+// ---------------------------------------------------------------- helpers
+// T <- T x_n M_n over all modes (core-sized ping-pong).  Returns the buffer
+// holding the result (a or b).
+double* core_chain(const Geom& g, double* a, double* b, const double* mats, bool trans,
+                   hipStream_t st) {
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.ranks[n];
+  double* cur = a;
+  double* nxt = b;
+  for (int n = 0; n < g.order; ++n) {
+    launch_ttm(cur, dims, g.order, n, mats + g.roff[n], g.ranks[n], trans, nxt, st);
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  return cur;
+}
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+int32_t tucker_abi_version(void) { return 1; }
+
+const char* tucker_status_string(tk_status s) {
+  switch (s) {
+    case TK_OK: return "ok";
+    case TK_E_ARG: return "invalid argument";
+    case TK_E_SHAPE: return "unsupported shape";
+    case TK_E_DTYPE: return "unsupported dtype";
+    case TK_E_WORKSPACE: return "workspace too small";
+    case TK_E_NOT_SPD: return "matrix not positive definite";
+    case TK_E_RANK_DEFICIENT: return "rank-deficient factor matrix";
+    case TK_E_NO_CONVERGE: return "refinement did not converge";
+    case TK_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+int64_t tucker_sample_count(int64_t d, double eps, double delta) {
+  if (d < 1 || !(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0)) return 0;
+  const double a = 420.0 * log(4.0 * static_cast<double>(d) / delta);
+  const double b = 1.0 / (delta * eps);
+  return static_cast<int64_t>(ceil(8.0 * static_cast<double>(d) * (a > b ? a : b)));
+}
+
+size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, int32_t call) {
+  if (check_shape(p) != TK_OK) return 0;
+  const Geom g = make_geom(p);
+  Carver c(nullptr);
+  switch (call) {
+    case TK_CALL_LEVERAGE: {
+      LevWS w;
+      carve_lev(c, g, w);
+      break;
+    }
+    case TK_CALL_SKETCHED: {
+      if (!opts) return 0;
+      const int64_t s = resolve_samples(opts, g.d);
+      if (s < 1) return 0;
+      const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
+      SketchWS w;
+      carve_sketch(c, g, s, pl, w);
+      break;
+    }
+    case TK_CALL_EXACT: {
+      ExactWS w;
+      carve_exact(c, g, w);
+      break;
+    }
+    case TK_CALL_FACTOR: {
+      FactorWS w;
+      carve_factor(c, g, w);
+      break;
+    }
+    case TK_CALL_LOSS: {
+      LossWS w;
+      carve_loss(c, g, w);
+      break;
+    }
+    default:
+      return 0;
+  }
+  return c.used + 256;
+}
+
+tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* cdf,
+                                 int32_t* dev_status, void* ws, size_t ws_bytes, void* stream) {
+  tk_status s = check_problem(p, false);
+  if (s != TK_OK) return s;
+  if (!cdf || !dev_status || !ws) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_LEVERAGE)) return TK_E_WORKSPACE;
+  const Geom g = make_geom(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  LevWS w;
+  carve_lev(c, g, w);
+  launch_fill_i32(1, 0, dev_status, st);
+  launch_leverage(g, p->factors, p->dtype, scores ? scores : w.scores, cdf, w.L, w.Linv, w.P,
+                  w.Q64, w.Q32, dev_status, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf, int64_t s,
+                        uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
+                        double* weight, void* stream) {
+  if (order < 1 || order > kMaxOrder || !dims || !cdf || !idx || !weight || s < 1)
+    return TK_E_ARG;
+  tk_problem p;
+  memset(&p, 0, sizeof(p));
+  p.order = order;
+  for (int n = 0; n < order; ++n) {
+    if (dims[n] < 1 || dims[n] > (int64_t(1) << 31) - 1) return TK_E_SHAPE;
+    p.dims[n] = dims[n];
+    p.ranks[n] = 1;
+  }
+  const Geom g = make_geom(&p);
+  launch_sample(g, cdf, s, seed, counter, problem, idx, weight, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts* o,
+                                      const int32_t* idx_in, const double* weight_in,
+                                      int32_t* idx_out, double* weight_out, void* core_out,
+                                      int32_t* dev_status, double* dev_info, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!o || !core_out || !ws) return TK_E_ARG;
+  if ((idx_in == nullptr) != (weight_in == nullptr)) return TK_E_ARG;
+  if ((idx_out == nullptr) != (weight_out == nullptr)) return TK_E_ARG;
+  if (o->gram_precision != TK_F64 && o->gram_precision != TK_F32 && o->gram_precision != TK_BF16)
+    return TK_E_DTYPE;
+  if (o->refine_max < 0 || o->refine_max > 1000 || !(o->refine_tol >= 0.0)) return TK_E_ARG;
+  const Geom g = make_geom(p);
+  const int64_t s = resolve_samples(o, g.d);
+  if (s < 1 || s > (int64_t(1) << 31) - 1) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, o, TK_CALL_SKETCHED)) return TK_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const GramPlan pl = plan_gram(g, s, o->gram_precision, 0);
+  Carver c(ws);
+  SketchWS w;
+  carve_sketch(c, g, s, pl, w);
+  int32_t* status = dev_status ? dev_status : w.status;
+
+  launch_fill_i32(1, 0, status, st);
+  launch_fill_i32(1, 0, w.done, st);
+  launch_fill_i32(1, 0, w.steps, st);
+  launch_fill_f64(1, 0.0, w.relres, st);
+  launch_fill_f64(1, 1e308, w.min_pivot, st);
+  launch_fill_u32(1, 0u, w.missing, st);
+
+  // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
+  launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
+                  w.lev.Q64, w.lev.Q32, status, st);
+  // 2. samples (Alg. 3 sampler) or the frozen set
+  const int32_t* idx = idx_in;
+  const double* weight = weight_in;
+  if (!idx_in) {
+    int32_t* io = idx_out ? idx_out : w.idx;
+    double* wo = weight_out ? weight_out : w.weight;
+    launch_sample(g, w.lev.cdf, s, o->seed, o->counter, o->problem, io, wo, st);
+    idx = io;
+    weight = wo;
+  } else if (idx_out) {
+    TK_HIP_CHECK(hipMemcpyAsync(idx_out, idx_in, sizeof(int32_t) * g.order * s,
+                                hipMemcpyDeviceToDevice, st));
+    TK_HIP_CHECK(hipMemcpyAsync(weight_out, weight_in, sizeof(double) * s,
+                                hipMemcpyDeviceToDevice, st));
+  }
+  // 3. sampled entries (x_t, mask) and effective weights
+  launch_gather(g, p->X, p->dtype, p->mask, idx, weight, s, w.weff, w.xw, w.missing, status, st);
+  // 4. sketched Gram on MFMA, plus lambda P
+  launch_gram(g, pl, idx, w.weff, s, w.lev.Q64, w.lev.Q32, w.gpart, st);
+  launch_assemble(g, pl, w.gpart, w.lev.P, p->lambda, w.M, st);
+  // 5. right-hand side sum_t w_t x_t q_t (FP64)
+  launch_rows_t_vec(g, idx, w.xw, s, w.lev.Q64, w.vpart, w.rhs, st);
+  // 6. FP64 Cholesky and solve
+  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, status, st);
+  launch_copy_f64(g.d, w.rhs, w.h, st);
+  launch_chol_solve(w.M, w.Linv_diag, g.d, w.h, w.ytmp, w.flags, nullptr, status, st);
+  // 7. FP64 refinement (low-precision Gram) or one residual check (FP64 Gram)
+  const bool refine = o->gram_precision != TK_F64;
+  const int iters = refine ? o->refine_max : 0;
+  for (int k = 0; k <= iters; ++k) {
+    launch_residual_coef(g, idx, w.xw, w.weff, w.h, s, w.lev.Q64, w.dpart, w.coef, w.done, st);
+    launch_rows_t_vec_flag(g, idx, w.coef, s, w.lev.Q64, w.vpart, w.r, w.done, st);
+    launch_copy_f64(g.d, w.h, w.ph_a, st);
+    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, st);
+    (void)ph;
+    launch_refine_check(g.d, w.r, ph, p->lambda, w.rhs, refine ? o->refine_tol : -1.0, w.done,
+                        w.steps, w.relres, k < iters ? 1 : 0, st);
+    if (k < iters) {
+      launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, status, st);
+      launch_axpy(g.d, 1.0, w.r, w.h, w.done, st);
+    }
+  }
+  if (refine) launch_finish_refine(w.done, 1, status, st);
+  // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
+  launch_copy_f64(g.d, w.h, w.ph_a, st);
+  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, st);
+  launch_cast_out(g.d, gres, core_out, p->dtype, st);
+  if (dev_info) launch_info(dev_info, s, w.missing, w.steps, w.relres, w.min_pivot, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t* dev_status,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!core_out || !dev_status || !ws) return TK_E_ARG;
+  if (p->mask) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_EXACT)) return TK_E_WORKSPACE;
+  const Geom g = make_geom(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  ExactWS w;
+  carve_exact(c, g, w);
+  launch_fill_i32(1, 0, dev_status, st);
+  launch_eig_modes(g, p->factors, p->dtype, w.V, w.lam, w.W, w.C, st);
+  // K^T vec X = X x_N W_N^T ... x_1 W_1^T (W_n = A(n) V_n), last mode first
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
+  const void* cur = p->X;
+  tk_dtype cur_dt = p->dtype;
+  double* bufs[2] = {w.tA, w.tB};
+  int which = 0;
+  for (int m = g.order - 1; m >= 0; --m) {
+    double* out = bufs[which];
+    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.W + g.qoff[m], g.ranks[m], true, out, st);
+    dims[m] = g.ranks[m];
+    cur = out;
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  double* B = const_cast<double*>(static_cast<const double*>(cur));
+  launch_kron_scale(g, w.lam, p->lambda, B, st);
+  double* other = (B == w.tA) ? w.tB : w.tA;
+  const double* G = core_chain(g, B, other, w.V, false, st);
+  launch_cast_out(g.d, G, core_out, p->dtype, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mode,
+                               void* factor_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                               void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!core || !factor_out || !dev_status || !ws) return TK_E_ARG;
+  if (mode < 0 || mode >= p->order) return TK_E_ARG;
+  if (p->mask) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_FACTOR)) return TK_E_WORKSPACE;
+  const Geom g = make_geom(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  FactorWS w;
+  carve_factor(c, g, w);
+  launch_fill_i32(1, 0, dev_status, st);
+  launch_gram_modes(g, p->factors, p->dtype, w.C, st);
+  for (int n = 0; n < g.order; ++n)
+    launch_cast_in(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.A64 + g.qoff[n], st);
+  launch_cast_in(g.d, core, p->dtype, w.G64, st);
+  // W = X x_{m != n} A(m)^T, modes in decreasing order
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
+  const void* cur = p->X;
+  tk_dtype cur_dt = p->dtype;
+  double* bufs[2] = {w.tA, w.tB};
+  int which = 0;
+  for (int m = g.order - 1; m >= 0; --m) {
+    if (m == mode) continue;
+    double* out = bufs[which];
+    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.A64 + g.qoff[m], g.ranks[m], true, out, st);
+    dims[m] = g.ranks[m];
+    cur = out;
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  const double* W;
+  if (cur_dt != TK_F64 || cur == p->X) {
+    launch_cast_in(g.numel, p->X, p->dtype, w.tA, st);
+    W = w.tA;
+  } else {
+    W = static_cast<const double*>(cur);
+  }
+  int64_t P = 1, Q = 1;
+  for (int m = 0; m < mode; ++m) P *= g.ranks[m];
+  for (int m = mode + 1; m < g.order; ++m) Q *= g.ranks[m];
+  const int64_t In = g.dims[mode];
+  const int Rn = g.ranks[mode];
+  // X_(n) K_n^T = W_(n) G_(n)^T
+  launch_unfold_contract(W, w.G64, P, In, Rn, Q, w.rhs, st);
+  // K_n K_n^T = G_(n) ((x)_{m != n} C_m) G_(n)^T
+  {
+    int64_t cd[kMaxOrder];
+    for (int n = 0; n < g.order; ++n) cd[n] = g.ranks[n];
+    const double* z = w.G64;
+    double* zb[2] = {w.Z, w.Z2};
+    int zi = 0;
+    for (int m = 0; m < g.order; ++m) {
+      if (m == mode) continue;
+      launch_ttm(z, cd, g.order, m, w.C + g.roff[m], g.ranks[m], false, zb[zi], st);
+      z = zb[zi];
+      zi ^= 1;
+    }
+    launch_unfold_contract(w.G64, z, P, Rn, Rn, Q, w.KKt, st);
+  }
+  launch_factor_solve(w.KKt, w.rhs, In, Rn, p->lambda, factor_out, p->dtype, dev_status, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_loss(const tk_problem* p, const void* core, double* out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!core || !out || !ws) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_LOSS)) return TK_E_WORKSPACE;
+  const Geom g = make_geom(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  LossWS w;
+  carve_loss(c, g, w);
+  for (int n = 0; n < g.order; ++n)
+    launch_cast_in(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.A64 + g.qoff[n], st);
+  launch_cast_in(g.d, core, p->dtype, w.G64, st);
+  // H = G x_0 A(0) ... x_{N-2} A(N-2)
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < g.order; ++n) dims[n] = g.ranks[n];
+  const double* cur = w.G64;
+  double* bufs[2] = {w.tA, w.tB};
+  int which = 0;
+  for (int m = 0; m < g.order - 1; ++m) {
+    launch_ttm(cur, dims, g.order, m, w.A64 + g.qoff[m], g.dims[m], false, bufs[which], st);
+    dims[m] = g.dims[m];
+    cur = bufs[which];
+    which ^= 1;
+  }
+  launch_loss_stream(g, p->X, p->dtype, p->mask, cur, w.A64 + g.qoff[g.order - 1], w.psq, w.pcnt,
+                     kLossParts, st);
+  launch_sq_reduce(g.d, core, p->dtype, w.preg, 64, st);
+  for (int n = 0; n < g.order; ++n)
+    launch_sq_reduce(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.preg + 64 * (n + 1), 64,
+                     st);
+  launch_loss_final(w.psq, w.pcnt, kLossParts, w.preg, 64 * (g.order + 1), p->lambda, out, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+}  // extern "C"

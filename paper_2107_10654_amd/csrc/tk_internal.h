@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 HIP library behind include/tucker.h.
+// Device helpers, kernel launch wrappers and the workspace carving shared by
+// the entry points in tk_api.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "tucker.h"
+
+namespace tk {
+
+constexpr int kMaxOrder = TK_MAX_ORDER;
+constexpr int kMaxRank = TK_MAX_RANK;
+constexpr int kBlock = 256;
+
+// Problem geometry passed by value to kernels.
+struct Geom {
+  int32_t order;
+  int32_t ranks[kMaxOrder];
+  int64_t dims[kMaxOrder];
+  int64_t strides[kMaxOrder];   // row-major element strides of X
+  int64_t off[kMaxOrder];       // offsets of mode n in concatenated per-mode arrays
+  int64_t qoff[kMaxOrder];      // offsets of mode n in concatenated I_n x R_n row arrays
+  int64_t roff[kMaxOrder];      // offsets of mode n in concatenated R_n x R_n arrays
+  int64_t total_rows;           // sum I_n
+  int64_t total_q;              // sum I_n R_n
+  int64_t total_rr;             // sum R_n^2
+  int64_t numel;                // prod I_n
+  int64_t d;                    // prod R_n
+};
+
+Geom make_geom(const tk_problem* p);
+
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Carver {
+  char* base;
+  size_t used;
+  explicit Carver(void* b) : base(static_cast<char*>(b)), used(0) {}
+  template <class T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* r = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; all enqueue on `st` and never synchronise)
+
+// Leverage scores / tables / whitening (tk_leverage.hip).
+// L, Linv and P (= (L^T L)^{-1}) per mode at geom.roff; Q64 / Q32 whitened rows
+// at geom.qoff; scores and cdf at geom.off.
+void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, double* scores,
+                     uint64_t* cdf, double* L, double* Linv, double* P, double* Q64, float* Q32,
+                     int32_t* status, hipStream_t st);
+
+// Sampler (tk_sample.hip).
+void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
+                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st);
+
+// Gather x_t and mask bits: weff_t = w_t [obs], xw_t = w_t x_t [obs].
+void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,
+                   const int32_t* idx, const double* weight, int64_t s, double* weff, double* xw,
+                   unsigned int* missing, int32_t* status, hipStream_t st);
+
+// Sketched Gram of whitened rows (tk_gram.hip): partial Grams per sample split.
+struct GramPlan {
+  tk_dtype prec;
+  int tile;        // output tile edge
+  int bk;          // samples per LDS chunk
+  int ksplit;      // sample splits (partials)
+  int64_t chunk;   // samples per split
+  int64_t ntiles;  // lower-triangular tiles
+};
+GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override);
+size_t gram_partial_bytes(const Geom& g, const GramPlan& pl);
+void launch_gram(const Geom& g, const GramPlan& pl, const int32_t* idx, const double* weff,
+                 int64_t s, const double* Q64, const float* Q32, void* partials, hipStream_t st);
+// M = sum of partials (lower triangle) + lambda * ((x) P_n); FP64, full d x d row-major.
+void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, const double* P,
+                     double lambda, double* M, hipStream_t st);
+
+// out[r] = sum_t c_t q_t[r] (q_t the whitened Kronecker row), FP64, deterministic.
+int64_t rows_t_vec_chunks(const Geom& g, int64_t s);
+void launch_rows_t_vec(const Geom& g, const int32_t* idx, const double* c, int64_t s,
+                       const double* Q64, double* part, double* out, hipStream_t st);
+void launch_rows_t_vec_flag(const Geom& g, const int32_t* idx, const double* c, int64_t s,
+                            const double* Q64, double* part, double* out, const int32_t* done,
+                            hipStream_t st);
+// Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part holds
+// cdiv(d, 256) * s doubles.
+void launch_residual_coef(const Geom& g, const int32_t* idx, const double* xw, const double* weff,
+                          const double* h, int64_t s, const double* Q64, double* part, double* c,
+                          const int32_t* done, hipStream_t st);
+
+// Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag receives the
+// inverses of the nb x nb diagonal blocks; min_pivot one double.
+constexpr int kCholNb = 64;
+void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
+                     hipStream_t st);
+// Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
+// scratch of 2 * ceil(d/nb) + 2 words.
+void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,
+                       double* y_tmp, int32_t* flags, const int32_t* done, int32_t* status,
+                       hipStream_t st);
+
+// Small FP64 helpers (tk_small.hip).
+// T' = T x_mode M  for row-major T of shape dims (order n), M: J x dims[mode] (row-major)
+void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
+                int64_t J, bool transpose_M, double* out, hipStream_t st);
+// ttm over an input of element type dt (F32 or F64) -> FP64 output
+void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
+                    const double* M, int64_t J, bool transpose_M, double* out, hipStream_t st);
+void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
+                 hipStream_t st);
+void launch_copy_f64(int64_t n, const double* x, double* y, hipStream_t st);
+void launch_cast_out(int64_t n, const double* x, void* y, tk_dtype dt, hipStream_t st);
+void launch_cast_in(int64_t n, const void* x, tk_dtype dt, double* y, hipStream_t st);
+void launch_fill_i32(int64_t n, int32_t v, int32_t* p, hipStream_t st);
+void launch_fill_f64(int64_t n, double v, double* p, hipStream_t st);
+void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st);
+// Refinement bookkeeping: r -= lambda * ph; relative residual; convergence flag.
+void launch_refine_check(int64_t d, double* r, const double* ph, double lambda, const double* rhs,
+                         double tol, int32_t* done, int32_t* steps, double* relres, int count_step,
+                         hipStream_t st);
+void launch_info(double* info, int64_t s, const unsigned int* missing, const int32_t* steps,
+                 const double* relres, const double* min_pivot, hipStream_t st);
+// Cholesky pivot sanity of a refinement that did not converge.
+void launch_finish_refine(const int32_t* done, int refine_enabled, int32_t* status,
+                          hipStream_t st);
+
+// Exact path (tk_exact.hip).
+void launch_eig_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* V,
+                      double* lam, double* W, double* C, hipStream_t st);
+void launch_gram_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* C,
+                       hipStream_t st);
+void launch_kron_scale(const Geom& g, const double* lam_modes, double lambda, double* B,
+                       hipStream_t st);
+void launch_sq_reduce(int64_t n, const void* x, tk_dtype dt, double* part, int64_t nparts,
+                      hipStream_t st);
+void launch_loss_stream(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,
+                        const double* H, const double* AN, double* part_sq, double* part_cnt,
+                        int64_t nparts, hipStream_t st);
+void launch_loss_final(const double* part_sq, const double* part_cnt, int64_t nparts,
+                       const double* part_reg, int64_t nreg, double lambda, double* out,
+                       hipStream_t st);
+void launch_unfold_contract(const double* U, const double* V, int64_t P, int64_t I, int64_t A,
+                            int64_t Q, double* out, hipStream_t st);
+void launch_factor_solve(const double* KKt, const double* rhs, int64_t I, int R, double lambda,
+                         void* out, tk_dtype dt, int32_t* status, hipStream_t st);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace tk
+
+#define TK_HIP_CHECK(expr)                         \
+  do {                                             \
+    if ((expr) != hipSuccess) return TK_E_HIP;     \
+  } while (0)

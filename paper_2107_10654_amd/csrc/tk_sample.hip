@@ -1,0 +1,89 @@
+// Product-distribution sampling of multi-indices (Alg. 3 sampler; Lemma 4.1:
+// the leverage scores of K = A(1) (x) ... (x) A(N) are products of the
+// factor scores, so each mode is drawn independently; proof of Thm 4.2: one
+// binary search per mode over the mode's CDF).
+//
+// Random words come from Philox4x64-10 (Salmon et al., SC'11), a
+// counter-based generator: sample t needs no state shared with other
+// threads, and the draw is reproducible from (seed, counter, problem, t).
+// Key = (seed, 0); counter = (t, counter, problem, b); output word j of block
+// b drives mode 4b + j.  The uniform u = floor(r W_n / 2^64) lies in
+// [0, W_n) and the row is the first j with cdf_j > u.
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull;
+  constexpr uint64_t M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull;
+  constexpr uint64_t W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]);
+    const uint64_t lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* __restrict__ cdf,
+                                                        int64_t s, uint64_t seed,
+                                                        uint64_t counter, uint64_t problem,
+                                                        int32_t* __restrict__ idx,
+                                                        double* __restrict__ weight) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= s) return;
+  double acc = 1.0;
+  const int N = g.order;
+  for (int b = 0; b * 4 < N; ++b) {
+    uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, static_cast<uint64_t>(b)};
+    philox4x64_10(c, seed, 0ull);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = 4 * b + j;
+      if (n < N) {
+        const uint64_t* C = cdf + g.off[n];
+        const int64_t I = g.dims[n];
+        const uint64_t W = C[I - 1];
+        const uint64_t u = __umul64hi(c[j], W);
+        int64_t lo = 0, hi = I;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (C[mid] > u)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        if (lo > I - 1) lo = I - 1;  // only when W == 0 (rank-deficient factor)
+        const uint64_t wi = C[lo] - (lo > 0 ? C[lo - 1] : 0ull);
+        idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(lo);
+        // weight = prod_n W_n / w_i, in mode order, then / s
+        acc = acc * (static_cast<double>(W) / static_cast<double>(wi));
+      }
+    }
+  }
+  weight[t] = acc / static_cast<double>(s);
+}
+
+}  // namespace
+
+void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
+                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st) {
+  if (s <= 0) return;
+  hipLaunchKernelGGL(sample_kernel, dim3(static_cast<unsigned>(cdiv(s, kBlock))), dim3(kBlock), 0,
+                     st, g, cdf, s, seed, counter, problem, idx, weight);
+}
+
+}  // namespace tk

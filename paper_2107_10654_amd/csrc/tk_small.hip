@@ -1,0 +1,291 @@
+// Mode-n products and small FP64 helpers.
+//
+// n-mode product (Sec. 2): (T x_n M)[.., j, ..] = sum_i M[j, i] T[.., i, ..].
+// A row-major tensor is viewed as (P, I, Q) around mode n; every thread owns
+// one (p, q) fibre and produces all J outputs, so each input element is read
+// once and reads are coalesced along q.  When mode n is the last mode (Q = 1)
+// rows of the input are staged through LDS instead.
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+template <class T>
+__device__ inline double ldd(const T* p, int64_t i) {
+  return static_cast<double>(p[i]);
+}
+
+// Mat(j, i): M stored J x I (trans = false) or I x J (trans = true)
+__device__ inline double mat(const double* M, int64_t I, int64_t J, bool trans, int64_t j,
+                             int64_t i) {
+  return trans ? M[i * J + j] : M[j * I + i];
+}
+
+// outputs j in [j0, j0 + jn), jn <= JMAX
+template <class T, int JMAX>
+__global__ __launch_bounds__(kBlock) void ttm_fibre_kernel(const T* __restrict__ in, int64_t P,
+                                                           int64_t I, int64_t Q,
+                                                           const double* __restrict__ M, int64_t J,
+                                                           bool trans, int64_t j0, int jn,
+                                                           double* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= P * Q) return;
+  const int64_t p = e / Q, q = e % Q;
+  double acc[JMAX];
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j) acc[j] = 0.0;
+  const T* src = in + p * I * Q + q;
+  for (int64_t i = 0; i < I; ++i) {
+    const double x = ldd(src, i * Q);
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j)
+      if (j < jn) acc[j] = fma(mat(M, I, J, trans, j0 + j, i), x, acc[j]);
+  }
+  double* dst = out + p * J * Q + q;
+#pragma unroll
+  for (int j = 0; j < JMAX; ++j)
+    if (j < jn) dst[(j0 + j) * Q] = acc[j];
+}
+
+// Q == 1: out[p][j] = sum_i Mat(j,i) in[p][i]; 64 rows per workgroup, i in chunks of 64.
+template <class T>
+__global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ in, int64_t P,
+                                                          int64_t I, const double* __restrict__ M,
+                                                          int64_t J, bool trans,
+                                                          double* __restrict__ out) {
+  __shared__ double Xs[64][65];
+  __shared__ double Ms[64][kMaxRank + 1];
+  const int tid = threadIdx.x;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int pr = tid & 63, jq = tid >> 6;  // row, quarter of the outputs
+  constexpr int JPT = kMaxRank / 4;
+  double acc[JPT];
+#pragma unroll
+  for (int k = 0; k < JPT; ++k) acc[k] = 0.0;
+  for (int64_t i0 = 0; i0 < I; i0 += 64) {
+    const int ic = static_cast<int>((I - i0) < 64 ? (I - i0) : 64);
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += kBlock) {
+      const int r = e / 64, c = e % 64;
+      const int64_t p = p0 + r;
+      Xs[r][c] = (p < P && c < ic) ? ldd(in, p * I + i0 + c) : 0.0;
+    }
+    for (int e = tid; e < 64 * J; e += kBlock) {
+      const int c = static_cast<int>(e / J), j = static_cast<int>(e % J);
+      Ms[c][j] = c < ic ? mat(M, I, J, trans, j, i0 + c) : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < ic; ++c) {
+      const double x = Xs[pr][c];
+#pragma unroll
+      for (int k = 0; k < JPT; ++k) {
+        const int j = jq + 4 * k;
+        if (j < J) acc[k] = fma(Ms[c][j], x, acc[k]);
+      }
+    }
+  }
+  const int64_t p = p0 + pr;
+  if (p < P) {
+#pragma unroll
+    for (int k = 0; k < JPT; ++k) {
+      const int j = jq + 4 * k;
+      if (j < J) out[p * J + j] = acc[k];
+    }
+  }
+}
+
+template <class T>
+void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const double* M,
+                  int64_t J, bool trans, double* out, hipStream_t st) {
+  int64_t P = 1, Q = 1;
+  for (int m = 0; m < mode; ++m) P *= dims[m];
+  for (int m = mode + 1; m < order; ++m) Q *= dims[m];
+  const int64_t I = dims[mode];
+  if (Q == 1 && J <= kMaxRank) {
+    hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
+                       0, st, in, P, I, M, J, trans, out);
+    return;
+  }
+  const dim3 grid(static_cast<unsigned>(cdiv(P * Q, kBlock)));
+  for (int64_t j0 = 0; j0 < J; j0 += 64) {
+    const int jn = static_cast<int>((J - j0) < 64 ? (J - j0) : 64);
+    if (jn <= 8)
+      hipLaunchKernelGGL((ttm_fibre_kernel<T, 8>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
+                         trans, j0, jn, out);
+    else if (jn <= 16)
+      hipLaunchKernelGGL((ttm_fibre_kernel<T, 16>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
+                         trans, j0, jn, out);
+    else if (jn <= 32)
+      hipLaunchKernelGGL((ttm_fibre_kernel<T, 32>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
+                         trans, j0, jn, out);
+    else
+      hipLaunchKernelGGL((ttm_fibre_kernel<T, 64>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
+                         trans, j0, jn, out);
+  }
+}
+
+__global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x,
+                            double* __restrict__ y, const int32_t* done) {
+  if (done && *done) return;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+
+template <class To, class From>
+__global__ void cast_kernel(int64_t n, const From* __restrict__ x, To* __restrict__ y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) y[i] = static_cast<To>(x[i]);
+}
+
+template <class T>
+__global__ void fill_kernel(int64_t n, T v, T* __restrict__ p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// r <- r - lambda * ph (when ph != null); relres = ||r|| / ||rhs||; done when <= tol.
+__global__ __launch_bounds__(1024) void refine_check_kernel(int64_t d, double* __restrict__ r,
+                                                            const double* __restrict__ ph,
+                                                            double lambda,
+                                                            const double* __restrict__ rhs,
+                                                            double tol, int32_t* done,
+                                                            int32_t* steps, double* relres,
+                                                            int count_step) {
+  if (*done) return;
+  __shared__ double s1[1024], s2[1024];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    double v = r[i];
+    if (ph) {
+      v = fma(-lambda, ph[i], v);
+      r[i] = v;
+    }
+    a = fma(v, v, a);
+    b = fma(rhs[i], rhs[i], b);
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double rel = s2[0] > 0.0 ? sqrt(s1[0] / s2[0]) : sqrt(s1[0]);
+    *relres = rel;
+    if (rel <= tol) {
+      *done = 1;
+    } else if (count_step) {
+      *steps += 1;
+    }
+  }
+}
+
+__global__ void info_kernel(double* info, int64_t s, const unsigned int* missing,
+                            const int32_t* steps, const double* relres, const double* min_pivot) {
+  if (threadIdx.x != 0) return;
+  info[0] = static_cast<double>(s);
+  info[1] = missing ? static_cast<double>(*missing) : 0.0;
+  info[2] = steps ? static_cast<double>(*steps) : 0.0;
+  info[3] = relres ? *relres : 0.0;
+  info[4] = min_pivot ? *min_pivot : 0.0;
+  info[5] = info[6] = info[7] = 0.0;
+}
+
+__global__ void finish_refine_kernel(const int32_t* done, int refine_enabled, int32_t* status) {
+  if (threadIdx.x == 0 && refine_enabled && !*done)
+    atomicMax(status, static_cast<int32_t>(TK_E_NO_CONVERGE));
+}
+
+}  // namespace
+
+void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
+                int64_t J, bool transpose_M, double* out, hipStream_t st) {
+  ttm_dispatch<double>(T, dims, order, mode, M, J, transpose_M, out, st);
+}
+
+void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
+                    const double* M, int64_t J, bool transpose_M, double* out, hipStream_t st) {
+  if (dt == TK_F64)
+    ttm_dispatch<double>(static_cast<const double*>(T), dims, order, mode, M, J, transpose_M, out,
+                         st);
+  else
+    ttm_dispatch<float>(static_cast<const float*>(T), dims, order, mode, M, J, transpose_M, out,
+                        st);
+}
+
+void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpy_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock))), dim3(kBlock), 0, st,
+                     n, a, x, y, done);
+}
+
+void launch_copy_f64(int64_t n, const double* x, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((cast_kernel<double, double>), dim3(static_cast<unsigned>(cdiv(n, kBlock))),
+                     dim3(kBlock), 0, st, n, x, y);
+}
+
+void launch_cast_out(int64_t n, const double* x, void* y, tk_dtype dt, hipStream_t st) {
+  if (n <= 0) return;
+  const dim3 grid(static_cast<unsigned>(cdiv(n, kBlock)));
+  if (dt == TK_F64)
+    hipLaunchKernelGGL((cast_kernel<double, double>), grid, dim3(kBlock), 0, st, n, x,
+                       static_cast<double*>(y));
+  else
+    hipLaunchKernelGGL((cast_kernel<float, double>), grid, dim3(kBlock), 0, st, n, x,
+                       static_cast<float*>(y));
+}
+
+void launch_cast_in(int64_t n, const void* x, tk_dtype dt, double* y, hipStream_t st) {
+  if (n <= 0) return;
+  const dim3 grid(static_cast<unsigned>(cdiv(n, kBlock)));
+  if (dt == TK_F64)
+    hipLaunchKernelGGL((cast_kernel<double, double>), grid, dim3(kBlock), 0, st, n,
+                       static_cast<const double*>(x), y);
+  else
+    hipLaunchKernelGGL((cast_kernel<double, float>), grid, dim3(kBlock), 0, st, n,
+                       static_cast<const float*>(x), y);
+}
+
+void launch_fill_i32(int64_t n, int32_t v, int32_t* p, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<int32_t>, dim3(static_cast<unsigned>(cdiv(n, kBlock))),
+                     dim3(kBlock), 0, st, n, v, p);
+}
+
+void launch_fill_f64(int64_t n, double v, double* p, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<double>, dim3(static_cast<unsigned>(cdiv(n, kBlock))),
+                     dim3(kBlock), 0, st, n, v, p);
+}
+
+void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<uint32_t>, dim3(static_cast<unsigned>(cdiv(n, kBlock))),
+                     dim3(kBlock), 0, st, n, v, p);
+}
+
+void launch_refine_check(int64_t d, double* r, const double* ph, double lambda, const double* rhs,
+                         double tol, int32_t* done, int32_t* steps, double* relres, int count_step,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1024), 0, st, d, r, ph, lambda, rhs, tol,
+                     done, steps, relres, count_step);
+}
+
+void launch_info(double* info, int64_t s, const unsigned int* missing, const int32_t* steps,
+                 const double* relres, const double* min_pivot, hipStream_t st) {
+  hipLaunchKernelGGL(info_kernel, dim3(1), dim3(64), 0, st, info, s, missing, steps, relres,
+                     min_pivot);
+}
+
+void launch_finish_refine(const int32_t* done, int refine_enabled, int32_t* status,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(finish_refine_kernel, dim3(1), dim3(64), 0, st, done, refine_enabled, status);
+}
+
+}  // namespace tk

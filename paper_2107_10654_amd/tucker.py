@@ -1,0 +1,280 @@
+"""Python binding of the gfx950 library (same names as the C ABI, minus the prefix).
+
+PyTorch supplies device memory and the current stream; every computation runs
+in the HIP kernels of ``libtucker_hip.so``.  Functions take CUDA (HIP) tensors:
+X is row-major with shape (I_1, ..., I_N), factor n is (I_n, R_n), the core is
+(R_1, ..., R_N); float64 or float32, all of one dtype.
+
+``check=True`` synchronises the stream after the call and raises
+``TuckerError`` when the library reported a data-dependent failure (not
+positive definite, rank-deficient factor, refinement not converged).
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.TK_F64, torch.float32: L.TK_F32}
+PRECISIONS = {"f64": L.TK_F64, "f32": L.TK_F32, "bf16": L.TK_BF16}
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = int(code)
+        super().__init__(f"{where}: {L.STATUS_NAMES.get(self.code, self.code)}")
+
+
+def _raise_if(code, where):
+    if code != 0:
+        raise TuckerError(code, where)
+
+
+_ws = {}
+_status = {}
+
+
+def _workspace(nbytes, device):
+    key = (device.index if device.index is not None else torch.cuda.current_device())
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws[key] = buf
+    return buf
+
+
+def _status_word(device):
+    key = (device.index if device.index is not None else torch.cuda.current_device())
+    s = _status.get(key)
+    if s is None:
+        s = torch.zeros(1, dtype=torch.int32, device=device)
+        _status[key] = s
+    return s
+
+
+def release_workspace():
+    """Free the cached workspace buffers."""
+    _ws.clear()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_tensor(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def make_problem(X, factors, lam, mask=None):
+    """Fill a TkProblem from tensors (X may be None for leverage scores)."""
+    factors = list(factors)
+    N = len(factors)
+    if not 1 <= N <= L.MAX_ORDER:
+        raise ValueError("order must be 1..8")
+    dtype = factors[0].dtype
+    if dtype not in _DT:
+        raise TypeError("factors must be float64 or float32")
+    p = L.TkProblem()
+    p.order = N
+    p.dtype = _DT[dtype]
+    p.lam = float(lam)
+    for n, A in enumerate(factors):
+        _check_tensor(A, f"factor {n}", dtype)
+        if A.dim() != 2:
+            raise ValueError("factors must be 2-D")
+        p.dims[n] = A.shape[0]
+        p.ranks[n] = A.shape[1]
+        p.factors[n] = A.data_ptr()
+    if X is not None:
+        _check_tensor(X, "X", dtype)
+        if tuple(X.shape) != tuple(A.shape[0] for A in factors):
+            raise ValueError(f"X shape {tuple(X.shape)} does not match the factors")
+        p.X = X.data_ptr()
+    if mask is not None:
+        _check_tensor(mask, "mask", torch.int32)
+        need = (int(torch.tensor(X.shape).prod()) + 31) // 32
+        if mask.numel() < need:
+            raise ValueError(f"mask needs {need} words")
+        p.mask = mask.data_ptr()
+    return p
+
+
+def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1):
+    o = L.TkSketchOpts()
+    o.num_samples = int(samples) if samples is not None else 0
+    o.eps, o.delta = float(eps), float(delta)
+    o.seed = int(seed) & ((1 << 64) - 1)
+    o.counter = int(counter) & ((1 << 64) - 1)
+    o.problem = int(problem) & ((1 << 64) - 1)
+    o.gram_precision = PRECISIONS[precision]
+    o.refine_max = int(refine_max)
+    o.refine_tol = float(refine_tol)
+    return o
+
+
+def _finish(device, status, where, check):
+    if check:
+        torch.cuda.current_stream(device).synchronize()
+        _raise_if(int(status.item()), where)
+
+
+def sample_count(d, eps, delta):
+    """Alg. 1 sample count with beta' = 1/2."""
+    return int(L.load().tucker_sample_count(int(d), float(eps), float(delta)))
+
+
+def leverage_scores(factors, check=True):
+    """Per-mode leverage scores (concatenated float64) and integer CDFs (int64 view of uint64)."""
+    lib = L.load()
+    p = make_problem(None, factors, 0.0)
+    dev = factors[0].device
+    total = sum(A.shape[0] for A in factors)
+    scores = torch.empty(total, dtype=torch.float64, device=dev)
+    cdf = torch.empty(total, dtype=torch.int64, device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_LEVERAGE)
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_leverage_scores(ctypes.byref(p), _ptr(scores), _ptr(cdf), _ptr(st),
+                                         _ptr(ws), ws.numel(), _stream()), "leverage_scores")
+    _finish(dev, st, "leverage_scores", check)
+    return scores, cdf
+
+
+def sample(dims, cdf, s, seed, counter=0, problem=0):
+    """Product-distribution samples: idx (N, s) int32 and weight (s,) float64."""
+    lib = L.load()
+    _check_tensor(cdf, "cdf", torch.int64)
+    dev = cdf.device
+    N = len(dims)
+    idx = torch.empty((N, int(s)), dtype=torch.int32, device=dev)
+    w = torch.empty(int(s), dtype=torch.float64, device=dev)
+    dims_c = (ctypes.c_int64 * N)(*[int(v) for v in dims])
+    _raise_if(lib.tucker_sample(N, dims_c, _ptr(cdf), int(s), int(seed) & ((1 << 64) - 1),
+                                int(counter), int(problem), _ptr(idx), _ptr(w), _stream()),
+              "sample")
+    return idx, w
+
+
+def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0, precision="f64",
+                         mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
+                         return_samples=False, return_info=False, check=True, out=None):
+    """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info)."""
+    lib = L.load()
+    p = make_problem(X, factors, lam, mask)
+    o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol)
+    dev = X.device
+    N = len(factors)
+    s = int(samples) if samples else sample_count(
+        int(torch.tensor([A.shape[1] for A in factors]).prod()), 0.1, 0.1)
+    if idx is not None:
+        _check_tensor(idx, "idx", torch.int32)
+        _check_tensor(weight, "weight", torch.float64)
+        if tuple(idx.shape) != (N, s) or weight.numel() != s:
+            raise ValueError("idx must be (N, s) and weight (s,)")
+    core = out if out is not None else torch.empty([A.shape[1] for A in factors], dtype=X.dtype,
+                                                   device=dev)
+    idx_out = w_out = None
+    if return_samples and idx is None:
+        idx_out = torch.empty((N, s), dtype=torch.int32, device=dev)
+        w_out = torch.empty(s, dtype=torch.float64, device=dev)
+    info = torch.empty(L.INFO_LEN, dtype=torch.float64, device=dev) if return_info else None
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), ctypes.byref(o), L.CALL_SKETCHED)
+    if nb == 0:
+        raise ValueError("unsupported problem for the sketched update")
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_core_update_sketched(ctypes.byref(p), ctypes.byref(o), _ptr(idx),
+                                              _ptr(weight), _ptr(idx_out), _ptr(w_out), _ptr(core),
+                                              _ptr(st), _ptr(info), _ptr(ws), ws.numel(),
+                                              _stream()), "core_update_sketched")
+    _finish(dev, st, "core_update_sketched", check)
+    res = [core]
+    if return_samples:
+        res += [idx if idx is not None else idx_out, weight if weight is not None else w_out]
+    if return_info:
+        res.append(info)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def core_update_exact(X, factors, lam, check=True, out=None):
+    """Exact core update (eigen form of the Kronecker normal equations)."""
+    lib = L.load()
+    p = make_problem(X, factors, lam)
+    dev = X.device
+    core = out if out is not None else torch.empty([A.shape[1] for A in factors], dtype=X.dtype,
+                                                   device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_EXACT)
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_core_update_exact(ctypes.byref(p), _ptr(core), _ptr(st), _ptr(ws),
+                                           ws.numel(), _stream()), "core_update_exact")
+    _finish(dev, st, "core_update_exact", check)
+    return core
+
+
+def factor_update(X, G, factors, mode, lam, out=None, check=True):
+    """Row-wise ridge update of factor `mode` (Alg. 2); returns the new factor."""
+    lib = L.load()
+    p = make_problem(X, factors, lam)
+    _check_tensor(G, "core", X.dtype)
+    dev = X.device
+    A = out if out is not None else torch.empty_like(factors[mode])
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_FACTOR)
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_factor_update(ctypes.byref(p), _ptr(G), int(mode), _ptr(A), _ptr(st),
+                                       _ptr(ws), ws.numel(), _stream()), "factor_update")
+    _finish(dev, st, "factor_update", check)
+    return A
+
+
+def loss(X, G, factors, lam, mask=None, sync=True):
+    """(L, sum of squared residuals, observed count) of the regularised Tucker loss (Sec. 2)."""
+    lib = L.load()
+    p = make_problem(X, factors, lam, mask)
+    _check_tensor(G, "core", X.dtype)
+    dev = X.device
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_LOSS)
+    ws = _workspace(nb, dev)
+    _raise_if(lib.tucker_loss(ctypes.byref(p), _ptr(G), _ptr(out), _ptr(ws), ws.numel(), _stream()),
+              "loss")
+    if not sync:
+        return out
+    v = out.cpu().tolist()
+    return v[0], v[1], v[2]
+
+
+def als(X, G0, factors0, lam, iters, core="exact", samples=None, seed=0, precision="f64",
+        record=None):
+    """Alg. 2 on the GPU: factor updates 1..N then the core (exact or sampled, counter = iteration).
+
+    Returns (G, factors, history) with history[k] = (loss, rmse) after iteration k.
+    """
+    G = G0.clone()
+    F = [A.clone() for A in factors0]
+    hist = []
+    for it in range(iters):
+        for n in range(len(F)):
+            F[n] = factor_update(X, G, F, n, lam)
+            if record is not None:
+                record.append(("factor", it, n, loss(X, G, F, lam)))
+        if core == "exact":
+            G = core_update_exact(X, F, lam)
+        else:
+            G = core_update_sketched(X, F, lam, samples, seed=seed, counter=it,
+                                     precision=precision)
+        Lv, sq, cnt = loss(X, G, F, lam)
+        hist.append((Lv, (sq / cnt) ** 0.5))
+        if record is not None:
+            record.append(("core", it, -1, (Lv, sq, cnt)))
+    return G, F, hist

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Bars (written per test):
+* integer work (CDF tables, sample indices) and the sample weights: bit-exact;
+* FP64 mode: relative error of the core <= 1e-10 (solutions of the same
+  sketched system computed in a different order; the system's condition
+  number here is < 1e3, so 1e-10 leaves ample room above rounding);
+* FP32 / BF16 Gram with FP64 refinement: relative error <= 1e-9 after the
+  refinement reports convergence to 1e-13.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def tk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2107_10654_amd as tk_mod
+    return tk_mod
+
+
+def T(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def tables_of(factors):
+    return [oracle.cdf_table(oracle.leverage_scores(A)) for A in factors]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SHAPES = [
+    ((23, 19, 17), (3, 4, 5)),        # d = 60, one ragged tile
+    ((41, 37, 29), (5, 6, 7)),        # d = 210, several tiles and a ragged tail
+    ((13, 11, 9, 7), (2, 3, 2, 3)),   # order 4
+    ((50,), (7,)),                    # order 1
+    ((30, 20), (1, 9)),               # a rank-1 mode
+    ((12, 10, 11), (4, 5, 1)),        # last rank 1
+]
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_leverage_scores_and_tables(tk, dims, ranks, dtype):
+    F = workloads.random_factors(dims, ranks, seed=1, kind="gaussian", dtype=dtype)
+    scores, cdf = tk.leverage_scores([T(A) for A in F])
+    scores, cdf = scores.cpu().numpy(), cdf.cpu().numpy().view(np.uint64)
+    off = 0
+    for A in F:
+        I = A.shape[0]
+        ref = oracle.leverage_scores(A.astype(np.float64))
+        np.testing.assert_allclose(scores[off:off + I], ref, rtol=1e-11, atol=1e-13)
+        _, C = oracle.cdf_table(ref)
+        mism = int((cdf[off:off + I] != C).sum())
+        assert mism == 0, f"{mism} CDF entries differ"
+        off += I
+
+
+@pytest.mark.parametrize("dims", [(23, 19, 17), (41, 37, 29, 5), (7, 5, 6, 4, 3, 5), (300,)])
+@pytest.mark.parametrize("s", [1, 17, 4099])
+def test_sampler_bit_exact(tk, dims, s):
+    ranks = tuple(min(3, I) for I in dims)
+    F = workloads.random_factors(dims, ranks, seed=2, kind="gaussian")
+    tabs = tables_of(F)
+    cdf = T(np.concatenate([C for _, C in tabs]).view(np.int64))
+    for seed, counter, problem in [(0, 0, 0), (12345, 7, 3), (2 ** 63 + 5, 2 ** 40, 1)]:
+        idx, w = tk.sample(dims, cdf, s, seed, counter, problem)
+        ridx, rw = oracle.sample(tabs, s, seed, counter, problem)
+        np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+        assert np.array_equal(w.cpu().numpy().view(np.uint64), rw.view(np.uint64)), "weights differ"
+
+
+def _sketch_case(dims, ranks, seed, dtype="f64", missing=None, factor="gaussian"):
+    p = workloads.tucker_tensor(dims, ranks, seed, dtype, factor=factor, noise=("sigma", 0.1),
+                                missing=missing)
+    F = [A.astype(workloads.NP_DTYPES[dtype]) for A in p["factors_true"]]
+    # move away from the generating factors so the fit is not trivial
+    rng = np.random.default_rng(seed + 7)
+    F = [(A + 0.1 * rng.standard_normal(A.shape)).astype(A.dtype) for A in F]
+    return p, F
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+def test_sketched_f64_matches_oracle(tk, dims, ranks):
+    p, F = _sketch_case(dims, ranks, 3)
+    lam, s = 1e-3, 3001
+    G, idx, w = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=11, counter=2,
+                                        precision="f64", return_samples=True)
+    Gr, ridx, rw, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 11, 2)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(w.cpu().numpy(), rw)
+    assert rel(G.cpu().numpy(), Gr) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+@pytest.mark.parametrize("dims,ranks", [((41, 37, 29), (5, 6, 7)), ((30, 28, 26), (8, 8, 4))])
+def test_sketched_low_precision_refined(tk, precision, dims, ranks):
+    p, F = _sketch_case(dims, ranks, 4, dtype="f32")
+    lam, s = 1e-2, 20000
+    X, FF = T(p["X"]), [T(A) for A in F]
+    G, info = tk.core_update_sketched(X, FF, lam, s, seed=5, precision=precision,
+                                      refine_max=30, refine_tol=1e-13, return_info=True)
+    info = info.cpu().numpy()
+    Gr, _, _, _ = oracle.fast_core_tensor_update(p["X"].astype(np.float64),
+                                                 [A.astype(np.float64) for A in F], lam, s, 5, 0)
+    assert info[3] <= 1e-13, info
+    # the core is returned in the problem dtype (f32): compare at f32 rounding
+    assert rel(G.cpu().numpy(), Gr) <= 1e-6
+    # the FP64 whitened solution before the cast: re-run in f64 problem dtype
+    X64, F64 = T(p["X"].astype(np.float64)), [T(A.astype(np.float64)) for A in F]
+    G64 = tk.core_update_sketched(X64, F64, lam, s, seed=5, precision=precision, refine_max=30,
+                                  refine_tol=1e-13)
+    assert rel(G64.cpu().numpy(), Gr) <= 1e-9
+
+
+def test_sketched_masked_matches_oracle(tk):
+    dims, ranks = (31, 27, 25), (4, 5, 3)
+    p, F = _sketch_case(dims, ranks, 6, missing=0.2)
+    lam, s = 1e-3, 5000
+    G, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=3,
+                                      mask=T(p["mask"].view(np.int32)), return_info=True)
+    Gr, idx, w, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 3, 0, mask=p["mask"])
+    assert rel(G.cpu().numpy(), Gr) <= 1e-10
+    _, obs = oracle.sampled_entries(p["X"], idx, p["mask"])
+    assert int(info[1].item()) == int((~obs).sum())
+
+
+def test_frozen_sample_set(tk):
+    p, F = _sketch_case((20, 18, 16), (3, 3, 3), 8)
+    lam = 0.05
+    tabs = tables_of(F)
+    idx, w = oracle.sample(tabs, 700, seed=9, counter=1)
+    G = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, 700, idx=T(idx), weight=T(w))
+    assert rel(G.cpu().numpy(), oracle.core_update_sketched(p["X"], F, lam, idx, w)) <= 1e-10
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_exact_core_matches_oracle(tk, dims, ranks, dtype):
+    p, F = _sketch_case(dims, ranks, 9, dtype=dtype)
+    lam = 1e-3
+    G = tk.core_update_exact(T(p["X"]), [T(A) for A in F], lam)
+    ref = oracle.core_update_exact(p["X"].astype(np.float64), [A.astype(np.float64) for A in F],
+                                   lam)
+    assert rel(G.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+def test_factor_update_matches_oracle(tk, dims, ranks):
+    p, F = _sketch_case(dims, ranks, 10)
+    lam = 1e-2
+    G = np.random.default_rng(1).standard_normal(ranks)
+    for n in range(len(dims)):
+        A = tk.factor_update(T(p["X"]), T(G), [T(B) for B in F], n, lam)
+        ref = oracle.factor_update(p["X"], G, F, n, lam)
+        assert rel(A.cpu().numpy(), ref) <= 1e-10, n
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+def test_loss_matches_oracle(tk, dims, ranks):
+    for missing in (None, 0.3):
+        p, F = _sketch_case(dims, ranks, 12, missing=missing)
+        G = np.random.default_rng(2).standard_normal(ranks)
+        mask = T(p["mask"].view(np.int32)) if missing else None
+        Lv, sq, cnt = tk.loss(T(p["X"]), T(G), [T(A) for A in F], 0.1, mask=mask)
+        rL, rrmse = oracle.loss(p["X"], G, F, 0.1, p["mask"])
+        assert abs(Lv - rL) <= 1e-10 * abs(rL)
+        assert abs((sq / cnt) ** 0.5 - rrmse) <= 1e-10 * rrmse
+
+
+def test_als_c1_exact_and_sketched(tk):
+    """C1 workload: 5 ALS iterations, exact and sketched cores, from the same U[0,1) start."""
+    prob = workloads.config_problem("c1")
+    cfg = prob["cfg"]
+    X = prob["X"]
+    G0, F0 = workloads.als_init(cfg["dims"], cfg["ranks"], 1000)
+    for core in ("exact", "sketched"):
+        Gg, Fg, hg = tk.als(T(X), T(G0), [T(A) for A in F0], cfg["lam"], cfg["als_iters"],
+                            core=core, samples=cfg["samples"], seed=0)
+        Gr, Fr, hr = oracle.als(X, G0, F0, cfg["lam"], cfg["als_iters"], core=core,
+                                s=cfg["samples"], seed=0)
+        for (a, ra), (b, rb) in zip(hg, hr):
+            assert abs(a - b) <= 1e-6 * abs(b), (core, hg, hr)
+        assert rel(Gg.cpu().numpy(), Gr) <= 1e-6
+
+
+def test_status_errors(tk):
+    from paper_2107_10654_amd import TuckerError
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((20, 4))
+    A[:, 3] = A[:, 0]
+    F = [T(A), T(rng.standard_normal((15, 3)))]
+    with pytest.raises(TuckerError, match="RANK_DEFICIENT"):
+        tk.leverage_scores(F)
+    X = T(rng.standard_normal((20, 15)))
+    good = [T(rng.standard_normal((20, 4))), F[1]]
+    idx = T(np.array([[0, 25], [1, 2]], dtype=np.int32))  # 25 is out of range
+    w = T(np.array([1.0, 1.0]))
+    with pytest.raises(TuckerError, match="E_ARG"):
+        tk.core_update_sketched(X, good, 0.1, 2, idx=idx, weight=w)
+    # a following good call clears the status word
+    tk.core_update_sketched(X, good, 0.1, 64)
