@@ -41,6 +41,7 @@ extern "C" {
 #define TK_MAX_RANK 64     /* largest supported per-mode rank R_n */
 #define TK_Q_BITS 24       /* fixed-point bits of the integer sampling weights */
 #define TK_INFO_LEN 8      /* doubles written to dev_info by the sketched update */
+#define TK_NUM_STAGE_EVENTS 10 /* stage boundaries of the sketched update (tk_sketch_opts) */
 
 typedef enum { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2 } tk_dtype;
 
@@ -84,6 +85,12 @@ typedef struct {
                               accumulation, FP64 Cholesky, FP64 refinement. */
   int32_t refine_max;      /* max refinement steps (low-precision Gram only) */
   double refine_tol;       /* stop when ||r||_2 <= refine_tol * ||rhs||_2 */
+  void* const* stage_events; /* NULL, or TK_NUM_STAGE_EVENTS hipEvent_t handles created by the
+                                caller; the call records event k on `stream` at stage boundary k:
+                                0 start, 1 leverage scores and CDFs done, 2 sampling done,
+                                3 gather done, 4 sketched Gram done, 5 assembly and right side
+                                done, 6 Cholesky done, 7 first solve done, 8 refinement done,
+                                9 end */
 } tk_sketch_opts;
 
 /* Which call tucker_workspace_bytes() sizes. */

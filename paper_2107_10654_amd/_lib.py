@@ -10,6 +10,7 @@ MAX_ORDER = 8
 MAX_RANK = 64
 Q_BITS = 24
 INFO_LEN = 8
+NUM_STAGE_EVENTS = 10
 
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 CALL_LEVERAGE, CALL_SKETCHED, CALL_EXACT, CALL_FACTOR, CALL_LOSS, CALL_ADJOINT = range(6)
@@ -46,6 +47,7 @@ class TkSketchOpts(ctypes.Structure):
         ("gram_precision", ctypes.c_int32),
         ("refine_max", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
+        ("stage_events", ctypes.c_void_p),
     ]
 
 

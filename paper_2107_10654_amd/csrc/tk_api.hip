@@ -13,7 +13,10 @@ Geom make_geom(const tk_problem* p) {
   memset(&g, 0, sizeof(g));
   g.order = p->order;
   int64_t off = 0, qoff = 0, roff = 0, numel = 1, d = 1;
+  int32_t soff = 0;
   for (int n = 0; n < p->order; ++n) {
+    g.soff[n] = soff;
+    soff += p->ranks[n];
     g.ranks[n] = p->ranks[n];
     g.dims[n] = p->dims[n];
     g.off[n] = off;
@@ -35,6 +38,7 @@ Geom make_geom(const tk_problem* p) {
   g.total_rr = roff;
   g.numel = numel;
   g.d = d;
+  g.sum_r = soff;
   return g;
 }
 
@@ -45,8 +49,10 @@ constexpr int64_t kMaxD = 16384;
 tk_status check_shape(const tk_problem* p) {
   if (!p) return TK_E_ARG;
   if (p->order < 1 || p->order > kMaxOrder) return TK_E_SHAPE;
-  int64_t numel = 1, d = 1;
+  int64_t numel = 1, d = 1, sum_r = 0;
   for (int n = 0; n < p->order; ++n) {
+    sum_r += p->ranks[n] > 0 ? p->ranks[n] : 0;
+    if (sum_r > kMaxSumR) return TK_E_SHAPE;
     if (p->dims[n] < 1 || p->dims[n] > (int64_t(1) << 31) - 1) return TK_E_SHAPE;
     if (p->ranks[n] < 1 || p->ranks[n] > kMaxRank) return TK_E_SHAPE;
     if (p->ranks[n] > p->dims[n]) return TK_E_SHAPE;
@@ -112,7 +118,8 @@ struct SketchWS {
   double* ph_a;
   double* ph_b;
   double* vpart;
-  double* dpart;
+  double* rows64;
+  float* rows32;
   double* coef;
   int32_t* flags;
   int32_t* status;
@@ -141,8 +148,9 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.delta = c.take<double>(d);
   w.ph_a = c.take<double>(d);
   w.ph_b = c.take<double>(d);
-  w.vpart = c.take<double>(rows_t_vec_chunks(g, s) * d);
-  w.dpart = c.take<double>(cdiv(d, 256) * s);
+  w.vpart = c.take<double>(vec_part_doubles(g, s));
+  w.rows64 = c.take<double>(static_cast<size_t>(s) * g.sum_r);
+  w.rows32 = c.take<float>(static_cast<size_t>(s) * g.sum_r);
   w.coef = c.take<double>(s);
   w.flags = c.take<int32_t>(2 * nblk + 2);
   w.status = c.take<int32_t>(1);
@@ -404,7 +412,11 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   SketchWS w;
   carve_sketch(c, g, s, pl, w);
   int32_t* status = dev_status ? dev_status : w.status;
+  auto stage = [&](int k) {
+    if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
+  };
 
+  stage(0);
   launch_fill_i32(1, 0, status, st);
   launch_fill_i32(1, 0, w.done, st);
   launch_fill_i32(1, 0, w.steps, st);
@@ -415,6 +427,7 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
   launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
                   w.lev.Q64, w.lev.Q32, status, st);
+  stage(1);
   // 2. samples (Alg. 3 sampler) or the frozen set
   const int32_t* idx = idx_in;
   const double* weight = weight_in;
@@ -430,23 +443,30 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
     TK_HIP_CHECK(hipMemcpyAsync(weight_out, weight_in, sizeof(double) * s,
                                 hipMemcpyDeviceToDevice, st));
   }
+  stage(2);
   // 3. sampled entries (x_t, mask) and effective weights
   launch_gather(g, p->X, p->dtype, p->mask, idx, weight, s, w.weff, w.xw, w.missing, status, st);
+  stage(3);
+  launch_pregather(g, idx, w.weff, s, w.lev.Q64, w.rows64, w.rows32, st);
   // 4. sketched Gram on MFMA, plus lambda P
-  launch_gram(g, pl, idx, w.weff, s, w.lev.Q64, w.lev.Q32, w.gpart, st);
+  launch_gram(g, pl, w.rows64, w.rows32, w.weff, s, w.gpart, st);
+  stage(4);
   launch_assemble(g, pl, w.gpart, w.lev.P, p->lambda, w.M, st);
   // 5. right-hand side sum_t w_t x_t q_t (FP64)
-  launch_rows_t_vec(g, idx, w.xw, s, w.lev.Q64, w.vpart, w.rhs, st);
+  launch_rows_t_vec(g, w.rows64, w.xw, s, w.vpart, w.rhs, nullptr, st);
+  stage(5);
   // 6. FP64 Cholesky and solve
   launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, status, st);
+  stage(6);
   launch_copy_f64(g.d, w.rhs, w.h, st);
   launch_chol_solve(w.M, w.Linv_diag, g.d, w.h, w.ytmp, w.flags, nullptr, status, st);
+  stage(7);
   // 7. FP64 refinement (low-precision Gram) or one residual check (FP64 Gram)
   const bool refine = o->gram_precision != TK_F64;
   const int iters = refine ? o->refine_max : 0;
   for (int k = 0; k <= iters; ++k) {
-    launch_residual_coef(g, idx, w.xw, w.weff, w.h, s, w.lev.Q64, w.dpart, w.coef, w.done, st);
-    launch_rows_t_vec_flag(g, idx, w.coef, s, w.lev.Q64, w.vpart, w.r, w.done, st);
+    launch_residual_coef(g, w.rows64, w.xw, w.weff, w.h, s, w.vpart, w.coef, w.done, st);
+    launch_rows_t_vec(g, w.rows64, w.coef, s, w.vpart, w.r, w.done, st);
     launch_copy_f64(g.d, w.h, w.ph_a, st);
     const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, st);
     (void)ph;
@@ -458,11 +478,13 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
     }
   }
   if (refine) launch_finish_refine(w.done, 1, status, st);
+  stage(8);
   // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
   launch_copy_f64(g.d, w.h, w.ph_a, st);
   const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, st);
   launch_cast_out(g.d, gres, core_out, p->dtype, st);
   if (dev_info) launch_info(dev_info, s, w.missing, w.steps, w.relres, w.min_pivot, st);
+  stage(9);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 

@@ -18,6 +18,7 @@ constexpr int NB = kCholNb;
 constexpr int LDA = NB + 1;
 
 // ---- diagonal tile: L_kk and its inverse
+// 16 x 16 thread grid; no runtime integer division in the inner loops.
 __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
                                                            int64_t k,
                                                            double* __restrict__ Linv_diag,
@@ -27,55 +28,68 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
   __shared__ int bad;
   __shared__ double pmin;
   const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
   const int64_t o = k * NB;
   const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    const int i = e / NB, j = e % NB;
-    A[i * LDA + j] = (i < b && j <= i) ? M[(o + i) * d + o + j] : (i == j ? 1.0 : 0.0);
-  }
+  for (int i = ty; i < NB; i += 16)
+    for (int j = tx; j < NB; j += 16)
+      A[i * LDA + j] = (i < b && j <= i) ? M[(o + i) * d + o + j] : (i == j ? 1.0 : 0.0);
   if (tid == 0) {
     bad = 0;
     pmin = 1e308;
   }
   __syncthreads();
   for (int j = 0; j < b; ++j) {
+    // every thread reads the pivot; column j below the diagonal is scaled by the threads
+    // that own it, then the trailing triangle is updated
+    double piv = A[j * LDA + j];
+    const bool ok = piv > 0.0;
+    if (!ok) piv = 1.0;
+    const double ljj = sqrt(piv);
+    const double inv = 1.0 / ljj;
+    __syncthreads();
     if (tid == 0) {
-      double piv = A[j * LDA + j];
-      if (!(piv > 0.0)) {
-        bad = 1;
-        piv = 1.0;
+      A[j * LDA + j] = ljj;
+      if (!ok) bad = 1;
+      pmin = fmin(pmin, ljj);
+    }
+    for (int i = j + 1 + tid; i < b; i += kBlock) A[i * LDA + j] *= inv;
+    __syncthreads();
+    for (int i = j + 1 + ty; i < b; i += 16) {
+      const double lij = A[i * LDA + j];
+      for (int c = j + 1 + tx; c <= i; c += 16) A[i * LDA + c] = fma(-lij, A[c * LDA + j], A[i * LDA + c]);
+    }
+    __syncthreads();
+  }
+  // inverse of the unit-scaled lower triangle, one column per thread group of 4:
+  // column c (thread c / 4 .. ), forward substitution with the dot split over 4 lanes
+  {
+    const int c = tid >> 2, part = tid & 3;
+    for (int i = 0; i < NB; ++i) {
+      double s = 0.0;
+      if (i > c)
+        for (int q = c + part; q < i; q += 4) s = fma(A[i * LDA + q], Li[q * LDA + c], s);
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if (part == 0) {
+        if (i < c)
+          Li[i * LDA + c] = 0.0;
+        else if (i == c)
+          Li[i * LDA + c] = 1.0 / A[i * LDA + i];
+        else
+          Li[i * LDA + c] = -s / A[i * LDA + i];
       }
-      const double l = sqrt(piv);
-      A[j * LDA + j] = l;
-      pmin = fmin(pmin, l);
+      // column c only depends on its own earlier entries: a wave-local dependency
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    const double ljj = A[j * LDA + j];
-    for (int i = j + 1 + tid; i < b; i += kBlock) A[i * LDA + j] /= ljj;
-    __syncthreads();
-    const int m = b - j - 1;
-    for (int e = tid; e < m * m; e += kBlock) {
-      const int i = j + 1 + e / m;
-      const int c = j + 1 + e % m;
-      if (c <= i) A[i * LDA + c] = fma(-A[i * LDA + j], A[c * LDA + j], A[i * LDA + c]);
-    }
-    __syncthreads();
   }
-  // inverse of the lower-triangular tile, row by row: Li[i][c] for c <= i
-  for (int i = 0; i < NB; ++i) {
-    for (int c = tid; c <= i; c += kBlock) {
-      double s = (c == i) ? 1.0 : 0.0;
-      for (int q = c; q < i; ++q) s = fma(-A[i * LDA + q], Li[q * LDA + c], s);
-      Li[i * LDA + c] = s / A[i * LDA + i];
-    }
-    __syncthreads();
-  }
+  __syncthreads();
   double* Lo = Linv_diag + k * NB * NB;
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    const int i = e / NB, j = e % NB;
-    Lo[e] = (j <= i) ? Li[i * LDA + j] : 0.0;
-    if (i < b && j <= i) M[(o + i) * d + o + j] = A[i * LDA + j];
-  }
+  for (int i = ty; i < NB; i += 16)
+    for (int j = tx; j < NB; j += 16) {
+      Lo[i * NB + j] = (j <= i) ? Li[i * LDA + j] : 0.0;
+      if (i < b && j <= i) M[(o + i) * d + o + j] = A[i * LDA + j];
+    }
   if (tid == 0) {
     if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
     // min pivot: monotone update through integer compare of non-negative doubles
@@ -193,14 +207,17 @@ __device__ inline bool wait_flag(const int32_t* f) {
 }
 
 // forward: L y = b.  flags[0] ticket, flags[2 + i] row-ready flags.
+// Thread (r, q): row r of the block row, column quarter q of each dependency
+// block.  The L block of the next dependency is loaded before waiting on its
+// flag, so a link of the dependency chain costs a flag hop and a few FMAs.
 __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ Linv_diag,
                                                             int64_t d, const double* __restrict__ b,
-                                                            double* y,
-                                                            int32_t* flags, const int32_t* done,
-                                                            int32_t* status) {
+                                                            double* y, int32_t* flags,
+                                                            const int32_t* done, int32_t* status) {
   if (done && *done) return;
   __shared__ int64_t row_blk;
+  __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
   __shared__ int ok;
@@ -213,22 +230,34 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
   const int64_t i = row_blk;
   const int64_t i0 = i * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
-  // thread layout: r = tid % 64 (row), q = tid / 64 (column quarter)
   const int r = tid & 63, q = tid >> 6;
+  {
+    const double* src = Linv_diag + i * NB * NB;
+    for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
+  }
+  const double* Lrow = L + (i0 + (r < rows ? r : 0)) * d + q * 16;
+  double cur[16], nxt[16];
+  if (i > 0) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) cur[c] = Lrow[c];
+  }
   double acc = 0.0;
   for (int64_t j = 0; j < i; ++j) {
-    if (tid == 0) {
+    if (j + 1 < i) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) nxt[c] = Lrow[(j + 1) * NB + c];
+    }
+    if (tid == 0 && ok) {
       if (!wait_flag(&flags[2 + j])) ok = 0;
     }
     __syncthreads();
     if (!ok) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const double* yj = y + j * NB;
-    if (r < rows) {
-      const double* Lr = L + (i0 + r) * d + j * NB + q * 16;
+    const double* yj = y + j * NB + q * 16;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc = fma(Lr[c], yj[q * 16 + c], acc);
-    }
+    for (int c = 0; c < 16; ++c) acc = fma(cur[c], yj[c], acc);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
   __syncthreads();
@@ -237,11 +266,14 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
     acc_s[tid] = bv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
   }
   __syncthreads();
-  if (tid < rows) {
-    const double* Li = Linv_diag + i * NB * NB + tid * NB;
+  // y_i = Li acc: row r, four partial sums over c
+  {
+    const int rr = tid >> 2, pp = tid & 3;
     double v = 0.0;
-    for (int c = 0; c <= tid; ++c) v = fma(Li[c], acc_s[c], v);
-    y[i0 + tid] = v;
+    for (int c = pp; c <= rr; c += 4) v = fma(Li[rr * LDA + c], acc_s[c], v);
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    if (pp == 0 && rr < rows) y[i0 + rr] = v;
   }
   __threadfence();
   __syncthreads();
@@ -256,11 +288,11 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
                                                             const double* __restrict__ Linv_diag,
                                                             int64_t d, int64_t nblk,
                                                             const double* __restrict__ y,
-                                                            double* x,
-                                                            int32_t* flags, const int32_t* done,
-                                                            int32_t* status) {
+                                                            double* x, int32_t* flags,
+                                                            const int32_t* done, int32_t* status) {
   if (done && *done) return;
   __shared__ int64_t row_blk;
+  __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
   __shared__ int ok;
@@ -274,11 +306,28 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   const int64_t i0 = i * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
   int32_t* fl = flags + 2 + nblk;
-  // acc[r] = sum_{j > i} sum_c L[j0 + c][i0 + r] x[j0 + c]; thread (r, quarter of c)
+  {
+    const double* src = Linv_diag + i * NB * NB;
+    for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
+  }
+  // acc[r] = sum_{j > i} sum_c L[j0 + c][i0 + r] x[j0 + c]; thread (r, quarter q of c)
   const int r = tid & 63, q = tid >> 6;
+  const int rc = r < rows ? r : 0;
+  auto load_blk = [&](int64_t j, double* v) {
+    const int64_t j0 = j * NB;
+    const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int cc = q * 16 + c;
+      v[c] = cc < rj ? L[(j0 + cc) * d + i0 + rc] : 0.0;
+    }
+  };
+  double cur[16], nxt[16];
+  if (i < nblk - 1) load_blk(nblk - 1, cur);
   double acc = 0.0;
   for (int64_t j = nblk - 1; j > i; --j) {
-    if (tid == 0) {
+    if (j - 1 > i) load_blk(j - 1, nxt);
+    if (tid == 0 && ok) {
       if (!wait_flag(&fl[j])) ok = 0;
     }
     __syncthreads();
@@ -286,10 +335,13 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int64_t j0 = j * NB;
     const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
-    if (r < rows) {
-      for (int c = q * 16; c < q * 16 + 16 && c < rj; ++c)
-        acc = fma(L[(j0 + c) * d + i0 + r], x[j0 + c], acc);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int cc = q * 16 + c;
+      if (cc < rj) acc = fma(cur[c], x[j0 + cc], acc);
     }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
   __syncthreads();
@@ -299,11 +351,13 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   }
   __syncthreads();
   // x_i = Li^T acc: x[r] = sum_{c >= r} Li[c][r] acc[c]
-  if (tid < rows) {
-    const double* Li = Linv_diag + i * NB * NB;
+  {
+    const int rr = tid >> 2, pp = tid & 3;
     double v = 0.0;
-    for (int c = tid; c < rows; ++c) v = fma(Li[c * NB + tid], acc_s[c], v);
-    x[i0 + tid] = v;
+    for (int c = rr + pp; c < rows; c += 4) v = fma(Li[c * LDA + rr], acc_s[c], v);
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    if (pp == 0 && rr < rows) x[i0 + rr] = v;
   }
   __threadfence();
   __syncthreads();

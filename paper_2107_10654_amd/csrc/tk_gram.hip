@@ -9,6 +9,9 @@
 //   out  = sum_t c_t q_t                 (rows_t_vec_kernel, FP64)
 //   c_t  = a_t - b_t (q_t . h)           (rows_dot_kernel, FP64)
 //
+// A pre-gather pass writes each sample's factor rows contiguously (one
+// row of sum_n R_n values per sample), so the hot kernels stream coalesced
+// chunks of samples and prefetch the next chunk while computing the current.
 // Kronecker rows are formed in LDS with one multiply per element: a design
 // index r splits into an outer index o = r / R_N (modes 1..N-1) and the last
 // mode's index r % R_N, so y_t[r] = O_t[o] * q^(N)_{i_N}[r % R_N] with
@@ -73,9 +76,6 @@ struct VarBF16 {
   __device__ static Op cvt(Src x) { return static_cast<__bf16>(x); }
 };
 
-struct QPtrs {
-  const void* p[kMaxOrder];  // whitened rows per mode (Src precision)
-};
 
 // lower-triangular tile index -> (ti, tj), ti >= tj
 __device__ inline void tri_index(int64_t tau, int64_t& ti, int64_t& tj) {
@@ -86,13 +86,35 @@ __device__ inline void tri_index(int64_t tau, int64_t& ti, int64_t& tj) {
   tj = tau - i * (i + 1) / 2;
 }
 
+// ------------------------------------------------------------------ pre-gather
+__global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t* __restrict__ idx,
+                                                           const double* __restrict__ weff,
+                                                           int64_t s,
+                                                           const double* __restrict__ Q64,
+                                                           double* __restrict__ rows64,
+                                                           float* __restrict__ rows32) {
+  const int SR = g.sum_r;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= s * SR) return;
+  const int64_t t = e / SR;
+  const int j = static_cast<int>(e - t * SR);
+  int n = 0;
+  while (n + 1 < g.order && j >= g.soff[n + 1]) ++n;
+  int32_t i = idx[static_cast<int64_t>(n) * s + t];
+  if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
+  const double v = Q64[g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n] + (j - g.soff[n])];
+  rows64[e] = v;
+  rows32[e] = static_cast<float>(n == 0 ? v * sqrt(weff[t]) : v);
+}
+
+// ------------------------------------------------------------------ Gram
 template <class V>
 struct GramSmem {
   static constexpr int T = V::TILE, BK = V::BK;
   static constexpr int NO = T + 1;  // outer indices a tile can touch (R_N >= 1)
-  int sidx[kMaxOrder][BK];
+  static constexpr int RS = kMaxSumR + 1;
+  typename V::Src rows[BK * RS];    // staged sample rows, row stride sum_r + 1
   typename V::Src sw[BK];
-  typename V::Src QL[kMaxRank][BK];
   typename V::Src OA[NO][BK];
   typename V::Src OB[NO][BK];
   unsigned char dig[2][NO][kMaxOrder];
@@ -102,22 +124,27 @@ struct GramSmem {
   alignas(16) typename V::Op YB[T * V::LDK];
 };
 
+// rows: per-sample rows in Src precision; prescaled: mode 0 already carries sqrt(weff)
 template <class V>
-__global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
-                                                      const int32_t* __restrict__ idx,
-                                                      const double* __restrict__ weff, int64_t s,
-                                                      int64_t chunk,
+__global__ __launch_bounds__(kBlock) void gram_kernel(Geom g,
+                                                      const typename V::Src* __restrict__ rows,
+                                                      const double* __restrict__ weff,
+                                                      int prescaled, int64_t s, int64_t chunk,
                                                       typename V::Out* __restrict__ part) {
   using Src = typename V::Src;
   using Op = typename V::Op;
   using Acc = typename V::Acc;
   constexpr int T = V::TILE, BK = V::BK, LDK = V::LDK;
+  constexpr int PF = (BK * kMaxSumR + kBlock - 1) / kBlock;  // prefetch registers
   __shared__ GramSmem<V> sm;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int N = g.order;
   const int RL = g.ranks[N - 1];
+  const int SR = g.sum_r;
+  const int RS = SR + 1;
+  const int sl = g.soff[N - 1];
   const int64_t d = g.d;
 
   int64_t ti, tj;
@@ -152,6 +179,33 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
     sm.rowl[side][i] = static_cast<short>(rr % RL);
   }
 
+  // chunk loader: BK consecutive sample rows (contiguous in global memory)
+  Src pf[PF];
+  auto fetch = [&](int64_t t0) {
+    const int64_t nvalid = ((sb - t0) < BK ? (sb - t0) : BK) * SR;
+    const Src* src = rows + t0 * SR;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * kBlock;
+      pf[k] = (e < nvalid) ? src[e] : Src(0);
+    }
+  };
+  auto commit = [&](int64_t t0) {
+    const int nval = BK * SR;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int e = tid + k * kBlock;
+      if (e < nval) {
+        const int t = e / SR, j = e - t * SR;
+        sm.rows[t * RS + j] = pf[k];
+      }
+    }
+    for (int t = tid; t < BK; t += kBlock) {
+      const int64_t tt = t0 + t;
+      sm.sw[t] = tt < sb ? (prescaled ? Src(1) : static_cast<Src>(sqrt(weff[tt]))) : Src(0);
+    }
+  };
+
   // wave sub-tile: 2 x 2 waves, each (T/2) x (T/2) = NB x NB MFMA blocks
   constexpr int WT = T / 2, NB = WT / V::MT;
   const int wr = wave >> 1, wc = wave & 1;
@@ -163,37 +217,23 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
 #pragma unroll
       for (int v = 0; v < V::NACC; ++v) acc[a][b][v] = 0;
 
+  if (sa < sb) {
+    fetch(sa);
+    commit(sa);
+  }
+  __syncthreads();
   for (int64_t t0 = sa; t0 < sb; t0 += BK) {
-    // (a) per-sample indices and sqrt weights
-    for (int e = tid; e < N * BK; e += kBlock) {
-      const int n = e / BK, t = e % BK;
-      const int64_t tt = t0 + t;
-      int32_t i = tt < sb ? idx[static_cast<int64_t>(n) * s + tt] : 0;
-      if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
-      sm.sidx[n][t] = i;
-    }
-    for (int t = tid; t < BK; t += kBlock) {
-      const int64_t tt = t0 + t;
-      sm.sw[t] = tt < sb ? static_cast<Src>(sqrt(weff[tt])) : Src(0);
-    }
-    __syncthreads();
-    // (b) last-mode rows and outer products
+    const bool more = t0 + BK < sb;
+    if (more) fetch(t0 + BK);
+    // (b) outer products O[oi][t] (mode 0 carries sqrt(weff) or sw)
     {
-      const Src* QLg = static_cast<const Src*>(qp.p[N - 1]);
-      for (int e = tid; e < RL * BK; e += kBlock) {
-        const int rl = e / BK, t = e % BK;
-        sm.QL[rl][t] = QLg[static_cast<int64_t>(sm.sidx[N - 1][t]) * RL + rl];
-      }
       const int nsides = diag ? 1 : 2;
       for (int side = 0; side < nsides; ++side) {
         Src(*O)[BK] = side == 0 ? sm.OA : sm.OB;
         for (int e = tid; e < no[side] * BK; e += kBlock) {
           const int oi = e / BK, t = e % BK;
-          Src v = sm.sw[t];
-          for (int n = 0; n < N - 1; ++n) {
-            const Src* Qn = static_cast<const Src*>(qp.p[n]);
-            v *= Qn[static_cast<int64_t>(sm.sidx[n][t]) * g.ranks[n] + sm.dig[side][oi][n]];
-          }
+          Src v = sm.sw[t];  // 1 when mode 0 is prescaled, sqrt(weff_t) otherwise
+          for (int n = 0; n < N - 1; ++n) v *= sm.rows[t * RS + g.soff[n] + sm.dig[side][oi][n]];
           O[oi][t] = v;
         }
       }
@@ -214,7 +254,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
             bf16x8 v;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-              v[k] = ok ? V::cvt(O[oi][tg + k] * sm.QL[rl][tg + k]) : static_cast<__bf16>(0.0f);
+              v[k] = ok ? V::cvt(O[oi][tg + k] * sm.rows[(tg + k) * RS + sl + rl])
+                        : static_cast<__bf16>(0.0f);
             *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
           }
         } else {
@@ -222,13 +263,13 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
             const int i = e / BK, t = e % BK;
             const bool ok = base + i < d;
             const int oi = sm.rowo[side][i], rl = sm.rowl[side][i];
-            Y[i * LDK + t] = ok ? V::cvt(O[oi][t] * sm.QL[rl][t]) : Op(0);
+            Y[i * LDK + t] = ok ? V::cvt(O[oi][t] * sm.rows[t * RS + sl + rl]) : Op(0);
           }
         }
       }
     }
     __syncthreads();
-    // (d) MFMA over the chunk
+    // (d) MFMA over the chunk; then stage the prefetched chunk
     const Op* YB = diag ? sm.YA : sm.YB;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += V::KT) {
@@ -246,6 +287,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g, QPtrs qp,
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = V::mma(af[a], bfr[b], acc[a][b]);
     }
+    if (more) commit(t0 + BK);
+    __syncthreads();
   }
 
   // store the tile of this split
@@ -324,101 +367,148 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Geom g, const T* __restr
 }
 
 // ------------------------------------------------------------------ rows^T c and rows . h
-constexpr int kVT = 256;  // design rows per workgroup
-constexpr int kVK = 16;   // samples per LDS chunk
-constexpr int kVO = kVT + 1;
+// FP64, contiguous sample rows.  A workgroup owns RW design rows (RW = min(1024,
+// 64 R_N), so at most 65 outer indices) and a split of the samples; thread
+// tid owns rows r0 + tid + 256 k (k < 4).
+constexpr int kVK = 32;      // samples per stage
+constexpr int kVO = 65;      // outer indices per workgroup
+constexpr int kVPF = (kVK * kMaxSumR + kBlock - 1) / kBlock;
 
 struct VecSmem {
-  int sidx[kMaxOrder][kVK];
+  double rows[kVK * (kMaxSumR + 1)];
   double sc[kVK];
-  double QL[kMaxRank][kVK];
   double O[kVO][kVK];
   unsigned char dig[kVO][kMaxOrder];
   double red[4][kVK];
 };
 
-__device__ inline void vec_setup(const Geom& g, VecSmem& sm, int64_t r0, int64_t& obase, int& no,
-                                 int& my_o, int& my_l, bool& my_ok) {
+struct VecGeo {
+  int64_t r0;
+  int rw;          // rows of this workgroup
+  int64_t obase;
+  int no;
+  int my_o[4], my_l[4];
+  bool my_ok[4];
+};
+
+__host__ __device__ inline int vec_rows_per_wg(const Geom& g) {
+  const int RL = g.ranks[g.order - 1];
+  const int rw = 64 * RL;
+  return rw < 1024 ? rw : 1024;
+}
+
+__device__ inline VecGeo vec_setup(const Geom& g, VecSmem& sm) {
+  VecGeo vg;
   const int N = g.order;
   const int RL = g.ranks[N - 1];
   const int64_t d = g.d;
-  const int64_t last = ((r0 + kVT < d) ? r0 + kVT : d) - 1;
-  obase = r0 / RL;
-  no = static_cast<int>(last / RL - obase + 1);
-  for (int oi = threadIdx.x; oi < no; oi += kBlock) {
-    int64_t o = obase + oi;
+  const int RW = vec_rows_per_wg(g);
+  vg.r0 = static_cast<int64_t>(blockIdx.x) * RW;
+  vg.rw = static_cast<int>((d - vg.r0) < RW ? (d - vg.r0) : RW);
+  vg.obase = vg.r0 / RL;
+  vg.no = static_cast<int>((vg.r0 + vg.rw - 1) / RL - vg.obase + 1);
+  for (int oi = threadIdx.x; oi < vg.no; oi += kBlock) {
+    int64_t o = vg.obase + oi;
     for (int n = N - 2; n >= 0; --n) {
       sm.dig[oi][n] = static_cast<unsigned char>(o % g.ranks[n]);
       o /= g.ranks[n];
     }
   }
-  const int64_t r = r0 + threadIdx.x;
-  my_ok = r < d;
-  const int64_t rr = my_ok ? r : d - 1;
-  my_o = static_cast<int>(rr / RL - obase);
-  my_l = static_cast<int>(rr % RL);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    vg.my_ok[k] = i < vg.rw;
+    const int64_t r = vg.r0 + (vg.my_ok[k] ? i : 0);
+    vg.my_o[k] = static_cast<int>(r / RL - vg.obase);
+    vg.my_l[k] = static_cast<int>(r % RL);
+  }
+  return vg;
 }
 
-// stage sample chunk: sidx, coefficient, QL, O (O includes the coefficient)
-__device__ inline void vec_stage(const Geom& g, VecSmem& sm, const QPtrs& qp,
-                                 const int32_t* idx, const double* coef, int64_t s, int64_t t0,
-                                 int64_t tend, int no) {
-  const int N = g.order;
-  const int RL = g.ranks[N - 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < N * kVK; e += kBlock) {
-    const int n = e / kVK, t = e % kVK;
+// stage samples [t0, t0 + kVK) of [.., tend): rows and coefficients into LDS
+__device__ inline void vec_fetch(const Geom& g, const double* rows, int64_t t0, int64_t tend,
+                                 double* pf) {
+  const int SR = g.sum_r;
+  const int64_t nvalid = ((tend - t0) < kVK ? (tend - t0) : kVK) * SR;
+  const double* src = rows + t0 * SR;
+#pragma unroll
+  for (int k = 0; k < kVPF; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    pf[k] = (e < nvalid) ? src[e] : 0.0;
+  }
+}
+
+__device__ inline void vec_commit(const Geom& g, VecSmem& sm, const double* pf,
+                                  const double* coef, int64_t t0, int64_t tend) {
+  const int SR = g.sum_r, RS = SR + 1;
+  const int nval = kVK * SR;
+#pragma unroll
+  for (int k = 0; k < kVPF; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    if (e < nval) {
+      const int t = e / SR, j = e - t * SR;
+      sm.rows[t * RS + j] = pf[k];
+    }
+  }
+  for (int t = threadIdx.x; t < kVK; t += kBlock) {
     const int64_t tt = t0 + t;
-    int32_t i = tt < tend ? idx[static_cast<int64_t>(n) * s + tt] : 0;
-    if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
-    sm.sidx[n][t] = i;
+    sm.sc[t] = tt < tend ? (coef ? coef[tt] : 1.0) : 0.0;
   }
-  for (int t = tid; t < kVK; t += kBlock) {
-    const int64_t tt = t0 + t;
-    sm.sc[t] = (tt < tend && coef) ? coef[tt] : (tt < tend ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const double* QLg = static_cast<const double*>(qp.p[N - 1]);
-  for (int e = tid; e < RL * kVK; e += kBlock) {
-    const int rl = e / kVK, t = e % kVK;
-    sm.QL[rl][t] = QLg[static_cast<int64_t>(sm.sidx[N - 1][t]) * RL + rl];
-  }
-  for (int e = tid; e < no * kVK; e += kBlock) {
+}
+
+// O[oi][t] = coef_t prod_{n < N-1} rows[t][soff_n + digit_n(o)]
+__device__ inline void vec_outer(const Geom& g, VecSmem& sm, const VecGeo& vg) {
+  const int N = g.order, RS = g.sum_r + 1;
+  for (int e = threadIdx.x; e < vg.no * kVK; e += kBlock) {
     const int oi = e / kVK, t = e % kVK;
     double v = sm.sc[t];
-    for (int n = 0; n < N - 1; ++n) {
-      const double* Qn = static_cast<const double*>(qp.p[n]);
-      v *= Qn[static_cast<int64_t>(sm.sidx[n][t]) * g.ranks[n] + sm.dig[oi][n]];
-    }
+    for (int n = 0; n < N - 1; ++n) v *= sm.rows[t * RS + g.soff[n] + sm.dig[oi][n]];
     sm.O[oi][t] = v;
   }
-  __syncthreads();
 }
 
-// part[chunk][r] = sum_{t in chunk} c_t q_t[r]
-__global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, QPtrs qp,
-                                                            const int32_t* __restrict__ idx,
+// part[split][r] = sum_{t in split} c_t q_t[r]
+__global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double* __restrict__ rows,
                                                             const double* __restrict__ c,
                                                             int64_t s, int64_t chunk,
                                                             double* __restrict__ part,
                                                             const int32_t* done) {
   if (done && *done) return;
   __shared__ VecSmem sm;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kVT;
-  int64_t obase;
-  int no, my_o, my_l;
-  bool my_ok;
-  vec_setup(g, sm, r0, obase, no, my_o, my_l, my_ok);
+  const VecGeo vg = vec_setup(g, sm);
+  const int RS = g.sum_r + 1, sl = g.soff[g.order - 1];
   const int64_t sa = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t sb = (sa + chunk < s) ? sa + chunk : s;
-  double acc = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double pf[kVPF];
+  if (sa < sb) {
+    vec_fetch(g, rows, sa, sb, pf);
+    vec_commit(g, sm, pf, c, sa, sb);
+  }
+  __syncthreads();
   for (int64_t t0 = sa; t0 < sb; t0 += kVK) {
-    vec_stage(g, sm, qp, idx, c, s, t0, sb, no);
+    const bool more = t0 + kVK < sb;
+    if (more) vec_fetch(g, rows, t0 + kVK, sb, pf);
+    vec_outer(g, sm, vg);
+    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < kVK; ++t) acc = fma(sm.O[my_o][t], sm.QL[my_l][t], acc);
+    for (int k = 0; k < 4; ++k) {
+      if (!vg.my_ok[k]) continue;
+      const double* Ok = sm.O[vg.my_o[k]];
+      const double* ql = sm.rows + sl + vg.my_l[k];
+      double a = acc[k];
+#pragma unroll 8
+      for (int t = 0; t < kVK; ++t) a = fma(Ok[t], ql[t * RS], a);
+      acc[k] = a;
+    }
+    __syncthreads();
+    if (more) vec_commit(g, sm, pf, c, t0 + kVK, sb);
     __syncthreads();
   }
-  if (my_ok) part[static_cast<int64_t>(blockIdx.y) * g.d + r0 + threadIdx.x] = acc;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (vg.my_ok[k])
+      part[static_cast<int64_t>(blockIdx.y) * g.d + vg.r0 + threadIdx.x + k * kBlock] = acc[k];
 }
 
 __global__ __launch_bounds__(kBlock) void sum_parts_kernel(const double* __restrict__ part,
@@ -434,40 +524,68 @@ __global__ __launch_bounds__(kBlock) void sum_parts_kernel(const double* __restr
 }
 
 // part[rchunk][t] = sum_{r in rchunk} h[r] q_t[r]
-__global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, QPtrs qp,
-                                                          const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* __restrict__ rows,
                                                           const double* __restrict__ h,
                                                           int64_t s, int64_t chunk,
                                                           double* __restrict__ part,
                                                           const int32_t* done) {
   if (done && *done) return;
   __shared__ VecSmem sm;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kVT;
-  int64_t obase;
-  int no, my_o, my_l;
-  bool my_ok;
-  vec_setup(g, sm, r0, obase, no, my_o, my_l, my_ok);
-  const double hr = my_ok ? h[r0 + threadIdx.x] : 0.0;
+  const VecGeo vg = vec_setup(g, sm);
+  const int RS = g.sum_r + 1, sl = g.soff[g.order - 1];
+  double hr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) hr[k] = vg.my_ok[k] ? h[vg.r0 + threadIdx.x + k * kBlock] : 0.0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t sa = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t sb = (sa + chunk < s) ? sa + chunk : s;
+  double pf[kVPF];
+  if (sa < sb) {
+    vec_fetch(g, rows, sa, sb, pf);
+    vec_commit(g, sm, pf, nullptr, sa, sb);
+  }
+  __syncthreads();
   for (int64_t t0 = sa; t0 < sb; t0 += kVK) {
-    vec_stage(g, sm, qp, idx, nullptr, s, t0, sb, no);
+    const bool more = t0 + kVK < sb;
+    if (more) vec_fetch(g, rows, t0 + kVK, sb, pf);
+    vec_outer(g, sm, vg);
+    __syncthreads();
+    double v[kVK];
 #pragma unroll
-    for (int t = 0; t < kVK; ++t) {
-      double v = hr * sm.O[my_o][t] * sm.QL[my_l][t];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) sm.red[wave][t] = v;
+    for (int t = 0; t < kVK; ++t) v[t] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!vg.my_ok[k]) continue;
+      const double* Ok = sm.O[vg.my_o[k]];
+      const double* ql = sm.rows + sl + vg.my_l[k];
+#pragma unroll
+      for (int t = 0; t < kVK; ++t) v[t] = fma(hr[k] * Ok[t], ql[t * RS], v[t]);
     }
+    // butterfly reduction over the wave: after the steps with masks 32..2 lane l
+    // holds sample (b5 b4 b3 b2 b1) of its lane index, summed over 32 lanes
+#pragma unroll
+    for (int w = kVK / 2, m = 32; w >= 1; w >>= 1, m >>= 1) {
+      const bool up = (lane & m) != 0;
+#pragma unroll
+      for (int j = 0; j < w; ++j) {
+        const double send = up ? v[j] : v[j + w];
+        const double keep = up ? v[j + w] : v[j];
+        v[j] = keep + __shfl_xor(send, m, 64);
+      }
+    }
+    v[0] += __shfl_xor(v[0], 1, 64);
+    const int tl = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+                   ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+    if ((lane & 1) == 0) sm.red[wave][tl] = v[0];
     __syncthreads();
     if (threadIdx.x < kVK) {
       const int64_t tt = t0 + threadIdx.x;
-      if (tt < sb) {
-        const double v = sm.red[0][threadIdx.x] + sm.red[1][threadIdx.x] +
-                         sm.red[2][threadIdx.x] + sm.red[3][threadIdx.x];
-        part[static_cast<int64_t>(blockIdx.x) * s + tt] = v;
-      }
+      if (tt < sb)
+        part[static_cast<int64_t>(blockIdx.x) * s + tt] =
+            sm.red[0][threadIdx.x] + sm.red[1][threadIdx.x] + sm.red[2][threadIdx.x] +
+            sm.red[3][threadIdx.x];
     }
+    if (more) vec_commit(g, sm, pf, nullptr, t0 + kVK, sb);
     __syncthreads();
   }
 }
@@ -524,25 +642,25 @@ size_t gram_partial_bytes(const Geom& g, const GramPlan& pl) {
   return static_cast<size_t>(pl.ksplit) * static_cast<size_t>(g.d) * static_cast<size_t>(g.d) * elt;
 }
 
-void launch_gram(const Geom& g, const GramPlan& pl, const int32_t* idx, const double* weff,
-                 int64_t s, const double* Q64, const float* Q32, void* partials, hipStream_t st) {
-  QPtrs qp;
-  for (int n = 0; n < kMaxOrder; ++n) {
-    if (n < g.order)
-      qp.p[n] = pl.prec == TK_F64 ? static_cast<const void*>(Q64 + g.qoff[n])
-                                  : static_cast<const void*>(Q32 + g.qoff[n]);
-    else
-      qp.p[n] = nullptr;
-  }
+void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int64_t s,
+                      const double* Q64, double* rows64, float* rows32, hipStream_t st) {
+  const int64_t n = s * g.sum_r;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(pregather_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock))), dim3(kBlock),
+                     0, st, g, idx, weff, s, Q64, rows64, rows32);
+}
+
+void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const float* rows32,
+                 const double* weff, int64_t s, void* partials, hipStream_t st) {
   dim3 grid(static_cast<unsigned>(pl.ntiles), static_cast<unsigned>(pl.ksplit));
   if (pl.prec == TK_F64)
-    hipLaunchKernelGGL(gram_kernel<VarF64>, grid, dim3(kBlock), 0, st, g, qp, idx, weff, s,
+    hipLaunchKernelGGL(gram_kernel<VarF64>, grid, dim3(kBlock), 0, st, g, rows64, weff, 0, s,
                        pl.chunk, static_cast<double*>(partials));
   else if (pl.prec == TK_F32)
-    hipLaunchKernelGGL(gram_kernel<VarF32>, grid, dim3(kBlock), 0, st, g, qp, idx, weff, s,
+    hipLaunchKernelGGL(gram_kernel<VarF32>, grid, dim3(kBlock), 0, st, g, rows32, weff, 1, s,
                        pl.chunk, static_cast<float*>(partials));
   else
-    hipLaunchKernelGGL(gram_kernel<VarBF16>, grid, dim3(kBlock), 0, st, g, qp, idx, weff, s,
+    hipLaunchKernelGGL(gram_kernel<VarBF16>, grid, dim3(kBlock), 0, st, g, rows32, weff, 1, s,
                        pl.chunk, static_cast<float*>(partials));
 }
 
@@ -572,65 +690,52 @@ void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* ma
                        status);
 }
 
-static QPtrs q64_ptrs(const Geom& g, const double* Q64) {
-  QPtrs qp;
-  for (int n = 0; n < kMaxOrder; ++n) qp.p[n] = n < g.order ? Q64 + g.qoff[n] : nullptr;
-  return qp;
+namespace {
+struct VecPlan {
+  int64_t nr;      // row chunks
+  int64_t nsplit;  // sample splits
+  int64_t chunk;   // samples per split
+};
+
+VecPlan plan_vec(const Geom& g, int64_t s) {
+  VecPlan vp;
+  vp.nr = cdiv(g.d, vec_rows_per_wg(g));
+  int64_t ns = cdiv(1024, vp.nr);
+  const int64_t maxs = cdiv(s, kVK * 4);
+  if (ns > maxs) ns = maxs;
+  if (ns < 1) ns = 1;
+  vp.chunk = cdiv(cdiv(s, ns), kVK) * kVK;
+  vp.nsplit = cdiv(s, vp.chunk);
+  return vp;
+}
+}  // namespace
+
+int64_t vec_part_doubles(const Geom& g, int64_t s) {
+  const VecPlan vp = plan_vec(g, s);
+  const int64_t a = vp.nsplit * g.d, b = vp.nr * s;
+  return a > b ? a : b;
 }
 
-int64_t rows_t_vec_chunks(const Geom& g, int64_t s) {
-  const int64_t nr = cdiv(g.d, kVT);
-  int64_t nc = cdiv(512, nr);
-  const int64_t maxc = cdiv(s, kVK * 4);
-  if (nc > maxc) nc = maxc;
-  if (nc < 1) nc = 1;
-  return nc;
-}
-
-void launch_rows_t_vec(const Geom& g, const int32_t* idx, const double* c, int64_t s,
-                       const double* Q64, double* part, double* out, hipStream_t st) {
-  // part: rows_t_vec_chunks(g, s) * d doubles
-  const int64_t nr = cdiv(g.d, kVT);
-  const int64_t nc = rows_t_vec_chunks(g, s);
-  const int64_t chunk = cdiv(cdiv(s, nc), kVK) * kVK;
-  const int64_t ncc = cdiv(s, chunk);
-  hipLaunchKernelGGL(rows_t_vec_kernel, dim3(static_cast<unsigned>(nr), static_cast<unsigned>(ncc)),
-                     dim3(kBlock), 0, st, g, q64_ptrs(g, Q64), idx, c, s, chunk, part,
-                     static_cast<const int32_t*>(nullptr));
+void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,
+                       double* part, double* out, const int32_t* done, hipStream_t st) {
+  const VecPlan vp = plan_vec(g, s);
+  hipLaunchKernelGGL(rows_t_vec_kernel,
+                     dim3(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit)),
+                     dim3(kBlock), 0, st, g, rows64, c, s, vp.chunk, part, done);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(static_cast<unsigned>(cdiv(g.d, kBlock))),
-                     dim3(kBlock), 0, st, part, ncc, g.d, out,
-                     static_cast<const int32_t*>(nullptr));
+                     dim3(kBlock), 0, st, static_cast<const double*>(part), vp.nsplit, g.d, out,
+                     done);
 }
 
-// Residual coefficient pass of the refinement: part needs cdiv(d,256)*s doubles.
-void launch_residual_coef(const Geom& g, const int32_t* idx, const double* xw, const double* weff,
-                          const double* h, int64_t s, const double* Q64, double* part, double* c,
+void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
+                          const double* weff, const double* h, int64_t s, double* part, double* c,
                           const int32_t* done, hipStream_t st) {
-  const int64_t nr = cdiv(g.d, kVT);
-  int64_t nsc = cdiv(1024, nr);
-  const int64_t maxc = cdiv(s, kVK * 4);
-  if (nsc > maxc) nsc = maxc;
-  if (nsc < 1) nsc = 1;
-  const int64_t chunk = cdiv(cdiv(s, nsc), kVK) * kVK;
-  const int64_t ncc = cdiv(s, chunk);
-  hipLaunchKernelGGL(rows_dot_kernel, dim3(static_cast<unsigned>(nr), static_cast<unsigned>(ncc)),
-                     dim3(kBlock), 0, st, g, q64_ptrs(g, Q64), idx, h, s, chunk, part, done);
+  const VecPlan vp = plan_vec(g, s);
+  hipLaunchKernelGGL(rows_dot_kernel,
+                     dim3(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit)),
+                     dim3(kBlock), 0, st, g, rows64, h, s, vp.chunk, part, done);
   hipLaunchKernelGGL(dot_finish_kernel, dim3(static_cast<unsigned>(cdiv(s, kBlock))), dim3(kBlock),
-                     0, st, part, nr, s, xw, weff, c, done);
-}
-
-// rows^T c with the done flag (refinement)
-void launch_rows_t_vec_flag(const Geom& g, const int32_t* idx, const double* c, int64_t s,
-                            const double* Q64, double* part, double* out, const int32_t* done,
-                            hipStream_t st) {
-  const int64_t nr = cdiv(g.d, kVT);
-  const int64_t nc = rows_t_vec_chunks(g, s);
-  const int64_t chunk = cdiv(cdiv(s, nc), kVK) * kVK;
-  const int64_t ncc = cdiv(s, chunk);
-  hipLaunchKernelGGL(rows_t_vec_kernel, dim3(static_cast<unsigned>(nr), static_cast<unsigned>(ncc)),
-                     dim3(kBlock), 0, st, g, q64_ptrs(g, Q64), idx, c, s, chunk, part, done);
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(static_cast<unsigned>(cdiv(g.d, kBlock))),
-                     dim3(kBlock), 0, st, part, ncc, g.d, out, done);
+                     0, st, static_cast<const double*>(part), vp.nr, s, xw, weff, c, done);
 }
 
 }  // namespace tk

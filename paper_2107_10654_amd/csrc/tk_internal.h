@@ -29,7 +29,11 @@ struct Geom {
   int64_t total_rr;             // sum R_n^2
   int64_t numel;                // prod I_n
   int64_t d;                    // prod R_n
+  int32_t soff[kMaxOrder];      // offsets of mode n inside a concatenated sample row (sum R_m)
+  int32_t sum_r;                // sum R_n: length of a concatenated sample row
 };
+
+constexpr int kMaxSumR = 160;   // longest concatenated sample row the kernels stage in LDS
 
 Geom make_geom(const tk_problem* p);
 
@@ -61,6 +65,11 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st);
 
+// Per-sample factor rows, stored contiguously: rows64[t][soff_n + r] = q^(n)_{i_n}[r]
+// and rows32 the same in FP32 with mode 0 scaled by sqrt(weff_t).
+void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int64_t s,
+                      const double* Q64, double* rows64, float* rows32, hipStream_t st);
+
 // Gather x_t and mask bits: weff_t = w_t [obs], xw_t = w_t x_t [obs].
 void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,
                    const int32_t* idx, const double* weight, int64_t s, double* weff, double* xw,
@@ -77,23 +86,20 @@ struct GramPlan {
 };
 GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override);
 size_t gram_partial_bytes(const Geom& g, const GramPlan& pl);
-void launch_gram(const Geom& g, const GramPlan& pl, const int32_t* idx, const double* weff,
-                 int64_t s, const double* Q64, const float* Q32, void* partials, hipStream_t st);
+void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const float* rows32,
+                 const double* weff, int64_t s, void* partials, hipStream_t st);
 // M = sum of partials (lower triangle) + lambda * ((x) P_n); FP64, full d x d row-major.
 void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, const double* P,
                      double lambda, double* M, hipStream_t st);
 
 // out[r] = sum_t c_t q_t[r] (q_t the whitened Kronecker row), FP64, deterministic.
-int64_t rows_t_vec_chunks(const Geom& g, int64_t s);
-void launch_rows_t_vec(const Geom& g, const int32_t* idx, const double* c, int64_t s,
-                       const double* Q64, double* part, double* out, hipStream_t st);
-void launch_rows_t_vec_flag(const Geom& g, const int32_t* idx, const double* c, int64_t s,
-                            const double* Q64, double* part, double* out, const int32_t* done,
-                            hipStream_t st);
-// Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part holds
-// cdiv(d, 256) * s doubles.
-void launch_residual_coef(const Geom& g, const int32_t* idx, const double* xw, const double* weff,
-                          const double* h, int64_t s, const double* Q64, double* part, double* c,
+// part: vec_part_doubles(g, s) scratch.
+int64_t vec_part_doubles(const Geom& g, int64_t s);
+void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,
+                       double* part, double* out, const int32_t* done, hipStream_t st);
+// Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part: vec_part_doubles.
+void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
+                          const double* weff, const double* h, int64_t s, double* part, double* c,
                           const int32_t* done, hipStream_t st);
 
 // Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag receives the

@@ -108,8 +108,10 @@ def make_problem(X, factors, lam, mask=None):
     return p
 
 
-def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1):
+def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1,
+          stage_events=None):
     o = L.TkSketchOpts()
+    o.stage_events = stage_events
     o.num_samples = int(samples) if samples is not None else 0
     o.eps, o.delta = float(eps), float(delta)
     o.seed = int(seed) & ((1 << 64) - 1)
@@ -166,11 +168,17 @@ def sample(dims, cdf, s, seed, counter=0, problem=0):
 
 def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0, precision="f64",
                          mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
-                         return_samples=False, return_info=False, check=True, out=None):
-    """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info)."""
+                         return_samples=False, return_info=False, check=True, out=None,
+                         stage_events=None):
+    """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info).
+
+    stage_events: optional address of an array of NUM_STAGE_EVENTS hipEvent_t
+    handles that the library records at its stage boundaries.
+    """
     lib = L.load()
     p = make_problem(X, factors, lam, mask)
-    o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol)
+    o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol,
+              stage_events=stage_events)
     dev = X.device
     N = len(factors)
     s = int(samples) if samples else sample_count(

@@ -309,3 +309,20 @@ def test_one_plus_eps_bound_thm_3_4():
     idx, w = oracle.sample(tables, 64, seed=0, counter=0)
     g = oracle.core_update_sketched(X, F, lam, idx, w)
     assert oracle.sketched_objective_excess(g, g_star, F, lam) > 10 * np.median(ratios) * f_star
+
+
+def test_normal_equation_residual_pin():
+    """Zero at the solution of the sketched normal equations, equal to the explicit
+    ||(Gram + lam I) g - rhs|| / ||rhs|| elsewhere."""
+    p = _tiny_problem(90)
+    X, F, lam = p["X"], p["factors_true"], 0.02
+    tables = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F]
+    idx, w = oracle.sample(tables, 400, seed=3, counter=0)
+    G = oracle.core_update_sketched(X, F, lam, idx, w)
+    assert oracle.normal_equation_residual(X, F, lam, idx, w, G, chunk=97) < 1e-12
+    Gp = G + 0.01 * np.random.default_rng(0).standard_normal(G.shape)
+    rows = oracle.kron_matrix(F)[np.ravel_multi_index(tuple(idx), X.shape)]
+    gram = (rows * w[:, None]).T @ rows + lam * np.eye(rows.shape[1])
+    rhs = rows.T @ (w * X.reshape(-1)[np.ravel_multi_index(tuple(idx), X.shape)])
+    ref = np.linalg.norm(gram @ Gp.reshape(-1) - rhs) / np.linalg.norm(rhs)
+    assert abs(oracle.normal_equation_residual(X, F, lam, idx, w, Gp, chunk=97) - ref) < 1e-12
