@@ -20,7 +20,8 @@ STATUS_NAMES = {
     5: "TK_E_NOT_SPD", 6: "TK_E_RANK_DEFICIENT", 7: "TK_E_NO_CONVERGE", 8: "TK_E_HIP",
 }
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtucker_hip.so")
+LIB_PATH = os.environ.get("TK_LIBRARY_PATH") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libtucker_hip.so")
 
 
 class TkProblem(ctypes.Structure):

@@ -39,6 +39,9 @@ Geom make_geom(const tk_problem* p) {
   g.numel = numel;
   g.d = d;
   g.sum_r = soff;
+  g.last = p->order - 1;
+  while (g.last > 0 && p->ranks[g.last] < 2) --g.last;
+  if (p->ranks[g.last] < 2) g.last = p->order - 1;
   return g;
 }
 
@@ -149,8 +152,8 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.ph_a = c.take<double>(d);
   w.ph_b = c.take<double>(d);
   w.vpart = c.take<double>(vec_part_doubles(g, s));
-  w.rows64 = c.take<double>(static_cast<size_t>(s) * g.sum_r);
-  w.rows32 = c.take<float>(static_cast<size_t>(s) * g.sum_r);
+  w.rows64 = c.take<double>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
+  w.rows32 = c.take<float>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
   w.coef = c.take<double>(s);
   w.flags = c.take<int32_t>(2 * nblk + 2);
   w.status = c.take<int32_t>(1);

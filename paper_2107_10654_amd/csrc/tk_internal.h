@@ -31,9 +31,14 @@ struct Geom {
   int64_t d;                    // prod R_n
   int32_t soff[kMaxOrder];      // offsets of mode n inside a concatenated sample row (sum R_m)
   int32_t sum_r;                // sum R_n: length of a concatenated sample row
+  int32_t last;                 // split mode: the last mode with R_n >= 2 (N-1 when d == 1)
 };
 
 constexpr int kMaxSumR = 160;   // longest concatenated sample row the kernels stage in LDS
+// Pre-gathered sample rows are stored chunk-transposed: chunk c of kRowChunk
+// samples holds element (sample t, row position j) at
+// c * sum_r * kRowChunk + j * kRowChunk + (t - c * kRowChunk); padding samples are 0.
+constexpr int kRowChunk = 32;
 
 Geom make_geom(const tk_problem* p);
 
@@ -65,8 +70,9 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st);
 
-// Per-sample factor rows, stored contiguously: rows64[t][soff_n + r] = q^(n)_{i_n}[r]
-// and rows32 the same in FP32 with mode 0 scaled by sqrt(weff_t).
+// Per-sample factor rows (chunk-transposed, see kRowChunk): q^(n)_{i_n}[r] at row
+// position soff_n + r; rows32 the same in FP32 with mode 0 scaled by sqrt(weff_t).
+__host__ __device__ inline int64_t row_chunks(int64_t s) { return (s + kRowChunk - 1) / kRowChunk; }
 void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int64_t s,
                       const double* Q64, double* rows64, float* rows32, hipStream_t st);
 
@@ -75,9 +81,16 @@ void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* ma
                    const int32_t* idx, const double* weight, int64_t s, double* weff, double* xw,
                    unsigned int* missing, int32_t* status, hipStream_t st);
 
-// Sketched Gram of whitened rows (tk_gram.hip): partial Grams per sample split.
+// Sketched Gram of whitened rows (tk_gram.hip).  FP64: partial Grams per
+// sample split (64 x 64 tiles).  FP32 / BF16: stream-K over 256 x 256 tiles
+// with partial tiles in per-workgroup slots.
+struct SkPlan {
+  int64_t nt, ntiles, nchunks, units, grid, maxseg;
+};
 struct GramPlan {
   tk_dtype prec;
+  bool streamk;
+  SkPlan sk;
   int tile;        // output tile edge
   int bk;          // samples per LDS chunk
   int ksplit;      // sample splits (partials)
