@@ -124,6 +124,7 @@ struct SketchWS {
   double* rows64;
   float* rows32;
   double* coef;
+  double* ttm_scratch;
   int32_t* flags;
   int32_t* status;
   int32_t* done;
@@ -155,6 +156,7 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.rows64 = c.take<double>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
   w.rows32 = c.take<float>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
   w.coef = c.take<double>(s);
+  w.ttm_scratch = c.take<double>(kTtmScratchDoubles);
   w.flags = c.take<int32_t>(2 * nblk + 2);
   w.status = c.take<int32_t>(1);
   w.done = c.take<int32_t>(1);
@@ -171,6 +173,7 @@ struct ExactWS {
   double* C;
   double* tA;
   double* tB;
+  double* scratch;
 };
 
 // largest intermediate of the mode-product chain that contracts modes in
@@ -211,6 +214,7 @@ void carve_exact(Carver& c, const Geom& g, ExactWS& w) {
   const int64_t mx = chain_max(g, -1);
   w.tA = c.take<double>(mx > g.d ? mx : g.d);
   w.tB = c.take<double>(mx > g.d ? mx : g.d);
+  w.scratch = c.take<double>(kTtmScratchDoubles);
 }
 
 struct FactorWS {
@@ -223,6 +227,7 @@ struct FactorWS {
   double* KKt;
   double* tA;
   double* tB;
+  double* scratch;
 };
 
 void carve_factor(Carver& c, const Geom& g, FactorWS& w) {
@@ -243,6 +248,7 @@ void carve_factor(Carver& c, const Geom& g, FactorWS& w) {
   if (g.order == 1) mx = g.numel;  // no contraction: W is X itself, converted to FP64
   w.tA = c.take<double>(mx);
   w.tB = c.take<double>(mx);
+  w.scratch = c.take<double>(kTtmScratchDoubles);
 }
 
 constexpr int64_t kLossParts = 1024;
@@ -255,6 +261,7 @@ struct LossWS {
   double* psq;
   double* pcnt;
   double* preg;
+  double* scratch;
 };
 
 void carve_loss(Carver& c, const Geom& g, LossWS& w) {
@@ -266,19 +273,20 @@ void carve_loss(Carver& c, const Geom& g, LossWS& w) {
   w.psq = c.take<double>(kLossParts);
   w.pcnt = c.take<double>(kLossParts);
   w.preg = c.take<double>(static_cast<size_t>(kMaxOrder + 1) * 64);
+  w.scratch = c.take<double>(kTtmScratchDoubles);
 }
 
 // ---------------------------------------------------------------- helpers
 // T <- T x_n M_n over all modes (core-sized ping-pong).  Returns the buffer
 // holding the result (a or b).
 double* core_chain(const Geom& g, double* a, double* b, const double* mats, bool trans,
-                   hipStream_t st) {
+                   double* scratch, hipStream_t st) {
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.ranks[n];
   double* cur = a;
   double* nxt = b;
   for (int n = 0; n < g.order; ++n) {
-    launch_ttm(cur, dims, g.order, n, mats + g.roff[n], g.ranks[n], trans, nxt, st);
+    launch_ttm(cur, dims, g.order, n, mats + g.roff[n], g.ranks[n], trans, nxt, scratch, st);
     double* t = cur;
     cur = nxt;
     nxt = t;
@@ -471,7 +479,7 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
     launch_residual_coef(g, w.rows64, w.xw, w.weff, w.h, s, w.vpart, w.coef, w.done, st);
     launch_rows_t_vec(g, w.rows64, w.coef, s, w.vpart, w.r, w.done, st);
     launch_copy_f64(g.d, w.h, w.ph_a, st);
-    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, st);
+    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st);
     (void)ph;
     launch_refine_check(g.d, w.r, ph, p->lambda, w.rhs, refine ? o->refine_tol : -1.0, w.done,
                         w.steps, w.relres, k < iters ? 1 : 0, st);
@@ -484,7 +492,7 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   stage(8);
   // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
   launch_copy_f64(g.d, w.h, w.ph_a, st);
-  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, st);
+  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, st);
   launch_cast_out(g.d, gres, core_out, p->dtype, st);
   if (dev_info) launch_info(dev_info, s, w.missing, w.steps, w.relres, w.min_pivot, st);
   stage(9);
@@ -514,7 +522,8 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
   int which = 0;
   for (int m = g.order - 1; m >= 0; --m) {
     double* out = bufs[which];
-    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.W + g.qoff[m], g.ranks[m], true, out, st);
+    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.W + g.qoff[m], g.ranks[m], true, out,
+                   w.scratch, st);
     dims[m] = g.ranks[m];
     cur = out;
     cur_dt = TK_F64;
@@ -523,7 +532,7 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
   double* B = const_cast<double*>(static_cast<const double*>(cur));
   launch_kron_scale(g, w.lam, p->lambda, B, st);
   double* other = (B == w.tA) ? w.tB : w.tA;
-  const double* G = core_chain(g, B, other, w.V, false, st);
+  const double* G = core_chain(g, B, other, w.V, false, w.scratch, st);
   launch_cast_out(g.d, G, core_out, p->dtype, st);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
@@ -557,7 +566,8 @@ tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mo
   for (int m = g.order - 1; m >= 0; --m) {
     if (m == mode) continue;
     double* out = bufs[which];
-    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.A64 + g.qoff[m], g.ranks[m], true, out, st);
+    launch_ttm_any(cur, cur_dt, dims, g.order, m, w.A64 + g.qoff[m], g.ranks[m], true, out,
+                   w.scratch, st);
     dims[m] = g.ranks[m];
     cur = out;
     cur_dt = TK_F64;
@@ -586,7 +596,7 @@ tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mo
     int zi = 0;
     for (int m = 0; m < g.order; ++m) {
       if (m == mode) continue;
-      launch_ttm(z, cd, g.order, m, w.C + g.roff[m], g.ranks[m], false, zb[zi], st);
+      launch_ttm(z, cd, g.order, m, w.C + g.roff[m], g.ranks[m], false, zb[zi], w.scratch, st);
       z = zb[zi];
       zi ^= 1;
     }
@@ -617,7 +627,8 @@ tk_status tucker_loss(const tk_problem* p, const void* core, double* out, void* 
   double* bufs[2] = {w.tA, w.tB};
   int which = 0;
   for (int m = 0; m < g.order - 1; ++m) {
-    launch_ttm(cur, dims, g.order, m, w.A64 + g.qoff[m], g.dims[m], false, bufs[which], st);
+    launch_ttm(cur, dims, g.order, m, w.A64 + g.qoff[m], g.dims[m], false, bufs[which], w.scratch,
+               st);
     dims[m] = g.dims[m];
     cur = bufs[which];
     which ^= 1;

@@ -18,72 +18,139 @@ constexpr int NB = kCholNb;
 constexpr int LDA = NB + 1;
 
 // ---- diagonal tile: L_kk and its inverse
-// 16 x 16 thread grid; no runtime integer division in the inner loops.
+// Blocked over four 16-column panels.  Wave 0 factors (and inverts) each
+// 16 x 16 diagonal panel in registers, lane r owning row r, with lane
+// shuffles in place of barriers; the workgroup then solves the rows below the
+// panel and updates the trailing triangle.  The 64 x 64 inverse is assembled
+// from the four 16 x 16 inverses block row by block row.
+constexpr int PB = 16;
 __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
                                                            int64_t k,
                                                            double* __restrict__ Linv_diag,
                                                            double* min_pivot, int32_t* status) {
   __shared__ double A[NB * LDA];
   __shared__ double Li[NB * LDA];
+  __shared__ double Tm[NB * (PB + 1)];
   __shared__ int bad;
   __shared__ double pmin;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int tx = tid & 15, ty = tid >> 4;
   const int64_t o = k * NB;
   const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
   for (int i = ty; i < NB; i += 16)
-    for (int j = tx; j < NB; j += 16)
+    for (int j = tx; j < NB; j += 16) {
       A[i * LDA + j] = (i < b && j <= i) ? M[(o + i) * d + o + j] : (i == j ? 1.0 : 0.0);
+      Li[i * LDA + j] = 0.0;
+    }
   if (tid == 0) {
     bad = 0;
     pmin = 1e308;
   }
   __syncthreads();
-  for (int j = 0; j < b; ++j) {
-    // every thread reads the pivot; column j below the diagonal is scaled by the threads
-    // that own it, then the trailing triangle is updated
-    double piv = A[j * LDA + j];
-    const bool ok = piv > 0.0;
-    if (!ok) piv = 1.0;
-    const double ljj = sqrt(piv);
-    const double inv = 1.0 / ljj;
-    __syncthreads();
-    if (tid == 0) {
-      A[j * LDA + j] = ljj;
-      if (!ok) bad = 1;
-      pmin = fmin(pmin, ljj);
-    }
-    for (int i = j + 1 + tid; i < b; i += kBlock) A[i * LDA + j] *= inv;
-    __syncthreads();
-    for (int i = j + 1 + ty; i < b; i += 16) {
-      const double lij = A[i * LDA + j];
-      for (int c = j + 1 + tx; c <= i; c += 16) A[i * LDA + c] = fma(-lij, A[c * LDA + j], A[i * LDA + c]);
-    }
-    __syncthreads();
-  }
-  // inverse of the unit-scaled lower triangle, one column per thread group of 4:
-  // column c (thread c / 4 .. ), forward substitution with the dot split over 4 lanes
-  {
-    const int c = tid >> 2, part = tid & 3;
-    for (int i = 0; i < NB; ++i) {
-      double s = 0.0;
-      if (i > c)
-        for (int q = c + part; q < i; q += 4) s = fma(A[i * LDA + q], Li[q * LDA + c], s);
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      if (part == 0) {
-        if (i < c)
-          Li[i * LDA + c] = 0.0;
-        else if (i == c)
-          Li[i * LDA + c] = 1.0 / A[i * LDA + i];
-        else
-          Li[i * LDA + c] = -s / A[i * LDA + i];
+  for (int p = 0; p < NB / PB; ++p) {
+    const int c0 = p * PB;
+    // (1) factor the 16 x 16 diagonal panel and invert it (wave 0, lane r = row r)
+    if (wave == 0) {
+      const int r = lane & 15;
+      double a[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) a[c] = (c <= r) ? A[(c0 + r) * LDA + c0 + c] : 0.0;
+      double pm = 1e308;
+      bool nb_ = false;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        double pj = __shfl(a[j], j, 64);
+        if (!(pj > 0.0)) {
+          nb_ = true;
+          pj = 1.0;
+        }
+        const double ljj = sqrt(pj);
+        pm = fmin(pm, ljj);
+        const double lj = (r == j) ? ljj : (r > j ? a[j] / ljj : 0.0);
+        a[j] = (r >= j) ? lj : 0.0;
+#pragma unroll
+        for (int c = j + 1; c < PB; ++c) {
+          const double lc = __shfl(lj, c, 64);
+          if (r >= c) a[c] = fma(-lj, lc, a[c]);
+        }
       }
-      // column c only depends on its own earlier entries: a wave-local dependency
-      __builtin_amdgcn_wave_barrier();
+      // inverse: lane r computes column r, x[i] for i >= r
+      double x[PB];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        double sacc = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) {
+          const double liq = __shfl(a[q], i, 64);  // L[i][q] from lane i
+          sacc = fma(-liq, x[q], sacc);
+        }
+        const double lii = __shfl(a[i], i, 64);
+        x[i] = (i >= r) ? sacc / lii : 0.0;
+      }
+      if (lane < PB) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) {
+          A[(c0 + r) * LDA + c0 + c] = (c <= r) ? a[c] : 0.0;
+          Li[(c0 + c) * LDA + c0 + r] = x[c];  // column r of the inverse
+        }
+      }
+      if (lane == 0) {
+        if (nb_) bad = 1;
+        pmin = fmin(pmin, pm);
+      }
+    }
+    __syncthreads();
+    const int below = NB - (c0 + PB);
+    if (below > 0) {
+      // (2) rows below: X = A[c0+16:, c0:c0+16] Li_pp^T
+      for (int e = tid; e < below * PB; e += kBlock) {
+        const int rr = c0 + PB + (e >> 4), c = e & 15;
+        double sacc = 0.0;
+#pragma unroll
+        for (int m = 0; m < PB; ++m)
+          sacc = fma(A[rr * LDA + c0 + m], Li[(c0 + c) * LDA + c0 + m], sacc);
+        Tm[(rr - c0 - PB) * (PB + 1) + c] = sacc;
+      }
+      __syncthreads();
+      for (int e = tid; e < below * PB; e += kBlock) {
+        const int rr = c0 + PB + (e >> 4), c = e & 15;
+        A[rr * LDA + c0 + c] = Tm[(rr - c0 - PB) * (PB + 1) + c];
+      }
+      __syncthreads();
+      // (3) trailing update of the lower triangle
+      for (int i = c0 + PB + ty; i < NB; i += 16)
+        for (int j = c0 + PB + tx; j <= i; j += 16) {
+          double sacc = A[i * LDA + j];
+#pragma unroll
+          for (int m = 0; m < PB; ++m)
+            sacc = fma(-A[i * LDA + c0 + m], A[j * LDA + c0 + m], sacc);
+          A[i * LDA + j] = sacc;
+        }
+      __syncthreads();
     }
   }
-  __syncthreads();
+  // (4) off-diagonal blocks of the inverse: Li_ij = -Li_ii sum_{q=j}^{i-1} L_iq Li_qj
+  for (int bi = 1; bi < NB / PB; ++bi) {
+    // S_j = sum_q L_{bi,q} Li_{q,j} for every block column j < bi (into Tm rows j*16..)
+    for (int e = tid; e < bi * PB * PB; e += kBlock) {
+      const int bj = e >> 8, rr = (e >> 4) & 15, c = e & 15;
+      double sacc = 0.0;
+      for (int q = bj * PB; q < bi * PB; ++q)
+        sacc = fma(A[(bi * PB + rr) * LDA + q], Li[q * LDA + bj * PB + c], sacc);
+      Tm[(bj * PB + rr) * (PB + 1) + c] = sacc;
+    }
+    __syncthreads();
+    for (int e = tid; e < bi * PB * PB; e += kBlock) {
+      const int bj = e >> 8, rr = (e >> 4) & 15, c = e & 15;
+      double sacc = 0.0;
+#pragma unroll
+      for (int m = 0; m < PB; ++m)
+        sacc = fma(Li[(bi * PB + rr) * LDA + bi * PB + m], Tm[(bj * PB + m) * (PB + 1) + c], sacc);
+      Li[(bi * PB + rr) * LDA + bj * PB + c] = -sacc;
+    }
+    __syncthreads();
+  }
   double* Lo = Linv_diag + k * NB * NB;
   for (int i = ty; i < NB; i += 16)
     for (int j = tx; j < NB; j += 16) {

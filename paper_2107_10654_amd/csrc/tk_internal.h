@@ -127,12 +127,16 @@ void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, doub
                        hipStream_t st);
 
 // Small FP64 helpers (tk_small.hip).
-// T' = T x_mode M  for row-major T of shape dims (order n), M: J x dims[mode] (row-major)
+// T' = T x_mode M  for row-major T of shape dims (order n), M: J x dims[mode]
+// (row-major; transpose_M: M stored dims[mode] x J).  scratch (nullable, at
+// least kTtmScratchDoubles) lets a contraction with few fibres split over i.
+constexpr int64_t kTtmScratchDoubles = int64_t(2) * 65536 * kMaxRank;
 void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
-                int64_t J, bool transpose_M, double* out, hipStream_t st);
+                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st);
 // ttm over an input of element type dt (F32 or F64) -> FP64 output
 void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
-                    const double* M, int64_t J, bool transpose_M, double* out, hipStream_t st);
+                    const double* M, int64_t J, bool transpose_M, double* out, double* scratch,
+                    hipStream_t st);
 void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
                  hipStream_t st);
 void launch_copy_f64(int64_t n, const double* x, double* y, hipStream_t st);

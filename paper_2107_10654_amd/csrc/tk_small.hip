@@ -21,30 +21,43 @@ __device__ inline double mat(const double* M, int64_t I, int64_t J, bool trans, 
   return trans ? M[i * J + j] : M[j * I + i];
 }
 
-// outputs j in [j0, j0 + jn), jn <= JMAX
+// outputs j in [j0, j0 + jn), jn <= JMAX; input range i in [ia, ib) of split blockIdx.y
+// (ib - ia = ilen); writes out + blockIdx.y * split_stride.
 template <class T, int JMAX>
 __global__ __launch_bounds__(kBlock) void ttm_fibre_kernel(const T* __restrict__ in, int64_t P,
                                                            int64_t I, int64_t Q,
                                                            const double* __restrict__ M, int64_t J,
                                                            bool trans, int64_t j0, int jn,
+                                                           int64_t ilen, int64_t split_stride,
                                                            double* __restrict__ out) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= P * Q) return;
   const int64_t p = e / Q, q = e % Q;
+  const int64_t ia = static_cast<int64_t>(blockIdx.y) * ilen;
+  const int64_t ib = (ia + ilen < I) ? ia + ilen : I;
   double acc[JMAX];
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) acc[j] = 0.0;
   const T* src = in + p * I * Q + q;
-  for (int64_t i = 0; i < I; ++i) {
+  for (int64_t i = ia; i < ib; ++i) {
     const double x = ldd(src, i * Q);
 #pragma unroll
     for (int j = 0; j < JMAX; ++j)
       if (j < jn) acc[j] = fma(mat(M, I, J, trans, j0 + j, i), x, acc[j]);
   }
-  double* dst = out + p * J * Q + q;
+  double* dst = out + static_cast<int64_t>(blockIdx.y) * split_stride + p * J * Q + q;
 #pragma unroll
   for (int j = 0; j < JMAX; ++j)
     if (j < jn) dst[(j0 + j) * Q] = acc[j];
+}
+
+__global__ void sum_splits_kernel(const double* __restrict__ part, int64_t nsplit, int64_t n,
+                                  double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int64_t k = 0; k < nsplit; ++k) v += part[k * n + i];
+  out[i] = v;
 }
 
 // Q == 1: out[p][j] = sum_i Mat(j,i) in[p][i]; 64 rows per workgroup, i in chunks of 64.
@@ -65,15 +78,19 @@ __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ 
   for (int64_t i0 = 0; i0 < I; i0 += 64) {
     const int ic = static_cast<int>((I - i0) < 64 ? (I - i0) : 64);
     __syncthreads();
-    for (int e = tid; e < 64 * 64; e += kBlock) {
-      const int r = e / 64, c = e % 64;
+    // unconditional (clamped) loads so they issue back to back
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + k * kBlock;
+      const int r = e >> 6, c = e & 63;
       const int64_t p = p0 + r;
-      Xs[r][c] = (p < P && c < ic) ? ldd(in, p * I + i0 + c) : 0.0;
+      const int64_t pc = p < P ? p : P - 1;
+      const int64_t cc = c < ic ? i0 + c : i0;
+      const double v = ldd(in, pc * I + cc);
+      Xs[r][c] = (p < P && c < ic) ? v : 0.0;
     }
-    for (int e = tid; e < 64 * J; e += kBlock) {
-      const int c = static_cast<int>(e / J), j = static_cast<int>(e % J);
-      Ms[c][j] = c < ic ? mat(M, I, J, trans, j, i0 + c) : 0.0;
-    }
+    for (int c = tid >> 2; c < 64; c += kBlock / 4)
+      for (int j = tid & 3; j < J; j += 4) Ms[c][j] = c < ic ? mat(M, I, J, trans, j, i0 + c) : 0.0;
     __syncthreads();
     for (int c = 0; c < ic; ++c) {
       const double x = Xs[pr][c];
@@ -94,34 +111,53 @@ __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ 
   }
 }
 
+constexpr int64_t kTtmThreadsWanted = 65536;
+
 template <class T>
 void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const double* M,
-                  int64_t J, bool trans, double* out, hipStream_t st) {
+                  int64_t J, bool trans, double* out, double* scratch, hipStream_t st) {
   int64_t P = 1, Q = 1;
   for (int m = 0; m < mode; ++m) P *= dims[m];
   for (int m = mode + 1; m < order; ++m) Q *= dims[m];
   const int64_t I = dims[mode];
-  if (Q == 1 && J <= kMaxRank) {
+  if (Q == 1 && J <= kMaxRank && P >= 64 * 256) {
     hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
                        0, st, in, P, I, M, J, trans, out);
     return;
   }
-  const dim3 grid(static_cast<unsigned>(cdiv(P * Q, kBlock)));
+  // split the contraction over i when there are too few fibres to fill the GPU
+  int64_t nsplit = 1;
+  if (scratch && P * Q < kTtmThreadsWanted) {
+    nsplit = cdiv(kTtmThreadsWanted, P * Q);
+    const int64_t maxs = cdiv(I, 8);
+    if (nsplit > maxs) nsplit = maxs;
+    if (nsplit > kTtmScratchDoubles / (P * J * Q)) nsplit = kTtmScratchDoubles / (P * J * Q);
+    if (nsplit < 1) nsplit = 1;
+  }
+  const int64_t ilen = cdiv(I, nsplit);
+  nsplit = cdiv(I, ilen);
+  double* dst = nsplit > 1 ? scratch : out;
+  const int64_t stride = P * J * Q;
+  const dim3 grid(static_cast<unsigned>(cdiv(P * Q, kBlock)), static_cast<unsigned>(nsplit));
   for (int64_t j0 = 0; j0 < J; j0 += 64) {
     const int jn = static_cast<int>((J - j0) < 64 ? (J - j0) : 64);
     if (jn <= 8)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 8>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, out);
+                         trans, j0, jn, ilen, stride, dst);
     else if (jn <= 16)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 16>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, out);
+                         trans, j0, jn, ilen, stride, dst);
     else if (jn <= 32)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 32>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, out);
+                         trans, j0, jn, ilen, stride, dst);
     else
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 64>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, out);
+                         trans, j0, jn, ilen, stride, dst);
   }
+  if (nsplit > 1)
+    hipLaunchKernelGGL(sum_splits_kernel, dim3(static_cast<unsigned>(cdiv(stride, kBlock))),
+                       dim3(kBlock), 0, st, static_cast<const double*>(scratch), nsplit, stride,
+                       out);
 }
 
 __global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x,
@@ -203,18 +239,19 @@ __global__ void finish_refine_kernel(const int32_t* done, int refine_enabled, in
 }  // namespace
 
 void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
-                int64_t J, bool transpose_M, double* out, hipStream_t st) {
-  ttm_dispatch<double>(T, dims, order, mode, M, J, transpose_M, out, st);
+                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st) {
+  ttm_dispatch<double>(T, dims, order, mode, M, J, transpose_M, out, scratch, st);
 }
 
 void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
-                    const double* M, int64_t J, bool transpose_M, double* out, hipStream_t st) {
+                    const double* M, int64_t J, bool transpose_M, double* out, double* scratch,
+                    hipStream_t st) {
   if (dt == TK_F64)
     ttm_dispatch<double>(static_cast<const double*>(T), dims, order, mode, M, J, transpose_M, out,
-                         st);
+                         scratch, st);
   else
     ttm_dispatch<float>(static_cast<const float*>(T), dims, order, mode, M, J, transpose_M, out,
-                        st);
+                        scratch, st);
 }
 
 void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
