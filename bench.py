@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip exact/ALS comparison timings")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain FP32 copy kernel over this many MiB (calibrates the "
+                         "HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -168,6 +171,16 @@ def main():
     log(f"[bench] workload {args.workload}: X {tuple(X.shape)} {X.dtype}, d={int(np.prod(cfg['ranks']))}, "
         f"s={s}, generated in {time.perf_counter() - t_gen:.1f} s")
     d = int(np.prod(cfg["ranks"]))
+
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"[bench] copy calibration: 3 launches reading and writing {nbytes} bytes each")
 
     hip = HipEvents()
     nst = tk.tucker.L.NUM_STAGE_EVENTS

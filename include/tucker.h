@@ -88,7 +88,8 @@ typedef struct {
   void* const* stage_events; /* NULL, or TK_NUM_STAGE_EVENTS hipEvent_t handles created by the
                                 caller; the call records event k on `stream` at stage boundary k:
                                 0 start, 1 leverage scores and CDFs done, 2 sampling done,
-                                3 gather done, 4 sketched Gram done, 5 assembly and right side
+                                3 gather of entries and sample rows done, 4 sketched Gram
+                                kernel done, 5 assembly and right side
                                 done, 6 Cholesky done, 7 first solve done, 8 refinement done,
                                 9 end */
 } tk_sketch_opts;

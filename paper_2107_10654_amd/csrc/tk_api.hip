@@ -457,8 +457,8 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   stage(2);
   // 3. sampled entries (x_t, mask) and effective weights
   launch_gather(g, p->X, p->dtype, p->mask, idx, weight, s, w.weff, w.xw, w.missing, status, st);
-  stage(3);
   launch_pregather(g, idx, w.weff, s, w.lev.Q64, w.rows64, w.rows32, st);
+  stage(3);
   // 4. sketched Gram on MFMA, plus lambda P
   launch_gram(g, pl, w.rows64, w.rows32, w.weff, s, w.gpart, st);
   stage(4);

@@ -24,6 +24,7 @@ namespace tk {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
 
@@ -331,7 +332,15 @@ __host__ __device__ inline int64_t sk_unit_start(const SkPlan& sp, int64_t w) {
   return (w * sp.units) / sp.grid;
 }
 
-template <class V>
+// PF4: 16-byte prefetch registers per thread; a chunk of rows holds
+// kRowChunk * sum_r values, so PF4 * 4 * kSkThreads >= kRowChunk * sum_r.
+constexpr int kSkPfSmall = 2;  // sum_r <= 64
+constexpr int kSkPfLarge = (kRowChunk * kMaxSumR / 4 + kSkThreads - 1) / kSkThreads;
+__host__ __device__ constexpr int sk_pf_slots(int sum_r) {
+  return kRowChunk * sum_r <= 4 * kSkThreads * kSkPfSmall ? kSkPfSmall : kSkPfLarge;
+}
+
+template <class V, int PF4>
 __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
     Geom g, SkPlan sp, const typename V::Src* __restrict__ rows,
     typename V::Out* __restrict__ slots) {
@@ -340,7 +349,6 @@ __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
   using Acc = typename V::Acc;
   using L = SkLayout<V>;
   constexpr int T = kSkT, BK = V::BK, LDK = V::LDK, RT = kSkRT, NO = kSkNO;
-  constexpr int PF4 = (BK * kMaxSumR / 4 + kSkThreads - 1) / kSkThreads;  // float4 prefetch
   constexpr int IW = V::EPL == 8 ? 8 : 4;         // samples per formation item
   constexpr int IPR = BK / IW;                    // items per row
   constexpr int ITEMS = T * IPR / kSkThreads;     // items per thread per side
@@ -370,9 +378,9 @@ __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
   Acc acc[NBR][NBC];
 
   const int nval4 = BK * SR / 4;
-  float4 pf[PF4];
+  f32x4 pf[PF4];
   auto fetch = [&](int64_t c) {
-    const float4* src = reinterpret_cast<const float4*>(rows + c * BK * SR);
+    const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
 #pragma unroll
     for (int k = 0; k < PF4; ++k) {
       const int e = tid + k * kSkThreads;
@@ -385,7 +393,7 @@ __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
       const int e = tid + k * kSkThreads;
       if (e < nval4) {
         const int f = 4 * e;  // element index j * 32 + t
-        *reinterpret_cast<float4*>(&rT[(f >> 5) * RT + (f & 31)]) = pf[k];
+        *reinterpret_cast<f32x4*>(&rT[(f >> 5) * RT + (f & 31)]) = pf[k];
       }
     }
   };
@@ -473,10 +481,10 @@ __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
           for (int k = 0; k < ITEMS; ++k) {
             const int e = tid + k * kSkThreads;
             const int i = e / IPR, tg = (e % IPR) * IW;
-            const float4* op = reinterpret_cast<const float4*>(O + iofs_o[side][k]);
-            const float4* qp = reinterpret_cast<const float4*>(rT + iofs_q[side][k]);
+            const f32x4* op = reinterpret_cast<const f32x4*>(O + iofs_o[side][k]);
+            const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
             if constexpr (V::EPL == 8) {
-              const float4 o0 = op[0], o1 = op[1], q0 = qp[0], q1 = qp[1];
+              const f32x4 o0 = op[0], o1 = op[1], q0 = qp[0], q1 = qp[1];
               bf16x8 v;
               v[0] = V::cvt(o0.x * q0.x);
               v[1] = V::cvt(o0.y * q0.y);
@@ -488,7 +496,7 @@ __global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
               v[7] = V::cvt(o1.w * q1.w);
               *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
             } else {
-              const float4 o = op[0], q = qp[0];
+              const f32x4 o = op[0], q = qp[0];
               Op* y = &Y[i * LDK + tg];
               y[0] = V::cvt(o.x * q.x);
               y[1] = V::cvt(o.y * q.y);
@@ -930,14 +938,27 @@ void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const 
     dim3 grid(static_cast<unsigned>(pl.ntiles), static_cast<unsigned>(pl.ksplit));
     hipLaunchKernelGGL(gram_kernel<VarF64>, grid, dim3(kBlock), 0, st, g, rows64, weff, 0, s,
                        pl.chunk, static_cast<double*>(partials));
-  } else if (pl.prec == TK_F32) {
-    hipLaunchKernelGGL(gram_sk_kernel<VarF32>, dim3(static_cast<unsigned>(pl.sk.grid)),
-                       dim3(kSkThreads), SkLayout<VarF32>::bytes(g.sum_r), st, g, pl.sk, rows32,
-                       static_cast<float*>(partials));
   } else {
-    hipLaunchKernelGGL(gram_sk_kernel<VarBF16>, dim3(static_cast<unsigned>(pl.sk.grid)),
-                       dim3(kSkThreads), SkLayout<VarBF16>::bytes(g.sum_r), st, g, pl.sk, rows32,
-                       static_cast<float*>(partials));
+    const bool small = sk_pf_slots(g.sum_r) == kSkPfSmall;
+    const dim3 grid(static_cast<unsigned>(pl.sk.grid)), block(kSkThreads);
+    float* out = static_cast<float*>(partials);
+    if (pl.prec == TK_F32) {
+      const size_t lds = SkLayout<VarF32>::bytes(g.sum_r);
+      if (small)
+        hipLaunchKernelGGL((gram_sk_kernel<VarF32, kSkPfSmall>), grid, block, lds, st, g, pl.sk,
+                           rows32, out);
+      else
+        hipLaunchKernelGGL((gram_sk_kernel<VarF32, kSkPfLarge>), grid, block, lds, st, g, pl.sk,
+                           rows32, out);
+    } else {
+      const size_t lds = SkLayout<VarBF16>::bytes(g.sum_r);
+      if (small)
+        hipLaunchKernelGGL((gram_sk_kernel<VarBF16, kSkPfSmall>), grid, block, lds, st, g, pl.sk,
+                           rows32, out);
+      else
+        hipLaunchKernelGGL((gram_sk_kernel<VarBF16, kSkPfLarge>), grid, block, lds, st, g, pl.sk,
+                           rows32, out);
+    }
   }
 }
 
