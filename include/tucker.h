@@ -178,6 +178,40 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
                                       size_t ws_bytes, void* stream);
 
 /*
+ * Adjoint (reverse-mode derivative) of the sampled core update with the
+ * sample set held fixed.  The forward map is the solution of the sketched
+ * ridge normal equations of Alg. 1 (proof of Thm 4.2),
+ *   g = M^{-1} sum_t w_t x_t k_t,   M = sum_t w_t k_t k_t^T + lambda I,
+ * with (idx, weight) constants: the sampling weights are not differentiated
+ * through the leverage scores.  For a cotangent gbar and v = M^{-1} gbar:
+ *   x_bar[i_t]        += w_t (k_t . v)                         (observed samples)
+ *   factor_bar(n)[i_n] += alpha_t (V x_{m!=n} a^(m)_{i_m}) - beta_t (G x_{m!=n} a^(m)_{i_m})
+ * with alpha_t = w_t (x_t - k_t . g), beta_t = w_t (k_t . v), V and G the
+ * core-shaped v and g.  M is rebuilt from (idx, weight) exactly as the
+ * forward call builds it (Gram precision opts->gram_precision, FP64 Cholesky,
+ * FP64 refinement of the solve for v).
+ *
+ *   idx, weight   device, the frozen sample set of the forward call (required;
+ *                 s = opts->num_samples entries, layout as tucker_sample)
+ *   core          device, the forward result g (prod(ranks) of p->dtype)
+ *   core_bar      device, the cotangent gbar (prod(ranks) of p->dtype)
+ *   factor_bar    host array of p->order device pointers; factor_bar[n] receives
+ *                 dims[n] x ranks[n] values of p->dtype (overwritten)
+ *   x_bar         device, dense tensor of p->dtype with the shape of X
+ *                 (overwritten: zero except at sampled observed entries), or NULL
+ *   dev_info      as for tucker_core_update_sketched (refinement of the v solve)
+ * Workspace: tucker_workspace_bytes(p, opts, TK_CALL_ADJOINT).  Duplicate
+ * samples are accumulated with FP64 (factors) or p->dtype (x_bar) atomics, so
+ * results agree with a sequential sum to rounding.
+ */
+tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sketch_opts* opts,
+                                              const int32_t* idx, const double* weight,
+                                              const void* core, const void* core_bar,
+                                              void* const* factor_bar, void* x_bar,
+                                              int32_t* dev_status, double* dev_info, void* ws,
+                                              size_t ws_bytes, void* stream);
+
+/*
  * Exact core-tensor update -- Alg. 2 core step,
  *   G = argmin ||K vec G - vec X||^2 + lambda ||G||^2,
  * through the eigen form of the proof of Lemma 4.1:

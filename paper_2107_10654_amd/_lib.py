@@ -67,6 +67,9 @@ _SIGNATURES = {
     "tucker_core_update_sketched": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp, _vp, _vp,
                                                      _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                                      _vp]),
+    "tucker_core_update_sketched_adjoint": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp,
+                                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                             _vp, ctypes.c_size_t, _vp]),
     "tucker_core_update_exact": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, ctypes.c_size_t,
                                                   _vp]),
     "tucker_factor_update": (ctypes.c_int32, [_P(TkProblem), _vp, ctypes.c_int32, _vp, _vp, _vp,

@@ -166,6 +166,29 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.missing = c.take<unsigned int>(1);
 }
 
+// Extra workspace of the adjoint, carved after the sampled-update workspace.
+struct AdjWS {
+  double* g64;    // forward core (FP64)
+  double* v64;    // v = M^{-1} gbar
+  double* hg;     // whitened forward core
+  double* hv;     // whitened v
+  double* bq;     // whitened cotangent
+  double* alpha;  // per sample
+  double* nbeta;  // per sample, -beta
+  double* abar;   // factor adjoints (FP64), at geom.qoff
+};
+
+void carve_adjoint(Carver& c, const Geom& g, int64_t s, AdjWS& a) {
+  a.g64 = c.take<double>(g.d);
+  a.v64 = c.take<double>(g.d);
+  a.hg = c.take<double>(g.d);
+  a.hv = c.take<double>(g.d);
+  a.bq = c.take<double>(g.d);
+  a.alpha = c.take<double>(s);
+  a.nbeta = c.take<double>(s);
+  a.abar = c.take<double>(g.total_q);
+}
+
 struct ExactWS {
   double* V;
   double* lam;
@@ -344,6 +367,17 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       carve_sketch(c, g, s, pl, w);
       break;
     }
+    case TK_CALL_ADJOINT: {
+      if (!opts) return 0;
+      const int64_t s = resolve_samples(opts, g.d);
+      if (s < 1) return 0;
+      const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
+      SketchWS w;
+      carve_sketch(c, g, s, pl, w);
+      AdjWS a;
+      carve_adjoint(c, g, s, a);
+      break;
+    }
     case TK_CALL_EXACT: {
       ExactWS w;
       carve_exact(c, g, w);
@@ -400,6 +434,148 @@ tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf,
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
+}  // extern "C"
+
+namespace tk {
+namespace {
+
+// State shared by the sampled update and its adjoint: steps 1-6 of the
+// sampled update leave the FP64 Cholesky factor of G_Q + lambda P in w.M.
+struct SketchRun {
+  Geom g;
+  int64_t s = 0;
+  GramPlan pl;
+  SketchWS w;
+  int32_t* status = nullptr;
+  const int32_t* idx = nullptr;
+  const double* weight = nullptr;
+  hipStream_t st = nullptr;
+  const tk_sketch_opts* o = nullptr;
+  Carver carver{nullptr};
+  void stage(int k) const {
+    if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
+  }
+};
+
+tk_status check_sketch_args(const tk_problem* p, const tk_sketch_opts* o, int64_t& s) {
+  if (o->gram_precision != TK_F64 && o->gram_precision != TK_F32 && o->gram_precision != TK_BF16)
+    return TK_E_DTYPE;
+  if (o->refine_max < 0 || o->refine_max > 1000 || !(o->refine_tol >= 0.0)) return TK_E_ARG;
+  const Geom g = make_geom(p);
+  s = resolve_samples(o, g.d);
+  if (s < 1 || s > (int64_t(1) << 31) - 1) return TK_E_ARG;
+  return TK_OK;
+}
+
+// Steps 1-6: leverage scores and whitened rows, samples, gather, Gram on
+// MFMA, assembly with lambda P, FP64 Cholesky.  With frozen samples (idx_in)
+// the sampler is skipped.
+tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
+                       const double* weight_in, int32_t* idx_out, double* weight_out) {
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
+  hipStream_t st = R.st;
+  R.stage(0);
+  launch_fill_i32(1, 0, R.status, st);
+  launch_fill_i32(1, 0, w.done, st);
+  launch_fill_i32(1, 0, w.steps, st);
+  launch_fill_f64(1, 0.0, w.relres, st);
+  launch_fill_f64(1, 1e308, w.min_pivot, st);
+  launch_fill_u32(1, 0u, w.missing, st);
+
+  // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
+  launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
+                  w.lev.Q64, w.lev.Q32, R.status, st);
+  R.stage(1);
+  // 2. samples (Alg. 3 sampler) or the frozen set
+  R.idx = idx_in;
+  R.weight = weight_in;
+  if (!idx_in) {
+    int32_t* io = idx_out ? idx_out : w.idx;
+    double* wo = weight_out ? weight_out : w.weight;
+    launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st);
+    R.idx = io;
+    R.weight = wo;
+  } else if (idx_out) {
+    TK_HIP_CHECK(hipMemcpyAsync(idx_out, idx_in, sizeof(int32_t) * g.order * R.s,
+                                hipMemcpyDeviceToDevice, st));
+    TK_HIP_CHECK(hipMemcpyAsync(weight_out, weight_in, sizeof(double) * R.s,
+                                hipMemcpyDeviceToDevice, st));
+  }
+  R.stage(2);
+  // 3. sampled entries (x_t, mask) and effective weights; sample rows
+  launch_gather(g, p->X, p->dtype, p->mask, R.idx, R.weight, R.s, w.weff, w.xw, w.missing,
+                R.status, st);
+  launch_pregather(g, R.idx, w.weff, R.s, w.lev.Q64, w.rows64, w.rows32, st);
+  R.stage(3);
+  // 4. sketched Gram on MFMA, plus lambda P
+  launch_gram(g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, st);
+  R.stage(4);
+  launch_assemble(g, R.pl, w.gpart, w.lev.P, p->lambda, w.M, st);
+  // 5. right-hand side sum_t w_t x_t q_t (FP64)
+  launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, st);
+  R.stage(5);
+  // 6. FP64 Cholesky
+  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, st);
+  R.stage(6);
+  return TK_OK;
+}
+
+// h = (G_Q + lambda P)^{-1} b with FP64 iterative refinement against the
+// matrix-free FP64 residual
+//   r = b + sum_t q_t (xw_t - weff_t q_t . h) - lambda P h
+// (xw == nullptr: the xw term is absent).  The sampled update passes b = 0
+// and its xw (so that r = rhs - M h); the adjoint passes its right side b
+// and no xw.  `norm_ref` is the vector whose norm scales the stopping test.
+void refined_solve(SketchRun& R, double lambda, const double* b, const double* xw,
+                   const double* norm_ref, double* h) {
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
+  hipStream_t st = R.st;
+  launch_fill_i32(1, 0, w.done, st);
+  launch_copy_f64(g.d, b ? b : w.rhs, h, st);
+  launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, nullptr, R.status, st);
+  R.stage(7);
+  const bool refine = R.o->gram_precision != TK_F64;
+  const int iters = refine ? R.o->refine_max : 0;
+  for (int k = 0; k <= iters; ++k) {
+    launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
+    launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
+    launch_copy_f64(g.d, h, w.ph_a, st);
+    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st);
+    launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
+                        w.done, w.steps, w.relres, k < iters ? 1 : 0, st);
+    if (k < iters) {
+      launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, R.status, st);
+      launch_axpy(g.d, 1.0, w.r, h, w.done, st);
+    }
+  }
+  if (refine) launch_finish_refine(w.done, 1, R.status, st);
+  R.stage(8);
+}
+
+tk_status sketch_begin(SketchRun& R, const tk_problem* p, const tk_sketch_opts* o,
+                       int32_t* dev_status, void* ws, size_t ws_bytes, void* stream, int call) {
+  int64_t s = 0;
+  tk_status stt = check_sketch_args(p, o, s);
+  if (stt != TK_OK) return stt;
+  if (ws_bytes < tucker_workspace_bytes(p, o, call)) return TK_E_WORKSPACE;
+  R.g = make_geom(p);
+  R.s = s;
+  R.o = o;
+  R.st = static_cast<hipStream_t>(stream);
+  R.pl = plan_gram(R.g, s, o->gram_precision, 0);
+  R.carver = Carver(ws);
+  carve_sketch(R.carver, R.g, s, R.pl, R.w);
+  R.status = dev_status ? dev_status : R.w.status;
+  return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" {
+
 tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts* o,
                                       const int32_t* idx_in, const double* weight_in,
                                       int32_t* idx_out, double* weight_out, void* core_out,
@@ -410,92 +586,74 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   if (!o || !core_out || !ws) return TK_E_ARG;
   if ((idx_in == nullptr) != (weight_in == nullptr)) return TK_E_ARG;
   if ((idx_out == nullptr) != (weight_out == nullptr)) return TK_E_ARG;
-  if (o->gram_precision != TK_F64 && o->gram_precision != TK_F32 && o->gram_precision != TK_BF16)
-    return TK_E_DTYPE;
-  if (o->refine_max < 0 || o->refine_max > 1000 || !(o->refine_tol >= 0.0)) return TK_E_ARG;
-  const Geom g = make_geom(p);
-  const int64_t s = resolve_samples(o, g.d);
-  if (s < 1 || s > (int64_t(1) << 31) - 1) return TK_E_ARG;
-  if (ws_bytes < tucker_workspace_bytes(p, o, TK_CALL_SKETCHED)) return TK_E_WORKSPACE;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const GramPlan pl = plan_gram(g, s, o->gram_precision, 0);
-  Carver c(ws);
-  SketchWS w;
-  carve_sketch(c, g, s, pl, w);
-  int32_t* status = dev_status ? dev_status : w.status;
-  auto stage = [&](int k) {
-    if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
-  };
-
-  stage(0);
-  launch_fill_i32(1, 0, status, st);
-  launch_fill_i32(1, 0, w.done, st);
-  launch_fill_i32(1, 0, w.steps, st);
-  launch_fill_f64(1, 0.0, w.relres, st);
-  launch_fill_f64(1, 1e308, w.min_pivot, st);
-  launch_fill_u32(1, 0u, w.missing, st);
-
-  // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
-  launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
-                  w.lev.Q64, w.lev.Q32, status, st);
-  stage(1);
-  // 2. samples (Alg. 3 sampler) or the frozen set
-  const int32_t* idx = idx_in;
-  const double* weight = weight_in;
-  if (!idx_in) {
-    int32_t* io = idx_out ? idx_out : w.idx;
-    double* wo = weight_out ? weight_out : w.weight;
-    launch_sample(g, w.lev.cdf, s, o->seed, o->counter, o->problem, io, wo, st);
-    idx = io;
-    weight = wo;
-  } else if (idx_out) {
-    TK_HIP_CHECK(hipMemcpyAsync(idx_out, idx_in, sizeof(int32_t) * g.order * s,
-                                hipMemcpyDeviceToDevice, st));
-    TK_HIP_CHECK(hipMemcpyAsync(weight_out, weight_in, sizeof(double) * s,
-                                hipMemcpyDeviceToDevice, st));
-  }
-  stage(2);
-  // 3. sampled entries (x_t, mask) and effective weights
-  launch_gather(g, p->X, p->dtype, p->mask, idx, weight, s, w.weff, w.xw, w.missing, status, st);
-  launch_pregather(g, idx, w.weff, s, w.lev.Q64, w.rows64, w.rows32, st);
-  stage(3);
-  // 4. sketched Gram on MFMA, plus lambda P
-  launch_gram(g, pl, w.rows64, w.rows32, w.weff, s, w.gpart, st);
-  stage(4);
-  launch_assemble(g, pl, w.gpart, w.lev.P, p->lambda, w.M, st);
-  // 5. right-hand side sum_t w_t x_t q_t (FP64)
-  launch_rows_t_vec(g, w.rows64, w.xw, s, w.vpart, w.rhs, nullptr, st);
-  stage(5);
-  // 6. FP64 Cholesky and solve
-  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, status, st);
-  stage(6);
-  launch_copy_f64(g.d, w.rhs, w.h, st);
-  launch_chol_solve(w.M, w.Linv_diag, g.d, w.h, w.ytmp, w.flags, nullptr, status, st);
-  stage(7);
-  // 7. FP64 refinement (low-precision Gram) or one residual check (FP64 Gram)
-  const bool refine = o->gram_precision != TK_F64;
-  const int iters = refine ? o->refine_max : 0;
-  for (int k = 0; k <= iters; ++k) {
-    launch_residual_coef(g, w.rows64, w.xw, w.weff, w.h, s, w.vpart, w.coef, w.done, st);
-    launch_rows_t_vec(g, w.rows64, w.coef, s, w.vpart, w.r, w.done, st);
-    launch_copy_f64(g.d, w.h, w.ph_a, st);
-    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st);
-    (void)ph;
-    launch_refine_check(g.d, w.r, ph, p->lambda, w.rhs, refine ? o->refine_tol : -1.0, w.done,
-                        w.steps, w.relres, k < iters ? 1 : 0, st);
-    if (k < iters) {
-      launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, status, st);
-      launch_axpy(g.d, 1.0, w.r, w.h, w.done, st);
-    }
-  }
-  if (refine) launch_finish_refine(w.done, 1, status, st);
-  stage(8);
+  SketchRun R;
+  stt = sketch_begin(R, p, o, dev_status, ws, ws_bytes, stream, TK_CALL_SKETCHED);
+  if (stt != TK_OK) return stt;
+  stt = sketch_setup(R, p, idx_in, weight_in, idx_out, weight_out);
+  if (stt != TK_OK) return stt;
+  // 7. FP64 solve with refinement (low-precision Gram) or one residual check
+  refined_solve(R, p->lambda, nullptr, R.w.xw, R.w.rhs, R.w.h);
   // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
-  launch_copy_f64(g.d, w.h, w.ph_a, st);
-  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, st);
-  launch_cast_out(g.d, gres, core_out, p->dtype, st);
-  if (dev_info) launch_info(dev_info, s, w.missing, w.steps, w.relres, w.min_pivot, st);
-  stage(9);
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
+  launch_copy_f64(g.d, w.h, w.ph_a, R.st);
+  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, R.st);
+  launch_cast_out(g.d, gres, core_out, p->dtype, R.st);
+  if (dev_info) launch_info(dev_info, R.s, w.missing, w.steps, w.relres, w.min_pivot, R.st);
+  R.stage(9);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sketch_opts* o,
+                                              const int32_t* idx, const double* weight,
+                                              const void* core, const void* core_bar,
+                                              void* const* factor_bar, void* x_bar,
+                                              int32_t* dev_status, double* dev_info, void* ws,
+                                              size_t ws_bytes, void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!o || !idx || !weight || !core || !core_bar || !factor_bar || !ws) return TK_E_ARG;
+  for (int n = 0; n < p->order; ++n)
+    if (!factor_bar[n]) return TK_E_ARG;
+  SketchRun R;
+  stt = sketch_begin(R, p, o, dev_status, ws, ws_bytes, stream, TK_CALL_ADJOINT);
+  if (stt != TK_OK) return stt;
+  AdjWS a;
+  carve_adjoint(R.carver, R.g, R.s, a);
+  stt = sketch_setup(R, p, idx, weight, nullptr, nullptr);
+  if (stt != TK_OK) return stt;
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
+  hipStream_t st = R.st;
+  // whitened forward core h_g = ((x) L_n^T) g, so that k_t . g = q_t . h_g
+  launch_cast_in(g.d, core, p->dtype, a.g64, st);
+  launch_copy_f64(g.d, a.g64, w.ph_a, st);
+  launch_copy_f64(g.d, core_chain(g, w.ph_a, w.ph_b, w.lev.L, true, w.ttm_scratch, st), a.hg, st);
+  // whitened cotangent b = ((x) L_n^{-1}) gbar; then (G_Q + lambda P) h_v = b
+  launch_cast_in(g.d, core_bar, p->dtype, w.ph_a, st);
+  launch_copy_f64(g.d, core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, false, w.ttm_scratch, st), a.bq,
+                  st);
+  refined_solve(R, p->lambda, a.bq, nullptr, a.bq, a.hv);
+  // v = ((x) L_n^{-T}) h_v = M^{-1} gbar
+  launch_copy_f64(g.d, a.hv, w.ph_a, st);
+  launch_copy_f64(g.d, core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, st), a.v64,
+                  st);
+  // alpha_t = weff_t (x_t - k_t . g), -beta_t = -weff_t (k_t . v)
+  launch_residual_coef(g, w.rows64, w.xw, w.weff, a.hg, R.s, w.vpart, a.alpha, nullptr, st);
+  launch_residual_coef(g, w.rows64, nullptr, w.weff, a.hv, R.s, w.vpart, a.nbeta, nullptr, st);
+  // factor adjoints
+  launch_fill_f64(g.total_q, 0.0, a.abar, st);
+  launch_adjoint_factors(g, p->factors, p->dtype, idx, R.s, a.v64, a.g64, a.alpha, a.nbeta,
+                         a.abar, st);
+  for (int n = 0; n < g.order; ++n)
+    launch_cast_out(g.dims[n] * g.ranks[n], a.abar + g.qoff[n], factor_bar[n], p->dtype, st);
+  // tensor adjoint: nonzero only at sampled observed entries
+  if (x_bar) {
+    launch_zero(x_bar, static_cast<size_t>(g.numel) * (p->dtype == TK_F64 ? 8 : 4), st);
+    launch_adjoint_x(g, idx, R.s, a.nbeta, x_bar, p->dtype, st);
+  }
+  if (dev_info) launch_info(dev_info, R.s, w.missing, w.steps, w.relres, w.min_pivot, st);
+  R.stage(9);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 

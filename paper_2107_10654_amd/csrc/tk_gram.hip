@@ -858,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void dot_finish_kernel(const double* __rest
   if (t >= s) return;
   double u = 0.0;
   for (int64_t k = 0; k < nrc; ++k) u += part[k * s + t];
-  c[t] = a[t] - b[t] * u;
+  c[t] = (a ? a[t] : 0.0) - b[t] * u;
 }
 
 }  // namespace

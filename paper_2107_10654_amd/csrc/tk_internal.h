@@ -145,15 +145,30 @@ void launch_cast_in(int64_t n, const void* x, tk_dtype dt, double* y, hipStream_
 void launch_fill_i32(int64_t n, int32_t v, int32_t* p, hipStream_t st);
 void launch_fill_f64(int64_t n, double v, double* p, hipStream_t st);
 void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st);
-// Refinement bookkeeping: r -= lambda * ph; relative residual; convergence flag.
-void launch_refine_check(int64_t d, double* r, const double* ph, double lambda, const double* rhs,
-                         double tol, int32_t* done, int32_t* steps, double* relres, int count_step,
-                         hipStream_t st);
+// Refinement bookkeeping: residual update, relative residual, convergence flag:
+// r <- r + b - lambda ph (b, ph may be NULL); stops (done = 1) once
+// ||r|| <= tol ||rhs||.
+void launch_refine_check(int64_t d, double* r, const double* ph, const double* b, double lambda,
+                         const double* rhs, double tol, int32_t* done, int32_t* steps,
+                         double* relres, int count_step, hipStream_t st);
 void launch_info(double* info, int64_t s, const unsigned int* missing, const int32_t* steps,
                  const double* relres, const double* min_pivot, hipStream_t st);
 // Cholesky pivot sanity of a refinement that did not converge.
 void launch_finish_refine(const int32_t* done, int refine_enabled, int32_t* status,
                           hipStream_t st);
+
+// Adjoint of the sampled update (tk_adjoint.hip).
+size_t adjoint_lds_bytes(const Geom& g);
+// abar[qoff_n + i * R_n + r] += alpha_t (V x_{m!=n} a^(m)) - beta_t (G x_{m!=n} a^(m)) at the
+// samples' factor rows (nbeta = -beta); FP64 atomics.
+void launch_adjoint_factors(const Geom& g, const void* const* factors, tk_dtype dt,
+                            const int32_t* idx, int64_t s, const double* V, const double* G,
+                            const double* alpha, const double* nbeta, double* abar,
+                            hipStream_t st);
+// xbar[flat(idx_t)] += beta_t (dense tensor of the problem dtype).
+void launch_adjoint_x(const Geom& g, const int32_t* idx, int64_t s, const double* nbeta,
+                      void* xbar, tk_dtype dt, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // Exact path (tk_exact.hip).
 void launch_eig_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* V,

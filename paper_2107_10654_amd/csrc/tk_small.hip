@@ -182,6 +182,7 @@ __global__ void fill_kernel(int64_t n, T v, T* __restrict__ p) {
 // r <- r - lambda * ph (when ph != null); relres = ||r|| / ||rhs||; done when <= tol.
 __global__ __launch_bounds__(1024) void refine_check_kernel(int64_t d, double* __restrict__ r,
                                                             const double* __restrict__ ph,
+                                                            const double* __restrict__ bvec,
                                                             double lambda,
                                                             const double* __restrict__ rhs,
                                                             double tol, int32_t* done,
@@ -192,10 +193,9 @@ __global__ __launch_bounds__(1024) void refine_check_kernel(int64_t d, double* _
   double a = 0.0, b = 0.0;
   for (int64_t i = threadIdx.x; i < d; i += 1024) {
     double v = r[i];
-    if (ph) {
-      v = fma(-lambda, ph[i], v);
-      r[i] = v;
-    }
+    if (bvec) v += bvec[i];
+    if (ph) v = fma(-lambda, ph[i], v);
+    if (bvec || ph) r[i] = v;
     a = fma(v, v, a);
     b = fma(rhs[i], rhs[i], b);
   }
@@ -307,10 +307,10 @@ void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st) {
                      dim3(kBlock), 0, st, n, v, p);
 }
 
-void launch_refine_check(int64_t d, double* r, const double* ph, double lambda, const double* rhs,
-                         double tol, int32_t* done, int32_t* steps, double* relres, int count_step,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1024), 0, st, d, r, ph, lambda, rhs, tol,
+void launch_refine_check(int64_t d, double* r, const double* ph, const double* b, double lambda,
+                         const double* rhs, double tol, int32_t* done, int32_t* steps,
+                         double* relres, int count_step, hipStream_t st) {
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(1024), 0, st, d, r, ph, b, lambda, rhs, tol,
                      done, steps, relres, count_step);
 }
 

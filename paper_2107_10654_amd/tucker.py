@@ -213,6 +213,45 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     return res[0] if len(res) == 1 else tuple(res)
 
 
+def core_update_sketched_adjoint(X, factors, lam, idx, weight, core, core_bar, precision="f64",
+                                 mask=None, refine_max=20, refine_tol=1e-13, want_x=True,
+                                 return_info=False, check=True):
+    """Adjoint of the sampled core update with the sample set (idx, weight) held fixed.
+
+    Returns (factor_bars, x_bar) -- the gradients of <core_bar, g> w.r.t. the
+    factors and the tensor entries (x_bar is None when want_x is False).
+    """
+    lib = L.load()
+    p = make_problem(X, factors, lam, mask)
+    N = len(factors)
+    _check_tensor(idx, "idx", torch.int32)
+    _check_tensor(weight, "weight", torch.float64)
+    s = idx.shape[1]
+    if idx.dim() != 2 or idx.shape[0] != N or weight.numel() != s:
+        raise ValueError("idx must be (N, s) and weight (s,)")
+    _check_tensor(core, "core", X.dtype)
+    _check_tensor(core_bar, "core_bar", X.dtype)
+    o = _opts(s, 0, 0, 0, precision, refine_max, refine_tol)
+    dev = X.device
+    fbar = [torch.empty_like(A) for A in factors]
+    fptrs = (ctypes.c_void_p * N)(*[t.data_ptr() for t in fbar])
+    xbar = torch.empty_like(X) if want_x else None
+    info = torch.empty(L.INFO_LEN, dtype=torch.float64, device=dev) if return_info else None
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), ctypes.byref(o), L.CALL_ADJOINT)
+    if nb == 0:
+        raise ValueError("unsupported problem for the adjoint")
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_core_update_sketched_adjoint(
+        ctypes.byref(p), ctypes.byref(o), _ptr(idx), _ptr(weight), _ptr(core), _ptr(core_bar),
+        fptrs, _ptr(xbar), _ptr(st), _ptr(info), _ptr(ws), ws.numel(), _stream()),
+        "core_update_sketched_adjoint")
+    _finish(dev, st, "core_update_sketched_adjoint", check)
+    if return_info:
+        return fbar, xbar, info
+    return fbar, xbar
+
+
 def core_update_exact(X, factors, lam, check=True, out=None):
     """Exact core update (eigen form of the Kronecker normal equations)."""
     lib = L.load()

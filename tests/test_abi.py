@@ -82,7 +82,7 @@ def test_sample_count_matches_oracle(lib):
 def test_workspace_sizes(lib):
     p = _problem((512, 512, 512), (16, 16, 16))
     o = _opts(131072)
-    for call in range(5):
+    for call in range(6):
         n = lib.tucker_workspace_bytes(ctypes.byref(p), ctypes.byref(o), call)
         assert n > 0, call
     # unsupported shapes give 0
@@ -127,6 +127,15 @@ def test_host_argument_errors(lib):
     pm = _problem((64, 64, 64), (4, 4, 4))
     pm.mask = 0x3000
     assert lib.tucker_factor_update(ctypes.byref(pm), core, 0, core, core, ws, 16, st) == 1
+    # adjoint: frozen samples, core and cotangent are required
+    fb = (ctypes.c_void_p * 3)(0x10, 0x10, 0x10)
+    adj = lib.tucker_core_update_sketched_adjoint
+    assert adj(ctypes.byref(p), ctypes.byref(o), None, None, core, core, fb, None, None, None, ws,
+               16, st) == 1
+    assert adj(ctypes.byref(p), ctypes.byref(o), core, core, core, core, None, None, None, None,
+               ws, 16, st) == 1
+    assert adj(ctypes.byref(p), ctypes.byref(o), core, core, core, core, fb, None, None, None, ws,
+               16, st) == 4
     # sampler arguments
     dims = (ctypes.c_int64 * 3)(4, 4, 4)
     assert lib.tucker_sample(0, dims, core, 10, 0, 0, 0, core, core, st) == 1
