@@ -125,8 +125,10 @@ int64_t tucker_sample_count(int64_t d, double eps, double delta);
  *                        the last entry of mode n is the mode's total W_n
  *                        (the per-mode CDFs of the proof of Thm 4.2)
  * A factor whose Cholesky pivot falls to <= R_n * 2^-52 * max diag(C_n) is
- * rank deficient: dev_status gets TK_E_RANK_DEFICIENT and that mode's outputs
- * are zero.  Reads only p->order, dims, ranks, dtype and factors.
+ * rank deficient: dev_status gets TK_E_RANK_DEFICIENT and the small pivots are
+ * replaced by 1, so the outputs stay finite but are not meaningful for that
+ * mode (callers check dev_status).  Reads only p->order, dims, ranks, dtype
+ * and factors.
  */
 tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* cdf,
                                  int32_t* dev_status, void* ws, size_t ws_bytes, void* stream);
@@ -218,9 +220,16 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
  *   K^T K + lambda I = ((x)V_n) ((x)Lambda_n + lambda I) ((x)V_n)^T,
  *   C_n = A(n)^T A(n) = V_n Lambda_n V_n^T.
  * One streaming pass over X forms K^T vec X.  With a mask, the update is over
- * observed entries only, solved by preconditioned conjugate gradients with
- * the unmasked inverse as preconditioner (relative residual 1e-10, at most
- * 200 iterations; TK_E_NO_CONVERGE otherwise).
+ * the observed entries only (the masked design of Sec. 4.2),
+ *   (K~^T K~ + lambda I) g = K~^T x~,
+ * solved by preconditioned conjugate gradients in the eigenbasis above, where
+ * the unmasked operator (x)Lambda_n + lambda I is diagonal and serves as the
+ * preconditioner; the start is the unmasked solution.  Each iteration applies
+ * the masked operator fibre by fibre along the last mode without forming a
+ * tensor of X's size.  Stops at relative residual 1e-10 (FP64); after 64
+ * iterations without reaching it dev_status gets TK_E_NO_CONVERGE.  The
+ * kernels of the remaining iterations return at once, so the call stays
+ * asynchronous.
  */
 tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t* dev_status,
                                    void* ws, size_t ws_bytes, void* stream);

@@ -197,6 +197,14 @@ struct ExactWS {
   double* tA;
   double* tB;
   double* scratch;
+  // conjugate gradients (masked tensors)
+  double* b;
+  double* y;
+  double* r;
+  double* p;
+  double* q;
+  double* scal;
+  int32_t* done;
 };
 
 // largest intermediate of the mode-product chain that contracts modes in
@@ -238,6 +246,82 @@ void carve_exact(Carver& c, const Geom& g, ExactWS& w) {
   w.tA = c.take<double>(mx > g.d ? mx : g.d);
   w.tB = c.take<double>(mx > g.d ? mx : g.d);
   w.scratch = c.take<double>(kTtmScratchDoubles);
+  w.b = c.take<double>(g.d);
+  w.y = c.take<double>(g.d);
+  w.r = c.take<double>(g.d);
+  w.p = c.take<double>(g.d);
+  w.q = c.take<double>(g.d);
+  w.scal = c.take<double>(8);
+  w.done = c.take<int32_t>(1);
+}
+
+constexpr int kPcgMaxIter = 64;
+constexpr double kPcgTol = 1e-10;
+
+// q = K_W^T D K_W v (rotated masked operator without the ridge term): up the
+// chain of modes 0..N-2, the masked fibre products along mode N-1, back down.
+void masked_apply(const Geom& g, ExactWS& w, const uint32_t* mask, const double* v, double* q,
+                  const int32_t* done, hipStream_t st) {
+  const int N = g.order, L = N - 1;
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < N; ++n) dims[n] = g.ranks[n];
+  double* bufs[2] = {w.tA, w.tB};
+  int which = 0;
+  const double* cur = v;
+  for (int m = 0; m < L; ++m) {
+    launch_ttm(cur, dims, N, m, w.W + g.qoff[m], g.dims[m], false, bufs[which], w.scratch, st,
+               done);
+    dims[m] = g.dims[m];
+    cur = bufs[which];
+    which ^= 1;
+  }
+  int64_t P = 1;
+  for (int n = 0; n < L; ++n) P *= g.dims[n];
+  launch_masked_normal(cur, mask, P, g.dims[L], w.W + g.qoff[L], g.ranks[L], bufs[which], done,
+                       st);
+  cur = bufs[which];
+  which ^= 1;
+  for (int m = L - 1; m >= 0; --m) {
+    launch_ttm(cur, dims, N, m, w.W + g.qoff[m], g.ranks[m], true, bufs[which], w.scratch, st,
+               done);
+    dims[m] = g.ranks[m];
+    cur = bufs[which];
+    which ^= 1;
+  }
+  launch_copy_f64(g.d, cur, q, st);
+}
+
+// Masked exact core: preconditioned conjugate gradients in the eigenbasis
+// (tk_masked.hip).  Leaves y = ((x) V_n)^T g in w.y.
+void exact_masked(const Geom& g, const tk_problem* p, ExactWS& w, int32_t* status,
+                  hipStream_t st) {
+  const int N = g.order, L = N - 1;
+  int64_t P = 1;
+  for (int n = 0; n < L; ++n) P *= g.dims[n];
+  // b = K_W^T D x
+  launch_masked_rhs(p->X, p->dtype, p->mask, P, g.dims[L], w.W + g.qoff[L], g.ranks[L], w.tA, st);
+  int64_t dims[kMaxOrder];
+  for (int n = 0; n < N; ++n) dims[n] = g.dims[n];
+  dims[L] = g.ranks[L];
+  double* bufs[2] = {w.tA, w.tB};
+  int which = 1;
+  const double* cur = w.tA;
+  for (int m = L - 1; m >= 0; --m) {
+    launch_ttm(cur, dims, N, m, w.W + g.qoff[m], g.ranks[m], true, bufs[which], w.scratch, st);
+    dims[m] = g.ranks[m];
+    cur = bufs[which];
+    which ^= 1;
+  }
+  launch_copy_f64(g.d, cur, w.b, st);
+  // start from the unmasked solution y0 = b / ((x) Lambda_n + lambda)
+  launch_pcg_guess(g, w.lam, p->lambda, w.b, w.y, st);
+  masked_apply(g, w, p->mask, w.y, w.q, nullptr, st);
+  launch_pcg_start(g, w.lam, p->lambda, kPcgTol, w.b, w.y, w.q, w.r, w.p, w.scal, w.done, st);
+  for (int k = 0; k < kPcgMaxIter; ++k) {
+    masked_apply(g, w, p->mask, w.p, w.q, w.done, st);
+    launch_pcg_step(g, w.lam, p->lambda, kPcgTol, w.q, w.y, w.r, w.p, w.scal, w.done, st);
+  }
+  launch_pcg_finish(w.done, status, st);
 }
 
 struct FactorWS {
@@ -662,7 +746,6 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
   tk_status stt = check_problem(p, true);
   if (stt != TK_OK) return stt;
   if (!core_out || !dev_status || !ws) return TK_E_ARG;
-  if (p->mask) return TK_E_ARG;
   if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_EXACT)) return TK_E_WORKSPACE;
   const Geom g = make_geom(p);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -671,6 +754,12 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
   carve_exact(c, g, w);
   launch_fill_i32(1, 0, dev_status, st);
   launch_eig_modes(g, p->factors, p->dtype, w.V, w.lam, w.W, w.C, st);
+  if (p->mask) {
+    exact_masked(g, p, w, dev_status, st);
+    const double* G = core_chain(g, w.y, w.tA, w.V, false, w.scratch, st);
+    launch_cast_out(g.d, G, core_out, p->dtype, st);
+    return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+  }
   // K^T vec X = X x_N W_N^T ... x_1 W_1^T (W_n = A(n) V_n), last mode first
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];

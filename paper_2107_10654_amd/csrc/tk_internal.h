@@ -130,9 +130,11 @@ void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, doub
 // T' = T x_mode M  for row-major T of shape dims (order n), M: J x dims[mode]
 // (row-major; transpose_M: M stored dims[mode] x J).  scratch (nullable, at
 // least kTtmScratchDoubles) lets a contraction with few fibres split over i.
+// done (nullable): the kernels return at once when *done != 0.
 constexpr int64_t kTtmScratchDoubles = int64_t(2) * 65536 * kMaxRank;
 void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
-                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st);
+                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st,
+                const int32_t* done = nullptr);
 // ttm over an input of element type dt (F32 or F64) -> FP64 output
 void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
                     const double* M, int64_t J, bool transpose_M, double* out, double* scratch,
@@ -169,6 +171,23 @@ void launch_adjoint_factors(const Geom& g, const void* const* factors, tk_dtype 
 void launch_adjoint_x(const Geom& g, const int32_t* idx, int64_t s, const double* nbeta,
                       void* xbar, tk_dtype dt, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// Masked exact core (tk_masked.hip): fibres along the last mode, P fibres of
+// length I, W = W_{N-1} (I x R, row-major).
+void launch_masked_rhs(const void* X, tk_dtype dt, const uint32_t* mask, int64_t P, int64_t I,
+                       const double* W, int R, double* out, hipStream_t st);
+void launch_masked_normal(const double* H, const uint32_t* mask, int64_t P, int64_t I,
+                          const double* W, int R, double* out, const int32_t* done,
+                          hipStream_t st);
+void launch_pcg_guess(const Geom& g, const double* lam, double lambda, const double* b, double* y,
+                      hipStream_t st);
+void launch_pcg_start(const Geom& g, const double* lam, double lambda, double tol, const double* b,
+                      const double* y, const double* q, double* r, double* p, double* scal,
+                      int32_t* done, hipStream_t st);
+void launch_pcg_step(const Geom& g, const double* lam, double lambda, double tol, const double* q,
+                     double* y, double* r, double* p, double* scal, int32_t* done,
+                     hipStream_t st);
+void launch_pcg_finish(const int32_t* done, int32_t* status, hipStream_t st);
 
 // Exact path (tk_exact.hip).
 void launch_eig_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* V,

@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kBlock) void ttm_fibre_kernel(const T* __restrict__
                                                            const double* __restrict__ M, int64_t J,
                                                            bool trans, int64_t j0, int jn,
                                                            int64_t ilen, int64_t split_stride,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out,
+                                                           const int32_t* done) {
+  if (done && *done) return;
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= P * Q) return;
   const int64_t p = e / Q, q = e % Q;
@@ -39,6 +41,7 @@ __global__ __launch_bounds__(kBlock) void ttm_fibre_kernel(const T* __restrict__
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) acc[j] = 0.0;
   const T* src = in + p * I * Q + q;
+#pragma unroll 4
   for (int64_t i = ia; i < ib; ++i) {
     const double x = ldd(src, i * Q);
 #pragma unroll
@@ -52,7 +55,8 @@ __global__ __launch_bounds__(kBlock) void ttm_fibre_kernel(const T* __restrict__
 }
 
 __global__ void sum_splits_kernel(const double* __restrict__ part, int64_t nsplit, int64_t n,
-                                  double* __restrict__ out) {
+                                  double* __restrict__ out, const int32_t* done) {
+  if (done && *done) return;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
   double v = 0.0;
@@ -65,7 +69,9 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ in, int64_t P,
                                                           int64_t I, const double* __restrict__ M,
                                                           int64_t J, bool trans,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out,
+                                                          const int32_t* done) {
+  if (done && *done) return;
   __shared__ double Xs[64][65];
   __shared__ double Ms[64][kMaxRank + 1];
   const int tid = threadIdx.x;
@@ -115,14 +121,15 @@ constexpr int64_t kTtmThreadsWanted = 65536;
 
 template <class T>
 void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const double* M,
-                  int64_t J, bool trans, double* out, double* scratch, hipStream_t st) {
+                  int64_t J, bool trans, double* out, double* scratch, hipStream_t st,
+                  const int32_t* done) {
   int64_t P = 1, Q = 1;
   for (int m = 0; m < mode; ++m) P *= dims[m];
   for (int m = mode + 1; m < order; ++m) Q *= dims[m];
   const int64_t I = dims[mode];
   if (Q == 1 && J <= kMaxRank && P >= 64 * 256) {
     hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
-                       0, st, in, P, I, M, J, trans, out);
+                       0, st, in, P, I, M, J, trans, out, done);
     return;
   }
   // split the contraction over i when there are too few fibres to fill the GPU
@@ -143,21 +150,21 @@ void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const d
     const int jn = static_cast<int>((J - j0) < 64 ? (J - j0) : 64);
     if (jn <= 8)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 8>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, ilen, stride, dst);
+                         trans, j0, jn, ilen, stride, dst, done);
     else if (jn <= 16)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 16>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, ilen, stride, dst);
+                         trans, j0, jn, ilen, stride, dst, done);
     else if (jn <= 32)
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 32>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, ilen, stride, dst);
+                         trans, j0, jn, ilen, stride, dst, done);
     else
       hipLaunchKernelGGL((ttm_fibre_kernel<T, 64>), grid, dim3(kBlock), 0, st, in, P, I, Q, M, J,
-                         trans, j0, jn, ilen, stride, dst);
+                         trans, j0, jn, ilen, stride, dst, done);
   }
   if (nsplit > 1)
     hipLaunchKernelGGL(sum_splits_kernel, dim3(static_cast<unsigned>(cdiv(stride, kBlock))),
                        dim3(kBlock), 0, st, static_cast<const double*>(scratch), nsplit, stride,
-                       out);
+                       out, done);
 }
 
 __global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x,
@@ -239,8 +246,9 @@ __global__ void finish_refine_kernel(const int32_t* done, int refine_enabled, in
 }  // namespace
 
 void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const double* M,
-                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st) {
-  ttm_dispatch<double>(T, dims, order, mode, M, J, transpose_M, out, scratch, st);
+                int64_t J, bool transpose_M, double* out, double* scratch, hipStream_t st,
+                const int32_t* done) {
+  ttm_dispatch<double>(T, dims, order, mode, M, J, transpose_M, out, scratch, st, done);
 }
 
 void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
@@ -248,10 +256,10 @@ void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, 
                     hipStream_t st) {
   if (dt == TK_F64)
     ttm_dispatch<double>(static_cast<const double*>(T), dims, order, mode, M, J, transpose_M, out,
-                         scratch, st);
+                         scratch, st, nullptr);
   else
     ttm_dispatch<float>(static_cast<const float*>(T), dims, order, mode, M, J, transpose_M, out,
-                        scratch, st);
+                        scratch, st, nullptr);
 }
 
 void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,

@@ -252,10 +252,11 @@ def core_update_sketched_adjoint(X, factors, lam, idx, weight, core, core_bar, p
     return fbar, xbar
 
 
-def core_update_exact(X, factors, lam, check=True, out=None):
-    """Exact core update (eigen form of the Kronecker normal equations)."""
+def core_update_exact(X, factors, lam, mask=None, check=True, out=None):
+    """Exact core update (eigen form of the Kronecker normal equations; with a
+    mask, preconditioned conjugate gradients over the observed entries)."""
     lib = L.load()
-    p = make_problem(X, factors, lam)
+    p = make_problem(X, factors, lam, mask)
     dev = X.device
     core = out if out is not None else torch.empty([A.shape[1] for A in factors], dtype=X.dtype,
                                                    device=dev)

@@ -122,7 +122,7 @@ def test_host_argument_errors(lib):
     bad = _problem((64, 64, 64), (4, 4, 4), lam=-1.0)
     assert f(ctypes.byref(bad), ctypes.byref(o), None, None, None, None, core, None, None, ws, 16,
              st) == 1
-    # factor update: bad mode; exact: mask unsupported
+    # factor update: bad mode; mask unsupported
     assert lib.tucker_factor_update(ctypes.byref(p), core, 3, core, core, ws, 16, st) == 1
     pm = _problem((64, 64, 64), (4, 4, 4))
     pm.mask = 0x3000

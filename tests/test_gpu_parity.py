@@ -162,6 +162,29 @@ def test_exact_core_matches_oracle(tk, dims, ranks, dtype):
 
 
 @pytest.mark.parametrize("dims,ranks", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_exact_core_masked_matches_oracle(tk, dims, ranks, dtype):
+    # PCG on both sides to 1e-10 (GPU) / 1e-12 (oracle) relative residual; the
+    # preconditioned system is well conditioned (20 % missing), so the
+    # solutions agree to ~1e-9
+    p, F = _sketch_case(dims, ranks, 10, dtype=dtype, missing=0.2)
+    lam = 1e-3
+    G = tk.core_update_exact(T(p["X"]), [T(A) for A in F], lam, mask=T(p["mask"].view(np.int32)))
+    ref = oracle.core_update_exact_masked(p["X"].astype(np.float64),
+                                          [A.astype(np.float64) for A in F], lam, p["mask"])
+    assert rel(G.cpu().numpy(), ref) <= (1e-8 if dtype == "f64" else 1e-6)
+
+
+def test_exact_core_all_observed_mask_equals_unmasked(tk):
+    p, F = _sketch_case((19, 17, 15), (3, 4, 5), 11)
+    X, FF = T(p["X"]), [T(A) for A in F]
+    ones = workloads.pack_mask(np.ones(p["X"].shape, dtype=bool))
+    Gm = tk.core_update_exact(X, FF, 1e-3, mask=T(ones.view(np.int32)))
+    Gu = tk.core_update_exact(X, FF, 1e-3)
+    assert rel(Gm.cpu().numpy(), Gu.cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
 def test_factor_update_matches_oracle(tk, dims, ranks):
     p, F = _sketch_case(dims, ranks, 10)
     lam = 1e-2
