@@ -214,6 +214,58 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
                                               size_t ws_bytes, void* stream);
 
 /*
+ * Batched sampled core updates: `count` (1..TK_MAX_BATCH) independent
+ * problems of any shapes and ranks, each updated exactly as
+ * tucker_core_update_sketched would (same samples for the same seed,
+ * counter and problem fields), with the sketched Grams of all problems
+ * computed by ONE persistent stream-K launch: the (tile, 32-sample chunk)
+ * units of every problem are laid out back to back and split evenly over the
+ * GPU, so small and large problems share the machine.  Leverage scores,
+ * sampling, assembly, Cholesky and refinement run per problem on `stream`.
+ * The call neither allocates nor synchronises, so it can be captured in a
+ * HIP graph and replayed.
+ *
+ *   probs, opts   host arrays [count]; every opts[k].gram_precision is the same,
+ *                 TK_F32 or TK_BF16 (FP32 accumulation; FP64 solve and refinement)
+ *   cfg           tile shape and persistent grid of the batched Gram (NULL: tile
+ *                 128, 3 workgroups per CU); tucker_tune_batched picks one
+ *   core_out      host array [count] of device pointers (prod(ranks_k) of dtype_k)
+ *   dev_status    device int32 [count], one status word per problem
+ *   dev_info      device double [count][TK_INFO_LEN] or NULL (as for the single call)
+ * Workspace: tucker_workspace_bytes_batched(probs, opts, count, cfg).
+ */
+#define TK_MAX_BATCH 64
+
+typedef struct {
+  int32_t tile;      /* Gram output tile edge: 64 or 128 (0: 128) */
+  int32_t wg_per_cu; /* workgroups per compute unit in the persistent grid, 1..8 (0: 3) */
+} tk_batch_config;
+
+size_t tucker_workspace_bytes_batched(const tk_problem* probs, const tk_sketch_opts* opts,
+                                      int32_t count, const tk_batch_config* cfg);
+
+tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_sketch_opts* opts,
+                                              int32_t count, const tk_batch_config* cfg,
+                                              void* const* core_out, int32_t* dev_status,
+                                              double* dev_info, void* ws, size_t ws_bytes,
+                                              void* stream);
+
+/*
+ * Autotuner of the batched call: runs steps 1-3 of every problem once, then
+ * times the batched Gram launch (one warm-up, one timed run, HIP events on
+ * `stream`) for each candidate tile shape and grid -- tile 128 with 3 or 2
+ * workgroups per CU, tile 64 with 4, 5 or 6 -- and returns the fastest in
+ * *best.  Unlike every other call it synchronises `stream`, so run it once
+ * per batch shape before capturing the batched call.  The workspace must be
+ * tucker_workspace_bytes_batched(probs, opts, count, NULL) bytes (enough for
+ * every candidate).  times_ms (host, may be NULL) receives each candidate's
+ * time and *n_candidates (may be NULL) their number.
+ */
+tk_status tucker_tune_batched(const tk_problem* probs, const tk_sketch_opts* opts, int32_t count,
+                              void* ws, size_t ws_bytes, void* stream, tk_batch_config* best,
+                              double* times_ms, int32_t* n_candidates);
+
+/*
  * Exact core-tensor update -- Alg. 2 core step,
  *   G = argmin ||K vec G - vec X||^2 + lambda ||G||^2,
  * through the eigen form of the proof of Lemma 4.1:

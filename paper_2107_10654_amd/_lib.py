@@ -52,6 +52,12 @@ class TkSketchOpts(ctypes.Structure):
     ]
 
 
+class TkBatchConfig(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+
+MAX_BATCH = 64
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 _SIGNATURES = {
@@ -70,6 +76,15 @@ _SIGNATURES = {
     "tucker_core_update_sketched_adjoint": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp,
                                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                              _vp, ctypes.c_size_t, _vp]),
+    "tucker_workspace_bytes_batched": (ctypes.c_size_t, [_P(TkProblem), _P(TkSketchOpts),
+                                                         ctypes.c_int32, _P(TkBatchConfig)]),
+    "tucker_core_update_sketched_batched": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts),
+                                                             ctypes.c_int32, _P(TkBatchConfig),
+                                                             _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                                             _vp]),
+    "tucker_tune_batched": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), ctypes.c_int32, _vp,
+                                             ctypes.c_size_t, _vp, _P(TkBatchConfig),
+                                             _P(ctypes.c_double), _P(ctypes.c_int32)]),
     "tucker_core_update_exact": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, ctypes.c_size_t,
                                                   _vp]),
     "tucker_factor_update": (ctypes.c_int32, [_P(TkProblem), _vp, ctypes.c_int32, _vp, _vp, _vp,

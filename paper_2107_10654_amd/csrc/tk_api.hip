@@ -134,14 +134,15 @@ struct SketchWS {
   unsigned int* missing;
 };
 
-void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w) {
+void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w,
+                  bool with_partials = true) {
   carve_lev(c, g, w.lev);
   const int64_t d = g.d;
   w.idx = c.take<int32_t>(static_cast<size_t>(g.order) * s);
   w.weight = c.take<double>(s);
   w.weff = c.take<double>(s);
   w.xw = c.take<double>(s);
-  w.gpart = c.take<char>(gram_partial_bytes(g, pl));
+  w.gpart = with_partials ? c.take<char>(gram_partial_bytes(g, pl)) : nullptr;
   w.M = c.take<double>(static_cast<size_t>(d) * d);
   const int64_t nblk = cdiv(d, kCholNb);
   w.Linv_diag = c.take<double>(nblk * kCholNb * kCholNb);
@@ -551,11 +552,11 @@ tk_status check_sketch_args(const tk_problem* p, const tk_sketch_opts* o, int64_
   return TK_OK;
 }
 
-// Steps 1-6: leverage scores and whitened rows, samples, gather, Gram on
-// MFMA, assembly with lambda P, FP64 Cholesky.  With frozen samples (idx_in)
-// the sampler is skipped.
-tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
-                       const double* weight_in, int32_t* idx_out, double* weight_out) {
+// Steps 1-3: leverage scores and whitened rows, samples, gather and the
+// pre-gathered sample rows.  With frozen samples (idx_in) the sampler is
+// skipped.
+tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
+                     const double* weight_in, int32_t* idx_out, double* weight_out) {
   const Geom& g = R.g;
   SketchWS& w = R.w;
   hipStream_t st = R.st;
@@ -592,16 +593,32 @@ tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
                 R.status, st);
   launch_pregather(g, R.idx, w.weff, R.s, w.lev.Q64, w.rows64, w.rows32, st);
   R.stage(3);
-  // 4. sketched Gram on MFMA, plus lambda P
-  launch_gram(g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, st);
-  R.stage(4);
-  launch_assemble(g, R.pl, w.gpart, w.lev.P, p->lambda, w.M, st);
+  return TK_OK;
+}
+
+// Steps 5-6 after the Gram is assembled: right side and FP64 Cholesky.
+void sketch_factor(SketchRun& R) {
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
   // 5. right-hand side sum_t w_t x_t q_t (FP64)
-  launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, st);
+  launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
   // 6. FP64 Cholesky
-  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, st);
+  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, R.st);
   R.stage(6);
+}
+
+// Steps 1-6 of one problem: ... the sketched Gram on MFMA (4) and its
+// assembly with lambda P, then the right side and the Cholesky factor.
+tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
+                       const double* weight_in, int32_t* idx_out, double* weight_out) {
+  tk_status stt = sketch_pre(R, p, idx_in, weight_in, idx_out, weight_out);
+  if (stt != TK_OK) return stt;
+  // 4. sketched Gram on MFMA, plus lambda P
+  launch_gram(R.g, R.pl, R.w.rows64, R.w.rows32, R.w.weff, R.s, R.w.gpart, R.st);
+  R.stage(4);
+  launch_assemble(R.g, R.pl, R.w.gpart, R.w.lev.P, p->lambda, R.w.M, R.st);
+  sketch_factor(R);
   return TK_OK;
 }
 
@@ -638,21 +655,85 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   R.stage(8);
 }
 
-tk_status sketch_begin(SketchRun& R, const tk_problem* p, const tk_sketch_opts* o,
-                       int32_t* dev_status, void* ws, size_t ws_bytes, void* stream, int call) {
+// Validates one problem's sampled-update arguments and carves its workspace
+// from `c` (the Gram partials too unless the problem is part of a batch).
+tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* o,
+                       int32_t* dev_status, Carver& c, void* stream, bool with_partials) {
   int64_t s = 0;
   tk_status stt = check_sketch_args(p, o, s);
   if (stt != TK_OK) return stt;
-  if (ws_bytes < tucker_workspace_bytes(p, o, call)) return TK_E_WORKSPACE;
   R.g = make_geom(p);
   R.s = s;
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_gram(R.g, s, o->gram_precision, 0);
-  R.carver = Carver(ws);
-  carve_sketch(R.carver, R.g, s, R.pl, R.w);
+  carve_sketch(c, R.g, s, R.pl, R.w, with_partials);
   R.status = dev_status ? dev_status : R.w.status;
   return TK_OK;
+}
+
+tk_status sketch_begin(SketchRun& R, const tk_problem* p, const tk_sketch_opts* o,
+                       int32_t* dev_status, void* ws, size_t ws_bytes, void* stream, int call) {
+  if (ws_bytes < tucker_workspace_bytes(p, o, call)) {
+    int64_t s = 0;
+    const tk_status stt = check_sketch_args(p, o, s);
+    return stt != TK_OK ? stt : TK_E_WORKSPACE;
+  }
+  R.carver = Carver(ws);
+  return sketch_carve(R, p, o, dev_status, R.carver, stream, true);
+}
+
+// ---------------------------------------------------------------- batches
+constexpr int kTuneCandidates = 5;
+const SkConfig kTuneSet[kTuneCandidates] = {{128, 3}, {128, 2}, {64, 4}, {64, 5}, {64, 6}};
+
+SkConfig batch_config(const tk_batch_config* cfg) {
+  SkConfig c{128, 3};
+  if (cfg && cfg->tile) c.tile = cfg->tile;
+  if (cfg && cfg->wg_per_cu) c.wg_per_cu = cfg->wg_per_cu;
+  return c;
+}
+
+tk_status check_batch(const tk_problem* probs, const tk_sketch_opts* opts, int32_t count) {
+  if (!probs || !opts || count < 1 || count > kSkMaxBatch) return TK_E_ARG;
+  const int32_t prec = opts[0].gram_precision;
+  if (prec != TK_F32 && prec != TK_BF16) return TK_E_DTYPE;
+  for (int k = 0; k < count; ++k) {
+    const tk_status stt = check_problem(&probs[k], true);
+    if (stt != TK_OK) return stt;
+    if (opts[k].gram_precision != prec) return TK_E_DTYPE;
+    int64_t s = 0;
+    const tk_status st2 = check_sketch_args(&probs[k], &opts[k], s);
+    if (st2 != TK_OK) return st2;
+  }
+  return TK_OK;
+}
+
+// Carves every problem's workspace (without per-problem partials) and fills
+// the stream-K batch descriptor; then the shared partial slots and index.
+void carve_batch(Carver& c, const tk_problem* probs, const tk_sketch_opts* opts, int32_t count,
+                 const SkConfig& cfg, SketchRun* runs, int32_t* dev_status, void* stream,
+                 SkBatch& b, float*& slots, int64_t*& index) {
+  b.count = count;
+  for (int k = 0; k < count; ++k) {
+    (void)sketch_carve(runs[k], &probs[k], &opts[k], dev_status ? dev_status + k : nullptr, c,
+                       stream, false);
+    b.p[k] = sk_prob(runs[k].g, runs[k].s, runs[k].w.rows32);
+  }
+  sk_finalize(b, static_cast<tk_dtype>(opts[0].gram_precision), cfg);
+  slots = c.take<float>(sk_slot_bytes(b) / sizeof(float));
+  index = c.take<int64_t>(sk_index_bytes(b) / sizeof(int64_t));
+}
+
+size_t batch_bytes(const tk_problem* probs, const tk_sketch_opts* opts, int32_t count,
+                   const SkConfig& cfg) {
+  SketchRun runs[kSkMaxBatch];
+  SkBatch b;
+  Carver c(nullptr);
+  float* slots;
+  int64_t* index;
+  carve_batch(c, probs, opts, count, cfg, runs, nullptr, nullptr, b, slots, index);
+  return c.used + 256;
 }
 
 }  // namespace
@@ -738,6 +819,118 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
   }
   if (dev_info) launch_info(dev_info, R.s, w.missing, w.steps, w.relres, w.min_pivot, st);
   R.stage(9);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+size_t tucker_workspace_bytes_batched(const tk_problem* probs, const tk_sketch_opts* opts,
+                                      int32_t count, const tk_batch_config* cfg) {
+  if (check_batch(probs, opts, count) != TK_OK) return 0;
+  if (cfg) {
+    const SkConfig c = batch_config(cfg);
+    if (!sk_config_valid(c)) return 0;
+    return batch_bytes(probs, opts, count, c);
+  }
+  size_t mx = 0;  // enough for every configuration the tuner tries
+  for (int k = 0; k < kTuneCandidates; ++k) {
+    const size_t v = batch_bytes(probs, opts, count, kTuneSet[k]);
+    mx = v > mx ? v : mx;
+  }
+  return mx;
+}
+
+tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_sketch_opts* opts,
+                                              int32_t count, const tk_batch_config* cfg,
+                                              void* const* core_out, int32_t* dev_status,
+                                              double* dev_info, void* ws, size_t ws_bytes,
+                                              void* stream) {
+  tk_status stt = check_batch(probs, opts, count);
+  if (stt != TK_OK) return stt;
+  if (!core_out || !dev_status || !ws) return TK_E_ARG;
+  for (int k = 0; k < count; ++k)
+    if (!core_out[k]) return TK_E_ARG;
+  const SkConfig conf = batch_config(cfg);
+  if (!sk_config_valid(conf)) return TK_E_ARG;
+  if (ws_bytes < batch_bytes(probs, opts, count, conf)) return TK_E_WORKSPACE;
+  SketchRun runs[kSkMaxBatch];
+  SkBatch b;
+  float* slots = nullptr;
+  int64_t* index = nullptr;
+  Carver c(ws);
+  carve_batch(c, probs, opts, count, conf, runs, dev_status, stream, b, slots, index);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // steps 1-3 per problem
+  for (int k = 0; k < count; ++k) {
+    stt = sketch_pre(runs[k], &probs[k], nullptr, nullptr, nullptr, nullptr);
+    if (stt != TK_OK) return stt;
+  }
+  // step 4 for the whole batch: one persistent stream-K launch
+  launch_gram_sk(b, slots, index, st);
+  // steps 4 (assembly) to 8 per problem
+  for (int k = 0; k < count; ++k) {
+    SketchRun& R = runs[k];
+    const tk_problem* p = &probs[k];
+    launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, p->lambda, R.w.M, st);
+    sketch_factor(R);
+    refined_solve(R, p->lambda, nullptr, R.w.xw, R.w.rhs, R.w.h);
+    launch_copy_f64(R.g.d, R.w.h, R.w.ph_a, st);
+    const double* gres =
+        core_chain(R.g, R.w.ph_a, R.w.ph_b, R.w.lev.Linv, true, R.w.ttm_scratch, st);
+    launch_cast_out(R.g.d, gres, core_out[k], p->dtype, st);
+    if (dev_info)
+      launch_info(dev_info + static_cast<int64_t>(k) * TK_INFO_LEN, R.s, R.w.missing, R.w.steps,
+                  R.w.relres, R.w.min_pivot, st);
+  }
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_tune_batched(const tk_problem* probs, const tk_sketch_opts* opts, int32_t count,
+                              void* ws, size_t ws_bytes, void* stream, tk_batch_config* best,
+                              double* times_ms, int32_t* n_candidates) {
+  tk_status stt = check_batch(probs, opts, count);
+  if (stt != TK_OK) return stt;
+  if (!ws || !best) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes_batched(probs, opts, count, nullptr))
+    return TK_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TK_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TK_E_HIP;
+  }
+  double best_ms = 1e300;
+  int best_k = 0;
+  for (int k = 0; k < kTuneCandidates; ++k) {
+    SketchRun runs[kSkMaxBatch];
+    SkBatch b;
+    float* slots = nullptr;
+    int64_t* index = nullptr;
+    Carver c(ws);
+    carve_batch(c, probs, opts, count, kTuneSet[k], runs, nullptr, stream, b, slots, index);
+    if (k == 0)  // the samples and rows are the same for every candidate
+      for (int q = 0; q < count; ++q)
+        (void)sketch_pre(runs[q], &probs[q], nullptr, nullptr, nullptr, nullptr);
+    launch_gram_sk(b, slots, index, st);  // warm-up
+    (void)hipEventRecord(e0, st);
+    launch_gram_sk(b, slots, index, st);
+    (void)hipEventRecord(e1, st);
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      stt = TK_E_HIP;
+      break;
+    }
+    if (times_ms) times_ms[k] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_k = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (stt != TK_OK) return stt;
+  best->tile = kTuneSet[best_k].tile;
+  best->wg_per_cu = kTuneSet[best_k].wg_per_cu;
+  if (n_candidates) *n_candidates = kTuneCandidates;
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 

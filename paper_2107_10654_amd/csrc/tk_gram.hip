@@ -18,76 +18,12 @@
 // o = r / R_L and r % R_L, so y_t[r] = O_t[o] * q^(L)_{i_L}[r % R_L] with
 // O_t[o] = sqrt(weff_t) prod_{n != L} q^(n)_{i_n}[digit_n(o)] staged per chunk
 // (modes after L have rank 1 and contribute their single entry).
-#include "tk_internal.h"
+#include <string.h>
+
+#include "tk_mfma.h"
 
 namespace tk {
 namespace {
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
-typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
-
-// ------------------------------------------------------------------ MFMA variants
-// Operand fragment of lane l: row (l % MT), k-run starting at (l / MT) * EPL.
-// Accumulator element v of lane l maps to (row, col) by acc_row / acc_col.
-struct VarF64 {
-  using Src = double;
-  using Op = double;
-  using Acc = doublex4;
-  using Out = double;
-  static constexpr int MT = 16, KT = 4, EPL = 1, NACC = 4;
-  static constexpr int TILE = 64, BK = kRowChunk, LDK = BK + 1;
-  __device__ static Acc mma(const Op* a, const Op* b, Acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
-  }
-  // FP64 16x16x4: accumulator register v of lane l holds row l / 16 + 4 v
-  __device__ static int acc_row(int lane, int v) { return lane / 16 + 4 * v; }
-  __device__ static int acc_col(int lane, int) { return lane % 16; }
-  __device__ static Op cvt(Src x) { return x; }
-};
-
-struct VarF32 {
-  using Src = float;
-  using Op = float;
-  using Acc = floatx16;
-  using Out = float;
-  static constexpr int MT = 32, KT = 2, EPL = 1, NACC = 16;
-  static constexpr int TILE = 128, BK = kRowChunk, LDK = BK + 1;
-  __device__ static Acc mma(const Op* a, const Op* b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], c, 0, 0, 0);
-  }
-  __device__ static int acc_row(int lane, int v) { return 8 * (v / 4) + 4 * (lane / 32) + (v % 4); }
-  __device__ static int acc_col(int lane, int) { return lane % 32; }
-  __device__ static Op cvt(Src x) { return x; }
-};
-
-struct VarBF16 {
-  using Src = float;
-  using Op = __bf16;
-  using Acc = floatx16;
-  using Out = float;
-  static constexpr int MT = 32, KT = 16, EPL = 8, NACC = 16;
-  static constexpr int TILE = 128, BK = kRowChunk, LDK = BK + 8;
-  __device__ static Acc mma(const Op* a, const Op* b, Acc c) {
-    const bf16x8 va = *reinterpret_cast<const bf16x8*>(a);
-    const bf16x8 vb = *reinterpret_cast<const bf16x8*>(b);
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(va, vb, c, 0, 0, 0);
-  }
-  __device__ static int acc_row(int lane, int v) { return 8 * (v / 4) + 4 * (lane / 32) + (v % 4); }
-  __device__ static int acc_col(int lane, int) { return lane % 32; }
-  __device__ static Op cvt(Src x) { return static_cast<__bf16>(x); }
-};
-
-
-// lower-triangular tile index -> (ti, tj), ti >= tj
-__device__ inline void tri_index(int64_t tau, int64_t& ti, int64_t& tj) {
-  int64_t i = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(tau) + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= tau) ++i;
-  while (i * (i + 1) / 2 > tau) --i;
-  ti = i;
-  tj = tau - i * (i + 1) / 2;
-}
 
 // ------------------------------------------------------------------ pre-gather
 __global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t* __restrict__ idx,
@@ -296,282 +232,6 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(Geom g,
         const int64_t cc = c0 + wc * WT + b * V::MT + V::acc_col(lane, v);
         if (r < d && cc < d) out[r * d + cc] = static_cast<typename V::Out>(acc[a][b][v]);
       }
-}
-
-// ------------------------------------------------------------------ stream-K Gram (FP32 / BF16)
-// T x T output tiles (T = 128), 4 waves (2 x 2), each wave (T/2) x (T/2) in MFMA
-// 32 x 32 blocks; up to three workgroups share a CU so some form Kronecker rows
-// while others run MFMA.  The (tile, chunk of 32 samples) units are laid out
-// tile by tile; workgroup w walks units [w U / G, (w + 1) U / G) and writes one
-// partial tile per tile it touches into slot w * maxseg + k.  The assembly
-// kernel sums the slots of each tile in workgroup order (deterministic).
-// LDS (dynamic, sized by sum_r): Y tiles | outer products | offsets | rows.
-constexpr int kSkT = 128;
-constexpr int kSkThreads = 256;
-#ifndef TK_SK_WG_PER_CU
-#define TK_SK_WG_PER_CU 3
-#endif
-constexpr int kSkWgPerCu = TK_SK_WG_PER_CU;
-constexpr int kSkNO = kSkT / 2 + 1;  // outer indices per tile (R_L >= 2)
-constexpr int kSkRT = kRowChunk + 4; // padded LDS row: conflict-free 32-byte reads
-
-template <class V>
-struct SkLayout {
-  static constexpr int BK = V::BK;
-  static constexpr size_t y_bytes = sizeof(typename V::Op) * kSkT * V::LDK;     // one side
-  static constexpr size_t o_bytes = sizeof(typename V::Src) * kSkNO * BK;       // one side
-  static constexpr size_t offs_bytes = 2 * kSkNO * kMaxOrder;
-  static constexpr size_t fixed = 2 * y_bytes + 2 * o_bytes + offs_bytes;
-  // rows: sum_r rows plus one zero row
-  __host__ __device__ static size_t bytes(int sum_r) {
-    return fixed + sizeof(typename V::Src) * static_cast<size_t>(sum_r + 1) * kSkRT;
-  }
-};
-
-__host__ __device__ inline int64_t sk_unit_start(const SkPlan& sp, int64_t w) {
-  return (w * sp.units) / sp.grid;
-}
-
-// PF4: 16-byte prefetch registers per thread; a chunk of rows holds
-// kRowChunk * sum_r values, so PF4 * 4 * kSkThreads >= kRowChunk * sum_r.
-constexpr int kSkPfSmall = 2;  // sum_r <= 64
-constexpr int kSkPfLarge = (kRowChunk * kMaxSumR / 4 + kSkThreads - 1) / kSkThreads;
-__host__ __device__ constexpr int sk_pf_slots(int sum_r) {
-  return kRowChunk * sum_r <= 4 * kSkThreads * kSkPfSmall ? kSkPfSmall : kSkPfLarge;
-}
-
-template <class V, int PF4>
-__global__ __launch_bounds__(kSkThreads, kSkWgPerCu) void gram_sk_kernel(
-    Geom g, SkPlan sp, const typename V::Src* __restrict__ rows,
-    typename V::Out* __restrict__ slots) {
-  using Src = typename V::Src;
-  using Op = typename V::Op;
-  using Acc = typename V::Acc;
-  using L = SkLayout<V>;
-  constexpr int T = kSkT, BK = V::BK, LDK = V::LDK, RT = kSkRT, NO = kSkNO;
-  constexpr int IW = V::EPL == 8 ? 8 : 4;         // samples per formation item
-  constexpr int IPR = BK / IW;                    // items per row
-  constexpr int ITEMS = T * IPR / kSkThreads;     // items per thread per side
-  static_assert(BK == kRowChunk, "chunk size");
-  extern __shared__ __align__(16) unsigned char sk_smem[];
-  Op* YA = reinterpret_cast<Op*>(sk_smem);
-  Op* YBs = reinterpret_cast<Op*>(sk_smem + L::y_bytes);
-  Src* OA = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes);
-  Src* OB = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes + L::o_bytes);
-  unsigned char* offs = sk_smem + 2 * L::y_bytes + 2 * L::o_bytes;  // [2][NO][kMaxOrder]
-  Src* rT = reinterpret_cast<Src*>(sk_smem + L::fixed);             // [sum_r + 1][RT]
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int N = g.order;
-  const int RL = g.ranks[g.last];
-  const int SR = g.sum_r;
-  const int sl = g.soff[g.last];
-  const int64_t d = g.d;
-  const int64_t w = blockIdx.x;
-  const int64_t u0 = sk_unit_start(sp, w), u1 = sk_unit_start(sp, w + 1);
-  if (u0 >= u1) return;
-  for (int e = tid; e < RT; e += kSkThreads) rT[SR * RT + e] = Src(0);  // zero row
-
-  constexpr int WR = T / 2, WC = T / 2, NBR = WR / V::MT, NBC = WC / V::MT;
-  const int wr = wave >> 1, wc = wave & 1;
-  Acc acc[NBR][NBC];
-
-  const int nval4 = BK * SR / 4;
-  f32x4 pf[PF4];
-  auto fetch = [&](int64_t c) {
-    const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
-#pragma unroll
-    for (int k = 0; k < PF4; ++k) {
-      const int e = tid + k * kSkThreads;
-      if (e < nval4) pf[k] = src[e];
-    }
-  };
-  auto commit = [&]() {
-#pragma unroll
-    for (int k = 0; k < PF4; ++k) {
-      const int e = tid + k * kSkThreads;
-      if (e < nval4) {
-        const int f = 4 * e;  // element index j * 32 + t
-        *reinterpret_cast<f32x4*>(&rT[(f >> 5) * RT + (f & 31)]) = pf[k];
-      }
-    }
-  };
-
-  int64_t u = u0;
-  int seg = 0;
-  while (u < u1) {
-    const int64_t tau = u / sp.nchunks;
-    const int64_t c_begin = u - tau * sp.nchunks;
-    const int64_t tile_end_unit = (tau + 1) * sp.nchunks;
-    const int64_t c_end = (u1 < tile_end_unit ? u1 : tile_end_unit) - tau * sp.nchunks;
-    int64_t ti, tj;
-    tri_index(tau, ti, tj);
-    const bool diag = (ti == tj);
-    const int64_t r0 = ti * T, c0 = tj * T;
-    int64_t ob[2];
-    int no[2];
-    for (int side = 0; side < 2; ++side) {
-      const int64_t base = side == 0 ? r0 : c0;
-      const int64_t last = ((base + T < d) ? base + T : d) - 1;
-      ob[side] = base / RL;
-      no[side] = static_cast<int>(last / RL - ob[side] + 1);
-    }
-    // this thread's formation items: LDS offsets into O and rT (zero row when
-    // the design row is past d)
-    int iofs_o[2][ITEMS], iofs_q[2][ITEMS];
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const int e = tid + k * kSkThreads;
-        const int i = e / IPR, tg = (e % IPR) * IW;
-        const int64_t r = (side == 0 ? r0 : c0) + i;
-        const int64_t rr = r < d ? r : d - 1;
-        iofs_o[side][k] = static_cast<int>(rr / RL - ob[side]) * BK + tg;
-        iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
-      }
-    __syncthreads();  // the previous tile's LDS use is complete
-#pragma unroll 1
-    for (int e = tid; e < 2 * NO; e += kSkThreads) {
-      const int side = e / NO, oi = e - side * NO;
-      outer_offsets(g, ob[side] + oi, offs + (side * NO + oi) * kMaxOrder);
-    }
-#pragma unroll
-    for (int a = 0; a < NBR; ++a)
-#pragma unroll
-      for (int b = 0; b < NBC; ++b)
-#pragma unroll
-        for (int v = 0; v < V::NACC; ++v) acc[a][b][v] = 0;
-
-    fetch(c_begin);
-    commit();
-    __syncthreads();
-    for (int64_t c = c_begin; c < c_end; ++c) {
-      const bool more = c + 1 < c_end;
-      if (more) fetch(c + 1);
-      // (b) outer products O[oi][t]
-      {
-        const int nsides = diag ? 1 : 2;
-#pragma unroll 1
-        for (int side = 0; side < nsides; ++side) {
-          Src* O = side == 0 ? OA : OB;
-          const unsigned char* so = offs + side * NO * kMaxOrder;
-#pragma unroll 1
-          for (int e = tid; e < no[side] * BK; e += kSkThreads) {
-            const int oi = e >> 5, t = e & 31;
-            const uint64_t pk = *reinterpret_cast<const uint64_t*>(so + oi * kMaxOrder);
-            Src v = Src(1);
-#pragma unroll
-            for (int k = 0; k < kMaxOrder - 1; ++k)
-              if (k < N - 1) v *= rT[static_cast<int>((pk >> (8 * k)) & 0xff) * RT + t];
-            O[e] = v;
-          }
-        }
-      }
-      __syncthreads();
-      // (c) Kronecker rows of both tiles
-      {
-        const int nsides = diag ? 1 : 2;
-#pragma unroll 1
-        for (int side = 0; side < nsides; ++side) {
-          const Src* O = side == 0 ? OA : OB;
-          Op* Y = side == 0 ? YA : YBs;
-#pragma unroll
-          for (int k = 0; k < ITEMS; ++k) {
-            const int e = tid + k * kSkThreads;
-            const int i = e / IPR, tg = (e % IPR) * IW;
-            const f32x4* op = reinterpret_cast<const f32x4*>(O + iofs_o[side][k]);
-            const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
-            if constexpr (V::EPL == 8) {
-              const f32x4 o0 = op[0], o1 = op[1], q0 = qp[0], q1 = qp[1];
-              bf16x8 v;
-              v[0] = V::cvt(o0.x * q0.x);
-              v[1] = V::cvt(o0.y * q0.y);
-              v[2] = V::cvt(o0.z * q0.z);
-              v[3] = V::cvt(o0.w * q0.w);
-              v[4] = V::cvt(o1.x * q1.x);
-              v[5] = V::cvt(o1.y * q1.y);
-              v[6] = V::cvt(o1.z * q1.z);
-              v[7] = V::cvt(o1.w * q1.w);
-              *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
-            } else {
-              const f32x4 o = op[0], q = qp[0];
-              Op* y = &Y[i * LDK + tg];
-              y[0] = V::cvt(o.x * q.x);
-              y[1] = V::cvt(o.y * q.y);
-              y[2] = V::cvt(o.z * q.z);
-              y[3] = V::cvt(o.w * q.w);
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // (d) MFMA; then stage the prefetched chunk
-      const Op* YB = diag ? YA : YBs;
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += V::KT) {
-        const int kofs = kk + (lane / V::MT) * V::EPL;
-#pragma unroll
-        for (int a = 0; a < NBR; ++a)
-#pragma unroll
-          for (int b = 0; b < NBC; ++b)
-            acc[a][b] = V::mma(&YA[(wr * WR + a * V::MT + lane % V::MT) * LDK + kofs],
-                               &YB[(wc * WC + b * V::MT + lane % V::MT) * LDK + kofs], acc[a][b]);
-      }
-      if (more) commit();
-      __syncthreads();
-    }
-    typename V::Out* out = slots + (w * sp.maxseg + seg) * static_cast<int64_t>(T * T);
-#pragma unroll
-    for (int a = 0; a < NBR; ++a)
-#pragma unroll
-      for (int b = 0; b < NBC; ++b)
-#pragma unroll
-        for (int v = 0; v < V::NACC; ++v) {
-          const int r = wr * WR + a * V::MT + V::acc_row(lane, v);
-          const int cc = wc * WC + b * V::MT + V::acc_col(lane, v);
-          out[r * T + cc] = static_cast<typename V::Out>(acc[a][b][v]);
-        }
-    ++seg;
-    u = tau * sp.nchunks + c_end;
-  }
-}
-
-// M[i][j] (i >= j) = sum of the tile's slots + lambda prod_n P_n[i_n][j_n]
-template <class In>
-__global__ __launch_bounds__(kBlock) void assemble_sk_kernel(Geom g, SkPlan sp,
-                                                             const In* __restrict__ slots,
-                                                             const double* __restrict__ P,
-                                                             double lambda,
-                                                             double* __restrict__ M) {
-  const int64_t d = g.d;
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t i = blockIdx.y;
-  if (j > i) return;
-  const int64_t ti = i / kSkT, tj = j / kSkT;
-  const int64_t tau = ti * (ti + 1) / 2 + tj;
-  const int64_t ua = tau * sp.nchunks, ub = ua + sp.nchunks;  // the tile's units [ua, ub)
-  int64_t w = (ua * sp.grid) / sp.units;
-  while (w > 0 && sk_unit_start(sp, w) > ua) --w;
-  while (sk_unit_start(sp, w + 1) <= ua) ++w;
-  const int64_t off = (i - ti * kSkT) * kSkT + (j - tj * kSkT);
-  double v = 0.0;
-  for (; w < sp.grid && sk_unit_start(sp, w) < ub; ++w) {
-    if (sk_unit_start(sp, w + 1) <= sk_unit_start(sp, w)) continue;  // empty range
-    const int64_t first_tile = sk_unit_start(sp, w) / sp.nchunks;
-    const int64_t k = tau - first_tile;
-    v += static_cast<double>(slots[(w * sp.maxseg + k) * static_cast<int64_t>(kSkT * kSkT) + off]);
-  }
-  double p = 1.0;
-  int64_t a = i, b = j;
-  for (int n = g.order - 1; n >= 0; --n) {
-    const int R = g.ranks[n];
-    p *= P[g.roff[n] + (a % R) * R + (b % R)];
-    a /= R;
-    b /= R;
-  }
-  M[i * d + j] = fma(lambda, p, v);
 }
 
 // ------------------------------------------------------------------ assemble (FP64 splits)
@@ -864,40 +524,21 @@ __global__ __launch_bounds__(kBlock) void dot_finish_kernel(const double* __rest
 }  // namespace
 
 // ------------------------------------------------------------------ host side
-static int device_cu_count() {
-  static int cached = 0;
-  if (cached == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        n > 0)
-      cached = n;
-    else
-      cached = 256;  // MI355X
-    (void)hipGetLastError();
-  }
-  return cached;
-}
-
 GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override) {
   GramPlan pl;
+  memset(&pl, 0, sizeof(pl));
   pl.prec = prec;
   pl.streamk = prec != TK_F64;
   pl.bk = kRowChunk;
   const int64_t nch = row_chunks(s);
   if (pl.streamk) {
-    pl.tile = kSkT;
-    SkPlan& sp = pl.sk;
-    sp.nt = cdiv(g.d, kSkT);
-    sp.ntiles = sp.nt * (sp.nt + 1) / 2;
-    sp.nchunks = nch;
-    sp.units = sp.ntiles * sp.nchunks;
-    int64_t G = ksplit_override > 0 ? ksplit_override : kSkWgPerCu * device_cu_count();
-    if (G > sp.units) G = sp.units;
-    if (G < 1) G = 1;
-    sp.grid = G;
-    sp.maxseg = cdiv(cdiv(sp.units, G), sp.nchunks) + 1;
-    pl.ntiles = sp.ntiles;
+    pl.sk.count = 1;
+    pl.sk.p[0] = sk_prob(g, s, nullptr);
+    SkConfig cfg{128, 3};
+    if (ksplit_override > 0) cfg.wg_per_cu = ksplit_override;
+    sk_finalize(pl.sk, prec, cfg);
+    pl.tile = cfg.tile;
+    pl.ntiles = pl.sk.tiles;
     pl.ksplit = 1;
     pl.chunk = nch * kRowChunk;
     return pl;
@@ -919,8 +560,7 @@ GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override)
 }
 
 size_t gram_partial_bytes(const Geom& g, const GramPlan& pl) {
-  if (pl.streamk)
-    return static_cast<size_t>(pl.sk.grid) * static_cast<size_t>(pl.sk.maxseg) * kSkT * kSkT * 4;
+  if (pl.streamk) return ((sk_slot_bytes(pl.sk) + 255) & ~size_t(255)) + sk_index_bytes(pl.sk);
   return static_cast<size_t>(pl.ksplit) * static_cast<size_t>(g.d) * static_cast<size_t>(g.d) * 8;
 }
 
@@ -938,39 +578,27 @@ void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const 
     dim3 grid(static_cast<unsigned>(pl.ntiles), static_cast<unsigned>(pl.ksplit));
     hipLaunchKernelGGL(gram_kernel<VarF64>, grid, dim3(kBlock), 0, st, g, rows64, weff, 0, s,
                        pl.chunk, static_cast<double*>(partials));
-  } else {
-    const bool small = sk_pf_slots(g.sum_r) == kSkPfSmall;
-    const dim3 grid(static_cast<unsigned>(pl.sk.grid)), block(kSkThreads);
-    float* out = static_cast<float*>(partials);
-    if (pl.prec == TK_F32) {
-      const size_t lds = SkLayout<VarF32>::bytes(g.sum_r);
-      if (small)
-        hipLaunchKernelGGL((gram_sk_kernel<VarF32, kSkPfSmall>), grid, block, lds, st, g, pl.sk,
-                           rows32, out);
-      else
-        hipLaunchKernelGGL((gram_sk_kernel<VarF32, kSkPfLarge>), grid, block, lds, st, g, pl.sk,
-                           rows32, out);
-    } else {
-      const size_t lds = SkLayout<VarBF16>::bytes(g.sum_r);
-      if (small)
-        hipLaunchKernelGGL((gram_sk_kernel<VarBF16, kSkPfSmall>), grid, block, lds, st, g, pl.sk,
-                           rows32, out);
-      else
-        hipLaunchKernelGGL((gram_sk_kernel<VarBF16, kSkPfLarge>), grid, block, lds, st, g, pl.sk,
-                           rows32, out);
-    }
+    return;
   }
+  SkBatch b = pl.sk;
+  b.p[0].rows = rows32;
+  char* base = static_cast<char*>(partials);
+  const size_t off = (sk_slot_bytes(b) + 255) & ~size_t(255);
+  launch_gram_sk(b, reinterpret_cast<float*>(base), reinterpret_cast<int64_t*>(base + off), st);
 }
 
 void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, const double* P,
                      double lambda, double* M, hipStream_t st) {
+  if (pl.streamk) {
+    const char* base = static_cast<const char*>(partials);
+    const size_t off = (sk_slot_bytes(pl.sk) + 255) & ~size_t(255);
+    launch_assemble_sk(pl.sk, 0, g, reinterpret_cast<const float*>(base),
+                       reinterpret_cast<const int64_t*>(base + off), P, lambda, M, st);
+    return;
+  }
   dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
-  if (pl.streamk)
-    hipLaunchKernelGGL(assemble_sk_kernel<float>, grid, dim3(kBlock), 0, st, g, pl.sk,
-                       static_cast<const float*>(partials), P, lambda, M);
-  else
-    hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(kBlock), 0, st, g,
-                       static_cast<const double*>(partials), pl.ksplit, P, lambda, M);
+  hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(kBlock), 0, st, g,
+                     static_cast<const double*>(partials), pl.ksplit, P, lambda, M);
 }
 
 void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,

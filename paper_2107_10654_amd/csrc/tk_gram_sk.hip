@@ -1,0 +1,487 @@
+// Stream-K sketched Gram on MFMA (FP32 or BF16 operands, FP32 accumulation)
+// for one problem or a batch of problems in one persistent launch.
+//
+// The Gram of a problem is sum_t w_t q_t q_t^T over its samples (proof of
+// Thm 4.2: s outer products of design rows), with q_t the whitened Kronecker
+// row of sample t.  Its lower triangle is cut into T x T output tiles.  A
+// unit of work is (tile, chunk of 32 samples); the units of all problems of
+// a launch are laid out problem by problem, tile by tile, and workgroup w of
+// G walks units [w U / G, (w + 1) U / G).  Where that range crosses a tile
+// (or problem) boundary the workgroup writes the finished partial tile to its
+// next slot; an index kernel gives every workgroup its first slot and first
+// tile, and the assembly kernel sums a tile's slots in workgroup order
+// (deterministic for a fixed grid).
+//
+// Per chunk a workgroup (4 waves, 2 x 2 over the tile) stages the chunk's
+// factor rows in LDS (prefetched in registers while the previous chunk's
+// MFMAs run), forms the outer-mode products O[o][t] (all modes but the last
+// mode L of rank >= 2), forms the two Kronecker row tiles
+// y[r][t] = O[r / R_L][t] q_L[r % R_L][t] in the operand precision, and runs
+// the 32 x 32 MFMAs.  Up to three (T = 128) or four (T = 64) workgroups share
+// a CU, so some form rows while others run MFMA.
+#include <string.h>
+
+#include "tk_mfma.h"
+
+namespace tk {
+namespace {
+
+constexpr int kSkThreads = 256;
+constexpr int kSkRT = kRowChunk + 4;  // padded LDS row: conflict-free 16-byte reads
+
+template <int T>
+struct SkTile {
+  static constexpr int NO = T / 2 + 1;  // outer indices per tile when R_L >= 2
+  static constexpr int WG_PER_CU = T == 128 ? 3 : 4;
+};
+
+template <class V, int T>
+struct SkLayout {
+  static constexpr int BK = V::BK;
+  static constexpr int NO = SkTile<T>::NO;
+  static constexpr size_t y_bytes = sizeof(typename V::Op) * T * V::LDK;   // one side
+  static constexpr size_t o_bytes = sizeof(typename V::Src) * NO * BK;     // one side
+  static constexpr size_t offs_bytes = 2 * NO * kMaxOrder;
+  static constexpr size_t fixed = 2 * y_bytes + 2 * o_bytes + offs_bytes;
+  // rows: sum_r rows plus one zero row
+  __host__ __device__ static size_t bytes(int sum_r) {
+    return fixed + sizeof(typename V::Src) * static_cast<size_t>(sum_r + 1) * kSkRT;
+  }
+};
+
+// prefetch registers (16-byte) per thread: a chunk holds kRowChunk * sum_r values
+constexpr int kSkPfSmall = 2;  // sum_r <= 64
+constexpr int kSkPfLarge = (kRowChunk * kMaxSumR / 4 + kSkThreads - 1) / kSkThreads;
+__host__ __device__ constexpr int sk_pf_slots(int sum_r) {
+  return kRowChunk * sum_r <= 4 * kSkThreads * kSkPfSmall ? kSkPfSmall : kSkPfLarge;
+}
+
+__host__ __device__ inline int64_t sk_unit_start(int64_t w, int64_t units, int64_t grid) {
+  return (w * units) / grid;
+}
+
+__device__ inline int sk_problem_of(const SkBatch& b, int64_t u) {
+  int p = 0;
+  while (p + 1 < b.count && b.p[p + 1].unit0 <= u) ++p;
+  return p;
+}
+
+__device__ inline int64_t sk_tile_of(const SkBatch& b, int64_t u) {
+  const int p = sk_problem_of(b, u);
+  return b.p[p].tile0 + (u - b.p[p].unit0) / row_chunks(b.p[p].s);
+}
+
+// Geometry of one problem, derived from its descriptor.
+struct SkGeom {
+  int order, last, sum_r, rl, sl;
+  int64_t d, nchunks;
+  int ranks[kMaxOrder], soff[kMaxOrder];
+};
+
+__device__ inline SkGeom sk_geom(const SkProb& q) {
+  SkGeom g;
+  g.order = q.order;
+  g.last = q.last;
+  g.sum_r = q.sum_r;
+  g.d = 1;
+  int so = 0;
+#pragma unroll
+  for (int n = 0; n < kMaxOrder; ++n) {
+    const int r = n < q.order ? q.ranks[n] : 1;
+    g.ranks[n] = r;
+    g.soff[n] = so;
+    so += n < q.order ? r : 0;
+    g.d *= r;
+  }
+  g.rl = g.ranks[g.last];
+  g.sl = g.soff[g.last];
+  g.nchunks = row_chunks(q.s);
+  return g;
+}
+
+// LDS row positions of the outer factors of outer index o: for the modes
+// before L, soff_n + digit_n(o); modes after L have rank 1 (digit 0).
+__device__ inline void sk_outer_offsets(const SkGeom& g, int64_t o, unsigned char* offs) {
+  unsigned char tmp[kMaxOrder];
+  int64_t rem = o;
+  for (int n = g.last - 1; n >= 0; --n) {
+    tmp[n] = static_cast<unsigned char>(g.soff[n] + rem % g.ranks[n]);
+    rem /= g.ranks[n];
+  }
+  int k = 0;
+  for (int n = 0; n < g.last; ++n) offs[k++] = tmp[n];
+  for (int n = g.last + 1; n < g.order; ++n) offs[k++] = static_cast<unsigned char>(g.soff[n]);
+  for (; k < kMaxOrder; ++k) offs[k] = 0;
+}
+
+// index[w] = first slot of workgroup w, index[G + w] = its first tile (-1: empty range)
+__global__ __launch_bounds__(1024) void sk_index_kernel(SkBatch b, int64_t* __restrict__ index) {
+  __shared__ int64_t part[1024];
+  const int64_t G = b.grid;
+  int64_t carry = 0;
+  for (int64_t w0 = 0; w0 < G; w0 += 1024) {
+    const int64_t w = w0 + threadIdx.x;
+    int64_t segs = 0, first = -1;
+    if (w < G) {
+      const int64_t u0 = sk_unit_start(w, b.units, G), u1 = sk_unit_start(w + 1, b.units, G);
+      if (u1 > u0) {
+        first = sk_tile_of(b, u0);
+        segs = sk_tile_of(b, u1 - 1) - first + 1;
+      }
+      index[G + w] = first;
+    }
+    part[threadIdx.x] = segs;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+      const int64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (w < G) index[w] = carry + part[threadIdx.x] - segs;
+    carry += part[1023];
+    __syncthreads();
+  }
+}
+
+template <class V, int T, int PF4>
+__global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kernel(
+    SkBatch b, typename V::Out* __restrict__ slots, const int64_t* __restrict__ index) {
+  using Src = typename V::Src;
+  using Op = typename V::Op;
+  using Acc = typename V::Acc;
+  using L = SkLayout<V, T>;
+  constexpr int BK = V::BK, LDK = V::LDK, RT = kSkRT, NO = L::NO;
+  constexpr int IW = V::EPL == 8 ? 8 : 4;         // samples per formation item
+  constexpr int IPR = BK / IW;                    // items per row
+  constexpr int ITEMS = T * IPR / kSkThreads;     // items per thread per side
+  static_assert(BK == kRowChunk, "chunk size");
+  static_assert(ITEMS >= 1, "tile too small for the workgroup");
+  extern __shared__ __align__(16) unsigned char sk_smem[];
+  Op* YA = reinterpret_cast<Op*>(sk_smem);
+  Op* YBs = reinterpret_cast<Op*>(sk_smem + L::y_bytes);
+  Src* OA = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes);
+  Src* OB = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes + L::o_bytes);
+  unsigned char* offs = sk_smem + 2 * L::y_bytes + 2 * L::o_bytes;  // [2][NO][kMaxOrder]
+  Src* rT = reinterpret_cast<Src*>(sk_smem + L::fixed);             // [sum_r + 1][RT]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t w = blockIdx.x;
+  const int64_t u0 = sk_unit_start(w, b.units, b.grid), u1 = sk_unit_start(w + 1, b.units, b.grid);
+  if (u0 >= u1) return;
+  const int64_t slot0 = index[w];
+
+  constexpr int WR = T / 2, WC = T / 2, NBR = WR / V::MT, NBC = WC / V::MT;
+  const int wr = wave >> 1, wc = wave & 1;
+  Acc acc[NBR][NBC];
+
+  f32x4 pf[PF4];
+  int64_t u = u0;
+  int seg = 0;
+  while (u < u1) {
+    const int pi = sk_problem_of(b, u);
+    const SkProb& pd = b.p[pi];
+    const SkGeom g = sk_geom(pd);
+    const int N = g.order, RL = g.rl, SR = g.sum_r, sl = g.sl;
+    const int64_t d = g.d;
+    const Src* rows = pd.rows;
+    const int nval4 = BK * SR / 4;
+    const int64_t lu = u - pd.unit0;  // unit within the problem
+    const int64_t tau = lu / g.nchunks;
+    const int64_t c_begin = lu - tau * g.nchunks;
+    const int64_t tile_end = pd.unit0 + (tau + 1) * g.nchunks;
+    const int64_t c_end = (u1 < tile_end ? u1 : tile_end) - pd.unit0 - tau * g.nchunks;
+    int64_t ti, tj;
+    tri_index(tau, ti, tj);
+    const bool diag = (ti == tj);
+    const int64_t r0 = ti * T, c0 = tj * T;
+    int64_t ob[2];
+    int no[2];
+    for (int side = 0; side < 2; ++side) {
+      const int64_t base = side == 0 ? r0 : c0;
+      const int64_t last = ((base + T < d) ? base + T : d) - 1;
+      ob[side] = base / RL;
+      no[side] = static_cast<int>(last / RL - ob[side] + 1);
+    }
+    // this thread's formation items: LDS offsets into O and rT (zero row when
+    // the design row is past d)
+    int iofs_o[2][ITEMS], iofs_q[2][ITEMS];
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const int e = tid + k * kSkThreads;
+        const int i = e / IPR, tg = (e % IPR) * IW;
+        const int64_t r = (side == 0 ? r0 : c0) + i;
+        const int64_t rr = r < d ? r : d - 1;
+        iofs_o[side][k] = static_cast<int>(rr / RL - ob[side]) * BK + tg;
+        iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
+      }
+    auto fetch = [&](int64_t c) {
+      const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
+#pragma unroll
+      for (int k = 0; k < PF4; ++k) {
+        const int e = tid + k * kSkThreads;
+        if (e < nval4) pf[k] = src[e];
+      }
+    };
+    auto commit = [&]() {
+#pragma unroll
+      for (int k = 0; k < PF4; ++k) {
+        const int e = tid + k * kSkThreads;
+        if (e < nval4) {
+          const int f = 4 * e;  // element index j * 32 + t
+          *reinterpret_cast<f32x4*>(&rT[(f >> 5) * RT + (f & 31)]) = pf[k];
+        }
+      }
+    };
+    __syncthreads();  // the previous segment's LDS use is complete
+    for (int e = tid; e < RT; e += kSkThreads) rT[SR * RT + e] = Src(0);  // zero row
+#pragma unroll 1
+    for (int e = tid; e < 2 * NO; e += kSkThreads) {
+      const int side = e / NO, oi = e - side * NO;
+      sk_outer_offsets(g, ob[side] + oi, offs + (side * NO + oi) * kMaxOrder);
+    }
+#pragma unroll
+    for (int a = 0; a < NBR; ++a)
+#pragma unroll
+      for (int bb = 0; bb < NBC; ++bb)
+#pragma unroll
+        for (int v = 0; v < V::NACC; ++v) acc[a][bb][v] = 0;
+
+    fetch(c_begin);
+    commit();
+    __syncthreads();
+    for (int64_t c = c_begin; c < c_end; ++c) {
+      const bool more = c + 1 < c_end;
+      if (more) fetch(c + 1);
+      // (b) outer products O[oi][t]
+      {
+        const int nsides = diag ? 1 : 2;
+#pragma unroll 1
+        for (int side = 0; side < nsides; ++side) {
+          Src* O = side == 0 ? OA : OB;
+          const unsigned char* so = offs + side * NO * kMaxOrder;
+#pragma unroll 1
+          for (int e = tid; e < no[side] * BK; e += kSkThreads) {
+            const int oi = e >> 5, t = e & 31;
+            const uint64_t pk = *reinterpret_cast<const uint64_t*>(so + oi * kMaxOrder);
+            Src v = Src(1);
+#pragma unroll
+            for (int k = 0; k < kMaxOrder - 1; ++k)
+              if (k < N - 1) v *= rT[static_cast<int>((pk >> (8 * k)) & 0xff) * RT + t];
+            O[e] = v;
+          }
+        }
+      }
+      __syncthreads();
+      // (c) Kronecker rows of both tiles
+      {
+        const int nsides = diag ? 1 : 2;
+#pragma unroll 1
+        for (int side = 0; side < nsides; ++side) {
+          const Src* O = side == 0 ? OA : OB;
+          Op* Y = side == 0 ? YA : YBs;
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            const int e = tid + k * kSkThreads;
+            const int i = e / IPR, tg = (e % IPR) * IW;
+            const f32x4* op = reinterpret_cast<const f32x4*>(O + iofs_o[side][k]);
+            const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
+            if constexpr (V::EPL == 8) {
+              const f32x4 o0 = op[0], o1 = op[1], q0 = qp[0], q1 = qp[1];
+              bf16x8 v;
+              v[0] = V::cvt(o0.x * q0.x);
+              v[1] = V::cvt(o0.y * q0.y);
+              v[2] = V::cvt(o0.z * q0.z);
+              v[3] = V::cvt(o0.w * q0.w);
+              v[4] = V::cvt(o1.x * q1.x);
+              v[5] = V::cvt(o1.y * q1.y);
+              v[6] = V::cvt(o1.z * q1.z);
+              v[7] = V::cvt(o1.w * q1.w);
+              *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
+            } else {
+              const f32x4 o = op[0], q = qp[0];
+              Op* y = &Y[i * LDK + tg];
+              y[0] = V::cvt(o.x * q.x);
+              y[1] = V::cvt(o.y * q.y);
+              y[2] = V::cvt(o.z * q.z);
+              y[3] = V::cvt(o.w * q.w);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // (d) MFMA; then stage the prefetched chunk
+      const Op* YB = diag ? YA : YBs;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += V::KT) {
+        const int kofs = kk + (lane / V::MT) * V::EPL;
+#pragma unroll
+        for (int a = 0; a < NBR; ++a)
+#pragma unroll
+          for (int bb = 0; bb < NBC; ++bb)
+            acc[a][bb] = V::mma(&YA[(wr * WR + a * V::MT + lane % V::MT) * LDK + kofs],
+                                &YB[(wc * WC + bb * V::MT + lane % V::MT) * LDK + kofs],
+                                acc[a][bb]);
+      }
+      if (more) commit();
+      __syncthreads();
+    }
+    typename V::Out* out = slots + (slot0 + seg) * static_cast<int64_t>(T * T);
+#pragma unroll
+    for (int a = 0; a < NBR; ++a)
+#pragma unroll
+      for (int bb = 0; bb < NBC; ++bb)
+#pragma unroll
+        for (int v = 0; v < V::NACC; ++v) {
+          const int r = wr * WR + a * V::MT + V::acc_row(lane, v);
+          const int cc = wc * WC + bb * V::MT + V::acc_col(lane, v);
+          out[r * T + cc] = static_cast<typename V::Out>(acc[a][bb][v]);
+        }
+    ++seg;
+    u = pd.unit0 + tau * g.nchunks + c_end;
+  }
+}
+
+// M[i][j] (i >= j) = sum of the tile's slots + lambda prod_n P_n[i_n][j_n]
+template <int T>
+__global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
+    Geom g, int64_t units, int64_t grid, int64_t unit0, int64_t tile0, int64_t nchunks,
+    const float* __restrict__ slots, const int64_t* __restrict__ index,
+    const double* __restrict__ P, double lambda, double* __restrict__ M) {
+  const int64_t d = g.d;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j > i) return;
+  const int64_t ti = i / T, tj = j / T;
+  const int64_t tau = ti * (ti + 1) / 2 + tj;
+  const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;  // the tile's units [ua, ub)
+  int64_t w = (ua * grid) / units;
+  while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
+  while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
+  const int64_t off = (i - ti * T) * T + (j - tj * T);
+  double v = 0.0;
+  for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
+    const int64_t first = index[grid + w];
+    if (first < 0) continue;  // empty range
+    const int64_t slot = index[w] + (tile0 + tau - first);
+    v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
+  }
+  double p = 1.0;
+  int64_t a = i, b = j;
+  for (int n = g.order - 1; n >= 0; --n) {
+    const int R = g.ranks[n];
+    p *= P[g.roff[n] + (a % R) * R + (b % R)];
+    a /= R;
+    b /= R;
+  }
+  M[i * d + j] = fma(lambda, p, v);
+}
+
+template <class V, int T>
+void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(b.grid)), block(kSkThreads);
+  const size_t lds = SkLayout<V, T>::bytes(b.max_sum_r);
+  if (sk_pf_slots(b.max_sum_r) == kSkPfSmall)
+    hipLaunchKernelGGL((gram_sk_kernel<V, T, kSkPfSmall>), grid, block, lds, st, b, slots, index);
+  else
+    hipLaunchKernelGGL((gram_sk_kernel<V, T, kSkPfLarge>), grid, block, lds, st, b, slots, index);
+}
+
+int device_cu_count() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        n > 0)
+      cached = n;
+    else
+      cached = 256;  // MI355X
+    (void)hipGetLastError();
+  }
+  return cached;
+}
+
+}  // namespace
+
+bool sk_config_valid(const SkConfig& c) {
+  return (c.tile == 64 || c.tile == 128) && c.wg_per_cu >= 1 && c.wg_per_cu <= 8;
+}
+
+SkProb sk_prob(const Geom& g, int64_t s, const float* rows32) {
+  SkProb q;
+  memset(&q, 0, sizeof(q));
+  q.rows = rows32;
+  q.s = static_cast<int32_t>(s);
+  q.order = static_cast<uint8_t>(g.order);
+  q.last = static_cast<uint8_t>(g.last);
+  q.sum_r = static_cast<uint8_t>(g.sum_r);
+  for (int n = 0; n < g.order; ++n) q.ranks[n] = static_cast<uint8_t>(g.ranks[n]);
+  return q;
+}
+
+void sk_finalize(SkBatch& b, tk_dtype prec, const SkConfig& cfg) {
+  b.tile = cfg.tile;
+  b.prec = prec;
+  int64_t units = 0, tiles = 0;
+  int msr = 1;
+  for (int k = 0; k < b.count; ++k) {
+    SkProb& q = b.p[k];
+    int64_t d = 1;
+    for (int n = 0; n < q.order; ++n) d *= q.ranks[n];
+    const int64_t nt = cdiv(d, cfg.tile);
+    const int64_t nti = nt * (nt + 1) / 2;
+    q.unit0 = units;
+    q.tile0 = tiles;
+    units += nti * row_chunks(q.s);
+    tiles += nti;
+    if (q.sum_r > msr) msr = q.sum_r;
+  }
+  b.units = units;
+  b.tiles = tiles;
+  b.max_sum_r = msr;
+  int64_t G = static_cast<int64_t>(cfg.wg_per_cu) * device_cu_count();
+  if (G > units) G = units;
+  if (G < 1) G = 1;
+  b.grid = G;
+}
+
+size_t sk_slot_bytes(const SkBatch& b) {
+  // every workgroup writes one slot per tile its range touches: at most
+  // grid + tiles slots in all
+  return static_cast<size_t>(b.grid + b.tiles) * b.tile * b.tile * sizeof(float);
+}
+
+size_t sk_index_bytes(const SkBatch& b) { return static_cast<size_t>(2 * b.grid) * 8; }
+
+void launch_gram_sk(const SkBatch& b, float* slots, int64_t* index, hipStream_t st) {
+  if (b.count < 1 || b.units < 1) return;
+  hipLaunchKernelGGL(sk_index_kernel, dim3(1), dim3(1024), 0, st, b, index);
+  const bool bf = b.prec == TK_BF16;
+  if (b.tile == 128) {
+    if (bf) gram_sk_launch<VarBF16, 128>(b, slots, index, st);
+    else gram_sk_launch<VarF32, 128>(b, slots, index, st);
+  } else {
+    if (bf) gram_sk_launch<VarBF16, 64>(b, slots, index, st);
+    else gram_sk_launch<VarF32, 64>(b, slots, index, st);
+  }
+}
+
+void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slots,
+                        const int64_t* index, const double* P, double lambda, double* M,
+                        hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
+  const SkProb& q = b.p[k];
+  const int64_t nch = row_chunks(q.s);
+  if (b.tile == 128)
+    hipLaunchKernelGGL(assemble_sk_kernel<128>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
+                       q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+  else
+    hipLaunchKernelGGL(assemble_sk_kernel<64>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
+                       q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+}
+
+}  // namespace tk

@@ -84,18 +84,54 @@ void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* ma
 // Sketched Gram of whitened rows (tk_gram.hip).  FP64: partial Grams per
 // sample split (64 x 64 tiles).  FP32 / BF16: stream-K over 256 x 256 tiles
 // with partial tiles in per-workgroup slots.
-struct SkPlan {
-  int64_t nt, ntiles, nchunks, units, grid, maxseg;
+// Stream-K Gram (tk_gram_sk.hip).  One launch computes the sketched Grams of
+// up to kSkMaxBatch problems: the (lower-triangular tile, 32-sample chunk)
+// units of all problems are laid out problem by problem and tile by tile, and
+// workgroup w of `grid` walks units [w U / grid, (w + 1) U / grid).
+constexpr int kSkMaxBatch = 64;
+struct SkProb {
+  const float* rows;  // chunk-transposed f32 sample rows, sqrt(weight) folded into mode 0
+  int64_t unit0;      // first unit of the problem in the launch
+  int64_t tile0;      // first tile of the problem (tile numbering over the launch)
+  int32_t s;          // samples
+  uint8_t order, last, sum_r, pad;
+  uint8_t ranks[kMaxOrder];
 };
+struct SkBatch {
+  int32_t count;
+  int32_t tile;       // output tile edge T: 64 or 128
+  int32_t prec;       // TK_F32 or TK_BF16
+  int32_t max_sum_r;
+  int64_t units, grid, tiles;
+  SkProb p[kSkMaxBatch];
+};
+// The knobs of a stream-K launch chosen by the batched call's tuner.
+struct SkConfig {
+  int32_t tile;       // 64 or 128
+  int32_t wg_per_cu;  // workgroups per compute unit of the persistent grid
+};
+SkProb sk_prob(const Geom& g, int64_t s, const float* rows32);
+// Fills unit0 / tile0 of every problem and the launch totals from cfg.
+void sk_finalize(SkBatch& b, tk_dtype prec, const SkConfig& cfg);
+size_t sk_slot_bytes(const SkBatch& b);   // partial tiles
+size_t sk_index_bytes(const SkBatch& b);  // per-workgroup slot bases and first tiles
+// Index kernel plus the persistent Gram kernel.
+void launch_gram_sk(const SkBatch& b, float* slots, int64_t* index, hipStream_t st);
+// M (d x d lower triangle, FP64) = sum of problem k's partial tiles + lambda P.
+void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slots,
+                        const int64_t* index, const double* P, double lambda, double* M,
+                        hipStream_t st);
+bool sk_config_valid(const SkConfig& c);
+
 struct GramPlan {
   tk_dtype prec;
   bool streamk;
-  SkPlan sk;
-  int tile;        // output tile edge
+  SkBatch sk;      // FP32 / BF16: a stream-K batch of one
+  int tile;        // FP64: output tile edge
   int bk;          // samples per LDS chunk
-  int ksplit;      // sample splits (partials)
-  int64_t chunk;   // samples per split
-  int64_t ntiles;  // lower-triangular tiles
+  int ksplit;      // FP64: sample splits (partials)
+  int64_t chunk;   // FP64: samples per split
+  int64_t ntiles;  // FP64: lower-triangular tiles
 };
 GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override);
 size_t gram_partial_bytes(const Geom& g, const GramPlan& pl);

@@ -326,3 +326,137 @@ def als(X, G0, factors0, lam, iters, core="exact", samples=None, seed=0, precisi
         if record is not None:
             record.append(("core", it, -1, (Lv, sq, cnt)))
     return G, F, hist
+
+
+# ---------------------------------------------------------------- batches
+def _batch(Xs, factors_list, lams, samples, seeds, counters, problems, precision, refine_max,
+           refine_tol, masks):
+    count = len(Xs)
+    if not 1 <= count <= L.MAX_BATCH:
+        raise ValueError(f"batch of 1..{L.MAX_BATCH} problems")
+
+    def per(v, default):
+        if v is None:
+            return [default] * count
+        return list(v) if isinstance(v, (list, tuple)) else [v] * count
+
+    lams, samples = per(lams, 0.0), per(samples, None)
+    seeds, counters = per(seeds, 0), per(counters, 0)
+    problems = per(problems, None)
+    masks = per(masks, None)
+    P = (L.TkProblem * count)()
+    O = (L.TkSketchOpts * count)()
+    for k in range(count):
+        P[k] = make_problem(Xs[k], factors_list[k], lams[k], masks[k])
+        O[k] = _opts(samples[k], seeds[k], counters[k], k if problems[k] is None else problems[k],
+                     precision, refine_max, refine_tol)
+    return P, O
+
+
+def _config(config):
+    if config is None:
+        return None
+    c = L.TkBatchConfig()
+    c.tile, c.wg_per_cu = int(config["tile"]), int(config["wg_per_cu"])
+    return c
+
+
+def tune_batched(Xs, factors_list, lams, samples, seeds=None, counters=None, problems=None,
+                 precision="bf16", masks=None):
+    """Time every candidate Gram configuration of the batched call; returns (best, times_ms)."""
+    lib = L.load()
+    P, O = _batch(Xs, factors_list, lams, samples, seeds, counters, problems, precision, 0, 0.0,
+                  masks)
+    count = len(Xs)
+    nb = lib.tucker_workspace_bytes_batched(P, O, count, None)
+    if nb == 0:
+        raise ValueError("unsupported batch")
+    dev = Xs[0].device
+    ws = _workspace(nb, dev)
+    best = L.TkBatchConfig()
+    times = (ctypes.c_double * 16)()
+    n = ctypes.c_int32(0)
+    _raise_if(lib.tucker_tune_batched(P, O, count, _ptr(ws), ws.numel(), _stream(),
+                                      ctypes.byref(best), times, ctypes.byref(n)), "tune_batched")
+    return {"tile": best.tile, "wg_per_cu": best.wg_per_cu}, list(times[:n.value])
+
+
+def core_update_sketched_batched(Xs, factors_list, lams, samples, seeds=None, counters=None,
+                                 problems=None, precision="bf16", config=None, refine_max=12,
+                                 refine_tol=1e-13, masks=None, out=None, return_info=False,
+                                 check=True, workspace=None, status=None):
+    """Sampled core updates of a batch of problems with one persistent Gram launch.
+
+    problems[k] (default k) is the sampler's problem field of problem k, so
+    problem k draws the samples of core_update_sketched(..., problem=k).
+    Returns the list of cores (and the (count, INFO_LEN) info tensor).
+    """
+    lib = L.load()
+    P, O = _batch(Xs, factors_list, lams, samples, seeds, counters, problems, precision,
+                  refine_max, refine_tol, masks)
+    count = len(Xs)
+    cfg = _config(config)
+    dev = Xs[0].device
+    cores = out if out is not None else [
+        torch.empty([A.shape[1] for A in F], dtype=X.dtype, device=dev)
+        for X, F in zip(Xs, factors_list)]
+    ptrs = (ctypes.c_void_p * count)(*[c.data_ptr() for c in cores])
+    st = status if status is not None else torch.zeros(count, dtype=torch.int32, device=dev)
+    info = torch.empty((count, L.INFO_LEN), dtype=torch.float64, device=dev) if return_info \
+        else None
+    nb = lib.tucker_workspace_bytes_batched(P, O, count, ctypes.byref(cfg) if cfg else None)
+    if nb == 0:
+        raise ValueError("unsupported batch")
+    ws = workspace if workspace is not None else _workspace(nb, dev)
+    if ws.numel() < nb:
+        raise ValueError(f"workspace needs {nb} bytes")
+    _raise_if(lib.tucker_core_update_sketched_batched(
+        P, O, count, ctypes.byref(cfg) if cfg else None, ptrs, _ptr(st), _ptr(info), _ptr(ws),
+        ws.numel(), _stream()), "core_update_sketched_batched")
+    if check:
+        torch.cuda.current_stream(dev).synchronize()
+        bad = st.cpu().tolist()
+        for k, code in enumerate(bad):
+            _raise_if(code, f"core_update_sketched_batched[{k}]")
+    if return_info:
+        return cores, info
+    return cores
+
+
+class BatchedSketchedUpdate:
+    """A batched sampled update captured once in a CUDA (HIP) graph.
+
+    The inputs are read at every replay (their contents may change between
+    replays; shapes and addresses may not); the sampler's seed, counter and
+    problem fields are fixed at capture.  replay() returns the list of cores.
+    """
+
+    def __init__(self, Xs, factors_list, lams, samples, seeds=None, counters=None, problems=None,
+                 precision="bf16", config=None, refine_max=12, refine_tol=1e-13, masks=None):
+        lib = L.load()
+        self._args = (Xs, factors_list, lams, samples, seeds, counters, problems, precision)
+        P, O = _batch(Xs, factors_list, lams, samples, seeds, counters, problems, precision,
+                      refine_max, refine_tol, masks)
+        cfg = _config(config)
+        dev = Xs[0].device
+        nb = lib.tucker_workspace_bytes_batched(P, O, len(Xs), ctypes.byref(cfg) if cfg else None)
+        if nb == 0:
+            raise ValueError("unsupported batch")
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.status = torch.zeros(len(Xs), dtype=torch.int32, device=dev)
+        self.info = torch.empty((len(Xs), L.INFO_LEN), dtype=torch.float64, device=dev)
+        self.cores = [torch.empty([A.shape[1] for A in F], dtype=X.dtype, device=dev)
+                      for X, F in zip(Xs, factors_list)]
+        kw = dict(seeds=seeds, counters=counters, problems=problems, precision=precision,
+                  config=config, refine_max=refine_max, refine_tol=refine_tol, masks=masks,
+                  out=self.cores, workspace=self.workspace, status=self.status)
+        # eager run first (checks the status words), then capture
+        core_update_sketched_batched(Xs, factors_list, lams, samples, check=True, **kw)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            core_update_sketched_batched(Xs, factors_list, lams, samples, check=False, **kw)
+
+    def replay(self):
+        self.graph.replay()
+        return self.cores

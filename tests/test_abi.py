@@ -142,6 +142,32 @@ def test_host_argument_errors(lib):
     assert lib.tucker_sample(3, dims, core, 0, 0, 0, 0, core, core, st) == 1
 
 
+def test_batched_host_checks(lib):
+    n = 3
+    P = (L.TkProblem * n)(*[_problem((40 + k, 30, 20), (4, 3, 2)) for k in range(n)])
+    O = (L.TkSketchOpts * n)(*[_opts(500) for _ in range(n)])
+    nb = lib.tucker_workspace_bytes_batched(P, O, n, None)
+    cfg = L.TkBatchConfig(64, 4)
+    nb64 = lib.tucker_workspace_bytes_batched(P, O, n, ctypes.byref(cfg))
+    assert nb >= nb64 > 0
+    assert lib.tucker_workspace_bytes_batched(P, O, 0, None) == 0
+    bad = L.TkBatchConfig(96, 3)
+    assert lib.tucker_workspace_bytes_batched(P, O, n, ctypes.byref(bad)) == 0
+    ws = ctypes.create_string_buffer(16)
+    outs = (ctypes.c_void_p * n)(0x10, 0x10, 0x10)
+    st = ctypes.c_void_p(0x10)
+    f = lib.tucker_core_update_sketched_batched
+    assert f(P, O, n, None, outs, st, None, ws, 16, None) == 4  # workspace too small
+    assert f(P, O, 0, None, outs, st, None, ws, 16, None) == 1
+    assert f(P, O, n, ctypes.byref(bad), outs, st, None, ws, nb, None) == 1
+    O64 = (L.TkSketchOpts * n)(*[_opts(500, prec=L.TK_F64) for _ in range(n)])
+    assert f(P, O64, n, None, outs, st, None, ws, 16, None) == 3  # batches use FP32 / BF16 Grams
+    mixed = (L.TkSketchOpts * n)(_opts(500), _opts(500, prec=L.TK_F32), _opts(500))
+    assert f(P, mixed, n, None, outs, st, None, ws, 16, None) == 3
+    best = L.TkBatchConfig()
+    assert lib.tucker_tune_batched(P, O, n, ws, 16, None, ctypes.byref(best), None, None) == 4
+
+
 def test_status_strings(lib):
     for code, name in L.STATUS_NAMES.items():
         assert lib.tucker_status_string(code)
