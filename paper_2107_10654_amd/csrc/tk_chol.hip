@@ -7,7 +7,7 @@
 // block column: factor the diagonal tile (and invert it), solve the tiles
 // below it with the inverse, update the trailing lower triangle on FP64
 // MFMA.  The triangular solves use one launch each: workgroups take block
-// rows in ticket order and wait (bounded spin) for the rows they depend on.
+// rows in ticket order and wait (bounded spin) for the values they depend on.
 #include "tk_internal.h"
 
 namespace tk {
@@ -20,10 +20,34 @@ constexpr int LDA = NB + 1;
 // ---- diagonal tile: L_kk and its inverse
 // Blocked over four 16-column panels.  Wave 0 factors (and inverts) each
 // 16 x 16 diagonal panel in registers, lane r owning row r, with lane
-// shuffles in place of barriers; the workgroup then solves the rows below the
-// panel and updates the trailing triangle.  The 64 x 64 inverse is assembled
-// from the four 16 x 16 inverses block row by block row.
+// broadcasts (readlane) in place of barriers; the workgroup then solves the
+// rows below the panel and updates the trailing triangle.  The 64 x 64
+// inverse is assembled from the four 16 x 16 inverses block row by block row.
 constexpr int PB = 16;
+
+// value of v in lane l (l wave-uniform): v_readlane into a scalar register,
+// a few cycles instead of an LDS round trip of a cross-lane shuffle
+__device__ inline double lane_value(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+// 1 / sqrt(x) for x > 0 to FP64 accuracy: the hardware estimate refined by
+// two Newton steps (each doubles the correct bits), in place of a square root
+// followed by IEEE divisions on the factorisation's serial chain
+__device__ inline double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
                                                            int64_t k,
                                                            double* __restrict__ Linv_diag,
@@ -38,11 +62,23 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
   const int tx = tid & 15, ty = tid >> 4;
   const int64_t o = k * NB;
   const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
-  for (int i = ty; i < NB; i += 16)
-    for (int j = tx; j < NB; j += 16) {
-      A[i * LDA + j] = (i < b && j <= i) ? M[(o + i) * d + o + j] : (i == j ? 1.0 : 0.0);
+  {
+    // unconditional loads from clamped (in-bounds) addresses, so they issue
+    // back to back; the selects run after all of them
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
+      const int ic = i < b ? i : b - 1, jc = j < b ? j : b - 1;
+      v[e] = M[(o + ic) * d + o + jc];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
+      A[i * LDA + j] = (i < b && j <= i) ? v[e] : (i == j ? 1.0 : 0.0);
       Li[i * LDA + j] = 0.0;
     }
+  }
   if (tid == 0) {
     bad = 0;
     pmin = 1e308;
@@ -58,20 +94,23 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
       for (int c = 0; c < PB; ++c) a[c] = (c <= r) ? A[(c0 + r) * LDA + c0 + c] : 0.0;
       double pm = 1e308;
       bool nb_ = false;
+      double rinv[PB];  // 1 / L[j][j] (the same in every lane)
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
-        double pj = __shfl(a[j], j, 64);
+        double pj = lane_value(a[j], j);
         if (!(pj > 0.0)) {
           nb_ = true;
           pj = 1.0;
         }
-        const double ljj = sqrt(pj);
+        const double y = rsqrt_f64(pj);
+        const double ljj = pj * y;
+        rinv[j] = y;
         pm = fmin(pm, ljj);
-        const double lj = (r == j) ? ljj : (r > j ? a[j] / ljj : 0.0);
+        const double lj = (r == j) ? ljj : (r > j ? a[j] * y : 0.0);
         a[j] = (r >= j) ? lj : 0.0;
 #pragma unroll
         for (int c = j + 1; c < PB; ++c) {
-          const double lc = __shfl(lj, c, 64);
+          const double lc = lane_value(lj, c);
           if (r >= c) a[c] = fma(-lj, lc, a[c]);
         }
       }
@@ -82,11 +121,10 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
         double sacc = (i == r) ? 1.0 : 0.0;
 #pragma unroll
         for (int q = 0; q < i; ++q) {
-          const double liq = __shfl(a[q], i, 64);  // L[i][q] from lane i
+          const double liq = lane_value(a[q], i);  // L[i][q] from lane i
           sacc = fma(-liq, x[q], sacc);
         }
-        const double lii = __shfl(a[i], i, 64);
-        x[i] = (i >= r) ? sacc / lii : 0.0;
+        x[i] = (i >= r) ? sacc * rinv[i] : 0.0;
       }
       if (lane < PB) {
 #pragma unroll
@@ -135,10 +173,18 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
     // S_j = sum_q L_{bi,q} Li_{q,j} for every block column j < bi (into Tm rows j*16..)
     for (int e = tid; e < bi * PB * PB; e += kBlock) {
       const int bj = e >> 8, rr = (e >> 4) & 15, c = e & 15;
-      double sacc = 0.0;
-      for (int q = bj * PB; q < bi * PB; ++q)
-        sacc = fma(A[(bi * PB + rr) * LDA + q], Li[q * LDA + bj * PB + c], sacc);
-      Tm[(bj * PB + rr) * (PB + 1) + c] = sacc;
+      // in 16-wide chunks, unrolled, so the LDS reads of a chunk issue together
+      double s0 = 0.0, s1 = 0.0;
+      for (int qb = bj; qb < bi; ++qb) {
+        const double* ar = &A[(bi * PB + rr) * LDA + qb * PB];
+        const double* lc = &Li[(qb * PB) * LDA + bj * PB + c];
+#pragma unroll
+        for (int m = 0; m < PB; m += 2) {
+          s0 = fma(ar[m], lc[m * LDA], s0);
+          s1 = fma(ar[m + 1], lc[(m + 1) * LDA], s1);
+        }
+      }
+      Tm[(bj * PB + rr) * (PB + 1) + c] = s0 + s1;
     }
     __syncthreads();
     for (int e = tid; e < bi * PB * PB; e += kBlock) {
@@ -176,10 +222,23 @@ __global__ __launch_bounds__(kBlock) void chol_trsm_kernel(double* __restrict__ 
   const int64_t o = k * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
   const double* L = Linv_diag + k * NB * NB;
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    const int i = e / NB, j = e % NB;
-    Li[i * LDA + j] = L[e];
-    A[i * LDA + j] = i < rows ? M[(i0 + i) * d + o + j] : 0.0;
+  {
+    double va[NB * NB / kBlock], vl[NB * NB / kBlock];
+#pragma unroll
+    for (int q = 0; q < NB * NB / kBlock; ++q) {
+      const int e = tid + q * kBlock;
+      const int i = e / NB, j = e % NB;
+      const int ic = i < rows ? i : rows - 1;
+      vl[q] = L[e];
+      va[q] = M[(i0 + ic) * d + o + j];
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / kBlock; ++q) {
+      const int e = tid + q * kBlock;
+      const int i = e / NB, j = e % NB;
+      Li[i * LDA + j] = vl[q];
+      A[i * LDA + j] = i < rows ? va[q] : 0.0;
+    }
   }
   __syncthreads();
   // X[r][c] = sum_{m <= c} A[r][m] Li[c][m]; each thread 4 x 4 outputs
@@ -220,10 +279,22 @@ __global__ __launch_bounds__(kBlock) void chol_syrk_kernel(double* __restrict__ 
   const int64_t i0 = bi * NB, j0 = bj * NB, o = k * NB;
   const int ri = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
   const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
-  for (int e = tid; e < NB * NB; e += kBlock) {
-    const int i = e / NB, j = e % NB;
-    La[i * LDA + j] = i < ri ? M[(i0 + i) * d + o + j] : 0.0;
-    Lb[i * LDA + j] = i < rj ? M[(j0 + i) * d + o + j] : 0.0;
+  {
+    double va[NB * NB / kBlock], vb[NB * NB / kBlock];
+#pragma unroll
+    for (int q = 0; q < NB * NB / kBlock; ++q) {
+      const int e = tid + q * kBlock;
+      const int i = e / NB, j = e % NB;
+      va[q] = M[(i0 + (i < ri ? i : ri - 1)) * d + o + j];
+      vb[q] = M[(j0 + (i < rj ? i : rj - 1)) * d + o + j];
+    }
+#pragma unroll
+    for (int q = 0; q < NB * NB / kBlock; ++q) {
+      const int e = tid + q * kBlock;
+      const int i = e / NB, j = e % NB;
+      La[i * LDA + j] = i < ri ? va[q] : 0.0;
+      Lb[i * LDA + j] = i < rj ? vb[q] : 0.0;
+    }
   }
   __syncthreads();
   // waves 2 x 2, each 32 x 32 = 2 x 2 MFMA 16 x 16 blocks
@@ -245,53 +316,94 @@ __global__ __launch_bounds__(kBlock) void chol_syrk_kernel(double* __restrict__ 
       }
     }
   }
+  // FP64 16x16x4 accumulator: register v of lane l holds row l / 16 + 4 v.
+  // Read the 16 outputs from clamped addresses first, then store the valid ones.
+  double old[2][2][4];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        // FP64 16x16x4 accumulator: register v of lane l holds row l / 16 + 4 v
         const int r = wr * 32 + x * 16 + lane / 16 + 4 * v;
         const int c = wc * 32 + y * 16 + lane % 16;
-        if (r < ri && c < rj && (bi != bj || c <= r)) {
-          double* p = &M[(i0 + r) * d + j0 + c];
-          *p -= acc[x][y][v];
-        }
+        old[x][y][v] = M[(i0 + (r < ri ? r : ri - 1)) * d + j0 + (c < rj ? c : rj - 1)];
+      }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * 32 + x * 16 + lane / 16 + 4 * v;
+        const int c = wc * 32 + y * 16 + lane % 16;
+        if (r < ri && c < rj && (bi != bj || c <= r))
+          M[(i0 + r) * d + j0 + c] = old[x][y][v] - acc[x][y][v];
       }
 }
 
 // ---- triangular solves with ticket-ordered block rows
+// Workgroups take 64-row blocks in ticket order.  A solved block is published
+// by storing its values (agent-scope atomic stores) over a sentinel that no
+// arithmetic produces; a consumer thread polls exactly the 16 values it needs
+// (agent-scope atomic loads), so a link of the dependency chain costs one
+// visibility hop and the block's own work -- no flag, fence or barrier.
+// Waits are bounded: after kSpinLimit polls a block reports TK_E_HIP and
+// uses 0, so every workgroup still finishes and publishes.
 constexpr long kSpinLimit = 1L << 22;
+constexpr unsigned long long kPending = 0x7FF4DEADBEEF0001ull;  // a signalling NaN
 
-__device__ inline bool wait_flag(const int32_t* f) {
+// v[c] = p[c] for c < n (0 beyond), waiting until all n are published
+__device__ inline bool load_published(const double* p, int n, double* v) {
   long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-    __builtin_amdgcn_s_sleep(2);
-    if (++spins > kSpinLimit) return false;
+  bool pending = true;
+  while (pending) {
+    pending = false;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const unsigned long long u =
+          c < n ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p + c),
+                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                : 0ull;
+      pending = pending || (u == kPending);
+      v[c] = __longlong_as_double(static_cast<long long>(u));
+    }
+    if (pending) {
+      if (++spins > kSpinLimit) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = 0.0;
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   return true;
 }
 
-// forward: L y = b.  flags[0] ticket, flags[2 + i] row-ready flags.
-// Thread (r, q): row r of the block row, column quarter q of each dependency
-// block.  The L block of the next dependency is loaded before waiting on its
-// flag, so a link of the dependency chain costs a flag hop and a few FMAs.
+__device__ inline void publish(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// forward: L y = b, b read from x; x is left holding the sentinel for the
+// backward solve.  flags[0] is the ticket.  Thread (r, q): row r of the block,
+// column quarter q of each dependency block.
 __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ Linv_diag,
-                                                            int64_t d, const double* __restrict__ b,
-                                                            double* y, int32_t* flags,
-                                                            const int32_t* done, int32_t* status) {
+                                                            int64_t d, double* x, double* y,
+                                                            int32_t* flags, const int32_t* done,
+                                                            int32_t* status) {
   if (done && *done) return;
   __shared__ int64_t row_blk;
   __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
-  __shared__ int ok;
+  __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) {
     row_blk = atomicAdd(&flags[0], 1);
-    ok = 1;
+    bad = 0;
   }
   __syncthreads();
   const int64_t i = row_blk;
@@ -302,6 +414,7 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
     const double* src = Linv_diag + i * NB * NB;
     for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
   }
+  const double bv = (q == 0 && r < rows) ? x[i0 + r] : 0.0;
   const double* Lrow = L + (i0 + (r < rows ? r : 0)) * d + q * 16;
   double cur[16], nxt[16];
   if (i > 0) {
@@ -309,48 +422,38 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
     for (int c = 0; c < 16; ++c) cur[c] = Lrow[c];
   }
   double acc = 0.0;
-  for (int64_t j = 0; j < i; ++j) {
+  bool ok = true;
+  for (int64_t j = 0; j < i; ++j) {  // blocks before the last are full
     if (j + 1 < i) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) nxt[c] = Lrow[(j + 1) * NB + c];
     }
-    if (tid == 0 && ok) {
-      if (!wait_flag(&flags[2 + j])) ok = 0;
-    }
-    __syncthreads();
-    if (!ok) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const double* yj = y + j * NB + q * 16;
+    double yv[16];
+    ok = load_published(y + j * NB + q * 16, 16, yv) && ok;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc = fma(cur[c], yj[c], acc);
+    for (int c = 0; c < 16; ++c) acc = fma(cur[c], yv[c], acc);
 #pragma unroll
     for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
+  if (!ok) bad = 1;
   __syncthreads();
-  if (tid < NB) {
-    const double bv = tid < rows ? b[i0 + tid] : 0.0;
-    acc_s[tid] = bv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
-  }
+  if (tid < NB) acc_s[tid] = bv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
+  if (q == 0 && r < rows) publish(x + i0 + r, __longlong_as_double(kPending));
   __syncthreads();
-  // y_i = Li acc: row r, four partial sums over c
+  // y_i = Li acc: row rr, four partial sums over c
   {
     const int rr = tid >> 2, pp = tid & 3;
     double v = 0.0;
     for (int c = pp; c <= rr; c += 4) v = fma(Li[rr * LDA + c], acc_s[c], v);
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
-    if (pp == 0 && rr < rows) y[i0 + rr] = v;
+    if (pp == 0 && rr < rows) publish(y + i0 + rr, v);
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&flags[2 + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
-  }
+  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
-// backward: L^T x = y.  flags[1] ticket, flags[2 + nblk + i] flags.
+// backward: L^T x = y.  flags[1] is the ticket (blocks from the last).
 __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ Linv_diag,
                                                             int64_t d, int64_t nblk,
@@ -362,17 +465,16 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
-  __shared__ int ok;
+  __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) {
     row_blk = nblk - 1 - atomicAdd(&flags[1], 1);
-    ok = 1;
+    bad = 0;
   }
   __syncthreads();
   const int64_t i = row_blk;
   const int64_t i0 = i * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
-  int32_t* fl = flags + 2 + nblk;
   {
     const double* src = Linv_diag + i * NB * NB;
     for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
@@ -383,34 +485,34 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   auto load_blk = [&](int64_t j, double* v) {
     const int64_t j0 = j * NB;
     const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
+    double t[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int cc = q * 16 + c;
-      v[c] = cc < rj ? L[(j0 + cc) * d + i0 + rc] : 0.0;
+      t[c] = L[(j0 + (cc < rj ? cc : rj - 1)) * d + i0 + rc];
     }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = (q * 16 + c) < rj ? t[c] : 0.0;
   };
   double cur[16], nxt[16];
   if (i < nblk - 1) load_blk(nblk - 1, cur);
   double acc = 0.0;
+  bool ok = true;
   for (int64_t j = nblk - 1; j > i; --j) {
     if (j - 1 > i) load_blk(j - 1, nxt);
-    if (tid == 0 && ok) {
-      if (!wait_flag(&fl[j])) ok = 0;
-    }
-    __syncthreads();
-    if (!ok) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int64_t j0 = j * NB;
     const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
+    int n = rj - q * 16;
+    n = n < 0 ? 0 : (n > 16 ? 16 : n);
+    double xv[16];
+    ok = load_published(x + j0 + q * 16, n, xv) && ok;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int cc = q * 16 + c;
-      if (cc < rj) acc = fma(cur[c], x[j0 + cc], acc);
-    }
+    for (int c = 0; c < 16; ++c) acc = fma(cur[c], xv[c], acc);
 #pragma unroll
     for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
+  if (!ok) bad = 1;
   __syncthreads();
   if (tid < NB) {
     const double yv = tid < rows ? y[i0 + tid] : 0.0;
@@ -424,20 +526,17 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
     for (int c = rr + pp; c < rows; c += 4) v = fma(Li[c * LDA + rr], acc_s[c], v);
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
-    if (pp == 0 && rr < rows) x[i0 + rr] = v;
+    if (pp == 0 && rr < rows) publish(x + i0 + rr, v);
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&fl[i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
-  }
+  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
-__global__ void fill_flags_kernel(int32_t* f, int64_t n, const int32_t* done) {
+// tickets to 0 and y to the sentinel
+__global__ void solve_init_kernel(int32_t* flags, double* y, int64_t d, const int32_t* done) {
   if (done && *done) return;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) f[i] = 0;
+  if (i < 2) flags[i] = 0;
+  if (i < d) y[i] = __longlong_as_double(static_cast<long long>(kPending));
 }
 
 }  // namespace
@@ -462,11 +561,10 @@ void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, doub
                        double* y_tmp, int32_t* flags, const int32_t* done, int32_t* status,
                        hipStream_t st) {
   const int64_t nblk = cdiv(d, NB);
-  const int64_t nf = 2 * nblk + 2;
-  hipLaunchKernelGGL(fill_flags_kernel, dim3(static_cast<unsigned>(cdiv(nf, kBlock))), dim3(kBlock),
-                     0, st, flags, nf, done);
+  hipLaunchKernelGGL(solve_init_kernel, dim3(static_cast<unsigned>(cdiv(d, kBlock))), dim3(kBlock),
+                     0, st, flags, y_tmp, d, done);
   hipLaunchKernelGGL(trsv_lower_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
-                     Linv_diag, d, static_cast<const double*>(x), y_tmp, flags, done, status);
+                     Linv_diag, d, x, y_tmp, flags, done, status);
   hipLaunchKernelGGL(trsv_upper_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
                      Linv_diag, d, nblk, static_cast<const double*>(y_tmp), x, flags, done, status);
 }
