@@ -237,7 +237,7 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
 #define TK_MAX_BATCH 64
 
 typedef struct {
-  int32_t tile;      /* Gram output tile edge: 64 or 128 (0: 128) */
+  int32_t tile;      /* Gram output tile edge: 64, 128 or 256 (0: 128) */
   int32_t wg_per_cu; /* workgroups per compute unit in the persistent grid, 1..8 (0: 3) */
 } tk_batch_config;
 
@@ -254,7 +254,8 @@ tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_
  * Autotuner of the batched call: runs steps 1-3 of every problem once, then
  * times the batched Gram launch (one warm-up, one timed run, HIP events on
  * `stream`) for each candidate tile shape and grid -- tile 128 with 3 or 2
- * workgroups per CU, tile 64 with 4, 5 or 6 -- and returns the fastest in
+ * workgroups per CU, tile 256 with 1, tile 64 with 4, 5 or 6 -- and returns
+ * the fastest in
  * *best.  Unlike every other call it synchronises `stream`, so run it once
  * per batch shape before capturing the batched call.  The workspace must be
  * tucker_workspace_bytes_batched(probs, opts, count, NULL) bytes (enough for

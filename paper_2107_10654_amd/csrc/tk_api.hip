@@ -388,13 +388,14 @@ void carve_loss(Carver& c, const Geom& g, LossWS& w) {
 // T <- T x_n M_n over all modes (core-sized ping-pong).  Returns the buffer
 // holding the result (a or b).
 double* core_chain(const Geom& g, double* a, double* b, const double* mats, bool trans,
-                   double* scratch, hipStream_t st) {
+                   double* scratch, hipStream_t st, const int32_t* done = nullptr) {
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.ranks[n];
   double* cur = a;
   double* nxt = b;
   for (int n = 0; n < g.order; ++n) {
-    launch_ttm(cur, dims, g.order, n, mats + g.roff[n], g.ranks[n], trans, nxt, scratch, st);
+    launch_ttm(cur, dims, g.order, n, mats + g.roff[n], g.ranks[n], trans, nxt, scratch, st,
+               done);
     double* t = cur;
     cur = nxt;
     nxt = t;
@@ -643,7 +644,7 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
     launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
     launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
     launch_copy_f64(g.d, h, w.ph_a, st);
-    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st);
+    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st, w.done);
     launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
                         w.done, w.steps, w.relres, k < iters ? 1 : 0, st);
     if (k < iters) {
@@ -684,8 +685,9 @@ tk_status sketch_begin(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
 }
 
 // ---------------------------------------------------------------- batches
-constexpr int kTuneCandidates = 5;
-const SkConfig kTuneSet[kTuneCandidates] = {{128, 3}, {128, 2}, {64, 4}, {64, 5}, {64, 6}};
+constexpr int kTuneCandidates = 6;
+const SkConfig kTuneSet[kTuneCandidates] = {{128, 3}, {128, 2}, {256, 1},
+                                             {64, 4},  {64, 5},  {64, 6}};
 
 SkConfig batch_config(const tk_batch_config* cfg) {
   SkConfig c{128, 3};

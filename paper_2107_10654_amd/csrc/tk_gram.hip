@@ -534,7 +534,7 @@ GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override)
   if (pl.streamk) {
     pl.sk.count = 1;
     pl.sk.p[0] = sk_prob(g, s, nullptr);
-    SkConfig cfg{128, 3};
+    SkConfig cfg = sk_default_config(g.d);
     if (ksplit_override > 0) cfg.wg_per_cu = ksplit_override;
     sk_finalize(pl.sk, prec, cfg);
     pl.tile = cfg.tile;

@@ -26,13 +26,18 @@
 namespace tk {
 namespace {
 
-constexpr int kSkThreads = 256;
 constexpr int kSkRT = kRowChunk + 4;  // padded LDS row: conflict-free 16-byte reads
 
+// Tile edge T: 64 and 128 use 2 x 2 waves (32 x 32 or 64 x 64 each, up to 4
+// or 3 workgroups per CU); 256 uses 4 x 2 waves of 64 x 128 in one
+// 512-thread workgroup per CU, which halves the row formation per MFMA.
 template <int T>
 struct SkTile {
   static constexpr int NO = T / 2 + 1;  // outer indices per tile when R_L >= 2
-  static constexpr int WG_PER_CU = T == 128 ? 3 : 4;
+  static constexpr int WAVES_R = T == 256 ? 4 : 2;
+  static constexpr int WAVES_C = 2;
+  static constexpr int THREADS = 64 * WAVES_R * WAVES_C;
+  static constexpr int WG_PER_CU = T == 128 ? 3 : (T == 64 ? 4 : 1);
 };
 
 template <class V, int T>
@@ -50,11 +55,12 @@ struct SkLayout {
 };
 
 // prefetch registers (16-byte) per thread: a chunk holds kRowChunk * sum_r values
-constexpr int kSkPfSmall = 2;  // sum_r <= 64
-constexpr int kSkPfLarge = (kRowChunk * kMaxSumR / 4 + kSkThreads - 1) / kSkThreads;
-__host__ __device__ constexpr int sk_pf_slots(int sum_r) {
-  return kRowChunk * sum_r <= 4 * kSkThreads * kSkPfSmall ? kSkPfSmall : kSkPfLarge;
-}
+template <int THREADS>
+struct SkPf {
+  static constexpr int SMALL = THREADS >= 1024 ? 1 : 2;  // sum_r <= 128 / 64
+  static constexpr int LARGE = (kRowChunk * kMaxSumR / 4 + THREADS - 1) / THREADS;
+  static constexpr bool small(int sum_r) { return kRowChunk * sum_r <= 4 * THREADS * SMALL; }
+};
 
 __host__ __device__ inline int64_t sk_unit_start(int64_t w, int64_t units, int64_t grid) {
   return (w * units) / grid;
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(1024) void sk_index_kernel(SkBatch b, int64_t* __re
 }
 
 template <class V, int T, int PF4>
-__global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kernel(
+__global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram_sk_kernel(
     SkBatch b, typename V::Out* __restrict__ slots, const int64_t* __restrict__ index) {
   using Src = typename V::Src;
   using Op = typename V::Op;
@@ -154,6 +160,7 @@ __global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kern
   constexpr int BK = V::BK, LDK = V::LDK, RT = kSkRT, NO = L::NO;
   constexpr int IW = V::EPL == 8 ? 8 : 4;         // samples per formation item
   constexpr int IPR = BK / IW;                    // items per row
+  constexpr int kSkThreads = SkTile<T>::THREADS;
   constexpr int ITEMS = T * IPR / kSkThreads;     // items per thread per side
   static_assert(BK == kRowChunk, "chunk size");
   static_assert(ITEMS >= 1, "tile too small for the workgroup");
@@ -172,8 +179,9 @@ __global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kern
   if (u0 >= u1) return;
   const int64_t slot0 = index[w];
 
-  constexpr int WR = T / 2, WC = T / 2, NBR = WR / V::MT, NBC = WC / V::MT;
-  const int wr = wave >> 1, wc = wave & 1;
+  constexpr int WR = T / SkTile<T>::WAVES_R, WC = T / SkTile<T>::WAVES_C;
+  constexpr int NBR = WR / V::MT, NBC = WC / V::MT;
+  const int wr = wave / SkTile<T>::WAVES_C, wc = wave % SkTile<T>::WAVES_C;
   Acc acc[NBR][NBC];
 
   f32x4 pf[PF4];
@@ -211,8 +219,9 @@ __global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kern
     for (int side = 0; side < 2; ++side)
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
+        // consecutive lanes take consecutive rows: conflict-free LDS stores
         const int e = tid + k * kSkThreads;
-        const int i = e / IPR, tg = (e % IPR) * IW;
+        const int i = e % T, tg = (e / T) * IW;
         const int64_t r = (side == 0 ? r0 : c0) + i;
         const int64_t rr = r < d ? r : d - 1;
         iofs_o[side][k] = static_cast<int>(rr / RL - ob[side]) * BK + tg;
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(kSkThreads, SkTile<T>::WG_PER_CU) void gram_sk_kern
 #pragma unroll
           for (int k = 0; k < ITEMS; ++k) {
             const int e = tid + k * kSkThreads;
-            const int i = e / IPR, tg = (e % IPR) * IW;
+            const int i = e % T, tg = (e / T) * IW;
             const f32x4* op = reinterpret_cast<const f32x4*>(O + iofs_o[side][k]);
             const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
             if constexpr (V::EPL == 8) {
@@ -382,12 +391,13 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
 
 template <class V, int T>
 void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(b.grid)), block(kSkThreads);
+  using Pf = SkPf<SkTile<T>::THREADS>;
+  const dim3 grid(static_cast<unsigned>(b.grid)), block(SkTile<T>::THREADS);
   const size_t lds = SkLayout<V, T>::bytes(b.max_sum_r);
-  if (sk_pf_slots(b.max_sum_r) == kSkPfSmall)
-    hipLaunchKernelGGL((gram_sk_kernel<V, T, kSkPfSmall>), grid, block, lds, st, b, slots, index);
+  if (Pf::small(b.max_sum_r))
+    hipLaunchKernelGGL((gram_sk_kernel<V, T, Pf::SMALL>), grid, block, lds, st, b, slots, index);
   else
-    hipLaunchKernelGGL((gram_sk_kernel<V, T, kSkPfLarge>), grid, block, lds, st, b, slots, index);
+    hipLaunchKernelGGL((gram_sk_kernel<V, T, Pf::LARGE>), grid, block, lds, st, b, slots, index);
 }
 
 int device_cu_count() {
@@ -407,8 +417,20 @@ int device_cu_count() {
 
 }  // namespace
 
+#ifndef TK_SK_BIG_TILE_D
+#define TK_SK_BIG_TILE_D 2048
+#endif
+
+SkConfig sk_default_config(int64_t d) {
+  // the 256 tile halves the row formation per MFMA once there are enough
+  // tiles to spread over the CUs
+  if (d >= TK_SK_BIG_TILE_D) return SkConfig{256, SkTile<256>::WG_PER_CU};
+  return SkConfig{128, SkTile<128>::WG_PER_CU};
+}
+
 bool sk_config_valid(const SkConfig& c) {
-  return (c.tile == 64 || c.tile == 128) && c.wg_per_cu >= 1 && c.wg_per_cu <= 8;
+  return (c.tile == 64 || c.tile == 128 || c.tile == 256) && c.wg_per_cu >= 1 &&
+         c.wg_per_cu <= 8;
 }
 
 SkProb sk_prob(const Geom& g, int64_t s, const float* rows32) {
@@ -461,7 +483,10 @@ void launch_gram_sk(const SkBatch& b, float* slots, int64_t* index, hipStream_t 
   if (b.count < 1 || b.units < 1) return;
   hipLaunchKernelGGL(sk_index_kernel, dim3(1), dim3(1024), 0, st, b, index);
   const bool bf = b.prec == TK_BF16;
-  if (b.tile == 128) {
+  if (b.tile == 256) {
+    if (bf) gram_sk_launch<VarBF16, 256>(b, slots, index, st);
+    else gram_sk_launch<VarF32, 256>(b, slots, index, st);
+  } else if (b.tile == 128) {
     if (bf) gram_sk_launch<VarBF16, 128>(b, slots, index, st);
     else gram_sk_launch<VarF32, 128>(b, slots, index, st);
   } else {
@@ -476,7 +501,10 @@ void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slo
   const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
   const SkProb& q = b.p[k];
   const int64_t nch = row_chunks(q.s);
-  if (b.tile == 128)
+  if (b.tile == 256)
+    hipLaunchKernelGGL(assemble_sk_kernel<256>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
+                       q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+  else if (b.tile == 128)
     hipLaunchKernelGGL(assemble_sk_kernel<128>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
                        q.unit0, q.tile0, nch, slots, index, P, lambda, M);
   else

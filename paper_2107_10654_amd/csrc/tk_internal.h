@@ -122,6 +122,8 @@ void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slo
                         const int64_t* index, const double* P, double lambda, double* M,
                         hipStream_t st);
 bool sk_config_valid(const SkConfig& c);
+// Tile and grid of a single problem's stream-K Gram.
+SkConfig sk_default_config(int64_t d);
 
 struct GramPlan {
   tk_dtype prec;
