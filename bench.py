@@ -76,10 +76,15 @@ class HipEvents:
             self.lib.hipEventDestroy(h)
 
 
+GRAM_SOURCES = ("tk_gram_sk.hip", "tk_mfma.h", "tk_internal.h")
+
+
 def kernel_source_hash():
+    """Hash of the sources the stream-K Gram kernel is built from."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2107_10654_amd", "csrc", "tk_gram.hip"), "rb") as f:
-        h.update(f.read())
+    for name in GRAM_SOURCES:
+        with open(os.path.join(ROOT, "paper_2107_10654_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
