@@ -306,7 +306,7 @@ constexpr int kVPF = (kVK * kMaxSumR + kBlock - 1) / kBlock;
 struct VecSmem {
   double rT[kMaxSumR * kVRT];
   double sc[kVK];
-  double O[kVO][kVK];
+  double O[kVO][kVK + 1];  // padded: MFMA fragments read 16 rows at one column
   unsigned char offs[kVO][kMaxOrder];
   double red[4][kVK];
 };
@@ -381,7 +381,16 @@ __device__ inline void vec_outer(const Geom& g, VecSmem& sm, const VecGeo& vg) {
   }
 }
 
-// part[split][r] = sum_{t in split} c_t q_t[r]
+// part[split][r] = sum_{t in split} c_t q_t[r], with r = (obase + o) R_L + l:
+// the block out[o][l] = sum_t O[o][t] q_L[l][t] is a small FP64 GEMM over the
+// samples, run on v_mfma_f64_16x16x4 in 16 x 16 blocks shared by the 4 waves.
+__device__ inline double mfma_f64_operand(const double* base, int stride, int row, int nrows,
+                                          int col) {
+  // row-clamped read, zero outside: the fragment of a partial 16-row block
+  const double v = base[(row < nrows ? row : nrows - 1) * stride + col];
+  return row < nrows ? v : 0.0;
+}
+
 __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double* __restrict__ rows,
                                                             const double* __restrict__ c,
                                                             int64_t s, int64_t cps,
@@ -391,10 +400,16 @@ __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double
   __shared__ VecSmem sm;
   const VecGeo vg = vec_setup(g, sm);
   const int sl = g.soff[g.last];
+  const int RL = g.ranks[g.last];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nob = (vg.no + 15) / 16, nlb = (RL + 15) / 16;
+  const int nblk = nob * nlb;  // <= 20 blocks of 16 x 16, wave w takes w, w + 4, ...
   const int64_t ca = static_cast<int64_t>(blockIdx.y) * cps;
   int64_t cb = ca + cps;
   if (cb > row_chunks(s)) cb = row_chunks(s);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  doublex4 acc[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc[q] = doublex4{0, 0, 0, 0};
   double pf[kVPF];
   if (ca < cb) {
     vec_fetch(g, rows, ca, pf);
@@ -407,23 +422,40 @@ __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double
     vec_outer(g, sm, vg);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (!vg.my_ok[k]) continue;
-      const double* Ok = sm.O[vg.my_o[k]];
-      const double* ql = sm.rT + (sl + vg.my_l[k]) * kVRT;
-      double a = acc[k];
-#pragma unroll 8
-      for (int t = 0; t < kVK; ++t) a = fma(Ok[t], ql[t], a);
-      acc[k] = a;
+    for (int q = 0; q < 5; ++q) {
+      const int blk = wave + 4 * q;
+      if (blk < nblk) {
+        const int ob = blk / nlb, lb = blk % nlb;
+#pragma unroll
+        for (int kk = 0; kk < kVK; kk += 4) {
+          const int t = kk + lane / 16;
+          const double av = mfma_f64_operand(&sm.O[0][0], kVK + 1, ob * 16 + lane % 16, vg.no, t);
+          const double bv =
+              mfma_f64_operand(sm.rT + sl * kVRT, kVRT, lb * 16 + lane % 16, RL, t);
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
     if (more) vec_commit(g, sm, pf, c, ch + 1, s);
     __syncthreads();
   }
+  // accumulator register v of lane l: o = ob 16 + l / 16 + 4 v, l_ = lb 16 + l % 16
+  const int64_t obase = vg.r0 / RL;
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (vg.my_ok[k])
-      part[static_cast<int64_t>(blockIdx.y) * g.d + vg.r0 + threadIdx.x + k * kBlock] = acc[k];
+  for (int q = 0; q < 5; ++q) {
+    const int blk = wave + 4 * q;
+    if (blk < nblk) {
+      const int ob = blk / nlb, lb = blk % nlb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = ob * 16 + lane / 16 + 4 * v, l = lb * 16 + lane % 16;
+        const int64_t r = (obase + o) * RL + l;
+        if (o < vg.no && l < RL && r >= vg.r0 && r < vg.r0 + vg.rw)
+          part[static_cast<int64_t>(blockIdx.y) * g.d + r] = acc[q][v];
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void sum_parts_kernel(const double* __restrict__ part,
@@ -433,12 +465,23 @@ __global__ __launch_bounds__(kBlock) void sum_parts_kernel(const double* __restr
   if (done && *done) return;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  double v = 0.0;
-  for (int64_t k = 0; k < nparts; ++k) v += part[k * n + i];
-  out[i] = v;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int64_t k = 0;
+  for (; k + 4 <= nparts; k += 4) {  // four independent loads in flight per step
+    v0 += part[k * n + i];
+    v1 += part[(k + 1) * n + i];
+    v2 += part[(k + 2) * n + i];
+    v3 += part[(k + 3) * n + i];
+  }
+  for (; k < nparts; ++k) v0 += part[k * n + i];
+  out[i] = (v0 + v1) + (v2 + v3);
 }
 
-// part[rchunk][t] = sum_{r in rchunk} h[r] q_t[r]
+// part[rchunk][t] = sum_{r in rchunk} h[r] q_t[r] = sum_o O[o][t] U[o][t] with
+// U[o][t] = sum_l h[(obase + o) R_L + l] q_L[l][t]: U is a small FP64 GEMM on
+// v_mfma_f64_16x16x4 (16 x 16 blocks (o, t) shared by the 4 waves, K = R_L); each
+// lane then multiplies its accumulators by O and the partial sums over o are
+// reduced across lanes and waves.
 __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* __restrict__ rows,
                                                           const double* __restrict__ h,
                                                           int64_t s, int64_t cps,
@@ -448,10 +491,18 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
   __shared__ VecSmem sm;
   const VecGeo vg = vec_setup(g, sm);
   const int sl = g.soff[g.last];
-  double hr[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) hr[k] = vg.my_ok[k] ? h[vg.r0 + threadIdx.x + k * kBlock] : 0.0;
+  const int RL = g.ranks[g.last];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t obase = vg.r0 / RL;
+  // h[(obase + o) R_L + l] inside this workgroup's rows, 0 outside (read through L1)
+  auto h_at = [&](int o, int l) -> double {
+    const int64_t r = (obase + o) * RL + l;
+    const bool ok = o < vg.no && l < RL && r >= vg.r0 && r < vg.r0 + vg.rw;
+    const double v = h[ok ? r : vg.r0];
+    return ok ? v : 0.0;
+  };
+  const int nob = (vg.no + 15) / 16;
+  const int nblk = nob * (kVK / 16);  // (o block, t block) pairs, <= 10
   const int64_t ca = static_cast<int64_t>(blockIdx.y) * cps;
   int64_t cb = ca + cps;
   if (cb > row_chunks(s)) cb = row_chunks(s);
@@ -466,33 +517,44 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
     if (more) vec_fetch(g, rows, ch + 1, pf);
     vec_outer(g, sm, vg);
     __syncthreads();
-    double v[kVK];
+    double ct[2] = {0.0, 0.0};  // this lane's partial c for t = tb 16 + lane % 16, tb = 0, 1
 #pragma unroll
-    for (int t = 0; t < kVK; ++t) v[t] = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      const int blk = wave + 4 * q;
+      if (blk < nblk) {
+        const int ob = blk >> 1, tb = blk & 1;
+        doublex4 u = doublex4{0, 0, 0, 0};
+        for (int kl = 0; kl < RL; kl += 4) {
+          const int l = kl + lane / 16;
+          const double av = h_at(ob * 16 + lane % 16, l);
+          const double bq = sm.rT[(sl + (l < RL ? l : RL - 1)) * kVRT + tb * 16 + lane % 16];
+          const double bv = l < RL ? bq : 0.0;
+          u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+        }
+        // register v: o = ob 16 + lane / 16 + 4 v, t = tb 16 + lane % 16
+        double p = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (!vg.my_ok[k]) continue;
-      const double* Ok = sm.O[vg.my_o[k]];
-      const double* ql = sm.rT + (sl + vg.my_l[k]) * kVRT;
-#pragma unroll
-      for (int t = 0; t < kVK; ++t) v[t] = fma(hr[k] * Ok[t], ql[t], v[t]);
-    }
-    // butterfly reduction over the wave: after the steps with masks 32..2 lane l
-    // holds sample (b5 b4 b3 b2 b1) of its lane index, summed over 32 lanes
-#pragma unroll
-    for (int wdt = kVK / 2, m = 32; wdt >= 1; wdt >>= 1, m >>= 1) {
-      const bool up = (lane & m) != 0;
-#pragma unroll
-      for (int j = 0; j < wdt; ++j) {
-        const double send = up ? v[j] : v[j + wdt];
-        const double keep = up ? v[j + wdt] : v[j];
-        v[j] = keep + __shfl_xor(send, m, 64);
+        for (int v = 0; v < 4; ++v) {
+          const int o = ob * 16 + lane / 16 + 4 * v;
+          const int oc = o < vg.no ? o : vg.no - 1;
+          const double ov = sm.O[oc][tb * 16 + lane % 16];
+          p = fma(o < vg.no ? ov : 0.0, u[v], p);
+        }
+        ct[tb] += p;
       }
     }
-    v[0] += __shfl_xor(v[0], 1, 64);
-    const int tl = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
-                   ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-    if ((lane & 1) == 0) sm.red[wave][tl] = v[0];
+    // sum the four lanes that share t (lane % 16), then the waves through LDS
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+      double v = ct[tb];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      ct[tb] = v;
+    }
+    if (lane < 16) {
+      sm.red[wave][lane] = ct[0];
+      sm.red[wave][16 + lane] = ct[1];
+    }
     __syncthreads();
     if (threadIdx.x < kVK) {
       const int64_t tt = ch * kVK + threadIdx.x;
