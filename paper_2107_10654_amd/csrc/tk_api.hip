@@ -605,7 +605,7 @@ void sketch_factor(SketchRun& R) {
   launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
   // 6. FP64 Cholesky
-  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, R.st);
+  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st);
   R.stage(6);
 }
 

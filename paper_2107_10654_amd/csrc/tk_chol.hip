@@ -3,10 +3,10 @@
 // normal equations with a pseudo-inverse; the system here is positive
 // definite for lambda > 0, so a Cholesky factorisation is the direct solver.
 //
-// Blocked right-looking algorithm with 64 x 64 tiles, three launches per
-// block column: factor the diagonal tile (and invert it), solve the tiles
-// below it with the inverse, update the trailing lower triangle on FP64
-// MFMA.  The triangular solves use one launch each: workgroups take block
+// Blocked right-looking algorithm with 64 x 64 tiles: after the first
+// diagonal tile and panel, one launch per block column updates the trailing
+// lower triangle on FP64 MFMA and, inside the same launch, factors (and
+// inverts) the next diagonal tile and solves the next panel with the inverse.  The triangular solves use one launch each: workgroups take block
 // rows in ticket order and wait (bounded spin) for the values they depend on.
 #include "tk_internal.h"
 
@@ -48,42 +48,18 @@ __device__ inline double rsqrt_f64(double x) {
   return y;
 }
 
-__global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
-                                                           int64_t k,
-                                                           double* __restrict__ Linv_diag,
-                                                           double* min_pivot, int32_t* status) {
-  __shared__ double A[NB * LDA];
-  __shared__ double Li[NB * LDA];
-  __shared__ double Tm[NB * (PB + 1)];
-  __shared__ int bad;
-  __shared__ double pmin;
+// Factor and invert the 64 x 64 block held in LDS A (lower triangle; rows past
+// the matrix hold the identity): on return A holds L and Li holds L^{-1}.
+// Li must be zero and *bad / *pmin initialised; Tm is scratch.
+__device__ __attribute__((always_inline)) inline void diag_factor(double* A, double* Li, double* Tm,
+                                                                int* bad_s, double* pmin_s) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int tx = tid & 15, ty = tid >> 4;
-  const int64_t o = k * NB;
-  const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
-  {
-    // unconditional loads from clamped (in-bounds) addresses, so they issue
-    // back to back; the selects run after all of them
-    double v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
-      const int ic = i < b ? i : b - 1, jc = j < b ? j : b - 1;
-      v[e] = M[(o + ic) * d + o + jc];
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
-      A[i * LDA + j] = (i < b && j <= i) ? v[e] : (i == j ? 1.0 : 0.0);
-      Li[i * LDA + j] = 0.0;
-    }
-  }
-  if (tid == 0) {
-    bad = 0;
-    pmin = 1e308;
-  }
-  __syncthreads();
+  int& bad = *bad_s;
+  double& pmin = *pmin_s;
+  (void)tx;
+  (void)ty;
   for (int p = 0; p < NB / PB; ++p) {
     const int c0 = p * PB;
     // (1) factor the 16 x 16 diagonal panel and invert it (wave 0, lane r = row r)
@@ -197,6 +173,45 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
+                                                           int64_t k,
+                                                           double* __restrict__ Linv_diag,
+                                                           double* min_pivot, int32_t* status) {
+  __shared__ double smem[2 * NB * LDA + NB * (PB + 1)];
+  double* A = smem;
+  double* Li = smem + NB * LDA;
+  double* Tm = smem + 2 * NB * LDA;
+  __shared__ int bad;
+  __shared__ double pmin;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t o = k * NB;
+  const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
+  {
+    // unconditional loads from clamped (in-bounds) addresses, so they issue
+    // back to back; the selects run after all of them
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
+      const int ic = i < b ? i : b - 1, jc = j < b ? j : b - 1;
+      v[e] = M[(o + ic) * d + o + jc];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
+      A[i * LDA + j] = (i < b && j <= i) ? v[e] : (i == j ? 1.0 : 0.0);
+      Li[i * LDA + j] = 0.0;
+    }
+  }
+  if (tid == 0) {
+    bad = 0;
+    pmin = 1e308;
+  }
+  __syncthreads();
+  diag_factor(A, Li, Tm, &bad, &pmin);
   double* Lo = Linv_diag + k * NB * NB;
   for (int i = ty; i < NB; i += 16)
     for (int j = tx; j < NB; j += 16) {
@@ -263,13 +278,74 @@ __global__ __launch_bounds__(kBlock) void chol_trsm_kernel(double* __restrict__ 
       if (tr + x < rows) M[(i0 + tr + x) * d + o + tc + y] = acc[x][y];
 }
 
-// ---- trailing update: M_ij -= L_ik L_jk^T for k < j <= i (FP64 MFMA 16x16x4)
-__global__ __launch_bounds__(kBlock) void chol_syrk_kernel(double* __restrict__ M, int64_t d,
-                                                           int64_t k) {
-  __shared__ double La[NB * LDA];
-  __shared__ double Lb[NB * LDA];
+// ---- one factorisation step with look-ahead: the trailing update of step k
+// (M_ij -= L_ik L_jk^T for k < j <= i) in one launch that also factors the
+// next diagonal block and solves the next panel.  Workgroup 0 owns tile
+// (k+1, k+1): after its update it factors and inverts the block in LDS and
+// raises flags[k+1].  The workgroups of tiles (i, k+1), i > k+1, wait for that
+// flag -- they wait only on workgroup 0, which waits on nothing and is
+// dispatched first; the wait is bounded -- and multiply their updated tile by
+// the new inverse.  Every other workgroup only updates its tile, so the
+// diagonal factorisation overlaps the bulk of the update.
+constexpr long kStepSpinLimit = 1L << 22;
+
+__device__ inline bool wait_flag(const int32_t* f) {
+  long spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kStepSpinLimit) return false;
+  }
+  return true;
+}
+
+// acc (2 x 2 blocks of 16 x 16 per wave, FP64 MFMA 16x16x4) = X Y^T over 64
+// columns, X and Y 64 x 64 in LDS (row stride LDA)
+__device__ inline void tile_gemm_nt(const double* X, const double* Y, doublex4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = doublex4{0, 0, 0, 0};
+  for (int kk = 0; kk < NB; kk += 4) {
+    const int kc = kk + lane / 16;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const double av = X[(wr * 32 + x * 16 + lane % 16) * LDA + kc];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const double bv = Y[(wc * 32 + y * 16 + lane % 16) * LDA + kc];
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[x][y], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// (row, col) of accumulator register v of block (x, y): FP64 16x16x4 puts
+// row l / 16 + 4 v, column l % 16 of the 16 x 16 block in lane l
+__device__ inline int acc_r(int x, int v) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave >> 1) * 32 + x * 16 + lane / 16 + 4 * v;
+}
+__device__ inline int acc_c(int y) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return (wave & 1) * 32 + y * 16 + lane % 16;
+}
+
+__global__ __launch_bounds__(kBlock) void chol_step_kernel(double* __restrict__ M, int64_t d,
+                                                           int64_t k,
+                                                           double* __restrict__ Linv_diag,
+                                                           double* min_pivot, int32_t* status,
+                                                           int32_t* flags) {
+  __shared__ double smem[2 * NB * LDA + NB * (PB + 1)];
+  double* La = smem;
+  double* Lb = smem + NB * LDA;
+  double* Tm = smem + 2 * NB * LDA;
+  __shared__ int bad;
+  __shared__ double pmin;
+  __shared__ int ok;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int tx = tid & 15, ty = tid >> 4;
   int64_t tau = blockIdx.x;
   int64_t a = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(tau) + 1.0) - 1.0) * 0.5);
   while ((a + 1) * (a + 2) / 2 <= tau) ++a;
@@ -297,49 +373,108 @@ __global__ __launch_bounds__(kBlock) void chol_syrk_kernel(double* __restrict__ 
     }
   }
   __syncthreads();
-  // waves 2 x 2, each 32 x 32 = 2 x 2 MFMA 16 x 16 blocks
-  const int wr = wave >> 1, wc = wave & 1;
   doublex4 acc[2][2];
+  tile_gemm_nt(La, Lb, acc);
+  // updated tile values of this thread's 16 elements (rows / columns clamped)
+  double nv[2][2][4];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = doublex4{0, 0, 0, 0};
-  for (int kk = 0; kk < NB; kk += 4) {
-    const int kc = kk + lane / 16;
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      const double av = La[(wr * 32 + x * 16 + lane % 16) * LDA + kc];
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_r(x, v), c = acc_c(y);
+        nv[x][y][v] = M[(i0 + (r < ri ? r : ri - 1)) * d + j0 + (c < rj ? c : rj - 1)] -
+                      acc[x][y][v];
+      }
+  __syncthreads();  // La / Lb are reused below
+  if (tau == 0) {
+    // diagonal tile (k+1, k+1): factor and invert, then publish
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const double bv = Lb[(wc * 32 + y * 16 + lane % 16) * LDA + kc];
-        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[x][y], 0, 0, 0);
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_r(x, v), c = acc_c(y);
+          La[r * LDA + c] = (r < ri && c <= r) ? nv[x][y][v] : (r == c ? 1.0 : 0.0);
+          Lb[r * LDA + c] = 0.0;
+        }
+    if (tid == 0) {
+      bad = 0;
+      pmin = 1e308;
+    }
+    __syncthreads();
+    diag_factor(La, Lb, Tm, &bad, &pmin);
+    double* Lo = Linv_diag + (k + 1) * NB * NB;
+    for (int i = ty; i < NB; i += 16)
+      for (int j = tx; j < NB; j += 16) {
+        Lo[i * NB + j] = (j <= i) ? Lb[i * LDA + j] : 0.0;
+        if (i < ri && j <= i) M[(i0 + i) * d + i0 + j] = La[i * LDA + j];
+      }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
+      atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
+                static_cast<unsigned long long>(__double_as_longlong(pmin)));
+      __hip_atomic_store(&flags[k + 1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (bb == 0) {
+    // panel tile (bi, k+1), bi > k+1 (block k+1 is then a full block):
+    // L_{bi,k+1} = A L_{k+1,k+1}^{-T} once the diagonal block is published
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_r(x, v), c = acc_c(y);
+          La[r * LDA + c] = r < ri ? nv[x][y][v] : 0.0;
+        }
+    if (tid == 0) ok = wait_flag(&flags[k + 1]) ? 1 : 0;
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    {
+      const double* Li = Linv_diag + (k + 1) * NB * NB;
+      double vl[NB * NB / kBlock];
+#pragma unroll
+      for (int q = 0; q < NB * NB / kBlock; ++q) vl[q] = Li[tid + q * kBlock];
+#pragma unroll
+      for (int q = 0; q < NB * NB / kBlock; ++q) {
+        const int e = tid + q * kBlock;
+        Lb[(e / NB) * LDA + e % NB] = vl[q];
       }
     }
+    __syncthreads();
+    doublex4 acc2[2][2];
+    tile_gemm_nt(La, Lb, acc2);  // X[r][c] = sum_m A[r][m] Li[c][m]
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_r(x, v), c = acc_c(y);
+          if (r < ri) M[(i0 + r) * d + j0 + c] = acc2[x][y][v];
+        }
+    if (tid == 0 && !ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = acc_r(x, v), c = acc_c(y);
+          if (r < ri && c < rj && (bi != bj || c <= r)) M[(i0 + r) * d + j0 + c] = nv[x][y][v];
+        }
   }
-  // FP64 16x16x4 accumulator: register v of lane l holds row l / 16 + 4 v.
-  // Read the 16 outputs from clamped addresses first, then store the valid ones.
-  double old[2][2][4];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wr * 32 + x * 16 + lane / 16 + 4 * v;
-        const int c = wc * 32 + y * 16 + lane % 16;
-        old[x][y][v] = M[(i0 + (r < ri ? r : ri - 1)) * d + j0 + (c < rj ? c : rj - 1)];
-      }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wr * 32 + x * 16 + lane / 16 + 4 * v;
-        const int c = wc * 32 + y * 16 + lane % 16;
-        if (r < ri && c < rj && (bi != bj || c <= r))
-          M[(i0 + r) * d + j0 + c] = old[x][y][v] - acc[x][y][v];
-      }
+}
+
+__global__ void chol_flags_kernel(int32_t* f, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) f[i] = 0;
 }
 
 // ---- triangular solves with ticket-ordered block rows
@@ -542,18 +677,20 @@ __global__ void solve_init_kernel(int32_t* flags, double* y, int64_t d, const in
 }  // namespace
 
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
-                     hipStream_t st) {
+                     int32_t* flags, hipStream_t st) {
   const int64_t nblk = cdiv(d, NB);
-  for (int64_t k = 0; k < nblk; ++k) {
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(kBlock), 0, st, M, d, k, Linv_diag,
-                       min_pivot, status);
+  int32_t* sf = flags + 2;  // flags[0..1] are the solves' tickets
+  hipLaunchKernelGGL(chol_flags_kernel, dim3(static_cast<unsigned>(cdiv(nblk, kBlock))),
+                     dim3(kBlock), 0, st, sf, nblk);
+  hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(kBlock), 0, st, M, d, int64_t(0), Linv_diag,
+                     min_pivot, status);
+  if (nblk > 1)
+    hipLaunchKernelGGL(chol_trsm_kernel, dim3(static_cast<unsigned>(nblk - 1)), dim3(kBlock), 0,
+                       st, M, d, int64_t(0), static_cast<const double*>(Linv_diag));
+  for (int64_t k = 0; k + 1 < nblk; ++k) {
     const int64_t below = nblk - k - 1;
-    if (below > 0) {
-      hipLaunchKernelGGL(chol_trsm_kernel, dim3(static_cast<unsigned>(below)), dim3(kBlock), 0, st,
-                         M, d, k, static_cast<const double*>(Linv_diag));
-      hipLaunchKernelGGL(chol_syrk_kernel, dim3(static_cast<unsigned>(below * (below + 1) / 2)),
-                         dim3(kBlock), 0, st, M, d, k);
-    }
+    hipLaunchKernelGGL(chol_step_kernel, dim3(static_cast<unsigned>(below * (below + 1) / 2)),
+                       dim3(kBlock), 0, st, M, d, k, Linv_diag, min_pivot, status, sf);
   }
 }
 

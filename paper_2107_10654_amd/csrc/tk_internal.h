@@ -154,10 +154,11 @@ void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
                           const int32_t* done, hipStream_t st);
 
 // Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag receives the
-// inverses of the nb x nb diagonal blocks; min_pivot one double.
+// inverses of the nb x nb diagonal blocks; min_pivot one double; flags at
+// least 2 + d / nb int32 (the step flags live past the solves' two tickets).
 constexpr int kCholNb = 64;
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
-                     hipStream_t st);
+                     int32_t* flags, hipStream_t st);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
 // scratch of 2 * ceil(d/nb) + 2 words.
 void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,
