@@ -64,7 +64,29 @@ __global__ void sum_splits_kernel(const double* __restrict__ part, int64_t nspli
   out[i] = v;
 }
 
-// Q == 1: out[p][j] = sum_i Mat(j,i) in[p][i]; 64 rows per workgroup, i in chunks of 64.
+// Q == 1: out[p][j] = sum_i Mat(j, i) in[p][i] -- a (P x I) (I x J) product,
+// J <= 64, run on v_mfma_f64_16x16x4: 64 rows per workgroup (a 16-row strip
+// per wave), i in chunks of 32 staged through LDS in FP64 (the input converted
+// exactly) with coalesced 16-byte loads, the next chunk prefetched into
+// registers while the current one is multiplied.
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double ttm_doublex4;
+constexpr int kTlRows = 64, kTlK = 32, kTlLd = kTlK + 1;
+
+template <class T>
+struct TlLoad;
+template <>
+struct TlLoad<float> {  // 64 rows x 32 floats = 512 x 16 bytes: two per thread
+  static constexpr int N = 2;
+  typedef float __attribute__((ext_vector_type(4))) vec;
+  static constexpr int W = 4;
+};
+template <>
+struct TlLoad<double> {  // 64 rows x 32 doubles = 1024 x 16 bytes: four per thread
+  static constexpr int N = 4;
+  typedef double __attribute__((ext_vector_type(2))) vec;
+  static constexpr int W = 2;
+};
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ in, int64_t P,
                                                           int64_t I, const double* __restrict__ M,
@@ -72,47 +94,75 @@ __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ 
                                                           double* __restrict__ out,
                                                           const int32_t* done) {
   if (done && *done) return;
-  __shared__ double Xs[64][65];
-  __shared__ double Ms[64][kMaxRank + 1];
+  using LD = TlLoad<T>;
+  using vec = typename LD::vec;
+  constexpr int W = LD::W, PER_ROW = kTlK / W;
+  __shared__ double Xs[kTlRows * kTlLd];
+  __shared__ double Ws[kMaxRank * kTlLd];  // Ws[j][i]
   const int tid = threadIdx.x;
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 64;
-  const int pr = tid & 63, jq = tid >> 6;  // row, quarter of the outputs
-  constexpr int JPT = kMaxRank / 4;
-  double acc[JPT];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kTlRows;
+  const int jb = static_cast<int>((J + 15) / 16);
+  // vectors of the chunk this thread loads: e = tid + 256 q -> row e / PER_ROW, cols W (e % PER_ROW)
+  vec pf[LD::N];
+  const bool vec_ok = (I % W) == 0;  // whole vectors inside each row
+  auto fetch = [&](int64_t i0) {
 #pragma unroll
-  for (int k = 0; k < JPT; ++k) acc[k] = 0.0;
-  for (int64_t i0 = 0; i0 < I; i0 += 64) {
-    const int ic = static_cast<int>((I - i0) < 64 ? (I - i0) : 64);
-    __syncthreads();
-    // unconditional (clamped) loads so they issue back to back
+    for (int q = 0; q < LD::N; ++q) {
+      const int e = tid + q * kBlock;
+      const int r = e / PER_ROW, c = (e % PER_ROW) * W;
+      const int64_t p = p0 + r < P ? p0 + r : P - 1;
+      const int64_t i = i0 + c;
+      if (vec_ok && i + W <= I) {
+        pf[q] = *reinterpret_cast<const vec*>(in + p * I + i);
+      } else {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = tid + k * kBlock;
-      const int r = e >> 6, c = e & 63;
-      const int64_t p = p0 + r;
-      const int64_t pc = p < P ? p : P - 1;
-      const int64_t cc = c < ic ? i0 + c : i0;
-      const double v = ldd(in, pc * I + cc);
-      Xs[r][c] = (p < P && c < ic) ? v : 0.0;
-    }
-    for (int c = tid >> 2; c < 64; c += kBlock / 4)
-      for (int j = tid & 3; j < J; j += 4) Ms[c][j] = c < ic ? mat(M, I, J, trans, j, i0 + c) : 0.0;
-    __syncthreads();
-    for (int c = 0; c < ic; ++c) {
-      const double x = Xs[pr][c];
-#pragma unroll
-      for (int k = 0; k < JPT; ++k) {
-        const int j = jq + 4 * k;
-        if (j < J) acc[k] = fma(Ms[c][j], x, acc[k]);
+        for (int t = 0; t < W; ++t) pf[q][t] = i + t < I ? in[p * I + i + t] : T(0);
       }
     }
-  }
-  const int64_t p = p0 + pr;
-  if (p < P) {
+  };
+  auto commit = [&]() {
 #pragma unroll
-    for (int k = 0; k < JPT; ++k) {
-      const int j = jq + 4 * k;
-      if (j < J) out[p * J + j] = acc[k];
+    for (int q = 0; q < LD::N; ++q) {
+      const int e = tid + q * kBlock;
+      const int r = e / PER_ROW, c = (e % PER_ROW) * W;
+#pragma unroll
+      for (int t = 0; t < W; ++t) Xs[r * kTlLd + c + t] = static_cast<double>(pf[q][t]);
+    }
+  };
+  ttm_doublex4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = ttm_doublex4{0, 0, 0, 0};
+  fetch(0);
+  for (int64_t i0 = 0; i0 < I; i0 += kTlK) {
+    __syncthreads();  // the previous chunk's LDS reads are done
+    commit();
+    for (int e = tid; e < jb * 16 * kTlK; e += kBlock) {
+      const int j = e / kTlK, c = e % kTlK;
+      const int64_t i = i0 + c;
+      Ws[j * kTlLd + c] = (j < J && i < I) ? mat(M, I, J, trans, j, i) : 0.0;
+    }
+    __syncthreads();
+    if (i0 + kTlK < I) fetch(i0 + kTlK);
+#pragma unroll 2
+    for (int kk = 0; kk < kTlK; kk += 4) {
+      const double av = Xs[(wave * 16 + lane % 16) * kTlLd + kk + lane / 16];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (cb < jb)
+          acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              av, Ws[(cb * 16 + lane % 16) * kTlLd + kk + lane / 16], acc[cb], 0, 0, 0);
+    }
+  }
+  // accumulator register v of lane l: row l / 16 + 4 v, column l % 16 of the 16 x 16 block
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    if (cb >= jb) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t p = p0 + wave * 16 + lane / 16 + 4 * v;
+      const int64_t j = cb * 16 + lane % 16;
+      if (p < P && j < J) out[p * J + j] = acc[cb][v];
     }
   }
 }

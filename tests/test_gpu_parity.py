@@ -175,6 +175,20 @@ def test_exact_core_masked_matches_oracle(tk, dims, ranks, dtype):
     assert rel(G.cpu().numpy(), ref) <= (1e-8 if dtype == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("dims,ranks,dtype", [
+    ((129, 130, 37), (4, 5, 6), "f64"),   # >= 16384 rows per last-mode fibre: MFMA contraction,
+    ((130, 128, 64), (6, 3, 16), "f32"),  # ragged (37) and vector-aligned (64) fibre lengths
+    ((128, 129, 33), (2, 2, 33), "f64"),  # last rank above 16 (three 16-wide output blocks)
+])
+def test_exact_core_long_fibres_matches_oracle(tk, dims, ranks, dtype):
+    p, F = _sketch_case(dims, ranks, 12, dtype=dtype)
+    lam = 1e-3
+    G = tk.core_update_exact(T(p["X"]), [T(A) for A in F], lam)
+    ref = oracle.core_update_exact(p["X"].astype(np.float64), [A.astype(np.float64) for A in F],
+                                   lam)
+    assert rel(G.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-6)
+
+
 def test_exact_core_all_observed_mask_equals_unmasked(tk):
     p, F = _sketch_case((19, 17, 15), (3, 4, 5), 11)
     X, FF = T(p["X"]), [T(A) for A in F]
