@@ -36,6 +36,9 @@ WORKLOADS = {
     "c1": "64x64x64 f64 Tucker tensor, rank 4x4x4 (d=64), lambda=1e-3, 2048 samples",
     "c3": "128x128x128x128 f32 Tucker tensor, rank 8x8x8x8 (d=4096), 10% entries missing, "
           "lambda=1e-3, 65536 samples per core update",
+    "t1": "1024x1024x1024 f32 tensor of the Sec. 5 synthetic protocol (true core 8x8x8, U[0,1] "
+          "core and factors, N(0,1) noise on 1% of entries), fitted at rank 4x4x4 (d=64) from a "
+          "U[0,1] initial state, lambda=1e-3, 1687583 samples (Alg. 1 count, eps=delta=0.1)",
     "c4": "batch of 64 order-3 f32 Tucker tensors, sides U{32..384}, ranks U{4..24}, 1% noise, "
           "lambda=1e-3, 16*prod(ranks) samples each; one persistent batched Gram launch, "
           "autotuned tiles, replayed as a HIP graph",
@@ -103,7 +106,7 @@ def read_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(prob, lam, s, s_cpu, seed, mask=None):
+def cpu_baseline(prob, F, lam, s, s_cpu, seed, mask=None):
     """The FP64 oracle on the host cores, on a bounded sample of the workload."""
     import numpy as np
     import oracle
@@ -113,7 +116,7 @@ def cpu_baseline(prob, lam, s, s_cpu, seed, mask=None):
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
     X = prob["X"]
-    F = [np.asarray(A, dtype=np.float64) for A in prob["factors_true"]]
+    F = [np.asarray(A, dtype=np.float64) for A in F]
     t0 = time.perf_counter()
     tables = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F]
     t1 = time.perf_counter()
@@ -178,8 +181,8 @@ def main():
     lam, s = cfg["lam"], cfg["samples"]
     np_dt = workloads.NP_DTYPES[cfg["dtype"]]
     X = torch.from_numpy(prob["X"]).to(dev)
-    F = [torch.from_numpy(np.ascontiguousarray(A.astype(np_dt))).to(dev)
-         for A in prob["factors_true"]]
+    F_host = prob.get("factors_fit", prob["factors_true"])
+    F = [torch.from_numpy(np.ascontiguousarray(A.astype(np_dt))).to(dev) for A in F_host]
     mask = (torch.from_numpy(prob["mask"].view(np.int32)).to(dev)
             if prob.get("mask") is not None else None)
     torch.cuda.synchronize()
@@ -303,7 +306,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_samples} samples ...")
-        cpu = cpu_baseline(prob, lam, s, min(args.cpu_samples, s), cfg["seed"], prob.get("mask"))
+        cpu = cpu_baseline(prob, [A.astype(np_dt) for A in F_host], lam, s,
+                           min(args.cpu_samples, s), cfg["seed"], prob.get("mask"))
         log(f"[bench] CPU oracle: {cpu['value']:.4g} updates/s on {cpu['cores']} threads")
 
     out = {

@@ -538,6 +538,9 @@ struct SketchRun {
   hipStream_t st = nullptr;
   const tk_sketch_opts* o = nullptr;
   Carver carver{nullptr};
+  // the FP64 sample rows are read by the FP64 Gram, the large-d vector passes
+  // and the adjoint; the small-d passes read the factor tables instead
+  bool want_rows64 = true;
   void stage(int k) const {
     if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
   }
@@ -592,7 +595,8 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   // 3. sampled entries (x_t, mask) and effective weights; sample rows
   launch_gather(g, p->X, p->dtype, p->mask, R.idx, R.weight, R.s, w.weff, w.xw, w.missing,
                 R.status, st);
-  launch_pregather(g, R.idx, w.weff, R.s, w.lev.Q64, w.rows64, w.rows32, st);
+  launch_pregather(g, R.idx, w.weff, R.s, w.lev.Q64, R.want_rows64 ? w.rows64 : nullptr, w.rows32,
+                   st);
   R.stage(3);
   return TK_OK;
 }
@@ -602,7 +606,11 @@ void sketch_factor(SketchRun& R) {
   const Geom& g = R.g;
   SketchWS& w = R.w;
   // 5. right-hand side sum_t w_t x_t q_t (FP64)
-  launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
+  if (resid_small_ok(g))
+    launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
+                       R.st);
+  else
+    launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
   // 6. FP64 Cholesky
   launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st);
@@ -641,8 +649,12 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   const bool refine = R.o->gram_precision != TK_F64;
   const int iters = refine ? R.o->refine_max : 0;
   for (int k = 0; k <= iters; ++k) {
-    launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
-    launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
+    if (resid_small_ok(g)) {
+      launch_resid_small(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
+    } else {
+      launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
+      launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
+    }
     launch_copy_f64(g.d, h, w.ph_a, st);
     const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st, w.done);
     launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
@@ -668,6 +680,7 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_gram(R.g, s, o->gram_precision, 0);
+  R.want_rows64 = !resid_small_ok(R.g) || o->gram_precision == TK_F64;
   carve_sketch(c, R.g, s, R.pl, R.w, with_partials);
   R.status = dev_status ? dev_status : R.w.status;
   return TK_OK;
@@ -784,6 +797,7 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
     if (!factor_bar[n]) return TK_E_ARG;
   SketchRun R;
   stt = sketch_begin(R, p, o, dev_status, ws, ws_bytes, stream, TK_CALL_ADJOINT);
+  R.want_rows64 = true;  // the adjoint's per-sample coefficients read the FP64 rows
   if (stt != TK_OK) return stt;
   AdjWS a;
   carve_adjoint(R.carver, R.g, R.s, a);

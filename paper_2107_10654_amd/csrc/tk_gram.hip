@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t
     v = Q64[g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n] + (j - g.soff[n])];
     v32 = static_cast<float>(n == 0 ? v * sqrt(weff[t]) : v);
   }
-  rows64[e] = v;
+  if (rows64) rows64[e] = v;
   rows32[e] = v32;
 }
 
@@ -583,6 +583,221 @@ __global__ __launch_bounds__(kBlock) void dot_finish_kernel(const double* __rest
   c[t] = (a ? a[t] : 0.0) - b[t] * u;
 }
 
+// ---- small Kronecker dimension: d <= kSmD and sum_r <= kSmSumR.
+// part[wg][r] = sum_{t in wg} c_t k_t[r], c_t = a_t - b_t (k_t . h) (the a term
+// absent when a is null, the dot when h is null), read straight from the
+// sample indices and the whitened factor tables Q64 in one pass.  Per chunk of
+// 256 samples: the chunk's indices are staged in LDS, then all threads load
+// the chunk's factor rows (sample k, row position j) with several loads in
+// flight; one thread per sample forms c_t (k_t . h through the last mode's
+// inner products, h in LDS, the other modes' offsets from a per-base table);
+// then one thread per Kronecker index r (and sample group when d < 256)
+// accumulates c_t prod_n q^(n)_t[r_n].  Groups are added in a fixed order.
+constexpr int kSmD = 256, kSmSumR = 20, kSmChunk = 256;
+
+struct SmallLds {  // byte offsets of the dynamic LDS regions
+  int rows, coef, hs, red, idx, offb, posq, posr;
+  int bytes;
+};
+
+__host__ __device__ inline SmallLds small_lds(int sum_r) {
+  SmallLds L;
+  const int ld = sum_r | 1;
+  L.rows = 0;
+  L.coef = L.rows + 8 * kSmChunk * ld;
+  L.hs = L.coef + 8 * kSmChunk;
+  L.red = L.hs + 8 * kSmD;
+  L.posq = L.red + 8 * kBlock;                 // int64 per row position: qoff[n] - r... base
+  L.idx = L.posq + 8 * kSmSumR;                // int32 [kMaxOrder][kSmChunk]
+  L.posr = L.idx + 4 * kMaxOrder * kSmChunk;   // int32 per row position: mode n | R_n << 8 | r << 16
+  L.offb = L.posr + 4 * kSmSumR;               // uint8 [kSmD][kMaxOrder]
+  L.bytes = L.offb + kSmD * kMaxOrder;
+  return L;
+}
+
+template <int N>  // tensor order: every loop over modes has a static bound
+__global__ __launch_bounds__(kBlock) void resid_small_kernel(
+    Geom g, const int32_t* __restrict__ idx, const double* __restrict__ Q64,
+    const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ h,
+    int64_t s, int64_t cpw, double* __restrict__ part, const int32_t* done) {
+  if (done && *done) return;
+  extern __shared__ __align__(16) char sm_small[];
+  const int d = static_cast<int>(g.d), SR = g.sum_r;
+  const int RL = g.ranks[N - 1], sl = g.soff[N - 1];
+  const int ld = SR | 1;
+  const SmallLds L = small_lds(SR);
+  double* rowsL = reinterpret_cast<double*>(sm_small + L.rows);
+  double* coefL = reinterpret_cast<double*>(sm_small + L.coef);
+  double* hs = reinterpret_cast<double*>(sm_small + L.hs);
+  double* red = reinterpret_cast<double*>(sm_small + L.red);
+  int64_t* posq = reinterpret_cast<int64_t*>(sm_small + L.posq);
+  int32_t* idxL = reinterpret_cast<int32_t*>(sm_small + L.idx);
+  int32_t* posr = reinterpret_cast<int32_t*>(sm_small + L.posr);
+  uint8_t* offb = reinterpret_cast<uint8_t*>(sm_small + L.offb);
+  const int tid = threadIdx.x;
+  // ---- per-workgroup tables
+  if (h)
+    for (int e = tid; e < d; e += kBlock) hs[e] = h[e];
+  if (tid < SR) {
+    int n = 0;
+#pragma unroll
+    for (int m = 1; m < N; ++m)
+      if (g.soff[m] <= tid) n = m;
+    int64_t qo = 0;
+    int R = 1, so = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+      if (m == n) {
+        qo = g.qoff[m];
+        R = g.ranks[m];
+        so = g.soff[m];
+      }
+    posq[tid] = qo + (tid - so);
+    posr[tid] = n | (R << 8);
+  }
+  const int nb = d / RL;  // bases of the last mode: offsets of modes 0 .. N-2
+  for (int base = tid; base < nb; base += kBlock) {
+    int q = base;
+#pragma unroll
+    for (int n = N - 2; n >= 0; --n) {
+      const int R = g.ranks[n];
+      offb[base * kMaxOrder + n] = static_cast<uint8_t>(g.soff[n] + q % R);
+      q /= R;
+    }
+  }
+  // phase-2 role: Kronecker index rr of sample group grp
+  const int ngrp = kBlock / d;
+  const int rr = tid % d, grp = tid / d;
+  int offs[N];
+  {
+    int q = rr;
+#pragma unroll
+    for (int n = N - 1; n >= 0; --n) {
+      const int R = g.ranks[n];
+      offs[n] = g.soff[n] + q % R;
+      q /= R;
+    }
+  }
+  double acc = 0.0;
+  const int64_t nch = (s + kSmChunk - 1) / kSmChunk;
+  const int64_t ca = static_cast<int64_t>(blockIdx.x) * cpw;
+  const int64_t cb = ca + cpw < nch ? ca + cpw : nch;
+  // this thread's sample of a chunk: indices and coefficients, loaded one chunk ahead
+  int32_t iv[N];
+  double av = 0.0, bv = 0.0;
+  auto fetch = [&](int64_t ch) {
+    const int64_t t = ch * kSmChunk + tid;
+    const int64_t tc = t < s ? t : s - 1;
+#pragma unroll
+    for (int n = 0; n < N; ++n) iv[n] = idx[n * s + tc];
+    av = a ? a[tc] : 0.0;
+    bv = (b && h) ? b[tc] : 0.0;
+  };
+  fetch(ca);
+  for (int64_t ch = ca; ch < cb; ++ch) {
+    const bool valid = ch * kSmChunk + tid < s;
+    __syncthreads();  // the previous chunk's LDS reads are done; tables are ready
+#pragma unroll
+    for (int n = 0; n < N; ++n) idxL[n * kSmChunk + tid] = iv[n];
+    const double a_t = av, b_t = bv;
+    __syncthreads();
+    if (ch + 1 < cb) fetch(ch + 1);
+    // the chunk's factor rows: item e = (sample e / SR, position e % SR), all
+    // loads issued together (positions past SR repeat the last one, unstored)
+    {
+      double v[kSmSumR];
+      int dst[kSmSumR];
+#pragma unroll
+      for (int m = 0; m < kSmSumR; ++m) {
+        const int mc = m < SR ? m : SR - 1;
+        const int e = tid + kBlock * mc;
+        const int k = e / SR, j = e - k * SR;
+        const int pr = posr[j];
+        v[m] = Q64[posq[j] + static_cast<int64_t>(idxL[(pr & 0xff) * kSmChunk + k]) * (pr >> 8)];
+        dst[m] = k * ld + j;
+      }
+#pragma unroll
+      for (int m = 0; m < kSmSumR; ++m)
+        if (m < SR) rowsL[dst[m]] = v[m];
+    }
+    __syncthreads();
+    double c = a_t;
+    if (h) {
+      const double* me = rowsL + tid * ld;
+      double u = 0.0;
+#pragma unroll 2
+      for (int base = 0; base < nb; ++base) {
+        double pr = 1.0;
+#pragma unroll
+        for (int n = 0; n < N - 1; ++n) pr *= me[offb[base * kMaxOrder + n]];
+        double in0 = 0.0, in1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= RL; k += 2) {
+          in0 = fma(me[sl + k], hs[base * RL + k], in0);
+          in1 = fma(me[sl + k + 1], hs[base * RL + k + 1], in1);
+        }
+        if (k < RL) in0 = fma(me[sl + k], hs[base * RL + k], in0);
+        u = fma(pr, in0 + in1, u);
+      }
+      c = fma(-b_t, u, c);
+    }
+    coefL[tid] = valid ? c : 0.0;
+    __syncthreads();
+    if (grp < ngrp) {
+#pragma unroll 4
+      for (int k = grp; k < kSmChunk; k += ngrp) {
+        const double* row = rowsL + k * ld;
+        double v = coefL[k];
+#pragma unroll
+        for (int n = 0; n < N; ++n) v *= row[offs[n]];
+        acc += v;
+      }
+    }
+  }
+  __syncthreads();
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < d) {
+    double v = 0.0;
+    for (int k = 0; k < ngrp; ++k) v += red[k * d + tid];
+    part[static_cast<int64_t>(blockIdx.x) * d + tid] = v;
+  }
+}
+
+// out[i] = sum_k part[k][i] for many parts: 64 outputs per workgroup of 16
+// waves, wave w adds a contiguous sixteenth of the parts eight at a time, the
+// waves' sums are added in wave order.
+constexpr int kSpWaves = 16;
+
+__global__ __launch_bounds__(64 * kSpWaves) void sum_parts_wide_kernel(
+    const double* __restrict__ part, int64_t nparts, int64_t n, double* __restrict__ out,
+    const int32_t* done) {
+  if (done && *done) return;
+  __shared__ double red[kSpWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const int64_t ic = i < n ? i : n - 1;
+  const int64_t ka = (nparts * wave) / kSpWaves, kb = (nparts * (wave + 1)) / kSpWaves;
+  double v = 0.0;
+  int64_t k = ka;
+  for (; k + 8 <= kb; k += 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = part[(k + u) * n + ic];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
+  }
+  for (; k < kb; ++k) v += part[k * n + ic];
+  red[wave][lane] = v;
+  __syncthreads();
+  if (wave == 0 && i < n) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSpWaves; ++w) sum += red[w][lane];
+    out[i] = sum;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -697,12 +912,57 @@ VecPlan plan_vec(const Geom& g, int64_t s) {
   vp.nsplit = cdiv(nch, vp.cps);
   return vp;
 }
+
+struct SmallPlan {
+  int64_t nwg;  // workgroups
+  int64_t cpw;  // 256-sample chunks per workgroup
+};
+
+SmallPlan plan_small(int64_t s) {
+  SmallPlan sp;
+  const int64_t nch = cdiv(s, kSmChunk);
+  const int64_t want = nch < 1024 ? nch : 1024;
+  sp.cpw = cdiv(nch, want < 1 ? 1 : want);
+  sp.nwg = cdiv(nch, sp.cpw);
+  return sp;
+}
 }  // namespace
+
+bool resid_small_ok(const Geom& g) { return g.d <= kSmD && g.sum_r <= kSmSumR; }
 
 int64_t vec_part_doubles(const Geom& g, int64_t s) {
   const VecPlan vp = plan_vec(g, s);
-  const int64_t a = vp.nsplit * g.d, b = vp.nr * s;
-  return a > b ? a : b;
+  int64_t n = vp.nsplit * g.d;
+  if (vp.nr * s > n) n = vp.nr * s;
+  if (resid_small_ok(g) && plan_small(s).nwg * g.d > n) n = plan_small(s).nwg * g.d;
+  return n;
+}
+
+void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
+                        const double* b, const double* h, int64_t s, double* part, double* out,
+                        const int32_t* done, hipStream_t st) {
+  const SmallPlan sp = plan_small(s);
+  const size_t lds = static_cast<size_t>(small_lds(g.sum_r).bytes);
+  const dim3 grid(static_cast<unsigned>(sp.nwg));
+#define TK_RS_CASE(NN)                                                                           \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL(resid_small_kernel<NN>, grid, dim3(kBlock), lds, st, g, idx, Q64, a, b, h, \
+                       s, sp.cpw, part, done);                                                    \
+    break;
+  switch (g.order) {
+    TK_RS_CASE(1)
+    TK_RS_CASE(2)
+    TK_RS_CASE(3)
+    TK_RS_CASE(4)
+    TK_RS_CASE(5)
+    TK_RS_CASE(6)
+    TK_RS_CASE(7)
+    TK_RS_CASE(8)
+  }
+#undef TK_RS_CASE
+  hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(static_cast<unsigned>(cdiv(g.d, 64))),
+                     dim3(64 * kSpWaves), 0, st, static_cast<const double*>(part), sp.nwg, g.d,
+                     out, done);
 }
 
 void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,

@@ -389,6 +389,78 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
   M[i * d + j] = fma(lambda, p, v);
 }
 
+// Smallest w with sk_unit_start(w) >= u (grid when there is none).
+__device__ inline int64_t sk_first_wg_at(int64_t u, int64_t units, int64_t grid) {
+  int64_t w = (u * grid) / units;
+  if (w > grid) w = grid;
+  while (w > 0 && sk_unit_start(w - 1, units, grid) >= u) --w;
+  while (w < grid && sk_unit_start(w, units, grid) < u) ++w;
+  return w;
+}
+
+// The same sum when a tile collects many slots (few tiles, many workgroups):
+// a workgroup of 16 waves takes 64 consecutive j of row i, each wave sums a
+// contiguous sixteenth of the tile's contributing workgroups eight slots at a
+// time, and the waves' sums are added in wave order (deterministic).
+constexpr int kAsmWaves = 16;
+
+template <int T>
+__global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_split_kernel(
+    Geom g, int64_t units, int64_t grid, int64_t unit0, int64_t tile0, int64_t nchunks,
+    const float* __restrict__ slots, const int64_t* __restrict__ index,
+    const double* __restrict__ P, double lambda, double* __restrict__ M) {
+  __shared__ double red[kAsmWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t d = g.d;
+  const int64_t i = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool act = j <= i;
+  const int64_t jc = act ? j : i;  // lanes past the diagonal stay inside row i's tile
+  const int64_t ti = i / T, tj = jc / T;
+  const int64_t tau = ti * (ti + 1) / 2 + tj;
+  const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;
+  const int64_t wlo = sk_first_wg_at(ua + 1, units, grid) - 1;
+  const int64_t wend = sk_first_wg_at(ub, units, grid);
+  const int64_t n = wend - wlo;
+  const int64_t wa = wlo + (n * wave) / kAsmWaves, wb = wlo + (n * (wave + 1)) / kAsmWaves;
+  const int64_t off = (i - ti * T) * T + (jc - tj * T);
+  constexpr int64_t TT = static_cast<int64_t>(T) * T;
+  double v = 0.0;
+  int64_t w = wa;
+  for (; w + 8 <= wb; w += 8) {
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t first = index[grid + w + k];
+      const int64_t slot = first >= 0 ? index[w + k] + (tile0 + tau - first) : 0;
+      const float y = slots[slot * TT + off];
+      x[k] = first >= 0 ? y : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += static_cast<double>(x[k]);
+  }
+  for (; w < wb; ++w) {
+    const int64_t first = index[grid + w];
+    if (first < 0) continue;
+    v += static_cast<double>(slots[(index[w] + (tile0 + tau - first)) * TT + off]);
+  }
+  red[wave][lane] = v;
+  __syncthreads();
+  if (wave != 0 || !act) return;
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kAsmWaves; ++k) sum += red[k][lane];
+  double p = 1.0;
+  int64_t a = i, b = j;
+  for (int nn = g.order - 1; nn >= 0; --nn) {
+    const int R = g.ranks[nn];
+    p *= P[g.roff[nn] + (a % R) * R + (b % R)];
+    a /= R;
+    b /= R;
+  }
+  M[i * d + j] = fma(lambda, p, sum);
+}
+
 template <class V, int T>
 void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
   using Pf = SkPf<SkTile<T>::THREADS>;
@@ -425,6 +497,8 @@ SkConfig sk_default_config(int64_t d) {
   // the 256 tile halves the row formation per MFMA once there are enough
   // tiles to spread over the CUs
   if (d >= TK_SK_BIG_TILE_D) return SkConfig{256, SkTile<256>::WG_PER_CU};
+  // a single 64 tile covers the whole Gram: no padding rows
+  if (d <= 64) return SkConfig{64, SkTile<64>::WG_PER_CU};
   return SkConfig{128, SkTile<128>::WG_PER_CU};
 }
 
@@ -498,9 +572,24 @@ void launch_gram_sk(const SkBatch& b, float* slots, int64_t* index, hipStream_t 
 void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slots,
                         const int64_t* index, const double* P, double lambda, double* M,
                         hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
   const SkProb& q = b.p[k];
   const int64_t nch = row_chunks(q.s);
+  if (b.grid >= 8 * b.tiles) {
+    // many slots per tile: split each element's sum over 16 waves
+    const dim3 grid(static_cast<unsigned>(cdiv(g.d, 64)), static_cast<unsigned>(g.d));
+    const dim3 block(64 * kAsmWaves);
+    if (b.tile == 256)
+      hipLaunchKernelGGL(assemble_sk_split_kernel<256>, grid, block, 0, st, g, b.units, b.grid,
+                         q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+    else if (b.tile == 128)
+      hipLaunchKernelGGL(assemble_sk_split_kernel<128>, grid, block, 0, st, g, b.units, b.grid,
+                         q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+    else
+      hipLaunchKernelGGL(assemble_sk_split_kernel<64>, grid, block, 0, st, g, b.units, b.grid,
+                         q.unit0, q.tile0, nch, slots, index, P, lambda, M);
+    return;
+  }
+  const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
   if (b.tile == 256)
     hipLaunchKernelGGL(assemble_sk_kernel<256>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
                        q.unit0, q.tile0, nch, slots, index, P, lambda, M);

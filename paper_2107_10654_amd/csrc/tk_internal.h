@@ -66,6 +66,15 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
                      uint64_t* cdf, double* L, double* Linv, double* P, double* Q64, float* Q32,
                      int32_t* status, hipStream_t st);
 
+// Rows times a per-mode R_n x R_n FP64 matrix M (at geom.roff):
+// out[i][c] = sum_k A(n)[i][k] M[k][c], or M transposed when trans != 0; out64
+// (and out32 unless null) at geom.qoff.  With weights != null also the row
+// scores ||out[i]||^2 (into scores unless null) and their integer weights, both
+// at geom.off.
+void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, const double* M,
+                      int trans, double* out64, float* out32, double* scores, uint64_t* weights,
+                      hipStream_t st);
+
 // Sampler (tk_sample.hip).
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st);
@@ -148,6 +157,14 @@ void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, co
 int64_t vec_part_doubles(const Geom& g, int64_t s);
 void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,
                        double* part, double* out, const int32_t* done, hipStream_t st);
+// Small Kronecker dimension (resid_small_ok): out = sum_t c_t q_t with
+// c_t = a_t - b_t (q_t . h) (a term absent when a is null, dot when h is null),
+// from the sample indices and the whitened factor tables in one pass; part:
+// vec_part_doubles.
+bool resid_small_ok(const Geom& g);
+void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
+                        const double* b, const double* h, int64_t s, double* part, double* out,
+                        const int32_t* done, hipStream_t st);
 // Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part: vec_part_doubles.
 void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
                           const double* weff, const double* h, int64_t s, double* part, double* c,

@@ -7,7 +7,11 @@
 // whose columns are orthonormal.  The per-mode CDF of the proof of Thm 4.2
 // is kept as integers: w_i = ceil(max(l_i, 0) 2^Q) and its inclusive prefix sum.
 //
-// One workgroup per mode: the mode's work is O(I_n R_n^2) and latency bound.
+// Three launches: one workgroup per mode forms C_n, L, L^{-1} and P (O(I_n R_n^2)
+// work, latency bound); a rows kernel with many workgroups stages blocks of
+// factor rows in LDS and multiplies them by L^{-T} (the same kernel forms
+// A(n) V_n for the exact update); one workgroup per mode then scans the
+// integer weights.
 #include "tk_internal.h"
 
 namespace tk {
@@ -22,12 +26,30 @@ __device__ inline double ld(const T* a, int64_t i) {
   return static_cast<double>(a[i]);
 }
 
+// buf[e] = src[e] for e < n (FP64), eight loads in flight per thread (indices
+// clamped into range so that the loads issue together)
+template <class T>
+__device__ inline void stage_rows(const T* src, int64_t n, double* buf) {
+  for (int64_t e0 = threadIdx.x; e0 < n; e0 += 8 * kBlock) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * kBlock;
+      v[k] = ld(src, e < n ? e : n - 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t e = e0 + k * kBlock;
+      if (e < n) buf[e] = v[k];
+    }
+  }
+}
+
 // LDS budget: two R x R FP64 buffers (64 KB at R = 64).
 template <class T>
-__global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp, double* scores,
-                                                          uint64_t* cdf, double* Lg,
-                                                          double* Linvg, double* Pg, double* Q64,
-                                                          float* Q32, int32_t* status) {
+__global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp, double* Lg,
+                                                          double* Linvg, double* Pg,
+                                                          int32_t* status) {
   __shared__ double bufC[kMaxRank * kMaxRank];  // C, then L (lower) in place
   __shared__ double bufA[kMaxRank * kMaxRank];  // row chunks of A, then L^{-1}
   __shared__ int bad;
@@ -40,8 +62,15 @@ __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp,
   const T* A = static_cast<const T*>(fp.p[n]);
   const int E = R * (R + 1) / 2;
 
-  // ---- C = A^T A (lower triangle, FP64), rows streamed through LDS
+  // ---- C = A^T A (lower triangle, FP64), rows streamed through LDS.  With
+  // E <= 256 entries, thread (e, grp) takes entry e over the rows i = grp mod
+  // G (G = 256 / E groups) and the groups are added in order at the end;
+  // otherwise each thread takes entries tid, tid + 256, ... over all rows.
   constexpr int kMaxPer = (kMaxRank * (kMaxRank + 1) / 2 + kBlock - 1) / kBlock;
+  const bool grouped = E <= kBlock;
+  const int G = grouped ? kBlock / E : 1;
+  const int grp = grouped ? tid / E : 0;
+  const int e0 = grouped ? tid % E : tid;
   double acc[kMaxPer];
 #pragma unroll
   for (int k = 0; k < kMaxPer; ++k) acc[k] = 0.0;
@@ -49,28 +78,44 @@ __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp,
   for (int64_t r0 = 0; r0 < I; r0 += chunk_rows) {
     const int64_t rows = (I - r0 < chunk_rows) ? (I - r0) : chunk_rows;
     __syncthreads();
-    for (int64_t e = tid; e < rows * R; e += kBlock) bufA[e] = ld(A, r0 * R + e);
+    stage_rows(A + r0 * R, rows * R, bufA);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kMaxPer; ++k) {
-      const int e = tid + k * kBlock;
-      if (e < E) {
+      const int e = e0 + k * kBlock;
+      if (e < E && grp < G && (k == 0 || !grouped)) {
         // e -> (a, b), b <= a
         int a = static_cast<int>((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
         while ((a + 1) * (a + 2) / 2 <= e) ++a;
         while (a * (a + 1) / 2 > e) --a;
         const int b = e - a * (a + 1) / 2;
-        double s = acc[k];
-        for (int64_t i = 0; i < rows; ++i) s = fma(bufA[i * R + a], bufA[i * R + b], s);
-        acc[k] = s;
+        double s0 = 0.0, s1 = 0.0;
+        int64_t i = grp;
+        for (; i + G < rows; i += 2 * G) {
+          s0 = fma(bufA[i * R + a], bufA[i * R + b], s0);
+          s1 = fma(bufA[(i + G) * R + a], bufA[(i + G) * R + b], s1);
+        }
+        if (i < rows) s0 = fma(bufA[i * R + a], bufA[i * R + b], s0);
+        acc[k] += s0 + s1;
       }
     }
   }
   __syncthreads();
+  if (grouped) {
+    // groups in order: bufA[grp][e] -> thread e
+    bufA[tid] = (grp < G) ? acc[0] : 0.0;
+    __syncthreads();
+    if (tid < E) {
+      double v = 0.0;
+      for (int k = 0; k < G; ++k) v += bufA[k * E + tid];
+      acc[0] = v;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int k = 0; k < kMaxPer; ++k) {
     const int e = tid + k * kBlock;
-    if (e < E) {
+    if (e < E && (k == 0 || !grouped)) {
       int a = static_cast<int>((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
       while ((a + 1) * (a + 2) / 2 <= e) ++a;
       while (a * (a + 1) / 2 > e) --a;
@@ -138,48 +183,95 @@ __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp,
     P[e] = s;
   }
 
-  // ---- whitened rows, scores, integer weights (one wave per row, lane = column)
-  double* sc = scores ? scores + g.off[n] : nullptr;
-  uint64_t* cd = cdf + g.off[n];
-  double* q64 = Q64 + g.qoff[n];
-  float* q32 = Q32 + g.qoff[n];
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int64_t i = wave; i < I; i += kBlock / 64) {
-    double q = 0.0;
-    if (lane < R) {
-      for (int k = 0; k <= lane; ++k) q = fma(bufA[lane * R + k], ld(A, i * R + k), q);
-      q64[i * R + lane] = q;
-      q32[i * R + lane] = static_cast<float>(q);
-    }
-    double l = q * q;
-    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
-    if (lane == 0) {
-      if (sc) sc[i] = l;
-      const double lc = l > 0.0 ? l : 0.0;
-      cd[i] = static_cast<uint64_t>(ceil(lc * static_cast<double>(1ull << TK_Q_BITS)));
-    }
-  }
-  __syncthreads();
+  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_RANK_DEFICIENT));
+}
 
-  // ---- inclusive prefix sum of the weights (integer, order independent)
-  uint64_t* sbuf = reinterpret_cast<uint64_t*>(bufC);  // L already stored
+// Rows times a per-mode R x R matrix: out[i][c] = sum_k A(n)[i][k] M[k][c], with
+// M row major at Mg + roff[n] (trans = 0) or M[k][c] = Mg[roff[n] + c R + k]
+// (trans = 1).  kModeRows rows per workgroup, staged in LDS with a padded
+// stride; workgroups walk the modes in order.  With `weights`, also the row
+// score l_i = ||out[i]||^2 and the integer weight ceil(max(l_i, 0) 2^Q).
+constexpr int kModeRows = 16;
+
+__host__ __device__ inline int64_t mode_row_blocks(int64_t I) {
+  return (I + kModeRows - 1) / kModeRows;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void mode_rows_kernel(Geom g, FactorPtrs fp, const double* Mg,
+                                                           int trans, double* out64, float* out32,
+                                                           double* scores, uint64_t* weights) {
+  __shared__ double Ms[kMaxRank * kMaxRank];
+  __shared__ double As[kModeRows * (kMaxRank + 1)];
+  __shared__ double Ss[kModeRows * (kMaxRank + 1)];
+  const int tid = threadIdx.x;
+  int n = 0;
+  int64_t b = blockIdx.x;
+  for (; n < g.order; ++n) {
+    const int64_t nb = mode_row_blocks(g.dims[n]);
+    if (b < nb) break;
+    b -= nb;
+  }
+  if (n >= g.order) return;  // uniform over the workgroup
+  const int R = g.ranks[n];
+  const int Rp = R + 1;
+  const int64_t r0 = b * kModeRows;
+  const int rows = static_cast<int>(g.dims[n] - r0 < kModeRows ? g.dims[n] - r0 : kModeRows);
+  const T* A = static_cast<const T*>(fp.p[n]) + r0 * R;
+  const double* M = Mg + g.roff[n];
+  for (int e = tid; e < R * R; e += kBlock) {
+    const int u = e / R, v = e % R;
+    Ms[trans ? v * R + u : e] = M[e];
+  }
+  for (int e = tid; e < rows * R; e += kBlock) As[(e / R) * Rp + e % R] = ld(A, e);
+  __syncthreads();
+  double* o64 = out64 + g.qoff[n] + r0 * R;
+  float* o32 = out32 ? out32 + g.qoff[n] + r0 * R : nullptr;
+  for (int e = tid; e < rows * R; e += kBlock) {
+    const int i = e / R, c = e % R;
+    double s = 0.0;
+    for (int k = 0; k < R; ++k) s = fma(As[i * Rp + k], Ms[k * R + c], s);
+    o64[e] = s;
+    if (o32) o32[e] = static_cast<float>(s);
+    Ss[i * Rp + c] = s * s;
+  }
+  if (!weights) return;
+  __syncthreads();
+  if (tid < rows) {
+    double l = 0.0;
+    for (int c = 0; c < R; ++c) l += Ss[tid * Rp + c];
+    if (scores) scores[g.off[n] + r0 + tid] = l;
+    const double lc = l > 0.0 ? l : 0.0;
+    weights[g.off[n] + r0 + tid] =
+        static_cast<uint64_t>(ceil(lc * static_cast<double>(1ull << TK_Q_BITS)));
+  }
+}
+
+// Inclusive prefix sum of each mode's integer weights (order independent:
+// integer adds), one workgroup per mode: per 256-entry block a wave scan by
+// shuffles, then the wave totals.
+__global__ __launch_bounds__(kBlock) void weight_scan_kernel(Geom g, uint64_t* cdf) {
+  __shared__ uint64_t wsum[kBlock / 64];
+  const int n = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t I = g.dims[n];
+  uint64_t* cd = cdf + g.off[n];
   uint64_t carry = 0;
   for (int64_t base = 0; base < I; base += kBlock) {
     const int64_t i = base + tid;
     uint64_t v = (i < I) ? cd[i] : 0;
-    sbuf[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-      uint64_t add = (tid >= off) ? sbuf[tid - off] : 0;
-      __syncthreads();
-      sbuf[tid] += add;
-      __syncthreads();
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
     }
-    if (i < I) cd[i] = sbuf[tid] + carry;
-    carry += sbuf[kBlock - 1];
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    uint64_t before = carry;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (i < I) cd[i] = v + before;
+    for (int w = 0; w < kBlock / 64; ++w) carry += wsum[w];
     __syncthreads();
   }
-  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_RANK_DEFICIENT));
 }
 
 }  // namespace
@@ -190,11 +282,29 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
   FactorPtrs fp;
   for (int n = 0; n < kMaxOrder; ++n) fp.p[n] = n < g.order ? factors[n] : nullptr;
   if (dt == TK_F64)
-    hipLaunchKernelGGL(leverage_kernel<double>, dim3(g.order), dim3(kBlock), 0, st, g, fp,
-                       scores, cdf, L, Linv, P, Q64, Q32, status);
+    hipLaunchKernelGGL(leverage_kernel<double>, dim3(g.order), dim3(kBlock), 0, st, g, fp, L, Linv,
+                       P, status);
   else
-    hipLaunchKernelGGL(leverage_kernel<float>, dim3(g.order), dim3(kBlock), 0, st, g, fp,
-                       scores, cdf, L, Linv, P, Q64, Q32, status);
+    hipLaunchKernelGGL(leverage_kernel<float>, dim3(g.order), dim3(kBlock), 0, st, g, fp, L, Linv,
+                       P, status);
+  launch_mode_rows(g, factors, dt, Linv, 1, Q64, Q32, scores, cdf, st);
+  hipLaunchKernelGGL(weight_scan_kernel, dim3(g.order), dim3(kBlock), 0, st, g, cdf);
+}
+
+void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, const double* M,
+                      int trans, double* out64, float* out32, double* scores, uint64_t* weights,
+                      hipStream_t st) {
+  FactorPtrs fp;
+  int64_t blocks = 0;
+  for (int n = 0; n < kMaxOrder; ++n) fp.p[n] = n < g.order ? factors[n] : nullptr;
+  for (int n = 0; n < g.order; ++n) blocks += mode_row_blocks(g.dims[n]);
+  if (blocks == 0) return;
+  if (dt == TK_F64)
+    hipLaunchKernelGGL(mode_rows_kernel<double>, dim3(blocks), dim3(kBlock), 0, st, g, fp, M,
+                       trans, out64, out32, scores, weights);
+  else
+    hipLaunchKernelGGL(mode_rows_kernel<float>, dim3(blocks), dim3(kBlock), 0, st, g, fp, M, trans,
+                       out64, out32, scores, weights);
 }
 
 }  // namespace tk

@@ -38,43 +38,66 @@ __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
   }
 }
 
+// With STAGE the concatenated tables are first copied to LDS (they are read
+// by every sample's binary searches); the grid strides over the samples.
+constexpr int64_t kSampleLdsRows = 6144;  // 48 KB of uint64 entries
+
+template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* __restrict__ cdf,
                                                         int64_t s, uint64_t seed,
                                                         uint64_t counter, uint64_t problem,
                                                         int32_t* __restrict__ idx,
                                                         double* __restrict__ weight) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= s) return;
-  double acc = 1.0;
-  const int N = g.order;
-  for (int b = 0; b * 4 < N; ++b) {
-    uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, static_cast<uint64_t>(b)};
-    philox4x64_10(c, seed, 0ull);
+  extern __shared__ uint64_t cs[];
+  if (STAGE) {
+    const int64_t n = g.total_rows;
+    for (int64_t e0 = threadIdx.x; e0 < n; e0 += 8 * kBlock) {
+      uint64_t v[8];  // eight loads in flight (indices clamped into range)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = 4 * b + j;
-      if (n < N) {
-        const uint64_t* C = cdf + g.off[n];
-        const int64_t I = g.dims[n];
-        const uint64_t W = C[I - 1];
-        const uint64_t u = __umul64hi(c[j], W);
-        int64_t lo = 0, hi = I;
-        while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (C[mid] > u)
-            hi = mid;
-          else
-            lo = mid + 1;
+      for (int k = 0; k < 8; ++k) {
+        const int64_t e = e0 + k * kBlock;
+        v[k] = cdf[e < n ? e : n - 1];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (e0 + k * kBlock < n) cs[e0 + k * kBlock] = v[k];
+    }
+    __syncthreads();
+  }
+  auto tab = [&](int64_t i) -> uint64_t { return STAGE ? cs[i] : cdf[i]; };
+  const int N = g.order;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < s;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    double acc = 1.0;
+    for (int b = 0; b * 4 < N; ++b) {
+      uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, static_cast<uint64_t>(b)};
+      philox4x64_10(c, seed, 0ull);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 4 * b + j;
+        if (n < N) {
+          const int64_t o = g.off[n];
+          const int64_t I = g.dims[n];
+          const uint64_t W = tab(o + I - 1);
+          const uint64_t u = __umul64hi(c[j], W);
+          int64_t lo = 0, hi = I;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (tab(o + mid) > u)
+              hi = mid;
+            else
+              lo = mid + 1;
+          }
+          if (lo > I - 1) lo = I - 1;  // only when W == 0 (rank-deficient factor)
+          const uint64_t wi = tab(o + lo) - (lo > 0 ? tab(o + lo - 1) : 0ull);
+          idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(lo);
+          // weight = prod_n W_n / w_i, in mode order, then / s
+          acc = acc * (static_cast<double>(W) / static_cast<double>(wi));
         }
-        if (lo > I - 1) lo = I - 1;  // only when W == 0 (rank-deficient factor)
-        const uint64_t wi = C[lo] - (lo > 0 ? C[lo - 1] : 0ull);
-        idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(lo);
-        // weight = prod_n W_n / w_i, in mode order, then / s
-        acc = acc * (static_cast<double>(W) / static_cast<double>(wi));
       }
     }
+    weight[t] = acc / static_cast<double>(s);
   }
-  weight[t] = acc / static_cast<double>(s);
 }
 
 }  // namespace
@@ -82,8 +105,16 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* 
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st) {
   if (s <= 0) return;
-  hipLaunchKernelGGL(sample_kernel, dim3(static_cast<unsigned>(cdiv(s, kBlock))), dim3(kBlock), 0,
-                     st, g, cdf, s, seed, counter, problem, idx, weight);
+  if (g.total_rows <= kSampleLdsRows) {
+    const int64_t want = cdiv(s, kBlock);
+    const unsigned grid = static_cast<unsigned>(want < 1024 ? want : 1024);
+    hipLaunchKernelGGL(sample_kernel<true>, dim3(grid), dim3(kBlock),
+                       sizeof(uint64_t) * g.total_rows, st, g, cdf, s, seed, counter, problem, idx,
+                       weight);
+  } else {
+    hipLaunchKernelGGL(sample_kernel<false>, dim3(static_cast<unsigned>(cdiv(s, kBlock))),
+                       dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, idx, weight);
+  }
 }
 
 }  // namespace tk

@@ -3,8 +3,9 @@
 // n-mode product (Sec. 2): (T x_n M)[.., j, ..] = sum_i M[j, i] T[.., i, ..].
 // A row-major tensor is viewed as (P, I, Q) around mode n; every thread owns
 // one (p, q) fibre and produces all J outputs, so each input element is read
-// once and reads are coalesced along q.  When mode n is the last mode (Q = 1)
-// rows of the input are staged through LDS instead.
+// once and reads are coalesced along q.  Large contractions run on FP64 MFMA:
+// when mode n is the last mode (Q = 1) rows of the input are staged through
+// LDS; otherwise each p is a (J x I) (I x Q) product read along q.
 #include "tk_internal.h"
 
 namespace tk {
@@ -167,6 +168,75 @@ __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ 
   }
 }
 
+// Q > 1: out[p][j][q] = sum_i Mat(j, i) in[p][i][q] -- per p a (J x I) (I x Q)
+// product on v_mfma_f64_16x16x4, J <= 16 JB.  A wave owns 64 consecutive q (four
+// 16-column blocks) and all J outputs; Mat is staged through LDS in chunks of
+// 64 i (the A operand, zero beyond I and J); the input is read directly in the
+// B operand layout (lane l: i = k + l / 16, q = 16 t + l % 16, so each row
+// contributes 16 consecutive elements), with indices clamped into range.
+constexpr int kTmK = 64, kTmLd = kTmK + 1;
+
+template <class T, int JB>
+__global__ __launch_bounds__(kBlock) void ttm_mid_kernel(const T* __restrict__ in, int64_t I,
+                                                         int64_t Q, const double* __restrict__ M,
+                                                         int64_t J, bool trans,
+                                                         double* __restrict__ out,
+                                                         const int32_t* done) {
+  if (done && *done) return;
+  __shared__ double Ms[JB * 16 * kTmLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t p = blockIdx.y;
+  const int64_t qw = static_cast<int64_t>(blockIdx.x) * 256 + wave * 64;
+  const T* src = in + p * I * Q;
+  int64_t qc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t q = qw + 16 * t + lr;
+    qc[t] = q < Q ? q : Q - 1;
+  }
+  ttm_doublex4 acc[JB][4];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[jb][t] = ttm_doublex4{0, 0, 0, 0};
+  for (int64_t i0 = 0; i0 < I; i0 += kTmK) {
+    __syncthreads();  // the previous chunk's LDS reads are done
+    for (int e = tid; e < JB * 16 * kTmK; e += kBlock) {
+      const int j = e / kTmK, c = e % kTmK;
+      const int64_t i = i0 + c;
+      Ms[j * kTmLd + c] = (j < J && i < I) ? mat(M, I, J, trans, j, i) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kTmK; kk += 4) {
+      const int64_t i = i0 + kk + lk;
+      const T* row = src + (i < I ? i : I - 1) * Q;
+      double b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t] = static_cast<double>(row[qc[t]]);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const double a = Ms[(jb * 16 + lr) * kTmLd + kk + lk];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[jb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[t], acc[jb][t], 0, 0, 0);
+      }
+    }
+  }
+  // accumulator register v of lane l: row (j) l / 16 + 4 v, column (q) l % 16
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = jb * 16 + lk + 4 * v;
+        const int64_t q = qw + 16 * t + lr;
+        if (j < J && q < Q) out[(p * J + j) * Q + q] = acc[jb][t][v];
+      }
+}
+
 constexpr int64_t kTtmThreadsWanted = 65536;
 
 template <class T>
@@ -180,6 +250,19 @@ void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const d
   if (Q == 1 && J <= kMaxRank && P >= 64 * 256) {
     hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
                        0, st, in, P, I, M, J, trans, out, done);
+    return;
+  }
+  if (Q >= 64 && J <= kMaxRank && P <= 65535 && P * cdiv(Q, 256) >= 512) {
+    const dim3 grid(static_cast<unsigned>(cdiv(Q, 256)), static_cast<unsigned>(P));
+    if (J <= 16)
+      hipLaunchKernelGGL((ttm_mid_kernel<T, 1>), grid, dim3(kBlock), 0, st, in, I, Q, M, J, trans,
+                         out, done);
+    else if (J <= 32)
+      hipLaunchKernelGGL((ttm_mid_kernel<T, 2>), grid, dim3(kBlock), 0, st, in, I, Q, M, J, trans,
+                         out, done);
+    else
+      hipLaunchKernelGGL((ttm_mid_kernel<T, 4>), grid, dim3(kBlock), 0, st, in, I, Q, M, J, trans,
+                         out, done);
     return;
   }
   // split the contraction over i when there are too few fibres to fill the GPU

@@ -72,7 +72,9 @@ def test_leverage_scores_and_tables(tk, dims, ranks, dtype):
         off += I
 
 
-@pytest.mark.parametrize("dims", [(23, 19, 17), (41, 37, 29, 5), (7, 5, 6, 4, 3, 5), (300,)])
+# (7000, 9): tables too long for the sampler's LDS copy (global binary searches)
+@pytest.mark.parametrize("dims", [(23, 19, 17), (41, 37, 29, 5), (7, 5, 6, 4, 3, 5), (300,),
+                                  (7000, 9)])
 @pytest.mark.parametrize("s", [1, 17, 4099])
 def test_sampler_bit_exact(tk, dims, s):
     ranks = tuple(min(3, I) for I in dims)
@@ -214,6 +216,47 @@ def test_loss_matches_oracle(tk, dims, ranks):
     for missing in (None, 0.3):
         p, F = _sketch_case(dims, ranks, 12, missing=missing)
         G = np.random.default_rng(2).standard_normal(ranks)
+        mask = T(p["mask"].view(np.int32)) if missing else None
+        Lv, sq, cnt = tk.loss(T(p["X"]), T(G), [T(A) for A in F], 0.1, mask=mask)
+        rL, rrmse = oracle.loss(p["X"], G, F, 0.1, p["mask"])
+        assert abs(Lv - rL) <= 1e-10 * abs(rL)
+        assert abs((sq / cnt) ** 0.5 - rrmse) <= 1e-10 * rrmse
+
+
+# Middle-mode contractions with many (p, q) fibres run as per-p MFMA products
+# (a wave per 64 q, J in blocks of 16): ragged q tails, a partial i chunk and
+# J = 4, 20 and 64 (one, two and four j blocks).  The rank-64 mode's own update
+# is left out: its system has condition number ~3e8 (rank 6 core unfolding).
+@pytest.mark.parametrize("dims,ranks,dtype,modes", [
+    ((520, 9, 70), (3, 4, 5), "f64", (0, 1, 2)),
+    ((530, 33, 66), (4, 20, 6), "f32", (0, 1, 2)),
+    ((520, 70, 64), (2, 64, 3), "f64", (0, 2)),
+])
+def test_factor_update_mid_mode_contraction(tk, dims, ranks, dtype, modes):
+    p, F = _sketch_case(dims, ranks, 13, dtype=dtype)
+    lam = 1e-2
+    G = np.random.default_rng(3).standard_normal(ranks)
+    Xf = p["X"].astype(np.float64)
+    Ff = [A.astype(np.float64) for A in F]
+    for n in modes:
+        A = tk.factor_update(T(p["X"]), T(G.astype(p["X"].dtype)), [T(B) for B in F], n, lam)
+        Gr = G.astype(p["X"].dtype).astype(np.float64)
+        ref = oracle.factor_update(Xf, Gr, Ff, n, lam)
+        assert rel(A.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-5), n
+
+
+# The loss expands the last mode on MFMA in k-steps of 4 ranks (1, 2, 4, 8 or 16
+# steps) with A_N staged in LDS in column chunks: R_N = 20 and 33 give 8 and 16
+# steps, the latter with eleven 64-column chunks; ragged last chunks.
+@pytest.mark.parametrize("dims,ranks", [
+    ((50, 37, 300), (2, 3, 20)),
+    ((40, 30, 700), (3, 4, 33)),
+    ((33, 1029), (5, 4)),
+])
+def test_loss_wide_last_mode(tk, dims, ranks):
+    for missing in (None, 0.25):
+        p, F = _sketch_case(dims, ranks, 14, missing=missing)
+        G = np.random.default_rng(4).standard_normal(ranks)
         mask = T(p["mask"].view(np.int32)) if missing else None
         Lv, sq, cnt = tk.loss(T(p["X"]), T(G), [T(A) for A in F], 0.1, mask=mask)
         rL, rrmse = oracle.loss(p["X"], G, F, 0.1, p["mask"])

@@ -20,6 +20,10 @@ Workloads (shapes follow the paper's experiments, Sec. 5, and the parity cases):
 * ``table1``: the synthetic protocol of Sec. 5 (true core 8^3, factor and core
   entries U[0,1], N(0,1) noise on 1 % of the entries), a stand-in for the
   paper's synthetic benchmark at any input shape.
+* ``t1``: that protocol at the largest shape of the paper's synthetic table,
+  1024^3 float32, fitted at rank 4^3 from the U[0,1] initial state of Alg. 2;
+  lambda 1e-3; the Alg. 1 sample count for eps = delta = 0.1 at d = 64
+  (1687583 samples).  Generated in mode-0 slabs with one child generator each.
 """
 import numpy as np
 
@@ -36,6 +40,9 @@ CONFIGS = {
     "c5": dict(dims=(256, 256, 256), ranks=(12, 12, 12), dtype="f32", lam=1e-2,
                samples=32768, seed=5, factor="qr", core="normal", noise=("snr_db", 20.0),
                gram="f64"),
+    "t1": dict(dims=(1024, 1024, 1024), ranks=(4, 4, 4), dtype="f32", lam=1e-3,
+               samples=1687583, seed=11, protocol="table1", true_rank=(8, 8, 8), init_seed=1011,
+               gram="bf16"),
 }
 
 NP_DTYPES = {"f64": np.float64, "f32": np.float32}
@@ -111,16 +118,45 @@ def config_problem(name, **overrides):
     """The named workload (see module docstring) with optional overrides."""
     cfg = dict(CONFIGS[name])
     cfg.update(overrides)
+    if cfg.get("protocol") == "table1":
+        prob = table1_problem(cfg["dims"], cfg["seed"], cfg["dtype"], cfg["true_rank"], slabs=True)
+        _, F0 = als_init(cfg["dims"], cfg["ranks"], cfg["init_seed"], "f64")
+        prob["factors_fit"] = F0
+        prob["cfg"] = cfg
+        return prob
     prob = tucker_tensor(cfg["dims"], cfg["ranks"], cfg["seed"], cfg["dtype"], cfg["factor"],
                          cfg["core"], cfg["noise"], cfg.get("missing"))
     prob["cfg"] = cfg
     return prob
 
 
-def table1_problem(dims, seed, dtype="f32", true_rank=(8, 8, 8)):
-    """Sec. 5 synthetic protocol: U[0,1] core and factors, N(0,1) noise on 1 % of entries."""
-    return tucker_tensor(dims, true_rank, seed, dtype, factor="uniform", core="uniform",
-                         noise=("sparse", 0.01, 1.0))
+def table1_problem(dims, seed, dtype="f32", true_rank=(8, 8, 8), slabs=False, slab_rows=32):
+    """Sec. 5 synthetic protocol: U[0,1] core and factors, N(0,1) noise on 1 % of entries.
+
+    With ``slabs`` the tensor is built ``slab_rows`` mode-0 rows at a time (same
+    core and factors; the noise of slab b comes from default_rng([seed, 1, b])),
+    so that a 1024^3 tensor needs no full-size float64 temporaries.
+    """
+    if not slabs:
+        return tucker_tensor(dims, true_rank, seed, dtype, factor="uniform", core="uniform",
+                             noise=("sparse", 0.01, 1.0))
+    rng = np.random.default_rng(seed)
+    A = [_factor(rng, I, R, "uniform") for I, R in zip(dims, true_rank)]
+    G = rng.random(true_rank)
+    # mode 0 applied last: W[j..., r0] = G x_1.. A(1..N-1) with the mode-0 index kept
+    W = G
+    for n in range(1, len(dims)):
+        W = _mode_mul(W, A[n], n)
+    W0 = W.reshape(true_rank[0], -1)
+    X = np.empty(dims, dtype=NP_DTYPES[dtype])
+    for b, i0 in enumerate(range(0, dims[0], slab_rows)):
+        i1 = min(dims[0], i0 + slab_rows)
+        child = np.random.default_rng([seed, 1, b])
+        xs = (A[0][i0:i1] @ W0).reshape((i1 - i0,) + tuple(dims[1:]))
+        hit = child.random(xs.shape) < 0.01
+        xs[hit] += child.standard_normal(int(hit.sum()))
+        X[i0:i1] = xs
+    return dict(X=X, G_true=G, factors_true=A, mask=None)
 
 
 def als_init(dims, ranks, init_seed, dtype="f64"):
