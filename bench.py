@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
-    ap.add_argument("--refine-max", type=int, default=12)
+    ap.add_argument("--refine-max", type=int, default=8)
     ap.add_argument("--cpu-samples", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip exact/ALS comparison timings")

@@ -648,6 +648,20 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   R.stage(7);
   const bool refine = R.o->gram_precision != TK_F64;
   const int iters = refine ? R.o->refine_max : 0;
+  if (resid_small_ok(g) && refine_small_ok(g)) {
+    // small d: the residual's partials, then one fused step (sum, P h, test,
+    // block solve, update) per iteration
+    for (int k = 0; k <= iters; ++k) {
+      const int64_t np =
+          launch_resid_small_parts(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.done, st);
+      launch_refine_step_small(g, w.vpart, np, w.lev.P, b, lambda, norm_ref,
+                               refine ? R.o->refine_tol : -1.0, w.M, w.Linv_diag, h, w.done,
+                               w.steps, w.relres, k < iters ? 1 : 0, st);
+    }
+    if (refine) launch_finish_refine(w.done, 1, R.status, st);
+    R.stage(8);
+    return;
+  }
   for (int k = 0; k <= iters; ++k) {
     if (resid_small_ok(g)) {
       launch_resid_small(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);

@@ -26,33 +26,66 @@ namespace tk {
 namespace {
 
 // ------------------------------------------------------------------ pre-gather
+// Element e of the chunk-transposed layout: chunk c = e / (32 sum_r), row
+// position j, sample t = 32 c + e % 32.  Each thread takes kPgPer elements
+// (stride: the grid) and issues their loads together.
+constexpr int kPgPer = 8;
+
 __global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t* __restrict__ idx,
                                                            const double* __restrict__ weff,
                                                            int64_t s,
                                                            const double* __restrict__ Q64,
                                                            double* __restrict__ rows64,
                                                            float* __restrict__ rows32) {
+  // per row position j: its mode, table offset, rank and largest index (LDS)
+  __shared__ int64_t pq[kMaxSumR];
+  __shared__ int32_t pn[kMaxSumR], pr[kMaxSumR], pi[kMaxSumR];
   const int SR = g.sum_r;
-  const int64_t total = row_chunks(s) * kRowChunk * SR;
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= total) return;
-  const int tt = static_cast<int>(e & (kRowChunk - 1));
-  const int64_t rest = e >> 5;
-  const int64_t c = rest / SR;
-  const int j = static_cast<int>(rest - c * SR);
-  const int64_t t = c * kRowChunk + tt;
-  double v = 0.0;
-  float v32 = 0.0f;
-  if (t < s) {
+  if (threadIdx.x < SR) {
+    const int j = threadIdx.x;
     int n = 0;
     while (n + 1 < g.order && j >= g.soff[n + 1]) ++n;
-    int32_t i = idx[static_cast<int64_t>(n) * s + t];
-    if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
-    v = Q64[g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n] + (j - g.soff[n])];
-    v32 = static_cast<float>(n == 0 ? v * sqrt(weff[t]) : v);
+    pn[j] = n;
+    pq[j] = g.qoff[n] + (j - g.soff[n]);
+    pr[j] = g.ranks[n];
+    pi[j] = static_cast<int32_t>(g.dims[n] - 1);
   }
-  if (rows64) rows64[e] = v;
-  rows32[e] = v32;
+  __syncthreads();
+  const int64_t total = row_chunks(s) * kRowChunk * SR;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  double v[kPgPer], wv[kPgPer];
+  int mode[kPgPer];
+#pragma unroll
+  for (int k = 0; k < kPgPer; ++k) {
+    const int64_t e = e0 + k * stride;
+    const int64_t ec = e < total ? e : total - 1;
+    const int tt = static_cast<int>(ec & (kRowChunk - 1));
+    const int64_t rest = ec >> 5;
+    // 32-bit division unless the position index needs more bits
+    const int64_t c = rest < 0xFFFFFFFFll
+                          ? static_cast<int64_t>(static_cast<uint32_t>(rest) /
+                                                 static_cast<uint32_t>(SR))
+                          : rest / SR;
+    const int j = static_cast<int>(rest - c * SR);
+    const int64_t t = c * kRowChunk + tt;
+    const int64_t tc = t < s ? t : s - 1;
+    const int n = pn[j];
+    int32_t i = idx[static_cast<int64_t>(n) * s + tc];
+    if (i < 0 || i > pi[j]) i = 0;  // flagged by the gather pass (weight 0)
+    const double q = Q64[pq[j] + static_cast<int64_t>(i) * pr[j]];
+    v[k] = t < s ? q : 0.0;
+    wv[k] = weff[tc];
+    mode[k] = n;
+  }
+#pragma unroll
+  for (int k = 0; k < kPgPer; ++k) {
+    const int64_t e = e0 + k * stride;
+    if (e < total) {
+      if (rows64) rows64[e] = v[k];
+      rows32[e] = static_cast<float>(mode[k] == 0 ? v[k] * sqrt(wv[k]) : v[k]);
+    }
+  }
 }
 
 // Row offsets of the outer factors of outer index o: for every mode n != L,
@@ -689,7 +722,11 @@ __global__ __launch_bounds__(kBlock) void resid_small_kernel(
     const int64_t t = ch * kSmChunk + tid;
     const int64_t tc = t < s ? t : s - 1;
 #pragma unroll
-    for (int n = 0; n < N; ++n) iv[n] = idx[n * s + tc];
+    for (int n = 0; n < N; ++n) {
+      const int32_t i = idx[n * s + tc];  // clamped into range (invalid ones carry weight 0)
+      const int32_t imax = static_cast<int32_t>(g.dims[n] - 1);
+      iv[n] = i < 0 ? 0 : (i > imax ? imax : i);
+    }
     av = a ? a[tc] : 0.0;
     bv = (b && h) ? b[tc] : 0.0;
   };
@@ -761,6 +798,191 @@ __global__ __launch_bounds__(kBlock) void resid_small_kernel(
     double v = 0.0;
     for (int k = 0; k < ngrp; ++k) v += red[k * d + tid];
     part[static_cast<int64_t>(blockIdx.x) * d + tid] = v;
+  }
+}
+
+// The same partial sums when every rank is at most RM (a power of two) and
+// RM^N <= 64, with the Kronecker row kept in registers: in the zero-padded
+// index space p = sum_n digit_n RM^(N-1-n), a sample is shared by SPL = RM
+// lanes, lane j owning the entries whose mode-0 digit is j,
+// i.e. RM^(N-1) static indices p'.  The lanes of a sample load its factor rows
+// (zero-padded to RM), form their part of k_t . h (h in LDS) and add it across
+// the group by xor shuffles, then accumulate c_t k_t over their entries.  The
+// workgroup adds its lanes' accumulators once at the end (xor tree over the
+// lanes of equal j, then the waves in order).
+template <int N, int RM>
+struct PadSpace {
+  static constexpr int PD = RM * PadSpace<N - 1, RM>::PD;
+};
+template <int RM>
+struct PadSpace<0, RM> {
+  static constexpr int PD = 1;
+};
+
+constexpr int kRegThreads = 256;
+
+template <int N, int RM, bool EXACT>  // EXACT: every rank equals RM (no padding)
+__global__ __launch_bounds__(kRegThreads) void resid_reg_kernel(
+    Geom g, const int32_t* __restrict__ idx, const double* __restrict__ Q64,
+    const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ h,
+    int64_t s, double* __restrict__ part, const int32_t* done) {
+  constexpr int PD = PadSpace<N, RM>::PD;
+  constexpr int SPL = RM;              // lanes per sample: one per mode-0 digit
+  constexpr int PL = PD / SPL;         // entries per lane
+  constexpr int HLD = PL + 1;          // padded stride of lane j's slice of h
+  if (done && *done) return;
+  __shared__ double hs[SPL * HLD];
+  __shared__ double red[kRegThreads / 64][PD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int j = lane % SPL;
+  int R[N];
+  int64_t qo[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    R[n] = g.ranks[n];
+    qo[n] = g.qoff[n];
+  }
+  // padded index -> unpadded Kronecker index (or -1 past a mode's rank)
+  auto unpad = [&](int p) {
+    int q = p, r = 0, mul = 1;
+    bool ok = true;
+#pragma unroll
+    for (int n = N - 1; n >= 0; --n) {
+      const int dg = q % RM;
+      q /= RM;
+      ok = ok && dg < R[n];
+      r += dg * mul;
+      mul *= R[n];
+    }
+    return ok ? r : -1;
+  };
+  for (int p = tid; p < PD; p += kRegThreads) {
+    const int r = unpad(p);
+    hs[(p / PL) * HLD + p % PL] = (h && r >= 0) ? h[r] : 0.0;
+  }
+  __syncthreads();
+  double acc[PL];
+#pragma unroll
+  for (int e = 0; e < PL; ++e) acc[e] = 0.0;
+  const int64_t slots = static_cast<int64_t>(gridDim.x) * (kRegThreads / SPL);
+  const int64_t t0 = static_cast<int64_t>(blockIdx.x) * (kRegThreads / SPL) + tid / SPL;
+  // software pipeline: indices and coefficients two samples ahead, factor
+  // rows one sample ahead (past the end: the last sample, never used)
+  struct Ix {
+    int32_t i[N];
+    double a, b;
+  };
+  struct Rows {
+    double q0;
+    double q[N > 1 ? N - 1 : 1][RM];
+  };
+  int32_t Imax[N];  // indices are clamped into range (invalid ones carry weight 0)
+#pragma unroll
+  for (int n = 0; n < N; ++n) Imax[n] = static_cast<int32_t>(g.dims[n] - 1);
+  auto fetch_ix = [&](int64_t t) {
+    Ix x;
+    const int64_t tc = t < s ? t : s - 1;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const int32_t i = idx[n * s + tc];
+      x.i[n] = i < 0 ? 0 : (i > Imax[n] ? Imax[n] : i);
+    }
+    x.a = a ? a[tc] : 0.0;
+    x.b = (b && h) ? b[tc] : 0.0;
+    return x;
+  };
+  auto fetch_rows = [&](const Ix& x) {
+    Rows w;
+    if (EXACT) {
+      // rows of RM doubles at RM-aligned offsets: 16-byte loads for RM >= 2
+      w.q0 = Q64[qo[0] + static_cast<int64_t>(x.i[0]) * RM + j];
+#pragma unroll
+      for (int n = 1; n < N; ++n) {
+        const double* row = Q64 + qo[n] + static_cast<int64_t>(x.i[n]) * RM;
+        if (RM >= 2) {
+          typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+          for (int r = 0; r < RM; r += 2) {
+            const d2 v = *reinterpret_cast<const d2*>(row + r);
+            w.q[n - 1][r] = v.x;
+            w.q[n - 1][r + 1] = v.y;
+          }
+        } else {
+          w.q[n - 1][0] = row[0];
+        }
+      }
+      return w;
+    }
+    {
+      const double v = Q64[qo[0] + static_cast<int64_t>(x.i[0]) * R[0] + (j < R[0] ? j : R[0] - 1)];
+      w.q0 = j < R[0] ? v : 0.0;
+    }
+#pragma unroll
+    for (int n = 1; n < N; ++n) {
+      const double* row = Q64 + qo[n] + static_cast<int64_t>(x.i[n]) * R[n];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const double v = row[r < R[n] ? r : R[n] - 1];
+        w.q[n - 1][r] = r < R[n] ? v : 0.0;
+      }
+    }
+    return w;
+  };
+  Ix xa = fetch_ix(t0), xb = fetch_ix(t0 + slots);
+  Rows wa = fetch_rows(xa);
+  for (int64_t t = t0; t < s; t += slots) {
+    const Ix xc = fetch_ix(t + 2 * slots);
+    const Rows wb = fetch_rows(xb);
+    // entry p' of this lane: q0 * prod_{n >= 1} q_n[digit_n(p')]
+    auto tail = [&](int pp) {
+      double k = 1.0;
+      int rest = pp;
+#pragma unroll
+      for (int n = N - 1; n >= 1; --n) {
+        k *= wa.q[n - 1][rest % RM];
+        rest /= RM;
+      }
+      return k;
+    };
+    double c = xa.a;
+    if (h) {
+      double u = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < PL; ++pp) u = fma(tail(pp), hs[j * HLD + pp], u);
+      u *= wa.q0;
+#pragma unroll
+      for (int off = 1; off < SPL; off <<= 1) u += __shfl_xor(u, off, 64);
+      c = fma(-xa.b, u, c);
+    }
+    const double cq = c * wa.q0;
+#pragma unroll
+    for (int pp = 0; pp < PL; ++pp) acc[pp] = fma(cq, tail(pp), acc[pp]);
+    xa = xb;
+    xb = xc;
+    wa = wb;
+  }
+  // lanes of equal j, then the waves
+#pragma unroll
+  for (int pp = 0; pp < PL; ++pp) {
+    double v = acc[pp];
+#pragma unroll
+    for (int off = SPL; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    acc[pp] = v;
+  }
+  if (lane < SPL) {
+#pragma unroll
+    for (int pp = 0; pp < PL; ++pp) red[wave][lane * PL + pp] = acc[pp];
+  }
+  __syncthreads();
+  for (int p = tid; p < PD; p += kRegThreads) {
+    const int r = unpad(p);
+    if (r >= 0) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < kRegThreads / 64; ++w) v += red[w][p];
+      part[static_cast<int64_t>(blockIdx.x) * g.d + r] = v;
+    }
   }
 }
 
@@ -845,8 +1067,8 @@ void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int
                       const double* Q64, double* rows64, float* rows32, hipStream_t st) {
   const int64_t n = row_chunks(s) * kRowChunk * g.sum_r;
   if (n <= 0) return;
-  hipLaunchKernelGGL(pregather_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock))), dim3(kBlock),
-                     0, st, g, idx, weff, s, Q64, rows64, rows32);
+  hipLaunchKernelGGL(pregather_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock * kPgPer))),
+                     dim3(kBlock), 0, st, g, idx, weff, s, Q64, rows64, rows32);
 }
 
 void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const float* rows32,
@@ -926,6 +1148,24 @@ SmallPlan plan_small(int64_t s) {
   sp.nwg = cdiv(nch, sp.cpw);
   return sp;
 }
+// (N, RM) of the register-resident kernel for this geometry, RM = 0 if none
+int reg_rm(const Geom& g) {
+  int rmax = 1;
+  for (int n = 0; n < g.order; ++n) rmax = g.ranks[n] > rmax ? g.ranks[n] : rmax;
+  int rm = 1;
+  while (rm < rmax) rm *= 2;
+  if (rm > 8) return 0;
+  int64_t pd = 1;
+  for (int n = 0; n < g.order; ++n) pd *= rm;
+  return (pd <= 64 && g.order <= 6) ? rm : 0;
+}
+
+int64_t reg_grid(int64_t s) {
+  // about eight samples per 64-lane slot group at most 1024 workgroups
+  const int64_t want = cdiv(s, 512);
+  return want < 1 ? 1 : (want > 1024 ? 1024 : want);
+}
+
 }  // namespace
 
 bool resid_small_ok(const Geom& g) { return g.d <= kSmD && g.sum_r <= kSmSumR; }
@@ -935,12 +1175,64 @@ int64_t vec_part_doubles(const Geom& g, int64_t s) {
   int64_t n = vp.nsplit * g.d;
   if (vp.nr * s > n) n = vp.nr * s;
   if (resid_small_ok(g) && plan_small(s).nwg * g.d > n) n = plan_small(s).nwg * g.d;
+  if (resid_small_ok(g) && reg_grid(s) * g.d > n) n = reg_grid(s) * g.d;
   return n;
 }
 
-void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
-                        const double* b, const double* h, int64_t s, double* part, double* out,
-                        const int32_t* done, hipStream_t st) {
+template <int N, int RM>
+void launch_reg(dim3 grid, hipStream_t st, const Geom& g, const int32_t* idx, const double* Q64,
+                const double* a, const double* b, const double* h, int64_t s, double* part,
+                const int32_t* done) {
+  // exact ranks: every mode RM wide and every mode's rows 16-byte aligned
+  bool exact = true;
+  for (int n = 0; n < N; ++n)
+    exact = exact && g.ranks[n] == RM && (RM < 2 || (g.qoff[n] % 2) == 0);
+  exact = exact && (reinterpret_cast<uintptr_t>(Q64) % 16) == 0;
+  if (exact)
+    hipLaunchKernelGGL((resid_reg_kernel<N, RM, true>), grid, dim3(kRegThreads), 0, st, g, idx, Q64,
+                       a, b, h, s, part, done);
+  else
+    hipLaunchKernelGGL((resid_reg_kernel<N, RM, false>), grid, dim3(kRegThreads), 0, st, g, idx,
+                       Q64, a, b, h, s, part, done);
+}
+
+bool try_resid_reg(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
+                   const double* b, const double* h, int64_t s, double* part, const int32_t* done,
+                   hipStream_t st, int64_t* nparts) {
+  const int rm = reg_rm(g);
+  if (rm == 0) return false;
+  const int64_t grid = reg_grid(s);
+  const dim3 gd(static_cast<unsigned>(grid));
+  const int key = g.order * 16 + rm;
+  switch (key) {
+    case 1 * 16 + 1: launch_reg<1, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 2: launch_reg<1, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 4: launch_reg<1, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 8: launch_reg<1, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 1: launch_reg<2, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 2: launch_reg<2, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 4: launch_reg<2, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 8: launch_reg<2, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 1: launch_reg<3, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 2: launch_reg<3, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 4: launch_reg<3, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 4 * 16 + 1: launch_reg<4, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 4 * 16 + 2: launch_reg<4, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 5 * 16 + 1: launch_reg<5, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 5 * 16 + 2: launch_reg<5, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 6 * 16 + 1: launch_reg<6, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 6 * 16 + 2: launch_reg<6, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    default: return false;
+  }
+  *nparts = grid;
+  return true;
+}
+
+int64_t launch_resid_small_parts(const Geom& g, const int32_t* idx, const double* Q64,
+                                 const double* a, const double* b, const double* h, int64_t s,
+                                 double* part, const int32_t* done, hipStream_t st) {
+  int64_t np = 0;
+  if (try_resid_reg(g, idx, Q64, a, b, h, s, part, done, st, &np)) return np;
   const SmallPlan sp = plan_small(s);
   const size_t lds = static_cast<size_t>(small_lds(g.sum_r).bytes);
   const dim3 grid(static_cast<unsigned>(sp.nwg));
@@ -960,9 +1252,16 @@ void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, co
     TK_RS_CASE(8)
   }
 #undef TK_RS_CASE
+  return sp.nwg;
+}
+
+void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
+                        const double* b, const double* h, int64_t s, double* part, double* out,
+                        const int32_t* done, hipStream_t st) {
+  const int64_t nwg = launch_resid_small_parts(g, idx, Q64, a, b, h, s, part, done, st);
   hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(static_cast<unsigned>(cdiv(g.d, 64))),
-                     dim3(64 * kSpWaves), 0, st, static_cast<const double*>(part), sp.nwg, g.d,
-                     out, done);
+                     dim3(64 * kSpWaves), 0, st, static_cast<const double*>(part), nwg, g.d, out,
+                     done);
 }
 
 void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,

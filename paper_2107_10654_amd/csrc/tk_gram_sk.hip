@@ -461,6 +461,50 @@ __global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_split_kernel(
   M[i * d + j] = fma(lambda, p, sum);
 }
 
+// One tile in the whole launch: every workgroup with units holds exactly one
+// slot, in workgroup order, so the tile's slots are 0 .. nslots - 1 and no
+// index lookups are needed.  Same split as above (16 waves per 64 entries of
+// row i, eight slots in flight per wave, waves added in order).
+template <int T>
+__global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_one_tile_kernel(
+    Geom g, int64_t nslots, const float* __restrict__ slots, const double* __restrict__ P,
+    double lambda, double* __restrict__ M) {
+  __shared__ double red[kAsmWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t d = g.d;
+  const int64_t i = blockIdx.y;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool act = j <= i;
+  const int64_t off = i * T + (act ? j : i);
+  constexpr int64_t TT = static_cast<int64_t>(T) * T;
+  const int64_t wa = (nslots * wave) / kAsmWaves, wb = (nslots * (wave + 1)) / kAsmWaves;
+  double v = 0.0;
+  int64_t w = wa;
+  for (; w + 8 <= wb; w += 8) {
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = slots[(w + k) * TT + off];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += static_cast<double>(x[k]);
+  }
+  for (; w < wb; ++w) v += static_cast<double>(slots[w * TT + off]);
+  red[wave][lane] = v;
+  __syncthreads();
+  if (wave != 0 || !act) return;
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kAsmWaves; ++k) sum += red[k][lane];
+  double p = 1.0;
+  int64_t a = i, b = j;
+  for (int nn = g.order - 1; nn >= 0; --nn) {
+    const int R = g.ranks[nn];
+    p *= P[g.roff[nn] + (a % R) * R + (b % R)];
+    a /= R;
+    b /= R;
+  }
+  M[i * d + j] = fma(lambda, p, sum);
+}
+
 template <class V, int T>
 void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
   using Pf = SkPf<SkTile<T>::THREADS>;
@@ -574,6 +618,22 @@ void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slo
                         hipStream_t st) {
   const SkProb& q = b.p[k];
   const int64_t nch = row_chunks(q.s);
+  if (b.tiles == 1 && b.count == 1) {
+    // a single tile: the workgroups with units hold slots 0 .. min(grid, units) - 1
+    const int64_t nslots = b.units < b.grid ? b.units : b.grid;
+    const dim3 grid(static_cast<unsigned>(cdiv(g.d, 64)), static_cast<unsigned>(g.d));
+    const dim3 block(64 * kAsmWaves);
+    if (b.tile == 256)
+      hipLaunchKernelGGL(assemble_sk_one_tile_kernel<256>, grid, block, 0, st, g, nslots, slots, P,
+                         lambda, M);
+    else if (b.tile == 128)
+      hipLaunchKernelGGL(assemble_sk_one_tile_kernel<128>, grid, block, 0, st, g, nslots, slots, P,
+                         lambda, M);
+    else
+      hipLaunchKernelGGL(assemble_sk_one_tile_kernel<64>, grid, block, 0, st, g, nslots, slots, P,
+                         lambda, M);
+    return;
+  }
   if (b.grid >= 8 * b.tiles) {
     // many slots per tile: split each element's sum over 16 waves
     const dim3 grid(static_cast<unsigned>(cdiv(g.d, 64)), static_cast<unsigned>(g.d));

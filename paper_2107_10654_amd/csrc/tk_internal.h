@@ -165,6 +165,21 @@ bool resid_small_ok(const Geom& g);
 void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
                         const double* b, const double* h, int64_t s, double* part, double* out,
                         const int32_t* done, hipStream_t st);
+// The per-workgroup partials of the same sum only (part[k][r], k < return value).
+int64_t launch_resid_small_parts(const Geom& g, const int32_t* idx, const double* Q64,
+                                 const double* a, const double* b, const double* h, int64_t s,
+                                 double* part, const int32_t* done, hipStream_t st);
+
+// One refinement step for d <= 256 in one workgroup (tk_refine.hip): r = the
+// summed partials + b - lambda P h, relres = ||r|| / ||norm_ref||, done once
+// relres <= tol, else (when do_solve) h += (L L^T)^{-1} r with L in M and the
+// diagonal-block inverses; returns at entry once done is set.
+bool refine_small_ok(const Geom& g);
+void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
+                              const double* b, double lambda, const double* norm_ref, double tol,
+                              const double* L, const double* Linv_diag, double* h, int32_t* done,
+                              int32_t* steps, double* relres, int do_solve, hipStream_t st);
+
 // Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part: vec_part_doubles.
 void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
                           const double* weff, const double* h, int64_t s, double* part, double* c,

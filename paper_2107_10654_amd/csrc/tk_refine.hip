@@ -1,0 +1,208 @@
+// One FP64 iterative-refinement step for a small Kronecker dimension
+// (d <= 256: at most four 64 x 64 Cholesky blocks), in a single workgroup.
+//
+// The sampled ridge system (whitened form) is (G_Q + lambda P) h = b_Q with
+// G_Q = sum_t weff_t q_t q_t^T and P = (x)_n P_n.  The Gram is formed in
+// BF16/FP32 on MFMA and factored in FP64; the refinement evaluates the
+// residual in FP64 without forming G_Q:
+//   r = b + sum_t q_t (xw_t - weff_t q_t . h) - lambda P h,
+// whose data term the residual kernel leaves as per-workgroup partial sums.
+// This step adds the partials in a fixed order, applies P mode by mode,
+// measures ||r|| / ||rhs||, sets the device `done` flag once it is at most
+// tol, and otherwise solves L L^T delta = r by block substitution with the
+// stored diagonal-block inverses and adds delta to h.  Once `done` is set the
+// step returns at entry, so the host may enqueue a fixed number of steps.
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+constexpr int kRsThreads = 1024;
+constexpr int kRsD = 256;
+constexpr int kNb = kCholNb;  // 64
+constexpr int kLd = kNb + 1;
+
+__device__ inline double block_sum(double v, double* red) {
+  // sum over the workgroup (fixed order: lanes by xor tree, then waves)
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kRsThreads / 64; ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
+    Geom g, const double* __restrict__ part, int64_t nparts, const double* __restrict__ P,
+    const double* __restrict__ b, double lambda, const double* __restrict__ norm_ref, double tol,
+    const double* __restrict__ L, const double* __restrict__ Linv_diag, double* __restrict__ h,
+    int32_t* done, int32_t* steps, double* relres, int do_solve) {
+  if (*done) return;
+  __shared__ double rs[kRsD], ta[kRsD], tb[kRsD], yv[kRsD], acc[kNb];
+  __shared__ double red[kRsThreads];
+  __shared__ double Li[kNb * kLd];
+  const int tid = threadIdx.x;
+  const int d = static_cast<int>(g.d);
+  const int N = g.order;
+  // the first diagonal-block inverse, loaded now and stored once it is needed
+  double li0[kNb * kNb / kRsThreads];
+#pragma unroll
+  for (int q = 0; q < kNb * kNb / kRsThreads; ++q) li0[q] = Linv_diag[tid + q * kRsThreads];
+
+  // 1. data term: sum of the workgroup partials, G groups of threads per entry
+  {
+    const int G = kRsThreads / d;
+    const int i = tid % d, gq = tid / d;
+    double v = 0.0;
+    if (gq < G) {
+      // eight loads in flight: parts gq, gq + G, ..., added in that order
+      int64_t k = gq;
+      for (; k + 7 * G < nparts; k += 8 * G) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[(k + u * G) * d + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+      }
+      for (; k < nparts; k += G) v += part[k * d + i];
+    }
+    red[tid] = v;
+    if (tid < d) ta[tid] = h[tid];
+    __syncthreads();
+    if (tid < d) {
+      double s = 0.0;
+      for (int k = 0; k < G; ++k) s += red[k * d + tid];
+      rs[tid] = s;
+    }
+    __syncthreads();
+  }
+  // 2. P h, one mode at a time: t <- t x_n P_n
+  double* cur = ta;
+  double* nxt = tb;
+  for (int n = 0; n < N; ++n) {
+    const int R = g.ranks[n];
+    int stride = 1;
+    for (int m = n + 1; m < N; ++m) stride *= g.ranks[m];
+    const double* Pn = P + g.roff[n];
+    if (tid < d) {
+      const int j = (tid / stride) % R;
+      const int base = tid - j * stride;
+      double v = 0.0;
+      for (int i2 = 0; i2 < R; ++i2) v = fma(Pn[j * R + i2], cur[base + i2 * stride], v);
+      nxt[tid] = v;
+    }
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  // 3. r = data + b - lambda P h, its relative norm and the convergence test
+  double a2 = 0.0, n2 = 0.0;
+  if (tid < d) {
+    double v = rs[tid];
+    if (b) v += b[tid];
+    v = fma(-lambda, cur[tid], v);
+    rs[tid] = v;
+    a2 = v * v;
+    n2 = norm_ref[tid] * norm_ref[tid];
+  }
+  const double sa = block_sum(a2, red);
+  const double sn = block_sum(n2, red + 32);
+  const double rel = sn > 0.0 ? sqrt(sa / sn) : sqrt(sa);
+  const bool conv = rel <= tol;
+  if (tid == 0) {
+    *relres = rel;
+    if (conv)
+      *done = 1;
+    else if (do_solve)
+      *steps += 1;
+  }
+  if (conv || !do_solve) return;
+
+  // 4. delta = (L L^T)^{-1} r by 64-row blocks; h += delta
+  const int nblk = (d + kNb - 1) / kNb;
+  const int row = tid & 63, pq = tid >> 6;  // 16 column groups per row
+  // forward: y_i = Linv_ii (r_i - sum_{j < i} L_ij y_j)
+  for (int i = 0; i < nblk; ++i) {
+    const int i0 = i * kNb;
+    const int rows = d - i0 < kNb ? d - i0 : kNb;
+    __syncthreads();
+    if (i == 0) {
+#pragma unroll
+      for (int q = 0; q < kNb * kNb / kRsThreads; ++q) {
+        const int e = tid + q * kRsThreads;
+        Li[(e >> 6) * kLd + (e & 63)] = li0[q];
+      }
+    } else {
+      for (int e = tid; e < kNb * kNb; e += kRsThreads)
+        Li[(e >> 6) * kLd + (e & 63)] = Linv_diag[static_cast<int64_t>(i) * kNb * kNb + e];
+    }
+    double v = 0.0;
+    if (row < rows)
+      for (int c = pq; c < i0; c += 16) v = fma(L[static_cast<int64_t>(i0 + row) * d + c], yv[c], v);
+    red[tid] = v;
+    __syncthreads();
+    if (tid < kNb) {
+      double s = 0.0;
+      for (int k = 0; k < 16; ++k) s += red[k * 64 + tid];
+      acc[tid] = tid < rows ? rs[i0 + tid] - s : 0.0;
+    }
+    __syncthreads();
+    v = 0.0;
+    for (int c = pq; c <= row; c += 16) v = fma(Li[row * kLd + c], acc[c], v);
+    red[tid] = v;
+    __syncthreads();
+    if (tid < rows) {
+      double s = 0.0;
+      for (int k = 0; k < 16; ++k) s += red[k * 64 + tid];
+      yv[i0 + tid] = s;
+    }
+  }
+  // backward: x_i = Linv_ii^T (y_i - sum_{j > i} L_ji^T x_j), x kept in rs
+  for (int i = nblk - 1; i >= 0; --i) {
+    const int i0 = i * kNb;
+    const int rows = d - i0 < kNb ? d - i0 : kNb;
+    __syncthreads();
+    if (i != nblk - 1)  // the last forward block is still in Li
+      for (int e = tid; e < kNb * kNb; e += kRsThreads)
+        Li[(e >> 6) * kLd + (e & 63)] = Linv_diag[static_cast<int64_t>(i) * kNb * kNb + e];
+    double v = 0.0;
+    if (row < rows)
+      for (int c = i0 + kNb + pq; c < d; c += 16)
+        v = fma(L[static_cast<int64_t>(c) * d + i0 + row], rs[c], v);
+    red[tid] = v;
+    __syncthreads();
+    if (tid < kNb) {
+      double s = 0.0;
+      for (int k = 0; k < 16; ++k) s += red[k * 64 + tid];
+      acc[tid] = tid < rows ? yv[i0 + tid] - s : 0.0;
+    }
+    __syncthreads();
+    v = 0.0;
+    for (int c = row + pq; c < kNb; c += 16) v = fma(Li[c * kLd + row], acc[c], v);
+    red[tid] = v;
+    __syncthreads();
+    if (tid < rows) {
+      double s = 0.0;
+      for (int k = 0; k < 16; ++k) s += red[k * 64 + tid];
+      rs[i0 + tid] = s;
+      h[i0 + tid] += s;
+    }
+  }
+}
+
+}  // namespace
+
+bool refine_small_ok(const Geom& g) { return g.d <= kRsD; }
+
+void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
+                              const double* b, double lambda, const double* norm_ref, double tol,
+                              const double* L, const double* Linv_diag, double* h, int32_t* done,
+                              int32_t* steps, double* relres, int do_solve, hipStream_t st) {
+  hipLaunchKernelGGL(refine_step_small_kernel, dim3(1), dim3(kRsThreads), 0, st, g, part, nparts,
+                     P, b, lambda, norm_ref, tol, L, Linv_diag, h, done, steps, relres, do_solve);
+}
+
+}  // namespace tk

@@ -131,6 +131,32 @@ def test_sketched_low_precision_refined(tk, precision, dims, ranks):
     assert rel(G64.cpu().numpy(), Gr) <= 1e-9
 
 
+# Every rank <= RM (a power of two <= 8) with RM^N <= 64: the refinement's
+# residual keeps Kronecker rows in registers (a sample shared by RM lanes,
+# ranks zero-padded to RM); ragged ranks, a rank-1 mode, orders 1 to 5, and a
+# sample count far below one pass of the grid.
+@pytest.mark.parametrize("precision", ["bf16", "f32"])
+@pytest.mark.parametrize("dims,ranks,s", [
+    ((40, 36, 30), (4, 4, 4), 20000),
+    ((33, 29, 27), (3, 2, 4), 20000),
+    ((12, 11, 10, 9, 8), (2, 2, 2, 2, 2), 20000),
+    ((60, 50), (8, 5), 20000),
+    ((45, 40, 35), (2, 1, 2), 7001),
+    ((70,), (8,), 5000),
+    ((40, 36, 30), (4, 4, 4), 300),
+])
+def test_sketched_refined_register_rows(tk, precision, dims, ranks, s):
+    p, F = _sketch_case(dims, ranks, 15)
+    lam = 1e-2
+    G, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=7, counter=1,
+                                      precision=precision, refine_max=40, refine_tol=1e-13,
+                                      return_info=True)
+    info = info.cpu().numpy()
+    Gr, _, _, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 7, 1)
+    assert info[3] <= 1e-13, info
+    assert rel(G.cpu().numpy(), Gr) <= 1e-9
+
+
 def test_sketched_masked_matches_oracle(tk):
     dims, ranks = (31, 27, 25), (4, 5, 3)
     p, F = _sketch_case(dims, ranks, 6, missing=0.2)
