@@ -168,6 +168,233 @@ __global__ __launch_bounds__(kBlock) void ttm_last_kernel(const T* __restrict__ 
   }
 }
 
+// Q == 1 with few outputs (J <= 8) and I J <= 4096: out[p][j] = sum_i Mat(j, i)
+// in[p][i] streamed at HBM speed without padding J to an MFMA block.  Lane l
+// owns the columns i = 64 W m + W l + k (W elements of 16 bytes per load, m < NM)
+// and keeps Mat for them in registers (NM W J doubles); a wave takes two rows
+// at a time, each lane forms J partial sums per row with FP64 FMAs, and the
+// partials are added across the wave by an xor tree.  Columns past I carry
+// zero weights (their loads are clamped into the row).
+template <class T>
+struct SkinnyVec;
+template <>
+struct SkinnyVec<float> {
+  typedef float __attribute__((ext_vector_type(4))) vec;
+  static constexpr int W = 4;
+};
+template <>
+struct SkinnyVec<double> {
+  typedef double __attribute__((ext_vector_type(2))) vec;
+  static constexpr int W = 2;
+};
+
+template <class T, int J, int NM>
+__global__ __launch_bounds__(kBlock) void ttm_last_skinny_kernel(const T* __restrict__ in,
+                                                                 int64_t P, int64_t I,
+                                                                 const double* __restrict__ M,
+                                                                 bool trans,
+                                                                 double* __restrict__ out,
+                                                                 const int32_t* done) {
+  if (done && *done) return;
+  using V = SkinnyVec<T>;
+  using vec = typename V::vec;
+  constexpr int W = V::W;
+  const int lane = threadIdx.x & 63;
+  double w[NM][W][J];
+  int64_t col[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int64_t c0 = static_cast<int64_t>(m) * 64 * W + lane * W;
+    col[m] = c0 + W <= I ? c0 : (I - W);  // clamped: a whole vector inside the row
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+      for (int j = 0; j < J; ++j) w[m][k][j] = c0 + W <= I ? mat(M, I, J, trans, j, c0 + k) : 0.0;
+  }
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
+  const int64_t wid = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  for (int64_t p0 = 2 * wid; p0 < P; p0 += 2 * waves) {
+    const bool two = p0 + 1 < P;
+    vec x[2][NM];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const T* row = in + (r == 1 && two ? p0 + 1 : p0) * I;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) x[r][m] = *reinterpret_cast<const vec*>(row + col[m]);
+    }
+    double acc[2][J];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < J; ++j) acc[r][j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const double xv = static_cast<double>(x[r][m][k]);
+#pragma unroll
+          for (int j = 0; j < J; ++j) acc[r][j] = fma(xv, w[m][k][j], acc[r][j]);
+        }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        double v = acc[r][j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[r][j] = v;
+      }
+    if (lane < J) {
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        if (j == lane) {
+          v0 = acc[0][j];
+          v1 = acc[1][j];
+        }
+      out[p0 * J + lane] = v0;
+      if (two) out[(p0 + 1) * J + lane] = v1;
+    }
+  }
+}
+
+// The same product when a row is too long for one wave's registers: the
+// workgroup's four waves split each row's columns (wave v owns the columns
+// 64 W (4 m + v) + W l + k), each forms its J partial sums, and the four
+// partials are added in wave order through LDS.  Two rows per iteration.
+template <class T, int J, int NM>
+__global__ __launch_bounds__(kBlock) void ttm_last_skinny_wg_kernel(const T* __restrict__ in,
+                                                                    int64_t P, int64_t I,
+                                                                    const double* __restrict__ M,
+                                                                    bool trans,
+                                                                    double* __restrict__ out,
+                                                                    const int32_t* done) {
+  if (done && *done) return;
+  using V = SkinnyVec<T>;
+  using vec = typename V::vec;
+  constexpr int W = V::W;
+  __shared__ double red[2][kBlock / 64][J];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double w[NM][W][J];
+  int64_t col[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int64_t c0 = (static_cast<int64_t>(m) * (kBlock / 64) + wave) * 64 * W + lane * W;
+    col[m] = c0 + W <= I ? c0 : (I - W);  // clamped: a whole vector inside the row
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+      for (int j = 0; j < J; ++j) w[m][k][j] = c0 + W <= I ? mat(M, I, J, trans, j, c0 + k) : 0.0;
+  }
+  for (int64_t p0 = 2 * static_cast<int64_t>(blockIdx.x); p0 < P; p0 += 2 * gridDim.x) {
+    const bool two = p0 + 1 < P;
+    vec x[2][NM];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const T* row = in + (r == 1 && two ? p0 + 1 : p0) * I;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) x[r][m] = *reinterpret_cast<const vec*>(row + col[m]);
+    }
+    double acc[2][J];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < J; ++j) acc[r][j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const double xv = static_cast<double>(x[r][m][k]);
+#pragma unroll
+          for (int j = 0; j < J; ++j) acc[r][j] = fma(xv, w[m][k][j], acc[r][j]);
+        }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        double v = acc[r][j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[r][j] = v;
+      }
+    __syncthreads();  // the previous rows' partials have been read
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < J; ++j) red[r][wave][j] = acc[r][j];
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * J) {
+      const int r = threadIdx.x / J, j = threadIdx.x % J;
+      if (r == 0 || two) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) v += red[r][q][j];
+        out[(p0 + r) * J + j] = v;
+      }
+    }
+  }
+}
+
+template <class T, int J>
+bool skinny_launch_j(const T* in, int64_t P, int64_t I, const double* M, bool trans, double* out,
+                     hipStream_t st, const int32_t* done) {
+  constexpr int W = SkinnyVec<T>::W;
+  const int64_t nm = cdiv(I, 64 * W);
+  const int64_t want = cdiv(P, 2 * (kBlock / 64));
+  const dim3 grid(static_cast<unsigned>(want < 4096 ? want : 4096));
+#define TK_SKINNY(NMV)                                                                          \
+  if constexpr (NMV * W * J <= 64) {                                                            \
+    if (nm <= NMV) {                                                                            \
+      hipLaunchKernelGGL((ttm_last_skinny_kernel<T, J, NMV>), grid, dim3(kBlock), 0, st, in, P, \
+                         I, M, trans, out, done);                                               \
+      return true;                                                                              \
+    }                                                                                           \
+  }
+  TK_SKINNY(1)
+  TK_SKINNY(2)
+  TK_SKINNY(4)
+  TK_SKINNY(8)
+  TK_SKINNY(16)
+#undef TK_SKINNY
+  // rows longer than one wave holds: four waves per row
+  const int64_t nmw = cdiv(I, 4 * 64 * W);
+  const int64_t wantw = cdiv(P, 2);
+  const dim3 gridw(static_cast<unsigned>(wantw < 8192 ? wantw : 8192));
+#define TK_SKINNY_WG(NMV)                                                                     \
+  if constexpr (NMV * W * J <= 64) {                                                          \
+    if (nmw <= NMV) {                                                                         \
+      hipLaunchKernelGGL((ttm_last_skinny_wg_kernel<T, J, NMV>), gridw, dim3(kBlock), 0, st, \
+                         in, P, I, M, trans, out, done);                                      \
+      return true;                                                                            \
+    }                                                                                         \
+  }
+  TK_SKINNY_WG(1)
+  TK_SKINNY_WG(2)
+  TK_SKINNY_WG(4)
+  TK_SKINNY_WG(8)
+  TK_SKINNY_WG(16)
+#undef TK_SKINNY_WG
+  return false;
+}
+
+template <class T>
+bool skinny_launch(const T* in, int64_t P, int64_t I, const double* M, int64_t J, bool trans,
+                   double* out, hipStream_t st, const int32_t* done) {
+  constexpr int W = SkinnyVec<T>::W;
+  if (I % W != 0 || I < W || (reinterpret_cast<uintptr_t>(in) % 16) != 0) return false;
+  if (J == 1) return skinny_launch_j<T, 1>(in, P, I, M, trans, out, st, done);
+  if (J == 2) return skinny_launch_j<T, 2>(in, P, I, M, trans, out, st, done);
+  if (J == 4) return skinny_launch_j<T, 4>(in, P, I, M, trans, out, st, done);
+  if (J == 8) return skinny_launch_j<T, 8>(in, P, I, M, trans, out, st, done);
+  return false;
+}
+
 // Q > 1: out[p][j][q] = sum_i Mat(j, i) in[p][i][q] -- per p a (J x I) (I x Q)
 // product on v_mfma_f64_16x16x4, J <= 16 JB.  A wave owns 64 consecutive q (four
 // 16-column blocks) and all J outputs; Mat is staged through LDS in chunks of
@@ -237,6 +464,88 @@ __global__ __launch_bounds__(kBlock) void ttm_mid_kernel(const T* __restrict__ i
       }
 }
 
+// Q > 1 with few outputs (J <= 8): out[p][j][q] = sum_i Mat(j, i) in[p][i][q]
+// without padding J to an MFMA block.  A thread owns W consecutive q (one
+// 16-byte load per i) and walks i with four rows of loads in flight, keeping
+// J W FP64 partial sums; Mat(j, i) is the same for the whole wave.
+template <class T, int J>
+__global__ __launch_bounds__(kBlock) void ttm_mid_skinny_kernel(const T* __restrict__ in,
+                                                                int64_t I, int64_t Q,
+                                                                const double* __restrict__ M,
+                                                                bool trans,
+                                                                double* __restrict__ out,
+                                                                const int32_t* done) {
+  if (done && *done) return;
+  using V = SkinnyVec<T>;
+  using vec = typename V::vec;
+  constexpr int W = V::W;
+  const int64_t p = blockIdx.y;
+  const int64_t q0 = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) * W;
+  if (q0 >= Q) return;
+  const T* src = in + p * I * Q + q0;
+  double acc[J][W];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[j][k] = 0.0;
+  int64_t i = 0;
+  for (; i + 4 <= I; i += 4) {
+    vec x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = *reinterpret_cast<const vec*>(src + (i + u) * Q);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const double mv = mat(M, I, J, trans, j, i + u);
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc[j][k] = fma(mv, static_cast<double>(x[u][k]), acc[j][k]);
+      }
+  }
+  for (; i < I; ++i) {
+    const vec x = *reinterpret_cast<const vec*>(src + i * Q);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const double mv = mat(M, I, J, trans, j, i);
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[j][k] = fma(mv, static_cast<double>(x[k]), acc[j][k]);
+    }
+  }
+  double* dst = out + p * J * Q + q0;
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int k = 0; k < W; ++k) dst[j * Q + k] = acc[j][k];
+}
+
+template <class T>
+bool mid_skinny_launch(const T* in, int64_t P, int64_t I, int64_t Q, const double* M, int64_t J,
+                       bool trans, double* out, hipStream_t st, const int32_t* done) {
+  constexpr int W = SkinnyVec<T>::W;
+  if (Q % W != 0 || (reinterpret_cast<uintptr_t>(in) % 16) != 0 || P > 65535) return false;
+  const dim3 grid(static_cast<unsigned>(cdiv(Q / W, kBlock)), static_cast<unsigned>(P));
+  switch (J) {
+    case 1:
+      hipLaunchKernelGGL((ttm_mid_skinny_kernel<T, 1>), grid, dim3(kBlock), 0, st, in, I, Q, M,
+                         trans, out, done);
+      return true;
+    case 2:
+      hipLaunchKernelGGL((ttm_mid_skinny_kernel<T, 2>), grid, dim3(kBlock), 0, st, in, I, Q, M,
+                         trans, out, done);
+      return true;
+    case 4:
+      hipLaunchKernelGGL((ttm_mid_skinny_kernel<T, 4>), grid, dim3(kBlock), 0, st, in, I, Q, M,
+                         trans, out, done);
+      return true;
+    case 8:
+      hipLaunchKernelGGL((ttm_mid_skinny_kernel<T, 8>), grid, dim3(kBlock), 0, st, in, I, Q, M,
+                         trans, out, done);
+      return true;
+    default:
+      return false;
+  }
+}
+
 constexpr int64_t kTtmThreadsWanted = 65536;
 
 template <class T>
@@ -247,11 +556,17 @@ void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const d
   for (int m = 0; m < mode; ++m) P *= dims[m];
   for (int m = mode + 1; m < order; ++m) Q *= dims[m];
   const int64_t I = dims[mode];
+  if (Q == 1 && J <= 8 && I * J <= 16384 && P >= 4096 &&
+      skinny_launch(in, P, I, M, J, trans, out, st, done))
+    return;
   if (Q == 1 && J <= kMaxRank && P >= 64 * 256) {
     hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
                        0, st, in, P, I, M, J, trans, out, done);
     return;
   }
+  if (Q >= 256 && J <= 8 && P * cdiv(Q, 1024) >= 256 &&
+      mid_skinny_launch(in, P, I, Q, M, J, trans, out, st, done))
+    return;
   if (Q >= 64 && J <= kMaxRank && P <= 65535 && P * cdiv(Q, 256) >= 512) {
     const dim3 grid(static_cast<unsigned>(cdiv(Q, 256)), static_cast<unsigned>(P));
     if (J <= 16)

@@ -217,6 +217,27 @@ def test_exact_core_long_fibres_matches_oracle(tk, dims, ranks, dtype):
     assert rel(G.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-6)
 
 
+# Last-mode contractions with J in {1, 2, 4, 8} outputs and I J <= 4096 stream
+# rows with per-lane weights in registers: J = 4 over 1024 columns, J = 8 with a
+# ragged last vector of columns, J = 1 with an odd number of rows.
+# Rows longer than one wave's registers (I J > 4096) are split over a
+# workgroup's four waves: J = 4 over 2600 columns, J = 2 over 3000 (odd rows).
+@pytest.mark.parametrize("dims,ranks,dtype", [
+    ((70, 65, 1024), (3, 2, 4), "f32"),
+    ((90, 50, 252), (2, 3, 8), "f64"),
+    ((101, 41, 100), (2, 2, 1), "f32"),
+    ((4100, 2600), (3, 4), "f32"),
+    ((4097, 3000), (5, 2), "f64"),
+])
+def test_exact_core_skinny_last_mode(tk, dims, ranks, dtype):
+    p, F = _sketch_case(dims, ranks, 16, dtype=dtype)
+    lam = 1e-3
+    G = tk.core_update_exact(T(p["X"]), [T(A) for A in F], lam)
+    ref = oracle.core_update_exact(p["X"].astype(np.float64), [A.astype(np.float64) for A in F],
+                                   lam)
+    assert rel(G.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-6)
+
+
 def test_exact_core_all_observed_mask_equals_unmasked(tk):
     p, F = _sketch_case((19, 17, 15), (3, 4, 5), 11)
     X, FF = T(p["X"]), [T(A) for A in F]
@@ -269,6 +290,25 @@ def test_factor_update_mid_mode_contraction(tk, dims, ranks, dtype, modes):
         Gr = G.astype(p["X"].dtype).astype(np.float64)
         ref = oracle.factor_update(Xf, Gr, Ff, n, lam)
         assert rel(A.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-5), n
+
+
+# Middle-mode contractions with J in {1, 2, 4, 8} and long q runs stream along
+# q without padding J: J = 4 (f32), J = 8 and J = 2 (f64, ragged q runs).
+@pytest.mark.parametrize("dims,ranks,dtype", [
+    ((300, 20, 512), (2, 4, 3), "f32"),
+    ((280, 9, 260), (3, 8, 2), "f64"),
+    ((270, 13, 258), (2, 2, 3), "f64"),
+])
+def test_factor_update_mid_mode_skinny(tk, dims, ranks, dtype):
+    p, F = _sketch_case(dims, ranks, 17, dtype=dtype)
+    lam = 1e-2
+    G = np.random.default_rng(5).standard_normal(ranks)
+    Xf = p["X"].astype(np.float64)
+    Ff = [A.astype(np.float64) for A in F]
+    Gt = G.astype(p["X"].dtype)
+    A = tk.factor_update(T(p["X"]), T(Gt), [T(B) for B in F], 2, lam)
+    ref = oracle.factor_update(Xf, Gt.astype(np.float64), Ff, 2, lam)
+    assert rel(A.cpu().numpy(), ref) <= (1e-10 if dtype == "f64" else 1e-5)
 
 
 # The loss expands the last mode on MFMA in k-steps of 4 ranks (1, 2, 4, 8 or 16

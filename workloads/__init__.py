@@ -24,6 +24,10 @@ Workloads (shapes follow the paper's experiments, Sec. 5, and the parity cases):
   1024^3 float32, fitted at rank 4^3 from the U[0,1] initial state of Alg. 2;
   lambda 1e-3; the Alg. 1 sample count for eps = delta = 0.1 at d = 64
   (1687583 samples).  Generated in mode-0 slabs with one child generator each.
+* ``t1big``: the same protocol at 2560^3 float32 (67 GB), generated on the
+  device by ``table1_problem_device`` (torch's seeded device generator, slab by
+  slab); no oracle reads it.  It shows the sampled update's cost staying fixed
+  while the exact update's pass over X grows with the tensor.
 """
 import numpy as np
 
@@ -43,6 +47,9 @@ CONFIGS = {
     "t1": dict(dims=(1024, 1024, 1024), ranks=(4, 4, 4), dtype="f32", lam=1e-3,
                samples=1687583, seed=11, protocol="table1", true_rank=(8, 8, 8), init_seed=1011,
                gram="bf16"),
+    "t1big": dict(dims=(2560, 2560, 2560), ranks=(4, 4, 4), dtype="f32", lam=1e-3,
+                  samples=1687583, seed=12, protocol="table1_device", true_rank=(8, 8, 8),
+                  init_seed=1012, gram="bf16"),
 }
 
 NP_DTYPES = {"f64": np.float64, "f32": np.float32}
@@ -118,6 +125,13 @@ def config_problem(name, **overrides):
     """The named workload (see module docstring) with optional overrides."""
     cfg = dict(CONFIGS[name])
     cfg.update(overrides)
+    if cfg.get("protocol") == "table1_device":
+        dev = overrides.get("device", "cuda")
+        prob = table1_problem_device(cfg["dims"], cfg["seed"], dev, cfg["true_rank"])
+        _, F0 = als_init(cfg["dims"], cfg["ranks"], cfg["init_seed"], "f64")
+        prob["factors_fit"] = F0
+        prob["cfg"] = cfg
+        return prob
     if cfg.get("protocol") == "table1":
         prob = table1_problem(cfg["dims"], cfg["seed"], cfg["dtype"], cfg["true_rank"], slabs=True)
         _, F0 = als_init(cfg["dims"], cfg["ranks"], cfg["init_seed"], "f64")
@@ -156,6 +170,34 @@ def table1_problem(dims, seed, dtype="f32", true_rank=(8, 8, 8), slabs=False, sl
         hit = child.random(xs.shape) < 0.01
         xs[hit] += child.standard_normal(int(hit.sum()))
         X[i0:i1] = xs
+    return dict(X=X, G_true=G, factors_true=A, mask=None)
+
+
+def table1_problem_device(dims, seed, device, true_rank=(8, 8, 8), slab_rows=64):
+    """Sec. 5 protocol built on a torch device in float32, for tensors too large
+    for host memory: U[0,1] core and factors from default_rng(seed) (host, as
+    in table1_problem), the low-rank part formed slab by slab on the device, and
+    N(0,1) noise on 1 % of the entries from a torch generator seeded with seed.
+    Returns X (device tensor), G_true and factors_true (numpy)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    A = [_factor(rng, I, R, "uniform") for I, R in zip(dims, true_rank)]
+    G = rng.random(true_rank)
+    W = G
+    for n in range(1, len(dims)):
+        W = _mode_mul(W, A[n], n)
+    W0 = torch.from_numpy(np.ascontiguousarray(W.reshape(true_rank[0], -1))).to(device)
+    A0 = torch.from_numpy(A[0]).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    X = torch.empty(dims, dtype=torch.float32, device=device)
+    for i0 in range(0, dims[0], slab_rows):
+        i1 = min(dims[0], i0 + slab_rows)
+        xs = (A0[i0:i1] @ W0).reshape((i1 - i0,) + tuple(dims[1:]))
+        hit = torch.rand(xs.shape, generator=gen, device=device, dtype=torch.float32) < 0.01
+        noise = torch.randn(xs.shape, generator=gen, device=device, dtype=torch.float32)
+        X[i0:i1] = (xs + hit * noise.double()).float()
+        del xs, hit, noise
     return dict(X=X, G_true=G, factors_true=A, mask=None)
 
 
