@@ -150,7 +150,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
     ap.add_argument("--refine-max", type=int, default=8)
-    ap.add_argument("--cpu-samples", type=int, default=32768)
+    ap.add_argument("--cpu-samples", type=int, default=131072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip exact/ALS comparison timings")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

@@ -384,12 +384,14 @@ def tune_batched(Xs, factors_list, lams, samples, seeds=None, counters=None, pro
 def core_update_sketched_batched(Xs, factors_list, lams, samples, seeds=None, counters=None,
                                  problems=None, precision="bf16", config=None, refine_max=12,
                                  refine_tol=1e-13, masks=None, out=None, return_info=False,
-                                 check=True, workspace=None, status=None):
+                                 check=True, workspace=None, status=None, info=None):
     """Sampled core updates of a batch of problems with one persistent Gram launch.
 
     problems[k] (default k) is the sampler's problem field of problem k, so
     problem k draws the samples of core_update_sketched(..., problem=k).
-    Returns the list of cores (and the (count, INFO_LEN) info tensor).
+    Returns the list of cores (and the (count, INFO_LEN) info tensor).  `info`
+    (optional, (count, INFO_LEN) float64 on the device) receives the per-problem
+    info rows; it is returned when return_info is set.
     """
     lib = L.load()
     P, O = _batch(Xs, factors_list, lams, samples, seeds, counters, problems, precision,
@@ -402,8 +404,11 @@ def core_update_sketched_batched(Xs, factors_list, lams, samples, seeds=None, co
         for X, F in zip(Xs, factors_list)]
     ptrs = (ctypes.c_void_p * count)(*[c.data_ptr() for c in cores])
     st = status if status is not None else torch.zeros(count, dtype=torch.int32, device=dev)
-    info = torch.empty((count, L.INFO_LEN), dtype=torch.float64, device=dev) if return_info \
-        else None
+    if info is None and return_info:
+        info = torch.empty((count, L.INFO_LEN), dtype=torch.float64, device=dev)
+    if info is not None and (tuple(info.shape) != (count, L.INFO_LEN) or
+                             info.dtype != torch.float64 or not info.is_contiguous()):
+        raise ValueError("info must be a contiguous (count, INFO_LEN) float64 tensor")
     nb = lib.tucker_workspace_bytes_batched(P, O, count, ctypes.byref(cfg) if cfg else None)
     if nb == 0:
         raise ValueError("unsupported batch")
@@ -449,7 +454,7 @@ class BatchedSketchedUpdate:
                       for X, F in zip(Xs, factors_list)]
         kw = dict(seeds=seeds, counters=counters, problems=problems, precision=precision,
                   config=config, refine_max=refine_max, refine_tol=refine_tol, masks=masks,
-                  out=self.cores, workspace=self.workspace, status=self.status)
+                  out=self.cores, workspace=self.workspace, status=self.status, info=self.info)
         # eager run first (checks the status words), then capture
         core_update_sketched_batched(Xs, factors_list, lams, samples, check=True, **kw)
         torch.cuda.synchronize(dev)

@@ -105,6 +105,10 @@ def test_graph_replays_match_eager(tk):
         for k in range(len(probs)):
             assert torch.equal(out[k], eager[k]), (rep, k)
         assert int(upd.status.abs().sum().item()) == 0
+        # the captured call writes its info rows: sample count, refinement residual
+        info = upd.info.cpu().numpy()
+        assert np.array_equal(info[:, 0], [float(p["samples"]) for p in probs]), info[:, 0]
+        assert (info[:, 3] <= 1e-13).all(), info[:, 3]
 
 
 def test_graph_replay_reads_new_inputs(tk):

@@ -326,3 +326,11 @@ def test_normal_equation_residual_pin():
     rhs = rows.T @ (w * X.reshape(-1)[np.ravel_multi_index(tuple(idx), X.shape)])
     ref = np.linalg.norm(gram @ Gp.reshape(-1) - rhs) / np.linalg.norm(rhs)
     assert abs(oracle.normal_equation_residual(X, F, lam, idx, w, Gp, chunk=97) - ref) < 1e-12
+
+
+def test_table1_workload_sample_count_is_alg1():
+    """The t1 / t1big workloads use Alg. 1's sample count for eps = delta = 0.1 at d = 4^3."""
+    for name in ("t1", "t1big"):
+        cfg = workloads.CONFIGS[name]
+        d = int(np.prod(cfg["ranks"]))
+        assert cfg["samples"] == oracle.s_theory(d, 0.1, 0.1), name
