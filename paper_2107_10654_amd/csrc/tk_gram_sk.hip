@@ -29,13 +29,14 @@ namespace {
 constexpr int kSkRT = kRowChunk + 4;  // padded LDS row: conflict-free 16-byte reads
 
 // Tile edge T: 64 and 128 use 2 x 2 waves (32 x 32 or 64 x 64 each, up to 4
-// or 3 workgroups per CU); 256 uses 4 x 2 waves of 64 x 128 in one
-// 512-thread workgroup per CU, which halves the row formation per MFMA.
+// or 3 workgroups per CU); 256 uses 4 x 4 waves of 64 x 64 in one
+// 1024-thread workgroup per CU, which halves the row formation per MFMA and
+// keeps four waves per SIMD to hide the formation's LDS latency.
 template <int T>
 struct SkTile {
   static constexpr int NO = T / 2 + 1;  // outer indices per tile when R_L >= 2
   static constexpr int WAVES_R = T == 256 ? 4 : 2;
-  static constexpr int WAVES_C = 2;
+  static constexpr int WAVES_C = T == 256 ? 4 : 2;
   static constexpr int THREADS = 64 * WAVES_R * WAVES_C;
   static constexpr int WG_PER_CU = T == 128 ? 3 : (T == 64 ? 4 : 1);
 };
