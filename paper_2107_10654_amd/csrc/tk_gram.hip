@@ -336,8 +336,10 @@ constexpr int kVO = 65;         // outer indices per workgroup
 constexpr int kVRT = kVK + 1;   // LDS row stride (doubles)
 constexpr int kVPF = (kVK * kMaxSumR + kBlock - 1) / kBlock;
 
+// The staged sample rows (sum_r x kVRT doubles) live in dynamic LDS sized by
+// the problem's sum_r at launch, so that small rank sums leave room for more
+// workgroups per CU.
 struct VecSmem {
-  double rT[kMaxSumR * kVRT];
   double sc[kVK];
   double O[kVO][kVK + 1];  // padded: MFMA fragments read 16 rows at one column
   unsigned char offs[kVO][kMaxOrder];
@@ -379,23 +381,28 @@ __device__ inline VecGeo vec_setup(const Geom& g, VecSmem& sm) {
   return vg;
 }
 
+// NPF prefetch registers per thread: kVK sum_r <= NPF kBlock
+constexpr int kVPFSmall = (kVK * 64 + kBlock - 1) / kBlock;  // sum_r <= 64
+
+template <int NPF>
 __device__ inline void vec_fetch(const Geom& g, const double* rows, int64_t c, double* pf) {
   const int nval = kVK * g.sum_r;
   const double* src = rows + c * nval;
 #pragma unroll
-  for (int k = 0; k < kVPF; ++k) {
+  for (int k = 0; k < NPF; ++k) {
     const int e = threadIdx.x + k * kBlock;
     pf[k] = (e < nval) ? src[e] : 0.0;
   }
 }
 
-__device__ inline void vec_commit(const Geom& g, VecSmem& sm, const double* pf,
+template <int NPF>
+__device__ inline void vec_commit(const Geom& g, VecSmem& sm, double* rT, const double* pf,
                                   const double* coef, int64_t c, int64_t s) {
   const int nval = kVK * g.sum_r;
 #pragma unroll
-  for (int k = 0; k < kVPF; ++k) {
+  for (int k = 0; k < NPF; ++k) {
     const int e = threadIdx.x + k * kBlock;
-    if (e < nval) sm.rT[(e >> 5) * kVRT + (e & 31)] = pf[k];
+    if (e < nval) rT[(e >> 5) * kVRT + (e & 31)] = pf[k];
   }
   for (int t = threadIdx.x; t < kVK; t += kBlock) {
     const int64_t tt = c * kVK + t;
@@ -404,12 +411,12 @@ __device__ inline void vec_commit(const Geom& g, VecSmem& sm, const double* pf,
 }
 
 // O[oi][t] = coef_t prod_{n != L} q^(n)[digit]
-__device__ inline void vec_outer(const Geom& g, VecSmem& sm, const VecGeo& vg) {
+__device__ inline void vec_outer(const Geom& g, VecSmem& sm, const double* rT, const VecGeo& vg) {
   const int N = g.order;
   for (int e = threadIdx.x; e < vg.no * kVK; e += kBlock) {
     const int oi = e >> 5, t = e & 31;
     double v = sm.sc[t];
-    for (int k = 0; k < N - 1; ++k) v *= sm.rT[sm.offs[oi][k] * kVRT + t];
+    for (int k = 0; k < N - 1; ++k) v *= rT[sm.offs[oi][k] * kVRT + t];
     sm.O[oi][t] = v;
   }
 }
@@ -424,6 +431,7 @@ __device__ inline double mfma_f64_operand(const double* base, int stride, int ro
   return row < nrows ? v : 0.0;
 }
 
+template <int NPF>
 __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double* __restrict__ rows,
                                                             const double* __restrict__ c,
                                                             int64_t s, int64_t cps,
@@ -431,6 +439,7 @@ __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double
                                                             const int32_t* done) {
   if (done && *done) return;
   __shared__ VecSmem sm;
+  extern __shared__ double rT[];  // sum_r x kVRT
   const VecGeo vg = vec_setup(g, sm);
   const int sl = g.soff[g.last];
   const int RL = g.ranks[g.last];
@@ -443,16 +452,16 @@ __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double
   doublex4 acc[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) acc[q] = doublex4{0, 0, 0, 0};
-  double pf[kVPF];
+  double pf[NPF];
   if (ca < cb) {
-    vec_fetch(g, rows, ca, pf);
-    vec_commit(g, sm, pf, c, ca, s);
+    vec_fetch<NPF>(g, rows, ca, pf);
+    vec_commit<NPF>(g, sm, rT, pf, c, ca, s);
   }
   __syncthreads();
   for (int64_t ch = ca; ch < cb; ++ch) {
     const bool more = ch + 1 < cb;
-    if (more) vec_fetch(g, rows, ch + 1, pf);
-    vec_outer(g, sm, vg);
+    if (more) vec_fetch<NPF>(g, rows, ch + 1, pf);
+    vec_outer(g, sm, rT, vg);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -464,13 +473,13 @@ __global__ __launch_bounds__(kBlock) void rows_t_vec_kernel(Geom g, const double
           const int t = kk + lane / 16;
           const double av = mfma_f64_operand(&sm.O[0][0], kVK + 1, ob * 16 + lane % 16, vg.no, t);
           const double bv =
-              mfma_f64_operand(sm.rT + sl * kVRT, kVRT, lb * 16 + lane % 16, RL, t);
+              mfma_f64_operand(rT + sl * kVRT, kVRT, lb * 16 + lane % 16, RL, t);
           acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
         }
       }
     }
     __syncthreads();
-    if (more) vec_commit(g, sm, pf, c, ch + 1, s);
+    if (more) vec_commit<NPF>(g, sm, rT, pf, c, ch + 1, s);
     __syncthreads();
   }
   // accumulator register v of lane l: o = ob 16 + l / 16 + 4 v, l_ = lb 16 + l % 16
@@ -515,6 +524,7 @@ __global__ __launch_bounds__(kBlock) void sum_parts_kernel(const double* __restr
 // v_mfma_f64_16x16x4 (16 x 16 blocks (o, t) shared by the 4 waves, K = R_L); each
 // lane then multiplies its accumulators by O and the partial sums over o are
 // reduced across lanes and waves.
+template <int NPF>
 __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* __restrict__ rows,
                                                           const double* __restrict__ h,
                                                           int64_t s, int64_t cps,
@@ -522,6 +532,7 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
                                                           const int32_t* done) {
   if (done && *done) return;
   __shared__ VecSmem sm;
+  extern __shared__ double rT[];  // sum_r x kVRT
   const VecGeo vg = vec_setup(g, sm);
   const int sl = g.soff[g.last];
   const int RL = g.ranks[g.last];
@@ -539,16 +550,16 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
   const int64_t ca = static_cast<int64_t>(blockIdx.y) * cps;
   int64_t cb = ca + cps;
   if (cb > row_chunks(s)) cb = row_chunks(s);
-  double pf[kVPF];
+  double pf[NPF];
   if (ca < cb) {
-    vec_fetch(g, rows, ca, pf);
-    vec_commit(g, sm, pf, nullptr, ca, s);
+    vec_fetch<NPF>(g, rows, ca, pf);
+    vec_commit<NPF>(g, sm, rT, pf, nullptr, ca, s);
   }
   __syncthreads();
   for (int64_t ch = ca; ch < cb; ++ch) {
     const bool more = ch + 1 < cb;
-    if (more) vec_fetch(g, rows, ch + 1, pf);
-    vec_outer(g, sm, vg);
+    if (more) vec_fetch<NPF>(g, rows, ch + 1, pf);
+    vec_outer(g, sm, rT, vg);
     __syncthreads();
     double ct[2] = {0.0, 0.0};  // this lane's partial c for t = tb 16 + lane % 16, tb = 0, 1
 #pragma unroll
@@ -560,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
         for (int kl = 0; kl < RL; kl += 4) {
           const int l = kl + lane / 16;
           const double av = h_at(ob * 16 + lane % 16, l);
-          const double bq = sm.rT[(sl + (l < RL ? l : RL - 1)) * kVRT + tb * 16 + lane % 16];
+          const double bq = rT[(sl + (l < RL ? l : RL - 1)) * kVRT + tb * 16 + lane % 16];
           const double bv = l < RL ? bq : 0.0;
           u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
         }
@@ -596,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void rows_dot_kernel(Geom g, const double* 
             sm.red[0][threadIdx.x] + sm.red[1][threadIdx.x] + sm.red[2][threadIdx.x] +
             sm.red[3][threadIdx.x];
     }
-    if (more) vec_commit(g, sm, pf, nullptr, ch + 1, s);
+    if (more) vec_commit<NPF>(g, sm, rT, pf, nullptr, ch + 1, s);
     __syncthreads();
   }
 }
@@ -1267,9 +1278,14 @@ void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, co
 void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,
                        double* part, double* out, const int32_t* done, hipStream_t st) {
   const VecPlan vp = plan_vec(g, s);
-  hipLaunchKernelGGL(rows_t_vec_kernel,
-                     dim3(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit)),
-                     dim3(kBlock), 0, st, g, rows64, c, s, vp.cps, part, done);
+  const size_t lds = sizeof(double) * static_cast<size_t>(g.sum_r) * kVRT;
+  const dim3 grid(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit));
+  if (g.sum_r <= 64)
+    hipLaunchKernelGGL(rows_t_vec_kernel<kVPFSmall>, grid, dim3(kBlock), lds, st, g, rows64, c, s,
+                       vp.cps, part, done);
+  else
+    hipLaunchKernelGGL(rows_t_vec_kernel<kVPF>, grid, dim3(kBlock), lds, st, g, rows64, c, s,
+                       vp.cps, part, done);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(static_cast<unsigned>(cdiv(g.d, kBlock))),
                      dim3(kBlock), 0, st, static_cast<const double*>(part), vp.nsplit, g.d, out,
                      done);
@@ -1279,9 +1295,14 @@ void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
                           const double* weff, const double* h, int64_t s, double* part, double* c,
                           const int32_t* done, hipStream_t st) {
   const VecPlan vp = plan_vec(g, s);
-  hipLaunchKernelGGL(rows_dot_kernel,
-                     dim3(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit)),
-                     dim3(kBlock), 0, st, g, rows64, h, s, vp.cps, part, done);
+  const size_t lds = sizeof(double) * static_cast<size_t>(g.sum_r) * kVRT;
+  const dim3 grid(static_cast<unsigned>(vp.nr), static_cast<unsigned>(vp.nsplit));
+  if (g.sum_r <= 64)
+    hipLaunchKernelGGL(rows_dot_kernel<kVPFSmall>, grid, dim3(kBlock), lds, st, g, rows64, h, s,
+                       vp.cps, part, done);
+  else
+    hipLaunchKernelGGL(rows_dot_kernel<kVPF>, grid, dim3(kBlock), lds, st, g, rows64, h, s,
+                       vp.cps, part, done);
   hipLaunchKernelGGL(dot_finish_kernel, dim3(static_cast<unsigned>(cdiv(s, kBlock))), dim3(kBlock),
                      0, st, static_cast<const double*>(part), vp.nr, s, xw, weff, c, done);
 }

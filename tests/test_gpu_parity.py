@@ -157,6 +157,21 @@ def test_sketched_refined_register_rows(tk, precision, dims, ranks, s):
     assert rel(G.cpu().numpy(), Gr) <= 1e-9
 
 
+# d > 256 with a rank sum above 64: the large-d refinement kernels with their
+# long prefetch (rows staged through LDS sized by the rank sum).
+@pytest.mark.parametrize("precision", ["bf16", "f32"])
+def test_sketched_refined_wide_rank_sum(tk, precision):
+    p, F = _sketch_case((80, 70), (40, 30), 18)
+    lam = 1e-2
+    G, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, 6000, seed=3,
+                                      precision=precision, refine_max=40, refine_tol=1e-13,
+                                      return_info=True)
+    info = info.cpu().numpy()
+    Gr, _, _, _ = oracle.fast_core_tensor_update(p["X"], F, lam, 6000, 3, 0)
+    assert info[3] <= 1e-13, info
+    assert rel(G.cpu().numpy(), Gr) <= 1e-9
+
+
 def test_sketched_masked_matches_oracle(tk):
     dims, ranks = (31, 27, 25), (4, 5, 3)
     p, F = _sketch_case(dims, ranks, 6, missing=0.2)
