@@ -669,10 +669,16 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
       launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
       launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
     }
-    launch_copy_f64(g.d, h, w.ph_a, st);
-    const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st, w.done);
-    launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
-                        w.done, w.steps, w.relres, k < iters ? 1 : 0, st);
+    if (refine_check_p_ok(g)) {
+      launch_refine_check_p(g, w.r, h, w.lev.P, b, lambda, norm_ref,
+                            refine ? R.o->refine_tol : -1.0, w.done, w.steps, w.relres,
+                            k < iters ? 1 : 0, st);
+    } else {
+      launch_copy_f64(g.d, h, w.ph_a, st);
+      const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st, w.done);
+      launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
+                          w.done, w.steps, w.relres, k < iters ? 1 : 0, st);
+    }
     if (k < iters) {
       launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, R.status, st);
       launch_axpy(g.d, 1.0, w.r, h, w.done, st);

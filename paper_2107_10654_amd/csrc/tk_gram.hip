@@ -279,10 +279,11 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(Geom g, const In* __re
   const int64_t j = e;
   double v = 0.0;
   for (int k = 0; k < ksplit; ++k) v += static_cast<double>(part[static_cast<int64_t>(k) * d * d + i * d + j]);
+  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
   double p = 1.0;
-  int64_t a = i, b = j;
+  uint32_t a = static_cast<uint32_t>(i), b = static_cast<uint32_t>(j);
   for (int n = g.order - 1; n >= 0; --n) {
-    const int R = g.ranks[n];
+    const uint32_t R = static_cast<uint32_t>(g.ranks[n]);
     p *= P[g.roff[n] + (a % R) * R + (b % R)];
     a /= R;
     b /= R;

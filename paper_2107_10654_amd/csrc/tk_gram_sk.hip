@@ -379,10 +379,11 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
     const int64_t slot = index[w] + (tile0 + tau - first);
     v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
   }
+  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
   double p = 1.0;
-  int64_t a = i, b = j;
+  uint32_t a = static_cast<uint32_t>(i), b = static_cast<uint32_t>(j);
   for (int n = g.order - 1; n >= 0; --n) {
-    const int R = g.ranks[n];
+    const uint32_t R = static_cast<uint32_t>(g.ranks[n]);
     p *= P[g.roff[n] + (a % R) * R + (b % R)];
     a /= R;
     b /= R;
@@ -451,10 +452,11 @@ __global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_split_kernel(
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < kAsmWaves; ++k) sum += red[k][lane];
+  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
   double p = 1.0;
-  int64_t a = i, b = j;
+  uint32_t a = static_cast<uint32_t>(i), b = static_cast<uint32_t>(j);
   for (int nn = g.order - 1; nn >= 0; --nn) {
-    const int R = g.ranks[nn];
+    const uint32_t R = static_cast<uint32_t>(g.ranks[nn]);
     p *= P[g.roff[nn] + (a % R) * R + (b % R)];
     a /= R;
     b /= R;
@@ -495,10 +497,11 @@ __global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_one_tile_kernel(
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < kAsmWaves; ++k) sum += red[k][lane];
+  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
   double p = 1.0;
-  int64_t a = i, b = j;
+  uint32_t a = static_cast<uint32_t>(i), b = static_cast<uint32_t>(j);
   for (int nn = g.order - 1; nn >= 0; --nn) {
-    const int R = g.ranks[nn];
+    const uint32_t R = static_cast<uint32_t>(g.ranks[nn]);
     p *= P[g.roff[nn] + (a % R) * R + (b % R)];
     a /= R;
     b /= R;

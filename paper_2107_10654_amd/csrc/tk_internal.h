@@ -175,6 +175,13 @@ int64_t launch_resid_small_parts(const Geom& g, const int32_t* idx, const double
 // relres <= tol, else (when do_solve) h += (L L^T)^{-1} r with L in M and the
 // diagonal-block inverses; returns at entry once done is set.
 bool refine_small_ok(const Geom& g);
+// For d <= 8192: P h applied in one workgroup, then r = r + b - lambda P h and the
+// same test (done / steps / relres) as launch_refine_check.
+bool refine_check_p_ok(const Geom& g);
+void launch_refine_check_p(const Geom& g, double* r, const double* h, const double* P,
+                           const double* b, double lambda, const double* norm_ref, double tol,
+                           int32_t* done, int32_t* steps, double* relres, int count_step,
+                           hipStream_t st);
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
                               const double* b, double lambda, const double* norm_ref, double tol,
                               const double* L, const double* Linv_diag, double* h, int32_t* done,

@@ -193,9 +193,94 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
   }
 }
 
+// The check of one refinement step for larger d (up to kPcD), in one
+// workgroup: t = P h mode by mode, each output element from the previous
+// buffer into the other (two d-vectors in dynamic LDS), then
+// r = r + b - lambda t, relres = ||r|| / ||norm_ref||, done once relres <= tol
+// (else steps += 1 when count_step).  r holds the summed data term on entry and
+// the residual on exit.
+constexpr int kPcD = 8192;
+
+__global__ __launch_bounds__(kRsThreads) void refine_check_p_kernel(
+    Geom g, double* __restrict__ r, const double* __restrict__ h, const double* __restrict__ P,
+    const double* __restrict__ b, double lambda, const double* __restrict__ norm_ref, double tol,
+    int32_t* done, int32_t* steps, double* relres, int count_step) {
+  if (*done) return;
+  extern __shared__ double tbuf[];  // 2 x d
+  __shared__ double red[64];
+  const int tid = threadIdx.x;
+  const int d = static_cast<int>(g.d);
+  const int N = g.order;
+  double* cur = tbuf;
+  double* nxt = tbuf + d;
+  for (int e = tid; e < d; e += kRsThreads) cur[e] = h[e];
+  __syncthreads();
+  for (int n = 0; n < N; ++n) {
+    const int R = g.ranks[n];
+    int stride = 1;
+    for (int m = n + 1; m < N; ++m) stride *= g.ranks[m];
+    const double* Pn = P + g.roff[n];
+    for (int e = tid; e < d; e += kRsThreads) {
+      const int j = (e / stride) % R;
+      const int base = e - j * stride;
+      const double* prow = Pn + j * R;
+      double v0 = 0.0, v1 = 0.0;
+      int i = 0;
+      for (; i + 2 <= R; i += 2) {
+        v0 = fma(prow[i], cur[base + i * stride], v0);
+        v1 = fma(prow[i + 1], cur[base + (i + 1) * stride], v1);
+      }
+      if (i < R) v0 = fma(prow[i], cur[base + i * stride], v0);
+      nxt[e] = v0 + v1;
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  double a2 = 0.0, n2 = 0.0;
+  for (int e = tid; e < d; e += kRsThreads) {
+    double v = r[e];
+    if (b) v += b[e];
+    v = fma(-lambda, cur[e], v);
+    r[e] = v;
+    a2 = fma(v, v, a2);
+    n2 = fma(norm_ref[e], norm_ref[e], n2);
+  }
+  const double sa = block_sum(a2, red);
+  const double sn = block_sum(n2, red + 32);
+  if (tid == 0) {
+    const double rel = sn > 0.0 ? sqrt(sa / sn) : sqrt(sa);
+    *relres = rel;
+    if (rel <= tol)
+      *done = 1;
+    else if (count_step)
+      *steps += 1;
+  }
+}
+
 }  // namespace
 
 bool refine_small_ok(const Geom& g) { return g.d <= kRsD; }
+
+bool refine_check_p_ok(const Geom& g) { return g.d <= kPcD; }
+
+void launch_refine_check_p(const Geom& g, double* r, const double* h, const double* P,
+                           const double* b, double lambda, const double* norm_ref, double tol,
+                           int32_t* done, int32_t* steps, double* relres, int count_step,
+                           hipStream_t st) {
+  const size_t lds = 2 * sizeof(double) * static_cast<size_t>(g.d);
+  static bool attr = false;  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_check_p_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(2 * sizeof(double) * kPcD));
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL(refine_check_p_kernel, dim3(1), dim3(kRsThreads), lds, st, g, r, h, P, b,
+                     lambda, norm_ref, tol, done, steps, relres, count_step);
+}
 
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
                               const double* b, double lambda, const double* norm_ref, double tol,
