@@ -19,20 +19,38 @@ constexpr int LDA = NB + 1;
 
 // ---- diagonal tile: L_kk and its inverse
 // Blocked over four 16-column panels.  Wave 0 factors (and inverts) each
-// 16 x 16 diagonal panel in registers, lane r owning row r, with lane
-// broadcasts (readlane) in place of barriers; the workgroup then solves the
+// 16 x 16 diagonal panel in registers, lane r owning row r (each 16-lane row of
+// the wave holds a copy), with DPP row broadcasts in place of barriers; the workgroup then solves the
 // rows below the panel and updates the trailing triangle.  The 64 x 64
 // inverse is assembled from the four 16 x 16 inverses block row by block row.
 constexpr int PB = 16;
 
-// value of v in lane l (l wave-uniform): v_readlane into a scalar register,
-// a few cycles instead of an LDS round trip of a cross-lane shuffle
-__device__ inline double lane_value(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), l);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), l);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                              static_cast<unsigned int>(lo));
+// value of v in lane c of this lane's 16-lane row (c a constant after unrolling):
+// the 64-bit DPP row broadcast, one vector move, so the panel factor keeps its
+// broadcasts out of scalar registers (no readlane hazards or spills)
+template <int C>
+__device__ inline double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + C, 0xF, 0xF, true);
+}
+__device__ inline double row_value(double v, int c) {
+  switch (c) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+  }
 }
 
 // 1 / sqrt(x) for x > 0 to FP64 accuracy: the hardware estimate refined by
@@ -70,43 +88,42 @@ __device__ __attribute__((always_inline)) inline void diag_factor(double* A, dou
       for (int c = 0; c < PB; ++c) a[c] = (c <= r) ? A[(c0 + r) * LDA + c0 + c] : 0.0;
       double pm = 1e308;
       bool nb_ = false;
-      double rinv[PB];  // 1 / L[j][j] (the same in every lane)
+      // the inverse is eliminated alongside the factor: lane r holds row r of
+      // Z, the forward elimination of L Z' = I without the final row scaling,
+      // so row j of the inverse is Z[j] / L[j][j] once column j is factored
+      double z[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) z[c] = (c == r) ? 1.0 : 0.0;
+      double yr = 1.0;  // 1 / L[r][r]
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
-        double pj = lane_value(a[j], j);
+        double pj = row_value(a[j], j);
         if (!(pj > 0.0)) {
           nb_ = true;
           pj = 1.0;
         }
         const double y = rsqrt_f64(pj);
         const double ljj = pj * y;
-        rinv[j] = y;
         pm = fmin(pm, ljj);
         const double lj = (r == j) ? ljj : (r > j ? a[j] * y : 0.0);
         a[j] = (r >= j) ? lj : 0.0;
+        if (r == j) yr = y;
 #pragma unroll
         for (int c = j + 1; c < PB; ++c) {
-          const double lc = lane_value(lj, c);
-          if (r >= c) a[c] = fma(-lj, lc, a[c]);
+          // entries above the diagonal (c > r) are never read again and are
+          // zeroed when their column is reached, so no select is needed here
+          a[c] = fma(-lj, row_value(lj, c), a[c]);
         }
-      }
-      // inverse: lane r computes column r, x[i] for i >= r
-      double x[PB];
+        // rows below j: Z[r] -= L[r][j] (Z[j] / L[j][j]); Z[j] is final here
+        const double mj = (r > j) ? lj * y : 0.0;
 #pragma unroll
-      for (int i = 0; i < PB; ++i) {
-        double sacc = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = 0; q < i; ++q) {
-          const double liq = lane_value(a[q], i);  // L[i][q] from lane i
-          sacc = fma(-liq, x[q], sacc);
-        }
-        x[i] = (i >= r) ? sacc * rinv[i] : 0.0;
+        for (int c = 0; c <= j; ++c) z[c] = fma(-mj, row_value(z[c], j), z[c]);
       }
       if (lane < PB) {
 #pragma unroll
         for (int c = 0; c < PB; ++c) {
           A[(c0 + r) * LDA + c0 + c] = (c <= r) ? a[c] : 0.0;
-          Li[(c0 + c) * LDA + c0 + r] = x[c];  // column r of the inverse
+          Li[(c0 + r) * LDA + c0 + c] = z[c] * yr;  // row r of the inverse
         }
       }
       if (lane == 0) {
