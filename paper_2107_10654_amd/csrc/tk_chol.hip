@@ -18,11 +18,13 @@ constexpr int NB = kCholNb;
 constexpr int LDA = NB + 1;
 
 // ---- diagonal tile: L_kk and its inverse
-// Blocked over four 16-column panels.  Wave 0 factors (and inverts) each
-// 16 x 16 diagonal panel in registers, lane r owning row r (each 16-lane row of
-// the wave holds a copy), with DPP row broadcasts in place of barriers; the workgroup then solves the
-// rows below the panel and updates the trailing triangle.  The 64 x 64
-// inverse is assembled from the four 16 x 16 inverses block row by block row.
+// Blocked over four 16-column panels.  Wave 0 factors each 16 x 16 diagonal
+// panel in registers, lane r owning row r (each 16-lane row of the wave holds a
+// copy), with DPP row broadcasts in place of barriers, and eliminates the
+// panel's inverse alongside.  The rows below the panel and the trailing
+// triangle are then 16 x 16 FP64 MFMA block products, one block per wave; the
+// off-diagonal blocks of the 64 x 64 inverse follow the same way, one block
+// column per wave.
 constexpr int PB = 16;
 
 // value of v in lane c of this lane's 16-lane row (c a constant after unrolling):
@@ -68,16 +70,17 @@ __device__ inline double rsqrt_f64(double x) {
 
 // Factor and invert the 64 x 64 block held in LDS A (lower triangle; rows past
 // the matrix hold the identity): on return A holds L and Li holds L^{-1}.
-// Li must be zero and *bad / *pmin initialised; Tm is scratch.
-__device__ __attribute__((always_inline)) inline void diag_factor(double* A, double* Li, double* Tm,
-                                                                int* bad_s, double* pmin_s) {
+// Li must be zero and *bad / *pmin initialised.  Entries of A above the
+// diagonal are scratch (never read).
+__device__ __attribute__((always_inline)) inline void diag_factor(double* A, double* Li, int* bad_s,
+                                                                double* pmin_s) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int tx = tid & 15, ty = tid >> 4;
+  // FP64 MFMA 16x16x4 operand lanes: row / column lr, k-slice lk; accumulator
+  // register v holds row lk + 4 v, column lr
+  const int lr = lane & 15, lk = lane >> 4;
   int& bad = *bad_s;
   double& pmin = *pmin_s;
-  (void)tx;
-  (void)ty;
   for (int p = 0; p < NB / PB; ++p) {
     const int c0 = p * PB;
     // (1) factor the 16 x 16 diagonal panel and invert it (wave 0, lane r = row r)
@@ -132,74 +135,79 @@ __device__ __attribute__((always_inline)) inline void diag_factor(double* A, dou
       }
     }
     __syncthreads();
-    const int below = NB - (c0 + PB);
-    if (below > 0) {
-      // (2) rows below: X = A[c0+16:, c0:c0+16] Li_pp^T
-      for (int e = tid; e < below * PB; e += kBlock) {
-        const int rr = c0 + PB + (e >> 4), c = e & 15;
-        double sacc = 0.0;
+    const int nbl = NB / PB - 1 - p;  // 16-row blocks below the panel
+    if (nbl > 0) {
+      // (2) rows below, one block per wave: X = A[rows, c0:c0+16] Li_pp^T,
+      // written over its own operand (the wave reads all of it first)
+      if (wave < nbl) {
+        const int R = c0 + PB + wave * PB;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int m = 0; m < PB; ++m)
-          sacc = fma(A[rr * LDA + c0 + m], Li[(c0 + c) * LDA + c0 + m], sacc);
-        Tm[(rr - c0 - PB) * (PB + 1) + c] = sacc;
+        for (int kk = 0; kk < PB / 4; ++kk)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(R + lr) * LDA + c0 + 4 * kk + lk],
+                                                     Li[(c0 + lr) * LDA + c0 + 4 * kk + lk], acc,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + c0 + lr] = acc[v];
       }
       __syncthreads();
-      for (int e = tid; e < below * PB; e += kBlock) {
-        const int rr = c0 + PB + (e >> 4), c = e & 15;
-        A[rr * LDA + c0 + c] = Tm[(rr - c0 - PB) * (PB + 1) + c];
-      }
-      __syncthreads();
-      // (3) trailing update of the lower triangle
-      for (int i = c0 + PB + ty; i < NB; i += 16)
-        for (int j = c0 + PB + tx; j <= i; j += 16) {
-          double sacc = A[i * LDA + j];
+      // (3) trailing update of the blocks (i, j), j <= i, below and right of
+      // the panel; diagonal blocks are updated whole (their upper halves are
+      // never read)
+      const int nt = nbl * (nbl + 1) / 2;
+      for (int t = wave; t < nt; t += kBlock / 64) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const int R = c0 + PB + i * PB, C = c0 + PB + j * PB;
+        doublex4 acc;
 #pragma unroll
-          for (int m = 0; m < PB; ++m)
-            sacc = fma(-A[i * LDA + c0 + m], A[j * LDA + c0 + m], sacc);
-          A[i * LDA + j] = sacc;
-        }
+        for (int v = 0; v < 4; ++v) acc[v] = A[(R + lk + 4 * v) * LDA + C + lr];
+#pragma unroll
+        for (int kk = 0; kk < PB / 4; ++kk)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(R + lr) * LDA + c0 + 4 * kk + lk],
+                                                     A[(C + lr) * LDA + c0 + 4 * kk + lk], acc,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + C + lr] = acc[v];
+      }
       __syncthreads();
     }
   }
-  // (4) off-diagonal blocks of the inverse: Li_ij = -Li_ii sum_{q=j}^{i-1} L_iq Li_qj
-  for (int bi = 1; bi < NB / PB; ++bi) {
-    // S_j = sum_q L_{bi,q} Li_{q,j} for every block column j < bi (into Tm rows j*16..)
-    for (int e = tid; e < bi * PB * PB; e += kBlock) {
-      const int bj = e >> 8, rr = (e >> 4) & 15, c = e & 15;
-      // in 16-wide chunks, unrolled, so the LDS reads of a chunk issue together
-      double s0 = 0.0, s1 = 0.0;
-      for (int qb = bj; qb < bi; ++qb) {
-        const double* ar = &A[(bi * PB + rr) * LDA + qb * PB];
-        const double* lc = &Li[(qb * PB) * LDA + bj * PB + c];
+  // (4) off-diagonal blocks of the inverse, Li_ij = -Li_ii sum_{q=j}^{i-1} L_iq Li_qj:
+  // wave w fills block column w top down, reading only blocks it wrote itself
+  // (and the diagonal inverses), so the columns need no barrier between rows
+  if (wave < NB / PB - 1) {
+    const int bj = wave;
+    for (int bi = bj + 1; bi < NB / PB; ++bi) {
+      doublex4 sacc = {0.0, 0.0, 0.0, 0.0};
+      for (int q = bj; q < bi; ++q)
 #pragma unroll
-        for (int m = 0; m < PB; m += 2) {
-          s0 = fma(ar[m], lc[m * LDA], s0);
-          s1 = fma(ar[m + 1], lc[(m + 1) * LDA], s1);
-        }
-      }
-      Tm[(bj * PB + rr) * (PB + 1) + c] = s0 + s1;
-    }
-    __syncthreads();
-    for (int e = tid; e < bi * PB * PB; e += kBlock) {
-      const int bj = e >> 8, rr = (e >> 4) & 15, c = e & 15;
-      double sacc = 0.0;
+        for (int kk = 0; kk < PB / 4; ++kk)
+          sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              A[(bi * PB + lr) * LDA + q * PB + 4 * kk + lk],
+              Li[(q * PB + 4 * kk + lk) * LDA + bj * PB + lr], sacc, 0, 0, 0);
+      // the accumulator's register v holds row 4 v + lk of the sum in lane
+      // (lk, lr): exactly the B operand of the k-slice v
+      doublex4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int m = 0; m < PB; ++m)
-        sacc = fma(Li[(bi * PB + rr) * LDA + bi * PB + m], Tm[(bj * PB + m) * (PB + 1) + c], sacc);
-      Li[(bi * PB + rr) * LDA + bj * PB + c] = -sacc;
+      for (int kk = 0; kk < PB / 4; ++kk)
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(-Li[(bi * PB + lr) * LDA + bi * PB + 4 * kk + lk],
+                                                 sacc[kk], o, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Li[(bi * PB + lk + 4 * v) * LDA + bj * PB + lr] = o[v];
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
                                                            int64_t k,
                                                            double* __restrict__ Linv_diag,
                                                            double* min_pivot, int32_t* status) {
-  __shared__ double smem[2 * NB * LDA + NB * (PB + 1)];
+  __shared__ double smem[2 * NB * LDA];
   double* A = smem;
   double* Li = smem + NB * LDA;
-  double* Tm = smem + 2 * NB * LDA;
   __shared__ int bad;
   __shared__ double pmin;
   const int tid = threadIdx.x;
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ 
     pmin = 1e308;
   }
   __syncthreads();
-  diag_factor(A, Li, Tm, &bad, &pmin);
+  diag_factor(A, Li, &bad, &pmin);
   double* Lo = Linv_diag + k * NB * NB;
   for (int i = ty; i < NB; i += 16)
     for (int j = tx; j < NB; j += 16) {
@@ -354,10 +362,9 @@ __global__ __launch_bounds__(kBlock) void chol_step_kernel(double* __restrict__ 
                                                            double* __restrict__ Linv_diag,
                                                            double* min_pivot, int32_t* status,
                                                            int32_t* flags) {
-  __shared__ double smem[2 * NB * LDA + NB * (PB + 1)];
+  __shared__ double smem[2 * NB * LDA];
   double* La = smem;
   double* Lb = smem + NB * LDA;
-  double* Tm = smem + 2 * NB * LDA;
   __shared__ int bad;
   __shared__ double pmin;
   __shared__ int ok;
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void chol_step_kernel(double* __restrict__ 
       pmin = 1e308;
     }
     __syncthreads();
-    diag_factor(La, Lb, Tm, &bad, &pmin);
+    diag_factor(La, Lb, &bad, &pmin);
     double* Lo = Linv_diag + (k + 1) * NB * NB;
     for (int i = ty; i < NB; i += 16)
       for (int j = tx; j < NB; j += 16) {
