@@ -12,14 +12,16 @@
 // tile, and the assembly kernel sums a tile's slots in workgroup order
 // (deterministic for a fixed grid).
 //
-// Per chunk a workgroup (4 waves, 2 x 2 over the tile) stages the chunk's
-// factor rows in LDS (prefetched in registers while the previous chunk's
-// MFMAs run), forms the outer-mode products O[o][t] (all modes but the last
-// mode L of rank >= 2), forms the two Kronecker row tiles
-// y[r][t] = O[r / R_L][t] q_L[r % R_L][t] in the operand precision, and runs
-// the 32 x 32 MFMAs.  Up to three (T = 128) or four (T = 64) workgroups share
-// a CU, so some form rows while others run MFMA.
+// Per chunk a workgroup stages the chunk's factor rows in LDS (prefetched in
+// registers while the previous chunk's MFMAs run), forms the two Kronecker
+// row tiles y[r][t] = O[r / R_L][t] q_L[r % R_L][t] in the operand precision,
+// O[o][t] being the product of the entries of all modes but the last mode L
+// of rank >= 2 (each thread reads its rows' outer factors straight from the
+// staged rows), and runs the 32 x 32 MFMAs.  Up to three (T = 128) or four
+// (T = 64) workgroups share a CU, so some form rows while others run MFMA.
 #include <string.h>
+
+#include <type_traits>
 
 #include "tk_mfma.h"
 
@@ -46,9 +48,8 @@ struct SkLayout {
   static constexpr int BK = V::BK;
   static constexpr int NO = SkTile<T>::NO;
   static constexpr size_t y_bytes = sizeof(typename V::Op) * T * V::LDK;   // one side
-  static constexpr size_t o_bytes = sizeof(typename V::Src) * NO * BK;     // one side
   static constexpr size_t offs_bytes = 2 * NO * kMaxOrder;
-  static constexpr size_t fixed = 2 * y_bytes + 2 * o_bytes + offs_bytes;
+  static constexpr size_t fixed = 2 * y_bytes + offs_bytes;
   // rows: sum_r rows plus one zero row
   __host__ __device__ static size_t bytes(int sum_r) {
     return fixed + sizeof(typename V::Src) * static_cast<size_t>(sum_r + 1) * kSkRT;
@@ -168,9 +169,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
   extern __shared__ __align__(16) unsigned char sk_smem[];
   Op* YA = reinterpret_cast<Op*>(sk_smem);
   Op* YBs = reinterpret_cast<Op*>(sk_smem + L::y_bytes);
-  Src* OA = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes);
-  Src* OB = reinterpret_cast<Src*>(sk_smem + 2 * L::y_bytes + L::o_bytes);
-  unsigned char* offs = sk_smem + 2 * L::y_bytes + 2 * L::o_bytes;  // [2][NO][kMaxOrder]
+  unsigned char* offs = sk_smem + 2 * L::y_bytes;                   // [2][NO][kMaxOrder]
   Src* rT = reinterpret_cast<Src*>(sk_smem + L::fixed);             // [sum_r + 1][RT]
 
   const int tid = threadIdx.x;
@@ -213,9 +212,10 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
       ob[side] = base / RL;
       no[side] = static_cast<int>(last / RL - ob[side] + 1);
     }
-    // this thread's formation items: LDS offsets into O and rT (zero row when
-    // the design row is past d)
-    int iofs_o[2][ITEMS], iofs_q[2][ITEMS];
+    // this thread's formation items: outer index within the tile and LDS
+    // offset of the last-mode row in rT (the zero row when the design row is
+    // past d)
+    int oidx[2][ITEMS], iofs_q[2][ITEMS];
 #pragma unroll
     for (int side = 0; side < 2; ++side)
 #pragma unroll
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         const int i = e % T, tg = (e / T) * IW;
         const int64_t r = (side == 0 ? r0 : c0) + i;
         const int64_t rr = r < d ? r : d - 1;
-        iofs_o[side][k] = static_cast<int>(rr / RL - ob[side]) * BK + tg;
+        oidx[side][k] = static_cast<int>(rr / RL - ob[side]);
         iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
       }
     auto fetch = [&](int64_t c) {
@@ -263,64 +263,78 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
     fetch(c_begin);
     commit();
     __syncthreads();
-    for (int64_t c = c_begin; c < c_end; ++c) {
-      const bool more = c + 1 < c_end;
-      if (more) fetch(c + 1);
-      // (b) outer products O[oi][t]
-      {
-        const int nsides = diag ? 1 : 2;
-#pragma unroll 1
-        for (int side = 0; side < nsides; ++side) {
-          Src* O = side == 0 ? OA : OB;
-          const unsigned char* so = offs + side * NO * kMaxOrder;
-#pragma unroll 1
-          for (int e = tid; e < no[side] * BK; e += kSkThreads) {
-            const int oi = e >> 5, t = e & 31;
-            const uint64_t pk = *reinterpret_cast<const uint64_t*>(so + oi * kMaxOrder);
-            Src v = Src(1);
+    // the rT rows of each item's outer factors (modes other than L), one byte
+    // per mode, packed
+    uint64_t pk[2][ITEMS];
 #pragma unroll
-            for (int k = 0; k < kMaxOrder - 1; ++k)
-              if (k < N - 1) v *= rT[static_cast<int>((pk >> (8 * k)) & 0xff) * RT + t];
-            O[e] = v;
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        pk[side][k] = *reinterpret_cast<const uint64_t*>(
+            offs + (side * NO + oidx[side][k]) * kMaxOrder);
+    // Kronecker rows of both tiles: y[r][t] = (prod over the outer modes of
+    // their factor entries) * q_L[r % R_L][t], in the operand precision; NM1
+    // (= N - 1 outer factors) is a constant so the LDS reads issue together
+    auto form = [&](auto nm1) {
+      constexpr int NM1 = decltype(nm1)::value;
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && diag) break;
+        Op* Y = side == 0 ? YA : YBs;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          const int e = tid + k * kSkThreads;
+          const int i = e % T, tg = (e / T) * IW;
+          const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
+          if constexpr (V::EPL == 8) {
+            f32x4 o0 = {1.0f, 1.0f, 1.0f, 1.0f}, o1 = o0;
+#pragma unroll
+            for (int m = 0; m < NM1; ++m) {
+              const f32x4* fp = reinterpret_cast<const f32x4*>(
+                  rT + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+              o0 *= fp[0];
+              o1 *= fp[1];
+            }
+            const f32x4 q0 = qp[0], q1 = qp[1];
+            bf16x8 v;
+            v[0] = V::cvt(o0.x * q0.x);
+            v[1] = V::cvt(o0.y * q0.y);
+            v[2] = V::cvt(o0.z * q0.z);
+            v[3] = V::cvt(o0.w * q0.w);
+            v[4] = V::cvt(o1.x * q1.x);
+            v[5] = V::cvt(o1.y * q1.y);
+            v[6] = V::cvt(o1.z * q1.z);
+            v[7] = V::cvt(o1.w * q1.w);
+            *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
+          } else {
+            f32x4 o = {1.0f, 1.0f, 1.0f, 1.0f};
+#pragma unroll
+            for (int m = 0; m < NM1; ++m)
+              o *= *reinterpret_cast<const f32x4*>(
+                  rT + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+            const f32x4 q = qp[0];
+            Op* y = &Y[i * LDK + tg];
+            y[0] = V::cvt(o.x * q.x);
+            y[1] = V::cvt(o.y * q.y);
+            y[2] = V::cvt(o.z * q.z);
+            y[3] = V::cvt(o.w * q.w);
           }
         }
       }
-      __syncthreads();
-      // (c) Kronecker rows of both tiles
-      {
-        const int nsides = diag ? 1 : 2;
-#pragma unroll 1
-        for (int side = 0; side < nsides; ++side) {
-          const Src* O = side == 0 ? OA : OB;
-          Op* Y = side == 0 ? YA : YBs;
-#pragma unroll
-          for (int k = 0; k < ITEMS; ++k) {
-            const int e = tid + k * kSkThreads;
-            const int i = e % T, tg = (e / T) * IW;
-            const f32x4* op = reinterpret_cast<const f32x4*>(O + iofs_o[side][k]);
-            const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
-            if constexpr (V::EPL == 8) {
-              const f32x4 o0 = op[0], o1 = op[1], q0 = qp[0], q1 = qp[1];
-              bf16x8 v;
-              v[0] = V::cvt(o0.x * q0.x);
-              v[1] = V::cvt(o0.y * q0.y);
-              v[2] = V::cvt(o0.z * q0.z);
-              v[3] = V::cvt(o0.w * q0.w);
-              v[4] = V::cvt(o1.x * q1.x);
-              v[5] = V::cvt(o1.y * q1.y);
-              v[6] = V::cvt(o1.z * q1.z);
-              v[7] = V::cvt(o1.w * q1.w);
-              *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
-            } else {
-              const f32x4 o = op[0], q = qp[0];
-              Op* y = &Y[i * LDK + tg];
-              y[0] = V::cvt(o.x * q.x);
-              y[1] = V::cvt(o.y * q.y);
-              y[2] = V::cvt(o.z * q.z);
-              y[3] = V::cvt(o.w * q.w);
-            }
-          }
-        }
+    };
+    for (int64_t c = c_begin; c < c_end; ++c) {
+      const bool more = c + 1 < c_end;
+      if (more) fetch(c + 1);
+      static_assert(kMaxOrder == 8, "one case per order");
+      switch (N) {
+        case 1: form(std::integral_constant<int, 0>{}); break;
+        case 2: form(std::integral_constant<int, 1>{}); break;
+        case 3: form(std::integral_constant<int, 2>{}); break;
+        case 4: form(std::integral_constant<int, 3>{}); break;
+        case 5: form(std::integral_constant<int, 4>{}); break;
+        case 6: form(std::integral_constant<int, 5>{}); break;
+        case 7: form(std::integral_constant<int, 6>{}); break;
+        default: form(std::integral_constant<int, 7>{}); break;
       }
       __syncthreads();
       // (d) MFMA; then stage the prefetched chunk
