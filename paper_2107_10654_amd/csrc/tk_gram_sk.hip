@@ -29,6 +29,7 @@ namespace tk {
 namespace {
 
 constexpr int kSkRT = kRowChunk + 4;  // padded LDS row: conflict-free 16-byte reads
+constexpr size_t kSkMaxLds = 160 * 1024;  // LDS per CU on gfx950
 
 // Tile edge T: 64 and 128 use 2 x 2 waves (32 x 32 or 64 x 64 each, up to 4
 // or 3 workgroups per CU); 256 uses 4 x 4 waves of 64 x 64 in one
@@ -43,16 +44,20 @@ struct SkTile {
   static constexpr int WG_PER_CU = T == 128 ? 3 : (T == 64 ? 4 : 1);
 };
 
-template <class V, int T>
+// LDS: NBUF sets of the two Kronecker row tiles, the outer-factor offsets,
+// then NBUF staged chunks of factor rows (sum_r rows plus one zero row each).
+template <class V, int T, int NBUF>
 struct SkLayout {
   static constexpr int BK = V::BK;
   static constexpr int NO = SkTile<T>::NO;
   static constexpr size_t y_bytes = sizeof(typename V::Op) * T * V::LDK;   // one side
   static constexpr size_t offs_bytes = 2 * NO * kMaxOrder;
-  static constexpr size_t fixed = 2 * y_bytes + offs_bytes;
-  // rows: sum_r rows plus one zero row
+  static constexpr size_t fixed = NBUF * 2 * y_bytes + offs_bytes;
+  __host__ __device__ static size_t rows_elems(int sum_r) {
+    return static_cast<size_t>(sum_r + 1) * kSkRT;
+  }
   __host__ __device__ static size_t bytes(int sum_r) {
-    return fixed + sizeof(typename V::Src) * static_cast<size_t>(sum_r + 1) * kSkRT;
+    return fixed + NBUF * sizeof(typename V::Src) * rows_elems(sum_r);
   }
 };
 
@@ -152,13 +157,16 @@ __global__ __launch_bounds__(1024) void sk_index_kernel(SkBatch b, int64_t* __re
   }
 }
 
-template <class V, int T, int PF4>
+// DB: two sets of row tiles and staged chunks, so that the rows of chunk
+// c + 1 are formed while the MFMAs of chunk c run, one barrier per chunk.
+template <class V, int T, int PF4, bool DB>
 __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram_sk_kernel(
     SkBatch b, typename V::Out* __restrict__ slots, const int64_t* __restrict__ index) {
   using Src = typename V::Src;
   using Op = typename V::Op;
   using Acc = typename V::Acc;
-  using L = SkLayout<V, T>;
+  constexpr int NBUF = DB ? 2 : 1;
+  using L = SkLayout<V, T, NBUF>;
   constexpr int BK = V::BK, LDK = V::LDK, RT = kSkRT, NO = L::NO;
   constexpr int IW = V::EPL == 8 ? 8 : 4;         // samples per formation item
   constexpr int IPR = BK / IW;                    // items per row
@@ -169,8 +177,12 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
   extern __shared__ __align__(16) unsigned char sk_smem[];
   Op* YA = reinterpret_cast<Op*>(sk_smem);
   Op* YBs = reinterpret_cast<Op*>(sk_smem + L::y_bytes);
-  unsigned char* offs = sk_smem + 2 * L::y_bytes;                   // [2][NO][kMaxOrder]
+  unsigned char* offs = sk_smem + NBUF * 2 * L::y_bytes;            // [2][NO][kMaxOrder]
   Src* rT = reinterpret_cast<Src*>(sk_smem + L::fixed);             // [sum_r + 1][RT]
+  // second set (DB): row tiles after the first pair, staged rows after rT
+  Op* YA2 = reinterpret_cast<Op*>(sk_smem + 2 * L::y_bytes);
+  Op* YB2s = reinterpret_cast<Op*>(sk_smem + 3 * L::y_bytes);
+  Src* rT2 = rT + L::rows_elems(b.max_sum_r);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -228,7 +240,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         oidx[side][k] = static_cast<int>(rr / RL - ob[side]);
         iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
       }
-    auto fetch = [&](int64_t c) {
+    auto fetch = [&](int64_t c) __attribute__((always_inline)) {
       const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
 #pragma unroll
       for (int k = 0; k < PF4; ++k) {
@@ -236,18 +248,21 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         if (e < nval4) pf[k] = src[e];
       }
     };
-    auto commit = [&]() {
+    auto commit = [&](Src* rs) __attribute__((always_inline)) {
 #pragma unroll
       for (int k = 0; k < PF4; ++k) {
         const int e = tid + k * kSkThreads;
         if (e < nval4) {
           const int f = 4 * e;  // element index j * 32 + t
-          *reinterpret_cast<f32x4*>(&rT[(f >> 5) * RT + (f & 31)]) = pf[k];
+          *reinterpret_cast<f32x4*>(&rs[(f >> 5) * RT + (f & 31)]) = pf[k];
         }
       }
     };
     __syncthreads();  // the previous segment's LDS use is complete
-    for (int e = tid; e < RT; e += kSkThreads) rT[SR * RT + e] = Src(0);  // zero row
+    for (int e = tid; e < RT; e += kSkThreads) {  // zero rows
+      rT[SR * RT + e] = Src(0);
+      if (DB) rT2[SR * RT + e] = Src(0);
+    }
 #pragma unroll 1
     for (int e = tid; e < 2 * NO; e += kSkThreads) {
       const int side = e / NO, oi = e - side * NO;
@@ -261,7 +276,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         for (int v = 0; v < V::NACC; ++v) acc[a][bb][v] = 0;
 
     fetch(c_begin);
-    commit();
+    commit(rT);
     __syncthreads();
     // the rT rows of each item's outer factors (modes other than L), one byte
     // per mode, packed
@@ -275,23 +290,23 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
     // Kronecker rows of both tiles: y[r][t] = (prod over the outer modes of
     // their factor entries) * q_L[r % R_L][t], in the operand precision; NM1
     // (= N - 1 outer factors) is a constant so the LDS reads issue together
-    auto form = [&](auto nm1) {
+    auto form = [&](auto nm1, const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
       constexpr int NM1 = decltype(nm1)::value;
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         if (side == 1 && diag) break;
-        Op* Y = side == 0 ? YA : YBs;
+        Op* Y = side == 0 ? ya : yb;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           const int e = tid + k * kSkThreads;
           const int i = e % T, tg = (e / T) * IW;
-          const f32x4* qp = reinterpret_cast<const f32x4*>(rT + iofs_q[side][k]);
+          const f32x4* qp = reinterpret_cast<const f32x4*>(rs + iofs_q[side][k]);
           if constexpr (V::EPL == 8) {
             f32x4 o0 = {1.0f, 1.0f, 1.0f, 1.0f}, o1 = o0;
 #pragma unroll
             for (int m = 0; m < NM1; ++m) {
               const f32x4* fp = reinterpret_cast<const f32x4*>(
-                  rT + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+                  rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
               o0 *= fp[0];
               o1 *= fp[1];
             }
@@ -311,7 +326,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
 #pragma unroll
             for (int m = 0; m < NM1; ++m)
               o *= *reinterpret_cast<const f32x4*>(
-                  rT + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+                  rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
             const f32x4 q = qp[0];
             Op* y = &Y[i * LDK + tg];
             y[0] = V::cvt(o.x * q.x);
@@ -322,23 +337,22 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         }
       }
     };
-    for (int64_t c = c_begin; c < c_end; ++c) {
-      const bool more = c + 1 < c_end;
-      if (more) fetch(c + 1);
+    auto form_rows = [&](const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
       static_assert(kMaxOrder == 8, "one case per order");
       switch (N) {
-        case 1: form(std::integral_constant<int, 0>{}); break;
-        case 2: form(std::integral_constant<int, 1>{}); break;
-        case 3: form(std::integral_constant<int, 2>{}); break;
-        case 4: form(std::integral_constant<int, 3>{}); break;
-        case 5: form(std::integral_constant<int, 4>{}); break;
-        case 6: form(std::integral_constant<int, 5>{}); break;
-        case 7: form(std::integral_constant<int, 6>{}); break;
-        default: form(std::integral_constant<int, 7>{}); break;
+        case 1: form(std::integral_constant<int, 0>{}, rs, ya, yb); break;
+        case 2: form(std::integral_constant<int, 1>{}, rs, ya, yb); break;
+        case 3: form(std::integral_constant<int, 2>{}, rs, ya, yb); break;
+        case 4: form(std::integral_constant<int, 3>{}, rs, ya, yb); break;
+        case 5: form(std::integral_constant<int, 4>{}, rs, ya, yb); break;
+        case 6: form(std::integral_constant<int, 5>{}, rs, ya, yb); break;
+        case 7: form(std::integral_constant<int, 6>{}, rs, ya, yb); break;
+        default: form(std::integral_constant<int, 7>{}, rs, ya, yb); break;
       }
-      __syncthreads();
-      // (d) MFMA; then stage the prefetched chunk
-      const Op* YB = diag ? YA : YBs;
+    };
+    // MFMAs of one chunk over its two row tiles
+    auto mma_chunk = [&](const Op* ya, const Op* ybs) __attribute__((always_inline)) {
+      const Op* yb = diag ? ya : ybs;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += V::KT) {
         const int kofs = kk + (lane / V::MT) * V::EPL;
@@ -346,12 +360,38 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         for (int a = 0; a < NBR; ++a)
 #pragma unroll
           for (int bb = 0; bb < NBC; ++bb)
-            acc[a][bb] = V::mma(&YA[(wr * WR + a * V::MT + lane % V::MT) * LDK + kofs],
-                                &YB[(wc * WC + bb * V::MT + lane % V::MT) * LDK + kofs],
+            acc[a][bb] = V::mma(&ya[(wr * WR + a * V::MT + lane % V::MT) * LDK + kofs],
+                                &yb[(wc * WC + bb * V::MT + lane % V::MT) * LDK + kofs],
                                 acc[a][bb]);
       }
-      if (more) commit();
+    };
+    if constexpr (DB) {
+      // chunk c_begin + j lives in set j % 2; its rows are formed one
+      // iteration ahead, and chunk c + 2 is staged where chunk c was
+      if (c_begin + 1 < c_end) fetch(c_begin + 1);
+      form_rows(rT, YA, YBs);
+      if (c_begin + 1 < c_end) commit(rT2);
       __syncthreads();
+      for (int64_t c = c_begin; c < c_end; ++c) {
+        const bool odd = ((c - c_begin) & 1) != 0;
+        Src* rcur = odd ? rT2 : rT;
+        const Src* rnext = odd ? rT : rT2;
+        if (c + 2 < c_end) fetch(c + 2);
+        mma_chunk(odd ? YA2 : YA, odd ? YB2s : YBs);
+        if (c + 1 < c_end) form_rows(rnext, odd ? YA : YA2, odd ? YBs : YB2s);
+        if (c + 2 < c_end) commit(rcur);
+        __syncthreads();
+      }
+    } else {
+      for (int64_t c = c_begin; c < c_end; ++c) {
+        const bool more = c + 1 < c_end;
+        if (more) fetch(c + 1);
+        form_rows(rT, YA, YBs);
+        __syncthreads();
+        mma_chunk(YA, YBs);  // then stage the prefetched chunk
+        if (more) commit(rT);
+        __syncthreads();
+      }
     }
     typename V::Out* out = slots + (slot0 + seg) * static_cast<int64_t>(T * T);
 #pragma unroll
@@ -523,15 +563,37 @@ __global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_one_tile_kernel(
   M[i * d + j] = fma(lambda, p, sum);
 }
 
+template <class V, int T, int PF4, bool DB>
+void gram_sk_launch_k(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
+  const size_t lds = SkLayout<V, T, DB ? 2 : 1>::bytes(b.max_sum_r);
+  if (lds > 64 * 1024) {
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_sk_kernel<V, T, PF4, DB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(kSkMaxLds));
+      attr = true;
+    }
+  }
+  hipLaunchKernelGGL((gram_sk_kernel<V, T, PF4, DB>), dim3(static_cast<unsigned>(b.grid)),
+                     dim3(SkTile<T>::THREADS), lds, st, b, slots, index);
+}
+
+// The double-buffered loop for the one-workgroup-per-CU 256 tile when both
+// sets fit in LDS; the single-buffered one otherwise (and for the smaller
+// tiles, whose several workgroups per CU already overlap formation and MFMA).
 template <class V, int T>
 void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
   using Pf = SkPf<SkTile<T>::THREADS>;
-  const dim3 grid(static_cast<unsigned>(b.grid)), block(SkTile<T>::THREADS);
-  const size_t lds = SkLayout<V, T>::bytes(b.max_sum_r);
-  if (Pf::small(b.max_sum_r))
-    hipLaunchKernelGGL((gram_sk_kernel<V, T, Pf::SMALL>), grid, block, lds, st, b, slots, index);
-  else
-    hipLaunchKernelGGL((gram_sk_kernel<V, T, Pf::LARGE>), grid, block, lds, st, b, slots, index);
+  if constexpr (T == 256) {
+    if (SkLayout<V, T, 2>::bytes(b.max_sum_r) <= kSkMaxLds) {
+      if (Pf::small(b.max_sum_r)) gram_sk_launch_k<V, T, Pf::SMALL, true>(b, slots, index, st);
+      else gram_sk_launch_k<V, T, Pf::LARGE, true>(b, slots, index, st);
+      return;
+    }
+  }
+  if (Pf::small(b.max_sum_r)) gram_sk_launch_k<V, T, Pf::SMALL, false>(b, slots, index, st);
+  else gram_sk_launch_k<V, T, Pf::LARGE, false>(b, slots, index, st);
 }
 
 int device_cu_count() {
