@@ -180,6 +180,31 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
                                       size_t ws_bytes, void* stream);
 
 /*
+ * The sketched ridge normal equations that tucker_core_update_sketched
+ * factors and solves (Alg. 1; proof of Thm 4.2), in the whitened
+ * coordinates of its solver.  With W = (x)_n L_n^{-1} (L_n the Cholesky factor
+ * of C_n = A(n)^T A(n), Kronecker product in mode order) and the Kronecker
+ * row q_t = W k_t of sample t (entries prod_n (L_n^{-1} a^(n)_{i_n})[r_n]):
+ *   M = sum_t weight_t q_t q_t^T + lambda P,   P = W W^T = (x)_n L_n^{-1} L_n^{-T},
+ *   b = sum_t weight_t x_t q_t,
+ * so that g = W^T M^{-1} b is the sampled core update.  Samples on unobserved
+ * entries contribute nothing.  The Gram term is summed on MFMA in
+ * opts->gram_precision (TK_F32 / TK_BF16 operands, FP32 accumulation) or in
+ * FP64, exactly as the update forms it; lambda P and b are FP64.
+ *
+ *   idx, weight  device, the sample set (required; s = opts->num_samples
+ *                entries, layout as tucker_sample)
+ *   M_out        device double [d * d], d = prod(ranks), row-major; entries
+ *                with row >= column are written, the others are unspecified
+ *   b_out        device double [d]
+ * Workspace: tucker_workspace_bytes(p, opts, TK_CALL_SKETCHED).
+ */
+tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* opts,
+                                 const int32_t* idx, const double* weight, double* M_out,
+                                 double* b_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                                 void* stream);
+
+/*
  * Adjoint (reverse-mode derivative) of the sampled core update with the
  * sample set held fixed.  The forward map is the solution of the sketched
  * ridge normal equations of Alg. 1 (proof of Thm 4.2),

@@ -76,6 +76,8 @@ _SIGNATURES = {
     "tucker_core_update_sketched_adjoint": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp,
                                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                              _vp, ctypes.c_size_t, _vp]),
+    "tucker_sketched_system": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp, _vp, _vp,
+                                                _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "tucker_workspace_bytes_batched": (ctypes.c_size_t, [_P(TkProblem), _P(TkSketchOpts),
                                                          ctypes.c_int32, _P(TkBatchConfig)]),
     "tucker_core_update_sketched_batched": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts),

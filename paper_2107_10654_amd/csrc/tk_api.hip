@@ -804,6 +804,36 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
+tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* o,
+                                 const int32_t* idx, const double* weight, double* M_out,
+                                 double* b_out, int32_t* dev_status, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  tk_status stt = check_problem(p, true);
+  if (stt != TK_OK) return stt;
+  if (!o || !idx || !weight || !M_out || !b_out || !ws) return TK_E_ARG;
+  SketchRun R;
+  stt = sketch_begin(R, p, o, dev_status, ws, ws_bytes, stream, TK_CALL_SKETCHED);
+  if (stt != TK_OK) return stt;
+  stt = sketch_pre(R, p, idx, weight, nullptr, nullptr);
+  if (stt != TK_OK) return stt;
+  const Geom& g = R.g;
+  SketchWS& w = R.w;
+  launch_gram(g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, R.st);
+  R.stage(4);
+  launch_assemble(g, R.pl, w.gpart, w.lev.P, p->lambda, w.M, R.st);
+  if (resid_small_ok(g))
+    launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
+                       R.st);
+  else
+    launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
+  R.stage(5);
+  TK_HIP_CHECK(hipMemcpyAsync(M_out, w.M, sizeof(double) * g.d * g.d, hipMemcpyDeviceToDevice,
+                              R.st));
+  TK_HIP_CHECK(hipMemcpyAsync(b_out, w.rhs, sizeof(double) * g.d, hipMemcpyDeviceToDevice, R.st));
+  R.stage(9);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
 tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sketch_opts* o,
                                               const int32_t* idx, const double* weight,
                                               const void* core, const void* core_bar,

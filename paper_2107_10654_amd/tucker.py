@@ -213,6 +213,35 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     return res[0] if len(res) == 1 else tuple(res)
 
 
+def sketched_system(X, factors, lam, idx, weight, precision="f64", mask=None, check=True):
+    """The sketched normal equations (M, b) of the sampled update on the samples (idx, weight),
+    in the solver's whitened coordinates: M = sum_t w_t q_t q_t^T + lam P (lower triangle
+    valid), b = sum_t w_t x_t q_t, q_t the Kronecker row of L_n^{-1} a^(n)_{i_n}."""
+    lib = L.load()
+    p = make_problem(X, factors, lam, mask)
+    N = len(factors)
+    _check_tensor(idx, "idx", torch.int32)
+    _check_tensor(weight, "weight", torch.float64)
+    s = idx.shape[1]
+    if idx.dim() != 2 or idx.shape[0] != N or weight.numel() != s:
+        raise ValueError("idx must be (N, s) and weight (s,)")
+    o = _opts(s, 0, 0, 0, precision, 0, 0.0)
+    dev = X.device
+    d = int(torch.tensor([A.shape[1] for A in factors]).prod())
+    M = torch.empty((d, d), dtype=torch.float64, device=dev)
+    b = torch.empty(d, dtype=torch.float64, device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), ctypes.byref(o), L.CALL_SKETCHED)
+    if nb == 0:
+        raise ValueError("unsupported problem for the sketched update")
+    ws = _workspace(nb, dev)
+    st = _status_word(dev)
+    _raise_if(lib.tucker_sketched_system(ctypes.byref(p), ctypes.byref(o), _ptr(idx),
+                                         _ptr(weight), _ptr(M), _ptr(b), _ptr(st), _ptr(ws),
+                                         ws.numel(), _stream()), "sketched_system")
+    _finish(dev, st, "sketched_system", check)
+    return M, b
+
+
 def core_update_sketched_adjoint(X, factors, lam, idx, weight, core, core_bar, precision="f64",
                                  mask=None, refine_max=20, refine_tol=1e-13, want_x=True,
                                  return_info=False, check=True):

@@ -1,0 +1,130 @@
+"""The sketched normal equations on the GPU (C ABI tucker_sketched_system)
+against the FP64 oracle, element by element.
+
+The system is the one the sampled update factors (Alg. 1; proof of Thm 4.2),
+in the solver's whitened coordinates: with Q_n = A(n) L_n^{-T} (rows
+q_i = L_n^{-1} a_i, L_n the Cholesky factor of A(n)^T A(n)),
+  M = sum_t w_t q_t q_t^T + lambda (x)_n L_n^{-1} L_n^{-T},   b = sum_t w_t x_t q_t.
+The reference takes the oracle's sketched normal equations of the whitened
+factors (the Kronecker rows formed by the oracle) and adds lambda P.
+
+Bars, per entry (i >= j), with A_ij = sum_t w_t |q_ti| |q_tj| (the sum of the
+magnitudes the entry adds up):
+* FP64 Gram: |dM_ij| <= 1e-11 A_ij + 1e-14 lambda |P_ij|;
+* FP32 operands: 2e-5 A_ij (operands formed in FP32 from FP64 whitened rows,
+  FP32 accumulation); one missing chunk of 32 samples would move a diagonal
+  entry by about 32 / s = 6e-3 of A_ii;
+* BF16 operands: 2^-8 (1 + 2^-8) A_ij (each operand rounded once to BF16, a
+  product of two at most 2^-8 off) + 2e-5 A_ij;
+* b (FP64 in every precision): 1e-11 sum_t w_t |x_t| |q_t|.
+Shapes cover the three Gram tile edges (64: d <= 64; 128; 256 with the
+double-buffered chunk loop: d >= 2048), ragged last tiles, orders 2 to 4,
+a rank-1 mode and an observation mask; s = 5000 spreads the stream-K ranges
+over tile boundaries with odd and even chunk counts.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+S = 5000
+
+CASES = [
+    ((23, 19, 17), (3, 4, 5), None),        # d = 60: 64 tile
+    ((60, 50), (8, 5), None),               # order 2, d = 40
+    ((41, 37, 29), (5, 6, 7), 0.3),         # d = 210: 128 tiles, ragged, masked
+    ((30, 28, 20), (6, 7, 1), None),        # rank-1 last mode, d = 42
+    ((40, 36, 30), (16, 16, 8), None),      # d = 2048: 256 tiles
+    ((12, 11, 10, 9), (8, 8, 6, 7), None),  # order 4, d = 2688: 256 tiles, ragged
+]
+
+
+@pytest.fixture(scope="module")
+def tk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2107_10654_amd as tk_mod
+    return tk_mod
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@functools.lru_cache(maxsize=None)
+def reference(case_index):
+    dims, ranks, missing = CASES[case_index]
+    p = workloads.tucker_tensor(dims, ranks, 40 + case_index, "f64", factor="gaussian",
+                                noise=("sigma", 0.1), missing=missing)
+    F = p["factors_true"]
+    rng = np.random.default_rng(90 + case_index)
+    idx = np.stack([rng.integers(0, I, S) for I in dims]).astype(np.int32)
+    weight = rng.uniform(0.5, 2.0, S) / S
+    lam = 0.05
+    C = [A.T @ A for A in F]
+    Ls = [np.linalg.cholesky(c) for c in C]
+    Q = [np.linalg.solve(L, A.T).T for L, A in zip(Ls, F)]  # rows L^{-1} a_i
+    G, b = oracle.sketched_normal_equations(p["X"], Q, idx, weight, p["mask"])
+    # P = W W^T for W = (x)_n L_n^{-1}: (x)_n L_n^{-1} L_n^{-T}
+    P = np.ones((1, 1))
+    for L in Ls:
+        Li = np.linalg.inv(L)
+        P = np.kron(P, Li @ Li.T)
+    # magnitudes summed by each entry (same observed samples)
+    Qa = [np.abs(q) for q in Q]
+    Aabs, babs = oracle.sketched_normal_equations(np.abs(p["X"]), Qa, idx, weight, p["mask"])
+    return dict(p=p, F=F, idx=idx, weight=weight, lam=lam, M=G + lam * P, P=P, b=b,
+                Aabs=Aabs, babs=babs)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_sketched_system_matches_oracle(tk, case, precision):
+    r = reference(case)
+    p = r["p"]
+    mask = T(p["mask"].view(np.int32)) if p["mask"] is not None else None
+    M, b = tk.sketched_system(T(p["X"]), [T(A) for A in r["F"]], r["lam"], T(r["idx"]),
+                              T(r["weight"]), precision=precision, mask=mask)
+    M = M.cpu().numpy()
+    b = b.cpu().numpy()
+    low = np.tril(np.ones(M.shape, dtype=bool))
+    err = np.abs(M - r["M"])[low]
+    A = r["Aabs"][low]
+    if precision == "f64":
+        bound = 1e-11 * A + 1e-14 * r["lam"] * np.abs(r["P"][low])
+    elif precision == "f32":
+        bound = 2e-5 * A + 1e-14 * r["lam"] * np.abs(r["P"][low])
+    else:
+        bound = (2.0 ** -8 * (1 + 2.0 ** -8) + 2e-5) * A + 1e-14 * r["lam"] * np.abs(r["P"][low])
+    worst = np.argmax(err - bound)
+    assert np.all(err <= bound), (float(err[worst]), float(bound[worst]), float(A[worst]))
+    assert np.all(np.abs(b - r["b"]) <= 1e-11 * r["babs"] + 1e-300)
+
+
+def test_sketched_system_solves_to_the_sampled_update(tk):
+    # g = W^T M^{-1} b is the sampled core update on the same samples (FP64)
+    r = reference(2)
+    p = r["p"]
+    mask = T(p["mask"].view(np.int32))
+    X, FF = T(p["X"]), [T(A) for A in r["F"]]
+    M, b = tk.sketched_system(X, FF, r["lam"], T(r["idx"]), T(r["weight"]), precision="f64",
+                              mask=mask)
+    M = np.tril(M.cpu().numpy())
+    M = M + np.tril(M, -1).T
+    h = np.linalg.solve(M, b.cpu().numpy())
+    W = np.ones((1, 1))
+    for A in r["F"]:
+        W = np.kron(W, np.linalg.inv(np.linalg.cholesky(A.T @ A)))
+    g = W.T @ h
+    G = tk.core_update_sketched(X, FF, r["lam"], S, idx=T(r["idx"]), weight=T(r["weight"]),
+                                precision="f64", mask=mask)
+    ref = oracle.core_update_sketched(p["X"], r["F"], r["lam"], r["idx"], r["weight"], p["mask"])
+    assert np.linalg.norm(g - ref.ravel()) <= 1e-9 * np.linalg.norm(ref)
+    assert np.linalg.norm(G.cpu().numpy().ravel() - ref.ravel()) <= 1e-9 * np.linalg.norm(ref)
