@@ -145,7 +145,7 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.gpart = with_partials ? c.take<char>(gram_partial_bytes(g, pl)) : nullptr;
   w.M = c.take<double>(static_cast<size_t>(d) * d);
   const int64_t nblk = cdiv(d, kCholNb);
-  w.Linv_diag = c.take<double>(nblk * kCholNb * kCholNb);
+  w.Linv_diag = c.take<double>(kCholAuxBlocks * nblk * kCholNb * kCholNb);
   w.rhs = c.take<double>(d);
   w.h = c.take<double>(d);
   w.r = c.take<double>(d);

@@ -545,30 +545,90 @@ __device__ inline void publish(double* p, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The chain matrices of the two solves, one pair per 64-row block i (their
+// last dependency folded into one product, so that a block finishes the rest
+// of its row before that dependency is published):
+//   forward  y_i = Li_ii (b_i - sum_{j < i-1} L_ij y_j) - Wl_i y_{i-1},  Wl_i = Li_ii L_{i,i-1}
+//   backward x_i = Li_ii^T (y_i - sum_{j > i+1} L_ji^T x_j) - Wu_i x_{i+1},
+//            Wu_i = Li_ii^T L_{i+1,i}^T
+// Both 64 x 64 products per block on FP64 MFMA, stored row-major after the
+// diagonal-block inverses (Wl at nblk blocks past Linv_diag, Wu at 2 nblk).
+__global__ __launch_bounds__(kBlock) void chol_chain_kernel(const double* __restrict__ M,
+                                                            int64_t d, int64_t nblk,
+                                                            double* __restrict__ Linv_diag) {
+  __shared__ double X[NB * LDA];
+  __shared__ double Y[NB * LDA];
+  const int tid = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const int64_t i0 = i * NB;
+  const double* Li = Linv_diag + i * NB * NB;
+  auto store = [&](double* W, const doublex4 (&acc)[2][2]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) W[acc_r(x, v) * NB + acc_c(y)] = acc[x][y][v];
+  };
+  if (i >= 1) {
+    // X = Li_ii, Y[c][m] = L_{i,i-1}[m][c] (rows past d are zero)
+    const int ri = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
+    for (int e = tid; e < NB * NB; e += kBlock) {
+      const int r = e >> 6, c = e & 63;
+      X[r * LDA + c] = Li[e];
+      Y[c * LDA + r] = r < ri ? M[(i0 + r) * d + i0 - NB + c] : 0.0;
+    }
+    __syncthreads();
+    doublex4 acc[2][2];
+    tile_gemm_nt(X, Y, acc);
+    store(Linv_diag + (nblk + i) * NB * NB, acc);
+    __syncthreads();
+  }
+  if (i + 1 < nblk) {
+    // X[r][m] = Li_ii[m][r], Y[c][m] = L_{i+1,i}[c][m] (rows past d are zero)
+    const int64_t n0 = i0 + NB;
+    const int rn = static_cast<int>((d - n0) < NB ? (d - n0) : NB);
+    for (int e = tid; e < NB * NB; e += kBlock) {
+      const int r = e >> 6, c = e & 63;
+      X[c * LDA + r] = Li[e];
+      Y[r * LDA + c] = r < rn ? M[(n0 + r) * d + i0 + c] : 0.0;
+    }
+    __syncthreads();
+    doublex4 acc[2][2];
+    tile_gemm_nt(X, Y, acc);
+    store(Linv_diag + (2 * nblk + i) * NB * NB, acc);
+  }
+}
+
 // forward: L y = b, b read from x; x is left holding the sentinel for the
 // backward solve.  flags[0] is the ticket.  Thread (r, q): row r of the block,
-// column quarter q of each dependency block.
+// column quarter q of each dependency block and of the chain product.
 __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __restrict__ L,
                                                             const double* __restrict__ Linv_diag,
-                                                            int64_t d, double* x, double* y,
-                                                            int32_t* flags, const int32_t* done,
-                                                            int32_t* status) {
+                                                            int64_t d, int64_t nblk, double* x,
+                                                            double* y, int32_t* flags,
+                                                            const int32_t* done, int32_t* status) {
   if (done && *done) return;
   __shared__ int64_t row_blk;
   __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
-  __shared__ int bad;
+  __shared__ double u_s[NB];
+  __shared__ double chain[4][NB];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    row_blk = atomicAdd(&flags[0], 1);
-    bad = 0;
-  }
+  if (tid == 0) row_blk = atomicAdd(&flags[0], 1);
   __syncthreads();
   const int64_t i = row_blk;
   const int64_t i0 = i * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
   const int r = tid & 63, q = tid >> 6;
+  // this thread's part of the chain matrix Wl_i: row r, columns of quarter q
+  double wrow[16];
+  if (i >= 1) {
+    const double* W = Linv_diag + (nblk + i) * NB * NB + r * NB + q * 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) wrow[c] = W[c];
+  }
   {
     const double* src = Linv_diag + i * NB * NB;
     for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
@@ -576,14 +636,14 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
   const double bv = (q == 0 && r < rows) ? x[i0 + r] : 0.0;
   const double* Lrow = L + (i0 + (r < rows ? r : 0)) * d + q * 16;
   double cur[16], nxt[16];
-  if (i > 0) {
+  if (i > 1) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) cur[c] = Lrow[c];
   }
   double acc = 0.0;
   bool ok = true;
-  for (int64_t j = 0; j < i; ++j) {  // blocks before the last are full
-    if (j + 1 < i) {
+  for (int64_t j = 0; j + 1 < i; ++j) {  // every dependency but the last (all full blocks)
+    if (j + 2 < i) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) nxt[c] = Lrow[(j + 1) * NB + c];
     }
@@ -595,21 +655,33 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
     for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
-  if (!ok) bad = 1;
   __syncthreads();
   if (tid < NB) acc_s[tid] = bv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
   if (q == 0 && r < rows) publish(x + i0 + r, __longlong_as_double(kPending));
   __syncthreads();
-  // y_i = Li acc: row rr, four partial sums over c
+  // u = Li acc: row rr, four partial sums over c
   {
     const int rr = tid >> 2, pp = tid & 3;
-    double v = 0.0;
-    for (int c = pp; c <= rr; c += 4) v = fma(Li[rr * LDA + c], acc_s[c], v);
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    if (pp == 0 && rr < rows) publish(y + i0 + rr, v);
+    double u = 0.0;
+    for (int c = pp; c <= rr; c += 4) u = fma(Li[rr * LDA + c], acc_s[c], u);
+    u += __shfl_xor(u, 1, 64);
+    u += __shfl_xor(u, 2, 64);
+    if (pp == 0) u_s[rr] = u;
   }
-  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
+  // y_i = u - Wl_i y_{i-1} once block i - 1 is published: each wave waits for
+  // its own quarter of y_{i-1}
+  double v = 0.0;
+  if (i >= 1) {
+    double yv[16];
+    ok = load_published(y + (i - 1) * NB + q * 16, 16, yv) && ok;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v = fma(wrow[c], yv[c], v);
+  }
+  chain[q][r] = v;
+  __syncthreads();
+  if (q == 0 && r < rows)
+    publish(y + i0 + r, u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r])));
+  if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
 // backward: L^T x = y.  flags[1] is the ticket (blocks from the last).
@@ -624,22 +696,27 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   __shared__ double Li[NB * LDA];
   __shared__ double acc_s[NB];
   __shared__ double part[4][NB];
-  __shared__ int bad;
+  __shared__ double u_s[NB];
+  __shared__ double chain[4][NB];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    row_blk = nblk - 1 - atomicAdd(&flags[1], 1);
-    bad = 0;
-  }
+  if (tid == 0) row_blk = nblk - 1 - atomicAdd(&flags[1], 1);
   __syncthreads();
   const int64_t i = row_blk;
   const int64_t i0 = i * NB;
   const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
+  const int r = tid & 63, q = tid >> 6;
+  // this thread's part of the chain matrix Wu_i: row r, columns of quarter q
+  double wrow[16];
+  if (i + 1 < nblk) {
+    const double* W = Linv_diag + (2 * nblk + i) * NB * NB + r * NB + q * 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) wrow[c] = W[c];
+  }
   {
     const double* src = Linv_diag + i * NB * NB;
     for (int e = tid; e < NB * NB; e += kBlock) Li[(e >> 6) * LDA + (e & 63)] = src[e];
   }
-  // acc[r] = sum_{j > i} sum_c L[j0 + c][i0 + r] x[j0 + c]; thread (r, quarter q of c)
-  const int r = tid & 63, q = tid >> 6;
+  // acc[r] = sum_{j > i+1} sum_c L[j0 + c][i0 + r] x[j0 + c]; thread (r, quarter q of c)
   const int rc = r < rows ? r : 0;
   auto load_blk = [&](int64_t j, double* v) {
     const int64_t j0 = j * NB;
@@ -653,41 +730,55 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
 #pragma unroll
     for (int c = 0; c < 16; ++c) v[c] = (q * 16 + c) < rj ? t[c] : 0.0;
   };
-  double cur[16], nxt[16];
-  if (i < nblk - 1) load_blk(nblk - 1, cur);
-  double acc = 0.0;
-  bool ok = true;
-  for (int64_t j = nblk - 1; j > i; --j) {
-    if (j - 1 > i) load_blk(j - 1, nxt);
+  auto published_count = [&](int64_t j, int quarter) {
     const int64_t j0 = j * NB;
     const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
-    int n = rj - q * 16;
-    n = n < 0 ? 0 : (n > 16 ? 16 : n);
+    const int n = rj - quarter * 16;
+    return n < 0 ? 0 : (n > 16 ? 16 : n);
+  };
+  double cur[16], nxt[16];
+  if (i + 2 < nblk) load_blk(nblk - 1, cur);
+  double acc = 0.0;
+  bool ok = true;
+  for (int64_t j = nblk - 1; j > i + 1; --j) {  // every dependency but the last
+    if (j - 1 > i + 1) load_blk(j - 1, nxt);
     double xv[16];
-    ok = load_published(x + j0 + q * 16, n, xv) && ok;
+    ok = load_published(x + j * NB + q * 16, published_count(j, q), xv) && ok;
 #pragma unroll
     for (int c = 0; c < 16; ++c) acc = fma(cur[c], xv[c], acc);
 #pragma unroll
     for (int c = 0; c < 16; ++c) cur[c] = nxt[c];
   }
   part[q][r] = acc;
-  if (!ok) bad = 1;
   __syncthreads();
   if (tid < NB) {
     const double yv = tid < rows ? y[i0 + tid] : 0.0;
     acc_s[tid] = yv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
   }
   __syncthreads();
-  // x_i = Li^T acc: x[r] = sum_{c >= r} Li[c][r] acc[c]
+  // u = Li^T acc: u[rr] = sum_{c >= rr} Li[c][rr] acc[c]
   {
     const int rr = tid >> 2, pp = tid & 3;
-    double v = 0.0;
-    for (int c = rr + pp; c < rows; c += 4) v = fma(Li[c * LDA + rr], acc_s[c], v);
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    if (pp == 0 && rr < rows) publish(x + i0 + rr, v);
+    double u = 0.0;
+    for (int c = rr + pp; c < rows; c += 4) u = fma(Li[c * LDA + rr], acc_s[c], u);
+    u += __shfl_xor(u, 1, 64);
+    u += __shfl_xor(u, 2, 64);
+    if (pp == 0) u_s[rr] = u;
   }
-  if (tid == 0 && bad) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
+  // x_i = u - Wu_i x_{i+1} once block i + 1 is published: each wave waits for
+  // its own quarter of x_{i+1}
+  double v = 0.0;
+  if (i + 1 < nblk) {
+    double xv[16];
+    ok = load_published(x + (i + 1) * NB + q * 16, published_count(i + 1, q), xv) && ok;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v = fma(wrow[c], xv[c], v);
+  }
+  chain[q][r] = v;
+  __syncthreads();
+  if (q == 0 && r < rows)
+    publish(x + i0 + r, u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r])));
+  if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
 // tickets to 0 and y to the sentinel
@@ -716,6 +807,8 @@ void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot,
     hipLaunchKernelGGL(chol_step_kernel, dim3(static_cast<unsigned>(below * (below + 1) / 2)),
                        dim3(kBlock), 0, st, M, d, k, Linv_diag, min_pivot, status, sf);
   }
+  hipLaunchKernelGGL(chol_chain_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st,
+                     static_cast<const double*>(M), d, nblk, Linv_diag);
 }
 
 void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,
@@ -725,7 +818,7 @@ void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, doub
   hipLaunchKernelGGL(solve_init_kernel, dim3(static_cast<unsigned>(cdiv(d, kBlock))), dim3(kBlock),
                      0, st, flags, y_tmp, d, done);
   hipLaunchKernelGGL(trsv_lower_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
-                     Linv_diag, d, x, y_tmp, flags, done, status);
+                     Linv_diag, d, nblk, x, y_tmp, flags, done, status);
   hipLaunchKernelGGL(trsv_upper_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
                      Linv_diag, d, nblk, static_cast<const double*>(y_tmp), x, flags, done, status);
 }

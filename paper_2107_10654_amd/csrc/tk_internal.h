@@ -192,10 +192,13 @@ void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
                           const double* weff, const double* h, int64_t s, double* part, double* c,
                           const int32_t* done, hipStream_t st);
 
-// Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag receives the
-// inverses of the nb x nb diagonal blocks; min_pivot one double; flags at
-// least 2 + d / nb int32 (the step flags live past the solves' two tickets).
+// Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag
+// (kCholAuxBlocks * ceil(d/nb) blocks of nb x nb doubles) receives the
+// inverses of the nb x nb diagonal blocks, then the two triangular solves'
+// chain matrices; min_pivot one double; flags at least 2 + d / nb int32 (the
+// step flags live past the solves' two tickets).
 constexpr int kCholNb = 64;
+constexpr int kCholAuxBlocks = 3;
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
                      int32_t* flags, hipStream_t st);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
