@@ -158,7 +158,7 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.rows32 = c.take<float>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
   w.coef = c.take<double>(s);
   w.ttm_scratch = c.take<double>(kTtmScratchDoubles);
-  w.flags = c.take<int32_t>(2 * nblk + 2);
+  w.flags = c.take<int32_t>(chol_flag_words(d));
   w.status = c.take<int32_t>(1);
   w.done = c.take<int32_t>(1);
   w.steps = c.take<int32_t>(1);

@@ -3,11 +3,12 @@
 // normal equations with a pseudo-inverse; the system here is positive
 // definite for lambda > 0, so a Cholesky factorisation is the direct solver.
 //
-// Blocked right-looking algorithm with 64 x 64 tiles: after the first
-// diagonal tile and panel, one launch per block column updates the trailing
-// lower triangle on FP64 MFMA and, inside the same launch, factors (and
-// inverts) the next diagonal tile and solves the next panel with the inverse.  The triangular solves use one launch each: workgroups take block
-// rows in ticket order and wait (bounded spin) for the values they depend on.
+// Left-looking factorisation over 64 x 64 tiles in one persistent launch:
+// one workgroup runs the chain of diagonal tiles (factor, inverse, next
+// tile) while the others form the remaining tiles and the chain's partial
+// sums, each tile written once and published by a flag.  The triangular
+// solves use one launch each: workgroups take block rows in ticket order and
+// wait (bounded spin) for the values they depend on.
 #include "tk_internal.h"
 
 namespace tk {
@@ -201,128 +202,6 @@ __device__ __attribute__((always_inline)) inline void diag_factor(double* A, dou
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void chol_diag_kernel(double* __restrict__ M, int64_t d,
-                                                           int64_t k,
-                                                           double* __restrict__ Linv_diag,
-                                                           double* min_pivot, int32_t* status) {
-  __shared__ double smem[2 * NB * LDA];
-  double* A = smem;
-  double* Li = smem + NB * LDA;
-  __shared__ int bad;
-  __shared__ double pmin;
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t o = k * NB;
-  const int b = static_cast<int>((d - o) < NB ? (d - o) : NB);
-  {
-    // unconditional loads from clamped (in-bounds) addresses, so they issue
-    // back to back; the selects run after all of them
-    double v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
-      const int ic = i < b ? i : b - 1, jc = j < b ? j : b - 1;
-      v[e] = M[(o + ic) * d + o + jc];
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = ty + 16 * (e >> 2), j = tx + 16 * (e & 3);
-      A[i * LDA + j] = (i < b && j <= i) ? v[e] : (i == j ? 1.0 : 0.0);
-      Li[i * LDA + j] = 0.0;
-    }
-  }
-  if (tid == 0) {
-    bad = 0;
-    pmin = 1e308;
-  }
-  __syncthreads();
-  diag_factor(A, Li, &bad, &pmin);
-  double* Lo = Linv_diag + k * NB * NB;
-  for (int i = ty; i < NB; i += 16)
-    for (int j = tx; j < NB; j += 16) {
-      Lo[i * NB + j] = (j <= i) ? Li[i * LDA + j] : 0.0;
-      if (i < b && j <= i) M[(o + i) * d + o + j] = A[i * LDA + j];
-    }
-  if (tid == 0) {
-    if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
-    // min pivot: monotone update through integer compare of non-negative doubles
-    atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
-              static_cast<unsigned long long>(__double_as_longlong(pmin)));
-  }
-}
-
-// ---- panel: L_ik = A_ik L_kk^{-T} for block rows i > k
-__global__ __launch_bounds__(kBlock) void chol_trsm_kernel(double* __restrict__ M, int64_t d,
-                                                           int64_t k,
-                                                           const double* __restrict__ Linv_diag) {
-  __shared__ double Li[NB * LDA];
-  __shared__ double A[NB * LDA];
-  const int tid = threadIdx.x;
-  const int64_t i0 = (k + 1 + blockIdx.x) * NB;
-  const int64_t o = k * NB;
-  const int rows = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
-  const double* L = Linv_diag + k * NB * NB;
-  {
-    double va[NB * NB / kBlock], vl[NB * NB / kBlock];
-#pragma unroll
-    for (int q = 0; q < NB * NB / kBlock; ++q) {
-      const int e = tid + q * kBlock;
-      const int i = e / NB, j = e % NB;
-      const int ic = i < rows ? i : rows - 1;
-      vl[q] = L[e];
-      va[q] = M[(i0 + ic) * d + o + j];
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB / kBlock; ++q) {
-      const int e = tid + q * kBlock;
-      const int i = e / NB, j = e % NB;
-      Li[i * LDA + j] = vl[q];
-      A[i * LDA + j] = i < rows ? va[q] : 0.0;
-    }
-  }
-  __syncthreads();
-  // X[r][c] = sum_{m <= c} A[r][m] Li[c][m]; each thread 4 x 4 outputs
-  const int tr = (tid / 16) * 4, tc = (tid % 16) * 4;
-  double acc[4][4] = {};
-  for (int m = 0; m < NB; ++m) {
-    double a[4], l[4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      a[x] = A[(tr + x) * LDA + m];
-      l[x] = Li[(tc + x) * LDA + m];
-    }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], l[y], acc[x][y]);
-  }
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-      if (tr + x < rows) M[(i0 + tr + x) * d + o + tc + y] = acc[x][y];
-}
-
-// ---- one factorisation step with look-ahead: the trailing update of step k
-// (M_ij -= L_ik L_jk^T for k < j <= i) in one launch that also factors the
-// next diagonal block and solves the next panel.  Workgroup 0 owns tile
-// (k+1, k+1): after its update it factors and inverts the block in LDS and
-// raises flags[k+1].  The workgroups of tiles (i, k+1), i > k+1, wait for that
-// flag -- they wait only on workgroup 0, which waits on nothing and is
-// dispatched first; the wait is bounded -- and multiply their updated tile by
-// the new inverse.  Every other workgroup only updates its tile, so the
-// diagonal factorisation overlaps the bulk of the update.
-constexpr long kStepSpinLimit = 1L << 22;
-
-__device__ inline bool wait_flag(const int32_t* f) {
-  long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-    __builtin_amdgcn_s_sleep(2);
-    if (++spins > kStepSpinLimit) return false;
-  }
-  return true;
-}
-
 // acc (2 x 2 blocks of 16 x 16 per wave, FP64 MFMA 16x16x4) = X Y^T over 64
 // columns, X and Y 64 x 64 in LDS (row stride LDA)
 __device__ inline void tile_gemm_nt(const double* X, const double* Y, doublex4 (&acc)[2][2]) {
@@ -357,50 +236,87 @@ __device__ inline int acc_c(int y) {
   return (wave & 1) * 32 + y * 16 + lane % 16;
 }
 
-__global__ __launch_bounds__(kBlock) void chol_step_kernel(double* __restrict__ M, int64_t d,
-                                                           int64_t k,
-                                                           double* __restrict__ Linv_diag,
-                                                           double* min_pivot, int32_t* status,
-                                                           int32_t* flags) {
-  __shared__ double smem[2 * NB * LDA];
-  double* La = smem;
-  double* Lb = smem + NB * LDA;
-  __shared__ int bad;
-  __shared__ double pmin;
-  __shared__ int ok;
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  int64_t tau = blockIdx.x;
-  int64_t a = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(tau) + 1.0) - 1.0) * 0.5);
-  while ((a + 1) * (a + 2) / 2 <= tau) ++a;
-  while (a * (a + 1) / 2 > tau) --a;
-  const int64_t bb = tau - a * (a + 1) / 2;
-  const int64_t bi = k + 1 + a, bj = k + 1 + bb;
-  const int64_t i0 = bi * NB, j0 = bj * NB, o = k * NB;
-  const int ri = static_cast<int>((d - i0) < NB ? (d - i0) : NB);
-  const int rj = static_cast<int>((d - j0) < NB ? (d - j0) : NB);
-  {
-    double va[NB * NB / kBlock], vb[NB * NB / kBlock];
-#pragma unroll
-    for (int q = 0; q < NB * NB / kBlock; ++q) {
-      const int e = tid + q * kBlock;
-      const int i = e / NB, j = e % NB;
-      va[q] = M[(i0 + (i < ri ? i : ri - 1)) * d + o + j];
-      vb[q] = M[(j0 + (i < rj ? i : rj - 1)) * d + o + j];
-    }
-#pragma unroll
-    for (int q = 0; q < NB * NB / kBlock; ++q) {
-      const int e = tid + q * kBlock;
-      const int i = e / NB, j = e % NB;
-      La[i * LDA + j] = i < ri ? va[q] : 0.0;
-      Lb[i * LDA + j] = i < rj ? vb[q] : 0.0;
+// ---- left-looking dataflow factorisation in one persistent launch
+// With S_ij = A_ij - sum_{k < j} L_ik L_jk^T over lower 64 x 64 tiles:
+//  * workgroup 0 runs the chain of the factorisation, column by column: S_jj
+//    (its last term L_{j,j-1} L_{j,j-1}^T from the tile it made itself, still in
+//    LDS), the factor and inverse of S_jj, then the next tile
+//    L_{j+1,j} = S_{j+1,j} L_jj^{-T}, which it keeps in LDS for the next column;
+//  * the other workgroups take tickets, column by column, for the tiles
+//    L_ij = S_ij L_jj^{-T}, i >= j + 2, and for the partial sums of column j + 2
+//    (S_{j+2,j+2} and S_{j+3,j+2} over k <= j, left in a scratch area for the
+//    chain).
+// Each tile is written once, then its flag is raised; published tiles are read
+// with agent-scope coherent loads, so no cache invalidation is needed.  A
+// ticketed task waits only on smaller tickets or on chain tiles of earlier
+// columns, and the chain at column j only on tickets of columns j - 2 and
+// j - 1, so the launch drains; every wait is bounded (TK_E_HIP past the limit,
+// the task then goes on).
+constexpr int kFlagStride = 32;  // one flag per 128-byte line
+__device__ inline int64_t tile_flag_index(int64_t i, int64_t j) {
+  return (i * (i + 1) / 2 + j) * kFlagStride;
+}
+
+// Bounded wait for a published tile: relaxed agent-scope polls, spaced out.
+// The limit (~2^18 polls of ~0.2 us) is far above the longest legitimate wait
+// (the chain's progress over all columns, a few ms); the first wait to run out
+// raises *abort, which ends every other wait of the launch at once.
+constexpr long kFlowSpinLimit = 1L << 18;
+__device__ inline bool wait_tile(const int32_t* f, int32_t* abort) {
+  long spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(8);
+    if (++spins > kFlowSpinLimit) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
     }
   }
-  __syncthreads();
+  return true;
+}
+
+// A published tile entry: read coherently at agent scope (no cached copy from
+// before the tile's flag).
+__device__ inline double load_tile(const double* p) {
+  return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+
+// dst (64 x 64 in LDS, row stride LDA) = rows [r0, r0 + rows) of column block k
+// of M, zero past `rows`
+__device__ inline void stage_tile(const double* M, int64_t d, int64_t r0, int rows, int64_t k,
+                                  double* dst) {
+  const int tid = threadIdx.x;
+  double v[NB * NB / kBlock];
+#pragma unroll
+  for (int q = 0; q < NB * NB / kBlock; ++q) {
+    const int e = tid + q * kBlock;
+    const int r = e / NB, c = e % NB;
+    v[q] = load_tile(&M[(r0 + (r < rows ? r : rows - 1)) * d + k * NB + c]);
+  }
+#pragma unroll
+  for (int q = 0; q < NB * NB / kBlock; ++q) {
+    const int e = tid + q * kBlock;
+    const int r = e / NB, c = e % NB;
+    dst[r * LDA + c] = r < rows ? v[q] : 0.0;
+  }
+}
+
+// S (accumulator layout) -= X Y^T, X and Y 64 x 64 in LDS
+__device__ inline void sub_gemm_nt(const double* X, const double* Y, double (&S)[2][2][4]) {
   doublex4 acc[2][2];
-  tile_gemm_nt(La, Lb, acc);
-  // updated tile values of this thread's 16 elements (rows / columns clamped)
-  double nv[2][2][4];
+  tile_gemm_nt(X, Y, acc);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[x][y][v] -= acc[x][y][v];
+}
+
+// S = A_ij (rows / columns clamped; entries past them are never used)
+__device__ inline void load_block(const double* M, int64_t d, int64_t i0, int ri, int64_t j0,
+                                  int rj, double (&S)[2][2][4]) {
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -408,92 +324,287 @@ __global__ __launch_bounds__(kBlock) void chol_step_kernel(double* __restrict__ 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = acc_r(x, v), c = acc_c(y);
-        nv[x][y][v] = M[(i0 + (r < ri ? r : ri - 1)) * d + j0 + (c < rj ? c : rj - 1)] -
-                      acc[x][y][v];
+        S[x][y][v] = M[(i0 + (r < ri ? r : ri - 1)) * d + j0 + (c < rj ? c : rj - 1)];
       }
-  __syncthreads();  // La / Lb are reused below
-  if (tau == 0) {
-    // diagonal tile (k+1, k+1): factor and invert, then publish
+}
+
+// M rows [i0, i0 + ri) of column block j = S Li^T, S in the accumulator layout
+// staged through X; Li (64 x 64) in LDS
+__device__ inline void apply_inverse_store(double* M, int64_t d, int64_t i0, int ri, int64_t j0,
+                                           const double (&S)[2][2][4], double* X,
+                                           const double* Li) {
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_r(x, v), c = acc_c(y);
-          La[r * LDA + c] = (r < ri && c <= r) ? nv[x][y][v] : (r == c ? 1.0 : 0.0);
-          Lb[r * LDA + c] = 0.0;
-        }
-    if (tid == 0) {
-      bad = 0;
-      pmin = 1e308;
-    }
-    __syncthreads();
-    diag_factor(La, Lb, &bad, &pmin);
-    double* Lo = Linv_diag + (k + 1) * NB * NB;
-    for (int i = ty; i < NB; i += 16)
-      for (int j = tx; j < NB; j += 16) {
-        Lo[i * NB + j] = (j <= i) ? Lb[i * LDA + j] : 0.0;
-        if (i < ri && j <= i) M[(i0 + i) * d + i0 + j] = La[i * LDA + j];
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_r(x, v), c = acc_c(y);
+        X[r * LDA + c] = r < ri ? S[x][y][v] : 0.0;
       }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
-      atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
-                static_cast<unsigned long long>(__double_as_longlong(pmin)));
-      __hip_atomic_store(&flags[k + 1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (bb == 0) {
-    // panel tile (bi, k+1), bi > k+1 (block k+1 is then a full block):
-    // L_{bi,k+1} = A L_{k+1,k+1}^{-T} once the diagonal block is published
+  __syncthreads();
+  doublex4 acc[2][2];
+  tile_gemm_nt(X, Li, acc);  // sum_m S[r][m] Li[c][m]
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_r(x, v), c = acc_c(y);
-          La[r * LDA + c] = r < ri ? nv[x][y][v] : 0.0;
-        }
-    if (tid == 0) ok = wait_flag(&flags[k + 1]) ? 1 : 0;
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    {
-      const double* Li = Linv_diag + (k + 1) * NB * NB;
-      double vl[NB * NB / kBlock];
-#pragma unroll
-      for (int q = 0; q < NB * NB / kBlock; ++q) vl[q] = Li[tid + q * kBlock];
-#pragma unroll
-      for (int q = 0; q < NB * NB / kBlock; ++q) {
-        const int e = tid + q * kBlock;
-        Lb[(e / NB) * LDA + e % NB] = vl[q];
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_r(x, v), c = acc_c(y);
+        if (r < ri) M[(i0 + r) * d + j0 + c] = acc[x][y][v];
       }
-    }
+}
+
+// Raise a tile's flag once every thread's stores to it are visible.
+__device__ inline void publish_tile(int32_t* flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// tickets of column j: tiles (i, j) for i >= j + 2, then the partial sums of
+// column j + 2
+__host__ __device__ inline int64_t chol_column_tickets(int64_t nblk, int64_t j) {
+  const int64_t tiles = nblk - j - 2 > 0 ? nblk - j - 2 : 0;
+  return tiles + (j + 2 < nblk ? 1 : 0);
+}
+__host__ __device__ inline int64_t chol_flow_tasks(int64_t nblk) {
+  int64_t n = 0;
+  for (int64_t j = 0; j < nblk; ++j) n += chol_column_tickets(nblk, j);
+  return n;
+}
+
+// S (accumulator layout) as a row-major 64 x 64 tile (rows past `rows` zero)
+__device__ inline void store_block(double* dst, int ld, int rows, const double (&S)[2][2][4]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_r(x, v), c = acc_c(y);
+        dst[r * ld + c] = r < rows ? S[x][y][v] : 0.0;
+      }
+}
+
+// pre: kCholAuxBlocks-sized scratch past the solves' chain matrices; column c's
+// partial sums at blocks 2c (S_cc) and 2c + 1 (S_{c+1,c})
+__global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict__ M, int64_t d,
+                                                              int64_t nblk,
+                                                              double* __restrict__ Linv_diag,
+                                                              double* __restrict__ pre,
+                                                              double* min_pivot, int32_t* status,
+                                                              int32_t* flags) {
+  __shared__ double smem[4 * NB * LDA];
+  double* La = smem;
+  double* Lb = smem + NB * LDA;
+  double* Lc = smem + 2 * NB * LDA;
+  double* Ld = smem + 3 * NB * LDA;
+  __shared__ int64_t task_s;
+  __shared__ int bad;
+  __shared__ double pmin;
+  __shared__ int ok_s;
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  int32_t* tile_flag = flags + kFlagStride;  // flags[0] is the ticket, flags[1] the abort word
+  int32_t* pre_flag = tile_flag + (nblk * (nblk + 1) / 2) * kFlagStride;
+  bool failed = false;
+  auto rows_of = [&](int64_t b) {
+    return static_cast<int>((d - b * NB) < NB ? (d - b * NB) : NB);
+  };
+  // tid 0 waits for the flags, then the workgroup goes on together
+  int32_t* abort = flags + 1;  // in the ticket's line
+  auto wait2 = [&](const int32_t* fa, const int32_t* fb) {
+    if (tid == 0)
+      ok_s = (wait_tile(fa, abort) && (fb == nullptr || wait_tile(fb, abort))) ? 1 : 0;
     __syncthreads();
-    doublex4 acc2[2][2];
-    tile_gemm_nt(La, Lb, acc2);  // X[r][c] = sum_m A[r][m] Li[c][m]
+    failed = failed || !ok_s;
+  };
+  if (blockIdx.x == 0) {
+    // ---------------- the chain (Lc holds L_{j,j-1} from the previous column)
+    __builtin_amdgcn_s_setprio(3);
+    for (int64_t j = 0; j < nblk; ++j) {
+      const int64_t j0 = j * NB;
+      const int rj = rows_of(j);
+      const bool next = j + 1 < nblk;
+      const int64_t i10 = (j + 1) * NB;
+      const int r1 = next ? rows_of(j + 1) : 0;
+      double Sd[2][2][4];
+      if (j >= 2) {
+        wait2(&pre_flag[j * kFlagStride], nullptr);
+        const double* P0 = pre + (2 * j) * NB * NB;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+          for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_r(x, v), c = acc_c(y);
-          if (r < ri) M[(i0 + r) * d + j0 + c] = acc2[x][y][v];
+            for (int v = 0; v < 4; ++v)
+              Sd[x][y][v] = load_tile(&P0[acc_r(x, v) * NB + acc_c(y)]);
+      } else {
+        load_block(M, d, j0, rj, j0, rj, Sd);
+      }
+      if (j >= 1) sub_gemm_nt(Lc, Lc, Sd);  // L_{j,j-1} L_{j,j-1}^T
+      // factor and invert S_jj (rows past d hold the identity)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = acc_r(x, v), c = acc_c(y);
+            La[r * LDA + c] = (r < rj && c <= r) ? Sd[x][y][v] : (r == c ? 1.0 : 0.0);
+            Lb[r * LDA + c] = 0.0;
+          }
+      if (tid == 0) {
+        bad = 0;
+        pmin = 1e308;
+      }
+      __syncthreads();
+      diag_factor(La, Lb, &bad, &pmin);
+      double* Lo = Linv_diag + j * NB * NB;
+      for (int r = ty; r < NB; r += 16)
+        for (int c = tx; c < NB; c += 16) {
+          Lo[r * NB + c] = (c <= r) ? Lb[r * LDA + c] : 0.0;
+          if (r < rj && c <= r) M[(j0 + r) * d + j0 + c] = La[r * LDA + c];
         }
-    if (tid == 0 && !ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
+      if (tid == 0) {
+        if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
+        atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
+                  static_cast<unsigned long long>(__double_as_longlong(pmin)));
+      }
+      publish_tile(&tile_flag[tile_flag_index(j, j)]);
+      if (!next) break;
+      // S_{j+1,j}: partial sums (or A), then its last term L_{j+1,j-1} L_{j,j-1}^T
+      double Sn[2][2][4];
+      if (j >= 2) {
+        const double* P1 = pre + (2 * j + 1) * NB * NB;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              Sn[x][y][v] = load_tile(&P1[acc_r(x, v) * NB + acc_c(y)]);
+      } else {
+        load_block(M, d, i10, r1, j0, rj, Sn);
+      }
+      if (j >= 1) {
+        wait2(&tile_flag[tile_flag_index(j + 1, j - 1)], nullptr);
+        stage_tile(M, d, i10, r1, j - 1, Ld);
+        __syncthreads();
+        sub_gemm_nt(Ld, Lc, Sn);
+        __syncthreads();  // Lc and Ld are rewritten below
+      }
+      // L_{j+1,j} = S_{j+1,j} Li_jj^T: stored, published and kept in Lc
+      store_block(Ld, LDA, r1, Sn);
+      __syncthreads();
+      doublex4 acc[2][2];
+      tile_gemm_nt(Ld, Lb, acc);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = acc_r(x, v), c = acc_c(y);
+            const double val = r < r1 ? acc[x][y][v] : 0.0;
+            Lc[r * LDA + c] = val;
+            if (r < r1) M[(i10 + r) * d + j0 + c] = val;
+          }
+      publish_tile(&tile_flag[tile_flag_index(j + 1, j)]);
+    }
   } else {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = acc_r(x, v), c = acc_c(y);
-          if (r < ri && c < rj && (bi != bj || c <= r)) M[(i0 + r) * d + j0 + c] = nv[x][y][v];
+    // ---------------- ticketed tasks
+    const int64_t ntasks = chol_flow_tasks(nblk);
+    for (;;) {
+      __syncthreads();  // the previous task is done with LDS and task_s
+      if (tid == 0) task_s = atomicAdd(&flags[0], 1);
+      __syncthreads();
+      const int64_t t = task_s;
+      if (t >= ntasks) break;
+      int64_t j = 0, start = 0;
+      for (;;) {
+        const int64_t cnt = chol_column_tickets(nblk, j);
+        if (t < start + cnt) break;
+        start += cnt;
+        ++j;
+      }
+      const int64_t off = t - start;
+      const int64_t ntile = nblk - j - 2 > 0 ? nblk - j - 2 : 0;
+      if (off < ntile) {
+        // tile (i, j), i >= j + 2 (block j is full)
+        const int64_t i = j + 2 + off, i0 = i * NB, j0 = j * NB;
+        const int ri = rows_of(i);
+        double S[2][2][4];
+        load_block(M, d, i0, ri, j0, NB, S);
+        for (int64_t k = 0; k < j; ++k) {
+          wait2(&tile_flag[tile_flag_index(i, k)], &tile_flag[tile_flag_index(j, k)]);
+          stage_tile(M, d, i0, ri, k, La);
+          stage_tile(M, d, j0, NB, k, Lb);
+          __syncthreads();
+          sub_gemm_nt(La, Lb, S);
+          __syncthreads();
         }
+        wait2(&tile_flag[tile_flag_index(j, j)], nullptr);
+        {
+          const double* Li = Linv_diag + j * NB * NB;
+          double vl[NB * NB / kBlock];
+#pragma unroll
+          for (int q = 0; q < NB * NB / kBlock; ++q) vl[q] = load_tile(&Li[tid + q * kBlock]);
+#pragma unroll
+          for (int q = 0; q < NB * NB / kBlock; ++q) {
+            const int e = tid + q * kBlock;
+            Lb[(e / NB) * LDA + e % NB] = vl[q];
+          }
+        }
+        apply_inverse_store(M, d, i0, ri, j0, S, La, Lb);
+        publish_tile(&tile_flag[tile_flag_index(i, j)]);
+      } else {
+        // partial sums of column c = j + 2 over k <= j
+        const int64_t c = j + 2, c0 = c * NB;
+        const int rc = rows_of(c);
+        const bool next = c + 1 < nblk;
+        const int64_t n0 = (c + 1) * NB;
+        const int rn = next ? rows_of(c + 1) : 0;
+        double Sd[2][2][4], Sn[2][2][4];
+        load_block(M, d, c0, rc, c0, rc, Sd);
+        if (next) load_block(M, d, n0, rn, c0, rc, Sn);
+        for (int64_t k = 0; k <= j; ++k) {
+          wait2(&tile_flag[tile_flag_index(c, k)],
+                next ? &tile_flag[tile_flag_index(c + 1, k)] : nullptr);
+          stage_tile(M, d, c0, rc, k, La);
+          if (next) stage_tile(M, d, n0, rn, k, Lb);
+          __syncthreads();
+          sub_gemm_nt(La, La, Sd);
+          if (next) sub_gemm_nt(Lb, La, Sn);
+          __syncthreads();
+        }
+        store_block(pre + (2 * c) * NB * NB, NB, NB, Sd);
+        if (next) store_block(pre + (2 * c + 1) * NB * NB, NB, NB, Sn);
+        publish_tile(&pre_flag[c * kFlagStride]);
+      }
+    }
   }
+  if (tid == 0 && failed) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
+}
+
+int chol_flow_grid(int64_t nblk) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        n > 0)
+      cus = n;
+    else
+      cus = 256;
+    (void)hipGetLastError();
+  }
+  const int64_t ntasks = chol_flow_tasks(nblk);
+  const int64_t g = cus;  // one workgroup per CU: the serial panel factor keeps its SIMD
+  return static_cast<int>(1 + ntasks < g ? 1 + ntasks : g);  // the chain + ticketed tasks
 }
 
 __global__ void chol_flags_kernel(int32_t* f, int64_t n) {
@@ -794,19 +905,13 @@ __global__ void solve_init_kernel(int32_t* flags, double* y, int64_t d, const in
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
                      int32_t* flags, hipStream_t st) {
   const int64_t nblk = cdiv(d, NB);
-  int32_t* sf = flags + 2;  // flags[0..1] are the solves' tickets
-  hipLaunchKernelGGL(chol_flags_kernel, dim3(static_cast<unsigned>(cdiv(nblk, kBlock))),
-                     dim3(kBlock), 0, st, sf, nblk);
-  hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(kBlock), 0, st, M, d, int64_t(0), Linv_diag,
-                     min_pivot, status);
-  if (nblk > 1)
-    hipLaunchKernelGGL(chol_trsm_kernel, dim3(static_cast<unsigned>(nblk - 1)), dim3(kBlock), 0,
-                       st, M, d, int64_t(0), static_cast<const double*>(Linv_diag));
-  for (int64_t k = 0; k + 1 < nblk; ++k) {
-    const int64_t below = nblk - k - 1;
-    hipLaunchKernelGGL(chol_step_kernel, dim3(static_cast<unsigned>(below * (below + 1) / 2)),
-                       dim3(kBlock), 0, st, M, d, k, Linv_diag, min_pivot, status, sf);
-  }
+  int32_t* ff = flags + 2;  // flags[0..1] are the solves' tickets
+  const int64_t nflags = (1 + nblk * (nblk + 1) / 2 + nblk) * kFlagStride;
+  hipLaunchKernelGGL(chol_flags_kernel, dim3(static_cast<unsigned>(cdiv(nflags, kBlock))),
+                     dim3(kBlock), 0, st, ff, nflags);
+  double* pre = Linv_diag + 3 * nblk * NB * NB;  // past the inverses and chain matrices
+  hipLaunchKernelGGL(chol_flow_kernel, dim3(static_cast<unsigned>(chol_flow_grid(nblk))),
+                     dim3(kBlock), 0, st, M, d, nblk, Linv_diag, pre, min_pivot, status, ff);
   hipLaunchKernelGGL(chol_chain_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st,
                      static_cast<const double*>(M), d, nblk, Linv_diag);
 }

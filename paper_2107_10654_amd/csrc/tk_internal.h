@@ -195,10 +195,15 @@ void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,
 // Dense FP64 Cholesky, lower, in place (tk_chol.hip).  Linv_diag
 // (kCholAuxBlocks * ceil(d/nb) blocks of nb x nb doubles) receives the
 // inverses of the nb x nb diagonal blocks, then the two triangular solves'
-// chain matrices; min_pivot one double; flags at least 2 + d / nb int32 (the
-// step flags live past the solves' two tickets).
+// chain matrices, then holds the factorisation's per-column partial sums;
+// min_pivot one double; flags chol_flag_words(d) int32 (the factorisation's
+// ticket and tile flags live past the solves' two tickets).
 constexpr int kCholNb = 64;
-constexpr int kCholAuxBlocks = 3;
+constexpr int kCholAuxBlocks = 5;
+inline int64_t chol_flag_words(int64_t d) {
+  const int64_t nblk = (d + kCholNb - 1) / kCholNb;
+  return 2 + (1 + nblk * (nblk + 1) / 2 + nblk) * 32;  // one 128-byte line per flag
+}
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
                      int32_t* flags, hipStream_t st);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
