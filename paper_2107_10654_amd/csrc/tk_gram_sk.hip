@@ -409,40 +409,97 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
   }
 }
 
-// M[i][j] (i >= j) = sum of the tile's slots + lambda prod_n P_n[i_n][j_n]
+// M[i][j] (i >= j) = sum of the tile's slots + lambda prod_n P_n[i_n][j_n].
+// The slots of the (at most kBlock / T) tiles a workgroup's columns touch are
+// listed once per workgroup in LDS (the workgroup ranges are found with 64-bit
+// divisions, too costly per element); a tile with more than kAsmMaxSlots
+// slots is summed by walking the ranges per element instead.
+constexpr int kAsmMaxSlots = 16;
+constexpr int kAsmRows = 16;  // rows per workgroup (all in one tile row: kAsmRows divides T)
+
 template <int T>
 __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
     Geom g, int64_t units, int64_t grid, int64_t unit0, int64_t tile0, int64_t nchunks,
     const float* __restrict__ slots, const int64_t* __restrict__ index,
     const double* __restrict__ P, double lambda, double* __restrict__ M) {
+  static_assert(T % kAsmRows == 0, "a workgroup's rows share one tile row");
+  constexpr int TPB = kBlock >= T ? kBlock / T : 1;  // tiles per workgroup row
+  __shared__ int64_t slot_of[TPB][kAsmMaxSlots];
+  __shared__ int nslot[TPB];
   const int64_t d = g.d;
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t i = blockIdx.y;
-  if (j > i) return;
-  const int64_t ti = i / T, tj = j / T;
-  const int64_t tau = ti * (ti + 1) / 2 + tj;
-  const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;  // the tile's units [ua, ub)
-  int64_t w = (ua * grid) / units;
-  while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
-  while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
-  const int64_t off = (i - ti * T) * T + (j - tj * T);
-  double v = 0.0;
-  for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
-    const int64_t first = index[grid + w];
-    if (first < 0) continue;  // empty range
-    const int64_t slot = index[w] + (tile0 + tau - first);
-    v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
+  const int64_t jb = static_cast<int64_t>(blockIdx.x) * kBlock;
+  const int64_t j = jb + threadIdx.x;
+  const int64_t ib = static_cast<int64_t>(blockIdx.y) * kAsmRows;
+  const int64_t ilast = (ib + kAsmRows < d ? ib + kAsmRows : d) - 1;
+  const int64_t ti = ib / T;
+  if (jb > ilast) return;  // the whole workgroup is above the diagonal
+  // the slots of the workgroup's tiles, in workgroup order (-1: too many)
+  if (threadIdx.x < TPB) {
+    const int64_t tj = jb / T + threadIdx.x;
+    int n = 0;
+    if (tj <= ti) {
+      const int64_t tau = ti * (ti + 1) / 2 + tj;
+      const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;  // the tile's units
+      int64_t w = (ua * grid) / units;
+      while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
+      while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
+      for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
+        const int64_t first = index[grid + w];
+        if (first < 0) continue;  // empty range
+        if (n < kAsmMaxSlots) slot_of[threadIdx.x][n] = index[w] + (tile0 + tau - first);
+        ++n;
+      }
+    }
+    nslot[threadIdx.x] = n <= kAsmMaxSlots ? n : -1;
   }
-  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
-  double p = 1.0;
-  uint32_t a = static_cast<uint32_t>(i), b = static_cast<uint32_t>(j);
-  for (int n = g.order - 1; n >= 0; --n) {
-    const uint32_t R = static_cast<uint32_t>(g.ranks[n]);
-    p *= P[g.roff[n] + (a % R) * R + (b % R)];
-    a /= R;
-    b /= R;
+  __syncthreads();
+  const int64_t tj = j / T;
+  const int tl = static_cast<int>(tj - jb / T);
+  const int ns = nslot[tl];
+  // column digits of j, reused for every row
+  uint32_t jd[kMaxOrder];
+  {
+    uint32_t b = static_cast<uint32_t>(j < d ? j : 0);
+#pragma unroll
+    for (int n = kMaxOrder - 1; n >= 0; --n) {
+      const uint32_t R = n < g.order ? static_cast<uint32_t>(g.ranks[n]) : 1u;
+      jd[n] = b % R;
+      b /= R;
+    }
   }
-  M[i * d + j] = fma(lambda, p, v);
+  for (int64_t i = ib; i <= ilast; ++i) {
+    if (j > i) continue;
+    const int64_t off = (i - ti * T) * T + (j - tj * T);
+    double v = 0.0;
+    if (ns >= 0) {
+      for (int k = 0; k < ns; ++k)
+        v += static_cast<double>(slots[slot_of[tl][k] * static_cast<int64_t>(T * T) + off]);
+    } else {
+      const int64_t tau = ti * (ti + 1) / 2 + tj;
+      const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;
+      int64_t w = (ua * grid) / units;
+      while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
+      while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
+      for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
+        const int64_t first = index[grid + w];
+        if (first < 0) continue;
+        const int64_t slot = index[w] + (tile0 + tau - first);
+        v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
+      }
+    }
+    // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
+    double p = 1.0;
+    uint32_t a = static_cast<uint32_t>(i);
+#pragma unroll
+    for (int n = kMaxOrder - 1; n >= 0; --n) {
+      if (n < g.order) {
+        const uint32_t R = static_cast<uint32_t>(g.ranks[n]);
+        p *= P[g.roff[n] + (a % R) * R + jd[n]];
+        a /= R;
+      }
+    }
+    M[i * d + j] = fma(lambda, p, v);
+  }
 }
 
 // Smallest w with sk_unit_start(w) >= u (grid when there is none).
@@ -729,7 +786,8 @@ void launch_assemble_sk(const SkBatch& b, int k, const Geom& g, const float* slo
                          q.unit0, q.tile0, nch, slots, index, P, lambda, M);
     return;
   }
-  const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)), static_cast<unsigned>(g.d));
+  const dim3 grid(static_cast<unsigned>(cdiv(g.d, kBlock)),
+                  static_cast<unsigned>(cdiv(g.d, kAsmRows)));
   if (b.tile == 256)
     hipLaunchKernelGGL(assemble_sk_kernel<256>, grid, dim3(kBlock), 0, st, g, b.units, b.grid,
                        q.unit0, q.tile0, nch, slots, index, P, lambda, M);
