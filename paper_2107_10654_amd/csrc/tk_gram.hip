@@ -26,10 +26,8 @@ namespace tk {
 namespace {
 
 // ------------------------------------------------------------------ pre-gather
-// Element e of the chunk-transposed layout: chunk c = e / (32 sum_r), row
-// position j, sample t = 32 c + e % 32.  Each thread takes kPgPer elements
-// (stride: the grid) and issues their loads together.
-constexpr int kPgPer = 8;
+// Element (t, j) of the chunk-transposed layout: chunk c = t / 32, row
+// position j, at c 32 sum_r + 32 j + t % 32.
 
 __global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t* __restrict__ idx,
                                                            const double* __restrict__ weff,
@@ -37,53 +35,33 @@ __global__ __launch_bounds__(kBlock) void pregather_kernel(Geom g, const int32_t
                                                            const double* __restrict__ Q64,
                                                            double* __restrict__ rows64,
                                                            float* __restrict__ rows32) {
-  // per row position j: its mode, table offset, rank and largest index (LDS)
-  __shared__ int64_t pq[kMaxSumR];
-  __shared__ int32_t pn[kMaxSumR], pr[kMaxSumR], pi[kMaxSumR];
+  // one thread per sample t: its indices and weight are read once, then its
+  // concatenated row goes to positions j of chunk t / 32 (consecutive threads
+  // write consecutive t of a position: coalesced)
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= row_chunks(s) * kRowChunk) return;
   const int SR = g.sum_r;
-  if (threadIdx.x < SR) {
-    const int j = threadIdx.x;
-    int n = 0;
-    while (n + 1 < g.order && j >= g.soff[n + 1]) ++n;
-    pn[j] = n;
-    pq[j] = g.qoff[n] + (j - g.soff[n]);
-    pr[j] = g.ranks[n];
-    pi[j] = static_cast<int32_t>(g.dims[n] - 1);
+  const int64_t base = (t >> 5) * SR * kRowChunk + (t & (kRowChunk - 1));
+  float* o32 = rows32 + base;
+  double* o64 = rows64 ? rows64 + base : nullptr;
+  if (t >= s) {  // padding samples of the last chunk
+    for (int j = 0; j < SR; ++j) {
+      o32[j * kRowChunk] = 0.0f;
+      if (o64) o64[j * kRowChunk] = 0.0;
+    }
+    return;
   }
-  __syncthreads();
-  const int64_t total = row_chunks(s) * kRowChunk * SR;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  double v[kPgPer], wv[kPgPer];
-  int mode[kPgPer];
-#pragma unroll
-  for (int k = 0; k < kPgPer; ++k) {
-    const int64_t e = e0 + k * stride;
-    const int64_t ec = e < total ? e : total - 1;
-    const int tt = static_cast<int>(ec & (kRowChunk - 1));
-    const int64_t rest = ec >> 5;
-    // 32-bit division unless the position index needs more bits
-    const int64_t c = rest < 0xFFFFFFFFll
-                          ? static_cast<int64_t>(static_cast<uint32_t>(rest) /
-                                                 static_cast<uint32_t>(SR))
-                          : rest / SR;
-    const int j = static_cast<int>(rest - c * SR);
-    const int64_t t = c * kRowChunk + tt;
-    const int64_t tc = t < s ? t : s - 1;
-    const int n = pn[j];
-    int32_t i = idx[static_cast<int64_t>(n) * s + tc];
-    if (i < 0 || i > pi[j]) i = 0;  // flagged by the gather pass (weight 0)
-    const double q = Q64[pq[j] + static_cast<int64_t>(i) * pr[j]];
-    v[k] = t < s ? q : 0.0;
-    wv[k] = weff[tc];
-    mode[k] = n;
-  }
-#pragma unroll
-  for (int k = 0; k < kPgPer; ++k) {
-    const int64_t e = e0 + k * stride;
-    if (e < total) {
-      if (rows64) rows64[e] = v[k];
-      rows32[e] = static_cast<float>(mode[k] == 0 ? v[k] * sqrt(wv[k]) : v[k]);
+  const double sw = sqrt(weff[t]);  // sqrt(w_t) folded into the mode-0 entries of rows32
+  for (int n = 0; n < g.order; ++n) {
+    int32_t i = idx[static_cast<int64_t>(n) * s + t];
+    if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
+    const int R = g.ranks[n];
+    const double* q = Q64 + g.qoff[n] + static_cast<int64_t>(i) * R;
+    const int j0 = g.soff[n];
+    for (int r = 0; r < R; ++r) {
+      const double v = q[r];
+      o32[(j0 + r) * kRowChunk] = static_cast<float>(n == 0 ? v * sw : v);
+      if (o64) o64[(j0 + r) * kRowChunk] = v;
     }
   }
 }
@@ -1079,7 +1057,8 @@ void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int
                       const double* Q64, double* rows64, float* rows32, hipStream_t st) {
   const int64_t n = row_chunks(s) * kRowChunk * g.sum_r;
   if (n <= 0) return;
-  hipLaunchKernelGGL(pregather_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock * kPgPer))),
+  hipLaunchKernelGGL(pregather_kernel,
+                     dim3(static_cast<unsigned>(cdiv(row_chunks(s) * kRowChunk, kBlock))),
                      dim3(kBlock), 0, st, g, idx, weff, s, Q64, rows64, rows32);
 }
 
