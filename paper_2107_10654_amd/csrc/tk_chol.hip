@@ -242,10 +242,12 @@ __device__ inline int acc_c(int y) {
 //    (its last term L_{j,j-1} L_{j,j-1}^T from the tile it made itself, still in
 //    LDS), the factor and inverse of S_jj, then the next tile
 //    L_{j+1,j} = S_{j+1,j} L_jj^{-T}, which it keeps in LDS for the next column;
-//  * the other workgroups take tickets, column by column, for the tiles
-//    L_ij = S_ij L_jj^{-T}, i >= j + 2, and for the partial sums of column j + 2
-//    (S_{j+2,j+2} and S_{j+3,j+2} over k <= j, left in a scratch area for the
-//    chain).
+//    both tiles are published together;
+//  * the other workgroups take tickets, column by column j, for the tiles
+//    L_ij = S_ij L_jj^{-T}, i >= j + 2, then for the finished S_{j+2,j+1} (its
+//    last term, with the chain's tile L_{j+1,j}) and for the partial sums of
+//    column j + 2 (S_{j+2,j+2} and S_{j+3,j+2} over k <= j), all left in a
+//    scratch area for the chain.
 // Each tile is written once, then its flag is raised; published tiles are read
 // with agent-scope coherent loads, so no cache invalidation is needed.  A
 // ticketed task waits only on smaller tickets or on chain tiles of earlier
@@ -364,11 +366,11 @@ __device__ inline void publish_tile(int32_t* flag) {
     __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// tickets of column j: tiles (i, j) for i >= j + 2, then the partial sums of
-// column j + 2
+// tickets of column j: tiles (i, j) for i >= j + 2, then the finished
+// S_{j+2,j+1} and the partial sums of column j + 2
 __host__ __device__ inline int64_t chol_column_tickets(int64_t nblk, int64_t j) {
   const int64_t tiles = nblk - j - 2 > 0 ? nblk - j - 2 : 0;
-  return tiles + (j + 2 < nblk ? 1 : 0);
+  return tiles + (j + 2 < nblk ? 2 : 0);
 }
 __host__ __device__ inline int64_t chol_flow_tasks(int64_t nblk) {
   int64_t n = 0;
@@ -389,8 +391,8 @@ __device__ inline void store_block(double* dst, int ld, int rows, const double (
       }
 }
 
-// pre: kCholAuxBlocks-sized scratch past the solves' chain matrices; column c's
-// partial sums at blocks 2c (S_cc) and 2c + 1 (S_{c+1,c})
+// pre: scratch; column c's partial sums at blocks 2c (S_cc) and 2c + 1
+// (S_{c+1,c}, then finished in place)
 __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict__ M, int64_t d,
                                                               int64_t nblk,
                                                               double* __restrict__ Linv_diag,
@@ -410,6 +412,7 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
   const int tx = tid & 15, ty = tid >> 4;
   int32_t* tile_flag = flags + kFlagStride;  // flags[0] is the ticket, flags[1] the abort word
   int32_t* pre_flag = tile_flag + (nblk * (nblk + 1) / 2) * kFlagStride;
+  int32_t* post_flag = pre_flag + nblk * kFlagStride;  // S_{c+1,c} finished
   bool failed = false;
   auto rows_of = [&](int64_t b) {
     return static_cast<int>((d - b * NB) < NB ? (d - b * NB) : NB);
@@ -474,11 +477,14 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
         atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
                   static_cast<unsigned long long>(__double_as_longlong(pmin)));
       }
-      publish_tile(&tile_flag[tile_flag_index(j, j)]);
-      if (!next) break;
-      // S_{j+1,j}: partial sums (or A), then its last term L_{j+1,j-1} L_{j,j-1}^T
+      if (!next) {
+        publish_tile(&tile_flag[tile_flag_index(j, j)]);
+        break;
+      }
+      // S_{j+1,j}: A_{1,0}, or the scratch block its ticketed task finished
       double Sn[2][2][4];
-      if (j >= 2) {
+      if (j >= 1) {
+        wait2(&post_flag[j * kFlagStride], nullptr);
         const double* P1 = pre + (2 * j + 1) * NB * NB;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -490,14 +496,8 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       } else {
         load_block(M, d, i10, r1, j0, rj, Sn);
       }
-      if (j >= 1) {
-        wait2(&tile_flag[tile_flag_index(j + 1, j - 1)], nullptr);
-        stage_tile(M, d, i10, r1, j - 1, Ld);
-        __syncthreads();
-        sub_gemm_nt(Ld, Lc, Sn);
-        __syncthreads();  // Lc and Ld are rewritten below
-      }
-      // L_{j+1,j} = S_{j+1,j} Li_jj^T: stored, published and kept in Lc
+      // L_{j+1,j} = S_{j+1,j} Li_jj^T: stored, kept in Lc, published with (j, j)
+      __syncthreads();  // every wave is done reading Lc (the previous tile)
       store_block(Ld, LDA, r1, Sn);
       __syncthreads();
       doublex4 acc[2][2];
@@ -513,7 +513,14 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
             Lc[r * LDA + c] = val;
             if (r < r1) M[(i10 + r) * d + j0 + c] = val;
           }
-      publish_tile(&tile_flag[tile_flag_index(j + 1, j)]);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) {
+        __hip_atomic_store(&tile_flag[tile_flag_index(j, j)], 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&tile_flag[tile_flag_index(j + 1, j)], 1, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   } else {
     // ---------------- ticketed tasks
@@ -533,7 +540,33 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       }
       const int64_t off = t - start;
       const int64_t ntile = nblk - j - 2 > 0 ? nblk - j - 2 : 0;
-      if (off < ntile) {
+      if (off == ntile) {
+        // finished S_{c+1,c}, c = j + 1: its partial sums (or A for c = 1) minus
+        // L_{c+1,j} L_{c,j}^T, the second tile being the chain's
+        const int64_t c = j + 1, c0 = c * NB, n0 = (c + 1) * NB;
+        const int rc = rows_of(c), rn = rows_of(c + 1);
+        double* P1 = pre + (2 * c + 1) * NB * NB;
+        double S[2][2][4];
+        if (c >= 2) {
+          wait2(&pre_flag[c * kFlagStride], nullptr);
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                S[x][y][v] = load_tile(&P1[acc_r(x, v) * NB + acc_c(y)]);
+        } else {
+          load_block(M, d, n0, rn, c0, rc, S);
+        }
+        wait2(&tile_flag[tile_flag_index(c + 1, j)], &tile_flag[tile_flag_index(c, j)]);
+        stage_tile(M, d, n0, rn, j, La);
+        stage_tile(M, d, c0, rc, j, Lb);
+        __syncthreads();
+        sub_gemm_nt(La, Lb, S);
+        store_block(P1, NB, NB, S);
+        publish_tile(&post_flag[c * kFlagStride]);
+      } else if (off < ntile) {
         // tile (i, j), i >= j + 2 (block j is full)
         const int64_t i = j + 2 + off, i0 = i * NB, j0 = j * NB;
         const int ri = rows_of(i);
@@ -906,7 +939,7 @@ void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot,
                      int32_t* flags, hipStream_t st) {
   const int64_t nblk = cdiv(d, NB);
   int32_t* ff = flags + 2;  // flags[0..1] are the solves' tickets
-  const int64_t nflags = (1 + nblk * (nblk + 1) / 2 + nblk) * kFlagStride;
+  const int64_t nflags = (1 + nblk * (nblk + 1) / 2 + 2 * nblk) * kFlagStride;
   hipLaunchKernelGGL(chol_flags_kernel, dim3(static_cast<unsigned>(cdiv(nflags, kBlock))),
                      dim3(kBlock), 0, st, ff, nflags);
   double* pre = Linv_diag + 3 * nblk * NB * NB;  // past the inverses and chain matrices

@@ -202,7 +202,7 @@ constexpr int kCholNb = 64;
 constexpr int kCholAuxBlocks = 5;
 inline int64_t chol_flag_words(int64_t d) {
   const int64_t nblk = (d + kCholNb - 1) / kCholNb;
-  return 2 + (1 + nblk * (nblk + 1) / 2 + nblk) * 32;  // one 128-byte line per flag
+  return 2 + (1 + nblk * (nblk + 1) / 2 + 2 * nblk) * 32;  // one 128-byte line per flag
 }
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
                      int32_t* flags, hipStream_t st);
