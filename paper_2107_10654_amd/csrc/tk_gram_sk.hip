@@ -224,22 +224,6 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
       ob[side] = base / RL;
       no[side] = static_cast<int>(last / RL - ob[side] + 1);
     }
-    // this thread's formation items: outer index within the tile and LDS
-    // offset of the last-mode row in rT (the zero row when the design row is
-    // past d)
-    int oidx[2][ITEMS], iofs_q[2][ITEMS];
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        // consecutive lanes take consecutive rows: conflict-free LDS stores
-        const int e = tid + k * kSkThreads;
-        const int i = e % T, tg = (e / T) * IW;
-        const int64_t r = (side == 0 ? r0 : c0) + i;
-        const int64_t rr = r < d ? r : d - 1;
-        oidx[side][k] = static_cast<int>(rr / RL - ob[side]);
-        iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
-      }
     auto fetch = [&](int64_t c) __attribute__((always_inline)) {
       const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
 #pragma unroll
@@ -278,66 +262,9 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
     fetch(c_begin);
     commit(rT);
     __syncthreads();
-    // the rT rows of each item's outer factors (modes other than L), one byte
-    // per mode, packed
-    uint64_t pk[2][ITEMS];
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k)
-        pk[side][k] = *reinterpret_cast<const uint64_t*>(
-            offs + (side * NO + oidx[side][k]) * kMaxOrder);
-    // Kronecker rows of both tiles: y[r][t] = (prod over the outer modes of
-    // their factor entries) * q_L[r % R_L][t], in the operand precision; NM1
-    // (= N - 1 outer factors) is a constant so the LDS reads issue together
-    auto form = [&](auto nm1, const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
-      constexpr int NM1 = decltype(nm1)::value;
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (side == 1 && diag) break;
-        Op* Y = side == 0 ? ya : yb;
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          const int e = tid + k * kSkThreads;
-          const int i = e % T, tg = (e / T) * IW;
-          const f32x4* qp = reinterpret_cast<const f32x4*>(rs + iofs_q[side][k]);
-          if constexpr (V::EPL == 8) {
-            f32x4 o0 = {1.0f, 1.0f, 1.0f, 1.0f}, o1 = o0;
-#pragma unroll
-            for (int m = 0; m < NM1; ++m) {
-              const f32x4* fp = reinterpret_cast<const f32x4*>(
-                  rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
-              o0 *= fp[0];
-              o1 *= fp[1];
-            }
-            const f32x4 q0 = qp[0], q1 = qp[1];
-            bf16x8 v;
-            v[0] = V::cvt(o0.x * q0.x);
-            v[1] = V::cvt(o0.y * q0.y);
-            v[2] = V::cvt(o0.z * q0.z);
-            v[3] = V::cvt(o0.w * q0.w);
-            v[4] = V::cvt(o1.x * q1.x);
-            v[5] = V::cvt(o1.y * q1.y);
-            v[6] = V::cvt(o1.z * q1.z);
-            v[7] = V::cvt(o1.w * q1.w);
-            *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
-          } else {
-            f32x4 o = {1.0f, 1.0f, 1.0f, 1.0f};
-#pragma unroll
-            for (int m = 0; m < NM1; ++m)
-              o *= *reinterpret_cast<const f32x4*>(
-                  rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
-            const f32x4 q = qp[0];
-            Op* y = &Y[i * LDK + tg];
-            y[0] = V::cvt(o.x * q.x);
-            y[1] = V::cvt(o.y * q.y);
-            y[2] = V::cvt(o.z * q.z);
-            y[3] = V::cvt(o.w * q.w);
-          }
-        }
-      }
-    };
-    auto form_rows = [&](const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
+    // a formation functor takes NM1 (= N - 1 outer factors) as a constant so
+    // that its LDS reads issue together
+    auto by_order = [&](auto form, const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
       static_assert(kMaxOrder == 8, "one case per order");
       switch (N) {
         case 1: form(std::integral_constant<int, 0>{}, rs, ya, yb); break;
@@ -365,33 +292,186 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
                                 acc[a][bb]);
       }
     };
-    if constexpr (DB) {
-      // chunk c_begin + j lives in set j % 2; its rows are formed one
-      // iteration ahead, and chunk c + 2 is staged where chunk c was
-      if (c_begin + 1 < c_end) fetch(c_begin + 1);
-      form_rows(rT, YA, YBs);
-      if (c_begin + 1 < c_end) commit(rT2);
-      __syncthreads();
-      for (int64_t c = c_begin; c < c_end; ++c) {
-        const bool odd = ((c - c_begin) & 1) != 0;
-        Src* rcur = odd ? rT2 : rT;
-        const Src* rnext = odd ? rT : rT2;
-        if (c + 2 < c_end) fetch(c + 2);
-        mma_chunk(odd ? YA2 : YA, odd ? YB2s : YBs);
-        if (c + 1 < c_end) form_rows(rnext, odd ? YA : YA2, odd ? YBs : YB2s);
-        if (c + 2 < c_end) commit(rcur);
-        __syncthreads();
-      }
-    } else {
-      for (int64_t c = c_begin; c < c_end; ++c) {
-        const bool more = c + 1 < c_end;
-        if (more) fetch(c + 1);
+    // the chunks [c_begin, c_end) of the tile with a given row formation
+    auto run = [&](auto form_rows) __attribute__((always_inline)) {
+      if constexpr (DB) {
+        // chunk c_begin + j lives in set j % 2; its rows are formed one
+        // iteration ahead, and chunk c + 2 is staged where chunk c was
+        if (c_begin + 1 < c_end) fetch(c_begin + 1);
         form_rows(rT, YA, YBs);
+        if (c_begin + 1 < c_end) commit(rT2);
         __syncthreads();
-        mma_chunk(YA, YBs);  // then stage the prefetched chunk
-        if (more) commit(rT);
-        __syncthreads();
+        for (int64_t c = c_begin; c < c_end; ++c) {
+          const bool odd = ((c - c_begin) & 1) != 0;
+          Src* rcur = odd ? rT2 : rT;
+          const Src* rnext = odd ? rT : rT2;
+          if (c + 2 < c_end) fetch(c + 2);
+          mma_chunk(odd ? YA2 : YA, odd ? YB2s : YBs);
+          if (c + 1 < c_end) form_rows(rnext, odd ? YA : YA2, odd ? YBs : YB2s);
+          if (c + 2 < c_end) commit(rcur);
+          __syncthreads();
+        }
+      } else {
+        for (int64_t c = c_begin; c < c_end; ++c) {
+          const bool more = c + 1 < c_end;
+          if (more) fetch(c + 1);
+          form_rows(rT, YA, YBs);
+          __syncthreads();
+          mma_chunk(YA, YBs);  // then stage the prefetched chunk
+          if (more) commit(rT);
+          __syncthreads();
+        }
       }
+    };
+    // Kronecker rows of both tiles: y[r][t] = (prod over the outer modes of
+    // their factor entries) * q_L[r % R_L][t], rounded once to the operand
+    // precision
+    bool formed = false;
+    if constexpr (V::EPL == 8 && T == 256) {
+      if (RL % 4 == 0 && N <= 4 && !diag) {
+        // BF16 operands, 256 tiles, R_L a multiple of 4, off-diagonal: an
+        // item is 4 rows x 4 samples, the 4 rows sharing their outer index
+        // (d and the tile origins are multiples of 4, so a row quad is
+        // wholly inside or past d), so the outer factors are read and
+        // multiplied once per 4 rows.  The products are taken in the same
+        // order as below.  Eight consecutive lanes cover one quad's 32
+        // samples.  (A diagonal tile forms one side only, which the one-row
+        // items below spread over all threads.)
+        constexpr int SG = BK / 4;
+        constexpr int PER_SIDE = (T / 4) * SG;
+        constexpr int ITEMS4 = 2 * PER_SIDE / kSkThreads;
+        static_assert(ITEMS4 >= 1 && (2 * PER_SIDE) % kSkThreads == 0 && PER_SIDE % 64 == 0,
+                      "items per thread");
+        int qo[ITEMS4], qs[ITEMS4], yo[ITEMS4];
+        uint64_t pk[ITEMS4];
+#pragma unroll
+        for (int k = 0; k < ITEMS4; ++k) {
+          const int it = tid + k * kSkThreads;
+          const int side = it / PER_SIDE, e = it - side * PER_SIDE;
+          const int sg = e % SG, rb = e / SG;
+          const int64_t r = (side == 0 ? r0 : c0) + 4 * rb;
+          const bool in = r < d;
+          const int64_t rr = in ? r : d - 1;
+          const int oi = static_cast<int>(rr / RL - ob[side]);
+          qo[k] = (in ? sl + static_cast<int>(rr % RL) : SR) * RT + 4 * sg;
+          qs[k] = in ? RT : 0;  // past d: the zero row four times
+          yo[k] = 4 * rb * LDK + 4 * sg;
+          pk[k] = *reinterpret_cast<const uint64_t*>(offs + (side * NO + oi) * kMaxOrder);
+        }
+        auto form4 = [&](auto nm1, const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
+          constexpr int NM1 = decltype(nm1)::value;
+#pragma unroll
+          for (int k = 0; k < ITEMS4; ++k) {
+            const int it = tid + k * kSkThreads;
+            const int side = it / PER_SIDE;
+            const int t4 = 4 * (it % SG);
+            f32x4 o = {1.0f, 1.0f, 1.0f, 1.0f};
+#pragma unroll
+            for (int m = 0; m < NM1; ++m)
+              o *= *reinterpret_cast<const f32x4*>(
+                  rs + static_cast<int>((pk[k] >> (8 * m)) & 0xff) * RT + t4);
+            Op* y = (side == 0 ? ya : yb) + yo[k];
+            const Src* qp = rs + qo[k];
+            f32x4 q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q[j] = *reinterpret_cast<const f32x4*>(qp + j * qs[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              bf16x4 v;
+              v[0] = V::cvt(o.x * q[j].x);
+              v[1] = V::cvt(o.y * q[j].y);
+              v[2] = V::cvt(o.z * q[j].z);
+              v[3] = V::cvt(o.w * q[j].w);
+              *reinterpret_cast<bf16x4*>(y + j * LDK) = v;
+            }
+          }
+        };
+        run([&](const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
+          switch (N) {
+            case 1: form4(std::integral_constant<int, 0>{}, rs, ya, yb); break;
+            case 2: form4(std::integral_constant<int, 1>{}, rs, ya, yb); break;
+            case 3: form4(std::integral_constant<int, 2>{}, rs, ya, yb); break;
+            default: form4(std::integral_constant<int, 3>{}, rs, ya, yb); break;
+          }
+        });
+        formed = true;
+      }
+    }
+    if (!formed) {
+      // an item is one row x IW samples: outer index within the tile and
+      // LDS offset of the last-mode row in rT (the zero row when the design
+      // row is past d)
+      int oidx[2][ITEMS], iofs_q[2][ITEMS];
+#pragma unroll
+      for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          // consecutive lanes take consecutive rows: conflict-free LDS stores
+          const int e = tid + k * kSkThreads;
+          const int i = e % T, tg = (e / T) * IW;
+          const int64_t r = (side == 0 ? r0 : c0) + i;
+          const int64_t rr = r < d ? r : d - 1;
+          oidx[side][k] = static_cast<int>(rr / RL - ob[side]);
+          iofs_q[side][k] = (r < d ? (sl + static_cast<int>(rr % RL)) : SR) * RT + tg;
+        }
+      // the rT rows of each item's outer factors (modes other than L), one
+      // byte per mode, packed
+      uint64_t pk[2][ITEMS];
+#pragma unroll
+      for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          pk[side][k] = *reinterpret_cast<const uint64_t*>(
+              offs + (side * NO + oidx[side][k]) * kMaxOrder);
+      auto form = [&](auto nm1, const Src* rs, Op* ya, Op* yb) __attribute__((always_inline)) {
+        constexpr int NM1 = decltype(nm1)::value;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (side == 1 && diag) break;
+          Op* Y = side == 0 ? ya : yb;
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            const int e = tid + k * kSkThreads;
+            const int i = e % T, tg = (e / T) * IW;
+            const f32x4* qp = reinterpret_cast<const f32x4*>(rs + iofs_q[side][k]);
+            if constexpr (V::EPL == 8) {
+              f32x4 o0 = {1.0f, 1.0f, 1.0f, 1.0f}, o1 = o0;
+#pragma unroll
+              for (int m = 0; m < NM1; ++m) {
+                const f32x4* fp = reinterpret_cast<const f32x4*>(
+                    rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+                o0 *= fp[0];
+                o1 *= fp[1];
+              }
+              const f32x4 q0 = qp[0], q1 = qp[1];
+              bf16x8 v;
+              v[0] = V::cvt(o0.x * q0.x);
+              v[1] = V::cvt(o0.y * q0.y);
+              v[2] = V::cvt(o0.z * q0.z);
+              v[3] = V::cvt(o0.w * q0.w);
+              v[4] = V::cvt(o1.x * q1.x);
+              v[5] = V::cvt(o1.y * q1.y);
+              v[6] = V::cvt(o1.z * q1.z);
+              v[7] = V::cvt(o1.w * q1.w);
+              *reinterpret_cast<bf16x8*>(&Y[i * LDK + tg]) = v;
+            } else {
+              f32x4 o = {1.0f, 1.0f, 1.0f, 1.0f};
+#pragma unroll
+              for (int m = 0; m < NM1; ++m)
+                o *= *reinterpret_cast<const f32x4*>(
+                    rs + static_cast<int>((pk[side][k] >> (8 * m)) & 0xff) * RT + tg);
+              const f32x4 q = qp[0];
+              Op* y = &Y[i * LDK + tg];
+              y[0] = V::cvt(o.x * q.x);
+              y[1] = V::cvt(o.y * q.y);
+              y[2] = V::cvt(o.z * q.z);
+              y[3] = V::cvt(o.w * q.w);
+            }
+          }
+        }
+      };
+      run([&](const Src* rs, Op* ya, Op* yb)
+              __attribute__((always_inline)) { by_order(form, rs, ya, yb); });
     }
     typename V::Out* out = slots + (slot0 + seg) * static_cast<int64_t>(T * T);
 #pragma unroll

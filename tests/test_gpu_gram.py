@@ -17,10 +17,15 @@ magnitudes the entry adds up):
 * BF16 operands: 2^-8 (1 + 2^-8) A_ij (each operand rounded once to BF16, a
   product of two at most 2^-8 off) + 2e-5 A_ij;
 * b (FP64 in every precision): 1e-11 sum_t w_t |x_t| |q_t|.
+The 1e-14 relative bar on lambda P holds for well-conditioned factors (every
+case here has cond(A_n) < 10); inverting C_n = A_n^T A_n in FP64 costs about
+cond(C_n) ulps, so an ill-conditioned factor would need a wider one.
 Shapes cover the three Gram tile edges (64: d <= 64; 128; 256 with the
 double-buffered chunk loop: d >= 2048), ragged last tiles, orders 2 to 4,
-a rank-1 mode and an observation mask; s = 5000 spreads the stream-K ranges
-over tile boundaries with odd and even chunk counts.
+a rank-1 mode and an observation mask, each with a last-mode rank R_L that
+is and one that is not a multiple of 4 (the two BF16 row formations); s =
+5000 spreads the stream-K ranges over tile boundaries with odd and even
+chunk counts.
 """
 import functools
 
@@ -43,6 +48,11 @@ CASES = [
     ((30, 28, 20), (6, 7, 1), None),        # rank-1 last mode, d = 42
     ((40, 36, 30), (16, 16, 8), None),      # d = 2048: 256 tiles
     ((12, 11, 10, 9), (8, 8, 6, 7), None),  # order 4, d = 2688: 256 tiles, ragged
+    # R_L a multiple of 4 (BF16: rows formed four at a time)
+    ((23, 19, 17), (3, 4, 4), None),        # d = 48: one 64 tile, rows past d
+    ((41, 37, 29), (5, 6, 8), 0.3),         # d = 240: 128 tiles, ragged, masked
+    ((60, 50), (8, 12), None),              # order 2, d = 96
+    ((18, 13, 11, 8), (10, 8, 7, 4), None),  # order 4, d = 2240: 256 tiles, ragged
 ]
 
 
