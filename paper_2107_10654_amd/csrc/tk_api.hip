@@ -609,6 +609,8 @@ void sketch_factor(SketchRun& R) {
   if (resid_small_ok(g))
     launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
+  else if (resid_big_ok(g))
+    launch_resid_big(g, w.rows64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr, R.st);
   else
     launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
@@ -665,6 +667,8 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   for (int k = 0; k <= iters; ++k) {
     if (resid_small_ok(g)) {
       launch_resid_small(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
+    } else if (resid_big_ok(g)) {
+      launch_resid_big(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
     } else {
       launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
       launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
@@ -824,6 +828,8 @@ tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* o,
   if (resid_small_ok(g))
     launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
+  else if (resid_big_ok(g))
+    launch_resid_big(g, w.rows64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr, R.st);
   else
     launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);

@@ -1010,6 +1010,211 @@ __global__ __launch_bounds__(64 * kSpWaves) void sum_parts_wide_kernel(
   }
 }
 
+// ------------------------------------------------------------------ fused residual, larger d
+// out_w = sum_t c_t q_t over workgroup w's sample chunks, c_t = a_t - b_t (q_t . h)
+// (a null: a_t = 0; h null: c_t = a_t), in one pass over the FP64 sample rows.
+// With design index r = o R_L + l, q_t[r] = O_t[o] q^(L)_t[l] and
+//   q_t . h = sum_o O_t[o] U[o][t],  U[o][t] = sum_l h[o R_L + l] q^(L)_t[l],
+//   sum_t c_t q_t[o R_L + l] = sum_t (c_t O_t[o]) q^(L)_t[l],
+// both products of a (16 outer indices) x (samples or last-mode entries) block
+// on v_mfma_f64_16x16x4.  Per chunk of 32 samples wave w takes the blocks of
+// 16 outer indices w, w + 4, ...: U and its lanes' share of the dot products,
+// which are added over the lanes and then the waves in wave order; then c_t
+// and the accumulation of Z[o][l] in registers.  h sits in LDS; the outer
+// factors O_t[o] are products of staged row entries, formed where used.
+constexpr int kRbMaxO = 512;  // outer indices (4 waves x 8 blocks of 16)
+constexpr int kRbMaxD = 4096;
+constexpr int kRbMaxRL = 32;
+
+// entry m of a packed offset word: the LDS row of outer factor m
+__device__ inline int rb_row(uint64_t pk, int m) { return static_cast<int>((pk >> (8 * m)) & 0xff); }
+
+// two workgroups per CU where the registers allow it without spilling
+template <int NOBW, int NLB>
+__global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_kernel(
+    Geom g, const double* __restrict__ rows, const double* __restrict__ a,
+    const double* __restrict__ b, const double* __restrict__ h, int64_t s, int64_t cpw,
+    double* __restrict__ part, const int32_t* done) {
+  if (done && *done) return;
+  constexpr int KS = kVK / 4;         // k-steps over the chunk's samples
+  constexpr int KL = kRbMaxRL / 4;    // k-steps over the last mode (at most)
+  __shared__ __align__(8) unsigned char offs[kRbMaxO][kMaxOrder];
+  __shared__ double ab[2][kVK];
+  __shared__ double red[4][kVK];
+  extern __shared__ double rb_smem[];  // h (d doubles), then the staged rows (sum_r x kVRT)
+  const int64_t d = g.d;
+  double* Hs = rb_smem;
+  double* rT = rb_smem + d;
+  const int RL = g.ranks[g.last], sl = g.soff[g.last], nm1 = g.order - 1;
+  const int O = static_cast<int>(d / RL);
+  const int nob = (O + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nch = row_chunks(s);
+  const int64_t ca = static_cast<int64_t>(blockIdx.x) * cpw;
+  const int64_t cb = ca + cpw < nch ? ca + cpw : nch;
+  for (int o = threadIdx.x; o < O; o += kBlock) {
+    unsigned char* po = offs[o];
+    outer_offsets(g, o, po);
+    for (int m = nm1; m < kMaxOrder; ++m) po[m] = 0;
+  }
+  if (h)
+    for (int64_t i = threadIdx.x; i < d; i += kBlock) Hs[i] = h[i];
+  doublex4 Z[NOBW][NLB];
+#pragma unroll
+  for (int j = 0; j < NOBW; ++j)
+#pragma unroll
+    for (int lb = 0; lb < NLB; ++lb) Z[j][lb] = doublex4{0, 0, 0, 0};
+  double pf[kVPFSmall];
+  auto commit = [&](int64_t c) __attribute__((always_inline)) {
+    const int nval = kVK * g.sum_r;
+#pragma unroll
+    for (int k = 0; k < kVPFSmall; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e < nval) rT[(e >> 5) * kVRT + (e & 31)] = pf[k];
+    }
+    if (threadIdx.x < kVK) {
+      const int64_t tt = c * kVK + threadIdx.x;
+      ab[0][threadIdx.x] = (tt < s && a) ? a[tt] : 0.0;
+      ab[1][threadIdx.x] = (tt < s && b) ? b[tt] : 0.0;
+    }
+  };
+  if (ca < cb) {
+    vec_fetch<kVPFSmall>(g, rows, ca, pf);
+    commit(ca);
+  }
+  __syncthreads();
+  for (int64_t ch = ca; ch < cb; ++ch) {
+    const bool more = ch + 1 < cb;
+    if (more) vec_fetch<kVPFSmall>(g, rows, ch + 1, pf);
+    if (h) {
+      // q^(L) operands of U, B[l][t] (lane: l = 4 k + lane / 16, t = tb 16 + lane % 16),
+      // loaded together (rows clamped into the last mode, zero past R_L)
+      double qa[2][KL];
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+          qa[tb][k] = 0.0;
+          if (4 * k < RL) {  // k-steps past R_L are skipped below
+            const int l = 4 * k + lane / 16;
+            const double v = rT[(sl + (l < RL ? l : RL - 1)) * kVRT + tb * 16 + lane % 16];
+            qa[tb][k] = l < RL ? v : 0.0;
+          }
+        }
+      // this lane's share of q_t . h for t = tb 16 + lane % 16
+      double pt[2] = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < NOBW; ++j) {
+        const int ob = wave + 4 * j;
+        if (ob < nob) {
+          const int oa = ob * 16 + lane % 16;
+          double hv[KL];
+#pragma unroll
+          for (int k = 0; k < KL; ++k) {
+            hv[k] = 0.0;
+            if (4 * k < RL) {
+              const int l = 4 * k + lane / 16;
+              const bool ok = oa < O && l < RL;
+              const double v = Hs[ok ? oa * RL + l : 0];
+              hv[k] = ok ? v : 0.0;
+            }
+          }
+          // outer factors at the accumulator positions o = ob 16 + lane / 16 + 4 v
+          uint64_t pk[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int o = ob * 16 + lane / 16 + 4 * v;
+            pk[v] = *reinterpret_cast<const uint64_t*>(offs[o < O ? o : 0]);
+          }
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb) {
+            doublex4 u = doublex4{0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < KL; ++k)
+              if (4 * k < RL) u = __builtin_amdgcn_mfma_f64_16x16x4f64(hv[k], qa[tb][k], u, 0, 0, 0);
+            const int t = tb * 16 + lane % 16;
+            double ov[4] = {1.0, 1.0, 1.0, 1.0};
+            for (int m = 0; m < nm1; ++m) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) ov[v] *= rT[rb_row(pk[v], m) * kVRT + t];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int o = ob * 16 + lane / 16 + 4 * v;
+              pt[tb] = fma(o < O ? ov[v] : 0.0, u[v], pt[tb]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) {
+        double v = pt[tb];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane < 16) red[wave][tb * 16 + lane] = v;
+      }
+    }
+    __syncthreads();
+    // this lane's operand samples t = 4 ks + lane / 16: c_t, and q^(L) as
+    // B[t][l] (l = lb 16 + lane % 16)
+    double cks[KS], qb[NLB][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int t = 4 * ks + lane / 16;
+      cks[ks] = h ? ab[0][t] - ab[1][t] * (((red[0][t] + red[1][t]) + red[2][t]) + red[3][t])
+                  : ab[0][t];
+#pragma unroll
+      for (int lb = 0; lb < NLB; ++lb) {
+        const int l = lb * 16 + lane % 16;
+        const double v = rT[(sl + (l < RL ? l : RL - 1)) * kVRT + t];
+        qb[lb][ks] = l < RL ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NOBW; ++j) {
+      const int ob = wave + 4 * j;
+      if (ob < nob) {
+        const int o = ob * 16 + lane % 16;
+        const bool ook = o < O;
+        const uint64_t pk = *reinterpret_cast<const uint64_t*>(offs[ook ? o : 0]);
+        double ov[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ov[ks] = 1.0;
+        for (int m = 0; m < nm1; ++m) {
+          const double* row = rT + rb_row(pk, m) * kVRT + lane / 16;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) ov[ks] *= row[4 * ks];
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const double av = ook ? ov[ks] * cks[ks] : 0.0;
+#pragma unroll
+          for (int lb = 0; lb < NLB; ++lb)
+            Z[j][lb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, qb[lb][ks], Z[j][lb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (more) commit(ch + 1);
+    __syncthreads();
+  }
+  // Z register v: o = ob 16 + lane / 16 + 4 v, l = lb 16 + lane % 16
+  double* out = part + static_cast<int64_t>(blockIdx.x) * d;
+#pragma unroll
+  for (int j = 0; j < NOBW; ++j) {
+    const int ob = wave + 4 * j;
+    if (ob < nob) {
+#pragma unroll
+      for (int lb = 0; lb < NLB; ++lb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = ob * 16 + lane / 16 + 4 * v, l = lb * 16 + lane % 16;
+          if (o < O && l < RL) out[static_cast<int64_t>(o) * RL + l] = Z[j][lb][v];
+        }
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -1161,9 +1366,33 @@ int64_t reg_grid(int64_t s) {
 
 bool resid_small_ok(const Geom& g) { return g.d <= kSmD && g.sum_r <= kSmSumR; }
 
+bool resid_big_ok(const Geom& g) {
+  const int RL = g.ranks[g.last];
+  return !resid_small_ok(g) && g.d <= kRbMaxD && g.sum_r <= 64 && RL <= kRbMaxRL &&
+         g.d / RL <= kRbMaxO;
+}
+
+namespace {
+struct BigPlan {
+  int64_t nwg;  // workgroups
+  int64_t cpw;  // sample chunks per workgroup
+};
+
+BigPlan plan_big(int64_t s) {
+  // about two workgroups per CU; each adds a d-vector of partials
+  BigPlan bp;
+  const int64_t nch = row_chunks(s);
+  const int64_t want = nch < 512 ? nch : 512;
+  bp.cpw = cdiv(nch, want < 1 ? 1 : want);
+  bp.nwg = cdiv(nch, bp.cpw);
+  return bp;
+}
+}  // namespace
+
 int64_t vec_part_doubles(const Geom& g, int64_t s) {
   const VecPlan vp = plan_vec(g, s);
   int64_t n = vp.nsplit * g.d;
+  if (resid_big_ok(g) && plan_big(s).nwg * g.d > n) n = plan_big(s).nwg * g.d;
   if (vp.nr * s > n) n = vp.nr * s;
   if (resid_small_ok(g) && plan_small(s).nwg * g.d > n) n = plan_small(s).nwg * g.d;
   if (resid_small_ok(g) && reg_grid(s) * g.d > n) n = reg_grid(s) * g.d;
@@ -1253,6 +1482,30 @@ void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, co
   hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(static_cast<unsigned>(cdiv(g.d, 64))),
                      dim3(64 * kSpWaves), 0, st, static_cast<const double*>(part), nwg, g.d, out,
                      done);
+}
+
+void launch_resid_big(const Geom& g, const double* rows64, const double* a, const double* b,
+                      const double* h, int64_t s, double* part, double* out, const int32_t* done,
+                      hipStream_t st) {
+  const BigPlan bp = plan_big(s);
+  const int RL = g.ranks[g.last];
+  const int nob = static_cast<int>(cdiv(g.d / RL, 16));
+  const int nobw = static_cast<int>(cdiv(nob, 4));
+  const int nlb = static_cast<int>(cdiv(RL, 16));
+  const size_t lds = sizeof(double) * static_cast<size_t>(g.d + g.sum_r * kVRT);
+  const dim3 grid(static_cast<unsigned>(bp.nwg));
+#define TK_RB_CASE(W, NL)                                                                      \
+  if (nobw <= W && nlb == NL) {                                                                \
+    hipLaunchKernelGGL((resid_big_kernel<W, NL>), grid, dim3(kBlock), lds, st, g, rows64, a, b, \
+                       h, s, bp.cpw, part, done);                                               \
+  } else
+  // (eight blocks of 16 outer indices per wave with R_L > 16 would exceed d = 4096)
+  TK_RB_CASE(1, 1) TK_RB_CASE(2, 1) TK_RB_CASE(4, 1) TK_RB_CASE(8, 1)
+  TK_RB_CASE(1, 2) TK_RB_CASE(2, 2) TK_RB_CASE(4, 2) {}
+#undef TK_RB_CASE
+  hipLaunchKernelGGL(sum_parts_wide_kernel, dim3(static_cast<unsigned>(cdiv(g.d, 64))),
+                     dim3(64 * kSpWaves), 0, st, static_cast<const double*>(part), bp.nwg, g.d,
+                     out, done);
 }
 
 void launch_rows_t_vec(const Geom& g, const double* rows64, const double* c, int64_t s,

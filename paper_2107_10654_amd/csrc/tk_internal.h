@@ -165,6 +165,13 @@ bool resid_small_ok(const Geom& g);
 void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
                         const double* b, const double* h, int64_t s, double* part, double* out,
                         const int32_t* done, hipStream_t st);
+// Larger Kronecker dimension (resid_big_ok: d <= 4096, at most 512 outer
+// indices, R_L <= 32, sum_r <= 64): the same sum from the FP64 sample rows in
+// one pass; part: vec_part_doubles.
+bool resid_big_ok(const Geom& g);
+void launch_resid_big(const Geom& g, const double* rows64, const double* a, const double* b,
+                      const double* h, int64_t s, double* part, double* out, const int32_t* done,
+                      hipStream_t st);
 // The per-workgroup partials of the same sum only (part[k][r], k < return value).
 int64_t launch_resid_small_parts(const Geom& g, const int32_t* idx, const double* Q64,
                                  const double* a, const double* b, const double* h, int64_t s,

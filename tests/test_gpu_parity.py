@@ -172,6 +172,37 @@ def test_sketched_refined_wide_rank_sum(tk, precision):
     assert rel(G.cpu().numpy(), Gr) <= 1e-9
 
 
+# 256 < d <= 4096 with at most 512 outer indices, R_L <= 32 and a rank sum
+# <= 64: the residual is one fused pass (FP64 MFMA in blocks of 16 outer
+# indices, 1 to 8 blocks per wave, one or two 16-wide last-mode blocks).
+# Shapes: (d, R_L, outer indices) = (512, 8, 64), (2880, 24, 120),
+# (2048, 8, 256), (4080, 17, 240), (2688, 7, 384) order 4, (640, 32, 20)
+# order 2, (378, 9, 42) masked; s = 700 leaves fewer chunks than workgroups
+# and a ragged last chunk.
+@pytest.mark.parametrize("precision", ["bf16", "f32"])
+@pytest.mark.parametrize("dims,ranks,s,missing", [
+    ((30, 28, 26), (8, 8, 8), 2000, None),
+    ((40, 36, 30), (12, 10, 24), 9000, None),
+    ((40, 36, 30), (16, 16, 8), 6500, None),
+    ((40, 36, 30), (16, 15, 17), 12000, None),
+    ((12, 11, 10, 9), (8, 8, 6, 7), 8500, None),
+    ((80, 70), (20, 32), 2500, None),
+    ((31, 27, 25), (6, 7, 9), 1500, 0.2),
+    ((30, 28, 26), (8, 8, 8), 700, None),
+])
+def test_sketched_refined_fused_residual(tk, precision, dims, ranks, s, missing):
+    p, F = _sketch_case(dims, ranks, 19, missing=missing)
+    lam = 1e-2
+    mask = T(p["mask"].view(np.int32)) if missing else None
+    G, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=13, counter=4,
+                                      precision=precision, refine_max=40, refine_tol=1e-13,
+                                      mask=mask, return_info=True)
+    info = info.cpu().numpy()
+    Gr, _, _, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 13, 4, mask=p["mask"])
+    assert info[3] <= 1e-13, info
+    assert rel(G.cpu().numpy(), Gr) <= 1e-9
+
+
 def test_sketched_masked_matches_oracle(tk):
     dims, ranks = (31, 27, 25), (4, 5, 3)
     p, F = _sketch_case(dims, ranks, 6, missing=0.2)
