@@ -1039,12 +1039,15 @@ __global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_ker
   constexpr int KS = kVK / 4;         // k-steps over the chunk's samples
   constexpr int KL = kRbMaxRL / 4;    // k-steps over the last mode (at most)
   __shared__ __align__(8) unsigned char offs[kRbMaxO][kMaxOrder];
-  __shared__ double ab[2][kVK];
+  __shared__ double abs_[2][2][kVK];  // per buffer: a_t, b_t
   __shared__ double red[4][kVK];
-  extern __shared__ double rb_smem[];  // h (d doubles), then the staged rows (sum_r x kVRT)
+  // h (d doubles), then two buffers of staged rows (sum_r x kVRT each): chunk
+  // k + 1 is staged while chunk k's second half runs
+  extern __shared__ double rb_smem[];
   const int64_t d = g.d;
   double* Hs = rb_smem;
-  double* rT = rb_smem + d;
+  double* rT0 = rb_smem + d;
+  double* rT1 = rT0 + g.sum_r * kVRT;
   const int RL = g.ranks[g.last], sl = g.soff[g.last], nm1 = g.order - 1;
   const int O = static_cast<int>(d / RL);
   const int nob = (O + 15) / 16;
@@ -1065,26 +1068,30 @@ __global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_ker
 #pragma unroll
     for (int lb = 0; lb < NLB; ++lb) Z[j][lb] = doublex4{0, 0, 0, 0};
   double pf[kVPFSmall];
-  auto commit = [&](int64_t c) __attribute__((always_inline)) {
+  auto commit = [&](int64_t c, int buf) __attribute__((always_inline)) {
+    double* rs = buf ? rT1 : rT0;
     const int nval = kVK * g.sum_r;
 #pragma unroll
     for (int k = 0; k < kVPFSmall; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      if (e < nval) rT[(e >> 5) * kVRT + (e & 31)] = pf[k];
+      if (e < nval) rs[(e >> 5) * kVRT + (e & 31)] = pf[k];
     }
     if (threadIdx.x < kVK) {
       const int64_t tt = c * kVK + threadIdx.x;
-      ab[0][threadIdx.x] = (tt < s && a) ? a[tt] : 0.0;
-      ab[1][threadIdx.x] = (tt < s && b) ? b[tt] : 0.0;
+      abs_[buf][0][threadIdx.x] = (tt < s && a) ? a[tt] : 0.0;
+      abs_[buf][1][threadIdx.x] = (tt < s && b) ? b[tt] : 0.0;
     }
   };
   if (ca < cb) {
     vec_fetch<kVPFSmall>(g, rows, ca, pf);
-    commit(ca);
+    commit(ca, 0);
   }
   __syncthreads();
   for (int64_t ch = ca; ch < cb; ++ch) {
     const bool more = ch + 1 < cb;
+    const int buf = static_cast<int>((ch - ca) & 1);
+    const double* rT = buf ? rT1 : rT0;
+    const double(*ab)[kVK] = abs_[buf];
     if (more) vec_fetch<kVPFSmall>(g, rows, ch + 1, pf);
     if (h) {
       // q^(L) operands of U, B[l][t] (lane: l = 4 k + lane / 16, t = tb 16 + lane % 16),
@@ -1133,8 +1140,20 @@ __global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_ker
             for (int k = 0; k < KL; ++k)
               if (4 * k < RL) u = __builtin_amdgcn_mfma_f64_16x16x4f64(hv[k], qa[tb][k], u, 0, 0, 0);
             const int t = tb * 16 + lane % 16;
+            // two modes per pass so that their loads issue together
             double ov[4] = {1.0, 1.0, 1.0, 1.0};
-            for (int m = 0; m < nm1; ++m) {
+            int m = 0;
+            for (; m + 2 <= nm1; m += 2) {
+              double f0[4], f1[4];
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                f0[v] = rT[rb_row(pk[v], m) * kVRT + t];
+                f1[v] = rT[rb_row(pk[v], m + 1) * kVRT + t];
+              }
+#pragma unroll
+              for (int v = 0; v < 4; ++v) ov[v] = (ov[v] * f0[v]) * f1[v];
+            }
+            if (m < nm1) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) ov[v] *= rT[rb_row(pk[v], m) * kVRT + t];
             }
@@ -1180,7 +1199,20 @@ __global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_ker
         double ov[KS];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) ov[ks] = 1.0;
-        for (int m = 0; m < nm1; ++m) {
+        int m = 0;
+        for (; m + 2 <= nm1; m += 2) {
+          const double* row0 = rT + rb_row(pk, m) * kVRT + lane / 16;
+          const double* row1 = rT + rb_row(pk, m + 1) * kVRT + lane / 16;
+          double f0[KS], f1[KS];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            f0[ks] = row0[4 * ks];
+            f1[ks] = row1[4 * ks];
+          }
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) ov[ks] = (ov[ks] * f0[ks]) * f1[ks];
+        }
+        if (m < nm1) {
           const double* row = rT + rb_row(pk, m) * kVRT + lane / 16;
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) ov[ks] *= row[4 * ks];
@@ -1194,8 +1226,7 @@ __global__ __launch_bounds__(kBlock, NOBW * NLB >= 8 ? 1 : 2) void resid_big_ker
         }
       }
     }
-    __syncthreads();
-    if (more) commit(ch + 1);
+    if (more) commit(ch + 1, buf ^ 1);  // the other buffer: last read two chunks ago
     __syncthreads();
   }
   // Z register v: o = ob 16 + lane / 16 + 4 v, l = lb 16 + lane % 16
@@ -1484,6 +1515,25 @@ void launch_resid_small(const Geom& g, const int32_t* idx, const double* Q64, co
                      done);
 }
 
+namespace {
+template <int W, int NL>
+void resid_big_launch(dim3 grid, size_t lds, hipStream_t st, const Geom& g, const double* rows64,
+                      const double* a, const double* b, const double* h, int64_t s, int64_t cpw,
+                      double* part, const int32_t* done) {
+  if (lds > 64 * 1024) {  // dynamic LDS above the default limit (gfx950: 160 KB per CU)
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&resid_big_kernel<W, NL>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      (void)hipGetLastError();
+      attr = true;
+    }
+  }
+  hipLaunchKernelGGL((resid_big_kernel<W, NL>), grid, dim3(kBlock), lds, st, g, rows64, a, b, h,
+                     s, cpw, part, done);
+}
+}  // namespace
+
 void launch_resid_big(const Geom& g, const double* rows64, const double* a, const double* b,
                       const double* h, int64_t s, double* part, double* out, const int32_t* done,
                       hipStream_t st) {
@@ -1492,12 +1542,11 @@ void launch_resid_big(const Geom& g, const double* rows64, const double* a, cons
   const int nob = static_cast<int>(cdiv(g.d / RL, 16));
   const int nobw = static_cast<int>(cdiv(nob, 4));
   const int nlb = static_cast<int>(cdiv(RL, 16));
-  const size_t lds = sizeof(double) * static_cast<size_t>(g.d + g.sum_r * kVRT);
+  const size_t lds = sizeof(double) * static_cast<size_t>(g.d + 2 * g.sum_r * kVRT);
   const dim3 grid(static_cast<unsigned>(bp.nwg));
-#define TK_RB_CASE(W, NL)                                                                      \
-  if (nobw <= W && nlb == NL) {                                                                \
-    hipLaunchKernelGGL((resid_big_kernel<W, NL>), grid, dim3(kBlock), lds, st, g, rows64, a, b, \
-                       h, s, bp.cpw, part, done);                                               \
+#define TK_RB_CASE(W, NL)                                                             \
+  if (nobw <= W && nlb == NL) {                                                       \
+    resid_big_launch<W, NL>(grid, lds, st, g, rows64, a, b, h, s, bp.cpw, part, done); \
   } else
   // (eight blocks of 16 outer indices per wave with R_L > 16 would exceed d = 4096)
   TK_RB_CASE(1, 1) TK_RB_CASE(2, 1) TK_RB_CASE(4, 1) TK_RB_CASE(8, 1)

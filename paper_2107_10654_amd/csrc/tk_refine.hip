@@ -195,31 +195,34 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
 
 // The check of one refinement step for larger d (up to kPcD), in one
 // workgroup: t = P h mode by mode, each output element from the previous
-// buffer into the other (two d-vectors in dynamic LDS), then
-// r = r + b - lambda t, relres = ||r|| / ||norm_ref||, done once relres <= tol
-// (else steps += 1 when count_step).  r holds the summed data term on entry and
-// the residual on exit.
+// buffer into the other (two d-vectors in dynamic LDS, and the P_n there too
+// when np_lds > 0), then r = r + b - lambda t, relres = ||r|| / ||norm_ref||,
+// done once relres <= tol (else steps += 1 when count_step).  r holds the
+// summed data term on entry and the residual on exit.
 constexpr int kPcD = 8192;
+constexpr size_t kPcMaxLds = 160 * 1024;
 
 __global__ __launch_bounds__(kRsThreads) void refine_check_p_kernel(
     Geom g, double* __restrict__ r, const double* __restrict__ h, const double* __restrict__ P,
     const double* __restrict__ b, double lambda, const double* __restrict__ norm_ref, double tol,
-    int32_t* done, int32_t* steps, double* relres, int count_step) {
+    int32_t* done, int32_t* steps, double* relres, int count_step, int np_lds) {
   if (*done) return;
-  extern __shared__ double tbuf[];  // 2 x d
+  extern __shared__ double tbuf[];  // 2 x d, then np_lds P entries
   __shared__ double red[64];
   const int tid = threadIdx.x;
   const int d = static_cast<int>(g.d);
   const int N = g.order;
   double* cur = tbuf;
   double* nxt = tbuf + d;
+  double* Ps = tbuf + 2 * d;
   for (int e = tid; e < d; e += kRsThreads) cur[e] = h[e];
+  for (int e = tid; e < np_lds; e += kRsThreads) Ps[e] = P[e];
   __syncthreads();
   for (int n = 0; n < N; ++n) {
     const int R = g.ranks[n];
     int stride = 1;
     for (int m = n + 1; m < N; ++m) stride *= g.ranks[m];
-    const double* Pn = P + g.roff[n];
+    const double* Pn = (np_lds > 0 ? Ps : P) + g.roff[n];
     for (int e = tid; e < d; e += kRsThreads) {
       const int j = (e / stride) % R;
       const int base = e - j * stride;
@@ -269,17 +272,26 @@ void launch_refine_check_p(const Geom& g, double* r, const double* h, const doub
                            const double* b, double lambda, const double* norm_ref, double tol,
                            int32_t* done, int32_t* steps, double* relres, int count_step,
                            hipStream_t st) {
-  const size_t lds = 2 * sizeof(double) * static_cast<size_t>(g.d);
+  // the P_n (sum_n R_n^2 entries, mode n at roff[n]) join the two vectors in
+  // LDS when all fit
+  int64_t np = 0;
+  for (int n = 0; n < g.order; ++n) np += static_cast<int64_t>(g.ranks[n]) * g.ranks[n];
+  size_t lds = 2 * sizeof(double) * static_cast<size_t>(g.d);
+  int np_lds = 0;
+  if (lds + sizeof(double) * static_cast<size_t>(np) + 64 * sizeof(double) <= kPcMaxLds) {
+    np_lds = static_cast<int>(np);
+    lds += sizeof(double) * static_cast<size_t>(np);
+  }
   static bool attr = false;  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_check_p_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(2 * sizeof(double) * kPcD));
+                              static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
     (void)hipGetLastError();
     attr = true;
   }
   hipLaunchKernelGGL(refine_check_p_kernel, dim3(1), dim3(kRsThreads), lds, st, g, r, h, P, b,
-                     lambda, norm_ref, tol, done, steps, relres, count_step);
+                     lambda, norm_ref, tol, done, steps, relres, count_step, np_lds);
 }
 
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
