@@ -28,7 +28,12 @@
 namespace tk {
 namespace {
 
-constexpr int kSkRT = kRowChunk + 4;  // padded LDS row: conflict-free 16-byte reads
+// Padded LDS rows of the staged factor entries.  One-row items read 16 bytes
+// from consecutive rows: a stride of 36 floats spreads 16 lanes over all 64
+// banks.  Four-row items read 128 contiguous bytes from each of two rows 4
+// apart per 16 lanes: a stride of 40 floats puts them half a bank sweep apart.
+constexpr int kSkRT = kRowChunk + 4;
+constexpr int kSkRT4 = kRowChunk + 8;
 constexpr size_t kSkMaxLds = 160 * 1024;  // LDS per CU on gfx950
 
 // Tile edge T: 64 and 128 use 2 x 2 waves (32 x 32 or 64 x 64 each, up to 4
@@ -54,7 +59,7 @@ struct SkLayout {
   static constexpr size_t offs_bytes = 2 * NO * kMaxOrder;
   static constexpr size_t fixed = NBUF * 2 * y_bytes + offs_bytes;
   __host__ __device__ static size_t rows_elems(int sum_r) {
-    return static_cast<size_t>(sum_r + 1) * kSkRT;
+    return static_cast<size_t>(sum_r + 1) * kSkRT4;  // room for either stride
   }
   __host__ __device__ static size_t bytes(int sum_r) {
     return fixed + NBUF * sizeof(typename V::Src) * rows_elems(sum_r);
@@ -224,6 +229,11 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
       ob[side] = base / RL;
       no[side] = static_cast<int>(last / RL - ob[side] + 1);
     }
+    // the formation this tile takes (four-row items, below) fixes the stride
+    // of the staged rows
+    bool use4 = false;
+    if constexpr (V::EPL == 8 && T == 256) use4 = RL % 4 == 0 && N <= 4 && !diag;
+    const int rt = use4 ? kSkRT4 : kSkRT;
     auto fetch = [&](int64_t c) __attribute__((always_inline)) {
       const f32x4* src = reinterpret_cast<const f32x4*>(rows + c * BK * SR);
 #pragma unroll
@@ -238,14 +248,14 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
         const int e = tid + k * kSkThreads;
         if (e < nval4) {
           const int f = 4 * e;  // element index j * 32 + t
-          *reinterpret_cast<f32x4*>(&rs[(f >> 5) * RT + (f & 31)]) = pf[k];
+          *reinterpret_cast<f32x4*>(&rs[(f >> 5) * rt + (f & 31)]) = pf[k];
         }
       }
     };
     __syncthreads();  // the previous segment's LDS use is complete
-    for (int e = tid; e < RT; e += kSkThreads) {  // zero rows
-      rT[SR * RT + e] = Src(0);
-      if (DB) rT2[SR * RT + e] = Src(0);
+    for (int e = tid; e < rt; e += kSkThreads) {  // zero rows
+      rT[SR * rt + e] = Src(0);
+      if (DB) rT2[SR * rt + e] = Src(0);
     }
 #pragma unroll 1
     for (int e = tid; e < 2 * NO; e += kSkThreads) {
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
     // precision
     bool formed = false;
     if constexpr (V::EPL == 8 && T == 256) {
-      if (RL % 4 == 0 && N <= 4 && !diag) {
+      if (use4) {
         // BF16 operands, 256 tiles, R_L a multiple of 4, off-diagonal: an
         // item is 4 rows x 4 samples, the 4 rows sharing their outer index
         // (d and the tile origins are multiples of 4, so a row quad is
@@ -353,8 +363,8 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
           const bool in = r < d;
           const int64_t rr = in ? r : d - 1;
           const int oi = static_cast<int>(rr / RL - ob[side]);
-          qo[k] = (in ? sl + static_cast<int>(rr % RL) : SR) * RT + 4 * sg;
-          qs[k] = in ? RT : 0;  // past d: the zero row four times
+          qo[k] = (in ? sl + static_cast<int>(rr % RL) : SR) * kSkRT4 + 4 * sg;
+          qs[k] = in ? kSkRT4 : 0;  // past d: the zero row four times
           yo[k] = 4 * rb * LDK + 4 * sg;
           pk[k] = *reinterpret_cast<const uint64_t*>(offs + (side * NO + oi) * kMaxOrder);
         }
@@ -369,7 +379,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
 #pragma unroll
             for (int m = 0; m < NM1; ++m)
               o *= *reinterpret_cast<const f32x4*>(
-                  rs + static_cast<int>((pk[k] >> (8 * m)) & 0xff) * RT + t4);
+                  rs + static_cast<int>((pk[k] >> (8 * m)) & 0xff) * kSkRT4 + t4);
             Op* y = (side == 0 ? ya : yb) + yo[k];
             const Src* qp = rs + qo[k];
             f32x4 q[4];
