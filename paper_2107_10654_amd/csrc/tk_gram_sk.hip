@@ -506,6 +506,7 @@ __global__ __launch_bounds__(SkTile<T>::THREADS, SkTile<T>::WG_PER_CU) void gram
 // slots is summed by walking the ranges per element instead.
 constexpr int kAsmMaxSlots = 16;
 constexpr int kAsmRows = 16;  // rows per workgroup (all in one tile row: kAsmRows divides T)
+constexpr int kAsmMaxP = 2048;  // P_n entries staged in LDS (sum_n R_n^2)
 
 template <int T>
 __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
@@ -516,6 +517,7 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
   constexpr int TPB = kBlock >= T ? kBlock / T : 1;  // tiles per workgroup row
   __shared__ int64_t slot_of[TPB][kAsmMaxSlots];
   __shared__ int nslot[TPB];
+  __shared__ double Ps[kAsmMaxP];  // the P_n (mode n at roff[n]) when they fit
   const int64_t d = g.d;
   const int64_t jb = static_cast<int64_t>(blockIdx.x) * kBlock;
   const int64_t j = jb + threadIdx.x;
@@ -542,7 +544,13 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
     }
     nslot[threadIdx.x] = n <= kAsmMaxSlots ? n : -1;
   }
+  int np = 0;
+  for (int n = 0; n < g.order; ++n) np += g.ranks[n] * g.ranks[n];
+  const bool pl = np <= kAsmMaxP;
+  if (pl)
+    for (int e = threadIdx.x; e < np; e += kBlock) Ps[e] = P[e];
   __syncthreads();
+  const double* Pb = pl ? Ps : P;
   const int64_t tj = j / T;
   const int tl = static_cast<int>(tj - jb / T);
   const int ns = nslot[tl];
@@ -557,38 +565,63 @@ __global__ __launch_bounds__(kBlock) void assemble_sk_kernel(
       b /= R;
     }
   }
-  for (int64_t i = ib; i <= ilast; ++i) {
-    if (j > i) continue;
-    const int64_t off = (i - ti * T) * T + (j - tj * T);
-    double v = 0.0;
-    if (ns >= 0) {
-      for (int k = 0; k < ns; ++k)
-        v += static_cast<double>(slots[slot_of[tl][k] * static_cast<int64_t>(T * T) + off]);
-    } else {
-      const int64_t tau = ti * (ti + 1) / 2 + tj;
-      const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;
-      int64_t w = (ua * grid) / units;
-      while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
-      while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
-      for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
-        const int64_t first = index[grid + w];
-        if (first < 0) continue;
-        const int64_t slot = index[w] + (tile0 + tau - first);
-        v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
-      }
-    }
-    // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
+  // lambda prod_n P_n[i_n][j_n] (32-bit digit arithmetic: d < 2^31)
+  auto lam_p = [&](int64_t i) __attribute__((always_inline)) {
     double p = 1.0;
     uint32_t a = static_cast<uint32_t>(i);
 #pragma unroll
     for (int n = kMaxOrder - 1; n >= 0; --n) {
       if (n < g.order) {
         const uint32_t R = static_cast<uint32_t>(g.ranks[n]);
-        p *= P[g.roff[n] + (a % R) * R + jd[n]];
+        p *= Pb[g.roff[n] + (a % R) * R + jd[n]];
         a /= R;
       }
     }
-    M[i * d + j] = fma(lambda, p, v);
+    return p;
+  };
+  if (ns >= 0) {
+    // rows in groups of four (all in one tile row): a slot's four entries
+    // are loaded together, and each row's sum keeps the slot order
+    static_assert(kAsmRows % 4 == 0, "row groups");
+    for (int64_t i0 = ib; i0 <= ilast; i0 += 4) {
+      if (j > i0 + 3) continue;  // the group is above the diagonal in column j
+      const int64_t off0 = (i0 - ti * T) * T + (j - tj * T);
+      double v4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < ns; ++k) {
+        const float* sp = slots + slot_of[tl][k] * static_cast<int64_t>(T * T) + off0;
+        // rows i0 .. i0 + 3 lie in the slot's T x T tile even past d (i0 % 4
+        // == 0 and 4 divides T), so the four loads need no guard
+        float x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = sp[r * T];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v4[r] += static_cast<double>(x[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + r;
+        if (i <= ilast && j <= i) M[i * d + j] = fma(lambda, lam_p(i), v4[r]);
+      }
+    }
+    return;
+  }
+  // a tile with more slots than the list holds: its ranges are walked per entry
+  for (int64_t i = ib; i <= ilast; ++i) {
+    if (j > i) continue;
+    const int64_t off = (i - ti * T) * T + (j - tj * T);
+    const int64_t tau = ti * (ti + 1) / 2 + tj;
+    const int64_t ua = unit0 + tau * nchunks, ub = ua + nchunks;
+    int64_t w = (ua * grid) / units;
+    while (w > 0 && sk_unit_start(w, units, grid) > ua) --w;
+    while (sk_unit_start(w + 1, units, grid) <= ua) ++w;
+    double v = 0.0;
+    for (; w < grid && sk_unit_start(w, units, grid) < ub; ++w) {
+      const int64_t first = index[grid + w];
+      if (first < 0) continue;
+      const int64_t slot = index[w] + (tile0 + tau - first);
+      v += static_cast<double>(slots[slot * static_cast<int64_t>(T * T) + off]);
+    }
+    M[i * d + j] = fma(lambda, lam_p(i), v);
   }
 }
 
