@@ -673,20 +673,22 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
       launch_residual_coef(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.coef, w.done, st);
       launch_rows_t_vec(g, w.rows64, w.coef, R.s, w.vpart, w.r, w.done, st);
     }
+    // the check also prepares the correction solve that follows it
+    const bool prep = refine_check_p_ok(g) && k < iters;
     if (refine_check_p_ok(g)) {
       launch_refine_check_p(g, w.r, h, w.lev.P, b, lambda, norm_ref,
                             refine ? R.o->refine_tol : -1.0, w.done, w.steps, w.relres,
-                            k < iters ? 1 : 0, st);
+                            k < iters ? 1 : 0, st, prep ? w.flags : nullptr,
+                            prep ? w.ytmp : nullptr);
     } else {
       launch_copy_f64(g.d, h, w.ph_a, st);
       const double* ph = core_chain(g, w.ph_a, w.ph_b, w.lev.P, false, w.ttm_scratch, st, w.done);
       launch_refine_check(g.d, w.r, ph, b, lambda, norm_ref, refine ? R.o->refine_tol : -1.0,
                           w.done, w.steps, w.relres, k < iters ? 1 : 0, st);
     }
-    if (k < iters) {
-      launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, R.status, st);
-      launch_axpy(g.d, 1.0, w.r, h, w.done, st);
-    }
+    if (k < iters)  // h += (L L^T)^{-1} r, added as the solve publishes it
+      launch_chol_solve(w.M, w.Linv_diag, g.d, w.r, w.ytmp, w.flags, w.done, R.status, st, h,
+                        prep);
   }
   if (refine) launch_finish_refine(w.done, 1, R.status, st);
   R.stage(8);

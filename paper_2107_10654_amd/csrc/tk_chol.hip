@@ -654,7 +654,7 @@ __global__ void chol_flags_kernel(int32_t* f, int64_t n) {
 // Waits are bounded: after kSpinLimit polls a block reports TK_E_HIP and
 // uses 0, so every workgroup still finishes and publishes.
 constexpr long kSpinLimit = 1L << 22;
-constexpr unsigned long long kPending = 0x7FF4DEADBEEF0001ull;  // a signalling NaN
+constexpr unsigned long long kPending = kSolvePending;
 
 // v[c] = p[c] for c < n (0 beyond), waiting until all n are published
 __device__ inline bool load_published(const double* p, int n, double* v) {
@@ -834,7 +834,8 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
                                                             int64_t d, int64_t nblk,
                                                             const double* __restrict__ y,
                                                             double* x, int32_t* flags,
-                                                            const int32_t* done, int32_t* status) {
+                                                            const int32_t* done, int32_t* status,
+                                                            double* accum) {
   if (done && *done) return;
   __shared__ int64_t row_blk;
   __shared__ double Li[NB * LDA];
@@ -920,8 +921,11 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   }
   chain[q][r] = v;
   __syncthreads();
-  if (q == 0 && r < rows)
-    publish(x + i0 + r, u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r])));
+  if (q == 0 && r < rows) {
+    const double xv = u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r]));
+    publish(x + i0 + r, xv);
+    if (accum) accum[i0 + r] += xv;
+  }
   if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
@@ -951,14 +955,16 @@ void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot,
 
 void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,
                        double* y_tmp, int32_t* flags, const int32_t* done, int32_t* status,
-                       hipStream_t st) {
+                       hipStream_t st, double* accum, bool prepared) {
   const int64_t nblk = cdiv(d, NB);
-  hipLaunchKernelGGL(solve_init_kernel, dim3(static_cast<unsigned>(cdiv(d, kBlock))), dim3(kBlock),
-                     0, st, flags, y_tmp, d, done);
+  if (!prepared)
+    hipLaunchKernelGGL(solve_init_kernel, dim3(static_cast<unsigned>(cdiv(d, kBlock))),
+                       dim3(kBlock), 0, st, flags, y_tmp, d, done);
   hipLaunchKernelGGL(trsv_lower_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
                      Linv_diag, d, nblk, x, y_tmp, flags, done, status);
   hipLaunchKernelGGL(trsv_upper_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st, L,
-                     Linv_diag, d, nblk, static_cast<const double*>(y_tmp), x, flags, done, status);
+                     Linv_diag, d, nblk, static_cast<const double*>(y_tmp), x, flags, done, status,
+                     accum);
 }
 
 }  // namespace tk

@@ -185,10 +185,13 @@ bool refine_small_ok(const Geom& g);
 // For d <= 8192: P h applied in one workgroup, then r = r + b - lambda P h and the
 // same test (done / steps / relres) as launch_refine_check.
 bool refine_check_p_ok(const Geom& g);
+// solve_flags / solve_y (nullable): also prepare the next launch_chol_solve
+// (prepared = true) with this scratch.
 void launch_refine_check_p(const Geom& g, double* r, const double* h, const double* P,
                            const double* b, double lambda, const double* norm_ref, double tol,
                            int32_t* done, int32_t* steps, double* relres, int count_step,
-                           hipStream_t st);
+                           hipStream_t st, int32_t* solve_flags = nullptr,
+                           double* solve_y = nullptr);
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
                               const double* b, double lambda, const double* norm_ref, double tol,
                               const double* L, const double* Linv_diag, double* h, int32_t* done,
@@ -214,10 +217,16 @@ inline int64_t chol_flag_words(int64_t d) {
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
                      int32_t* flags, hipStream_t st);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
-// scratch of 2 * ceil(d/nb) + 2 words.
+// scratch of 2 * ceil(d/nb) + 2 words.  accum (nullable): accum += x, entry by
+// entry as x is published.  prepared: y_tmp already holds kSolvePending and
+// flags[0], flags[1] are zero (the refinement check can leave them so), and
+// the initialising launch is skipped.
 void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,
                        double* y_tmp, int32_t* flags, const int32_t* done, int32_t* status,
-                       hipStream_t st);
+                       hipStream_t st, double* accum = nullptr, bool prepared = false);
+// The triangular solves' "not yet published" word (a signalling-NaN pattern no
+// arithmetic result takes).
+constexpr unsigned long long kSolvePending = 0x7FF4DEADBEEF0001ull;
 
 // Small FP64 helpers (tk_small.hip).
 // T' = T x_mode M  for row-major T of shape dims (order n), M: J x dims[mode]

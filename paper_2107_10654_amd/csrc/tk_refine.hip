@@ -205,7 +205,8 @@ constexpr size_t kPcMaxLds = 160 * 1024;
 __global__ __launch_bounds__(kRsThreads) void refine_check_p_kernel(
     Geom g, double* __restrict__ r, const double* __restrict__ h, const double* __restrict__ P,
     const double* __restrict__ b, double lambda, const double* __restrict__ norm_ref, double tol,
-    int32_t* done, int32_t* steps, double* relres, int count_step, int np_lds) {
+    int32_t* done, int32_t* steps, double* relres, int count_step, int np_lds,
+    int32_t* solve_flags, double* solve_y) {
   if (*done) return;
   extern __shared__ double tbuf[];  // 2 x d, then np_lds P entries
   __shared__ double red[64];
@@ -250,6 +251,11 @@ __global__ __launch_bounds__(kRsThreads) void refine_check_p_kernel(
     a2 = fma(v, v, a2);
     n2 = fma(norm_ref[e], norm_ref[e], n2);
   }
+  // the next correction solve's sentinels and tickets (unused once done)
+  if (solve_y)
+    for (int e = tid; e < d; e += kRsThreads)
+      solve_y[e] = __longlong_as_double(static_cast<long long>(kSolvePending));
+  if (solve_flags && tid < 2) solve_flags[tid] = 0;
   const double sa = block_sum(a2, red);
   const double sn = block_sum(n2, red + 32);
   if (tid == 0) {
@@ -271,7 +277,7 @@ bool refine_check_p_ok(const Geom& g) { return g.d <= kPcD; }
 void launch_refine_check_p(const Geom& g, double* r, const double* h, const double* P,
                            const double* b, double lambda, const double* norm_ref, double tol,
                            int32_t* done, int32_t* steps, double* relres, int count_step,
-                           hipStream_t st) {
+                           hipStream_t st, int32_t* solve_flags, double* solve_y) {
   // the P_n (sum_n R_n^2 entries, mode n at roff[n]) join the two vectors in
   // LDS when all fit
   int64_t np = 0;
@@ -291,7 +297,8 @@ void launch_refine_check_p(const Geom& g, double* r, const double* h, const doub
     attr = true;
   }
   hipLaunchKernelGGL(refine_check_p_kernel, dim3(1), dim3(kRsThreads), lds, st, g, r, h, P, b,
-                     lambda, norm_ref, tol, done, steps, relres, count_step, np_lds);
+                     lambda, norm_ref, tol, done, steps, relres, count_step, np_lds, solve_flags,
+                     solve_y);
 }
 
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
