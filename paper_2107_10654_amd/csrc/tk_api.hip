@@ -802,9 +802,13 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
   const Geom& g = R.g;
   SketchWS& w = R.w;
-  launch_copy_f64(g.d, w.h, w.ph_a, R.st);
-  const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, R.st);
-  launch_cast_out(g.d, gres, core_out, p->dtype, R.st);
+  if (core_chain_small_ok(g)) {
+    launch_core_chain_small(g, w.h, w.lev.Linv, true, core_out, p->dtype, R.st);
+  } else {
+    launch_copy_f64(g.d, w.h, w.ph_a, R.st);
+    const double* gres = core_chain(g, w.ph_a, w.ph_b, w.lev.Linv, true, w.ttm_scratch, R.st);
+    launch_cast_out(g.d, gres, core_out, p->dtype, R.st);
+  }
   if (dev_info) launch_info(dev_info, R.s, w.missing, w.steps, w.relres, w.min_pivot, R.st);
   R.stage(9);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
@@ -946,10 +950,14 @@ tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_
     launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, p->lambda, R.w.M, st);
     sketch_factor(R);
     refined_solve(R, p->lambda, nullptr, R.w.xw, R.w.rhs, R.w.h);
-    launch_copy_f64(R.g.d, R.w.h, R.w.ph_a, st);
-    const double* gres =
-        core_chain(R.g, R.w.ph_a, R.w.ph_b, R.w.lev.Linv, true, R.w.ttm_scratch, st);
-    launch_cast_out(R.g.d, gres, core_out[k], p->dtype, st);
+    if (core_chain_small_ok(R.g)) {
+      launch_core_chain_small(R.g, R.w.h, R.w.lev.Linv, true, core_out[k], p->dtype, st);
+    } else {
+      launch_copy_f64(R.g.d, R.w.h, R.w.ph_a, st);
+      const double* gres =
+          core_chain(R.g, R.w.ph_a, R.w.ph_b, R.w.lev.Linv, true, R.w.ttm_scratch, st);
+      launch_cast_out(R.g.d, gres, core_out[k], p->dtype, st);
+    }
     if (dev_info)
       launch_info(dev_info + static_cast<int64_t>(k) * TK_INFO_LEN, R.s, R.w.missing, R.w.steps,
                   R.w.relres, R.w.min_pivot, st);

@@ -185,6 +185,11 @@ bool refine_small_ok(const Geom& g);
 // For d <= 8192: P h applied in one workgroup, then r = r + b - lambda P h and the
 // same test (done / steps / relres) as launch_refine_check.
 bool refine_check_p_ok(const Geom& g);
+// out = ((x)_n M_n^T) t (trans) or ((x)_n M_n) t, M_n at roff[n], in one
+// workgroup for d <= 8192 (core_chain_small_ok), written in dtype dt.
+bool core_chain_small_ok(const Geom& g);
+void launch_core_chain_small(const Geom& g, const double* t, const double* mats, bool trans,
+                             void* out, tk_dtype dt, hipStream_t st);
 // solve_flags / solve_y (nullable): also prepare the next launch_chol_solve
 // (prepared = true) with this scratch.
 void launch_refine_check_p(const Geom& g, double* r, const double* h, const double* P,

@@ -268,7 +268,84 @@ __global__ __launch_bounds__(kRsThreads) void refine_check_p_kernel(
   }
 }
 
+// out = ((x)_n M_n^T) t (trans) or ((x)_n M_n) t for d <= kPcD in one
+// workgroup: t and, when they fit, the M_n (mode n at roff[n]) in LDS, one
+// mode after the other between two LDS vectors, the result written in the
+// output precision.
+__global__ __launch_bounds__(kRsThreads) void core_chain_small_kernel(Geom g,
+                                                                      const double* __restrict__ t,
+                                                                      const double* __restrict__ mats,
+                                                                      int trans, int np_lds,
+                                                                      void* out, int out_f64) {
+  extern __shared__ double tbuf[];  // 2 x d, then np_lds matrix entries
+  const int tid = threadIdx.x;
+  const int d = static_cast<int>(g.d);
+  const int N = g.order;
+  double* cur = tbuf;
+  double* nxt = tbuf + d;
+  double* Ms = tbuf + 2 * d;
+  for (int e = tid; e < d; e += kRsThreads) cur[e] = t[e];
+  for (int e = tid; e < np_lds; e += kRsThreads) Ms[e] = mats[e];
+  __syncthreads();
+  for (int n = 0; n < N; ++n) {
+    const int R = g.ranks[n];
+    int stride = 1;
+    for (int m = n + 1; m < N; ++m) stride *= g.ranks[m];
+    const double* Mn = (np_lds > 0 ? Ms : mats) + g.roff[n];
+    // entry (j, i) of the applied matrix: M_n[j][i], or M_n[i][j] when trans
+    const int sj = trans ? 1 : R, si = trans ? R : 1;
+    for (int e = tid; e < d; e += kRsThreads) {
+      const int j = (e / stride) % R;
+      const int base = e - j * stride;
+      double v0 = 0.0, v1 = 0.0;
+      int i = 0;
+      for (; i + 2 <= R; i += 2) {
+        v0 = fma(Mn[j * sj + i * si], cur[base + i * stride], v0);
+        v1 = fma(Mn[j * sj + (i + 1) * si], cur[base + (i + 1) * stride], v1);
+      }
+      if (i < R) v0 = fma(Mn[j * sj + i * si], cur[base + i * stride], v0);
+      nxt[e] = v0 + v1;
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  for (int e = tid; e < d; e += kRsThreads) {
+    if (out_f64)
+      static_cast<double*>(out)[e] = cur[e];
+    else
+      static_cast<float*>(out)[e] = static_cast<float>(cur[e]);
+  }
+}
+
 }  // namespace
+
+// two d-vectors of kPcD doubles (128 KB) always fit; the M_n join them when
+// there is room
+bool core_chain_small_ok(const Geom& g) { return g.d <= kPcD; }
+
+void launch_core_chain_small(const Geom& g, const double* t, const double* mats, bool trans,
+                             void* out, tk_dtype dt, hipStream_t st) {
+  int64_t np = 0;
+  for (int n = 0; n < g.order; ++n) np += static_cast<int64_t>(g.ranks[n]) * g.ranks[n];
+  size_t lds = 2 * sizeof(double) * static_cast<size_t>(g.d);
+  int np_lds = 0;
+  if (lds + sizeof(double) * static_cast<size_t>(np) + 64 * sizeof(double) <= kPcMaxLds) {
+    np_lds = static_cast<int>(np);
+    lds += sizeof(double) * static_cast<size_t>(np);
+  }
+  static bool attr = false;  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&core_chain_small_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL(core_chain_small_kernel, dim3(1), dim3(kRsThreads), lds, st, g, t, mats,
+                     trans ? 1 : 0, np_lds, out, dt == TK_F64 ? 1 : 0);
+}
 
 bool refine_small_ok(const Geom& g) { return g.d <= kRsD; }
 
