@@ -1395,6 +1395,35 @@ int64_t reg_grid(int64_t s) {
 
 }  // namespace
 
+int resident_grid(const void* kernel, int threads, size_t dyn_lds) {
+  static const void* keys[64];
+  static size_t ldss[64];
+  static int vals[64];
+  static int n = 0;
+  for (int k = 0; k < n; ++k)
+    if (keys[k] == kernel && ldss[k] == dyn_lds) return vals[k];
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  (void)hipGetLastError();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  (void)hipGetLastError();
+  const int v = per_cu * cus;
+  if (n < 64) {
+    keys[n] = kernel;
+    ldss[n] = dyn_lds;
+    vals[n] = v;
+    ++n;
+  }
+  return v;
+}
+
 bool resid_small_ok(const Geom& g) { return g.d <= kSmD && g.sum_r <= kSmSumR; }
 
 bool resid_big_ok(const Geom& g) {
@@ -1430,21 +1459,29 @@ int64_t vec_part_doubles(const Geom& g, int64_t s) {
   return n;
 }
 
+// Returns the grid used (one partial vector per workgroup): at most `grid`,
+// and no more workgroups than are resident at once.
 template <int N, int RM>
-void launch_reg(dim3 grid, hipStream_t st, const Geom& g, const int32_t* idx, const double* Q64,
-                const double* a, const double* b, const double* h, int64_t s, double* part,
-                const int32_t* done) {
+int64_t launch_reg(int64_t grid, hipStream_t st, const Geom& g, const int32_t* idx,
+                   const double* Q64, const double* a, const double* b, const double* h,
+                   int64_t s, double* part, const int32_t* done) {
   // exact ranks: every mode RM wide and every mode's rows 16-byte aligned
   bool exact = true;
   for (int n = 0; n < N; ++n)
     exact = exact && g.ranks[n] == RM && (RM < 2 || (g.qoff[n] % 2) == 0);
   exact = exact && (reinterpret_cast<uintptr_t>(Q64) % 16) == 0;
+  const void* k = exact ? reinterpret_cast<const void*>(&resid_reg_kernel<N, RM, true>)
+                        : reinterpret_cast<const void*>(&resid_reg_kernel<N, RM, false>);
+  const int64_t res = resident_grid(k, kRegThreads, 0);
+  if (grid > res) grid = res;
+  const dim3 gd(static_cast<unsigned>(grid));
   if (exact)
-    hipLaunchKernelGGL((resid_reg_kernel<N, RM, true>), grid, dim3(kRegThreads), 0, st, g, idx, Q64,
+    hipLaunchKernelGGL((resid_reg_kernel<N, RM, true>), gd, dim3(kRegThreads), 0, st, g, idx, Q64,
                        a, b, h, s, part, done);
   else
-    hipLaunchKernelGGL((resid_reg_kernel<N, RM, false>), grid, dim3(kRegThreads), 0, st, g, idx,
+    hipLaunchKernelGGL((resid_reg_kernel<N, RM, false>), gd, dim3(kRegThreads), 0, st, g, idx,
                        Q64, a, b, h, s, part, done);
+  return grid;
 }
 
 bool try_resid_reg(const Geom& g, const int32_t* idx, const double* Q64, const double* a,
@@ -1452,27 +1489,27 @@ bool try_resid_reg(const Geom& g, const int32_t* idx, const double* Q64, const d
                    hipStream_t st, int64_t* nparts) {
   const int rm = reg_rm(g);
   if (rm == 0) return false;
-  const int64_t grid = reg_grid(s);
-  const dim3 gd(static_cast<unsigned>(grid));
+  const int64_t gd = reg_grid(s);
+  int64_t grid = 0;
   const int key = g.order * 16 + rm;
   switch (key) {
-    case 1 * 16 + 1: launch_reg<1, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 1 * 16 + 2: launch_reg<1, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 1 * 16 + 4: launch_reg<1, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 1 * 16 + 8: launch_reg<1, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 2 * 16 + 1: launch_reg<2, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 2 * 16 + 2: launch_reg<2, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 2 * 16 + 4: launch_reg<2, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 2 * 16 + 8: launch_reg<2, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 3 * 16 + 1: launch_reg<3, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 3 * 16 + 2: launch_reg<3, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 3 * 16 + 4: launch_reg<3, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 4 * 16 + 1: launch_reg<4, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 4 * 16 + 2: launch_reg<4, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 5 * 16 + 1: launch_reg<5, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 5 * 16 + 2: launch_reg<5, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 6 * 16 + 1: launch_reg<6, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
-    case 6 * 16 + 2: launch_reg<6, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 1: grid = launch_reg<1, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 2: grid = launch_reg<1, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 4: grid = launch_reg<1, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 1 * 16 + 8: grid = launch_reg<1, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 1: grid = launch_reg<2, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 2: grid = launch_reg<2, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 4: grid = launch_reg<2, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 2 * 16 + 8: grid = launch_reg<2, 8>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 1: grid = launch_reg<3, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 2: grid = launch_reg<3, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 3 * 16 + 4: grid = launch_reg<3, 4>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 4 * 16 + 1: grid = launch_reg<4, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 4 * 16 + 2: grid = launch_reg<4, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 5 * 16 + 1: grid = launch_reg<5, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 5 * 16 + 2: grid = launch_reg<5, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 6 * 16 + 1: grid = launch_reg<6, 1>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
+    case 6 * 16 + 2: grid = launch_reg<6, 2>(gd, st, g, idx, Q64, a, b, h, s, part, done); break;
     default: return false;
   }
   *nparts = grid;

@@ -152,6 +152,11 @@ void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const 
 void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, const double* P,
                      double lambda, double* M, hipStream_t st);
 
+// Workgroups of `kernel` (with `threads` threads and dyn_lds bytes of dynamic
+// LDS) resident on the whole device at once, cached: a grid-stride pass with
+// equal shares per workgroup runs in one wave only if its grid is no larger.
+int resident_grid(const void* kernel, int threads, size_t dyn_lds);
+
 // out[r] = sum_t c_t q_t[r] (q_t the whitened Kronecker row), FP64, deterministic.
 // part: vec_part_doubles(g, s) scratch.
 int64_t vec_part_doubles(const Geom& g, int64_t s);

@@ -106,11 +106,14 @@ void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st) {
   if (s <= 0) return;
   if (g.total_rows <= kSampleLdsRows) {
+    // as many workgroups as are resident at once (each stages the tables)
+    const size_t lds = sizeof(uint64_t) * g.total_rows;
     const int64_t want = cdiv(s, kBlock);
-    const unsigned grid = static_cast<unsigned>(want < 1024 ? want : 1024);
-    hipLaunchKernelGGL(sample_kernel<true>, dim3(grid), dim3(kBlock),
-                       sizeof(uint64_t) * g.total_rows, st, g, cdf, s, seed, counter, problem, idx,
-                       weight);
+    const int64_t res =
+        resident_grid(reinterpret_cast<const void*>(&sample_kernel<true>), kBlock, lds);
+    const unsigned grid = static_cast<unsigned>(want < res ? want : res);
+    hipLaunchKernelGGL(sample_kernel<true>, dim3(grid), dim3(kBlock), lds, st, g, cdf, s, seed,
+                       counter, problem, idx, weight);
   } else {
     hipLaunchKernelGGL(sample_kernel<false>, dim3(static_cast<unsigned>(cdiv(s, kBlock))),
                        dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, idx, weight);
