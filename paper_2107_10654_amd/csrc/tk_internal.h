@@ -251,8 +251,6 @@ void launch_ttm(const double* T, const int64_t* dims, int order, int mode, const
 void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, int mode,
                     const double* M, int64_t J, bool transpose_M, double* out, double* scratch,
                     hipStream_t st);
-void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
-                 hipStream_t st);
 void launch_copy_f64(int64_t n, const double* x, double* y, hipStream_t st);
 void launch_cast_out(int64_t n, const double* x, void* y, tk_dtype dt, hipStream_t st);
 void launch_cast_in(int64_t n, const void* x, tk_dtype dt, double* y, hipStream_t st);

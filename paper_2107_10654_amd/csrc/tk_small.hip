@@ -615,13 +615,6 @@ void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const d
                        out, done);
 }
 
-__global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x,
-                            double* __restrict__ y, const int32_t* done) {
-  if (done && *done) return;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) y[i] = fma(a, x[i], y[i]);
-}
-
 template <class To, class From>
 __global__ void cast_kernel(int64_t n, const From* __restrict__ x, To* __restrict__ y) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -708,13 +701,6 @@ void launch_ttm_any(const void* T, tk_dtype dt, const int64_t* dims, int order, 
   else
     ttm_dispatch<float>(static_cast<const float*>(T), dims, order, mode, M, J, transpose_M, out,
                         scratch, st, nullptr);
-}
-
-void launch_axpy(int64_t n, double a, const double* x, double* y, const int32_t* done,
-                 hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(axpy_kernel, dim3(static_cast<unsigned>(cdiv(n, kBlock))), dim3(kBlock), 0, st,
-                     n, a, x, y, done);
 }
 
 void launch_copy_f64(int64_t n, const double* x, double* y, hipStream_t st) {
