@@ -644,15 +644,15 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   const Geom& g = R.g;
   SketchWS& w = R.w;
   hipStream_t st = R.st;
-  launch_fill_i32(1, 0, w.done, st);
-  launch_copy_f64(g.d, b ? b : w.rhs, h, st);
-  launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, nullptr, R.status, st);
-  R.stage(7);
   const bool refine = R.o->gram_precision != TK_F64;
   const int iters = refine ? R.o->refine_max : 0;
   if (resid_small_ok(g) && refine_small_ok(g)) {
-    // small d: the residual's partials, then one fused step (sum, P h, test,
-    // block solve, update) per iteration
+    // small d: the first solve in the one-workgroup step kernel (which also
+    // clears done), then the residual's partials and one fused step (sum,
+    // P h, test, block solve, update) per iteration
+    launch_refine_step_small(g, nullptr, 0, w.lev.P, b ? b : w.rhs, lambda, norm_ref, -1.0, w.M,
+                             w.Linv_diag, h, w.done, w.steps, w.relres, 1, st, 1);
+    R.stage(7);
     for (int k = 0; k <= iters; ++k) {
       const int64_t np =
           launch_resid_small_parts(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.done, st);
@@ -664,6 +664,10 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
     R.stage(8);
     return;
   }
+  launch_fill_i32(1, 0, w.done, st);
+  launch_copy_f64(g.d, b ? b : w.rhs, h, st);
+  launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, nullptr, R.status, st);
+  R.stage(7);
   for (int k = 0; k <= iters; ++k) {
     if (resid_small_ok(g)) {
       launch_resid_small(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);

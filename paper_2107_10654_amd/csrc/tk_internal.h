@@ -185,7 +185,9 @@ int64_t launch_resid_small_parts(const Geom& g, const int32_t* idx, const double
 // One refinement step for d <= 256 in one workgroup (tk_refine.hip): r = the
 // summed partials + b - lambda P h, relres = ||r|| / ||norm_ref||, done once
 // relres <= tol, else (when do_solve) h += (L L^T)^{-1} r with L in M and the
-// diagonal-block inverses; returns at entry once done is set.
+// diagonal-block inverses; returns at entry once done is set.  first: the
+// initial solve instead, h = (L L^T)^{-1} b with no partials (nparts 0), done
+// cleared, steps and relres untouched.
 bool refine_small_ok(const Geom& g);
 // For d <= 8192: P h applied in one workgroup, then r = r + b - lambda P h and the
 // same test (done / steps / relres) as launch_refine_check.
@@ -205,7 +207,8 @@ void launch_refine_check_p(const Geom& g, double* r, const double* h, const doub
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
                               const double* b, double lambda, const double* norm_ref, double tol,
                               const double* L, const double* Linv_diag, double* h, int32_t* done,
-                              int32_t* steps, double* relres, int do_solve, hipStream_t st);
+                              int32_t* steps, double* relres, int do_solve, hipStream_t st,
+                              int first = 0);
 
 // Refinement residual coefficients c_t = xw_t - weff_t (q_t . h); part: vec_part_doubles.
 void launch_residual_coef(const Geom& g, const double* rows64, const double* xw,

@@ -38,8 +38,10 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
     Geom g, const double* __restrict__ part, int64_t nparts, const double* __restrict__ P,
     const double* __restrict__ b, double lambda, const double* __restrict__ norm_ref, double tol,
     const double* __restrict__ L, const double* __restrict__ Linv_diag, double* __restrict__ h,
-    int32_t* done, int32_t* steps, double* relres, int do_solve) {
-  if (*done) return;
+    int32_t* done, int32_t* steps, double* relres, int do_solve, int first) {
+  // first: the initial solve h = (L L^T)^{-1} b (no partials, h taken as
+  // zero and written, done cleared, no step counted)
+  if (!first && *done) return;
   __shared__ double rs[kRsD], ta[kRsD], tb[kRsD], yv[kRsD], acc[kNb];
   __shared__ double red[kRsThreads];
   __shared__ double Li[kNb * kLd];
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
       for (; k < nparts; k += G) v += part[k * d + i];
     }
     red[tid] = v;
-    if (tid < d) ta[tid] = h[tid];
+    if (tid < d) ta[tid] = first ? 0.0 : h[tid];
     __syncthreads();
     if (tid < d) {
       double s = 0.0;
@@ -111,15 +113,19 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
   const double sa = block_sum(a2, red);
   const double sn = block_sum(n2, red + 32);
   const double rel = sn > 0.0 ? sqrt(sa / sn) : sqrt(sa);
-  const bool conv = rel <= tol;
+  const bool conv = !first && rel <= tol;
   if (tid == 0) {
-    *relres = rel;
-    if (conv)
-      *done = 1;
-    else if (do_solve)
-      *steps += 1;
+    if (first) {
+      *done = 0;
+    } else {
+      *relres = rel;
+      if (conv)
+        *done = 1;
+      else if (do_solve)
+        *steps += 1;
+    }
   }
-  if (conv || !do_solve) return;
+  if (conv || !(do_solve || first)) return;
 
   // 4. delta = (L L^T)^{-1} r by 64-row blocks; h += delta
   const int nblk = (d + kNb - 1) / kNb;
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(kRsThreads) void refine_step_small_kernel(
       double s = 0.0;
       for (int k = 0; k < 16; ++k) s += red[k * 64 + tid];
       rs[i0 + tid] = s;
-      h[i0 + tid] += s;
+      h[i0 + tid] = first ? s : h[i0 + tid] + s;
     }
   }
 }
@@ -381,9 +387,11 @@ void launch_refine_check_p(const Geom& g, double* r, const double* h, const doub
 void launch_refine_step_small(const Geom& g, const double* part, int64_t nparts, const double* P,
                               const double* b, double lambda, const double* norm_ref, double tol,
                               const double* L, const double* Linv_diag, double* h, int32_t* done,
-                              int32_t* steps, double* relres, int do_solve, hipStream_t st) {
+                              int32_t* steps, double* relres, int do_solve, hipStream_t st,
+                              int first) {
   hipLaunchKernelGGL(refine_step_small_kernel, dim3(1), dim3(kRsThreads), 0, st, g, part, nparts,
-                     P, b, lambda, norm_ref, tol, L, Linv_diag, h, done, steps, relres, do_solve);
+                     P, b, lambda, norm_ref, tol, L, Linv_diag, h, done, steps, relres, do_solve,
+                     first);
 }
 
 }  // namespace tk
