@@ -247,7 +247,8 @@ def main():
     traffic = read_traffic(f"gram_{args.precision}", args.workload)
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": f"gram_kernel ({args.precision} operands, fp32 accumulation)",
+                "kernel": f"gram_sk_kernel (stream-K Gram, {args.precision} operands, fp32 "
+                          "accumulation; time of the Gram stage, with its slot-index kernel)",
                 "algorithmic_flops": flops, "kernel_ms": round(gram_ms, 4)}
 
     extras = {}
