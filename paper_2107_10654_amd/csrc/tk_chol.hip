@@ -358,9 +358,15 @@ __device__ inline void apply_inverse_store(double* M, int64_t d, int64_t i0, int
       }
 }
 
+// Release at agent scope: this thread's stores are written back from L2
+// before anything after the fence.  Readers take published data with coherent
+// (agent-scope atomic) loads, so no invalidation is needed here; a full fence
+// would also invalidate this XCD's L2 at every publication.
+__device__ inline void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
 // Raise a tile's flag once every thread's stores to it are visible.
 __device__ inline void publish_tile(int32_t* flag) {
-  __threadfence();
+  release_fence();
   __syncthreads();
   if (threadIdx.x == 0)
     __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -513,7 +519,7 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
             Lc[r * LDA + c] = val;
             if (r < r1) M[(i10 + r) * d + j0 + c] = val;
           }
-      __threadfence();
+      release_fence();
       __syncthreads();
       if (tid == 0) {
         __hip_atomic_store(&tile_flag[tile_flag_index(j, j)], 1, __ATOMIC_RELEASE,
