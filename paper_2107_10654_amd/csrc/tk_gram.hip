@@ -20,6 +20,8 @@
 // (modes after L have rank 1 and contribute their single entry).
 #include <string.h>
 
+#include <mutex>
+
 #include "tk_mfma.h"
 
 namespace tk {
@@ -1396,10 +1398,12 @@ int64_t reg_grid(int64_t s) {
 }  // namespace
 
 int resident_grid(const void* kernel, int threads, size_t dyn_lds) {
+  static std::mutex mu;  // host threads may launch concurrently
   static const void* keys[64];
   static size_t ldss[64];
   static int vals[64];
   static int n = 0;
+  std::lock_guard<std::mutex> lock(mu);
   for (int k = 0; k < n; ++k)
     if (keys[k] == kernel && ldss[k] == dyn_lds) return vals[k];
   int per_cu = 0;
