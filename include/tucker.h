@@ -139,7 +139,10 @@ tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* 
  * product are products of factor scores) and Alg. 1 (s i.i.d. draws with
  * replacement, sketch entry 1/sqrt(P(j) s)).
  *
- *   cdf     device, concatenated per-mode integer CDFs (as written above)
+ *   dims    host [order], I_n >= 1 each
+ *   cdf     device, concatenated per-mode integer CDFs (as written above): exactly
+ *           sum_n dims[n] uint64 entries, owned by the caller.  The call cannot check
+ *           the length of a device buffer; a shorter table is read out of bounds.
  *   idx     device int32 [order][s] (structure of arrays): idx[n*s + t] = i_n of sample t
  *   weight  device double [s]: weight_t = (prod_n W_n / w_{i_n}) / s = 1/(s P(t)),
  *           the product taken in mode order, one IEEE operation at a time

@@ -164,13 +164,13 @@ void launch_adjoint_factors(const Geom& g, const void* const* factors, tk_dtype 
   const dim3 grid(static_cast<unsigned>(cdiv(s, kAdjS)));
   const size_t lds = adjoint_lds_bytes(g);
   if (dt == TK_F64) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_factor_kernel<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    ensure_dyn_lds(reinterpret_cast<const void*>(&adjoint_factor_kernel<double>),
+                   static_cast<int>(lds));
     hipLaunchKernelGGL(adjoint_factor_kernel<double>, grid, dim3(kBlock), lds, st, g, fp, idx, s,
                        V, G, alpha, nbeta, abar);
   } else {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&adjoint_factor_kernel<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    ensure_dyn_lds(reinterpret_cast<const void*>(&adjoint_factor_kernel<float>),
+                   static_cast<int>(lds));
     hipLaunchKernelGGL(adjoint_factor_kernel<float>, grid, dim3(kBlock), lds, st, g, fp, idx, s, V,
                        G, alpha, nbeta, abar);
   }

@@ -238,7 +238,8 @@ __device__ inline int acc_c(int y) {
 
 // ---- left-looking dataflow factorisation in one persistent launch
 // With S_ij = A_ij - sum_{k < j} L_ik L_jk^T over lower 64 x 64 tiles:
-//  * workgroup 0 runs the chain of the factorisation, column by column: S_jj
+//  * the workgroup that starts first (ticket 0) runs the chain of the
+//    factorisation, column by column: S_jj
 //    (its last term L_{j,j-1} L_{j,j-1}^T from the tile it made itself, still in
 //    LDS), the factor and inverse of S_jj, then the next tile
 //    L_{j+1,j} = S_{j+1,j} L_jj^{-T}, which it keeps in LDS for the next column;
@@ -252,8 +253,11 @@ __device__ inline int acc_c(int y) {
 // with agent-scope coherent loads, so no cache invalidation is needed.  A
 // ticketed task waits only on smaller tickets or on chain tiles of earlier
 // columns, and the chain at column j only on tickets of columns j - 2 and
-// j - 1, so the launch drains; every wait is bounded (TK_E_HIP past the limit,
-// the task then goes on).
+// j - 1.  Tickets are taken when a workgroup starts, so every wait is on a
+// workgroup that is already running and never gives up its compute unit:
+// the launch drains whatever the dispatch order or the number of co-resident
+// workgroups.  Every wait is still bounded (TK_E_HIP past the limit, the task
+// then goes on).
 constexpr int kFlagStride = 32;  // one flag per 128-byte line
 __device__ inline int64_t tile_flag_index(int64_t i, int64_t j) {
   return (i * (i + 1) / 2 + j) * kFlagStride;
@@ -431,7 +435,13 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
     __syncthreads();
     failed = failed || !ok_s;
   };
-  if (blockIdx.x == 0) {
+  // Roles come from the ticket counter, in the order workgroups start: ticket 0
+  // runs the chain, ticket k >= 1 runs task k - 1.  Every wait is then on work
+  // held by a workgroup that has already started (the chain, or a smaller
+  // ticket), never on one that may still be queued for a compute unit.
+  if (tid == 0) task_s = atomicAdd(&flags[0], 1);
+  __syncthreads();
+  if (task_s == 0) {
     // ---------------- the chain (Lc holds L_{j,j-1} from the previous column)
     __builtin_amdgcn_s_setprio(3);
     for (int64_t j = 0; j < nblk; ++j) {
@@ -531,11 +541,13 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
   } else {
     // ---------------- ticketed tasks
     const int64_t ntasks = chol_flow_tasks(nblk);
-    for (;;) {
-      __syncthreads();  // the previous task is done with LDS and task_s
-      if (tid == 0) task_s = atomicAdd(&flags[0], 1);
-      __syncthreads();
-      const int64_t t = task_s;
+    for (bool first = true;; first = false) {
+      if (!first) {
+        __syncthreads();  // the previous task is done with LDS and task_s
+        if (tid == 0) task_s = atomicAdd(&flags[0], 1);
+        __syncthreads();
+      }
+      const int64_t t = task_s - 1;
       if (t >= ntasks) break;
       int64_t j = 0, start = 0;
       for (;;) {
@@ -630,17 +642,7 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
 }
 
 int chol_flow_grid(int64_t nblk) {
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        n > 0)
-      cus = n;
-    else
-      cus = 256;
-    (void)hipGetLastError();
-  }
+  const int cus = device_cu_count();
   const int64_t ntasks = chol_flow_tasks(nblk);
   const int64_t g = cus;  // one workgroup per CU: the serial panel factor keeps its SIMD
   return static_cast<int>(1 + ntasks < g ? 1 + ntasks : g);  // the chain + ticketed tasks

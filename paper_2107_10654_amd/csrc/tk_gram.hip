@@ -1397,35 +1397,99 @@ int64_t reg_grid(int64_t s) {
 
 }  // namespace
 
+namespace {
+std::mutex g_query_mu;  // guards every cache below
+
+// Runs one HIP query; on failure clears the error only if none was pending
+// before it (an earlier error stays visible to the entry point and the caller).
+template <class F>
+hipError_t quiet_query(F&& f) {
+  const hipError_t prior = hipPeekAtLastError();
+  const hipError_t e = f();
+  if (e != hipSuccess && prior == hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+int current_device() {
+  int dev = 0;
+  if (quiet_query([&] { return hipGetDevice(&dev); }) != hipSuccess) dev = 0;
+  return dev;
+}
+
+constexpr int kQueryDevices = 64;
+int g_cus[kQueryDevices];
+
+int cu_count_locked(int dev) {
+  if (dev >= 0 && dev < kQueryDevices && g_cus[dev] > 0) return g_cus[dev];
+  int n = 0;
+  if (quiet_query([&] {
+        return hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+      }) != hipSuccess ||
+      n < 1)
+    n = 256;  // MI355X
+  if (dev >= 0 && dev < kQueryDevices) g_cus[dev] = n;
+  return n;
+}
+
+struct GridKey {
+  int dev;
+  const void* kernel;
+  size_t lds;
+  int threads;
+  int val;
+};
+GridKey g_grids[128];
+int g_ngrids = 0;
+
+struct LdsKey {
+  int dev;
+  const void* kernel;
+  int bytes;
+};
+LdsKey g_lds[64];
+int g_nlds = 0;
+}  // namespace
+
+int device_cu_count() {
+  std::lock_guard<std::mutex> lock(g_query_mu);
+  return cu_count_locked(current_device());
+}
+
 int resident_grid(const void* kernel, int threads, size_t dyn_lds) {
-  static std::mutex mu;  // host threads may launch concurrently
-  static const void* keys[64];
-  static size_t ldss[64];
-  static int vals[64];
-  static int n = 0;
-  std::lock_guard<std::mutex> lock(mu);
-  for (int k = 0; k < n; ++k)
-    if (keys[k] == kernel && ldss[k] == dyn_lds) return vals[k];
+  std::lock_guard<std::mutex> lock(g_query_mu);
+  const int dev = current_device();
+  for (int k = 0; k < g_ngrids; ++k)
+    if (g_grids[k].dev == dev && g_grids[k].kernel == kernel && g_grids[k].lds == dyn_lds &&
+        g_grids[k].threads == threads)
+      return g_grids[k].val;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_lds) !=
-          hipSuccess ||
+  if (quiet_query([&] {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_lds);
+      }) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
-  (void)hipGetLastError();
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus < 1)
-    cus = 256;
-  (void)hipGetLastError();
-  const int v = per_cu * cus;
-  if (n < 64) {
-    keys[n] = kernel;
-    ldss[n] = dyn_lds;
-    vals[n] = v;
-    ++n;
-  }
+  const int v = per_cu * cu_count_locked(dev);
+  if (g_ngrids < 128) g_grids[g_ngrids++] = GridKey{dev, kernel, dyn_lds, threads, v};
   return v;
+}
+
+void ensure_dyn_lds(const void* kernel, int bytes) {
+  std::lock_guard<std::mutex> lock(g_query_mu);
+  const int dev = current_device();
+  for (int k = 0; k < g_nlds; ++k)
+    if (g_lds[k].dev == dev && g_lds[k].kernel == kernel) {
+      if (g_lds[k].bytes >= bytes) return;
+      if (quiet_query([&] {
+            return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+          }) == hipSuccess)
+        g_lds[k].bytes = bytes;
+      return;
+    }
+  if (quiet_query([&] {
+        return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+      }) == hipSuccess &&
+      g_nlds < 64)
+    g_lds[g_nlds++] = LdsKey{dev, kernel, bytes};
 }
 
 bool resid_small_ok(const Geom& g) { return g.d <= kSmD && g.sum_r <= kSmSumR; }
@@ -1561,15 +1625,8 @@ template <int W, int NL>
 void resid_big_launch(dim3 grid, size_t lds, hipStream_t st, const Geom& g, const double* rows64,
                       const double* a, const double* b, const double* h, int64_t s, int64_t cpw,
                       double* part, const int32_t* done) {
-  if (lds > 64 * 1024) {  // dynamic LDS above the default limit (gfx950: 160 KB per CU)
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&resid_big_kernel<W, NL>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      (void)hipGetLastError();
-      attr = true;
-    }
-  }
+  if (lds > 64 * 1024)  // dynamic LDS above the default limit (gfx950: 160 KB per CU)
+    ensure_dyn_lds(reinterpret_cast<const void*>(&resid_big_kernel<W, NL>), 96 * 1024);
   hipLaunchKernelGGL((resid_big_kernel<W, NL>), grid, dim3(kBlock), lds, st, g, rows64, a, b, h,
                      s, cpw, part, done);
 }

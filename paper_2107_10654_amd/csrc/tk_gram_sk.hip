@@ -746,15 +746,9 @@ __global__ __launch_bounds__(64 * kAsmWaves) void assemble_sk_one_tile_kernel(
 template <class V, int T, int PF4, bool DB>
 void gram_sk_launch_k(const SkBatch& b, float* slots, const int64_t* index, hipStream_t st) {
   const size_t lds = SkLayout<V, T, DB ? 2 : 1>::bytes(b.max_sum_r);
-  if (lds > 64 * 1024) {
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gram_sk_kernel<V, T, PF4, DB>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(kSkMaxLds));
-      attr = true;
-    }
-  }
+  if (lds > 64 * 1024)
+    ensure_dyn_lds(reinterpret_cast<const void*>(&gram_sk_kernel<V, T, PF4, DB>),
+                   static_cast<int>(kSkMaxLds));
   hipLaunchKernelGGL((gram_sk_kernel<V, T, PF4, DB>), dim3(static_cast<unsigned>(b.grid)),
                      dim3(SkTile<T>::THREADS), lds, st, b, slots, index);
 }
@@ -776,20 +770,6 @@ void gram_sk_launch(const SkBatch& b, float* slots, const int64_t* index, hipStr
   else gram_sk_launch_k<V, T, Pf::LARGE, false>(b, slots, index, st);
 }
 
-int device_cu_count() {
-  static int cached = 0;
-  if (cached == 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        n > 0)
-      cached = n;
-    else
-      cached = 256;  // MI355X
-    (void)hipGetLastError();
-  }
-  return cached;
-}
 
 }  // namespace
 

@@ -152,10 +152,21 @@ void launch_gram(const Geom& g, const GramPlan& pl, const double* rows64, const 
 void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, const double* P,
                      double lambda, double* M, hipStream_t st);
 
+// Host-side device queries (tk_gram.hip).  Each caches its answer per HIP
+// device under one mutex (host threads may launch concurrently).  A failing
+// query falls back to a safe value and clears only the HIP error it raised
+// itself: an error already pending from an earlier call is never cleared, so
+// the entry point's final hipGetLastError() check (and the caller) still see it.
+//
 // Workgroups of `kernel` (with `threads` threads and dyn_lds bytes of dynamic
-// LDS) resident on the whole device at once, cached: a grid-stride pass with
+// LDS) resident on the whole current device at once: a grid-stride pass with
 // equal shares per workgroup runs in one wave only if its grid is no larger.
 int resident_grid(const void* kernel, int threads, size_t dyn_lds);
+// Compute units of the current device (256 on MI355X).
+int device_cu_count();
+// Raises `kernel`'s dynamic-LDS limit to `bytes` on the current device (once
+// per device and kernel; later calls with the same or a smaller size return at once).
+void ensure_dyn_lds(const void* kernel, int bytes);
 
 // out[r] = sum_t c_t q_t[r] (q_t the whitened Kronecker row), FP64, deterministic.
 // part: vec_part_doubles(g, s) scratch.

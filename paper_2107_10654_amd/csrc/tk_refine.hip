@@ -341,14 +341,9 @@ void launch_core_chain_small(const Geom& g, const double* t, const double* mats,
     np_lds = static_cast<int>(np);
     lds += sizeof(double) * static_cast<size_t>(np);
   }
-  static bool attr = false;  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&core_chain_small_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
-    (void)hipGetLastError();
-    attr = true;
-  }
+  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
+  ensure_dyn_lds(reinterpret_cast<const void*>(&core_chain_small_kernel),
+                 static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
   hipLaunchKernelGGL(core_chain_small_kernel, dim3(1), dim3(kRsThreads), lds, st, g, t, mats,
                      trans ? 1 : 0, np_lds, out, dt == TK_F64 ? 1 : 0);
 }
@@ -371,14 +366,9 @@ void launch_refine_check_p(const Geom& g, double* r, const double* h, const doub
     np_lds = static_cast<int>(np);
     lds += sizeof(double) * static_cast<size_t>(np);
   }
-  static bool attr = false;  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&refine_check_p_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
-    (void)hipGetLastError();
-    attr = true;
-  }
+  // dynamic LDS above the 64 KB default (gfx950: 160 KB per CU)
+  ensure_dyn_lds(reinterpret_cast<const void*>(&refine_check_p_kernel),
+                 static_cast<int>(kPcMaxLds - 64 * sizeof(double)));
   hipLaunchKernelGGL(refine_check_p_kernel, dim3(1), dim3(kRsThreads), lds, st, g, r, h, P, b,
                      lambda, norm_ref, tol, done, steps, relres, count_step, np_lds, solve_flags,
                      solve_y);

@@ -155,6 +155,13 @@ def sample(dims, cdf, s, seed, counter=0, problem=0):
     """Product-distribution samples: idx (N, s) int32 and weight (s,) float64."""
     lib = L.load()
     _check_tensor(cdf, "cdf", torch.int64)
+    dims = [int(v) for v in dims]
+    if not 1 <= len(dims) <= L.MAX_ORDER or min(dims) < 1:
+        raise ValueError("dims must hold 1..8 sizes, each >= 1")
+    if cdf.numel() != sum(dims):
+        raise ValueError(f"cdf must hold sum(dims) = {sum(dims)} entries, got {cdf.numel()}")
+    if int(s) < 1:
+        raise ValueError("s must be >= 1")
     dev = cdf.device
     N = len(dims)
     idx = torch.empty((N, int(s)), dtype=torch.int32, device=dev)
@@ -169,11 +176,13 @@ def sample(dims, cdf, s, seed, counter=0, problem=0):
 def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0, precision="f64",
                          mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
                          return_samples=False, return_info=False, check=True, out=None,
-                         stage_events=None):
+                         stage_events=None, status=None):
     """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info).
 
     stage_events: optional address of an array of NUM_STAGE_EVENTS hipEvent_t
     handles that the library records at its stage boundaries.
+    status: optional int32 device tensor of one element that receives the call's
+    status word (default: a per-device word shared by all calls).
     """
     lib = L.load()
     p = make_problem(X, factors, lam, mask)
@@ -199,7 +208,11 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     if nb == 0:
         raise ValueError("unsupported problem for the sketched update")
     ws = _workspace(nb, dev)
-    st = _status_word(dev)
+    if status is not None:
+        _check_tensor(status, "status", torch.int32)
+        if status.numel() != 1:
+            raise ValueError("status must hold one int32 word")
+    st = status if status is not None else _status_word(dev)
     _raise_if(lib.tucker_core_update_sketched(ctypes.byref(p), ctypes.byref(o), _ptr(idx),
                                               _ptr(weight), _ptr(idx_out), _ptr(w_out), _ptr(core),
                                               _ptr(st), _ptr(info), _ptr(ws), ws.numel(),

@@ -34,10 +34,13 @@ def T(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def rel(a, b):
+def elem_err(a, b):
+    """Element-wise error bound: max_i |a_i - b_i| / max_i |b_i| (every entry of a
+    lies within this fraction of the reference's largest entry)."""
     a = np.asarray(a, dtype=np.float64).ravel()
     b = np.asarray(b, dtype=np.float64).ravel()
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    assert a.shape == b.shape, (a.shape, b.shape)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
 def _small_batch(dtype="f64", count=10):
@@ -63,10 +66,10 @@ def test_batched_equals_single_calls_and_oracle(tk, config):
         assert info[k, 3] <= 1e-13, (k, info[k])
         G1 = tk.core_update_sketched(Xs[k], Fs[k], lam, ss[k], seed=9, counter=2, problem=k,
                                      precision="bf16", refine_max=30)
-        assert rel(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-10, k
+        assert elem_err(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-10, k
         Gr, _, _, _ = oracle.fast_core_tensor_update(p["X"], p["factors_true"], lam, ss[k], 9, 2,
                                                      problem=k)
-        assert rel(cores[k].cpu().numpy(), Gr) <= 1e-9, k
+        assert elem_err(cores[k].cpu().numpy(), Gr) <= 1e-9, k
 
 
 def test_batched_f32_precision_and_f32_problems(tk):
@@ -77,7 +80,7 @@ def test_batched_f32_precision_and_f32_problems(tk):
     for k in range(len(probs)):
         G1 = tk.core_update_sketched(Xs[k], Fs[k], lam, ss[k], seed=4, problem=k,
                                      precision="f32")
-        assert rel(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-5, k
+        assert elem_err(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-5, k
 
 
 def test_tuner_returns_a_candidate(tk):
@@ -121,7 +124,7 @@ def test_graph_replay_reads_new_inputs(tk):
     Xs[2].mul_(2.0)  # the core is linear in X
     after = upd.replay()
     torch.cuda.synchronize()
-    assert rel(after[2].cpu().numpy(), 2.0 * before[2].cpu().numpy()) <= 1e-10
+    assert elem_err(after[2].cpu().numpy(), 2.0 * before[2].cpu().numpy()) <= 1e-10
     assert torch.equal(after[1], before[1])
 
 
@@ -148,11 +151,11 @@ def test_c4_batch_matches_single_calls(tk, c4):
     for k in list(order[:4]) + list(order[-2:]):  # smallest and largest cores
         G1 = tk.core_update_sketched(Xs[k], Fs[k], lam, ss[k], seed=4, problem=int(k),
                                      precision="bf16")
-        assert rel(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-5, k
+        assert elem_err(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-5, k
     for k in order[:3]:  # the oracle solves the small ones end to end
         p = probs[k]
         Gr, _, _, _ = oracle.fast_core_tensor_update(
             p["X"].astype(np.float64), [A.astype(np.float32).astype(np.float64)
                                         for A in p["factors_true"]], lam, ss[k], 4, 0,
             problem=int(k))
-        assert rel(cores[k].cpu().numpy(), Gr) <= 1e-5, k
+        assert elem_err(cores[k].cpu().numpy(), Gr) <= 1e-5, k

@@ -334,3 +334,65 @@ def test_table1_workload_sample_count_is_alg1():
         cfg = workloads.CONFIGS[name]
         d = int(np.prod(cfg["ranks"]))
         assert cfg["samples"] == oracle.s_theory(d, 0.1, 0.1), name
+
+
+# ---------------------------------------------------------------- objective and mask pins
+
+def test_ridge_objective_equals_explicit_kronecker_form():
+    """ridge_objective is ||K vec G - vec X||^2 + lam ||G||^2 (Alg. 2 core step), with K
+    built here by np.kron of the factors in mode order; with a mask the sum runs over
+    the observed rows of K only (Sec. 4.2: missing entries remove rows of K)."""
+    p = workloads.tucker_tensor((5, 4, 6), (2, 3, 2), 91, "f64", factor="gaussian",
+                                noise=("sigma", 0.5), missing=0.3)
+    X, F = p["X"], p["factors_true"]
+    G = rand((2, 3, 2), 92)
+    lam = 0.7
+    K = np.kron(np.kron(F[0], F[1]), F[2])
+    r = K @ G.reshape(-1) - X.reshape(-1)
+    ref = float(r @ r + lam * np.sum(G * G))
+    assert abs(oracle.ridge_objective(X, G, F, lam) - ref) <= 1e-12 * ref
+    obs = np.zeros(X.size, dtype=bool)
+    words = p["mask"]
+    for e in range(X.size):  # bit e & 31 of word e >> 5, written out per entry
+        obs[e] = (int(words[e // 32]) >> (e % 32)) & 1 == 1
+    ro = r[obs]
+    ref_m = float(ro @ ro + lam * np.sum(G * G))
+    assert 0 < obs.sum() < X.size
+    assert abs(oracle.ridge_objective(X, G, F, lam, mask=words) - ref_m) <= 1e-12 * ref_m
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.5, 3.0])
+def test_objective_excess_equals_objective_difference(lam):
+    """For the exact ridge minimiser g*, f(g) - f(g*) = (g - g*)^T (K^T K + lam I)(g - g*)
+    exactly (a quadratic expanded at its minimiser), so sketched_objective_excess
+    must equal the difference of two ridge_objective values; a dropped lam term,
+    a missing factor or a transposed Gram shows up at these lam values."""
+    p = _tiny_problem(93, dims=(6, 7, 5), ranks=(2, 3, 2))
+    X, F = p["X"], p["factors_true"]
+    g_star = oracle.core_update_exact(X, F, lam)
+    f_star = oracle.ridge_objective(X, g_star, F, lam)
+    for k in range(3):
+        g = g_star + 0.3 * rand(g_star.shape, 94 + k)
+        diff = oracle.ridge_objective(X, g, F, lam) - f_star
+        exc = oracle.sketched_objective_excess(g, g_star, F, lam)
+        assert diff > 0
+        assert abs(exc - diff) <= 1e-9 * diff, (lam, exc, diff)
+
+
+def test_mask_bit_order_and_pack_roundtrip():
+    """Masks are LSB-first uint32 words: entry e is bit (e & 31) of word e >> 5.
+    Hand-built words pin the bit order; a random mask with a ragged last word
+    round-trips through the workload packer and the oracle's unpacker."""
+    words = np.array([0b1011, 1 << 31, 0x1], dtype=np.uint32)
+    flat = np.arange(65, dtype=np.int64)
+    got = oracle.mask_lookup(words, flat)
+    want = np.zeros(65, dtype=bool)
+    want[[0, 1, 3, 63, 64]] = True
+    assert np.array_equal(got, want)
+    assert np.array_equal(workloads.pack_mask(want), words)
+    rng = np.random.default_rng(95)
+    for dims in [(5, 7, 3), (33,), (4, 4, 2)]:
+        M = rng.random(dims) < 0.6
+        packed = workloads.pack_mask(M)
+        assert packed.size == (M.size + 31) // 32
+        assert np.array_equal(oracle.unpack_mask(packed, dims), M)
