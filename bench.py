@@ -109,8 +109,25 @@ def read_traffic(kernel, workload):
     return None
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(prob, F, lam, s, s_cpu, seed, mask=None):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    """The FP64 oracle on the host cores, on a bounded sample of the workload.
+
+    Returns the baseline record and, when the sample is the whole workload
+    (s_cpu == s), the oracle's core for counter 0, else None."""
     import numpy as np
     import oracle
     try:
@@ -118,6 +135,7 @@ def cpu_baseline(prob, F, lam, s, s_cpu, seed, mask=None):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+    model, ncpu = host_cpu()
     X = prob["X"]
     F = [np.asarray(A, dtype=np.float64) for A in F]
     t0 = time.perf_counter()
@@ -129,17 +147,22 @@ def cpu_baseline(prob, F, lam, s, s_cpu, seed, mask=None):
     t3 = time.perf_counter()
     d = gram.shape[0]
     Lc = np.linalg.cholesky(gram + lam * np.eye(d))
-    _ = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
+    g = np.linalg.solve(Lc.T, np.linalg.solve(Lc, rhs))
     t4 = time.perf_counter()
     scale = s / s_cpu
     t_full = (t1 - t0) + (t2 - t1 + t3 - t2) * scale + (t4 - t3)
-    return {
+    omp = os.environ.get("OMP_NUM_THREADS")
+    rec = {
         "value": 1.0 / t_full, "unit": "updates/s", "cores": int(cores), "kind": "oracle",
+        "host_cpus": ncpu, "cpu_model": model,
+        "threads_note": (f"BLAS threads = {cores} (OMP_NUM_THREADS={omp} on this host; "
+                         f"{ncpu} logical CPUs visible)"),
         "sample": (f"FP64 NumPy oracle sketched update with {s_cpu} of the {s} samples: sampling and "
                    f"Gram/right side timed on {s_cpu} samples and scaled linearly to {s}; leverage "
                    f"scores and the d={d} Cholesky solve timed in full; measured "
                    f"{t4 - t0:.1f} s of CPU work, extrapolated update time {t_full:.1f} s"),
     }
+    return rec, (g if s_cpu == s else None)
 
 
 def main():
@@ -207,26 +230,36 @@ def main():
     hip = HipEvents()
     nst = tk.tucker.L.NUM_STAGE_EVENTS
 
-    def run(k, events=None, check=False, info=False):
+    def run(k, events=None, check=False, info=False, status=None):
         return tk.core_update_sketched(X, F, lam, s, seed=cfg["seed"], counter=k, mask=mask,
                                        precision=args.precision, refine_max=args.refine_max,
                                        refine_tol=1e-13, check=check, return_info=info,
-                                       stage_events=ctypes.addressof(events) if events else None)
+                                       stage_events=ctypes.addressof(events) if events else None,
+                                       status=status)
 
-    # warmup (first call checked)
+    # warmup (first call checked); the counter-0 core is compared with the oracle's
     G, info = run(0, check=True, info=True)
+    G0 = G.detach().clone()
     for k in range(1, args.warmup):
         run(k)
     torch.cuda.synchronize()
     log(f"[bench] warmup done; refinement steps {info[2].item():.0f}, rel. residual {info[3].item():.2e}")
 
     ev = [hip.create(nst) for _ in range(args.steps)]
+    # one status word per timed step: a data-dependent failure in any of them
+    # (not positive definite, refinement not converged, a bounded wait that
+    # ran out) is caught after the timed region
+    st_words = torch.zeros(args.steps, dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        G = run(1000 + k, events=ev[k])
+        G = run(1000 + k, events=ev[k], status=st_words[k:k + 1])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    bad = st_words.cpu().numpy()
+    if bad.any():
+        log(f"[bench] timed steps reported status words {bad.tolist()}; no result")
+        sys.exit(3)
     stage_names = ["leverage", "sample", "gather", "gram", "assemble_rhs", "cholesky", "solve",
                    "refine", "finish"]
     stage_ms = {n: 0.0 for n in stage_names}
@@ -309,11 +342,24 @@ def main():
             f"loss exact {L_e[0]:.6e} sketched {L_s[0]:.6e}")
 
     cpu = None
+    oracle_err = None
     if not args.no_cpu_baseline and not on_device:
         log(f"[bench] CPU oracle baseline on {args.cpu_samples} samples ...")
-        cpu = cpu_baseline(prob, [A.astype(np_dt) for A in F_host], lam, s,
-                           min(args.cpu_samples, s), cfg["seed"], prob.get("mask"))
+        cpu, g_ref = cpu_baseline(prob, [A.astype(np_dt) for A in F_host], lam, s,
+                                  min(args.cpu_samples, s), cfg["seed"], prob.get("mask"))
         log(f"[bench] CPU oracle: {cpu['value']:.4g} updates/s on {cpu['cores']} threads")
+        if g_ref is not None:
+            # the GPU's counter-0 core against the oracle's solve of the same
+            # samples (FP64): max |G - G_ref| / max |G_ref| and the 2-norm ratio
+            a = G0.double().cpu().numpy().ravel()
+            oracle_err = {
+                "elementwise": float(np.max(np.abs(a - g_ref)) / np.max(np.abs(g_ref))),
+                "norm": float(np.linalg.norm(a - g_ref) / np.linalg.norm(g_ref)),
+                "what": "core of the counter-0 update vs the FP64 oracle's Cholesky solve of the "
+                        "same sketched system (same seed and samples); the GPU core is returned "
+                        f"in {cfg['dtype']}",
+            }
+            log(f"[bench] error vs FP64 oracle: element-wise {oracle_err['elementwise']:.3e}")
 
     out = {
         "metric": "sketched core updates/sec and ALS iteration time vs exact update at equal loss",
@@ -334,6 +380,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_rel_err": oracle_err,
     }
     out.update(extras)
     print(json.dumps(out), flush=True)

@@ -134,8 +134,24 @@ struct SketchWS {
   unsigned int* missing;
 };
 
+// Which optional slices a sampled update (call TK_CALL_SKETCHED) or its adjoint
+// (TK_CALL_ADJOINT) reads: the FP64 sample rows feed the FP64 Gram, the
+// large-d vector passes and the adjoint; the mode-product scratch serves the
+// multi-launch TTM chain, used for d above the one-workgroup kernels' limit
+// and by the adjoint.
+struct SketchNeeds {
+  bool rows64;
+  bool ttm;
+};
+
+SketchNeeds sketch_needs(const Geom& g, int32_t prec, int call) {
+  const bool adj = call == TK_CALL_ADJOINT;
+  return {adj || !resid_small_ok(g) || prec == TK_F64,
+          adj || !core_chain_small_ok(g) || !refine_check_p_ok(g)};
+}
+
 void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w,
-                  bool with_partials = true) {
+                  const SketchNeeds& need, bool with_partials = true) {
   carve_lev(c, g, w.lev);
   const int64_t d = g.d;
   w.idx = c.take<int32_t>(static_cast<size_t>(g.order) * s);
@@ -154,10 +170,12 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.ph_a = c.take<double>(d);
   w.ph_b = c.take<double>(d);
   w.vpart = c.take<double>(vec_part_doubles(g, s));
-  w.rows64 = c.take<double>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
+  w.rows64 = need.rows64
+                 ? c.take<double>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r)
+                 : nullptr;
   w.rows32 = c.take<float>(static_cast<size_t>(row_chunks(s)) * kRowChunk * g.sum_r);
   w.coef = c.take<double>(s);
-  w.ttm_scratch = c.take<double>(kTtmScratchDoubles);
+  w.ttm_scratch = need.ttm ? c.take<double>(kTtmScratchDoubles) : nullptr;
   w.flags = c.take<int32_t>(chol_flag_words(d));
   w.status = c.take<int32_t>(1);
   w.done = c.take<int32_t>(1);
@@ -450,7 +468,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w);
+      carve_sketch(c, g, s, pl, w, sketch_needs(g, opts->gram_precision, call));
       break;
     }
     case TK_CALL_ADJOINT: {
@@ -459,7 +477,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w);
+      carve_sketch(c, g, s, pl, w, sketch_needs(g, opts->gram_precision, call));
       AdjWS a;
       carve_adjoint(c, g, s, a);
       break;
@@ -701,7 +719,8 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
 // Validates one problem's sampled-update arguments and carves its workspace
 // from `c` (the Gram partials too unless the problem is part of a batch).
 tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* o,
-                       int32_t* dev_status, Carver& c, void* stream, bool with_partials) {
+                       int32_t* dev_status, Carver& c, void* stream, bool with_partials,
+                       int call) {
   int64_t s = 0;
   tk_status stt = check_sketch_args(p, o, s);
   if (stt != TK_OK) return stt;
@@ -710,8 +729,9 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_gram(R.g, s, o->gram_precision, 0);
-  R.want_rows64 = !resid_small_ok(R.g) || o->gram_precision == TK_F64;
-  carve_sketch(c, R.g, s, R.pl, R.w, with_partials);
+  const SketchNeeds need = sketch_needs(R.g, o->gram_precision, call);
+  R.want_rows64 = need.rows64;
+  carve_sketch(c, R.g, s, R.pl, R.w, need, with_partials);
   R.status = dev_status ? dev_status : R.w.status;
   return TK_OK;
 }
@@ -724,7 +744,7 @@ tk_status sketch_begin(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
     return stt != TK_OK ? stt : TK_E_WORKSPACE;
   }
   R.carver = Carver(ws);
-  return sketch_carve(R, p, o, dev_status, R.carver, stream, true);
+  return sketch_carve(R, p, o, dev_status, R.carver, stream, true, call);
 }
 
 // ---------------------------------------------------------------- batches
@@ -762,7 +782,7 @@ void carve_batch(Carver& c, const tk_problem* probs, const tk_sketch_opts* opts,
   b.count = count;
   for (int k = 0; k < count; ++k) {
     (void)sketch_carve(runs[k], &probs[k], &opts[k], dev_status ? dev_status + k : nullptr, c,
-                       stream, false);
+                       stream, false, TK_CALL_SKETCHED);
     b.p[k] = sk_prob(runs[k].g, runs[k].s, runs[k].w.rows32);
   }
   sk_finalize(b, static_cast<tk_dtype>(opts[0].gram_precision), cfg);
@@ -863,7 +883,6 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
     if (!factor_bar[n]) return TK_E_ARG;
   SketchRun R;
   stt = sketch_begin(R, p, o, dev_status, ws, ws_bytes, stream, TK_CALL_ADJOINT);
-  R.want_rows64 = true;  // the adjoint's per-sample coefficients read the FP64 rows
   if (stt != TK_OK) return stt;
   AdjWS a;
   carve_adjoint(R.carver, R.g, R.s, a);

@@ -160,12 +160,38 @@ def _f(tk, c, X, F):
     return float((G * c["gbar"]).sum().item())
 
 
+def test_c5_forward_matches_oracle(tk, c5):
+    """The full-size C5 forward (FP64 mode) against the oracle: samples bit-exact
+    with the oracle's sampler, core within 1e-10 element-wise of the oracle's
+    Cholesky solve of the same sketched system."""
+    cfg = c5["cfg"]
+    Fn = [np.asarray(A, dtype=np.float64) for A in c5["prob"]["factors_true"]]
+    tables = [oracle.cdf_table(oracle.leverage_scores(A)) for A in Fn]
+    ridx, rw = oracle.sample(tables, cfg["samples"], cfg["seed"], 0)
+    assert np.array_equal(c5["idx"].cpu().numpy(), ridx)
+    assert np.array_equal(c5["w"].cpu().numpy(), rw)
+    Gr = oracle.core_update_sketched(c5["prob"]["X"].astype(np.float64), Fn, cfg["lam"], ridx, rw)
+    assert elem_err(c5["G"].cpu().numpy(), Gr) <= 1e-10
+
+
+def _fd_check(ad, fd, floor):
+    # central differences at h = 1e-4 in FP64: truncation ~1e-8 relative, and the
+    # forward's rounding noise (~1e-13 of <gbar, g>) divided by 2h gives an
+    # absolute floor
+    assert abs(ad - fd) <= 1e-6 * abs(fd) + floor, (ad, fd)
+
+
 def test_c5_adjoint_matches_central_differences(tk, c5):
+    """32 random unit directions per factor and for X, and 64 coordinates (16
+    per factor: rows that were sampled and rows drawn at random; 16 of X: 8
+    sampled entries and 8 random ones, whose gradient is 0 unless sampled)."""
     h = 1e-4
     rng = np.random.default_rng(7)
     F = c5["F"]
+    scale = abs(float((c5["G"] * c5["gbar"]).sum().item()))
+    floor = 1e-13 * scale / h
     for n in range(3):
-        for _ in range(3):
+        for _ in range(32):
             D = rng.standard_normal(tuple(F[n].shape))
             D /= np.linalg.norm(D)
             Dt = T(D)
@@ -173,14 +199,71 @@ def test_c5_adjoint_matches_central_differences(tk, c5):
             Fm = [A if m != n else A - h * Dt for m, A in enumerate(F)]
             fd = (_f(tk, c5, c5["X"], Fp) - _f(tk, c5, c5["X"], Fm)) / (2 * h)
             ad = float((c5["fbar"][n] * Dt).sum().item())
-            assert abs(ad - fd) <= 1e-6 * max(abs(fd), 1e-3), (n, ad, fd)
-    for _ in range(3):
+            _fd_check(ad, fd, floor)
+    for _ in range(32):
         D = rng.standard_normal(tuple(c5["X"].shape))
         D /= np.linalg.norm(D)
         Dt = T(D)
         fd = (_f(tk, c5, c5["X"] + h * Dt, F) - _f(tk, c5, c5["X"] - h * Dt, F)) / (2 * h)
         ad = float((c5["xbar"] * Dt).sum().item())
-        assert abs(ad - fd) <= 1e-6 * max(abs(fd), 1e-6), (ad, fd)
+        _fd_check(ad, fd, floor)
+    # A single coordinate carries the whole step h (a random unit direction
+    # spreads it over thousands of entries), so the O(h^2) truncation of the
+    # central difference is larger there: the coordinate checks combine the
+    # central differences at h and h/2 (Richardson, error O(h^4)), whose
+    # rounding noise is three times that of one difference.
+    idx = c5["idx"].cpu().numpy()
+
+    def factor_fd(n, i, r, step):
+        Fp = [A.clone() for A in F]
+        Fm = [A.clone() for A in F]
+        Fp[n][i, r] += step
+        Fm[n][i, r] -= step
+        return (_f(tk, c5, c5["X"], Fp) - _f(tk, c5, c5["X"], Fm)) / (2 * step)
+
+    def x_fd(c, step):
+        Xp, Xm = c5["X"].clone(), c5["X"].clone()
+        Xp[c] += step
+        Xm[c] -= step
+        return (_f(tk, c5, Xp, F) - _f(tk, c5, Xm, F)) / (2 * step)
+
+    for n in range(3):
+        I, R = F[n].shape
+        rows = list(rng.choice(idx[n], 8)) + list(rng.integers(0, I, 8))
+        for i in rows:
+            r = int(rng.integers(0, R))
+            fd = (4 * factor_fd(n, int(i), r, h / 2) - factor_fd(n, int(i), r, h)) / 3
+            _fd_check(float(c5["fbar"][n][int(i), r].item()), fd, 3 * floor)
+    cols = rng.choice(idx.shape[1], 8)
+    coords = [tuple(int(v) for v in idx[:, t]) for t in cols]
+    coords += [tuple(int(rng.integers(0, I)) for I in c5["X"].shape) for _ in range(8)]
+    for c in coords:
+        fd = (4 * x_fd(c, h / 2) - x_fd(c, h)) / 3
+        _fd_check(float(c5["xbar"][c].item()), fd, 3 * floor)
+
+
+def test_adjoint_repeatable_with_duplicate_samples(tk):
+    """Duplicate samples accumulate through atomics in an order that can vary
+    from run to run; two runs agree to rounding (1e-13 of the largest entry in
+    FP64), and both match the oracle's sequential sums (1e-9)."""
+    dims, ranks = (10, 9, 8), (3, 3, 2)
+    p, F = _case(dims, ranks, 41)
+    lam, s = 1e-3, 20000  # 720 entries, so every entry is drawn many times
+    tabs = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F]
+    idx, w = oracle.sample(tabs, s, 3, 1)
+    assert len(np.unique(oracle.flat_index(idx, dims))) < s // 10
+    gbar = np.random.default_rng(42).standard_normal(ranks)
+    X, FF = T(p["X"]), [T(A) for A in F]
+    G = tk.core_update_sketched(X, FF, lam, s, idx=T(idx), weight=T(w), precision="f64")
+    runs = [tk.core_update_sketched_adjoint(X, FF, lam, T(idx), T(w), G, T(gbar))
+            for _ in range(2)]
+    bars_r, xbar_r, _ = oracle.sketched_adjoint(p["X"], F, lam, idx, w, gbar)
+    for n in range(3):
+        a, b = runs[0][0][n].cpu().numpy(), runs[1][0][n].cpu().numpy()
+        assert elem_err(a, b) <= 1e-13, n
+        assert elem_err(a, bars_r[n]) <= 1e-9, n
+    assert elem_err(runs[0][1].cpu().numpy(), runs[1][1].cpu().numpy()) <= 1e-13
+    assert elem_err(runs[0][1].cpu().numpy(), xbar_r) <= 1e-9
 
 
 def test_c5_adjoint_against_exact_solve_gradient(tk, c5):

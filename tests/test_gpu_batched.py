@@ -149,9 +149,23 @@ def test_c4_batch_matches_single_calls(tk, c4):
     assert (info[:, 3] <= 1e-13).all(), info[:, 3].max()
     order = np.argsort([int(p["G_true"].size) for p in probs])
     for k in list(order[:4]) + list(order[-2:]):  # smallest and largest cores
-        G1 = tk.core_update_sketched(Xs[k], Fs[k], lam, ss[k], seed=4, problem=int(k),
-                                     precision="bf16")
+        G1, idx1, w1 = tk.core_update_sketched(Xs[k], Fs[k], lam, ss[k], seed=4, problem=int(k),
+                                               precision="bf16", return_samples=True)
         assert elem_err(cores[k].cpu().numpy(), G1.cpu().numpy()) <= 1e-5, k
+        if k in order[-2:]:
+            # the largest problems against the oracle: the batch draws the single
+            # call's samples (bit-exact with the oracle's sampler), and the batched
+            # core solves the sketched normal equations of those samples to the
+            # f32 output's rounding (oracle FP64 residual)
+            p = probs[k]
+            F64 = [A.astype(np.float32).astype(np.float64) for A in p["factors_true"]]
+            tables = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F64]
+            ridx, rw = oracle.sample(tables, ss[k], 4, 0, problem=int(k))
+            assert np.array_equal(idx1.cpu().numpy(), ridx), k
+            assert np.array_equal(w1.cpu().numpy(), rw), k
+            res = oracle.normal_equation_residual(p["X"].astype(np.float64), F64, lam, ridx, rw,
+                                                  cores[k].cpu().numpy())
+            assert res <= 1e-6, (k, res)
     for k in order[:3]:  # the oracle solves the small ones end to end
         p = probs[k]
         Gr, _, _, _ = oracle.fast_core_tensor_update(

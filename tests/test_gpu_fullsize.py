@@ -119,3 +119,30 @@ def test_c3_masked_exact_core_is_the_minimiser(tk, c3):
     assert second > 0
     assert first <= 1e-4 * second, (first, second)
     assert Ls >= L0
+
+
+# ---------------------------------------------------------------- the paper's sample count
+# Alg. 1's count for eps = delta = 0.1 at d = 64 (the learned rank (4, 4, 4) of
+# the paper's synthetic table), on a small tensor: the sampler's grid-stride
+# loop runs many passes per workgroup and the refinement uses the per-sample
+# residual kernels at full s.  Bars: indices and weights bit-exact against the
+# oracle's sampler; the BF16 + refinement core solves its sketched normal
+# equations to <= 1e-9 (FP64 problem, so no output rounding), oracle FP64 residual.
+def test_paper_sample_count_bit_exact_and_solved(tk):
+    s = oracle.s_theory(64, 0.1, 0.1)
+    assert s == 1687583
+    prob = workloads.table1_problem((48, 40, 44), seed=31, dtype="f64", true_rank=(8, 8, 8))
+    F0 = workloads.random_factors((48, 40, 44), (4, 4, 4), seed=32, kind="uniform")
+    X, F = T(prob["X"]), [T(A) for A in F0]
+    print(f"[t1-count] s={s} dims (48, 40, 44) ranks (4, 4, 4)", flush=True)
+    G, idx, w, info = tk.core_update_sketched(X, F, 1e-3, s, seed=11, counter=4,
+                                              precision="bf16", refine_max=12, refine_tol=1e-13,
+                                              return_samples=True, return_info=True)
+    info = info.cpu().numpy()
+    tables = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F0]
+    ridx, rw = oracle.sample(tables, s, 11, 4)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(w.cpu().numpy(), rw)
+    assert info[3] <= 1e-13, info
+    res = oracle.normal_equation_residual(prob["X"], F0, 1e-3, ridx, rw, G.cpu().numpy())
+    assert res <= 1e-9, res
