@@ -183,6 +183,33 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
                                       size_t ws_bytes, void* stream);
 
 /*
+ * The sampled core update of tucker_core_update_sketched for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Arguments, results, status and
+ * errors are those of tucker_core_update_sketched, without the workspace: the
+ * call uses a device array of TK_NOALLOC_SCRATCH_BYTES built into the library
+ * (one copy per GPU, allocated when the library's code is first loaded on that
+ * GPU and held until the process ends).  Its device address is looked up on
+ * the first call made with each device current; the call itself never
+ * allocates, frees or synchronises.
+ *   Returns TK_E_WORKSPACE when the problem needs more workspace than that,
+ *   i.e. tucker_workspace_bytes(p, opts, TK_CALL_SKETCHED) >
+ *   TK_NOALLOC_SCRATCH_BYTES (use tucker_core_update_sketched with a caller
+ *   workspace instead); TK_E_HIP when the array's address cannot be found.
+ * Every call on one GPU shares that GPU's array and finds it holding the
+ * previous call's contents (the update clears what must start at zero).  Calls
+ * that overlap in time on one GPU -- on different streams, or from several
+ * threads -- race on the array and give undefined results; serialise them.
+ */
+#define TK_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+tk_status tucker_core_update_sketched_noalloc(const tk_problem* p, const tk_sketch_opts* opts,
+                                              const int32_t* idx_in, const double* weight_in,
+                                              int32_t* idx_out, double* weight_out,
+                                              void* core_out, int32_t* dev_status,
+                                              double* dev_info, void* stream);
+
+/*
  * The sketched ridge normal equations that tucker_core_update_sketched
  * factors and solves (Alg. 1; proof of Thm 4.2), in the whitened
  * coordinates of its solver.  With W = (x)_n L_n^{-1} (L_n the Cholesky factor

@@ -8,7 +8,8 @@ marshal arguments; see ``tucker.py``.
 """
 from .tucker import (  # noqa: F401
     BatchedSketchedUpdate, TuckerError, PRECISIONS, als, core_update_exact, core_update_sketched,
-    core_update_sketched_adjoint, core_update_sketched_batched, factor_update, leverage_scores,
+    core_update_sketched_adjoint, core_update_sketched_batched, core_update_sketched_noalloc,
+    factor_update, leverage_scores,
     loss, make_problem, release_workspace, sample, sample_count, sketched_system, tune_batched,
 )
 from .autograd import SketchedCoreUpdate, sketched_core_update  # noqa: F401

@@ -11,6 +11,7 @@ MAX_RANK = 64
 Q_BITS = 24
 INFO_LEN = 8
 NUM_STAGE_EVENTS = 10
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 CALL_LEVERAGE, CALL_SKETCHED, CALL_EXACT, CALL_FACTOR, CALL_LOSS, CALL_ADJOINT = range(6)
@@ -73,6 +74,8 @@ _SIGNATURES = {
     "tucker_core_update_sketched": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp, _vp, _vp,
                                                      _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                                      _vp]),
+    "tucker_core_update_sketched_noalloc": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp,
+                                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tucker_core_update_sketched_adjoint": (ctypes.c_int32, [_P(TkProblem), _P(TkSketchOpts), _vp,
                                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                              _vp, ctypes.c_size_t, _vp]),

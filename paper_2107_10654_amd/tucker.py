@@ -226,6 +226,52 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     return res[0] if len(res) == 1 else tuple(res)
 
 
+def core_update_sketched_noalloc(X, factors, lam, samples, seed=0, counter=0, problem=0,
+                                 precision="f64", mask=None, idx=None, weight=None, refine_max=20,
+                                 refine_tol=1e-13, return_samples=False, return_info=False,
+                                 check=True, out=None, status=None):
+    """The sampled core update of core_update_sketched through the library's
+    no-allocation entry point: its workspace is a device array built into the
+    library (NOALLOC_SCRATCH_BYTES per GPU), so the call allocates nothing in
+    the library.  Raises TuckerError(TK_E_WORKSPACE) for problems that need
+    more workspace than that.  Calls on one GPU share the array: do not overlap
+    them in time."""
+    lib = L.load()
+    p = make_problem(X, factors, lam, mask)
+    o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol)
+    dev = X.device
+    N = len(factors)
+    s = int(samples) if samples else sample_count(
+        int(torch.tensor([A.shape[1] for A in factors]).prod()), 0.1, 0.1)
+    if idx is not None:
+        _check_tensor(idx, "idx", torch.int32)
+        _check_tensor(weight, "weight", torch.float64)
+        if tuple(idx.shape) != (N, s) or weight.numel() != s:
+            raise ValueError("idx must be (N, s) and weight (s,)")
+    core = out if out is not None else torch.empty([A.shape[1] for A in factors], dtype=X.dtype,
+                                                   device=dev)
+    idx_out = w_out = None
+    if return_samples and idx is None:
+        idx_out = torch.empty((N, s), dtype=torch.int32, device=dev)
+        w_out = torch.empty(s, dtype=torch.float64, device=dev)
+    info = torch.empty(L.INFO_LEN, dtype=torch.float64, device=dev) if return_info else None
+    if status is not None:
+        _check_tensor(status, "status", torch.int32)
+        if status.numel() != 1:
+            raise ValueError("status must hold one int32 word")
+    st = status if status is not None else _status_word(dev)
+    _raise_if(lib.tucker_core_update_sketched_noalloc(
+        ctypes.byref(p), ctypes.byref(o), _ptr(idx), _ptr(weight), _ptr(idx_out), _ptr(w_out),
+        _ptr(core), _ptr(st), _ptr(info), _stream()), "core_update_sketched_noalloc")
+    _finish(dev, st, "core_update_sketched_noalloc", check)
+    res = [core]
+    if return_samples:
+        res += [idx if idx is not None else idx_out, weight if weight is not None else w_out]
+    if return_info:
+        res.append(info)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
 def sketched_system(X, factors, lam, idx, weight, precision="f64", mask=None, check=True):
     """The sketched normal equations (M, b) of the sampled update on the samples (idx, weight),
     in the solver's whitened coordinates: M = sum_t w_t q_t q_t^T + lam P (lower triangle
