@@ -393,6 +393,31 @@ def factor_update(X, G, factors, n, lam):
     return np.linalg.solve(KKt + lam * np.eye(Rn), rhs.T).T
 
 
+def factor_update_masked(X, G, factors, n, lam, mask, rows=None):
+    """New A(n) over the observed entries only: row i solves
+        a_i = argmin_y sum_{j observed in row i} (x_(n),ij - y . k_j)^2 + lam ||y||^2,
+    k_j the column j of K_n = G_(n) ((x)_{m != n} A(m))^T (Alg. 2 factor step,
+    restricted to the observed entries as in the tensor completion setting of
+    Sec. 4.2).  K_n is formed as the mode-n unfolding of G multiplied by every
+    factor but A(n).  ``rows`` (optional) limits the result to those rows (the
+    other rows of the returned matrix are NaN).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(G, dtype=np.float64)
+    for m, A in enumerate(factors):
+        if m != n:
+            Y = mode_product(Y, np.asarray(A, dtype=np.float64), m)
+    Kn = unfold(Y, n)                       # R_n x prod_{m != n} I_m
+    B = unfold(X, n)
+    obs = unfold(unpack_mask(mask, X.shape), n)
+    Rn = Kn.shape[0]
+    out = np.full((X.shape[n], Rn), np.nan)
+    for i in (range(X.shape[n]) if rows is None else rows):
+        Ko = Kn[:, obs[i]]
+        out[i] = np.linalg.solve(Ko @ Ko.T + lam * np.eye(Rn), Ko @ B[i, obs[i]])
+    return out
+
+
 # --------------------------------------------------------------------------
 # Loss (Sec. 2) and RMSE
 # --------------------------------------------------------------------------

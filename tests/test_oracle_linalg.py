@@ -396,3 +396,63 @@ def test_mask_bit_order_and_pack_roundtrip():
         packed = workloads.pack_mask(M)
         assert packed.size == (M.size + 31) // 32
         assert np.array_equal(oracle.unpack_mask(packed, dims), M)
+
+
+# ---------------------------------------------------------------- masked factor update
+def _row_design_by_reconstruction(G, F, n, i):
+    """Design of row i of A(n) built from the model itself: column r is the
+    slice i of the reconstruction with A(n) replaced by the unit matrix e_i e_r^T
+    (independent of any unfolding or Kronecker ordering)."""
+    cols = []
+    for r in range(F[n].shape[1]):
+        E = np.zeros_like(F[n])
+        E[i, r] = 1.0
+        Fe = [E if m == n else A for m, A in enumerate(F)]
+        cols.append(np.take(oracle.reconstruct(G, Fe), i, axis=n).reshape(-1))
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("dims,ranks", [((6, 5, 4), (2, 3, 2)), ((4, 5, 3, 3), (2, 2, 3, 2)),
+                                        ((7, 6), (3, 2))])
+def test_masked_factor_update_equals_rowwise_ridge_over_observed(dims, ranks):
+    p = workloads.tucker_tensor(dims, ranks, 60, "f64", factor="gaussian", noise=("sigma", 0.3),
+                                missing=0.3)
+    X, F, lam, mask = p["X"], p["factors_true"], 0.07, p["mask"]
+    G = rand(ranks, 61)
+    obs = oracle.unpack_mask(mask, dims)
+    for n in range(len(dims)):
+        got = oracle.factor_update_masked(X, G, F, n, lam, mask)
+        for i in range(dims[n]):
+            D = _row_design_by_reconstruction(G, F, n, i)
+            o = np.take(obs, i, axis=n).reshape(-1)
+            x = np.take(X, i, axis=n).reshape(-1)
+            M = np.vstack([D[o], np.sqrt(lam) * np.eye(ranks[n])])
+            rhs = np.concatenate([x[o], np.zeros(ranks[n])])
+            ref = np.linalg.lstsq(M, rhs, rcond=None)[0]
+            np.testing.assert_allclose(got[i], ref, rtol=1e-9, atol=1e-11)
+
+
+def test_masked_factor_update_special_cases():
+    p = _tiny_problem(62, dims=(6, 5, 4), ranks=(2, 3, 2))
+    X, F, lam = p["X"], p["factors_true"], 0.05
+    G = rand((2, 3, 2), 63)
+    full = workloads.pack_mask(np.ones(X.shape, bool))
+    for n in range(3):
+        np.testing.assert_allclose(oracle.factor_update_masked(X, G, F, n, lam, full),
+                                   oracle.factor_update(X, G, F, n, lam), rtol=1e-10, atol=1e-12)
+    # a row with no observed entry is pulled to zero by the ridge term alone
+    obs = np.ones(X.shape, bool)
+    obs[:, 2, :] = False
+    A1 = oracle.factor_update_masked(X, G, F, 1, lam, workloads.pack_mask(obs))
+    assert np.all(A1[2] == 0.0)
+    # the update minimises the masked objective over A(n): moving any row off it
+    # raises the loss
+    obs = np.random.default_rng(64).random(X.shape) > 0.25
+    mk = workloads.pack_mask(obs)
+    A0 = oracle.factor_update_masked(X, G, F, 0, lam, mk)
+    Fa = [A0, F[1], F[2]]
+    base = oracle.loss(X, G, Fa, lam, mk)[0]
+    rng = np.random.default_rng(65)
+    for _ in range(5):
+        Fb = [A0 + 1e-3 * rng.standard_normal(A0.shape), F[1], F[2]]
+        assert oracle.loss(X, G, Fb, lam, mk)[0] > base
