@@ -307,15 +307,15 @@ def main():
             Fi = list(F)
             Gi = G_e
             for n in range(len(Fi)):
-                Fi[n] = tk.factor_update(X, Gi, Fi, n, lam, check=False)
+                Fi[n] = tk.factor_update(X, Gi, Fi, n, lam, check=False, mask=mask)
             if core == "exact":
-                return tk.core_update_exact(X, Fi, lam, check=False)
+                return tk.core_update_exact(X, Fi, lam, check=False, mask=mask)
             return tk.core_update_sketched(X, Fi, lam, s, seed=cfg["seed"], counter=99,
                                            precision=args.precision, refine_max=args.refine_max,
-                                           refine_tol=1e-13, check=False)
+                                           refine_tol=1e-13, check=False, mask=mask)
         als_ms = {}
-        # the factor update is for fully observed tensors; no ALS timing for masked workloads
-        for core in (("exact", "sketched") if mask is None else ()):
+        # with a mask every update (factors and core) fits the observed entries only
+        for core in ("exact", "sketched"):
             als_iter(core)
             torch.cuda.synchronize()
             e0.record()

@@ -347,10 +347,19 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
  *   a_i = argmin_y ||y K_n - x_(n),i||^2 + lambda ||y||^2,
  *   K_n = G_(n) ((x)_{m != n} A(m))^T,
  * i.e. A(n) = X_(n) K_n^T (K_n K_n^T + lambda I)^{-1}.  One streaming pass over
- * X.  Fully observed tensors only (a mask gives TK_E_ARG).
+ * X.  With a mask (tensor completion, Sec. 4.2) each row solves its ridge
+ * problem over its observed entries only,
+ *   a_i = (sum_{j obs} k_j k_j^T + lambda I)^{-1} sum_{j obs} x_ij k_j,
+ * with k_j the column j of K_n: one pass over X and the mask that accumulates
+ * every row's R_n x R_n Gram in FP64, then a FP64 Cholesky per row (order >= 2,
+ * else TK_E_SHAPE; unobserved entries of X are never read, so they may hold
+ * anything, NaN included).  A row whose system is not positive definite
+ * (lambda = 0 with too few observations) sets dev_status to TK_E_NOT_SPD.
  *   core        device, prod(ranks) elements of p->dtype
  *   factor_out  device, dims[mode] x ranks[mode] of p->dtype (may alias
  *               p->factors[mode]; it is written last)
+ * Workspace: tucker_workspace_bytes(p, NULL, TK_CALL_FACTOR), which depends on
+ * whether p->mask is set.
  */
 tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mode,
                                void* factor_out, int32_t* dev_status, void* ws,

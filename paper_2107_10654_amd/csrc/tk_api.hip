@@ -356,10 +356,14 @@ struct FactorWS {
   double* scratch;
 };
 
-void carve_factor(Carver& c, const Geom& g, FactorWS& w) {
-  w.C = c.take<double>(g.total_rr);
+void carve_factor(Carver& c, const Geom& g, FactorWS& w, bool masked) {
   w.A64 = c.take<double>(g.total_q);
   w.G64 = c.take<double>(g.d);
+  if (masked) {  // the observed-entries pass needs only its own partials
+    w.scratch = c.take<double>(factor_masked_bytes(g) / sizeof(double) + 1);
+    return;
+  }
+  w.C = c.take<double>(g.total_rr);
   w.Z = c.take<double>(g.d);
   w.Z2 = c.take<double>(g.d);
   int64_t maxI = 1;
@@ -489,7 +493,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
     }
     case TK_CALL_FACTOR: {
       FactorWS w;
-      carve_factor(c, g, w);
+      carve_factor(c, g, w, p->mask != nullptr);
       break;
     }
     case TK_CALL_LOSS: {
@@ -1089,14 +1093,23 @@ tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mo
   if (stt != TK_OK) return stt;
   if (!core || !factor_out || !dev_status || !ws) return TK_E_ARG;
   if (mode < 0 || mode >= p->order) return TK_E_ARG;
-  if (p->mask) return TK_E_ARG;
-  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_FACTOR)) return TK_E_WORKSPACE;
   const Geom g = make_geom(p);
+  if (p->mask && !factor_masked_ok(g)) return TK_E_SHAPE;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_FACTOR)) return TK_E_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   Carver c(ws);
   FactorWS w;
-  carve_factor(c, g, w);
+  carve_factor(c, g, w, p->mask != nullptr);
   launch_fill_i32(1, 0, dev_status, st);
+  if (p->mask) {
+    // row-wise ridge over the observed entries (one pass over X and the mask)
+    for (int n = 0; n < g.order; ++n)
+      launch_cast_in(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.A64 + g.qoff[n], st);
+    launch_cast_in(g.d, core, p->dtype, w.G64, st);
+    launch_factor_masked(g, mode, p->X, p->dtype, p->mask, w.A64, w.G64, p->lambda, factor_out,
+                         dev_status, w.scratch, st);
+    return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+  }
   launch_gram_modes(g, p->factors, p->dtype, w.C, st);
   for (int n = 0; n < g.order; ++n)
     launch_cast_in(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.A64 + g.qoff[n], st);

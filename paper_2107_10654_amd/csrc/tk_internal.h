@@ -330,6 +330,14 @@ void launch_loss_final(const double* part_sq, const double* part_cnt, int64_t np
                        hipStream_t st);
 void launch_unfold_contract(const double* U, const double* V, int64_t P, int64_t I, int64_t A,
                             int64_t Q, double* out, hipStream_t st);
+// Factor update over the observed entries (tk_factor_masked.hip): order >= 2;
+// scratch holds factor_masked_bytes(g) bytes; A64 the FP64 factors at
+// geom.qoff, G64 the FP64 core; out I_n x R_n of dt.
+bool factor_masked_ok(const Geom& g);
+size_t factor_masked_bytes(const Geom& g);
+void launch_factor_masked(const Geom& g, int n, const void* X, tk_dtype dt, const uint32_t* mask,
+                          const double* A64, const double* G64, double lambda, void* out,
+                          int32_t* status, void* scratch, hipStream_t st);
 void launch_factor_solve(const double* KKt, const double* rhs, int64_t I, int R, double lambda,
                          void* out, tk_dtype dt, int32_t* status, hipStream_t st);
 

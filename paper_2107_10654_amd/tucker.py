@@ -357,10 +357,12 @@ def core_update_exact(X, factors, lam, mask=None, check=True, out=None):
     return core
 
 
-def factor_update(X, G, factors, mode, lam, out=None, check=True):
-    """Row-wise ridge update of factor `mode` (Alg. 2); returns the new factor."""
+def factor_update(X, G, factors, mode, lam, out=None, check=True, mask=None):
+    """Row-wise ridge update of factor `mode` (Alg. 2); returns the new factor.
+    With ``mask`` (int32 view of the LSB-first bit mask) every row is fitted to
+    its observed entries only."""
     lib = L.load()
-    p = make_problem(X, factors, lam)
+    p = make_problem(X, factors, lam, mask)
     _check_tensor(G, "core", X.dtype)
     dev = X.device
     A = out if out is not None else torch.empty_like(factors[mode])
@@ -391,8 +393,9 @@ def loss(X, G, factors, lam, mask=None, sync=True):
 
 
 def als(X, G0, factors0, lam, iters, core="exact", samples=None, seed=0, precision="f64",
-        record=None):
+        record=None, mask=None):
     """Alg. 2 on the GPU: factor updates 1..N then the core (exact or sampled, counter = iteration).
+    With ``mask`` every update fits the observed entries only.
 
     Returns (G, factors, history) with history[k] = (loss, rmse) after iteration k.
     """
@@ -401,15 +404,15 @@ def als(X, G0, factors0, lam, iters, core="exact", samples=None, seed=0, precisi
     hist = []
     for it in range(iters):
         for n in range(len(F)):
-            F[n] = factor_update(X, G, F, n, lam)
+            F[n] = factor_update(X, G, F, n, lam, mask=mask)
             if record is not None:
-                record.append(("factor", it, n, loss(X, G, F, lam)))
+                record.append(("factor", it, n, loss(X, G, F, lam, mask=mask)))
         if core == "exact":
-            G = core_update_exact(X, F, lam)
+            G = core_update_exact(X, F, lam, mask=mask)
         else:
             G = core_update_sketched(X, F, lam, samples, seed=seed, counter=it,
-                                     precision=precision)
-        Lv, sq, cnt = loss(X, G, F, lam)
+                                     precision=precision, mask=mask)
+        Lv, sq, cnt = loss(X, G, F, lam, mask=mask)
         hist.append((Lv, (sq / cnt) ** 0.5))
         if record is not None:
             record.append(("core", it, -1, (Lv, sq, cnt)))

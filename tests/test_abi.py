@@ -122,11 +122,14 @@ def test_host_argument_errors(lib):
     bad = _problem((64, 64, 64), (4, 4, 4), lam=-1.0)
     assert f(ctypes.byref(bad), ctypes.byref(o), None, None, None, None, core, None, None, ws, 16,
              st) == 1
-    # factor update: bad mode; mask unsupported
+    # factor update: bad mode; a masked order-1 problem; too small a workspace
     assert lib.tucker_factor_update(ctypes.byref(p), core, 3, core, core, ws, 16, st) == 1
+    pm = _problem((64,), (4,))
+    pm.mask = 0x3000
+    assert lib.tucker_factor_update(ctypes.byref(pm), core, 0, core, core, ws, 16, st) == 2
     pm = _problem((64, 64, 64), (4, 4, 4))
     pm.mask = 0x3000
-    assert lib.tucker_factor_update(ctypes.byref(pm), core, 0, core, core, ws, 16, st) == 1
+    assert lib.tucker_factor_update(ctypes.byref(pm), core, 0, core, core, ws, 16, st) == 4
     # adjoint: frozen samples, core and cotangent are required
     fb = (ctypes.c_void_p * 3)(0x10, 0x10, 0x10)
     adj = lib.tucker_core_update_sketched_adjoint
