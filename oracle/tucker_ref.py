@@ -152,6 +152,24 @@ def s_theory(d, eps, delta, beta_prime=0.5):
                          * max(420.0 * math.log(4.0 * d / delta), 1.0 / (delta * eps))))
 
 
+def ridge_row_mass(d, d_eff_lower):
+    """c = min{1, d - d'_eff}: the unnormalised mass of each of the d ridge rows
+    in the augmented distribution D(l, d'_eff) (Sec. 3, its definition), whose
+    data rows carry the overestimates normalised to total mass d.  Clamped at 0
+    (a lower bound d'_eff above d leaves the ridge rows no mass)."""
+    return min(1.0, max(0.0, float(d) - float(d_eff_lower)))
+
+
+def s_theory_augmented(d, eps, delta, d_eff_lower=0.0):
+    """Alg. 1's sample count with beta' = 1/(rank/d + c) = 1/(1 + c) for a
+    full-rank design (Cor. 3.3 with the leverage scores as overestimates):
+    ceil(4 d (1 + c) max{420 ln(4d/delta), 1/(delta eps)}); c = 1 (d'_eff = 0)
+    gives the count of ``s_theory``."""
+    c = ridge_row_mass(d, d_eff_lower)
+    return int(math.ceil(4.0 * d * (1.0 + c)
+                         * max(420.0 * math.log(4.0 * d / delta), 1.0 / (delta * eps))))
+
+
 # --------------------------------------------------------------------------
 # Integer CDF tables and product-distribution sampling
 # (Lemma 4.1 product law; Alg. 3 sampler; proof of Thm 4.2: per-mode CDFs
@@ -172,21 +190,9 @@ def cdf_table(scores, q_bits=Q_BITS):
     return w, C
 
 
-def sample(tables, s, seed, counter, problem=0):
-    """Draw s multi-indices i.i.d. from the product of the per-mode distributions.
-
-    tables : list of (w, C) per mode from ``cdf_table``.
-    Random words: Philox4x64-10 with key (seed, 0) and counter
-    (t, counter, problem, block); word j of block b drives mode 4b + j.
-    Mode n draws u = floor(r * W_n / 2^64) and takes the first row j with
-    C_j > u (inverse-CDF by binary search).  Draws are with replacement (Alg. 1).
-
-    Returns idx (N, s) int32 and weight (s,) float64, where
-    weight_t = (prod_n W_n / w_{i_n}) / s  = 1 / (s * P(row t))
-    so that sum_t weight_t k_t k_t^T is the sketched Gram (S K)^T (S K) of Alg. 1
-    (sketch entries 1/sqrt(P(j) s)).  The product is taken in mode order,
-    one IEEE operation at a time.
-    """
+def _product_draws(tables, s, seed, counter, problem):
+    """Indices of s product-distribution draws and prod_n W_n / w_{i_n} per draw
+    (the product in mode order, one IEEE operation at a time)."""
     N = len(tables)
     t = np.arange(s, dtype=np.uint64)
     idx = np.empty((N, s), dtype=np.int32)
@@ -205,7 +211,74 @@ def sample(tables, s, seed, counter, problem=0):
         w, C = tables[n]
         W = np.float64(C[-1])
         acc = acc * (W / w[idx[n]].astype(np.float64))
-    weight = acc / np.float64(s)
+    return idx, acc
+
+
+def sample(tables, s, seed, counter, problem=0):
+    """Draw s multi-indices i.i.d. from the product of the per-mode distributions.
+
+    tables : list of (w, C) per mode from ``cdf_table``.
+    Random words: Philox4x64-10 with key (seed, 0) and counter
+    (t, counter, problem, block); word j of block b drives mode 4b + j.
+    Mode n draws u = floor(r * W_n / 2^64) and takes the first row j with
+    C_j > u (inverse-CDF by binary search).  Draws are with replacement (Alg. 1).
+
+    Returns idx (N, s) int32 and weight (s,) float64, where
+    weight_t = (prod_n W_n / w_{i_n}) / s  = 1 / (s * P(row t))
+    so that sum_t weight_t k_t k_t^T is the sketched Gram (S K)^T (S K) of Alg. 1
+    (sketch entries 1/sqrt(P(j) s)).  The product is taken in mode order,
+    one IEEE operation at a time.
+    """
+    idx, acc = _product_draws(tables, s, seed, counter, problem)
+    return idx, acc / np.float64(s)
+
+
+#: Philox block (counter word 3) of the augmented distribution's branch draws;
+#: blocks 0 and 1 drive the modes (orders up to 8).
+AUG_BLOCK = 2
+
+
+def coin_weights(d, d_eff_lower):
+    """Integer weights of the two branches of D(l, d'_eff): the data rows
+    (total mass d after normalisation) get D = 2^Q, the d ridge rows (total
+    mass d c) get C = ceil(c 2^Q), so a draw is a ridge row with probability
+    C / (D + C) ~ c / (1 + c)."""
+    c = ridge_row_mass(d, d_eff_lower)
+    return 2 ** Q_BITS, int(math.ceil(c * float(2 ** Q_BITS)))
+
+
+def sample_augmented(tables, ranks, s, seed, counter, d_eff_lower=0.0, problem=0):
+    """s i.i.d. draws from the augmented distribution D(l, d'_eff) of Alg. 1.
+
+    Each draw first flips the branch coin (Sec. 3: branch on the two index
+    subsets, then sample the conditional): with the Philox words of block
+    AUG_BLOCK, u = floor(r_0 (D + C) / 2^64) < D picks a data row, drawn from
+    the product distribution exactly as ``sample`` draws it; otherwise ridge
+    row k = floor(r_1 d / 2^64), uniform over the d rows sqrt(lam) e_k.
+    A ridge draw is stored as idx[n][t] = I_n + k_n, the digits k_n of k
+    (row-major over the ranks).  weight_t = 1 / (s P(j_t)):
+      data:  ((prod_n W_n / w_{i_n}) * ((D + C) / D)) / s
+      ridge: (((D + C) / C) * d) / s
+    each factor one IEEE operation, in this order.
+    """
+    N = len(tables)
+    dims = [len(C) for _, C in tables]
+    d = int(np.prod(ranks))
+    D, Cw = coin_weights(d, d_eff_lower)
+    idx, acc = _product_draws(tables, s, seed, counter, problem)
+    t = np.arange(s, dtype=np.uint64)
+    words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(AUG_BLOCK), seed, 0)
+    u = mulhi64(words[0], np.uint64(D + Cw))
+    ridge = u >= np.uint64(D)
+    k = mulhi64(words[1], np.uint64(d)).astype(np.int64)
+    rem = k.copy()
+    for n in range(N - 1, -1, -1):
+        dig = rem % ranks[n]
+        rem //= ranks[n]
+        idx[n] = np.where(ridge, dims[n] + dig, idx[n]).astype(np.int32)
+    w_data = (acc * (np.float64(D + Cw) / np.float64(D))) / np.float64(s)
+    w_ridge = ((np.float64(D + Cw) / np.float64(Cw)) * np.float64(d)) / np.float64(s) if Cw else 0.0
+    weight = np.where(ridge, w_ridge, w_data)
     return idx, weight
 
 
@@ -261,6 +334,58 @@ def core_update_sketched(X, factors, lam, idx, weight, mask=None):
     L = np.linalg.cholesky(gram + lam * np.eye(d))
     g = np.linalg.solve(L.T, np.linalg.solve(L, rhs))
     return g.reshape([A.shape[1] for A in factors])
+
+
+def augmented_rows(X, factors, lam, idx, mask=None):
+    """Rows of the augmented design [K; sqrt(lam) I] and response [vec X; 0] at
+    the draws idx of ``sample_augmented`` (Alg. 1 line Abar, bbar): data draws
+    give (k_t, x_t), with x_t = 0 and k_t = 0 on unobserved entries (they
+    contribute nothing); ridge draws give (sqrt(lam) e_k, 0)."""
+    X = np.asarray(X)
+    idx = np.asarray(idx)
+    dims = X.shape
+    ranks = [A.shape[1] for A in factors]
+    d = int(np.prod(ranks))
+    s = idx.shape[1]
+    ridge = idx[0] >= dims[0]
+    rows = np.zeros((s, d))
+    x = np.zeros(s)
+    data = np.nonzero(~ridge)[0]
+    if len(data):
+        xd, obs = sampled_entries(X, idx[:, data], mask)
+        rows[data] = kron_rows(factors, idx[:, data]) * obs[:, None]
+        x[data] = xd * obs
+    rid = np.nonzero(ridge)[0]
+    if len(rid):
+        k = np.zeros(len(rid), dtype=np.int64)
+        for n in range(len(dims)):
+            k = k * ranks[n] + (idx[n, rid].astype(np.int64) - dims[n])
+        rows[rid, k] = math.sqrt(lam)
+    return rows, x
+
+
+def core_update_sketched_augmented(X, factors, lam, idx, weight, mask=None):
+    """Alg. 1's solve on augmented draws: argmin_g ||S Abar g - S bbar||^2 by its
+    normal equations (sum_t w_t abar_t abar_t^T) g = sum_t w_t bbar_t abar_t
+    (Cholesky); the ridge enters only through the sampled rows sqrt(lam) e_k."""
+    rows, x = augmented_rows(X, factors, lam, idx, mask)
+    w = np.asarray(weight, dtype=np.float64)
+    gram = (rows * w[:, None]).T @ rows
+    rhs = rows.T @ (w * x)
+    L = np.linalg.cholesky(gram)
+    g = np.linalg.solve(L.T, np.linalg.solve(L, rhs))
+    return g.reshape([A.shape[1] for A in factors])
+
+
+def fast_core_tensor_update_augmented(X, factors, lam, s, seed, counter, d_eff_lower=0.0,
+                                      mask=None, problem=0):
+    """Alg. 3 with Alg. 1 taken literally: factor leverage scores as the
+    overestimate, draws from the augmented distribution, solve on S Abar."""
+    tables = [cdf_table(leverage_scores(A)) for A in factors]
+    ranks = [A.shape[1] for A in factors]
+    idx, weight = sample_augmented(tables, ranks, s, seed, counter, d_eff_lower, problem)
+    G = core_update_sketched_augmented(X, factors, lam, idx, weight, mask)
+    return G, idx, weight, tables
 
 
 def fast_core_tensor_update(X, factors, lam, s, seed, counter, mask=None, problem=0):
