@@ -92,6 +92,18 @@ typedef struct {
                                 kernel done, 5 assembly and right side
                                 done, 6 Cholesky done, 7 first solve done, 8 refinement done,
                                 9 end */
+  int32_t augmented;       /* 0: the sketched Gram plus the exact lambda I (unbiased, since
+                              E[sketched Gram] = K^T K).  1: Alg. 1 taken literally: draws
+                              from the augmented distribution D(l, d'_eff) of Sec. 3 over
+                              the rows of [K; sqrt(lambda) I] (a branch coin, then a product
+                              draw or a uniform ridge row; see tucker_sample_augmented) and
+                              the solve of min ||S Abar g - S bbar||, in which lambda enters
+                              only through the sampled ridge rows. */
+  double d_eff_lower;      /* augmented = 1: the lower bound d'_eff of the effective
+                              dimension; each ridge row has mass c = min{1, d - d'_eff}
+                              (clamped at 0), so 0 gives c = 1.  With num_samples <= 0 the
+                              count is ceil(4 d (1 + c) max{420 ln(4d/delta), 1/(delta eps)})
+                              (Cor. 3.3: beta' = 1 / (1 + c)). */
 } tk_sketch_opts;
 
 /* Which call tucker_workspace_bytes() sizes. */
@@ -112,6 +124,12 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
 /* Sample count of Alg. 1 with beta' = 1/2 (Cor. 3.3), as used when
  * num_samples <= 0. */
 int64_t tucker_sample_count(int64_t d, double eps, double delta);
+
+/* Sample count of Alg. 1 for draws from the augmented distribution with lower
+ * bound d_eff_lower (Cor. 3.3 with the leverage scores as overestimates:
+ * beta' = 1/(1 + c), c = min{1, d - d_eff_lower} clamped at 0):
+ * ceil(4 d (1 + c) max{420 ln(4d/delta), 1/(delta eps)}); 0 on bad input. */
+int64_t tucker_sample_count_augmented(int64_t d, double eps, double delta, double d_eff_lower);
 
 /*
  * Factor leverage scores and sampling tables -- Alg. 3, first step; the
@@ -156,6 +174,33 @@ tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf,
                         double* weight, void* stream);
 
 /*
+ * Draws from the augmented distribution D(l, d'_eff) of Alg. 1 (Sec. 3: the
+ * data rows of [K; sqrt(lambda) I] with the product of the factor leverage
+ * scores, normalised to mass d, and the d ridge rows with mass c each,
+ * c = min{1, d - d_eff_lower} clamped at 0).  Per draw a branch coin, then a
+ * product draw (exactly the draw tucker_sample makes for the same t) or a
+ * uniform ridge row:
+ *   Philox words of block 2 (counter (t, counter, problem, 2)): with integer
+ *   branch weights D = 2^TK_Q_BITS and C = ceil(c 2^TK_Q_BITS),
+ *   u = floor(r_0 (D + C) / 2^64) < D keeps the data draw; otherwise ridge row
+ *   k = floor(r_1 d / 2^64), d = prod(ranks).
+ *   idx     device int32 [order][s]: data draws as tucker_sample; a ridge draw
+ *           stores idx[n*s + t] = dims[n] + k_n, k_n the row-major digits of k
+ *           over the ranks (so every entry lies in [dims[n], dims[n] + ranks[n]))
+ *   weight  device double [s], 1/(s P(j)) with the factors in this order, one
+ *           IEEE operation each: data ((prod_n W_n / w_{i_n}) * ((D + C) / D)) / s,
+ *           ridge (((D + C) / C) * d) / s
+ *   ranks   host [order], 1..TK_MAX_RANK, prod <= 16384; other arguments as
+ *           tucker_sample.
+ * With C = 0 (d_eff_lower >= d) every draw is a data draw and the output equals
+ * tucker_sample's bit for bit.
+ */
+tk_status tucker_sample_augmented(int32_t order, const int64_t* dims, const int32_t* ranks,
+                                  const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
+                                  uint64_t problem, double d_eff_lower, int32_t* idx,
+                                  double* weight, void* stream);
+
+/*
  * Sampled core-tensor update -- Alg. 3 FastCoreTensorUpdate calling Alg. 1
  * ApproximateRidgeRegression; normal equations as in the proof of Thm 4.2,
  * with the ridge term added to the sketched Gram:
@@ -175,6 +220,13 @@ tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf,
  *                      [5..7] reserved (0).
  * Internally the rows are whitened per mode (q_i = L_n^{-1} a_i^T); the
  * solution is mapped back exactly, so the result is the g above.
+ * With opts->augmented = 1 the draws come from the augmented distribution
+ * (tucker_sample_augmented; frozen sets may contain its ridge draws) and the
+ * result is Alg. 1's
+ *   g = argmin_g sum_t weight_t (bbar_t - abar_t . g)^2,
+ * abar_t = k_t and bbar_t = x_t for data draws (0 and 0 on unobserved
+ * entries), abar_t = sqrt(lambda) e_k and bbar_t = 0 for ridge draws: no
+ * lambda I is added.
  */
 tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts* opts,
                                       const int32_t* idx_in, const double* weight_in,
@@ -227,6 +279,9 @@ tk_status tucker_core_update_sketched_noalloc(const tk_problem* p, const tk_sket
  *   M_out        device double [d * d], d = prod(ranks), row-major; entries
  *                with row >= column are written, the others are unspecified
  *   b_out        device double [d]
+ * With opts->augmented = 1 the sample set may hold ridge draws (as written by
+ * tucker_sample_augmented), whose whitened rows sqrt(lambda) W e_k enter the
+ * Gram term, and lambda P is not added.
  * Workspace: tucker_workspace_bytes(p, opts, TK_CALL_SKETCHED).
  */
 tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* opts,
@@ -257,6 +312,7 @@ tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* opts
  *   x_bar         device, dense tensor of p->dtype with the shape of X
  *                 (overwritten: zero except at sampled observed entries), or NULL
  *   dev_info      as for tucker_core_update_sketched (refinement of the v solve)
+ * opts->augmented must be 0 (TK_E_ARG otherwise).
  * Workspace: tucker_workspace_bytes(p, opts, TK_CALL_ADJOINT).  Duplicate
  * samples are accumulated with FP64 (factors) or p->dtype (x_bar) atomics, so
  * results agree with a sequential sum to rounding.

@@ -684,3 +684,21 @@ def normal_equation_residual(X, factors, lam, idx, weight, G, mask=None, chunk=4
         b += rows.T @ (w[a:e] * x[a:e])
         r += rows.T @ (w[a:e] * (x[a:e] - rows @ g))
     return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+def normal_equation_residual_augmented(X, factors, lam, idx, weight, G, mask=None, chunk=4096):
+    """Relative residual ||sum_t w_t abar_t (bbar_t - abar_t . g)|| / ||sum_t w_t bbar_t abar_t||
+    of Alg. 1's normal equations on augmented draws (rows from ``augmented_rows``);
+    zero exactly when G solves them.  Computed in chunks of draws."""
+    idx = np.asarray(idx)
+    w = np.asarray(weight, dtype=np.float64)
+    g = np.asarray(G, dtype=np.float64).reshape(-1)
+    r = np.zeros_like(g)
+    b = np.zeros_like(g)
+    for a in range(0, idx.shape[1], chunk):
+        e = min(idx.shape[1], a + chunk)
+        rows, x = augmented_rows(X, factors, lam, idx[:, a:e], mask)
+        b += rows.T @ (w[a:e] * x)
+        r += rows.T @ (w[a:e] * (x - rows @ g))
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+

@@ -50,6 +50,8 @@ class TkSketchOpts(ctypes.Structure):
         ("refine_max", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
         ("stage_events", ctypes.c_void_p),
+        ("augmented", ctypes.c_int32),
+        ("d_eff_lower", ctypes.c_double),
     ]
 
 
@@ -65,6 +67,12 @@ _SIGNATURES = {
     "tucker_abi_version": (ctypes.c_int32, []),
     "tucker_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "tucker_sample_count": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_double, ctypes.c_double]),
+    "tucker_sample_count_augmented": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_double,
+                                                       ctypes.c_double, ctypes.c_double]),
+    "tucker_sample_augmented": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64),
+                                                 _P(ctypes.c_int32), _vp, ctypes.c_int64,
+                                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                                 ctypes.c_double, _vp, _vp, _vp]),
     "tucker_workspace_bytes": (ctypes.c_size_t, [_P(TkProblem), _P(TkSketchOpts), ctypes.c_int32]),
     "tucker_leverage_scores": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                                 _vp]),

@@ -45,6 +45,15 @@ Geom make_geom(const tk_problem* p) {
   return g;
 }
 
+// Geometry of the augmented row tables: mode n gets R_n more rows (the ridge
+// rows' whitened digits), so qoff and total_q cover I_n + R_n rows per mode.
+// Only the table offsets and ranks of this geometry are used.
+Geom make_geom_aug(const tk_problem* p) {
+  tk_problem q = *p;
+  for (int n = 0; n < p->order; ++n) q.dims[n] += p->ranks[n];
+  return make_geom(&q);
+}
+
 namespace {
 
 constexpr int64_t kMaxD = 16384;
@@ -80,7 +89,22 @@ tk_status check_problem(const tk_problem* p, bool need_x) {
 
 int64_t resolve_samples(const tk_sketch_opts* o, int64_t d) {
   if (o->num_samples > 0) return o->num_samples;
+  if (o->augmented) return tucker_sample_count_augmented(d, o->eps, o->delta, o->d_eff_lower);
   return tucker_sample_count(d, o->eps, o->delta);
+}
+
+// c = min{1, d - d'_eff} clamped at 0: the mass of each ridge row in the
+// augmented distribution (data rows normalised to total mass d).
+double ridge_row_mass(int64_t d, double d_eff_lower) {
+  double c = static_cast<double>(d) - d_eff_lower;
+  if (!(c > 0.0)) c = 0.0;
+  return c < 1.0 ? c : 1.0;
+}
+
+// Integer weight C = ceil(c 2^Q) of the ridge branch (the data branch has 2^Q).
+uint64_t ridge_coin_weight(int64_t d, double d_eff_lower) {
+  return static_cast<uint64_t>(
+      ceil(ridge_row_mass(d, d_eff_lower) * static_cast<double>(1ull << TK_Q_BITS)));
 }
 
 // ---------------------------------------------------------------- workspaces
@@ -132,6 +156,7 @@ struct SketchWS {
   double* relres;
   double* min_pivot;
   unsigned int* missing;
+  double* Q64a;  // augmented whitened row tables (augmented draws only)
 };
 
 // Which optional slices a sampled update (call TK_CALL_SKETCHED) or its adjoint
@@ -142,12 +167,15 @@ struct SketchWS {
 struct SketchNeeds {
   bool rows64;
   bool ttm;
+  int64_t aug_q;  // entries of the augmented row tables (0: plain draws)
 };
 
-SketchNeeds sketch_needs(const Geom& g, int32_t prec, int call) {
+SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, const tk_sketch_opts* o, int call) {
   const bool adj = call == TK_CALL_ADJOINT;
+  const int32_t prec = o->gram_precision;
   return {adj || !resid_small_ok(g) || prec == TK_F64,
-          adj || !core_chain_small_ok(g) || !refine_check_p_ok(g)};
+          adj || !core_chain_small_ok(g) || !refine_check_p_ok(g),
+          o->augmented ? make_geom_aug(p).total_q : 0};
 }
 
 void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w,
@@ -183,6 +211,7 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.relres = c.take<double>(1);
   w.min_pivot = c.take<double>(1);
   w.missing = c.take<unsigned int>(1);
+  w.Q64a = need.aug_q ? c.take<double>(need.aug_q) : nullptr;
 }
 
 // Extra workspace of the adjoint, carved after the sampled-update workspace.
@@ -456,6 +485,15 @@ int64_t tucker_sample_count(int64_t d, double eps, double delta) {
   return static_cast<int64_t>(ceil(8.0 * static_cast<double>(d) * (a > b ? a : b)));
 }
 
+int64_t tucker_sample_count_augmented(int64_t d, double eps, double delta, double d_eff_lower) {
+  if (d < 1 || !(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0) || !isfinite(d_eff_lower))
+    return 0;
+  const double c = ridge_row_mass(d, d_eff_lower);
+  const double a = 420.0 * log(4.0 * static_cast<double>(d) / delta);
+  const double b = 1.0 / (delta * eps);
+  return static_cast<int64_t>(ceil(4.0 * static_cast<double>(d) * (1.0 + c) * (a > b ? a : b)));
+}
+
 size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, int32_t call) {
   if (check_shape(p) != TK_OK) return 0;
   const Geom g = make_geom(p);
@@ -472,7 +510,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(g, opts->gram_precision, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
       break;
     }
     case TK_CALL_ADJOINT: {
@@ -481,7 +519,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(g, opts->gram_precision, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
       AdjWS a;
       carve_adjoint(c, g, s, a);
       break;
@@ -542,6 +580,31 @@ tk_status tucker_sample(int32_t order, const int64_t* dims, const uint64_t* cdf,
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
+tk_status tucker_sample_augmented(int32_t order, const int64_t* dims, const int32_t* ranks,
+                                  const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
+                                  uint64_t problem, double d_eff_lower, int32_t* idx,
+                                  double* weight, void* stream) {
+  if (order < 1 || order > kMaxOrder || !dims || !ranks || !cdf || !idx || !weight || s < 1 ||
+      !isfinite(d_eff_lower))
+    return TK_E_ARG;
+  tk_problem p;
+  memset(&p, 0, sizeof(p));
+  p.order = order;
+  int64_t d = 1;
+  for (int n = 0; n < order; ++n) {
+    if (dims[n] < 1 || dims[n] > (int64_t(1) << 31) - 1 - kMaxRank) return TK_E_SHAPE;
+    if (ranks[n] < 1 || ranks[n] > kMaxRank) return TK_E_SHAPE;
+    p.dims[n] = dims[n];
+    p.ranks[n] = ranks[n];
+    d *= ranks[n];
+    if (d > kMaxD) return TK_E_SHAPE;
+  }
+  const Geom g = make_geom(&p);
+  launch_sample(g, cdf, s, seed, counter, problem, idx, weight, static_cast<hipStream_t>(stream),
+                1, ridge_coin_weight(d, d_eff_lower));
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
 }  // extern "C"
 
 namespace tk {
@@ -563,6 +626,13 @@ struct SketchRun {
   // the FP64 sample rows are read by the FP64 Gram, the large-d vector passes
   // and the adjoint; the small-d passes read the factor tables instead
   bool want_rows64 = true;
+  // Augmented draws (Alg. 1 over [K; sqrt(lambda) I]): the sample-side kernels
+  // read the augmented tables in geometry ga, and the ridge enters only
+  // through the sampled ridge rows, so no lambda P is added (lam_sys = 0).
+  bool aug = false;
+  Geom ga;
+  const double* q64s = nullptr;  // whitened row tables the sample-side kernels read
+  double lam_sys = 0.0;          // lambda of the assembled and refined system
   void stage(int k) const {
     if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
   }
@@ -571,6 +641,12 @@ struct SketchRun {
 tk_status check_sketch_args(const tk_problem* p, const tk_sketch_opts* o, int64_t& s) {
   if (o->gram_precision != TK_F64 && o->gram_precision != TK_F32 && o->gram_precision != TK_BF16)
     return TK_E_DTYPE;
+  if (o->augmented != 0 && o->augmented != 1) return TK_E_ARG;
+  if (o->augmented && !isfinite(o->d_eff_lower)) return TK_E_ARG;
+  if (o->augmented) {
+    for (int n = 0; n < p->order; ++n)
+      if (p->dims[n] > (int64_t(1) << 31) - 1 - kMaxRank) return TK_E_SHAPE;
+  }
   if (o->refine_max < 0 || o->refine_max > 1000 || !(o->refine_tol >= 0.0)) return TK_E_ARG;
   const Geom g = make_geom(p);
   s = resolve_samples(o, g.d);
@@ -597,6 +673,7 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
   launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
                   w.lev.Q64, w.lev.Q32, R.status, st);
+  if (R.aug) launch_aug_tables(g, R.ga, w.lev.Q64, w.lev.Linv, p->lambda, w.Q64a, st);
   R.stage(1);
   // 2. samples (Alg. 3 sampler) or the frozen set
   R.idx = idx_in;
@@ -604,7 +681,8 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   if (!idx_in) {
     int32_t* io = idx_out ? idx_out : w.idx;
     double* wo = weight_out ? weight_out : w.weight;
-    launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st);
+    launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st,
+                  R.aug ? 1 : 0, R.aug ? ridge_coin_weight(g.d, R.o->d_eff_lower) : 0);
     R.idx = io;
     R.weight = wo;
   } else if (idx_out) {
@@ -616,8 +694,8 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   R.stage(2);
   // 3. sampled entries (x_t, mask) and effective weights; sample rows
   launch_gather(g, p->X, p->dtype, p->mask, R.idx, R.weight, R.s, w.weff, w.xw, w.missing,
-                R.status, st);
-  launch_pregather(g, R.idx, w.weff, R.s, w.lev.Q64, R.want_rows64 ? w.rows64 : nullptr, w.rows32,
+                R.status, st, R.aug ? 1 : 0);
+  launch_pregather(R.ga, R.idx, w.weff, R.s, R.q64s, R.want_rows64 ? w.rows64 : nullptr, w.rows32,
                    st);
   R.stage(3);
   return TK_OK;
@@ -629,7 +707,7 @@ void sketch_factor(SketchRun& R) {
   SketchWS& w = R.w;
   // 5. right-hand side sum_t w_t x_t q_t (FP64)
   if (resid_small_ok(g))
-    launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
+    launch_resid_small(R.ga, R.idx, R.q64s, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
   else if (resid_big_ok(g))
     launch_resid_big(g, w.rows64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr, R.st);
@@ -650,7 +728,7 @@ tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   // 4. sketched Gram on MFMA, plus lambda P
   launch_gram(R.g, R.pl, R.w.rows64, R.w.rows32, R.w.weff, R.s, R.w.gpart, R.st);
   R.stage(4);
-  launch_assemble(R.g, R.pl, R.w.gpart, R.w.lev.P, p->lambda, R.w.M, R.st);
+  launch_assemble(R.g, R.pl, R.w.gpart, R.w.lev.P, R.lam_sys, R.w.M, R.st);
   sketch_factor(R);
   return TK_OK;
 }
@@ -677,7 +755,7 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
     R.stage(7);
     for (int k = 0; k <= iters; ++k) {
       const int64_t np =
-          launch_resid_small_parts(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.done, st);
+          launch_resid_small_parts(R.ga, R.idx, R.q64s, xw, w.weff, h, R.s, w.vpart, w.done, st);
       launch_refine_step_small(g, w.vpart, np, w.lev.P, b, lambda, norm_ref,
                                refine ? R.o->refine_tol : -1.0, w.M, w.Linv_diag, h, w.done,
                                w.steps, w.relres, k < iters ? 1 : 0, st);
@@ -692,7 +770,7 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   R.stage(7);
   for (int k = 0; k <= iters; ++k) {
     if (resid_small_ok(g)) {
-      launch_resid_small(g, R.idx, w.lev.Q64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
+      launch_resid_small(R.ga, R.idx, R.q64s, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
     } else if (resid_big_ok(g)) {
       launch_resid_big(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
     } else {
@@ -733,10 +811,14 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_gram(R.g, s, o->gram_precision, 0);
-  const SketchNeeds need = sketch_needs(R.g, o->gram_precision, call);
+  const SketchNeeds need = sketch_needs(p, R.g, o, call);
   R.want_rows64 = need.rows64;
   carve_sketch(c, R.g, s, R.pl, R.w, need, with_partials);
   R.status = dev_status ? dev_status : R.w.status;
+  R.aug = o->augmented != 0;
+  R.ga = R.aug ? make_geom_aug(p) : R.g;
+  R.q64s = R.aug ? R.w.Q64a : R.w.lev.Q64;
+  R.lam_sys = R.aug ? 0.0 : p->lambda;
   return TK_OK;
 }
 
@@ -826,7 +908,7 @@ tk_status tucker_core_update_sketched(const tk_problem* p, const tk_sketch_opts*
   stt = sketch_setup(R, p, idx_in, weight_in, idx_out, weight_out);
   if (stt != TK_OK) return stt;
   // 7. FP64 solve with refinement (low-precision Gram) or one residual check
-  refined_solve(R, p->lambda, nullptr, R.w.xw, R.w.rhs, R.w.h);
+  refined_solve(R, R.lam_sys, nullptr, R.w.xw, R.w.rhs, R.w.h);
   // 8. back from whitened coordinates: g = ((x) L_n^{-T}) h
   const Geom& g = R.g;
   SketchWS& w = R.w;
@@ -858,9 +940,9 @@ tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* o,
   SketchWS& w = R.w;
   launch_gram(g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, R.st);
   R.stage(4);
-  launch_assemble(g, R.pl, w.gpart, w.lev.P, p->lambda, w.M, R.st);
+  launch_assemble(g, R.pl, w.gpart, w.lev.P, R.lam_sys, w.M, R.st);
   if (resid_small_ok(g))
-    launch_resid_small(g, R.idx, w.lev.Q64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
+    launch_resid_small(R.ga, R.idx, R.q64s, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
   else if (resid_big_ok(g))
     launch_resid_big(g, w.rows64, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr, R.st);
@@ -883,6 +965,7 @@ tk_status tucker_core_update_sketched_adjoint(const tk_problem* p, const tk_sket
   tk_status stt = check_problem(p, true);
   if (stt != TK_OK) return stt;
   if (!o || !idx || !weight || !core || !core_bar || !factor_bar || !ws) return TK_E_ARG;
+  if (o->augmented) return TK_E_ARG;  // the adjoint is of the Gram + lambda I form
   for (int n = 0; n < p->order; ++n)
     if (!factor_bar[n]) return TK_E_ARG;
   SketchRun R;
@@ -974,9 +1057,9 @@ tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_
   for (int k = 0; k < count; ++k) {
     SketchRun& R = runs[k];
     const tk_problem* p = &probs[k];
-    launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, p->lambda, R.w.M, st);
+    launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, R.lam_sys, R.w.M, st);
     sketch_factor(R);
-    refined_solve(R, p->lambda, nullptr, R.w.xw, R.w.rhs, R.w.h);
+    refined_solve(R, R.lam_sys, nullptr, R.w.xw, R.w.rhs, R.w.h);
     if (core_chain_small_ok(R.g)) {
       launch_core_chain_small(R.g, R.w.h, R.w.lev.Linv, true, core_out[k], p->dtype, st);
     } else {

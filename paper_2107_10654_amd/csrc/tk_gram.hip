@@ -279,20 +279,28 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Geom g, const T* __restr
                                                         const double* __restrict__ weight,
                                                         int64_t s, double* __restrict__ weff,
                                                         double* __restrict__ xw,
-                                                        unsigned int* missing, int32_t* status) {
+                                                        unsigned int* missing, int32_t* status,
+                                                        int ridge_ok) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   bool miss = false, bad = false;
   if (t < s) {
     int64_t flat = 0;
+    int nridge = 0;  // modes whose index lies in the ridge range [I_n, I_n + R_n)
     for (int n = 0; n < g.order; ++n) {
       const int32_t i = idx[static_cast<int64_t>(n) * s + t];
-      if (i < 0 || i >= g.dims[n]) bad = true;
+      if (ridge_ok && i >= g.dims[n] && i < g.dims[n] + g.ranks[n])
+        ++nridge;
+      else if (i < 0 || i >= g.dims[n])
+        bad = true;
       flat += static_cast<int64_t>(i) * g.strides[n];
     }
+    if (nridge != 0 && nridge != g.order) bad = true;  // a ridge draw has all digits in range
     double w = weight[t];
     double x = 0.0;
     if (bad) {
       w = 0.0;
+    } else if (nridge) {
+      x = 0.0;  // ridge row: response 0, never masked
     } else {
       x = static_cast<double>(X[flat]);
       if (mask && !((mask[flat >> 5] >> (flat & 31)) & 1u)) {
@@ -1331,17 +1339,17 @@ void launch_assemble(const Geom& g, const GramPlan& pl, const void* partials, co
 
 void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,
                    const int32_t* idx, const double* weight, int64_t s, double* weff, double* xw,
-                   unsigned int* missing, int32_t* status, hipStream_t st) {
+                   unsigned int* missing, int32_t* status, hipStream_t st, int ridge) {
   if (s <= 0) return;
   dim3 grid(static_cast<unsigned>(cdiv(s, kBlock)));
   if (dt == TK_F64)
     hipLaunchKernelGGL(gather_kernel<double>, grid, dim3(kBlock), 0, st, g,
                        static_cast<const double*>(X), mask, idx, weight, s, weff, xw, missing,
-                       status);
+                       status, ridge);
   else
     hipLaunchKernelGGL(gather_kernel<float>, grid, dim3(kBlock), 0, st, g,
                        static_cast<const float*>(X), mask, idx, weight, s, weff, xw, missing,
-                       status);
+                       status, ridge);
 }
 
 namespace {

@@ -76,8 +76,18 @@ void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, co
                       hipStream_t st);
 
 // Sampler (tk_sample.hip).
+// aug != 0: augmented draws over [K; sqrt(lambda) I] with ridge branch weight
+// coin_c (tk_sample.hip); g.ranks and g.d give the ridge rows' digits.
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
-                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st);
+                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug = 0,
+                   uint64_t coin_c = 0);
+
+// Whitened row tables of the augmented design (tk_leverage.hip): in the
+// geometry ga (dims I_n + R_n), rows i < I_n of mode n copy Q64's rows and
+// row I_n + k is column k of L_n^{-1}, times sqrt(lambda) in mode 0, so that
+// the Kronecker row of ridge draw (I_n + k_n)_n is sqrt(lambda) W e_k.
+void launch_aug_tables(const Geom& g, const Geom& ga, const double* Q64, const double* Linv,
+                       double lambda, double* Q64a, hipStream_t st);
 
 // Per-sample factor rows (chunk-transposed, see kRowChunk): q^(n)_{i_n}[r] at row
 // position soff_n + r; rows32 the same in FP32 with mode 0 scaled by sqrt(weff_t).
@@ -86,9 +96,11 @@ void launch_pregather(const Geom& g, const int32_t* idx, const double* weff, int
                       const double* Q64, double* rows64, float* rows32, hipStream_t st);
 
 // Gather x_t and mask bits: weff_t = w_t [obs], xw_t = w_t x_t [obs].
+// ridge != 0: draws with every i_n in [I_n, I_n + R_n) are ridge rows
+// (x_t = 0, always observed).
 void launch_gather(const Geom& g, const void* X, tk_dtype dt, const uint32_t* mask,
                    const int32_t* idx, const double* weight, int64_t s, double* weff, double* xw,
-                   unsigned int* missing, int32_t* status, hipStream_t st);
+                   unsigned int* missing, int32_t* status, hipStream_t st, int ridge = 0);
 
 // Sketched Gram of whitened rows (tk_gram.hip).  FP64: partial Grams per
 // sample split (64 x 64 tiles).  FP32 / BF16: stream-K over 256 x 256 tiles

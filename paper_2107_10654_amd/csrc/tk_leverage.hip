@@ -276,6 +276,41 @@ __global__ __launch_bounds__(kBlock) void weight_scan_kernel(Geom g, uint64_t* c
 
 }  // namespace
 
+namespace {
+
+// Rows of the augmented whitened tables: one thread per table entry of ga.
+__global__ __launch_bounds__(kBlock) void aug_tables_kernel(Geom g, Geom ga,
+                                                            const double* __restrict__ Q64,
+                                                            const double* __restrict__ Linv,
+                                                            double sqrt_lambda,
+                                                            double* __restrict__ Q64a) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= ga.total_q) return;
+  int n = 0;
+  while (n + 1 < ga.order && e >= ga.qoff[n + 1]) ++n;
+  const int R = ga.ranks[n];
+  const int64_t i = (e - ga.qoff[n]) / R;
+  const int r = static_cast<int>((e - ga.qoff[n]) % R);
+  double v;
+  if (i < g.dims[n]) {
+    v = Q64[g.qoff[n] + i * R + r];
+  } else {
+    // ridge row k: entry r of L_n^{-1} e_k (L_n^{-1} row-major at roff)
+    const int64_t k = i - g.dims[n];
+    v = Linv[g.roff[n] + static_cast<int64_t>(r) * R + k];
+    if (n == 0) v *= sqrt_lambda;
+  }
+  Q64a[e] = v;
+}
+
+}  // namespace
+
+void launch_aug_tables(const Geom& g, const Geom& ga, const double* Q64, const double* Linv,
+                       double lambda, double* Q64a, hipStream_t st) {
+  hipLaunchKernelGGL(aug_tables_kernel, dim3(static_cast<unsigned>(cdiv(ga.total_q, kBlock))),
+                     dim3(kBlock), 0, st, g, ga, Q64, Linv, sqrt(lambda), Q64a);
+}
+
 void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, double* scores,
                      uint64_t* cdf, double* L, double* Linv, double* P, double* Q64, float* Q32,
                      int32_t* status, hipStream_t st) {

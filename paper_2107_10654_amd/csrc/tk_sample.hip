@@ -9,6 +9,14 @@
 // Key = (seed, 0); counter = (t, counter, problem, b); output word j of block
 // b drives mode 4b + j.  The uniform u = floor(r W_n / 2^64) lies in
 // [0, W_n) and the row is the first j with cdf_j > u.
+//
+// Augmented draws (Alg. 1 taken literally: the augmented distribution of
+// Sec. 3 over the rows of [K; sqrt(lambda) I]) add one branch coin per
+// sample from block kAugBlock: with integer branch weights D = 2^Q (data rows,
+// normalised mass d) and C = ceil(c 2^Q) (ridge rows, mass d c), word 0 gives
+// u = floor(r (D + C) / 2^64) and u >= D selects ridge row
+// k = floor(r' d / 2^64) (word 1), stored as idx[n] = I_n + k_n with k_n the
+// row-major digits of k over the ranks.
 #include "tk_internal.h"
 
 namespace tk {
@@ -41,11 +49,15 @@ __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
 // With STAGE the concatenated tables are first copied to LDS (they are read
 // by every sample's binary searches); the grid strides over the samples.
 constexpr int64_t kSampleLdsRows = 6144;  // 48 KB of uint64 entries
+constexpr uint64_t kAugBlock = 2;          // Philox block of the branch draws (modes use 0, 1)
+constexpr uint64_t kCoinData = 1ull << TK_Q_BITS;
 
+// aug: 0 plain product draws; 1 augmented draws with ridge branch weight coin_c
 template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* __restrict__ cdf,
                                                         int64_t s, uint64_t seed,
                                                         uint64_t counter, uint64_t problem,
+                                                        int aug, uint64_t coin_c,
                                                         int32_t* __restrict__ idx,
                                                         double* __restrict__ weight) {
   extern __shared__ uint64_t cs[];
@@ -96,14 +108,35 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* 
         }
       }
     }
-    weight[t] = acc / static_cast<double>(s);
+    if (!aug) {
+      weight[t] = acc / static_cast<double>(s);
+      continue;
+    }
+    uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, kAugBlock};
+    philox4x64_10(c, seed, 0ull);
+    const uint64_t tot = kCoinData + coin_c;
+    if (__umul64hi(c[0], tot) >= kCoinData) {
+      // ridge row k of the d rows sqrt(lambda) e_k
+      uint64_t k = __umul64hi(c[1], static_cast<uint64_t>(g.d));
+      for (int n = N - 1; n >= 0; --n) {
+        const uint64_t R = static_cast<uint64_t>(g.ranks[n]);
+        idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(g.dims[n] + (k % R));
+        k /= R;
+      }
+      const double r = static_cast<double>(tot) / static_cast<double>(coin_c);
+      weight[t] = (r * static_cast<double>(g.d)) / static_cast<double>(s);
+    } else {
+      const double r = static_cast<double>(tot) / static_cast<double>(kCoinData);
+      weight[t] = (acc * r) / static_cast<double>(s);
+    }
   }
 }
 
 }  // namespace
 
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
-                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st) {
+                   uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug,
+                   uint64_t coin_c) {
   if (s <= 0) return;
   if (g.total_rows <= kSampleLdsRows) {
     // as many workgroups as are resident at once (each stages the tables)
@@ -113,10 +146,11 @@ void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed,
         resident_grid(reinterpret_cast<const void*>(&sample_kernel<true>), kBlock, lds);
     const unsigned grid = static_cast<unsigned>(want < res ? want : res);
     hipLaunchKernelGGL(sample_kernel<true>, dim3(grid), dim3(kBlock), lds, st, g, cdf, s, seed,
-                       counter, problem, idx, weight);
+                       counter, problem, aug, coin_c, idx, weight);
   } else {
     hipLaunchKernelGGL(sample_kernel<false>, dim3(static_cast<unsigned>(cdiv(s, kBlock))),
-                       dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, idx, weight);
+                       dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, aug, coin_c, idx,
+                       weight);
   }
 }
 

@@ -109,8 +109,10 @@ def make_problem(X, factors, lam, mask=None):
 
 
 def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1,
-          stage_events=None):
+          stage_events=None, augmented=False, d_eff_lower=0.0):
     o = L.TkSketchOpts()
+    o.augmented = 1 if augmented else 0
+    o.d_eff_lower = float(d_eff_lower)
     o.stage_events = stage_events
     o.num_samples = int(samples) if samples is not None else 0
     o.eps, o.delta = float(eps), float(delta)
@@ -132,6 +134,12 @@ def _finish(device, status, where, check):
 def sample_count(d, eps, delta):
     """Alg. 1 sample count with beta' = 1/2."""
     return int(L.load().tucker_sample_count(int(d), float(eps), float(delta)))
+
+
+def sample_count_augmented(d, eps, delta, d_eff_lower=0.0):
+    """Alg. 1 sample count for augmented draws: beta' = 1/(1 + c), c = min{1, d - d'_eff}."""
+    return int(L.load().tucker_sample_count_augmented(int(d), float(eps), float(delta),
+                                                      float(d_eff_lower)))
 
 
 def leverage_scores(factors, check=True):
@@ -173,25 +181,54 @@ def sample(dims, cdf, s, seed, counter=0, problem=0):
     return idx, w
 
 
+def sample_augmented(dims, ranks, cdf, s, seed, counter=0, problem=0, d_eff_lower=0.0):
+    """Draws from Alg. 1's augmented distribution: idx (N, s) int32 (ridge draws
+    stored as dims[n] + digit) and weight (s,) float64."""
+    lib = L.load()
+    _check_tensor(cdf, "cdf", torch.int64)
+    dims = [int(v) for v in dims]
+    ranks = [int(v) for v in ranks]
+    if not 1 <= len(dims) <= L.MAX_ORDER or len(ranks) != len(dims) or min(dims) < 1:
+        raise ValueError("dims and ranks must hold 1..8 sizes each")
+    if cdf.numel() != sum(dims):
+        raise ValueError(f"cdf must hold sum(dims) = {sum(dims)} entries, got {cdf.numel()}")
+    if int(s) < 1:
+        raise ValueError("s must be >= 1")
+    dev = cdf.device
+    N = len(dims)
+    idx = torch.empty((N, int(s)), dtype=torch.int32, device=dev)
+    w = torch.empty(int(s), dtype=torch.float64, device=dev)
+    dims_c = (ctypes.c_int64 * N)(*dims)
+    ranks_c = (ctypes.c_int32 * N)(*ranks)
+    _raise_if(lib.tucker_sample_augmented(N, dims_c, ranks_c, _ptr(cdf), int(s),
+                                          int(seed) & ((1 << 64) - 1), int(counter), int(problem),
+                                          float(d_eff_lower), _ptr(idx), _ptr(w), _stream()),
+              "sample_augmented")
+    return idx, w
+
+
 def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0, precision="f64",
                          mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
                          return_samples=False, return_info=False, check=True, out=None,
-                         stage_events=None, status=None):
+                         stage_events=None, status=None, augmented=False, d_eff_lower=0.0):
     """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info).
 
     stage_events: optional address of an array of NUM_STAGE_EVENTS hipEvent_t
     handles that the library records at its stage boundaries.
     status: optional int32 device tensor of one element that receives the call's
     status word (default: a per-device word shared by all calls).
+    augmented: draw from Alg. 1's augmented distribution (lower bound d_eff_lower
+    of the effective dimension) and solve on the sampled rows of [K; sqrt(lam) I].
     """
     lib = L.load()
     p = make_problem(X, factors, lam, mask)
     o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol,
-              stage_events=stage_events)
+              stage_events=stage_events, augmented=augmented, d_eff_lower=d_eff_lower)
     dev = X.device
     N = len(factors)
-    s = int(samples) if samples else sample_count(
-        int(torch.tensor([A.shape[1] for A in factors]).prod()), 0.1, 0.1)
+    d = int(torch.tensor([A.shape[1] for A in factors]).prod())
+    s = int(samples) if samples else (sample_count_augmented(d, 0.1, 0.1, d_eff_lower)
+                                      if augmented else sample_count(d, 0.1, 0.1))
     if idx is not None:
         _check_tensor(idx, "idx", torch.int32)
         _check_tensor(weight, "weight", torch.float64)
@@ -272,7 +309,8 @@ def core_update_sketched_noalloc(X, factors, lam, samples, seed=0, counter=0, pr
     return res[0] if len(res) == 1 else tuple(res)
 
 
-def sketched_system(X, factors, lam, idx, weight, precision="f64", mask=None, check=True):
+def sketched_system(X, factors, lam, idx, weight, precision="f64", mask=None, check=True,
+                    augmented=False):
     """The sketched normal equations (M, b) of the sampled update on the samples (idx, weight),
     in the solver's whitened coordinates: M = sum_t w_t q_t q_t^T + lam P (lower triangle
     valid), b = sum_t w_t x_t q_t, q_t the Kronecker row of L_n^{-1} a^(n)_{i_n}."""
@@ -284,7 +322,7 @@ def sketched_system(X, factors, lam, idx, weight, precision="f64", mask=None, ch
     s = idx.shape[1]
     if idx.dim() != 2 or idx.shape[0] != N or weight.numel() != s:
         raise ValueError("idx must be (N, s) and weight (s,)")
-    o = _opts(s, 0, 0, 0, precision, 0, 0.0)
+    o = _opts(s, 0, 0, 0, precision, 0, 0.0, augmented=augmented)
     dev = X.device
     d = int(torch.tensor([A.shape[1] for A in factors]).prod())
     M = torch.empty((d, d), dtype=torch.float64, device=dev)

@@ -46,7 +46,9 @@ def test_struct_layouts_match_header(lib):
     # tk_problem: int32 order, int64 dims[8], int32 ranks[8], enum dtype, 2 pointers,
     # 8 pointers, double -> natural alignment
     assert ctypes.sizeof(L.TkProblem) == 4 + 4 + 64 + 32 + 4 + 4 + 8 + 8 + 64 + 8
-    assert ctypes.sizeof(L.TkSketchOpts) == 8 * 6 + 4 + 4 + 8 + 8
+    # ... int32 gram_precision, int32 refine_max, double, pointer, int32 augmented
+    # (+4 padding), double d_eff_lower
+    assert ctypes.sizeof(L.TkSketchOpts) == 8 * 6 + 4 + 4 + 8 + 8 + 8 + 8
 
 
 def _problem(dims, ranks, dtype=L.TK_F32, lam=1e-2):
@@ -77,6 +79,10 @@ def test_sample_count_matches_oracle(lib):
             assert lib.tucker_sample_count(d, eps, delta) == oracle.s_theory(d, eps, delta)
     assert lib.tucker_sample_count(0, 0.1, 0.1) == 0
     assert lib.tucker_sample_count(8, 0.1, 1.5) == 0
+    for d in (1, 8, 64, 4096):
+        for deff in (0.0, d - 0.25, d - 0.5, float(d), d + 3.0):
+            assert lib.tucker_sample_count_augmented(d, 0.1, 0.1, deff) == \
+                oracle.s_theory_augmented(d, 0.1, 0.1, deff), (d, deff)
 
 
 def test_workspace_sizes(lib):

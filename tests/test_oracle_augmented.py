@@ -179,3 +179,22 @@ def test_one_plus_eps_bound_augmented():
     idx, w = oracle.sample_augmented(tabs, ranks, 64, seed=0, counter=0)
     g = oracle.core_update_sketched_augmented(X, F, lam, idx, w)
     assert oracle.sketched_objective_excess(g, g_star, F, lam) > 10 * np.median(ratios) * f_star
+
+
+def test_augmented_normal_equation_residual_pin():
+    """Zero at Alg. 1's solve, equal to the explicit ||Gram g - rhs|| / ||rhs||
+    of the sampled augmented rows elsewhere (chunking does not matter)."""
+    dims, ranks = (6, 5, 4), (2, 3, 2)
+    p = workloads.tucker_tensor(dims, ranks, 23, "f64", factor="gaussian", noise=("sigma", 0.3))
+    X, F, lam = p["X"], p["factors_true"], 0.05
+    tabs = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F]
+    idx, w = oracle.sample_augmented(tabs, ranks, 500, seed=2, counter=0, d_eff_lower=0.0)
+    G = oracle.core_update_sketched_augmented(X, F, lam, idx, w)
+    assert oracle.normal_equation_residual_augmented(X, F, lam, idx, w, G, chunk=77) < 1e-12
+    Gp = G + 0.01 * np.random.default_rng(1).standard_normal(G.shape)
+    rows, x = oracle.augmented_rows(X, F, lam, idx)
+    gram = (rows * w[:, None]).T @ rows
+    rhs = rows.T @ (w * x)
+    ref = np.linalg.norm(gram @ Gp.reshape(-1) - rhs) / np.linalg.norm(rhs)
+    got = oracle.normal_equation_residual_augmented(X, F, lam, idx, w, Gp, chunk=77)
+    assert abs(got - ref) < 1e-12
