@@ -324,7 +324,15 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             als_ms[core] = e0.elapsed_time(e1) / 3
+        bound = None
+        if mask is not None:
+            # Cor. B.1: the count Alg. 1 would need for the masked design at
+            # eps = delta = 0.1 (reported beside the configured s)
+            ib, prod, beta_p, s_b = tk.masked_sample_bound(F, lam, 0.1, 0.1)
+            bound = {"inv_beta_bound": ib, "beta_prime": beta_p, "samples_for_guarantee": s_b,
+                     "samples_used": s}
         extras = {
+            "masked_sample_bound": bound,
             "sketched_update_ms": round(ms, 4),
             "exact_update_ms": round(exact_ms, 4),
             "exact_over_sketched_speed": round(exact_ms / ms, 4),

@@ -113,7 +113,8 @@ typedef enum {
   TK_CALL_EXACT = 2,
   TK_CALL_FACTOR = 3,
   TK_CALL_LOSS = 4,
-  TK_CALL_ADJOINT = 5
+  TK_CALL_ADJOINT = 5,
+  TK_CALL_MASKED_BOUND = 6
 } tk_call;
 
 /* Bytes of workspace the named call needs for this problem (0 on bad input).
@@ -150,6 +151,29 @@ int64_t tucker_sample_count_augmented(int64_t d, double eps, double delta, doubl
  */
 tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* cdf,
                                  int32_t* dev_status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Sample count for missing data -- Sec. 4.2 (Thm 4.3 with Lemma 4.4: the ridge
+ * scores of K over-estimate those of the observed-rows design K~ by a factor
+ * 1/beta = 1 + 1/(1 - lambda_max(L_{Sbar,Sbar})), L the cross ridge-score
+ * matrix of K and Sbar the missing rows) and App. B, Cor. B.1, which bounds it
+ * for ANY set of missing rows through the factors' spectral norms:
+ *   1/beta <= 2 + prod_n sigma_max(A(n))^2 / lambda.
+ * The sampled masked update draws from the unmasked product distribution and
+ * drops the draws that land on missing entries, i.e. it samples K~'s rows with
+ * these overestimates; Alg. 1's count for them is
+ *   beta' = beta / (1 + c),  s = ceil(4 d (1 + c) (1/beta) max{420 ln(4d/delta), 1/(delta eps)}),
+ * c = min{1, d - d_eff_lower} clamped at 0.  The bound does not depend on the
+ * mask, so p->mask and p->X are not read.  sigma_max(A(n))^2 is the largest
+ * eigenvalue of A(n)^T A(n) (FP64 Jacobi).
+ *   out  device double [4]: [0] the 1/beta bound, [1] prod_n sigma_max(A(n))^2,
+ *        [2] beta', [3] s (as a double: it can exceed 2^53 for small lambda).
+ * lambda must be > 0 (TK_E_ARG otherwise).  Workspace:
+ * tucker_workspace_bytes(p, NULL, TK_CALL_MASKED_BOUND).
+ */
+tk_status tucker_masked_sample_bound(const tk_problem* p, double eps, double delta,
+                                     double d_eff_lower, double* out, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /*
  * Product-distribution sampling of s multi-indices -- Alg. 3 (sample from

@@ -171,6 +171,44 @@ def s_theory_augmented(d, eps, delta, d_eff_lower=0.0):
 
 
 # --------------------------------------------------------------------------
+# Missing data (Sec. 4.2): how much the scores of K overestimate those of the
+# masked design K~ (Thm 4.3, Lemma 4.4, Cor. B.1)
+# --------------------------------------------------------------------------
+
+def masked_inverse_beta(factors, lam, mask):
+    """1/beta = 1 + 1/(1 - lambda_max(L_{Sbar,Sbar})) for the missing rows Sbar of
+    K (Thm 4.3 with Lemma 4.4: the ridge scores of K are a beta-overestimate for
+    those of K~).  L is K's matrix of cross ridge scores, formed explicitly:
+    tiny shapes only.  lam > 0."""
+    K = kron_matrix(factors)
+    L = cross_ridge_scores(K, lam)
+    dims = [np.asarray(A).shape[0] for A in factors]
+    miss = np.nonzero(~unpack_mask(mask, dims).reshape(-1))[0]
+    if len(miss) == 0:
+        return 2.0  # lambda_max of an empty block taken as 0
+    lmax = float(np.linalg.eigvalsh(L[np.ix_(miss, miss)]).max())
+    return 1.0 + 1.0 / (1.0 - lmax)
+
+
+def masked_inverse_beta_bound(factors, lam):
+    """Cor. B.1's bound, valid for any set of missing rows:
+    1/beta <= 1 + (1 + prod_n ||A(n)||_2^2 / lam) = 2 + prod_n sigma_max(A(n))^2 / lam."""
+    prod = 1.0
+    for A in factors:
+        prod *= float(np.linalg.norm(np.asarray(A, dtype=np.float64), 2)) ** 2
+    return 2.0 + prod / lam
+
+
+def s_theory_masked(d, eps, delta, inv_beta, d_eff_lower=0.0):
+    """Alg. 1's count with a beta-overestimate, beta = 1/inv_beta <= 1:
+    beta' = beta / (1 + c), s = ceil(4 d (1 + c) inv_beta max{420 ln(4d/delta), 1/(delta eps)}).
+    Returned as a float (the count can exceed 2^63 for small lam)."""
+    c = ridge_row_mass(d, d_eff_lower)
+    return math.ceil(4.0 * d * (1.0 + c) * inv_beta
+                     * max(420.0 * math.log(4.0 * d / delta), 1.0 / (delta * eps)))
+
+
+# --------------------------------------------------------------------------
 # Integer CDF tables and product-distribution sampling
 # (Lemma 4.1 product law; Alg. 3 sampler; proof of Thm 4.2: per-mode CDFs
 #  and one binary search per mode)

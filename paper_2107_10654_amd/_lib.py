@@ -14,7 +14,8 @@ NUM_STAGE_EVENTS = 10
 NOALLOC_SCRATCH_BYTES = 128 << 20
 
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
-CALL_LEVERAGE, CALL_SKETCHED, CALL_EXACT, CALL_FACTOR, CALL_LOSS, CALL_ADJOINT = range(6)
+(CALL_LEVERAGE, CALL_SKETCHED, CALL_EXACT, CALL_FACTOR, CALL_LOSS, CALL_ADJOINT,
+ CALL_MASKED_BOUND) = range(7)
 
 STATUS_NAMES = {
     0: "TK_OK", 1: "TK_E_ARG", 2: "TK_E_SHAPE", 3: "TK_E_DTYPE", 4: "TK_E_WORKSPACE",
@@ -74,6 +75,9 @@ _SIGNATURES = {
                                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                                  ctypes.c_double, _vp, _vp, _vp]),
     "tucker_workspace_bytes": (ctypes.c_size_t, [_P(TkProblem), _P(TkSketchOpts), ctypes.c_int32]),
+    "tucker_masked_sample_bound": (ctypes.c_int32, [_P(TkProblem), ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_double, _vp, _vp,
+                                                    ctypes.c_size_t, _vp]),
     "tucker_leverage_scores": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                                 _vp]),
     "tucker_sample": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64), _vp, ctypes.c_int64,

@@ -128,6 +128,12 @@ void carve_lev(Carver& c, const Geom& g, LevWS& w) {
   w.Q32 = c.take<float>(g.total_q);
 }
 
+void carve_bound(Carver& c, const Geom& g, double*& V, double*& C, double*& lam) {
+  V = c.take<double>(g.total_rr);
+  C = c.take<double>(g.total_rr);
+  lam = c.take<double>(static_cast<size_t>(kMaxOrder) * kMaxRank);
+}
+
 struct SketchWS {
   LevWS lev;
   int32_t* idx;
@@ -539,10 +545,38 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       carve_loss(c, g, w);
       break;
     }
+    case TK_CALL_MASKED_BOUND: {
+      double *V, *C, *lam;
+      carve_bound(c, g, V, C, lam);
+      break;
+    }
     default:
       return 0;
   }
   return c.used + 256;
+}
+
+tk_status tucker_masked_sample_bound(const tk_problem* p, double eps, double delta,
+                                     double d_eff_lower, double* out, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  tk_status s = check_problem(p, false);
+  if (s != TK_OK) return s;
+  if (!out || !ws) return TK_E_ARG;
+  if (!(p->lambda > 0.0)) return TK_E_ARG;  // Cor. B.1 needs lambda > 0
+  if (!(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0) || !isfinite(d_eff_lower)) return TK_E_ARG;
+  const Geom g = make_geom(p);
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_MASKED_BOUND)) return TK_E_WORKSPACE;
+  Carver c(ws);
+  double *V, *C, *lam;
+  carve_bound(c, g, V, C, lam);
+  const double cm = ridge_row_mass(g.d, d_eff_lower);
+  const double a = 420.0 * log(4.0 * static_cast<double>(g.d) / delta);
+  const double b = 1.0 / (delta * eps);
+  const double k = 4.0 * static_cast<double>(g.d) * (1.0 + cm) * (a > b ? a : b);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  launch_eig_modes(g, p->factors, p->dtype, V, lam, nullptr, C, st);
+  launch_masked_bound(g, lam, p->lambda, k, 1.0 + cm, out, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
 tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* cdf,

@@ -458,7 +458,36 @@ void launch_eig_modes(const Geom& g, const void* const* factors, tk_dtype dt, do
   else
     hipLaunchKernelGGL(eig_modes_kernel<float>, dim3(g.order), dim3(kBlock), 0, st, g, fp, V, lam,
                        C);
-  launch_mode_rows(g, factors, dt, V, 0, W, nullptr, nullptr, nullptr, st);
+  if (W) launch_mode_rows(g, factors, dt, V, 0, W, nullptr, nullptr, nullptr, st);
+}
+
+namespace {
+
+// Cor. B.1: with sigma_max(A(n))^2 the largest eigenvalue of C_n,
+// out = {1/beta bound, prod_n sigma_max^2, beta', s}; s = ceil(k / beta)
+// with k = 4 d (1 + c) max{420 ln(4d/delta), 1/(delta eps)} formed on the host.
+__global__ void masked_bound_kernel(Geom g, const double* __restrict__ lam_modes, double lambda,
+                                    double k, double one_plus_c, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double prod = 1.0;
+  for (int n = 0; n < g.order; ++n) {
+    double mx = 0.0;
+    for (int a = 0; a < g.ranks[n]; ++a) mx = fmax(mx, lam_modes[n * kMaxRank + a]);
+    prod *= mx;
+  }
+  const double inv_beta = 2.0 + prod / lambda;
+  out[0] = inv_beta;
+  out[1] = prod;
+  out[2] = (1.0 / inv_beta) / one_plus_c;
+  out[3] = ceil(k * inv_beta);
+}
+
+}  // namespace
+
+void launch_masked_bound(const Geom& g, const double* lam_modes, double lambda, double k,
+                         double one_plus_c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(masked_bound_kernel, dim3(1), dim3(64), 0, st, g, lam_modes, lambda, k,
+                     one_plus_c, out);
 }
 
 void launch_gram_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* C,

@@ -330,6 +330,9 @@ void launch_eig_modes(const Geom& g, const void* const* factors, tk_dtype dt, do
                       double* lam, double* W, double* C, hipStream_t st);
 void launch_gram_modes(const Geom& g, const void* const* factors, tk_dtype dt, double* C,
                        hipStream_t st);
+// Cor. B.1 overestimate from the eigenvalues of eig_modes (lam_modes[n * 64 + a]).
+void launch_masked_bound(const Geom& g, const double* lam_modes, double lambda, double k,
+                         double one_plus_c, double* out, hipStream_t st);
 void launch_kron_scale(const Geom& g, const double* lam_modes, double lambda, double* B,
                        hipStream_t st);
 void launch_sq_reduce(int64_t n, const void* x, tk_dtype dt, double* part, int64_t nparts,

@@ -142,6 +142,21 @@ def sample_count_augmented(d, eps, delta, d_eff_lower=0.0):
                                                       float(d_eff_lower)))
 
 
+def masked_sample_bound(factors, lam, eps=0.1, delta=0.1, d_eff_lower=0.0):
+    """Cor. B.1's overestimate for missing data and Alg. 1's count with it:
+    (1/beta bound, prod_n sigma_max(A(n))^2, beta', s) as floats."""
+    lib = L.load()
+    p = make_problem(None, factors, lam)
+    dev = factors[0].device
+    out = torch.empty(4, dtype=torch.float64, device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_MASKED_BOUND)
+    ws = _workspace(nb, dev)
+    _raise_if(lib.tucker_masked_sample_bound(ctypes.byref(p), float(eps), float(delta),
+                                             float(d_eff_lower), _ptr(out), _ptr(ws), ws.numel(),
+                                             _stream()), "masked_sample_bound")
+    return tuple(out.cpu().tolist())
+
+
 def leverage_scores(factors, check=True):
     """Per-mode leverage scores (concatenated float64) and integer CDFs (int64 view of uint64)."""
     lib = L.load()

@@ -21,6 +21,8 @@ through a route that does not reuse the oracle's own formula:
 """
 import itertools
 
+import math
+
 import numpy as np
 import pytest
 
@@ -456,3 +458,34 @@ def test_masked_factor_update_special_cases():
     for _ in range(5):
         Fb = [A0 + 1e-3 * rng.standard_normal(A0.shape), F[1], F[2]]
         assert oracle.loss(X, G, Fb, lam, mk)[0] > base
+
+
+# ---------------------------------------------------------------- missing-data sample count
+def test_masked_overestimate_chain():
+    """Cor. B.1's bound dominates the exact 1/beta of Thm 4.3 for any mask; the
+    exact value makes the K scores a beta-overestimate of the K~ ridge scores
+    (each K~ score <= its K score / beta); for semi-orthogonal factors the bound
+    is exactly 2 + 1/lam (the remark after Lemma 4.4)."""
+    lam = 0.2
+    F = [rand((5, 2), 91), rand((4, 2), 92), rand((3, 2), 93)]
+    K = oracle.kron_matrix(F)
+    lK = oracle.ridge_leverage_scores(K, lam)
+    bound = oracle.masked_inverse_beta_bound(F, lam)
+    rng = np.random.default_rng(94)
+    for _ in range(10):
+        obs = rng.random((5, 4, 3)) > 0.3
+        mk = workloads.pack_mask(obs)
+        ib = oracle.masked_inverse_beta(F, lam, mk)
+        assert 2.0 <= ib <= bound + 1e-9
+        keep = obs.reshape(-1)
+        lt = oracle.ridge_leverage_scores(K[keep], lam)
+        assert np.all(lt <= lK[keep] * ib + 1e-12)
+    Q = [np.linalg.qr(rand((6, 3), 95 + n))[0] for n in range(3)]
+    assert abs(oracle.masked_inverse_beta_bound(Q, 0.01) - (2.0 + 1.0 / 0.01)) < 1e-9
+
+
+def test_masked_sample_count():
+    a = max(420.0 * math.log(4.0 * 64 / 0.1), 1.0 / (0.1 * 0.1))
+    assert oracle.s_theory_masked(64, 0.1, 0.1, 2.0) == math.ceil(4.0 * 64 * 2.0 * 2.0 * a)
+    # inv_beta = 1 with c = 1 recovers the plain count
+    assert oracle.s_theory_masked(64, 0.1, 0.1, 1.0) == oracle.s_theory(64, 0.1, 0.1)
