@@ -329,6 +329,101 @@ def sampling_probabilities(tables, idx):
 
 
 # --------------------------------------------------------------------------
+# True lambda-ridge leverage scores of K (Sec. 2 SVD form; Sec. 4.1): a mixture
+# over the tuples of singular values, sampled without forming K
+# --------------------------------------------------------------------------
+
+#: Philox block (counter word 3) of the tuple draw of the ridge-score sampler.
+RIDGE_BLOCK = 3
+
+
+def ridge_tables(factors, lam, q_bits=Q_BITS):
+    """Integer tables of the ridge-score mixture of K = A(1) (x) ... (x) A(N).
+
+    With the SVDs A(n) = U_n S_n V_n^T, K's ridge scores are
+      l_i^lam(K) = sum_t pi_t prod_n U_n[i_n, t_n]^2,
+      pi_t = prod_n s_{n,t_n}^2 / (prod_n s_{n,t_n}^2 + lam)
+    (the SVD form of the ridge score applied to K's SVD (x)U_n (x)S_n (x)V_n),
+    a mixture over tuples t (row-major over the ranks) of product distributions
+    whose mode-n factor is column t_n of U_n squared (columns have unit norm).
+    Returns (tuple table (w, C) over the d tuples with w_t = ceil(pi_t 2^Q),
+    list over modes of lists over columns c of (w, C) with
+    w_i = ceil(U_n[i, c]^2 2^Q), and d_eff = sum_t pi_t).
+    """
+    Us, S2 = [], []
+    for A in factors:
+        U, sv, _ = np.linalg.svd(np.asarray(A, dtype=np.float64), full_matrices=False)
+        Us.append(U)
+        S2.append(sv ** 2)
+    prod = np.ones(1)
+    for s2 in S2:
+        prod = np.kron(prod, s2)
+    pi = prod / (prod + lam)
+    tuple_tab = cdf_table(pi, q_bits)
+    cols = [[cdf_table(U[:, c] ** 2, q_bits) for c in range(U.shape[1])] for U in Us]
+    return tuple_tab, cols, float(pi.sum())
+
+
+def ridge_mixture_probabilities(tuple_tab, cols, ranks, idx):
+    """P(row i) of the quantised mixture, sum_t (w_t / W) prod_n w_{n,t_n,i_n} / W_{n,t_n},
+    for every column of idx (a sum over all d tuples)."""
+    idx = np.asarray(idx)
+    wt, Ct = tuple_tab
+    W = float(Ct[-1])
+    P = np.zeros(idx.shape[1])
+    for t in range(len(wt)):
+        rem, dig = t, []
+        for R in reversed(ranks):
+            dig.append(rem % R)
+            rem //= R
+        dig = dig[::-1]
+        term = np.full(idx.shape[1], float(wt[t]) / W)
+        for n, c in enumerate(dig):
+            w, C = cols[n][c]
+            term = term * (w[idx[n]].astype(np.float64) / float(C[-1]))
+        P += term
+    return P
+
+
+def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0):
+    """s i.i.d. draws from the ridge-score mixture.
+
+    Per draw: the tuple t from the tuple table with word 0 of Philox block
+    RIDGE_BLOCK (u = floor(r W / 2^64), first t with C_t > u); then mode n's row
+    from the table of column t_n of U_n with the word that drives mode n in
+    ``sample`` (block n // 4, word n % 4), by the same inverse-CDF search.
+    weight_t = 1 / (s P(row t)) with P from ``ridge_mixture_probabilities``.
+    """
+    N = len(cols)
+    t = np.arange(s, dtype=np.uint64)
+    wt, Ct = tuple_tab
+    tw = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(RIDGE_BLOCK), seed, 0)
+    tup = np.searchsorted(Ct, mulhi64(tw[0], np.uint64(Ct[-1])), side="right").astype(np.int64)
+    digits = []
+    rem = tup.copy()
+    for n in range(N - 1, -1, -1):
+        digits.append(rem % ranks[n])
+        rem //= ranks[n]
+    digits = digits[::-1]
+    idx = np.empty((N, s), dtype=np.int32)
+    for b in range((N + 3) // 4):
+        words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(b), seed, 0)
+        for j in range(4):
+            n = 4 * b + j
+            if n >= N:
+                break
+            for c in range(ranks[n]):
+                sel = digits[n] == c
+                if not sel.any():
+                    continue
+                w, C = cols[n][c]
+                u = mulhi64(words[j][sel], np.uint64(C[-1]))
+                idx[n, sel] = np.searchsorted(C, u, side="right")
+    P = ridge_mixture_probabilities(tuple_tab, cols, ranks, idx)
+    return idx, 1.0 / (float(s) * P)
+
+
+# --------------------------------------------------------------------------
 # Sketched core update (Alg. 3 -> Alg. 1, normal equations as in the proof
 # of Thm 4.2; ridge handled as Gram + lam I)
 # --------------------------------------------------------------------------
