@@ -104,6 +104,11 @@ typedef struct {
                               (clamped at 0), so 0 gives c = 1.  With num_samples <= 0 the
                               count is ceil(4 d (1 + c) max{420 ln(4d/delta), 1/(delta eps)})
                               (Cor. 3.3: beta' = 1 / (1 + c)). */
+  int32_t sampling;        /* distribution of the data draws: 0 the product of the factor
+                              leverage scores (Alg. 3; Lemma 4.1), 1 the true lambda-ridge
+                              leverage scores of K (Sec. 2 SVD form), a mixture over
+                              singular-value tuples (tucker_ridge_tables,
+                              tucker_sample_ridge) */
 } tk_sketch_opts;
 
 /* Which call tucker_workspace_bytes() sizes. */
@@ -114,7 +119,8 @@ typedef enum {
   TK_CALL_FACTOR = 3,
   TK_CALL_LOSS = 4,
   TK_CALL_ADJOINT = 5,
-  TK_CALL_MASKED_BOUND = 6
+  TK_CALL_MASKED_BOUND = 6,
+  TK_CALL_RIDGE_TABLES = 7
 } tk_call;
 
 /* Bytes of workspace the named call needs for this problem (0 on bad input).
@@ -174,6 +180,49 @@ tk_status tucker_leverage_scores(const tk_problem* p, double* scores, uint64_t* 
 tk_status tucker_masked_sample_bound(const tk_problem* p, double eps, double delta,
                                      double d_eff_lower, double* out, void* ws, size_t ws_bytes,
                                      void* stream);
+
+/*
+ * Tables of the true lambda-ridge leverage scores of K = A(1) (x) ... (x) A(N)
+ * (Sec. 2: l_i^lambda = sum_k s_k^2/(s_k^2 + lambda) u_ik^2, applied to K's SVD
+ * (x)U_n (x)S_n (x)V_n; Sec. 4.1).  The scores are a mixture over the d tuples t
+ * of singular-value indices (row-major over the ranks):
+ *   l_i^lambda(K) = sum_t pi_t prod_n U_n[i_n, t_n]^2,
+ *   pi_t = prod_n s_{n,t_n}^2 / (prod_n s_{n,t_n}^2 + lambda),
+ * each component the product of the squared singular-vector columns (unit
+ * norm).  With C_n = A(n)^T A(n) = V_n Lambda_n V_n^T (FP64 Jacobi),
+ * s_{n,c}^2 = Lambda_n[c] and U_n[:, c] = A(n) V_n[:, c] / s_{n,c}.
+ *   tuple_cdf  device uint64 [d]: inclusive prefix sums of ceil(pi_t 2^TK_Q_BITS)
+ *              (pi_t = 0 when the eigenvalue product is not positive)
+ *   col_cdf    device uint64 [sum_n I_n R_n]: for mode n and column c, at offset
+ *              sum_{m<n} I_m R_m + c I_n, the inclusive prefix sums of
+ *              ceil(U_n[i, c]^2 2^TK_Q_BITS) over i (a column whose eigenvalue
+ *              is <= R_n 2^-52 max is all zero)
+ *   d_eff      device double [1] or NULL: sum_t pi_t, the effective dimension
+ * Degenerate eigenvalues make the singular vectors, and so these tables, one
+ * valid choice among many; the mixture's row probabilities do not depend on it.
+ * Workspace: tucker_workspace_bytes(p, NULL, TK_CALL_RIDGE_TABLES).
+ */
+tk_status tucker_ridge_tables(const tk_problem* p, uint64_t* tuple_cdf, uint64_t* col_cdf,
+                              double* d_eff, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Draws from the ridge-score mixture of K (tables of tucker_ridge_tables): per
+ * draw the tuple t from tuple_cdf with word 0 of Philox block 3 (counter
+ * (t, counter, problem, 3)), u = floor(r W / 2^64), first t with C_t > u; then
+ * mode n's row from the table of column t_n with the word that drives mode n
+ * in tucker_sample (block n / 4, word n % 4), by the same search.
+ *   weight_t = 1 / (s P(i_t)),  P(i) = sum_t (w_t / W) prod_n w_{n,t_n,i_n} / W_{n,t_n},
+ * the sum over all d tuples evaluated in FP64 (contracted mode by mode), so
+ * weights agree with another summation order to rounding, not bit for bit.
+ * augmented = 1 adds the branch coin of tucker_sample_augmented (same words,
+ * same ridge-row encoding and weights; data weights times (D + C) / D).
+ * Indices are bit-identical to the FP64 oracle given equal tables.
+ */
+tk_status tucker_sample_ridge(int32_t order, const int64_t* dims, const int32_t* ranks,
+                              const uint64_t* tuple_cdf, const uint64_t* col_cdf, int64_t s,
+                              uint64_t seed, uint64_t counter, uint64_t problem,
+                              int32_t augmented, double d_eff_lower, int32_t* idx,
+                              double* weight, void* stream);
 
 /*
  * Product-distribution sampling of s multi-indices -- Alg. 3 (sample from

@@ -385,7 +385,7 @@ def ridge_mixture_probabilities(tuple_tab, cols, ranks, idx):
     return P
 
 
-def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0):
+def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0, d_eff_lower=None):
     """s i.i.d. draws from the ridge-score mixture.
 
     Per draw: the tuple t from the tuple table with word 0 of Philox block
@@ -393,6 +393,10 @@ def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0):
     from the table of column t_n of U_n with the word that drives mode n in
     ``sample`` (block n // 4, word n % 4), by the same inverse-CDF search.
     weight_t = 1 / (s P(row t)) with P from ``ridge_mixture_probabilities``.
+    With ``d_eff_lower`` the draws are those of the augmented distribution of
+    Alg. 1 with these scores as the overestimate: the branch coin of
+    ``sample_augmented`` (same words) replaces a draw by a ridge row, and data
+    weights are multiplied by (D + C) / D.
     """
     N = len(cols)
     t = np.arange(s, dtype=np.uint64)
@@ -420,7 +424,21 @@ def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0):
                 u = mulhi64(words[j][sel], np.uint64(C[-1]))
                 idx[n, sel] = np.searchsorted(C, u, side="right")
     P = ridge_mixture_probabilities(tuple_tab, cols, ranks, idx)
-    return idx, 1.0 / (float(s) * P)
+    weight = 1.0 / (float(s) * P)
+    if d_eff_lower is None:
+        return idx, weight
+    dims = [len(colt[0][1]) for colt in cols]
+    d = int(np.prod(ranks))
+    D, Cw = coin_weights(d, d_eff_lower)
+    words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(AUG_BLOCK), seed, 0)
+    ridge = mulhi64(words[0], np.uint64(D + Cw)) >= np.uint64(D)
+    k = mulhi64(words[1], np.uint64(d)).astype(np.int64)
+    for n in range(N - 1, -1, -1):
+        idx[n] = np.where(ridge, dims[n] + k % ranks[n], idx[n]).astype(np.int32)
+        k //= ranks[n]
+    w_ridge = ((np.float64(D + Cw) / np.float64(Cw)) * np.float64(d)) / np.float64(s) if Cw else 0.0
+    weight = np.where(ridge, w_ridge, weight * (float(D + Cw) / float(D)))
+    return idx, weight
 
 
 # --------------------------------------------------------------------------

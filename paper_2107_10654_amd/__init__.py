@@ -10,7 +10,7 @@ from .tucker import (  # noqa: F401
     BatchedSketchedUpdate, TuckerError, PRECISIONS, als, core_update_exact, core_update_sketched,
     core_update_sketched_adjoint, core_update_sketched_batched, core_update_sketched_noalloc,
     factor_update, leverage_scores,
-    loss, make_problem, masked_sample_bound, release_workspace, sample, sample_augmented, sample_count,
-    sample_count_augmented, sketched_system, tune_batched,
+    loss, make_problem, masked_sample_bound, release_workspace, ridge_tables, sample, sample_augmented, sample_count,
+    sample_count_augmented, sample_ridge, sketched_system, tune_batched,
 )
 from .autograd import SketchedCoreUpdate, sketched_core_update  # noqa: F401

@@ -15,7 +15,7 @@ NOALLOC_SCRATCH_BYTES = 128 << 20
 
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 (CALL_LEVERAGE, CALL_SKETCHED, CALL_EXACT, CALL_FACTOR, CALL_LOSS, CALL_ADJOINT,
- CALL_MASKED_BOUND) = range(7)
+ CALL_MASKED_BOUND, CALL_RIDGE_TABLES) = range(8)
 
 STATUS_NAMES = {
     0: "TK_OK", 1: "TK_E_ARG", 2: "TK_E_SHAPE", 3: "TK_E_DTYPE", 4: "TK_E_WORKSPACE",
@@ -53,6 +53,7 @@ class TkSketchOpts(ctypes.Structure):
         ("stage_events", ctypes.c_void_p),
         ("augmented", ctypes.c_int32),
         ("d_eff_lower", ctypes.c_double),
+        ("sampling", ctypes.c_int32),
     ]
 
 
@@ -78,6 +79,12 @@ _SIGNATURES = {
     "tucker_masked_sample_bound": (ctypes.c_int32, [_P(TkProblem), ctypes.c_double,
                                                     ctypes.c_double, ctypes.c_double, _vp, _vp,
                                                     ctypes.c_size_t, _vp]),
+    "tucker_ridge_tables": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                             _vp]),
+    "tucker_sample_ridge": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int32),
+                                             _vp, _vp, ctypes.c_int64, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
+                                             ctypes.c_double, _vp, _vp, _vp]),
     "tucker_leverage_scores": (ctypes.c_int32, [_P(TkProblem), _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                                 _vp]),
     "tucker_sample": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int64), _vp, ctypes.c_int64,

@@ -134,6 +134,30 @@ void carve_bound(Carver& c, const Geom& g, double*& V, double*& C, double*& lam)
   lam = c.take<double>(static_cast<size_t>(kMaxOrder) * kMaxRank);
 }
 
+// Eigenpairs of every C_n and the ridge-score mixture tables of K.
+struct RidgeWS {
+  double* V;
+  double* C;
+  double* lamm;
+  double* W;        // A(n) V_n rows at qoff
+  uint64_t* tcdf;   // [d]
+  uint64_t* ccdf;   // [sum I_n R_n], column c of mode n at qoff[n] + c I_n
+  double* deff;
+};
+
+void carve_ridge(Carver& c, const Geom& g, RidgeWS& r) {
+  carve_bound(c, g, r.V, r.C, r.lamm);
+  r.W = c.take<double>(g.total_q);
+  r.tcdf = c.take<uint64_t>(g.d);
+  r.ccdf = c.take<uint64_t>(g.total_q);
+  r.deff = c.take<double>(1);
+}
+
+void launch_ridge(const Geom& g, const tk_problem* p, RidgeWS& r, hipStream_t st) {
+  launch_eig_modes(g, p->factors, p->dtype, r.V, r.lamm, r.W, r.C, st);
+  launch_ridge_tables(g, r.lamm, r.W, p->lambda, r.tcdf, r.ccdf, r.deff, st);
+}
+
 struct SketchWS {
   LevWS lev;
   int32_t* idx;
@@ -163,6 +187,8 @@ struct SketchWS {
   double* min_pivot;
   unsigned int* missing;
   double* Q64a;  // augmented whitened row tables (augmented draws only)
+  RidgeWS ridge; // ridge-score mixture tables (sampling = 1 only)
+  bool has_ridge;
 };
 
 // Which optional slices a sampled update (call TK_CALL_SKETCHED) or its adjoint
@@ -174,6 +200,7 @@ struct SketchNeeds {
   bool rows64;
   bool ttm;
   int64_t aug_q;  // entries of the augmented row tables (0: plain draws)
+  bool ridge;     // ridge-score mixture tables
 };
 
 SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, const tk_sketch_opts* o, int call) {
@@ -181,7 +208,7 @@ SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, const tk_sketch_opt
   const int32_t prec = o->gram_precision;
   return {adj || !resid_small_ok(g) || prec == TK_F64,
           adj || !core_chain_small_ok(g) || !refine_check_p_ok(g),
-          o->augmented ? make_geom_aug(p).total_q : 0};
+          o->augmented ? make_geom_aug(p).total_q : 0, o->sampling == 1};
 }
 
 void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w,
@@ -218,6 +245,8 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.min_pivot = c.take<double>(1);
   w.missing = c.take<unsigned int>(1);
   w.Q64a = need.aug_q ? c.take<double>(need.aug_q) : nullptr;
+  w.has_ridge = need.ridge;
+  if (need.ridge) carve_ridge(c, g, w.ridge);
 }
 
 // Extra workspace of the adjoint, carved after the sampled-update workspace.
@@ -550,6 +579,11 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       carve_bound(c, g, V, C, lam);
       break;
     }
+    case TK_CALL_RIDGE_TABLES: {
+      RidgeWS r;
+      carve_ridge(c, g, r);
+      break;
+    }
     default:
       return 0;
   }
@@ -576,6 +610,54 @@ tk_status tucker_masked_sample_bound(const tk_problem* p, double eps, double del
   hipStream_t st = static_cast<hipStream_t>(stream);
   launch_eig_modes(g, p->factors, p->dtype, V, lam, nullptr, C, st);
   launch_masked_bound(g, lam, p->lambda, k, 1.0 + cm, out, st);
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_ridge_tables(const tk_problem* p, uint64_t* tuple_cdf, uint64_t* col_cdf,
+                              double* d_eff, void* ws, size_t ws_bytes, void* stream) {
+  tk_status s = check_problem(p, false);
+  if (s != TK_OK) return s;
+  if (!tuple_cdf || !col_cdf || !ws) return TK_E_ARG;
+  if (ws_bytes < tucker_workspace_bytes(p, nullptr, TK_CALL_RIDGE_TABLES)) return TK_E_WORKSPACE;
+  const Geom g = make_geom(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  RidgeWS r;
+  carve_ridge(c, g, r);
+  launch_ridge(g, p, r, st);
+  TK_HIP_CHECK(hipMemcpyAsync(tuple_cdf, r.tcdf, sizeof(uint64_t) * g.d, hipMemcpyDeviceToDevice,
+                              st));
+  TK_HIP_CHECK(hipMemcpyAsync(col_cdf, r.ccdf, sizeof(uint64_t) * g.total_q,
+                              hipMemcpyDeviceToDevice, st));
+  if (d_eff)
+    TK_HIP_CHECK(hipMemcpyAsync(d_eff, r.deff, sizeof(double), hipMemcpyDeviceToDevice, st));
+  return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
+}
+
+tk_status tucker_sample_ridge(int32_t order, const int64_t* dims, const int32_t* ranks,
+                              const uint64_t* tuple_cdf, const uint64_t* col_cdf, int64_t s,
+                              uint64_t seed, uint64_t counter, uint64_t problem,
+                              int32_t augmented, double d_eff_lower, int32_t* idx,
+                              double* weight, void* stream) {
+  if (order < 1 || order > kMaxOrder || !dims || !ranks || !tuple_cdf || !col_cdf || !idx ||
+      !weight || s < 1 || (augmented != 0 && augmented != 1) || !isfinite(d_eff_lower))
+    return TK_E_ARG;
+  tk_problem p;
+  memset(&p, 0, sizeof(p));
+  p.order = order;
+  int64_t d = 1;
+  for (int n = 0; n < order; ++n) {
+    if (dims[n] < 1 || dims[n] > (int64_t(1) << 31) - 1 - kMaxRank) return TK_E_SHAPE;
+    if (ranks[n] < 1 || ranks[n] > kMaxRank || ranks[n] > dims[n]) return TK_E_SHAPE;
+    p.dims[n] = dims[n];
+    p.ranks[n] = ranks[n];
+    d *= ranks[n];
+    if (d > kMaxD) return TK_E_SHAPE;
+  }
+  const Geom g = make_geom(&p);
+  launch_sample_ridge(g, tuple_cdf, col_cdf, s, seed, counter, problem, idx, weight,
+                      static_cast<hipStream_t>(stream), augmented,
+                      augmented ? ridge_coin_weight(d, d_eff_lower) : 0);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
@@ -676,6 +758,7 @@ tk_status check_sketch_args(const tk_problem* p, const tk_sketch_opts* o, int64_
   if (o->gram_precision != TK_F64 && o->gram_precision != TK_F32 && o->gram_precision != TK_BF16)
     return TK_E_DTYPE;
   if (o->augmented != 0 && o->augmented != 1) return TK_E_ARG;
+  if (o->sampling != 0 && o->sampling != 1) return TK_E_ARG;
   if (o->augmented && !isfinite(o->d_eff_lower)) return TK_E_ARG;
   if (o->augmented) {
     for (int n = 0; n < p->order; ++n)
@@ -715,8 +798,15 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   if (!idx_in) {
     int32_t* io = idx_out ? idx_out : w.idx;
     double* wo = weight_out ? weight_out : w.weight;
-    launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st,
-                  R.aug ? 1 : 0, R.aug ? ridge_coin_weight(g.d, R.o->d_eff_lower) : 0);
+    const uint64_t coin = R.aug ? ridge_coin_weight(g.d, R.o->d_eff_lower) : 0;
+    if (R.o->sampling == 1) {  // the ridge-score mixture of K
+      launch_ridge(g, p, w.ridge, st);
+      launch_sample_ridge(g, w.ridge.tcdf, w.ridge.ccdf, R.s, R.o->seed, R.o->counter,
+                          R.o->problem, io, wo, st, R.aug ? 1 : 0, coin);
+    } else {
+      launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st,
+                    R.aug ? 1 : 0, coin);
+    }
     R.idx = io;
     R.weight = wo;
   } else if (idx_out) {

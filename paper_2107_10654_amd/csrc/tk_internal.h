@@ -82,6 +82,17 @@ void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug = 0,
                    uint64_t coin_c = 0);
 
+// Ridge-score mixture of K (tk_leverage.hip, tk_sample.hip): from the
+// eigenpairs of eig_modes (lamm[n * 64 + c], W_n = A(n) V_n rows at qoff) the
+// tuple CDF [d] and the column CDFs (mode n column c at qoff[n] + c I_n),
+// d_eff = sum_t pi_t (device double); then draws from the mixture (with the
+// augmented coin when aug != 0), weights 1/(s P).
+void launch_ridge_tables(const Geom& g, const double* lamm, const double* W, double lambda,
+                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st);
+void launch_sample_ridge(const Geom& g, const uint64_t* tcdf, const uint64_t* ccdf, int64_t s,
+                         uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
+                         double* weight, hipStream_t st, int aug = 0, uint64_t coin_c = 0);
+
 // Whitened row tables of the augmented design (tk_leverage.hip): in the
 // geometry ga (dims I_n + R_n), rows i < I_n of mode n copy Q64's rows and
 // row I_n + k is column k of L_n^{-1}, times sqrt(lambda) in mode 0, so that

@@ -278,6 +278,92 @@ __global__ __launch_bounds__(kBlock) void weight_scan_kernel(Geom g, uint64_t* c
 
 namespace {
 
+// In-place inclusive prefix sum of len uint64 entries by one workgroup of
+// kBlock threads (integer adds: any order gives the same table).
+__device__ void block_scan_u64(uint64_t* cd, int64_t len, uint64_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < len; base += kBlock) {
+    const int64_t i = base + tid;
+    uint64_t v = (i < len) ? cd[i] : 0;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    uint64_t before = carry;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (i < len) cd[i] = v + before;
+    for (int w = 0; w < kBlock / 64; ++w) carry += wsum[w];
+    __syncthreads();
+  }
+}
+
+// Ridge-score mixture of K (Sec. 2 SVD form applied to K's SVD): with
+// C_n = V_n Lambda_n V_n^T and W_n = A(n) V_n, column c of U_n is
+// W_n[:, c] / sqrt(Lambda_n[c]).  Workgroup j builds the table of global
+// column j (mode n, column c) at qoff[n] + c I_n: weights
+// ceil(W[i][c]^2 / Lambda[c] 2^Q), then their inclusive prefix sums.  A
+// numerically zero eigenvalue (<= R 2^-52 max) gets an all-zero column.
+__global__ __launch_bounds__(kBlock) void ridge_col_kernel(Geom g, const double* __restrict__ lamm,
+                                                           const double* __restrict__ W,
+                                                           uint64_t* __restrict__ ccdf) {
+  __shared__ uint64_t wsum[kBlock / 64];
+  int n = 0, c = blockIdx.x;
+  while (c >= g.ranks[n]) c -= g.ranks[n++];
+  const int R = g.ranks[n];
+  const int64_t I = g.dims[n];
+  double mx = 0.0;
+  for (int a = 0; a < R; ++a) mx = fmax(mx, lamm[n * kMaxRank + a]);
+  const double lc = lamm[n * kMaxRank + c];
+  const bool zero = !(lc > static_cast<double>(R) * 0x1p-52 * mx);
+  uint64_t* cd = ccdf + g.qoff[n] + static_cast<int64_t>(c) * I;
+  const double* w = W + g.qoff[n] + c;
+  for (int64_t i = threadIdx.x; i < I; i += kBlock) {
+    const double v = w[i * R];
+    const double u2 = zero ? 0.0 : (v * v) / lc;
+    cd[i] = static_cast<uint64_t>(ceil(u2 * static_cast<double>(1ull << TK_Q_BITS)));
+  }
+  __syncthreads();
+  block_scan_u64(cd, I, wsum);
+}
+
+// Tuple table: pi_t = prod_n Lambda_n[t_n] / (prod + lambda) (the product in
+// mode order; 0 when it is not positive), weights ceil(pi_t 2^Q), their
+// inclusive prefix sums, and d_eff = sum_t pi_t (per-thread sums over
+// t = tid + k kBlock, then added in thread order).
+__global__ __launch_bounds__(kBlock) void ridge_tuple_kernel(Geom g, const double* __restrict__ lamm,
+                                                             double lambda,
+                                                             uint64_t* __restrict__ tcdf,
+                                                             double* __restrict__ deff) {
+  __shared__ uint64_t wsum[kBlock / 64];
+  __shared__ double part[kBlock];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t t = tid; t < g.d; t += kBlock) {
+    int64_t rem = t;
+    int dig[kMaxOrder];
+    for (int n = g.order - 1; n >= 0; --n) {
+      dig[n] = static_cast<int>(rem % g.ranks[n]);
+      rem /= g.ranks[n];
+    }
+    double prod = 1.0;
+    for (int n = 0; n < g.order; ++n) prod = prod * lamm[n * kMaxRank + dig[n]];
+    const double pi = prod > 0.0 ? prod / (prod + lambda) : 0.0;
+    acc += pi;
+    tcdf[t] = static_cast<uint64_t>(ceil(pi * static_cast<double>(1ull << TK_Q_BITS)));
+  }
+  part[tid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int k = 0; k < kBlock; ++k) sum += part[k];
+    *deff = sum;
+  }
+  block_scan_u64(tcdf, g.d, wsum);
+}
+
 // Rows of the augmented whitened tables: one thread per table entry of ga.
 __global__ __launch_bounds__(kBlock) void aug_tables_kernel(Geom g, Geom ga,
                                                             const double* __restrict__ Q64,
@@ -304,6 +390,12 @@ __global__ __launch_bounds__(kBlock) void aug_tables_kernel(Geom g, Geom ga,
 }
 
 }  // namespace
+
+void launch_ridge_tables(const Geom& g, const double* lamm, const double* W, double lambda,
+                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st) {
+  hipLaunchKernelGGL(ridge_col_kernel, dim3(g.sum_r), dim3(kBlock), 0, st, g, lamm, W, ccdf);
+  hipLaunchKernelGGL(ridge_tuple_kernel, dim3(1), dim3(kBlock), 0, st, g, lamm, lambda, tcdf, deff);
+}
 
 void launch_aug_tables(const Geom& g, const Geom& ga, const double* Q64, const double* Linv,
                        double lambda, double* Q64a, hipStream_t st) {

@@ -132,7 +132,170 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* 
   }
 }
 
+// ---------------------------------------------------------------- ridge-score mixture
+// Draws from the mixture of K's lambda-ridge scores over singular-value tuples
+// (tables from ridge tables: tuple CDF over the d tuples, row-major over the
+// ranks; the CDF of column c of mode n at qoff[n] + c I_n).  The tuple comes
+// from word 0 of Philox block kRidgeBlock, then mode n's row from column t_n's
+// table with the word that drives mode n in the product sampler.  With aug
+// the branch coin of the augmented distribution is drawn as in sample_kernel;
+// ridge rows get their weight here, data draws in ridge_weight_kernel.
+constexpr uint64_t kRidgeBlock = 3;
+
+__device__ inline int64_t upper_search(const uint64_t* __restrict__ C, int64_t len, uint64_t u) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (C[mid] > u)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo < len ? lo : len - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void ridge_sample_kernel(
+    Geom g, const uint64_t* __restrict__ tcdf, const uint64_t* __restrict__ ccdf, int64_t s,
+    uint64_t seed, uint64_t counter, uint64_t problem, int aug, uint64_t coin_c,
+    int32_t* __restrict__ idx, double* __restrict__ weight) {
+  const int N = g.order;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < s;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    uint64_t c4[4] = {static_cast<uint64_t>(t), counter, problem, kRidgeBlock};
+    philox4x64_10(c4, seed, 0ull);
+    const uint64_t Wt = tcdf[g.d - 1];
+    int64_t tup = upper_search(tcdf, g.d, __umul64hi(c4[0], Wt));
+    int32_t col[kMaxOrder];
+    for (int n = N - 1; n >= 0; --n) {
+      col[n] = static_cast<int32_t>(tup % g.ranks[n]);
+      tup /= g.ranks[n];
+    }
+    for (int b = 0; b * 4 < N; ++b) {
+      uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, static_cast<uint64_t>(b)};
+      philox4x64_10(c, seed, 0ull);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 4 * b + j;
+        if (n < N) {
+          const int64_t I = g.dims[n];
+          const uint64_t* C = ccdf + g.qoff[n] + static_cast<int64_t>(col[n]) * I;
+          const int64_t i = upper_search(C, I, __umul64hi(c[j], C[I - 1]));
+          idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(i);
+        }
+      }
+    }
+    if (!aug) continue;
+    uint64_t ca[4] = {static_cast<uint64_t>(t), counter, problem, kAugBlock};
+    philox4x64_10(ca, seed, 0ull);
+    const uint64_t tot = kCoinData + coin_c;
+    if (__umul64hi(ca[0], tot) >= kCoinData) {
+      uint64_t k = __umul64hi(ca[1], static_cast<uint64_t>(g.d));
+      for (int n = N - 1; n >= 0; --n) {
+        const uint64_t R = static_cast<uint64_t>(g.ranks[n]);
+        idx[static_cast<int64_t>(n) * s + t] = static_cast<int32_t>(g.dims[n] + (k % R));
+        k /= R;
+      }
+      const double r = static_cast<double>(tot) / static_cast<double>(coin_c);
+      weight[t] = (r * static_cast<double>(g.d)) / static_cast<double>(s);
+    }
+  }
+}
+
+// Weight 1/(s P) of a data draw, P = sum_t (w_t / W) prod_n w_{n,t_n,i_n} / W_{n,t_n}:
+// one wave per draw.  Lanes form u_n[c] = w_{n,c,i_n} / W_{n,c} in LDS, then the
+// sum over tuples is contracted mode by mode from the last mode with rank >= 2
+// to the first (Y[p] = sum_c Y[p R + c] u[c], lanes over p), each step a
+// short dot product per lane; rank-1 modes multiply the result.  Dynamic LDS:
+// sum_r + 2 bufmax doubles.
+__global__ __launch_bounds__(64) void ridge_weight_kernel(
+    Geom g, const uint64_t* __restrict__ tcdf, const uint64_t* __restrict__ ccdf,
+    const int32_t* __restrict__ idx, int64_t s, int aug, uint64_t coin_c, int64_t bufmax,
+    double* __restrict__ weight) {
+  extern __shared__ double sm[];
+  double* u = sm;                  // [sum_r]
+  double* ya = u + g.sum_r;        // [bufmax]
+  double* yb = ya + bufmax;        // [bufmax]
+  const int lane = threadIdx.x;
+  const int N = g.order;
+  const double Wt = static_cast<double>(tcdf[g.d - 1]);
+  for (int64_t t = blockIdx.x; t < s; t += gridDim.x) {
+    if (aug && idx[t] >= g.dims[0]) continue;  // a ridge row: weighted by the sampler
+    for (int j = lane; j < g.sum_r; j += 64) {
+      int n = 0;
+      while (j >= g.soff[n] + g.ranks[n]) ++n;
+      const int c = j - g.soff[n];
+      const int64_t I = g.dims[n];
+      const uint64_t* C = ccdf + g.qoff[n] + static_cast<int64_t>(c) * I;
+      const int64_t i = idx[static_cast<int64_t>(n) * s + t];
+      const uint64_t Om = C[I - 1];
+      const uint64_t om = C[i] - (i > 0 ? C[i - 1] : 0ull);
+      u[j] = Om ? static_cast<double>(om) / static_cast<double>(Om) : 0.0;
+    }
+    __syncthreads();
+    // contraction over the modes with rank >= 2, last to first
+    int64_t len = g.d;
+    const double* src = nullptr;  // nullptr: the tuple weights themselves
+    double* dst = ya;
+    double scal = 1.0;
+    for (int n = N - 1; n >= 0; --n) {
+      const int R = g.ranks[n];
+      if (R < 2) {
+        scal *= u[g.soff[n]];
+        continue;
+      }
+      const int64_t out = len / R;
+      const double* un = u + g.soff[n];
+      for (int64_t p = lane; p < out; p += 64) {
+        double acc = 0.0;
+        for (int c = 0; c < R; ++c) {
+          const int64_t e = p * R + c;
+          const double y = src ? src[e]
+                               : static_cast<double>(tcdf[e] - (e > 0 ? tcdf[e - 1] : 0ull));
+          acc = fma(y, un[c], acc);
+        }
+        dst[p] = acc;
+      }
+      __syncthreads();
+      src = dst;
+      dst = (dst == ya) ? yb : ya;
+      len = out;
+    }
+    if (lane == 0) {
+      const double num =
+          (src ? src[0] : static_cast<double>(tcdf[0])) * scal;  // sum_t w_t prod_n u_n[t_n]
+      double w = Wt / num;
+      if (aug) w = w * (static_cast<double>(kCoinData + coin_c) / static_cast<double>(kCoinData));
+      weight[t] = w / static_cast<double>(s);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+void launch_sample_ridge(const Geom& g, const uint64_t* tcdf, const uint64_t* ccdf, int64_t s,
+                         uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
+                         double* weight, hipStream_t st, int aug, uint64_t coin_c) {
+  if (s <= 0) return;
+  const int64_t want = cdiv(s, kBlock);
+  const int64_t res =
+      resident_grid(reinterpret_cast<const void*>(&ridge_sample_kernel), kBlock, 0);
+  hipLaunchKernelGGL(ridge_sample_kernel, dim3(static_cast<unsigned>(want < res ? want : res)),
+                     dim3(kBlock), 0, st, g, tcdf, ccdf, s, seed, counter, problem, aug, coin_c,
+                     idx, weight);
+  // the largest intermediate of the contraction: d over the last rank >= 2
+  int64_t bufmax = 1;
+  for (int n = g.order - 1; n >= 0; --n)
+    if (g.ranks[n] >= 2) {
+      bufmax = g.d / g.ranks[n];
+      break;
+    }
+  const size_t lds = sizeof(double) * (static_cast<size_t>(g.sum_r) + 2 * bufmax);
+  ensure_dyn_lds(reinterpret_cast<const void*>(&ridge_weight_kernel), static_cast<int>(lds));
+  const int64_t grid = s < 65536 ? s : 65536;
+  hipLaunchKernelGGL(ridge_weight_kernel, dim3(static_cast<unsigned>(grid)), dim3(64), lds, st, g,
+                     tcdf, ccdf, idx, s, aug, coin_c, bufmax, weight);
+}
 
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug,

@@ -108,11 +108,15 @@ def make_problem(X, factors, lam, mask=None):
     return p
 
 
+SAMPLINGS = {"leverage": 0, "ridge": 1}
+
+
 def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1,
-          stage_events=None, augmented=False, d_eff_lower=0.0):
+          stage_events=None, augmented=False, d_eff_lower=0.0, sampling="leverage"):
     o = L.TkSketchOpts()
     o.augmented = 1 if augmented else 0
     o.d_eff_lower = float(d_eff_lower)
+    o.sampling = SAMPLINGS[sampling]
     o.stage_events = stage_events
     o.num_samples = int(samples) if samples is not None else 0
     o.eps, o.delta = float(eps), float(delta)
@@ -196,6 +200,52 @@ def sample(dims, cdf, s, seed, counter=0, problem=0):
     return idx, w
 
 
+def ridge_tables(factors, lam):
+    """Tables of the lambda-ridge leverage scores of K (mixture over singular-value
+    tuples): tuple CDF (d,), column CDFs (sum I_n R_n,) as int64 views of uint64,
+    and d_eff."""
+    lib = L.load()
+    p = make_problem(None, factors, lam)
+    dev = factors[0].device
+    d = 1
+    for A in factors:
+        d *= A.shape[1]
+    tq = sum(A.shape[0] * A.shape[1] for A in factors)
+    tcdf = torch.empty(d, dtype=torch.int64, device=dev)
+    ccdf = torch.empty(tq, dtype=torch.int64, device=dev)
+    deff = torch.empty(1, dtype=torch.float64, device=dev)
+    nb = lib.tucker_workspace_bytes(ctypes.byref(p), None, L.CALL_RIDGE_TABLES)
+    ws = _workspace(nb, dev)
+    _raise_if(lib.tucker_ridge_tables(ctypes.byref(p), _ptr(tcdf), _ptr(ccdf), _ptr(deff),
+                                      _ptr(ws), ws.numel(), _stream()), "ridge_tables")
+    return tcdf, ccdf, float(deff.item())
+
+
+def sample_ridge(dims, ranks, tuple_cdf, col_cdf, s, seed, counter=0, problem=0, augmented=False,
+                 d_eff_lower=0.0):
+    """Draws from the ridge-score mixture of K: idx (N, s) int32, weight (s,) float64."""
+    lib = L.load()
+    _check_tensor(tuple_cdf, "tuple_cdf", torch.int64)
+    _check_tensor(col_cdf, "col_cdf", torch.int64)
+    dims = [int(v) for v in dims]
+    ranks = [int(v) for v in ranks]
+    d = 1
+    for r in ranks:
+        d *= r
+    if tuple_cdf.numel() != d or col_cdf.numel() != sum(a * b for a, b in zip(dims, ranks)):
+        raise ValueError("table lengths do not match dims and ranks")
+    dev = tuple_cdf.device
+    N = len(dims)
+    idx = torch.empty((N, int(s)), dtype=torch.int32, device=dev)
+    w = torch.empty(int(s), dtype=torch.float64, device=dev)
+    _raise_if(lib.tucker_sample_ridge(N, (ctypes.c_int64 * N)(*dims), (ctypes.c_int32 * N)(*ranks),
+                                      _ptr(tuple_cdf), _ptr(col_cdf), int(s),
+                                      int(seed) & ((1 << 64) - 1), int(counter), int(problem),
+                                      1 if augmented else 0, float(d_eff_lower), _ptr(idx),
+                                      _ptr(w), _stream()), "sample_ridge")
+    return idx, w
+
+
 def sample_augmented(dims, ranks, cdf, s, seed, counter=0, problem=0, d_eff_lower=0.0):
     """Draws from Alg. 1's augmented distribution: idx (N, s) int32 (ridge draws
     stored as dims[n] + digit) and weight (s,) float64."""
@@ -225,7 +275,8 @@ def sample_augmented(dims, ranks, cdf, s, seed, counter=0, problem=0, d_eff_lowe
 def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0, precision="f64",
                          mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
                          return_samples=False, return_info=False, check=True, out=None,
-                         stage_events=None, status=None, augmented=False, d_eff_lower=0.0):
+                         stage_events=None, status=None, augmented=False, d_eff_lower=0.0,
+                         sampling="leverage"):
     """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info).
 
     stage_events: optional address of an array of NUM_STAGE_EVENTS hipEvent_t
@@ -234,11 +285,14 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     status word (default: a per-device word shared by all calls).
     augmented: draw from Alg. 1's augmented distribution (lower bound d_eff_lower
     of the effective dimension) and solve on the sampled rows of [K; sqrt(lam) I].
+    sampling: "leverage" (product of the factor leverage scores) or "ridge" (the
+    lambda-ridge leverage scores of K, a mixture over singular-value tuples).
     """
     lib = L.load()
     p = make_problem(X, factors, lam, mask)
     o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol,
-              stage_events=stage_events, augmented=augmented, d_eff_lower=d_eff_lower)
+              stage_events=stage_events, augmented=augmented, d_eff_lower=d_eff_lower,
+              sampling=sampling)
     dev = X.device
     N = len(factors)
     d = int(torch.tensor([A.shape[1] for A in factors]).prod())

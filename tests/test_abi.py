@@ -47,8 +47,8 @@ def test_struct_layouts_match_header(lib):
     # 8 pointers, double -> natural alignment
     assert ctypes.sizeof(L.TkProblem) == 4 + 4 + 64 + 32 + 4 + 4 + 8 + 8 + 64 + 8
     # ... int32 gram_precision, int32 refine_max, double, pointer, int32 augmented
-    # (+4 padding), double d_eff_lower
-    assert ctypes.sizeof(L.TkSketchOpts) == 8 * 6 + 4 + 4 + 8 + 8 + 8 + 8
+    # (+4 padding), double d_eff_lower, int32 sampling (+4 padding)
+    assert ctypes.sizeof(L.TkSketchOpts) == 8 * 6 + 4 + 4 + 8 + 8 + 8 + 8 + 8
 
 
 def _problem(dims, ranks, dtype=L.TK_F32, lam=1e-2):

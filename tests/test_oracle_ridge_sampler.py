@@ -97,3 +97,24 @@ def test_large_lambda_concentrates_on_large_singular_values():
     wt_b = tt_big[0].astype(float) / float(tt_big[1][-1])
     # the tuple with the largest singular values carries the most mass
     assert np.argmax(wt_b) == 0
+
+
+def test_ridge_draws_with_the_branch_coin():
+    """The augmented coin over ridge-score draws: ridge rows exactly where
+    sample_augmented puts them (same words), data rows those of the plain
+    ridge draws with weights times (D + C) / D; c = 0 changes nothing."""
+    dims, ranks = (6, 5, 4), (2, 2, 2)
+    F = _factors(dims, ranks, 6)
+    tt, cols, _ = oracle.ridge_tables(F, 0.2)
+    lev = [oracle.cdf_table(oracle.leverage_scores(A)) for A in F]
+    ip, wp = oracle.sample_ridge(tt, cols, ranks, 4000, seed=2, counter=7)
+    ia, wa = oracle.sample_ridge(tt, cols, ranks, 4000, seed=2, counter=7, d_eff_lower=7.6)
+    il, wl = oracle.sample_augmented(lev, ranks, 4000, 2, 7, 7.6)
+    ridge = ia[0] >= dims[0]
+    assert np.array_equal(ridge, il[0] >= dims[0])
+    assert np.array_equal(ia[:, ridge], il[:, ridge]) and np.array_equal(wa[ridge], wl[ridge])
+    D, C = oracle.coin_weights(8, 7.6)
+    assert np.array_equal(ia[:, ~ridge], ip[:, ~ridge])
+    np.testing.assert_allclose(wa[~ridge], wp[~ridge] * (D + C) / D, rtol=1e-15)
+    i0, w0 = oracle.sample_ridge(tt, cols, ranks, 4000, seed=2, counter=7, d_eff_lower=8.0)
+    assert np.array_equal(i0, ip) and np.array_equal(w0, wp)
