@@ -176,6 +176,13 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=131072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip exact/ALS comparison timings")
+    ap.add_argument("--protocol", choices=["table1", "movie"], default=None,
+                    help="run the paper's ALS vs ALS-RS comparison instead of the headline "
+                         "benchmark (one JSON line per point)")
+    ap.add_argument("--dims", default=None, help="tensor shape of --protocol table1, e.g. 512,512,512")
+    ap.add_argument("--microbench", action="store_true",
+                    help="time the sampling and gather steps at Alg. 1's count and the sampler "
+                         "alone at 2^24 samples (one JSON line)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain FP32 copy kernel over this many MiB (calibrates the "
                          "HBM byte counters of a profiler run)")
@@ -198,6 +205,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.protocol:
+        return bench_protocol(args, tk, workloads, np, torch, dev)
+    if args.microbench:
+        return bench_microbench(args, tk, workloads, np, torch, dev)
     if args.workload == "c4":
         return bench_batch(args, tk, workloads, np, torch, dev)
 
@@ -391,6 +402,163 @@ def main():
         "oracle_rel_err": oracle_err,
     }
     out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+def bench_protocol(args, tk, workloads, np, torch, dev):
+    """The paper's ALS vs ALS-RS comparisons (Sec. 5), one JSON line per point.
+
+    table1: the synthetic protocol (true core 8^3, U[0,1] core and factors,
+    N(0,1) noise on 1 % of entries) at --dims (default 1024^3), fitted at ranks
+    (2,2,2), (4,2,2), (4,4,2), (4,4,4) for 10 iterations from the same U[0,1)
+    initial state; the sampled core uses s = 32 d and Alg. 1's count
+    (eps = delta = 0.1).  movie: the (100, 1080, 1920, 3) stand-in, core
+    (2, 4, 4, 2), 5 iterations.  Every step is timed with device events and the
+    RMSE is taken after each iteration.
+    """
+    lam = 1e-3
+    t_gen = time.perf_counter()
+    if args.protocol == "table1":
+        dims = tuple(int(v) for v in args.dims.split(",")) if args.dims else (1024, 1024, 1024)
+        X = workloads.table1_problem_device(dims, 11, dev)["X"]
+        rank_list = [(2, 2, 2), (4, 2, 2), (4, 4, 2), (4, 4, 4)]
+        iters, init_seed = 10, 1011
+    else:
+        dims = (100, 1080, 1920, 3)
+        X = workloads.movie_problem_device(21, dev)
+        rank_list = [(2, 4, 4, 2)]
+        iters, init_seed = 5, 1021
+    torch.cuda.synchronize()
+    log(f"[bench] protocol {args.protocol}: X {dims} generated in {time.perf_counter() - t_gen:.1f} s")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    def run_als(ranks, core, s):
+        G0, F0 = workloads.als_init(dims, ranks, init_seed, "f32")
+        G = torch.from_numpy(np.ascontiguousarray(G0)).to(dev)
+        F = [torch.from_numpy(np.ascontiguousarray(A)).to(dev) for A in F0]
+        hist = []
+        for it in range(iters):
+            fms = []
+            for n in range(len(F)):
+                F[n], ms_f = timed(lambda: tk.factor_update(X, G, F, n, lam, check=False))
+                fms.append(ms_f)
+            if core == "exact":
+                G, ms_c = timed(lambda: tk.core_update_exact(X, F, lam, check=False))
+            else:
+                G, ms_c = timed(lambda: tk.core_update_sketched(
+                    X, F, lam, s, seed=7, counter=it, precision="bf16", refine_max=8,
+                    refine_tol=1e-13, check=False))
+            Lv, sq, cnt = tk.loss(X, G, F, lam)
+            hist.append({"iter": it + 1, "factor_ms": [round(v, 4) for v in fms],
+                         "core_ms": round(ms_c, 4), "rmse": (sq / cnt) ** 0.5, "loss": Lv})
+        return hist
+
+    for ranks in rank_list:
+        d = int(np.prod(ranks))
+        exact = run_als(ranks, "exact", None)
+        for s_mode in ("32d", "theory"):
+            s = 32 * d if s_mode == "32d" else tk.sample_count(d, 0.1, 0.1)
+            sk = run_als(ranks, "sketched", s)
+
+            def mean(h, key, skip=1):  # the first iteration includes warm-up
+                vals = [r[key] for r in h[skip:]]
+                return sum(vals) / len(vals)
+
+            out = {
+                "metric": "sketched core updates/sec and ALS iteration time vs exact update at "
+                          "equal loss",
+                "protocol": args.protocol,
+                "dims": list(dims), "ranks": list(ranks), "lambda": lam, "samples": s,
+                "samples_rule": "32 d" if s_mode == "32d" else "Alg. 1 count, eps = delta = 0.1",
+                "iterations": iters,
+                "mean_core_ms": {"exact": round(mean(exact, "core_ms"), 4),
+                                 "sketched": round(mean(sk, "core_ms"), 4)},
+                "mean_factor_ms": [round(sum(r["factor_ms"][n] for r in exact[1:]) /
+                                         (iters - 1), 4) for n in range(len(dims))],
+                "core_speedup": round(mean(exact, "core_ms") / mean(sk, "core_ms"), 3),
+                "final_rmse": {"exact": exact[-1]["rmse"], "sketched": sk[-1]["rmse"]},
+                "rmse_per_iteration": {"exact": [r["rmse"] for r in exact],
+                                       "sketched": [r["rmse"] for r in sk]},
+                "core_ms_per_iteration": {"exact": [r["core_ms"] for r in exact],
+                                          "sketched": [r["core_ms"] for r in sk]},
+                "data": "synthetic, generated on the device",
+            }
+            log(f"[bench] ranks {ranks} s {s}: core exact {out['mean_core_ms']['exact']:.3f} ms, "
+                f"sketched {out['mean_core_ms']['sketched']:.3f} ms, rmse "
+                f"{out['final_rmse']['exact']:.5f} / {out['final_rmse']['sketched']:.5f}")
+            print(json.dumps(out), flush=True)
+
+
+def bench_microbench(args, tk, workloads, np, torch, dev):
+    """The sampling and gather steps (a2-a4) at sizes where their HBM rate means
+    something: Alg. 1's count (s = 1687583) on the 1024^3 synthetic-protocol
+    tensor fitted at rank 4^3 (whole sampled updates, stage events), and the
+    sampler alone at s = 2^24 on the same tables.  Algorithmic bytes: the
+    sampler writes s (4 N + 8) bytes (indices and weights; the CDF tables stay
+    in LDS); the gather reads s (4 N + 8) bytes of samples plus one tensor
+    element per sample and writes 16 s bytes."""
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"[bench] copy calibration: 3 launches reading and writing {nbytes} bytes each")
+    dims, ranks = (1024, 1024, 1024), (4, 4, 4)
+    X = workloads.table1_problem_device(dims, 11, dev)["X"]
+    _, F0 = workloads.als_init(dims, ranks, 1011, "f32")
+    F = [torch.from_numpy(np.ascontiguousarray(A)).to(dev) for A in F0]
+    lam, s = 1e-3, 1687583
+    hip = HipEvents()
+    nst = tk.tucker.L.NUM_STAGE_EVENTS
+    for k in range(2):
+        tk.core_update_sketched(X, F, lam, s, seed=11, counter=k, precision="bf16",
+                                refine_max=8, refine_tol=1e-13, check=False)
+    ev = [hip.create(nst) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        tk.core_update_sketched(X, F, lam, s, seed=11, counter=100 + k, precision="bf16",
+                                refine_max=8, refine_tol=1e-13, check=False,
+                                stage_events=ctypes.addressof(ev[k]))
+    torch.cuda.synchronize()
+    st = {"sample": 0.0, "gather": 0.0}
+    for k in range(args.steps):
+        st["sample"] += hip.elapsed_ms(ev[k][1], ev[k][2]) / args.steps
+        st["gather"] += hip.elapsed_ms(ev[k][2], ev[k][3]) / args.steps
+    for e in ev:
+        hip.destroy(e)
+    N = 3
+    # the sampler alone at s = 2^24
+    _, cdf = tk.leverage_scores(F)
+    big = 1 << 24
+    tk.sample(dims, cdf, big, seed=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for k in range(reps):
+        tk.sample(dims, cdf, big, seed=2, counter=k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_big = e0.elapsed_time(e1) / reps
+    out = {
+        "microbench": "sampling and gather at Alg. 1's count (1024^3 synthetic protocol, rank 4^3)",
+        "t1_samples": s,
+        "t1_stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "t1_sample_write_GBps": round(s * (4 * N + 8) / (st["sample"] * 1e-3) / 1e9, 1),
+        "sampler_2e24_ms": round(ms_big, 4),
+        "sampler_2e24_write_GBps": round(big * (4 * N + 8) / (ms_big * 1e-3) / 1e9, 1),
+        "sampler_2e24_frac_of_8TBps": round(big * (4 * N + 8) / (ms_big * 1e-3) / 8e12, 4),
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -292,12 +292,33 @@ struct ExactWS {
 
 // largest intermediate of the mode-product chain that contracts modes in
 // decreasing order, skipping `skip` (or none when skip < 0)
+// Order of the mode products X x_m W_m^T over every mode but `skip`: the
+// longest mode first (its product shrinks X the most and reads it in long
+// runs), ties taken from the last mode down.  Returns the number of modes.
+int contraction_order(const Geom& g, int skip, int* seq) {
+  int k = 0;
+  for (int m = g.order - 1; m >= 0; --m)
+    if (m != skip) seq[k++] = m;
+  for (int a = 1; a < k; ++a) {  // stable insertion sort by decreasing size
+    const int v = seq[a];
+    int b = a;
+    while (b > 0 && g.dims[seq[b - 1]] < g.dims[v]) {
+      seq[b] = seq[b - 1];
+      --b;
+    }
+    seq[b] = v;
+  }
+  return k;
+}
+
 int64_t chain_max(const Geom& g, int skip) {
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
   int64_t mx = 1;
-  for (int m = g.order - 1; m >= 0; --m) {
-    if (m == skip) continue;
+  int seq[kMaxOrder];
+  const int nseq = contraction_order(g, skip, seq);
+  for (int k = 0; k < nseq; ++k) {
+    const int m = seq[k];
     dims[m] = g.ranks[m];
     int64_t sz = 1;
     for (int n = 0; n < g.order; ++n) sz *= dims[n];
@@ -325,7 +346,12 @@ void carve_exact(Carver& c, const Geom& g, ExactWS& w) {
   w.lam = c.take<double>(static_cast<size_t>(kMaxOrder) * kMaxRank);
   w.W = c.take<double>(g.total_q);
   w.C = c.take<double>(g.total_rr);
-  const int64_t mx = chain_max(g, -1);
+  int64_t mx = chain_max(g, -1);
+  // the masked path contracts the last mode first: its largest intermediate is
+  // X without the last mode times R_L (the masked right side and the operator's
+  // chain)
+  const int64_t masked = g.numel / g.dims[g.order - 1] * g.ranks[g.order - 1];
+  if (masked > mx) mx = masked;
   w.tA = c.take<double>(mx > g.d ? mx : g.d);
   w.tB = c.take<double>(mx > g.d ? mx : g.d);
   w.scratch = c.take<double>(kTtmScratchDoubles);
@@ -1269,14 +1295,17 @@ tk_status tucker_core_update_exact(const tk_problem* p, void* core_out, int32_t*
     launch_cast_out(g.d, G, core_out, p->dtype, st);
     return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
   }
-  // K^T vec X = X x_N W_N^T ... x_1 W_1^T (W_n = A(n) V_n), last mode first
+  // K^T vec X = X x_N W_N^T ... x_1 W_1^T (W_n = A(n) V_n), longest mode first
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
   const void* cur = p->X;
   tk_dtype cur_dt = p->dtype;
   double* bufs[2] = {w.tA, w.tB};
   int which = 0;
-  for (int m = g.order - 1; m >= 0; --m) {
+  int seq[kMaxOrder];
+  const int nseq = contraction_order(g, -1, seq);
+  for (int k = 0; k < nseq; ++k) {
+    const int m = seq[k];
     double* out = bufs[which];
     launch_ttm_any(cur, cur_dt, dims, g.order, m, w.W + g.qoff[m], g.ranks[m], true, out,
                    w.scratch, st);
@@ -1321,15 +1350,17 @@ tk_status tucker_factor_update(const tk_problem* p, const void* core, int32_t mo
   for (int n = 0; n < g.order; ++n)
     launch_cast_in(g.dims[n] * g.ranks[n], p->factors[n], p->dtype, w.A64 + g.qoff[n], st);
   launch_cast_in(g.d, core, p->dtype, w.G64, st);
-  // W = X x_{m != n} A(m)^T, modes in decreasing order
+  // W = X x_{m != n} A(m)^T, longest mode first
   int64_t dims[kMaxOrder];
   for (int n = 0; n < g.order; ++n) dims[n] = g.dims[n];
   const void* cur = p->X;
   tk_dtype cur_dt = p->dtype;
   double* bufs[2] = {w.tA, w.tB};
   int which = 0;
-  for (int m = g.order - 1; m >= 0; --m) {
-    if (m == mode) continue;
+  int seq[kMaxOrder];
+  const int nseq = contraction_order(g, mode, seq);
+  for (int k = 0; k < nseq; ++k) {
+    const int m = seq[k];
     double* out = bufs[which];
     launch_ttm_any(cur, cur_dt, dims, g.order, m, w.A64 + g.qoff[m], g.ranks[m], true, out,
                    w.scratch, st);

@@ -548,6 +548,23 @@ bool mid_skinny_launch(const T* in, int64_t P, int64_t I, int64_t Q, const doubl
 
 constexpr int64_t kTtmThreadsWanted = 65536;
 
+// Mq = M (x) I_Q in M's storage: trans (M is I x J): Mq[(i Q + q) (J Q) + j Q + q'] =
+// M[i J + j] [q == q']; else (M is J x I): Mq[(j Q + q') (I Q) + i Q + q] = M[j I + i] [q == q'].
+__global__ void kron_identity_kernel(const double* __restrict__ M, int64_t I, int64_t J, int64_t Q,
+                                     bool trans, double* __restrict__ Mq) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= I * Q * J * Q) return;
+  if (trans) {
+    const int64_t row = e / (J * Q), col = e % (J * Q);
+    const int64_t i = row / Q, q = row % Q, j = col / Q, q2 = col % Q;
+    Mq[e] = q == q2 ? M[i * J + j] : 0.0;
+  } else {
+    const int64_t row = e / (I * Q), col = e % (I * Q);
+    const int64_t j = row / Q, q2 = row % Q, i = col / Q, q = col % Q;
+    Mq[e] = q == q2 ? M[j * I + i] : 0.0;
+  }
+}
+
 template <class T>
 void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const double* M,
                   int64_t J, bool trans, double* out, double* scratch, hipStream_t st,
@@ -556,6 +573,18 @@ void ttm_dispatch(const T* in, const int64_t* dims, int order, int mode, const d
   for (int m = 0; m < mode; ++m) P *= dims[m];
   for (int m = mode + 1; m < order; ++m) Q *= dims[m];
   const int64_t I = dims[mode];
+  // A few trailing entries per fibre (Q small): read X as [P][I Q] rows and
+  // contract them with M (x) I_Q, whose output [P][J Q] is the mode product's
+  // [P][J][Q]; the rows are then long and contiguous.
+  if (Q > 1 && Q <= 4 && J * Q <= kMaxRank && P >= 64 * 256 && scratch &&
+      I * Q * J * Q <= kTtmScratchDoubles) {
+    const int64_t e = I * Q * J * Q;
+    hipLaunchKernelGGL(kron_identity_kernel, dim3(static_cast<unsigned>(cdiv(e, kBlock))),
+                       dim3(kBlock), 0, st, M, I, J, Q, trans, scratch);
+    hipLaunchKernelGGL(ttm_last_kernel<T>, dim3(static_cast<unsigned>(cdiv(P, 64))), dim3(kBlock),
+                       0, st, in, P, I * Q, scratch, J * Q, trans, out, done);
+    return;
+  }
   if (Q == 1 && J <= 8 && I * J <= 16384 && P >= 4096 &&
       skinny_launch(in, P, I, M, J, trans, out, st, done))
     return;

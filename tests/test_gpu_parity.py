@@ -411,3 +411,23 @@ def test_status_errors(tk):
         tk.core_update_sketched(X, good, 0.1, 2, idx=idx, weight=w)
     # a following good call clears the status word
     tk.core_update_sketched(X, good, 0.1, 64)
+
+
+# A tiny trailing mode (the video-shaped case): the exact update contracts the
+# longest mode first, and a product whose fibres hold at most 4 trailing entries
+# reads X as long rows against M (x) I_Q.  f32 data: bars 1e-5 element-wise.
+def test_exact_and_factor_update_tiny_last_mode(tk):
+    dims, ranks = (20, 850, 1000, 3), (2, 3, 4, 2)
+    p = workloads.tucker_tensor(dims, ranks, 61, "f32", factor="gaussian", noise=("sigma", 0.1))
+    F = [A.astype(np.float32) for A in p["factors_true"]]
+    X, FF = T(p["X"]), [T(A) for A in F]
+    X64, F64 = p["X"].astype(np.float64), [A.astype(np.float64) for A in F]
+    lam = 1e-2
+    G = tk.core_update_exact(X, FF, lam)
+    ref = oracle.core_update_exact(X64, F64, lam)
+    assert elem_err(G.cpu().numpy(), ref) <= 1e-5
+    Gc = np.random.default_rng(62).standard_normal(ranks).astype(np.float32)
+    for n in range(4):
+        A = tk.factor_update(X, T(Gc), FF, n, lam)
+        ref = oracle.factor_update(X64, Gc.astype(np.float64), F64, n, lam)
+        assert elem_err(A.cpu().numpy(), ref) <= 1e-5, n

@@ -24,6 +24,9 @@ Workloads (shapes follow the paper's experiments, Sec. 5, and the parity cases):
   1024^3 float32, fitted at rank 4^3 from the U[0,1] initial state of Alg. 2;
   lambda 1e-3; the Alg. 1 sample count for eps = delta = 0.1 at d = 64
   (1687583 samples).  Generated in mode-0 slabs with one child generator each.
+* ``movie``: a stand-in for the paper's video tensor, (100, 1080, 1920, 3)
+  float32 in [0, 1], low rank in time and colour and smooth in space, built on
+  the device (``movie_problem_device``); fitted at core (2, 4, 4, 2).
 * ``t1big``: the same protocol at 2560^3 float32 (67 GB), generated on the
   device by ``table1_problem_device`` (torch's seeded device generator, slab by
   slab); no oracle reads it.  It shows the sampled update's cost staying fixed
@@ -199,6 +202,46 @@ def table1_problem_device(dims, seed, device, true_rank=(8, 8, 8), slab_rows=64)
         X[i0:i1] = (xs + hit * noise.double()).float()
         del xs, hit, noise
     return dict(X=X, G_true=G, factors_true=A, mask=None)
+
+
+def movie_problem_device(seed, device, dims=(100, 1080, 1920, 3), components=6, sigma=0.02):
+    """Stand-in for the paper's video tensor (Sec. 5: 100 frames of 1080 x 1920
+    RGB; the dataset itself is not available): float32 in [0, 1], built on the
+    device frame by frame as
+      X[t, h, w, c] = clip(0.5 + sum_k a_k(t) s_k(h) r_k(w) q_k(c) + noise, 0, 1),
+    with slowly varying temporal weights a_k(t), smooth low-frequency spatial
+    profiles s_k, r_k (a separable picture per component), per-component colour
+    vectors q_k, and N(0, sigma^2) pixel noise.  Low rank in time and colour,
+    smooth in space; a (2, 4, 4, 2) Tucker model fits it only approximately.
+    The parameters come from default_rng(seed), the noise from a torch
+    generator seeded with seed.  Returns X (device tensor)."""
+    import torch
+    T, H, W, C = dims
+    rng = np.random.default_rng(seed)
+    tt, hh, ww = np.arange(T) / T, np.arange(H) / H, np.arange(W) / W
+    a = np.stack([0.25 * np.sin(2 * np.pi * (rng.uniform(0.2, 1.5) * tt + rng.random()))
+                  for _ in range(components)])                       # (K, T)
+    sh = np.stack([np.cos(2 * np.pi * (rng.uniform(0.3, 2.5) * hh + rng.random()))
+                   for _ in range(components)])                      # (K, H)
+    sw = np.stack([np.cos(2 * np.pi * (rng.uniform(0.3, 2.5) * ww + rng.random()))
+                   for _ in range(components)])                      # (K, W)
+    q = rng.random((components, C))                                  # (K, C)
+    dev_a = torch.from_numpy(a).to(device)
+    S = torch.from_numpy(sh).to(device)
+    R = torch.from_numpy(sw).to(device)
+    Q = torch.from_numpy(q).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    X = torch.empty(dims, dtype=torch.float32, device=device)
+    for t in range(T):
+        # frame t: sum_k a_k(t) s_k(h) r_k(w) q_k(c), elementwise broadcasts only
+        f = torch.full((H, W, C), 0.5, dtype=torch.float64, device=device)
+        for k in range(components):
+            f += dev_a[k, t] * (S[k][:, None, None] * R[k][None, :, None] * Q[k][None, None, :])
+        f += sigma * torch.randn(f.shape, generator=gen, device=device, dtype=torch.float64)
+        X[t] = f.clamp_(0.0, 1.0).float()
+        del f
+    return X
 
 
 def als_init(dims, ranks, init_seed, dtype="f64"):
