@@ -334,6 +334,18 @@ __device__ inline void load_block(const double* M, int64_t d, int64_t i0, int ri
       }
 }
 
+// Published data is stored with agent-scope atomic stores, which write through
+// this XCD's L2 to the device's coherence point, and read with agent-scope
+// atomic loads (load_tile).  Such a store is visible to every reader once it has
+// completed, so a publisher waits for its own stores to complete (s_waitcnt) and
+// then raises the flag: no L2 writeback fence is needed, which would write back
+// every dirty line of the XCD's L2 at each publication.
+__device__ inline void pub_store(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // M rows [i0, i0 + ri) of column block j = S Li^T, S in the accumulator layout
 // staged through X; Li (64 x 64) in LDS
 __device__ inline void apply_inverse_store(double* M, int64_t d, int64_t i0, int ri, int64_t j0,
@@ -358,22 +370,22 @@ __device__ inline void apply_inverse_store(double* M, int64_t d, int64_t i0, int
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = acc_r(x, v), c = acc_c(y);
-        if (r < ri) M[(i0 + r) * d + j0 + c] = acc[x][y][v];
+        if (r < ri) pub_store(&M[(i0 + r) * d + j0 + c], acc[x][y][v]);
       }
 }
 
-// Release at agent scope: this thread's stores are written back from L2
-// before anything after the fence.  Readers take published data with coherent
-// (agent-scope atomic) loads, so no invalidation is needed here; a full fence
-// would also invalidate this XCD's L2 at every publication.
-__device__ inline void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+// Wait until every memory operation this wave issued has completed.
+__device__ inline void complete_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
-// Raise a tile's flag once every thread's stores to it are visible.
+// Raise a tile's flag once every thread's (write-through) stores to it completed.
 __device__ inline void publish_tile(int32_t* flag) {
-  release_fence();
+  complete_stores();
   __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // tickets of column j: tiles (i, j) for i >= j + 2, then the finished
@@ -386,6 +398,20 @@ __host__ __device__ inline int64_t chol_flow_tasks(int64_t nblk) {
   int64_t n = 0;
   for (int64_t j = 0; j < nblk; ++j) n += chol_column_tickets(nblk, j);
   return n;
+}
+
+// S (accumulator layout) as a row-major 64 x 64 tile in device memory, published
+// with write-through stores (rows past `rows` zero)
+__device__ inline void store_block_pub(double* dst, int ld, int rows, const double (&S)[2][2][4]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = acc_r(x, v), c = acc_c(y);
+        pub_store(&dst[r * ld + c], r < rows ? S[x][y][v] : 0.0);
+      }
 }
 
 // S (accumulator layout) as a row-major 64 x 64 tile (rows past `rows` zero)
@@ -485,8 +511,8 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       double* Lo = Linv_diag + j * NB * NB;
       for (int r = ty; r < NB; r += 16)
         for (int c = tx; c < NB; c += 16) {
-          Lo[r * NB + c] = (c <= r) ? Lb[r * LDA + c] : 0.0;
-          if (r < rj && c <= r) M[(j0 + r) * d + j0 + c] = La[r * LDA + c];
+          pub_store(&Lo[r * NB + c], (c <= r) ? Lb[r * LDA + c] : 0.0);
+          if (r < rj && c <= r) pub_store(&M[(j0 + r) * d + j0 + c], La[r * LDA + c]);
         }
       if (tid == 0) {
         if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
@@ -527,14 +553,14 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
             const int r = acc_r(x, v), c = acc_c(y);
             const double val = r < r1 ? acc[x][y][v] : 0.0;
             Lc[r * LDA + c] = val;
-            if (r < r1) M[(i10 + r) * d + j0 + c] = val;
+            if (r < r1) pub_store(&M[(i10 + r) * d + j0 + c], val);
           }
-      release_fence();
+      complete_stores();
       __syncthreads();
       if (tid == 0) {
-        __hip_atomic_store(&tile_flag[tile_flag_index(j, j)], 1, __ATOMIC_RELEASE,
+        __hip_atomic_store(&tile_flag[tile_flag_index(j, j)], 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&tile_flag[tile_flag_index(j + 1, j)], 1, __ATOMIC_RELEASE,
+        __hip_atomic_store(&tile_flag[tile_flag_index(j + 1, j)], 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -582,7 +608,7 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
         stage_tile(M, d, c0, rc, j, Lb);
         __syncthreads();
         sub_gemm_nt(La, Lb, S);
-        store_block(P1, NB, NB, S);
+        store_block_pub(P1, NB, NB, S);
         publish_tile(&post_flag[c * kFlagStride]);
       } else if (off < ntile) {
         // tile (i, j), i >= j + 2 (block j is full)
@@ -632,8 +658,8 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
           if (next) sub_gemm_nt(Lb, La, Sn);
           __syncthreads();
         }
-        store_block(pre + (2 * c) * NB * NB, NB, NB, Sd);
-        if (next) store_block(pre + (2 * c + 1) * NB * NB, NB, NB, Sn);
+        store_block_pub(pre + (2 * c) * NB * NB, NB, NB, Sd);
+        if (next) store_block_pub(pre + (2 * c + 1) * NB * NB, NB, NB, Sn);
         publish_tile(&pre_flag[c * kFlagStride]);
       }
     }
@@ -689,12 +715,6 @@ __device__ inline bool load_published(const double* p, int n, double* v) {
     }
   }
   return true;
-}
-
-__device__ inline void publish(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The chain matrices of the two solves, one pair per 64-row block i (their
@@ -809,7 +829,7 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
   part[q][r] = acc;
   __syncthreads();
   if (tid < NB) acc_s[tid] = bv - (part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid]);
-  if (q == 0 && r < rows) publish(x + i0 + r, __longlong_as_double(kPending));
+  if (q == 0 && r < rows) pub_store(x + i0 + r, __longlong_as_double(kPending));
   __syncthreads();
   // u = Li acc: row rr, four partial sums over c
   {
@@ -832,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void trsv_lower_kernel(const double* __rest
   chain[q][r] = v;
   __syncthreads();
   if (q == 0 && r < rows)
-    publish(y + i0 + r, u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r])));
+    pub_store(y + i0 + r, u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r])));
   if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
@@ -931,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void trsv_upper_kernel(const double* __rest
   __syncthreads();
   if (q == 0 && r < rows) {
     const double xv = u_s[r] - ((chain[0][r] + chain[1][r]) + (chain[2][r] + chain[3][r]));
-    publish(x + i0 + r, xv);
+    pub_store(x + i0 + r, xv);
     if (accum) accum[i0 + r] += xv;
   }
   if (!ok) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
