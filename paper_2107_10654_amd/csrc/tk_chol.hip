@@ -22,10 +22,10 @@ constexpr int LDA = NB + 1;
 // Blocked over four 16-column panels.  Wave 0 factors each 16 x 16 diagonal
 // panel in registers, lane r owning row r (each 16-lane row of the wave holds a
 // copy), with DPP row broadcasts in place of barriers, and eliminates the
-// panel's inverse alongside.  The rows below the panel and the trailing
-// triangle are then 16 x 16 FP64 MFMA block products, one block per wave; the
-// off-diagonal blocks of the 64 x 64 inverse follow the same way, one block
-// column per wave.
+// panel's inverse alongside.  The rows below the panel, the trailing triangle
+// and the off-diagonal blocks of the 64 x 64 inverse are 16 x 16 FP64 MFMA
+// block products, done by the other waves while wave 0 factors the next panel
+// where the dependencies allow.
 constexpr int PB = 16;
 
 // value of v in lane c of this lane's 16-lane row (c a constant after unrolling):
@@ -56,11 +56,10 @@ __device__ inline double row_value(double v, int c) {
   }
 }
 
-// 1 / sqrt(x) for x > 0 to FP64 accuracy: the hardware estimate refined by
-// two Newton steps (each doubles the correct bits), in place of a square root
-// followed by IEEE divisions on the factorisation's serial chain
-__device__ inline double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
+// Newton steps for 1 / sqrt(x) from the hardware estimate y (each step
+// doubles the correct bits), in place of a square root followed by IEEE
+// divisions on the factorisation's serial chain
+__device__ inline double rsqrt_refine(double x, double y) {
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const double e = fma(-x * y, y, 1.0);
@@ -69,10 +68,146 @@ __device__ inline double rsqrt_f64(double x) {
   return y;
 }
 
+// Factor the 16 x 16 diagonal panel at (c0, c0) of A and invert it into Li
+// (one wave).  Lane (g, r) = (lane / 16, lane % 16) holds row r of the panel;
+// the four 16-lane rows repeat the factorisation, and each eliminates its own
+// four columns 4 g .. 4 g + 3 of the inverse: Z, the forward elimination of
+// L Z' = I without the final row scaling, so row j of the inverse is
+// Z[j] / L[j][j].  The column after the pivot is updated first and its
+// reciprocal square root estimate issued before the rest of the pivot's
+// updates, which then hide that estimate's latency; the Newton steps follow
+// them (the scheduling barriers keep this order).
+__device__ __attribute__((always_inline)) inline void panel_factor(double* A, double* Li, int c0,
+                                                                  int lane, int* bad_s,
+                                                                  double* pmin_s) {
+  const int r = lane & 15, g = lane >> 4;
+  double a[PB];
+#pragma unroll
+  for (int c = 0; c < PB; ++c) a[c] = (c <= r) ? A[(c0 + r) * LDA + c0 + c] : 0.0;
+  double z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = (4 * g + k == r) ? 1.0 : 0.0;
+  double pm = 1e308;
+  bool nb_ = false;
+  double yr = 1.0;  // 1 / L[r][r]
+  double pj = row_value(a[0], 0);
+  if (!(pj > 0.0)) {
+    nb_ = true;
+    pj = 1.0;
+  }
+  double y = rsqrt_refine(pj, __builtin_amdgcn_rsq(pj));
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    const double ljj = pj * y;
+    pm = fmin(pm, ljj);
+    const double lj = (r == j) ? ljj : (r > j ? a[j] * y : 0.0);
+    a[j] = (r >= j) ? lj : 0.0;
+    if (r == j) yr = y;
+    double pn = 1.0, yn = 1.0;
+    if (j + 1 < PB) {
+      // entries above the diagonal (c > r) are never read again and are
+      // zeroed when their column is reached, so no select is needed here
+      a[j + 1] = fma(-lj, row_value(lj, j + 1), a[j + 1]);
+      pn = row_value(a[j + 1], j + 1);
+      if (!(pn > 0.0)) {
+        nb_ = true;
+        pn = 1.0;
+      }
+      yn = __builtin_amdgcn_rsq(pn);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the broadcasts first, each into its own register, so that they issue
+    // back to back instead of each waiting for the previous product
+    double bl[PB], bz[4];
+#pragma unroll
+    for (int c = j + 2; c < PB; ++c) bl[c] = row_value(lj, c);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bz[k] = row_value(z[k], j);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = j + 2; c < PB; ++c) a[c] = fma(-lj, bl[c], a[c]);
+    // rows below j: Z[r] -= L[r][j] (Z[j] / L[j][j]); Z[j] is final here and
+    // zero past column j
+    const double mj = (r > j) ? lj * y : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] = fma(-mj, bz[k], z[k]);
+    __builtin_amdgcn_sched_barrier(0);
+    if (j + 1 < PB) {
+      y = rsqrt_refine(pn, yn);
+      pj = pn;
+    }
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int c = 0; c < PB; ++c) A[(c0 + r) * LDA + c0 + c] = (c <= r) ? a[c] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Li[(c0 + r) * LDA + c0 + 4 * g + k] = z[k] * yr;  // row r
+  if (lane == 0) {
+    if (nb_) *bad_s = 1;
+    *pmin_s = fmin(*pmin_s, pm);
+  }
+}
+
+// rows below panel c0, block at row R: X = A[R.., c0:c0+16] Li_pp^T, written
+// over its own operand (the wave reads all of it first)
+__device__ inline void rows_below(double* A, const double* Li, int c0, int R, int lr, int lk) {
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < PB / 4; ++kk)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(R + lr) * LDA + c0 + 4 * kk + lk],
+                                               Li[(c0 + lr) * LDA + c0 + 4 * kk + lk], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + c0 + lr] = acc[v];
+}
+
+// trailing update of block (R, C) by panel c0: A_RC -= L_R,p L_C,p^T (a
+// diagonal block is updated whole; its upper half is never read)
+__device__ inline void trail_block(double* A, int c0, int R, int C, int lr, int lk) {
+  doublex4 acc;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = A[(R + lk + 4 * v) * LDA + C + lr];
+#pragma unroll
+  for (int kk = 0; kk < PB / 4; ++kk)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(R + lr) * LDA + c0 + 4 * kk + lk],
+                                               A[(C + lr) * LDA + c0 + 4 * kk + lk], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + C + lr] = acc[v];
+}
+
+// off-diagonal block (bi, bj) of the inverse, Li_ij = -Li_ii sum_{q=j}^{i-1} L_iq Li_qj,
+// from the finished block rows of L and earlier block rows of the inverse
+__device__ inline void inv_block(const double* A, double* Li, int bi, int bj, int lr, int lk) {
+  doublex4 sacc = {0.0, 0.0, 0.0, 0.0};
+  for (int q = bj; q < bi; ++q)
+#pragma unroll
+    for (int kk = 0; kk < PB / 4; ++kk)
+      sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(bi * PB + lr) * LDA + q * PB + 4 * kk + lk],
+                                                  Li[(q * PB + 4 * kk + lk) * LDA + bj * PB + lr],
+                                                  sacc, 0, 0, 0);
+  // the accumulator's register v holds row 4 v + lk of the sum in lane
+  // (lk, lr): exactly the B operand of the k-slice v
+  doublex4 o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < PB / 4; ++kk)
+    o = __builtin_amdgcn_mfma_f64_16x16x4f64(-Li[(bi * PB + lr) * LDA + bi * PB + 4 * kk + lk],
+                                             sacc[kk], o, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Li[(bi * PB + lk + 4 * v) * LDA + bj * PB + lr] = o[v];
+}
+
 // Factor and invert the 64 x 64 block held in LDS A (lower triangle; rows past
 // the matrix hold the identity): on return A holds L and Li holds L^{-1}.
 // Li must be zero and *bad / *pmin initialised.  Entries of A above the
 // diagonal are scratch (never read).
+//
+// Blocked over four 16-column panels p.  Wave 0 factors panel p while waves
+// 1..3 finish what panel p - 1 left: its trailing update (all blocks but the
+// next diagonal one, which wave 0 updated itself right after the rows below)
+// and block row p - 1 of the inverse.  Then the rows below panel p are
+// 16 x 16 FP64 MFMA products, one block per wave.  Each phase touches blocks
+// the concurrent one does not, and a barrier separates a block's producer from
+// its readers.
 __device__ __attribute__((always_inline)) inline void diag_factor(double* A, double* Li, int* bad_s,
                                                                 double* pmin_s) {
   const int tid = threadIdx.x;
@@ -80,125 +215,40 @@ __device__ __attribute__((always_inline)) inline void diag_factor(double* A, dou
   // FP64 MFMA 16x16x4 operand lanes: row / column lr, k-slice lk; accumulator
   // register v holds row lk + 4 v, column lr
   const int lr = lane & 15, lk = lane >> 4;
-  int& bad = *bad_s;
-  double& pmin = *pmin_s;
-  for (int p = 0; p < NB / PB; ++p) {
+  constexpr int NP = NB / PB;
+  for (int p = 0; p < NP; ++p) {
     const int c0 = p * PB;
-    // (1) factor the 16 x 16 diagonal panel and invert it (wave 0, lane r = row r)
     if (wave == 0) {
-      const int r = lane & 15;
-      double a[PB];
-#pragma unroll
-      for (int c = 0; c < PB; ++c) a[c] = (c <= r) ? A[(c0 + r) * LDA + c0 + c] : 0.0;
-      double pm = 1e308;
-      bool nb_ = false;
-      // the inverse is eliminated alongside the factor: lane r holds row r of
-      // Z, the forward elimination of L Z' = I without the final row scaling,
-      // so row j of the inverse is Z[j] / L[j][j] once column j is factored
-      double z[PB];
-#pragma unroll
-      for (int c = 0; c < PB; ++c) z[c] = (c == r) ? 1.0 : 0.0;
-      double yr = 1.0;  // 1 / L[r][r]
-#pragma unroll
-      for (int j = 0; j < PB; ++j) {
-        double pj = row_value(a[j], j);
-        if (!(pj > 0.0)) {
-          nb_ = true;
-          pj = 1.0;
+      panel_factor(A, Li, c0, lane, bad_s, pmin_s);
+    } else if (p > 0) {
+      // panel p - 1's trailing blocks (i, j), p <= j <= i < NP, but (p, p);
+      // then the blocks (p - 1, bj), bj < p - 1, of the inverse
+      const int m = NP - p;
+      const int ntr = m * (m + 1) / 2 - 1;
+      const int nitems = ntr + (p - 1);
+      for (int t = wave - 1; t < nitems; t += kBlock / 64 - 1) {
+        if (t < ntr) {
+          const int u = t + 1;
+          int i = 0;
+          while ((i + 1) * (i + 2) / 2 <= u) ++i;
+          const int j = u - i * (i + 1) / 2;
+          trail_block(A, c0 - PB, c0 + i * PB, c0 + j * PB, lr, lk);
+        } else {
+          inv_block(A, Li, p - 1, t - ntr, lr, lk);
         }
-        const double y = rsqrt_f64(pj);
-        const double ljj = pj * y;
-        pm = fmin(pm, ljj);
-        const double lj = (r == j) ? ljj : (r > j ? a[j] * y : 0.0);
-        a[j] = (r >= j) ? lj : 0.0;
-        if (r == j) yr = y;
-#pragma unroll
-        for (int c = j + 1; c < PB; ++c) {
-          // entries above the diagonal (c > r) are never read again and are
-          // zeroed when their column is reached, so no select is needed here
-          a[c] = fma(-lj, row_value(lj, c), a[c]);
-        }
-        // rows below j: Z[r] -= L[r][j] (Z[j] / L[j][j]); Z[j] is final here
-        const double mj = (r > j) ? lj * y : 0.0;
-#pragma unroll
-        for (int c = 0; c <= j; ++c) z[c] = fma(-mj, row_value(z[c], j), z[c]);
-      }
-      if (lane < PB) {
-#pragma unroll
-        for (int c = 0; c < PB; ++c) {
-          A[(c0 + r) * LDA + c0 + c] = (c <= r) ? a[c] : 0.0;
-          Li[(c0 + r) * LDA + c0 + c] = z[c] * yr;  // row r of the inverse
-        }
-      }
-      if (lane == 0) {
-        if (nb_) bad = 1;
-        pmin = fmin(pmin, pm);
       }
     }
     __syncthreads();
-    const int nbl = NB / PB - 1 - p;  // 16-row blocks below the panel
+    const int nbl = NP - 1 - p;  // 16-row blocks below the panel
     if (nbl > 0) {
-      // (2) rows below, one block per wave: X = A[rows, c0:c0+16] Li_pp^T,
-      // written over its own operand (the wave reads all of it first)
-      if (wave < nbl) {
-        const int R = c0 + PB + wave * PB;
-        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < PB / 4; ++kk)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(R + lr) * LDA + c0 + 4 * kk + lk],
-                                                     Li[(c0 + lr) * LDA + c0 + 4 * kk + lk], acc,
-                                                     0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + c0 + lr] = acc[v];
-      }
+      if (wave < nbl) rows_below(A, Li, c0, c0 + PB + wave * PB, lr, lk);
       __syncthreads();
-      // (3) trailing update of the blocks (i, j), j <= i, below and right of
-      // the panel; diagonal blocks are updated whole (their upper halves are
-      // never read)
-      const int nt = nbl * (nbl + 1) / 2;
-      for (int t = wave; t < nt; t += kBlock / 64) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
-        const int j = t - i * (i + 1) / 2;
-        const int R = c0 + PB + i * PB, C = c0 + PB + j * PB;
-        doublex4 acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = A[(R + lk + 4 * v) * LDA + C + lr];
-#pragma unroll
-        for (int kk = 0; kk < PB / 4; ++kk)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(R + lr) * LDA + c0 + 4 * kk + lk],
-                                                     A[(C + lr) * LDA + c0 + 4 * kk + lk], acc,
-                                                     0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) A[(R + lk + 4 * v) * LDA + C + lr] = acc[v];
-      }
-      __syncthreads();
+      // the next diagonal block, which the next panel factor needs first
+      if (wave == 0) trail_block(A, c0, c0 + PB, c0 + PB, lr, lk);
     }
   }
-  // (4) off-diagonal blocks of the inverse, Li_ij = -Li_ii sum_{q=j}^{i-1} L_iq Li_qj:
-  // wave w fills block column w top down, reading only blocks it wrote itself
-  // (and the diagonal inverses), so the columns need no barrier between rows
-  if (wave < NB / PB - 1) {
-    const int bj = wave;
-    for (int bi = bj + 1; bi < NB / PB; ++bi) {
-      doublex4 sacc = {0.0, 0.0, 0.0, 0.0};
-      for (int q = bj; q < bi; ++q)
-#pragma unroll
-        for (int kk = 0; kk < PB / 4; ++kk)
-          sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              A[(bi * PB + lr) * LDA + q * PB + 4 * kk + lk],
-              Li[(q * PB + 4 * kk + lk) * LDA + bj * PB + lr], sacc, 0, 0, 0);
-      // the accumulator's register v holds row 4 v + lk of the sum in lane
-      // (lk, lr): exactly the B operand of the k-slice v
-      doublex4 o = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < PB / 4; ++kk)
-        o = __builtin_amdgcn_mfma_f64_16x16x4f64(-Li[(bi * PB + lr) * LDA + bi * PB + 4 * kk + lk],
-                                                 sacc[kk], o, 0, 0, 0);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Li[(bi * PB + lk + 4 * v) * LDA + bj * PB + lr] = o[v];
-    }
-  }
+  // the last block row of the inverse
+  if (wave < NP - 1) inv_block(A, Li, NP - 1, wave, lr, lk);
   __syncthreads();
 }
 
