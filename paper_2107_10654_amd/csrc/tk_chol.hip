@@ -520,6 +520,7 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
   if (task_s == 0) {
     // ---------------- the chain (Lc holds L_{j,j-1} from the previous column)
     __builtin_amdgcn_s_setprio(3);
+    double Sd_next[2][2][4];  // partial sums of the next diagonal tile
     for (int64_t j = 0; j < nblk; ++j) {
       const int64_t j0 = j * NB;
       const int rj = rows_of(j);
@@ -528,15 +529,13 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       const int r1 = next ? rows_of(j + 1) : 0;
       double Sd[2][2][4];
       if (j >= 2) {
-        wait2(&pre_flag[j * kFlagStride], nullptr);
-        const double* P0 = pre + (2 * j) * NB * NB;
+        // loaded during the previous column (with its S_{j,j-1})
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              Sd[x][y][v] = load_tile(&P0[acc_r(x, v) * NB + acc_c(y)]);
+            for (int v = 0; v < 4; ++v) Sd[x][y][v] = Sd_next[x][y][v];
       } else {
         load_block(M, d, j0, rj, j0, rj, Sd);
       }
@@ -558,12 +557,31 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       }
       __syncthreads();
       diag_factor(La, Lb, &bad, &pmin);
-      double* Lo = Linv_diag + j * NB * NB;
-      for (int r = ty; r < NB; r += 16)
-        for (int c = tx; c < NB; c += 16) {
-          pub_store(&Lo[r * NB + c], (c <= r) ? Lb[r * LDA + c] : 0.0);
-          if (r < rj && c <= r) pub_store(&M[(j0 + r) * d + j0 + c], La[r * LDA + c]);
+      {
+        // this thread's entries (ty + 16 a, tx + 16 b): all LDS reads first,
+        // then the stores
+        double* Lo = Linv_diag + j * NB * NB;
+        double lo_v[4][4], m_v[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int r = ty + 16 * a, c = tx + 16 * b;
+            lo_v[a][b] = (c <= r) ? Lb[r * LDA + c] : 0.0;
+            m_v[a][b] = La[r * LDA + c];
+          }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int r = ty + 16 * a;
+          double* Mrow = M + (j0 + r) * d + j0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int c = tx + 16 * b;
+            pub_store(&Lo[r * NB + c], lo_v[a][b]);
+            if (r < rj && c <= r) pub_store(&Mrow[c], m_v[a][b]);
+          }
         }
+      }
       if (tid == 0) {
         if (bad) atomicMax(status, static_cast<int32_t>(TK_E_NOT_SPD));
         atomicMin(reinterpret_cast<unsigned long long*>(min_pivot),
@@ -575,8 +593,11 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       }
       // S_{j+1,j}: A_{1,0}, or the scratch block its ticketed task finished
       double Sn[2][2][4];
+      if (j >= 1) wait2(&post_flag[j * kFlagStride], nullptr);
+      // (j, j) is published now (its stores have had the wait to complete), so
+      // that the tiles of column j start before this column's last tile
+      publish_tile(&tile_flag[tile_flag_index(j, j)]);
       if (j >= 1) {
-        wait2(&post_flag[j * kFlagStride], nullptr);
         const double* P1 = pre + (2 * j + 1) * NB * NB;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -588,12 +609,25 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
       } else {
         load_block(M, d, i10, r1, j0, rj, Sn);
       }
-      // L_{j+1,j} = S_{j+1,j} Li_jj^T: stored, kept in Lc, published with (j, j)
+      // L_{j+1,j} = S_{j+1,j} Li_jj^T: stored, kept in Lc, published as (j + 1, j)
       __syncthreads();  // every wave is done reading Lc (the previous tile)
       store_block(Ld, LDA, r1, Sn);
       __syncthreads();
       doublex4 acc[2][2];
       tile_gemm_nt(Ld, Lb, acc);
+      if (j >= 1) {
+        // the partial sums of S_{j+1,j+1}: their loads complete with this
+        // tile's stores below
+        wait2(&pre_flag[(j + 1) * kFlagStride], nullptr);
+        const double* P0 = pre + (2 * (j + 1)) * NB * NB;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              Sd_next[x][y][v] = load_tile(&P0[acc_r(x, v) * NB + acc_c(y)]);
+      }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -607,12 +641,9 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
           }
       complete_stores();
       __syncthreads();
-      if (tid == 0) {
-        __hip_atomic_store(&tile_flag[tile_flag_index(j, j)], 1, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0)
         __hip_atomic_store(&tile_flag[tile_flag_index(j + 1, j)], 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-      }
     }
   } else {
     // ---------------- ticketed tasks
