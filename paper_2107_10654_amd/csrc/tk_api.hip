@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "tk_internal.h"
 
 namespace tk {
@@ -1026,6 +1028,72 @@ void carve_batch(Carver& c, const tk_problem* probs, const tk_sketch_opts* opts,
   index = c.take<int64_t>(sk_index_bytes(b) / sizeof(int64_t));
 }
 
+// Streams the per-problem chains of a batch spread over: the caller's stream
+// plus kAuxStreams of the library's own (default priority, created once per
+// device, kept until the process ends).  Work joins them through events
+// recorded on the caller's stream and waited for there again at the end, so
+// the call stays one stream's worth of ordered work (and capturable into a
+// graph).  The events are reused, so one batched call enqueues at a time per
+// device.
+constexpr int kAuxStreams = 3;
+constexpr int kAuxMaxDevices = 64;
+struct AuxPool {
+  std::mutex mu;
+  bool ready = false;
+  hipStream_t s[kAuxStreams];
+  hipEvent_t fork;
+  hipEvent_t join[kAuxStreams];
+};
+AuxPool g_aux[kAuxMaxDevices];
+std::mutex g_aux_init_mu;
+
+// The current device's pool, created on first use; none (the chains then run
+// on the caller's stream alone) if that first use is under stream capture or
+// creation fails.
+AuxPool* aux_pool(hipStream_t st) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kAuxMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_aux_init_mu);
+  AuxPool& p = g_aux[dev];
+  if (!p.ready) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return nullptr;
+    if (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    for (int i = 0; i < kAuxStreams; ++i) {
+      if (hipStreamCreateWithFlags(&p.s[i], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming) != hipSuccess)
+        return nullptr;  // the objects made so far stay until the process ends
+    }
+    p.ready = true;
+  }
+  return &p;
+}
+
+// Problem k's stream, and the fork / join of the streams in use.
+struct Spread {
+  AuxPool* pool;
+  hipStream_t st;
+  int n;  // streams in use, the caller's first
+  hipStream_t stream(int k) const {
+    const int i = k % n;
+    return i == 0 ? st : pool->s[i - 1];
+  }
+  bool fork() const {
+    if (n <= 1) return true;
+    bool ok = hipEventRecord(pool->fork, st) == hipSuccess;
+    for (int i = 0; i + 1 < n; ++i) ok = ok && hipStreamWaitEvent(pool->s[i], pool->fork, 0) == hipSuccess;
+    return ok;
+  }
+  bool join() const {
+    bool ok = true;
+    for (int i = 0; i + 1 < n; ++i)
+      ok = ok && hipEventRecord(pool->join[i], pool->s[i]) == hipSuccess &&
+           hipStreamWaitEvent(st, pool->join[i], 0) == hipSuccess;
+    return ok;
+  }
+};
+
 size_t batch_bytes(const tk_problem* probs, const tk_sketch_opts* opts, int32_t count,
                    const SkConfig& cfg) {
   SketchRun runs[kSkMaxBatch];
@@ -1196,32 +1264,51 @@ tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_
   Carver c(ws);
   carve_batch(c, probs, opts, count, conf, runs, dev_status, stream, b, slots, index);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // steps 1-3 per problem
-  for (int k = 0; k < count; ++k) {
-    stt = sketch_pre(runs[k], &probs[k], nullptr, nullptr, nullptr, nullptr);
-    if (stt != TK_OK) return stt;
+  // The problems' chains are independent (each has its own workspace and
+  // status word; the partial slots are only read after the Gram), so they
+  // run spread over several streams.
+  Spread sp{aux_pool(st), st, 1};
+  std::unique_lock<std::mutex> pool_lock;
+  if (sp.pool) {
+    pool_lock = std::unique_lock<std::mutex>(sp.pool->mu);
+    sp.n = count < kAuxStreams + 1 ? count : kAuxStreams + 1;
   }
+  // steps 1-3 per problem
+  if (!sp.fork()) return TK_E_HIP;
+  for (int k = 0; k < count; ++k) {
+    runs[k].st = sp.stream(k);
+    stt = sketch_pre(runs[k], &probs[k], nullptr, nullptr, nullptr, nullptr);
+    if (stt != TK_OK) {
+      sp.join();
+      return stt;
+    }
+  }
+  if (!sp.join()) return TK_E_HIP;
   // step 4 for the whole batch: one persistent stream-K launch
   launch_gram_sk(b, slots, index, st);
   // steps 4 (assembly) to 8 per problem
+  if (!sp.fork()) return TK_E_HIP;
   for (int k = 0; k < count; ++k) {
     SketchRun& R = runs[k];
     const tk_problem* p = &probs[k];
-    launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, R.lam_sys, R.w.M, st);
+    hipStream_t sk = sp.stream(k);
+    R.st = sk;
+    launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, R.lam_sys, R.w.M, sk);
     sketch_factor(R);
     refined_solve(R, R.lam_sys, nullptr, R.w.xw, R.w.rhs, R.w.h);
     if (core_chain_small_ok(R.g)) {
-      launch_core_chain_small(R.g, R.w.h, R.w.lev.Linv, true, core_out[k], p->dtype, st);
+      launch_core_chain_small(R.g, R.w.h, R.w.lev.Linv, true, core_out[k], p->dtype, sk);
     } else {
-      launch_copy_f64(R.g.d, R.w.h, R.w.ph_a, st);
+      launch_copy_f64(R.g.d, R.w.h, R.w.ph_a, sk);
       const double* gres =
-          core_chain(R.g, R.w.ph_a, R.w.ph_b, R.w.lev.Linv, true, R.w.ttm_scratch, st);
-      launch_cast_out(R.g.d, gres, core_out[k], p->dtype, st);
+          core_chain(R.g, R.w.ph_a, R.w.ph_b, R.w.lev.Linv, true, R.w.ttm_scratch, sk);
+      launch_cast_out(R.g.d, gres, core_out[k], p->dtype, sk);
     }
     if (dev_info)
       launch_info(dev_info + static_cast<int64_t>(k) * TK_INFO_LEN, R.s, R.w.missing, R.w.steps,
-                  R.w.relres, R.w.min_pivot, st);
+                  R.w.relres, R.w.min_pivot, sk);
   }
+  if (!sp.join()) return TK_E_HIP;
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
