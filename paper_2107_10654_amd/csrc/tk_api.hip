@@ -777,6 +777,7 @@ struct SketchRun {
   Geom ga;
   const double* q64s = nullptr;  // whitened row tables the sample-side kernels read
   double lam_sys = 0.0;          // lambda of the assembled and refined system
+  int chol_grid = 0;             // cap of the Cholesky's workgroups (0: one per CU)
   void stage(int k) const {
     if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
   }
@@ -867,7 +868,7 @@ void sketch_factor(SketchRun& R) {
     launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
   // 6. FP64 Cholesky
-  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st);
+  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st, R.chol_grid);
   R.stage(6);
 }
 
@@ -1293,6 +1294,9 @@ tk_status tucker_core_update_sketched_batched(const tk_problem* probs, const tk_
     const tk_problem* p = &probs[k];
     hipStream_t sk = sp.stream(k);
     R.st = sk;
+    // concurrent Cholesky launches share the CUs (their task workers would
+    // otherwise hold every CU while spinning on their chains)
+    if (sp.n > 1) R.chol_grid = device_cu_count() / sp.n;
     launch_assemble_sk(b, k, R.g, slots, index, R.w.lev.P, R.lam_sys, R.w.M, sk);
     sketch_factor(R);
     refined_solve(R, R.lam_sys, nullptr, R.w.xw, R.w.rhs, R.w.h);

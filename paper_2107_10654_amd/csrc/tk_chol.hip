@@ -748,10 +748,11 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
   if (tid == 0 && failed) atomicMax(status, static_cast<int32_t>(TK_E_HIP));
 }
 
-int chol_flow_grid(int64_t nblk) {
+int chol_flow_grid(int64_t nblk, int max_grid) {
   const int cus = device_cu_count();
   const int64_t ntasks = chol_flow_tasks(nblk);
-  const int64_t g = cus;  // one workgroup per CU: the serial panel factor keeps its SIMD
+  int64_t g = cus;  // one workgroup per CU: the serial panel factor keeps its SIMD
+  if (max_grid > 0 && max_grid < g) g = max_grid < 2 ? 2 : max_grid;
   return static_cast<int>(1 + ntasks < g ? 1 + ntasks : g);  // the chain + ticketed tasks
 }
 
@@ -1049,14 +1050,14 @@ __global__ void solve_init_kernel(int32_t* flags, double* y, int64_t d, const in
 }  // namespace
 
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
-                     int32_t* flags, hipStream_t st) {
+                     int32_t* flags, hipStream_t st, int max_grid) {
   const int64_t nblk = cdiv(d, NB);
   int32_t* ff = flags + 2;  // flags[0..1] are the solves' tickets
   const int64_t nflags = (1 + nblk * (nblk + 1) / 2 + 2 * nblk) * kFlagStride;
   hipLaunchKernelGGL(chol_flags_kernel, dim3(static_cast<unsigned>(cdiv(nflags, kBlock))),
                      dim3(kBlock), 0, st, ff, nflags);
   double* pre = Linv_diag + 3 * nblk * NB * NB;  // past the inverses and chain matrices
-  hipLaunchKernelGGL(chol_flow_kernel, dim3(static_cast<unsigned>(chol_flow_grid(nblk))),
+  hipLaunchKernelGGL(chol_flow_kernel, dim3(static_cast<unsigned>(chol_flow_grid(nblk, max_grid))),
                      dim3(kBlock), 0, st, M, d, nblk, Linv_diag, pre, min_pivot, status, ff);
   hipLaunchKernelGGL(chol_chain_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st,
                      static_cast<const double*>(M), d, nblk, Linv_diag);

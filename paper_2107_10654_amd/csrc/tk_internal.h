@@ -261,8 +261,11 @@ inline int64_t chol_flag_words(int64_t d) {
   const int64_t nblk = (d + kCholNb - 1) / kCholNb;
   return 2 + (1 + nblk * (nblk + 1) / 2 + 2 * nblk) * 32;  // one 128-byte line per flag
 }
+// max_grid > 0 caps the workgroups (at least 2: the chain and one task worker),
+// for calls that share the GPU with concurrent work; the tasks are ticketed,
+// so a smaller grid only serialises them.
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
-                     int32_t* flags, hipStream_t st);
+                     int32_t* flags, hipStream_t st, int max_grid = 0);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
 // scratch of 2 * ceil(d/nb) + 2 words.  accum (nullable): accum += x, entry by
 // entry as x is published.  prepared: y_tmp already holds kSolvePending and
