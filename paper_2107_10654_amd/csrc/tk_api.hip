@@ -213,6 +213,14 @@ SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, const tk_sketch_opt
           o->augmented ? make_geom_aug(p).total_q : 0, o->sampling == 1};
 }
 
+// Gram plan of one sketched problem: the sample-split / stream-K plan, and the
+// grouped FP64 Gram over the row geometry (augmented rows when augmented).
+GramPlan plan_sketch_gram(const tk_problem* p, const Geom& g, int64_t s, const tk_sketch_opts* o) {
+  GramPlan pl = plan_gram(g, s, o->gram_precision, 0);
+  pl.grp = plan_grouped(o->augmented ? make_geom_aug(p) : g, s, o->gram_precision);
+  return pl;
+}
+
 void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, SketchWS& w,
                   const SketchNeeds& need, bool with_partials = true) {
   carve_lev(c, g, w.lev);
@@ -571,7 +579,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (!opts) return 0;
       const int64_t s = resolve_samples(opts, g.d);
       if (s < 1) return 0;
-      const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
+      const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
       carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
       break;
@@ -580,7 +588,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (!opts) return 0;
       const int64_t s = resolve_samples(opts, g.d);
       if (s < 1) return 0;
-      const GramPlan pl = plan_gram(g, s, opts->gram_precision, 0);
+      const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
       carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
       AdjWS a;
@@ -872,6 +880,20 @@ void sketch_factor(SketchRun& R) {
   R.stage(6);
 }
 
+// Step 4: M = sketched Gram + lambda P (grouped FP64, or partials then assembly).
+void sketch_gram(SketchRun& R) {
+  SketchWS& w = R.w;
+  if (R.pl.grp.on) {
+    launch_grouped_gram(R.ga, R.pl.grp, R.idx, R.q64s, w.weff, w.lev.P, R.lam_sys, w.gpart, w.M,
+                        R.st);
+    R.stage(4);
+    return;
+  }
+  launch_gram(R.g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, R.st);
+  R.stage(4);
+  launch_assemble(R.g, R.pl, w.gpart, w.lev.P, R.lam_sys, w.M, R.st);
+}
+
 // Steps 1-6 of one problem: ... the sketched Gram on MFMA (4) and its
 // assembly with lambda P, then the right side and the Cholesky factor.
 tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
@@ -879,9 +901,7 @@ tk_status sketch_setup(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   tk_status stt = sketch_pre(R, p, idx_in, weight_in, idx_out, weight_out);
   if (stt != TK_OK) return stt;
   // 4. sketched Gram on MFMA, plus lambda P
-  launch_gram(R.g, R.pl, R.w.rows64, R.w.rows32, R.w.weff, R.s, R.w.gpart, R.st);
-  R.stage(4);
-  launch_assemble(R.g, R.pl, R.w.gpart, R.w.lev.P, R.lam_sys, R.w.M, R.st);
+  sketch_gram(R);
   sketch_factor(R);
   return TK_OK;
 }
@@ -963,7 +983,7 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.s = s;
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
-  R.pl = plan_gram(R.g, s, o->gram_precision, 0);
+  R.pl = plan_sketch_gram(p, R.g, s, o);
   const SketchNeeds need = sketch_needs(p, R.g, o, call);
   R.want_rows64 = need.rows64;
   carve_sketch(c, R.g, s, R.pl, R.w, need, with_partials);
@@ -1157,9 +1177,7 @@ tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* o,
   if (stt != TK_OK) return stt;
   const Geom& g = R.g;
   SketchWS& w = R.w;
-  launch_gram(g, R.pl, w.rows64, w.rows32, w.weff, R.s, w.gpart, R.st);
-  R.stage(4);
-  launch_assemble(g, R.pl, w.gpart, w.lev.P, R.lam_sys, w.M, R.st);
+  sketch_gram(R);
   if (resid_small_ok(g))
     launch_resid_small(R.ga, R.idx, R.q64s, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);

@@ -1295,6 +1295,7 @@ GramPlan plan_gram(const Geom& g, int64_t s, tk_dtype prec, int ksplit_override)
 }
 
 size_t gram_partial_bytes(const Geom& g, const GramPlan& pl) {
+  if (pl.grp.on) return grouped_bytes(pl.grp);
   if (pl.streamk) return ((sk_slot_bytes(pl.sk) + 255) & ~size_t(255)) + sk_index_bytes(pl.sk);
   return static_cast<size_t>(pl.ksplit) * static_cast<size_t>(g.d) * static_cast<size_t>(g.d) * 8;
 }

@@ -157,9 +157,36 @@ bool sk_config_valid(const SkConfig& c);
 // Tile and grid of a single problem's stream-K Gram.
 SkConfig sk_default_config(int64_t d);
 
+// Grouped FP64 Gram (tk_gram_grouped.hip): with L = geom.last the samples
+// are grouped by i_L and G = sum_k B_k (x) e_k e_k^T (B_k over the group's
+// rows of the modes before L, e_k the whitened row k of mode L).
+struct GroupedPlan {
+  int32_t on;      // 1: replaces the sample-split FP64 Gram and its assembly
+  int32_t L, RL;   // grouping mode and its rank
+  int64_t s;       // samples
+  int64_t dp;      // d / R_L
+  int64_t groups;  // rows of mode L in the row geometry
+  int64_t nb;      // sort blocks of 256 samples
+  int64_t ncnt;    // count-table entries groups nb + 1
+  int64_t nparts;  // scan partials of the count table
+  int64_t ptiles;  // lower 64 x 64 tiles of d' x d'
+};
+// On for FP64 when d >= 256, R_L >= 2 and the grouped form needs clearly
+// fewer multiply-adds; gr is the row geometry (the augmented one for
+// augmented draws).
+GroupedPlan plan_grouped(const Geom& gr, int64_t s, tk_dtype prec);
+size_t grouped_bytes(const GroupedPlan& gp);
+// M (d x d, lower triangle) = sum_t weff_t q_t q_t^T + lambda (x)_n P_n from the
+// samples' indices idx ([order][s]) and the row tables Q64 (at gr.qoff);
+// ws: grouped_bytes(gp) bytes.
+void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* idx,
+                         const double* Q64, const double* weff, const double* P, double lambda,
+                         void* ws, double* M, hipStream_t st);
+
 struct GramPlan {
   tk_dtype prec;
   bool streamk;
+  GroupedPlan grp; // FP64: the grouped Gram when grp.on
   SkBatch sk;      // FP32 / BF16: a stream-K batch of one
   int tile;        // FP64: output tile edge
   int bk;          // samples per LDS chunk

@@ -98,6 +98,74 @@ def test_full_size_core_solves_its_normal_equations(tk, c2, c3, name):
     assert res <= 1e-6, res
 
 
+# ---------------------------------------------------------------- FP64 grouped Gram at C2
+# The FP64 path at the C2 size takes the Gram grouped by the last mode (512
+# groups of about 256 samples, d' = 256).  Its M is checked on sampled entries
+# against FP64 sums over all 131072 samples formed here from the whitened
+# factor rows (rows q_i = L_n^{-1} a_i), with the FP64 Gram bar of the small
+# cases (|dM_ij| <= 1e-11 A_ij + 1e-14 lambda |P_ij|, A_ij = sum_t w_t |q_ti q_tj|);
+# the entries include every (m, m') pair of two same-p blocks and random
+# pairs across the lower triangle.  The f64 update solves its normal
+# equations to the f32 output's rounding, on the same samples as the BF16 run.
+@pytest.fixture(scope="module")
+def c2f64(tk):
+    return _run(tk, "c2", precision="f64")
+
+
+def test_c2_f64_grouped_gram_sampled_entries(tk, c2f64):
+    c = c2f64
+    cfg = c["cfg"]
+    ranks = tuple(int(A.shape[1]) for A in c["Fn"])
+    idx = c["idx"].cpu().numpy()
+    w = c["w"].cpu().numpy()
+    print(f"[c2 f64] grouped Gram, ranks {ranks}, s {idx.shape[1]}", flush=True)
+    M, _ = tk.sketched_system(c["X"], c["F"], cfg["lam"], c["idx"], c["w"], precision="f64")
+    Ls = [np.linalg.cholesky(A.T @ A) for A in c["Fn"]]
+    Q = [np.linalg.solve(L, A.T).T for L, A in zip(Ls, c["Fn"])]
+    Pn = [np.linalg.inv(L) @ np.linalg.inv(L).T for L in Ls]
+    d = int(np.prod(ranks))
+    RL = ranks[-1]
+    rng = np.random.default_rng(12)
+    i = rng.integers(0, d, 400)
+    j = (rng.random(400) * (i + 1)).astype(np.int64)
+    blk = np.arange(RL * RL)
+    for p0, q0 in ((37, 37), (201, 5)):  # all (m, m') of the (p, p') blocks, lower part
+        bi, bj = p0 * RL + blk // RL, q0 * RL + blk % RL
+        keep = bi >= bj
+        i, j = np.concatenate([i, bi[keep]]), np.concatenate([j, bj[keep]])
+
+    def digits(r):
+        out = []
+        for R in reversed(ranks):
+            out.append(r % R)
+            r //= R
+        return out[::-1]
+
+    def column(r):
+        col = np.ones(idx.shape[1])
+        for n, dg in enumerate(digits(r)):
+            col *= Q[n][idx[n], dg]
+        return col
+
+    got = M[torch.as_tensor(i, device=M.device), torch.as_tensor(j, device=M.device)].cpu().numpy()
+    for k in range(i.size):
+        qi, qj = column(int(i[k])), column(int(j[k]))
+        pij = np.prod([Pn[n][a, b] for n, (a, b) in
+                       enumerate(zip(digits(int(i[k])), digits(int(j[k]))))])
+        ref = np.dot(w * qi, qj) + cfg["lam"] * pij
+        bound = 1e-11 * np.dot(w * np.abs(qi), np.abs(qj)) + 1e-14 * cfg["lam"] * abs(pij)
+        assert abs(got[k] - ref) <= bound, (int(i[k]), int(j[k]), float(got[k]), float(ref))
+
+
+def test_c2_f64_core_solves_its_normal_equations(tk, c2, c2f64):
+    assert np.array_equal(c2f64["idx"].cpu().numpy(), c2["idx"].cpu().numpy())
+    assert np.array_equal(c2f64["w"].cpu().numpy(), c2["w"].cpu().numpy())
+    res = oracle.normal_equation_residual(c2f64["prob"]["X"], c2f64["Fn"], c2f64["cfg"]["lam"],
+                                          c2f64["idx"].cpu().numpy(), c2f64["w"].cpu().numpy(),
+                                          c2f64["G"].cpu().numpy())
+    assert res <= 1e-6, res
+
+
 def test_c2_exact_core_matches_oracle(tk, c2):
     G = tk.core_update_exact(c2["X"], c2["F"], c2["cfg"]["lam"])
     ref = oracle.core_update_exact(c2["prob"]["X"].astype(np.float64), c2["Fn"], c2["cfg"]["lam"])

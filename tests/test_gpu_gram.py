@@ -20,6 +20,9 @@ magnitudes the entry adds up):
 The 1e-14 relative bar on lambda P holds for well-conditioned factors (every
 case here has cond(A_n) < 10); inverting C_n = A_n^T A_n in FP64 costs about
 cond(C_n) ulps, so an ill-conditioned factor would need a wider one.
+In FP64 the shapes with d >= 256 take the Gram grouped by the last mode of
+rank >= 2 (sums over the samples of each index of that mode, then a product
+with that mode's rows), the others the per-sample one.
 Shapes cover the three Gram tile edges (64: d <= 64; 128; 256 with the
 double-buffered chunk loop: d >= 2048), ragged last tiles, orders 2 to 4,
 a rank-1 mode and an observation mask, each with a last-mode rank R_L that
@@ -53,6 +56,12 @@ CASES = [
     ((41, 37, 29), (5, 6, 8), 0.3),         # d = 240: 128 tiles, ragged, masked
     ((60, 50), (8, 12), None),              # order 2, d = 96
     ((18, 13, 11, 8), (10, 8, 7, 4), None),  # order 4, d = 2240: 256 tiles, ragged
+    # FP64 Gram grouped by the last mode of rank >= 2 (d >= 256): d' = d / R_L
+    # in 64-tiles; a trailing rank-1 mode with a mask, an order-2 problem with
+    # one d' tile and 64 groups, and R_L^2 = 144 over three 64-column blocks
+    ((40, 36, 30, 20), (16, 16, 8, 1), 0.3),  # d = 2048, L = 2, masked
+    ((70, 64), (64, 8), None),              # order 2, d = 512, d' = 64
+    ((30, 28, 26), (12, 12, 12), None),     # d = 1728, d' = 144: ragged tiles
 ]
 
 

@@ -101,7 +101,14 @@ def _sketch_case(dims, ranks, seed, dtype="f64", missing=None, factor="gaussian"
     return p, F
 
 
-@pytest.mark.parametrize("dims,ranks", SHAPES)
+# FP64 shapes with d >= 256 take the Gram grouped by the last mode of rank >= 2
+GROUPED_SHAPES = [
+    ((40, 36, 30), (8, 8, 8)),          # d = 512, 30 groups
+    ((30, 28, 26, 9), (8, 6, 6, 1)),    # d = 288, trailing rank-1 mode, d' = 48
+]
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES + GROUPED_SHAPES)
 def test_sketched_f64_matches_oracle(tk, dims, ranks):
     p, F = _sketch_case(dims, ranks, 3)
     lam, s = 1e-3, 3001
