@@ -149,28 +149,58 @@ __global__ __launch_bounds__(kBlock) void grp_scatter_kernel(const int32_t* __re
 }
 
 struct GrpArgs {
-  const int32_t* idx;   // [order][s]
-  const double* Q64;    // whitened rows at geom.qoff
-  const double* weff;   // per sample
-  const int32_t* perm;  // samples by key
-  const int32_t* cnt;   // scanned count table: group k is perm[cnt[k nb], cnt[(k + 1) nb])
+  const double* rows;   // sorted sample rows: [u][S'], the rows of modes < L of sample perm[u]
+  const double* scs;    // sorted w_t times the squared entries of the modes after L
+  const int32_t* cnt;   // scanned count table: group k is [cnt[k nb], cnt[(k + 1) nb])
   double* B;            // [group][lower tile][64][64]
+  const double* E;      // whitened rows of mode L (groups x R_L)
   const double* P;      // (L_n^T L_n)^{-1} at geom.roff
   double lambda;
   double* M;            // d x d, lower triangle written
-  int64_t s, nb, groups, dp, ptiles;
-  int32_t L, RL;
+  int64_t nb, groups, dp, ptiles;
+  int32_t L, RL, sp;    // sp = S' = sum_{n<L} R_n
 };
 
 // ------------------------------------------------------------------ pass 2: B_k
-// Workgroup (group k, lower tile (ta, tb) of d' x d').  Thread (wave w, lane l)
-// forms rows pa = 64 ta + l (times w_t) and pb = 64 tb + l of y_t for samples
-// w, w + 4, ... of each chunk; wave w then multiplies quadrant (w / 2, w % 2)
-// of the tile (the upper quadrant of a diagonal tile is left zero).
+// Sorted sample rows: element e = u S' + j holds entry j of the concatenated
+// rows of modes < L of sample t = perm[u]; scs[u] = w_t prod_{n>L} q^(n)_{i_n}[0]^2.
+__global__ __launch_bounds__(kBlock) void grp_rows_kernel(Geom g, const int32_t* __restrict__ idx,
+                                                          int64_t s, const double* __restrict__ Q64,
+                                                          const double* __restrict__ weff,
+                                                          const int32_t* __restrict__ perm, int L,
+                                                          int sp, double* __restrict__ rows,
+                                                          double* __restrict__ scs) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= s * sp) return;
+  const int64_t u = e / sp;
+  const int j = static_cast<int>(e - u * sp);
+  const int64_t t = perm[u];
+  int n = 0;
+  while (n + 1 < L && g.soff[n + 1] <= j) ++n;
+  int32_t i = idx[static_cast<int64_t>(n) * s + t];
+  if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
+  rows[e] = Q64[g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n] + (j - g.soff[n])];
+  if (j == 0) {
+    double sc = weff[t];
+    for (int m = L + 1; m < g.order; ++m) {
+      int32_t im = idx[static_cast<int64_t>(m) * s + t];
+      if (im < 0 || im >= g.dims[m]) im = 0;
+      const double q = Q64[g.qoff[m] + im];  // rank 1
+      sc *= q * q;
+    }
+    scs[u] = sc;
+  }
+}
+
+// Workgroup (group k, lower tile (ta, tb) of d' x d'); wave w multiplies
+// quadrant (w / 2, w % 2) of the 64 x 64 tile (the upper quadrant of a
+// diagonal tile stays zero).  Per chunk of 32 samples the rows (32 S'
+// contiguous doubles) go to LDS from registers loaded during the previous
+// chunk's products; each lane forms its operands y_t[p] = prod_{n<L}
+// row_t[soff_n + digit_n(p)] (times scs on the left) from LDS.  NR >= S' / 8.
+template <int NR>
 __global__ __launch_bounds__(kBlock) void grp_block_kernel(Geom g, GrpArgs a) {
-  __shared__ double ya[kGkc][kGld];
-  __shared__ double yb[kGkc][kGld];
-  __shared__ int64_t sbase[kGkc][kMaxOrder];
+  extern __shared__ double rowbuf[];  // [kGkc][S' + 1]
   __shared__ double ssc[kGkc];
   const int64_t tau = blockIdx.x % a.ptiles;
   const int64_t k = blockIdx.x / a.ptiles;
@@ -178,81 +208,91 @@ __global__ __launch_bounds__(kBlock) void grp_block_kernel(Geom g, GrpArgs a) {
   tri_index(tau, ta, tb);
   const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int L = a.L;
-  const int64_t pa = ta * kGt + lane, pb = tb * kGt + lane;
-  const bool va = pa < a.dp, vb = pb < a.dp;
-  int da[kMaxOrder], db[kMaxOrder];
-  {
-    int64_t xa = va ? pa : 0, xb = vb ? pb : 0;
+  const int L = a.L, SP = a.sp, LD = a.sp + 1;
+  const int qa = w >> 1, qb = w & 1;
+  const bool active = !(ta == tb && qa < qb);
+  // LDS offsets (within a sample's row) of the digits of this lane's operand rows
+  int oa[2][kMaxOrder], ob[2][kMaxOrder];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = i * 16 + (lane & 15);
+    const int64_t pa = ta * kGt + qa * 32 + row, pb = tb * kGt + qb * 32 + row;
+    va[i] = pa < a.dp;
+    vb[i] = pb < a.dp;
+    int64_t xa = va[i] ? pa : 0, xb = vb[i] ? pb : 0;
 #pragma unroll
     for (int n = kMaxOrder - 1; n >= 0; --n) {
-      da[n] = 0;
-      db[n] = 0;
+      oa[i][n] = 0;
+      ob[i][n] = 0;
       if (n < L) {
         const int R = g.ranks[n];
-        da[n] = static_cast<int>(xa % R);
-        db[n] = static_cast<int>(xb % R);
+        oa[i][n] = g.soff[n] + static_cast<int>(xa % R);
+        ob[i][n] = g.soff[n] + static_cast<int>(xb % R);
         xa /= R;
         xb /= R;
       }
     }
   }
-  const int qa = w >> 1, qb = w & 1;
-  const bool active = !(ta == tb && qa < qb);
+  // staging: element e = tid + 256 i of a chunk -> LDS (e / S') LD + e % S'
+  const int nel = kGkc * SP;
+  int lofs[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int e = tid + kBlock * i;
+    lofs[i] = e < nel ? (e / SP) * LD + e % SP : -1;
+  }
+  double pf[NR];
+  double psc = 0.0;
+  auto fetch = [&](int64_t c0) {
+    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * SP;
+    const double* src = a.rows + c0 * SP;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int e = tid + kBlock * i;
+      pf[i] = e < lim ? src[e] : 0.0;
+    }
+    if (tid < kGkc) psc = c0 + tid < g1 ? a.scs[c0 + tid] : 0.0;
+  };
   doublex4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  if (g0 < g1) fetch(g0);
   for (int64_t c0 = g0; c0 < g1; c0 += kGkc) {
-    if (tid < kGkc) {  // the chunk's samples: row offsets of modes < L, w_t times modes > L
-      const int64_t u = c0 + tid;
-      double sc = 0.0;
-      if (u < g1) {
-        const int64_t t = a.perm[u];
-        sc = a.weff[t];
-        for (int n = 0; n < g.order; ++n) {
-          int32_t i = a.idx[static_cast<int64_t>(n) * a.s + t];
-          if (i < 0 || i >= g.dims[n]) i = 0;
-          const int64_t off = g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n];
-          if (n < L) sbase[tid][n] = off;
-          if (n > L) sc *= a.Q64[off] * a.Q64[off];
-        }
-      } else {
-        for (int n = 0; n < L; ++n) sbase[tid][n] = g.qoff[n];
-      }
-      ssc[tid] = sc;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kGkc / 4; ++i) {
-      const int j = w + 4 * i;
-      double xa = ssc[j], xb = 1.0;
-#pragma unroll
-      for (int n = 0; n < kMaxOrder; ++n) {
-        if (n < L) {
-          xa *= a.Q64[sbase[j][n] + da[n]];
-          xb *= a.Q64[sbase[j][n] + db[n]];
-        }
-      }
-      ya[j][lane] = va ? xa : 0.0;
-      yb[j][lane] = vb ? xb : 0.0;
-    }
+    for (int i = 0; i < NR; ++i)
+      if (lofs[i] >= 0) rowbuf[lofs[i]] = pf[i];
+    if (tid < kGkc) ssc[tid] = psc;
     __syncthreads();
+    if (c0 + kGkc < g1) fetch(c0 + kGkc);
     if (active) {
-#pragma unroll
+#pragma unroll 2
       for (int ks = 0; ks < kGkc / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        const double a0 = ya[kk][qa * 32 + (lane & 15)];
-        const double a1 = ya[kk][qa * 32 + 16 + (lane & 15)];
-        const double b0 = yb[kk][qb * 32 + (lane & 15)];
-        const double b1 = yb[kk][qb * 32 + 16 + (lane & 15)];
+        const double* rk = rowbuf + kk * LD;
+        double a0 = ssc[kk], a1 = a0, b0 = 1.0, b1 = 1.0;
+#pragma unroll
+        for (int n = 0; n < kMaxOrder; ++n) {
+          if (n < L) {
+            a0 *= rk[oa[0][n]];
+            a1 *= rk[oa[1][n]];
+            b0 *= rk[ob[0][n]];
+            b1 *= rk[ob[1][n]];
+          }
+        }
+        a0 = va[0] ? a0 : 0.0;
+        a1 = va[1] ? a1 : 0.0;
+        b0 = vb[0] ? b0 : 0.0;
+        b1 = vb[1] ? b1 : 0.0;
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
     }
+    __syncthreads();
   }
   // accumulator v of lane l: row l / 16 + 4 v, column l % 16 of its 16 x 16 block
   double* out = a.B + (k * a.ptiles + tau) * (kGt * kGt);
@@ -272,13 +312,16 @@ __global__ __launch_bounds__(kBlock) void grp_block_kernel(Geom g, GrpArgs a) {
 // Workgroup (row a of lower tile tau, block cb of 64 columns c = m R_L + m'):
 // out[b][c] = sum_k B_k[tau][a][b] e_k[m] e_k[m'] for b in [0, 64), the pairs
 // (p, p') = (64 ta + a, 64 tb + b).  Wave w takes quadrant (w / 2, w % 2) of
-// the 64 x 64 output.  Workgroup ids are spread so that the column blocks of
-// one row, which read the same B entries, run on one XCD (ids go round-robin
-// over the 8 XCDs).
+// the 64 x 64 output.  Per chunk of 32 groups the B_k entries and the rows e_k
+// go to LDS from registers loaded during the previous chunk's products; each
+// lane forms its e_k[m] e_k[m'] operands from LDS.  Workgroup ids are spread
+// so that the column blocks of one row, which read the same B_k entries, run
+// on one XCD (ids go round-robin over the 8 XCDs).  NE >= R_L / 8.
+template <int NE>
 __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, int64_t nunits,
                                                             int ncb) {
   __shared__ double as[kGkc][kGld];
-  __shared__ double fs[kGkc][kGld];
+  __shared__ double es[kGkc * kMaxRank];
   const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
   const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (unit >= nunits) return;
@@ -296,49 +339,59 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
   const int qa = w >> 1, qc = w & 1;
   // quadrant rows b >= 32 qa; on a diagonal tile only b <= arow is stored
   const bool active = !(ta == tb && qa * 32 > arow) && cb * 64 + qc * 32 < rr;
-  // staging roles: group kk = tid / 8, entries 8 (tid % 8) .. + 8
+  // this lane's two operand columns c -> (m, m')
+  int fm[2], fmp[2];
+  bool fv[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int c = cb * 64 + qc * 32 + j * 16 + (lane & 15);
+    fv[j] = c < rr;
+    fm[j] = fv[j] ? c / RL : 0;
+    fmp[j] = fv[j] ? c % RL : 0;
+  }
+  // staging roles: B entries (group tid / 8, entries 8 (tid % 8) .. + 8) and
+  // row elements tid + 256 i of the chunk's 32 R_L contiguous e_k entries
   const int skk = tid >> 3, se = (tid & 7) * 8;
   const double* Bsrc = a.B + tau * (kGt * kGt) + static_cast<int64_t>(arow) * kGt + se;
   const int64_t bstride = a.ptiles * (kGt * kGt);
-  const double* E = a.Q64 + g.qoff[a.L];
-  int fm[8], fmp[8];
+  double pa[8], pe[NE];
+  auto fetch = [&](int64_t k0) {
+    const bool kv = k0 + skk < a.groups;
+    const double* src = Bsrc + (k0 + skk) * bstride;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int c = cb * 64 + se + e;
-    fm[e] = c < rr ? c / RL : -1;
-    fmp[e] = c < rr ? c % RL : 0;
-  }
+    for (int e = 0; e < 8; ++e) pa[e] = kv ? src[e] : 0.0;
+    const int64_t lim = ((a.groups < k0 + kGkc ? a.groups : k0 + kGkc) - k0) * RL;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + kBlock * i;
+      pe[i] = e < lim ? a.E[k0 * RL + e] : 0.0;
+    }
+  };
   doublex4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
   for (int64_t k0 = 0; k0 < a.groups; k0 += kGkc) {
-    const int64_t k = k0 + skk;
-    if (k < a.groups) {
-      const double* src = Bsrc + k * bstride;
-      const double* ek = E + k * RL;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        as[skk][se + e] = src[e];
-        fs[skk][se + e] = fm[e] >= 0 ? ek[fm[e]] * ek[fmp[e]] : 0.0;
-      }
-    } else {
+    for (int e = 0; e < 8; ++e) as[skk][se + e] = pa[e];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        as[skk][se + e] = 0.0;
-        fs[skk][se + e] = 0.0;
-      }
+    for (int i = 0; i < NE; ++i) {
+      const int e = tid + kBlock * i;
+      if (e < kGkc * RL) es[e] = pe[i];
     }
     __syncthreads();
+    if (k0 + kGkc < a.groups) fetch(k0 + kGkc);
     if (active) {
-#pragma unroll
+#pragma unroll 2
       for (int ks = 0; ks < kGkc / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
         const double a0 = as[kk][qa * 32 + (lane & 15)];
         const double a1 = as[kk][qa * 32 + 16 + (lane & 15)];
-        const double f0 = fs[kk][qc * 32 + (lane & 15)];
-        const double f1 = fs[kk][qc * 32 + 16 + (lane & 15)];
+        const double* ek = es + kk * RL;
+        const double f0 = fv[0] ? ek[fm[0]] * ek[fmp[0]] : 0.0;
+        const double f1 = fv[1] ? ek[fm[1]] * ek[fmp[1]] : 0.0;
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, f0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, f1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, f0, acc[1][0], 0, 0, 0);
@@ -387,6 +440,8 @@ struct GrpWS {
   int32_t* perm;
   int32_t* cnt;
   int32_t* part;
+  double* rows;
+  double* scs;
   double* B;
 };
 
@@ -395,7 +450,23 @@ void carve_grouped(Carver& c, const GroupedPlan& gp, GrpWS& w) {
   w.perm = c.take<int32_t>(gp.s);
   w.cnt = c.take<int32_t>(gp.ncnt);
   w.part = c.take<int32_t>(gp.nparts);
+  w.rows = c.take<double>(static_cast<size_t>(gp.s) * gp.sp);
+  w.scs = c.take<double>(gp.s);
   w.B = c.take<double>(static_cast<size_t>(gp.groups) * gp.ptiles * kGt * kGt);
+}
+
+// Register sizes of the two MFMA passes' staging.
+int block_nr(int sp) { return sp <= 16 ? 2 : sp <= 32 ? 4 : sp <= 64 ? 8 : 17; }
+int expand_ne(int rl) { return rl <= 8 ? 1 : rl <= 16 ? 2 : rl <= 32 ? 4 : 8; }
+
+template <int NR>
+void launch_block(const Geom& gr, const GrpArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(grp_block_kernel<NR>, dim3(grid), dim3(kBlock), lds, st, gr, a);
+}
+template <int NE>
+void launch_expand(const Geom& gr, const GrpArgs& a, int64_t nunits, int ncb, hipStream_t st) {
+  hipLaunchKernelGGL(grp_expand_kernel<NE>, dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)),
+                     dim3(kBlock), 0, st, gr, a, nunits, ncb);
 }
 
 }  // namespace
@@ -417,7 +488,10 @@ GroupedPlan plan_grouped(const Geom& gr, int64_t s, tk_dtype prec) {
   gp.nparts = cdiv(gp.ncnt, kScanPer);
   const int64_t pt = cdiv(gp.dp, kGt);
   gp.ptiles = pt * (pt + 1) / 2;
-  if (gp.ncnt > (int64_t(1) << 24) || gp.groups * gp.ptiles >= (int64_t(1) << 31)) return gp;
+  gp.sp = gr.soff[L];
+  if (gp.ncnt > (int64_t(1) << 24) || gp.groups * gp.ptiles >= (int64_t(1) << 31) ||
+      s * gp.sp >= (int64_t(1) << 31) || gp.sp > 17 * kBlock / kGkc)
+    return gp;
   // multiply-adds of the two forms (tiles padded to 64): grouped only when
   // clearly fewer, and B_k within 4 GiB
   const double dd = static_cast<double>(gr.d);
@@ -454,29 +528,41 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
                      0, st, w.cnt, gp.ncnt, w.part);
   hipLaunchKernelGGL(grp_scatter_kernel, dim3(static_cast<unsigned>(gp.nb)), dim3(kBlock), 0, st,
                      key, gp.s, gp.groups, gp.nb, w.rank, w.cnt, w.perm);
+  const int64_t nel = gp.s * gp.sp;
+  hipLaunchKernelGGL(grp_rows_kernel, dim3(static_cast<unsigned>(cdiv(nel, kBlock))), dim3(kBlock),
+                     0, st, gr, idx, gp.s, Q64, weff, w.perm, gp.L, gp.sp, w.rows, w.scs);
   GrpArgs a;
-  a.idx = idx;
-  a.Q64 = Q64;
-  a.weff = weff;
-  a.perm = w.perm;
+  a.rows = w.rows;
+  a.scs = w.scs;
   a.cnt = w.cnt;
   a.B = w.B;
+  a.E = Q64 + gr.qoff[gp.L];
   a.P = P;
   a.lambda = lambda;
   a.M = M;
-  a.s = gp.s;
   a.nb = gp.nb;
   a.groups = gp.groups;
   a.dp = gp.dp;
   a.ptiles = gp.ptiles;
   a.L = gp.L;
   a.RL = gp.RL;
-  hipLaunchKernelGGL(grp_block_kernel, dim3(static_cast<unsigned>(gp.groups * gp.ptiles)),
-                     dim3(kBlock), 0, st, gr, a);
+  a.sp = gp.sp;
+  const unsigned grid = static_cast<unsigned>(gp.groups * gp.ptiles);
+  const size_t lds = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double);
+  switch (block_nr(gp.sp)) {
+    case 2: launch_block<2>(gr, a, grid, lds, st); break;
+    case 4: launch_block<4>(gr, a, grid, lds, st); break;
+    case 8: launch_block<8>(gr, a, grid, lds, st); break;
+    default: launch_block<17>(gr, a, grid, lds, st); break;
+  }
   const int ncb = static_cast<int>(cdiv(static_cast<int64_t>(gp.RL) * gp.RL, kGt));
   const int64_t nunits = gp.ptiles * kGt * ncb;
-  hipLaunchKernelGGL(grp_expand_kernel, dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)),
-                     dim3(kBlock), 0, st, gr, a, nunits, ncb);
+  switch (expand_ne(gp.RL)) {
+    case 1: launch_expand<1>(gr, a, nunits, ncb, st); break;
+    case 2: launch_expand<2>(gr, a, nunits, ncb, st); break;
+    case 4: launch_expand<4>(gr, a, nunits, ncb, st); break;
+    default: launch_expand<8>(gr, a, nunits, ncb, st); break;
+  }
 }
 
 }  // namespace tk

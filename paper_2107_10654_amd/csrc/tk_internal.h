@@ -170,6 +170,7 @@ struct GroupedPlan {
   int64_t ncnt;    // count-table entries groups nb + 1
   int64_t nparts;  // scan partials of the count table
   int64_t ptiles;  // lower 64 x 64 tiles of d' x d'
+  int32_t sp;      // S' = sum_{n<L} R_n: length of a sample's rows of the modes before L
 };
 // On for FP64 when d >= 256, R_L >= 2 and the grouped form needs clearly
 // fewer multiply-adds; gr is the row geometry (the augmented one for
