@@ -191,6 +191,7 @@ struct SketchWS {
   double* Q64a;  // augmented whitened row tables (augmented draws only)
   RidgeWS ridge; // ridge-score mixture tables (sampling = 1 only)
   bool has_ridge;
+  void* cgws;    // conjugate-gradient scratch (cg solves only)
 };
 
 // Which optional slices a sampled update (call TK_CALL_SKETCHED) or its adjoint
@@ -201,15 +202,24 @@ struct SketchWS {
 struct SketchNeeds {
   bool rows64;
   bool ttm;
+  bool cg;        // FP64 solve by conjugate gradients (Cholesky as fallback)
   int64_t aug_q;  // entries of the augmented row tables (0: plain draws)
   bool ridge;     // ridge-score mixture tables
 };
 
-SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, const tk_sketch_opts* o, int call) {
+// The FP64 update solves by conjugate gradients when d is large and the
+// sample count is well above d (the sketched Gram then has eigenvalues near 1).
+constexpr int kCgMaxIter = 64;
+bool use_cg(const Geom& g, int64_t s, const tk_sketch_opts* o, int call) {
+  return call == TK_CALL_SKETCHED && o->gram_precision == TK_F64 && cg_ok(g.d) && s >= 8 * g.d;
+}
+
+SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, int64_t s, const tk_sketch_opts* o,
+                         int call) {
   const bool adj = call == TK_CALL_ADJOINT;
   const int32_t prec = o->gram_precision;
   return {adj || !resid_small_ok(g) || prec == TK_F64,
-          adj || !core_chain_small_ok(g) || !refine_check_p_ok(g),
+          adj || !core_chain_small_ok(g) || !refine_check_p_ok(g), use_cg(g, s, o, call),
           o->augmented ? make_geom_aug(p).total_q : 0, o->sampling == 1};
 }
 
@@ -257,6 +267,7 @@ void carve_sketch(Carver& c, const Geom& g, int64_t s, const GramPlan& pl, Sketc
   w.Q64a = need.aug_q ? c.take<double>(need.aug_q) : nullptr;
   w.has_ridge = need.ridge;
   if (need.ridge) carve_ridge(c, g, w.ridge);
+  w.cgws = need.cg ? c.take<char>(cg_bytes(d)) : nullptr;
 }
 
 // Extra workspace of the adjoint, carved after the sampled-update workspace.
@@ -581,7 +592,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call));
       break;
     }
     case TK_CALL_ADJOINT: {
@@ -590,7 +601,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, opts, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call));
       AdjWS a;
       carve_adjoint(c, g, s, a);
       break;
@@ -786,6 +797,7 @@ struct SketchRun {
   const double* q64s = nullptr;  // whitened row tables the sample-side kernels read
   double lam_sys = 0.0;          // lambda of the assembled and refined system
   int chol_grid = 0;             // cap of the Cholesky's workgroups (0: one per CU)
+  bool cg = false;               // FP64 solve by conjugate gradients, Cholesky only as fallback
   void stage(int k) const {
     if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
   }
@@ -875,8 +887,9 @@ void sketch_factor(SketchRun& R) {
   else
     launch_rows_t_vec(g, w.rows64, w.xw, R.s, w.vpart, w.rhs, nullptr, R.st);
   R.stage(5);
-  // 6. FP64 Cholesky
-  launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st, R.chol_grid);
+  // 6. FP64 Cholesky (with conjugate gradients: run by the solve, if needed)
+  if (!R.cg)
+    launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, R.st, R.chol_grid);
   R.stage(6);
 }
 
@@ -938,8 +951,18 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
     return;
   }
   launch_fill_i32(1, 0, w.done, st);
-  launch_copy_f64(g.d, b ? b : w.rhs, h, st);
-  launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, nullptr, R.status, st);
+  if (R.cg) {
+    // conjugate gradients; the factorisation and its solves run only when
+    // they did not converge (they return at once on the done word otherwise)
+    launch_cg(w.M, g.d, b ? b : w.rhs, h, w.r, w.cgws, w.steps, w.relres, w.min_pivot, R.status,
+              kCgMaxIter, st);
+    const int32_t* cdone = cg_done_word(w.cgws, g.d);
+    launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, st, R.chol_grid, cdone);
+    launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, cdone, R.status, st);
+  } else {
+    launch_copy_f64(g.d, b ? b : w.rhs, h, st);
+    launch_chol_solve(w.M, w.Linv_diag, g.d, h, w.ytmp, w.flags, nullptr, R.status, st);
+  }
   R.stage(7);
   for (int k = 0; k <= iters; ++k) {
     if (resid_small_ok(g)) {
@@ -984,8 +1007,9 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_sketch_gram(p, R.g, s, o);
-  const SketchNeeds need = sketch_needs(p, R.g, o, call);
+  const SketchNeeds need = sketch_needs(p, R.g, s, o, call);
   R.want_rows64 = need.rows64;
+  R.cg = need.cg;
   carve_sketch(c, R.g, s, R.pl, R.w, need, with_partials);
   R.status = dev_status ? dev_status : R.w.status;
   R.aug = o->augmented != 0;

@@ -484,7 +484,9 @@ __global__ __launch_bounds__(kBlock, 1) void chol_flow_kernel(double* __restrict
                                                               double* __restrict__ Linv_diag,
                                                               double* __restrict__ pre,
                                                               double* min_pivot, int32_t* status,
-                                                              int32_t* flags) {
+                                                              int32_t* flags,
+                                                              const int32_t* skip) {
+  if (skip && *skip != 0) return;  // the system was already solved
   __shared__ double smem[4 * NB * LDA];
   double* La = smem;
   double* Lb = smem + NB * LDA;
@@ -809,7 +811,9 @@ __device__ inline bool load_published(const double* p, int n, double* v) {
 // diagonal-block inverses (Wl at nblk blocks past Linv_diag, Wu at 2 nblk).
 __global__ __launch_bounds__(kBlock) void chol_chain_kernel(const double* __restrict__ M,
                                                             int64_t d, int64_t nblk,
-                                                            double* __restrict__ Linv_diag) {
+                                                            double* __restrict__ Linv_diag,
+                                                            const int32_t* skip) {
+  if (skip && *skip != 0) return;
   __shared__ double X[NB * LDA];
   __shared__ double Y[NB * LDA];
   const int tid = threadIdx.x;
@@ -1050,7 +1054,7 @@ __global__ void solve_init_kernel(int32_t* flags, double* y, int64_t d, const in
 }  // namespace
 
 void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot, int32_t* status,
-                     int32_t* flags, hipStream_t st, int max_grid) {
+                     int32_t* flags, hipStream_t st, int max_grid, const int32_t* skip) {
   const int64_t nblk = cdiv(d, NB);
   int32_t* ff = flags + 2;  // flags[0..1] are the solves' tickets
   const int64_t nflags = (1 + nblk * (nblk + 1) / 2 + 2 * nblk) * kFlagStride;
@@ -1058,9 +1062,9 @@ void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot,
                      dim3(kBlock), 0, st, ff, nflags);
   double* pre = Linv_diag + 3 * nblk * NB * NB;  // past the inverses and chain matrices
   hipLaunchKernelGGL(chol_flow_kernel, dim3(static_cast<unsigned>(chol_flow_grid(nblk, max_grid))),
-                     dim3(kBlock), 0, st, M, d, nblk, Linv_diag, pre, min_pivot, status, ff);
+                     dim3(kBlock), 0, st, M, d, nblk, Linv_diag, pre, min_pivot, status, ff, skip);
   hipLaunchKernelGGL(chol_chain_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, st,
-                     static_cast<const double*>(M), d, nblk, Linv_diag);
+                     static_cast<const double*>(M), d, nblk, Linv_diag, skip);
 }
 
 void launch_chol_solve(const double* L, const double* Linv_diag, int64_t d, double* x,

@@ -158,6 +158,9 @@ def test_c2_f64_grouped_gram_sampled_entries(tk, c2f64):
 
 
 def test_c2_f64_core_solves_its_normal_equations(tk, c2, c2f64):
+    # solved by conjugate gradients (s = 32 d), no factorisation
+    info = c2f64["info"]
+    assert 1 <= info[2] < 64 and info[4] == 0.0 and info[3] <= 1e-12, info
     assert np.array_equal(c2f64["idx"].cpu().numpy(), c2["idx"].cpu().numpy())
     assert np.array_equal(c2f64["w"].cpu().numpy(), c2["w"].cpu().numpy())
     res = oracle.normal_equation_residual(c2f64["prob"]["X"], c2f64["Fn"], c2f64["cfg"]["lam"],

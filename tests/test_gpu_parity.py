@@ -120,6 +120,57 @@ def test_sketched_f64_matches_oracle(tk, dims, ranks):
     assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
 
 
+# FP64 with d >= 1024 and s >= 8 d solves by conjugate gradients (one
+# persistent launch; the Cholesky runs only when they do not converge).
+# info[2] = iterations, info[4] = 0 (no factorisation ran), info[3] the
+# matrix-free FP64 residual check.  Shapes: d = 1024 (16 x 16 tiles), and
+# d = 1287 with a ragged last 64-block; both with the grouped Gram.
+CG_SHAPES = [
+    ((40, 36, 30), (16, 16, 4), 9000),
+    ((30, 28, 26), (13, 11, 9), 12000),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,s", CG_SHAPES)
+def test_sketched_f64_cg_matches_oracle(tk, dims, ranks, s):
+    p, F = _sketch_case(dims, ranks, 6)
+    lam = 1e-3
+    print(f"[cg] dims {dims} ranks {ranks} s {s}", flush=True)
+    G, idx, w, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=13,
+                                              counter=1, precision="f64", return_samples=True,
+                                              return_info=True)
+    Gr, ridx, rw, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 13, 1)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(w.cpu().numpy(), rw)
+    info = info.cpu().numpy()
+    assert 1 <= info[2] < 64 and info[4] == 0.0, info
+    assert info[3] <= 1e-12, info
+    assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
+
+
+def test_sketched_f64_cg_falls_back_to_cholesky(tk):
+    # a frozen sample set with weights over six decades and a tiny lambda: the
+    # system's condition number (~1e6) keeps conjugate gradients from reaching
+    # 1e-14 in their 64 iterations, so the factorisation and its solves run.
+    # Bars: the Cholesky ran (positive pivot reported); the core solves its
+    # normal equations (oracle FP64 residual <= 1e-9); against the oracle's
+    # own Cholesky solve within 1e-6 (both carry cond * 1e-16 error).
+    dims, ranks, s = (40, 36, 30), (16, 16, 4), 9000
+    p, F = _sketch_case(dims, ranks, 8)
+    lam = 1e-6
+    rng = np.random.default_rng(21)
+    idx = np.stack([rng.integers(0, I, s) for I in dims]).astype(np.int32)
+    w = 10.0 ** rng.uniform(-6.0, 0.0, s) / s
+    G, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, idx=T(idx),
+                                      weight=T(w), precision="f64", return_info=True)
+    info = info.cpu().numpy()
+    assert info[2] == 64 and info[4] > 0.0, info
+    G = G.cpu().numpy()
+    res = oracle.normal_equation_residual(p["X"], F, lam, idx, w, G)
+    assert res <= 1e-9, res
+    assert elem_err(G, oracle.core_update_sketched(p["X"], F, lam, idx, w)) <= 1e-6
+
+
 @pytest.mark.parametrize("precision", ["f32", "bf16"])
 @pytest.mark.parametrize("dims,ranks", [((41, 37, 29), (5, 6, 7)), ((30, 28, 26), (8, 8, 4))])
 def test_sketched_low_precision_refined(tk, precision, dims, ranks):
