@@ -954,7 +954,7 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   if (R.cg) {
     // conjugate gradients; the factorisation and its solves run only when
     // they did not converge (they return at once on the done word otherwise)
-    launch_cg(w.M, g.d, b ? b : w.rhs, h, w.r, w.cgws, w.steps, w.relres, w.min_pivot, R.status,
+    launch_cg(w.M, g.d, b ? b : w.rhs, h, w.cgws, w.steps, w.relres, w.min_pivot, R.status,
               kCgMaxIter, st);
     const int32_t* cdone = cg_done_word(w.cgws, g.d);
     launch_cholesky(w.M, g.d, w.Linv_diag, w.min_pivot, R.status, w.flags, st, R.chol_grid, cdone);

@@ -11,21 +11,29 @@
 // FP64 accuracy after a few tens of products with M.  The caller runs the
 // Cholesky factorisation only when this solve reports no convergence.
 //
-// One persistent launch runs every iteration.  Per iteration:
-//   S  each workgroup multiplies its lower 64 x 64 tiles M_IJ by the search
-//      direction p = r + beta p_prev (formed on the fly from r and p_prev):
-//      the row part M_IJ p_J and, off the diagonal, the column part
-//      M_IJ^T p_I (diagonal tiles: strictly lower part transposed), written
-//      to per-tile partials; each workgroup also writes its own entries of p;
-//   R  each workgroup sums the partials of its own entries of q = M p in a
-//      fixed order, and its share of p.q;
-//   U  alpha = r.r / p.q (the shares summed in a fixed order by every
-//      workgroup alike), h += alpha p, r -= alpha q on its own entries, and
-//      its share of the new r.r;
-// with a grid-wide barrier after each.  Every sum has a fixed order, so the
-// result does not depend on timing.  Data that other workgroups read (p, r,
-// partials, shares) is written through to memory and read with agent-scope
-// loads, since the L2 of one XCD does not see another's writes.
+// The recurrence is the single-reduction form of conjugate gradients
+// (Chronopoulos and Gear): with s_i = M r_i, gamma_i = r_i.r_i and
+// delta_i = r_i.s_i, both dot products of an iteration come from one
+// reduction,
+//   beta_i = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = r_i + beta_i p_{i-1},  w_i = s_i + beta_i w_{i-1}  (w_i = M p_i),
+//   h_{i+1} = h_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i w_i,
+// the same iterates as the textbook form in exact arithmetic.
+//
+// One persistent launch runs every iteration, two grid-wide barriers each:
+//   S  each workgroup forms r_{i+1} on the entries its tiles need (from r_i,
+//      s_i, w_{i-1} and the scalars, the same arithmetic as the entries'
+//      owners) and multiplies its lower 64 x 64 tiles M_IJ by it: the row part
+//      M_IJ r_J and the column part M_IJ^T r_I (diagonal tiles: the strictly
+//      lower part transposed) go to per-tile partials.  Owners of entries
+//      also update h, p, w, r there.  The next tiles' M entries and vector
+//      values load while the current tile is used (two tiles ahead);
+//   R  each workgroup sums the partials of its own entries of s_{i+1} in a
+//      fixed order, and its shares of gamma and delta.
+// Every sum has a fixed order and every workgroup sums the shares alike, so
+// the result does not depend on timing.  Data that other workgroups read is
+// written through to memory and read with agent-scope loads, since the L2 of
+// one XCD does not see another's writes.
 #include <string.h>
 
 #include "tk_internal.h"
@@ -41,17 +49,26 @@ constexpr int kCgTerms = (kCgMaxBlocks + 1 + 15) / 16;  // partial terms per thr
 constexpr long kCgSpinLimit = 1L << 20;
 // stop once ||r|| <= kCgTol ||b|| (the recursively updated residual)
 constexpr double kCgTol = 1e-14;
+constexpr int kCgSyncWords = 32;  // arrival count and abort word, each on its own line
+// Resident tiles: a workgroup with at most kResReg + kResLds tiles keeps them
+// on chip for every iteration, kResReg in registers and kResLds in LDS.
+constexpr int kResReg = 8;
+constexpr int kResLds = 1;
+constexpr int kMaxRes = kResReg + kResLds;
+constexpr int kMaxVb = 2 * kMaxRes;           // distinct vector blocks of those tiles
+constexpr int kVbPer = kMaxVb * kCt / kBlock;  // their entries per thread
 
 struct CgArgs {
   const double* M;   // lower triangle, d x d row-major
   const double* b;
   double* h;         // out: solution (b when the iteration did not converge)
-  double* r;         // residual (shared)
-  double* pbuf;      // two direction vectors (previous, current), 2 d
-  double* rowpart;   // [tile][64]
-  double* colpart;   // [tile][64]
-  double* shares;    // [2][grid]: p.q and r.r shares
-  int32_t* sync;     // [0] barrier arrivals, [1] abort word
+  double* rbuf;      // r_i, two halves of d
+  double* sbuf;      // s_i = M r_i, two halves
+  double* wbuf;      // w_i = M p_i, two halves
+  double* rowpart;   // [tile][64], plus a spare slot
+  double* colpart;   // [tile][64], plus a spare slot
+  double* shares;    // [2][grid]: gamma and delta shares
+  int32_t* sync;     // [0] arrivals, [16] abort word
   int32_t* cg_done;  // out: 1 when converged
   int32_t* steps;    // out: iterations taken
   double* relres;    // out: final ||r|| / ||b|| of the recursion
@@ -75,8 +92,23 @@ __device__ inline void cg_complete_stores() {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-__device__ inline double dir(double r, double beta, double pprev) { return fma(beta, pprev, r); }
 __device__ inline int64_t tri(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+__device__ inline void tile_of(int64_t t, int64_t& i, int64_t& j) {
+  i = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(t) + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  j = t - i * (i + 1) / 2;
+}
+
+// The vector recurrences of one entry, shared by its owner and every reader:
+// w_i = s_i + beta w_{i-1}, r_{i+1} = r_i - alpha w_i.
+struct Next {
+  double w, r;
+};
+__device__ inline Next next_entry(double r, double s, double wprev, double alpha, double beta) {
+  const double w = fma(beta, wprev, s);
+  return {w, fma(-alpha, w, r)};
+}
 
 // Sum of one value per thread over the workgroup in a fixed tree order.
 __device__ inline double block_sum(double v, double* red) {
@@ -93,39 +125,67 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(kBlock) void cg_kernel(CgArgs a) {
+// One tile's operands in registers: this thread's 16 entries of M_IJ and, for
+// threads < 128, the vector values at position tid (block J) or tid - 64
+// (block I) of the tile.
+struct TileRegs {
+  double v[16];
+  double r, s, w;
+};
+
+// FULL: d is a multiple of 64, every tile is whole and its entries load as
+// 16-byte vectors without conditions (the diagonal tiles' upper parts are
+// zeroed on their way to LDS).  RES (with FULL): the workgroup's tiles are
+// read from memory once and stay in registers and LDS; the vector blocks
+// they need are formed into LDS once per iteration.
+template <bool FULL, bool RES>
+__global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
   __shared__ double tile[kCt * kCld];
-  __shared__ double pI[kCt], pJ[kCt];
+  __shared__ double tile2[RES ? kCt * kCld : 1];  // second column-pass buffer
+  __shared__ double tres[RES ? kResLds : 1][RES ? kCt * kCld : 1];
+  __shared__ double vblk[RES ? kMaxVb : 1][kCt];
+  __shared__ double csum_all[RES ? kMaxRes : 1][4][kCt];
+  __shared__ int slot_of[RES ? 2 * kMaxRes : 1];  // [k]: slot of tile k's J block, [kMaxRes + k]: I
+  __shared__ int diag_of[RES ? kMaxRes : 1];
+  __shared__ int64_t blk_of[RES ? kMaxVb : 1];
+  __shared__ int nslot_s;
+  __shared__ double vIJ[kBlock];  // tile vector values: J at [0, 64), I at [64, 128)
   __shared__ double red[kBlock];
   __shared__ double csum[4][kCt];
-  __shared__ double own_p[kCgMaxOwn], own_q[kCgMaxOwn], own_h[kCgMaxOwn];
+  __shared__ double own_h[kCgMaxOwn], own_p[kCgMaxOwn], own_r[kCgMaxOwn], own_s[kCgMaxOwn];
   __shared__ int ok_s;
   const int tid = threadIdx.x;
-  const int G = gridDim.x, w = blockIdx.x;
+  const int G = gridDim.x, wg = blockIdx.x;
   const int64_t d = a.d, nb = a.nb;
-  const int64_t e0 = w * a.own;
-  const int64_t ne = (e0 + a.own < d ? e0 + a.own : d) - e0 > 0
-                         ? (e0 + a.own < d ? e0 + a.own : d) - e0 : 0;
-  const int64_t t0 = w * a.ntiles / G, t1 = (w + 1) * a.ntiles / G;
-  double* sh_pq = a.shares;
-  double* sh_rr = a.shares + G;
-  int32_t* abort = a.sync + 1;
-  int target = 0;
+  const int64_t e0 = wg * a.own;
+  const int64_t e1 = e0 + a.own < d ? e0 + a.own : d;
+  const int64_t ne = e1 > e0 ? e1 - e0 : 0;
+  const int64_t t0 = wg * a.ntiles / G, t1 = (wg + 1) * a.ntiles / G;
+  const int srow = tid >> 2, scol = (tid & 3) * 16;  // tile roles: row, 16 columns
+  const int nloc = static_cast<int>(t1 - t0);
+  double* sh_g = a.shares;
+  double* sh_d = a.shares + G;
+  int32_t* arrivals = a.sync;
+  int32_t* abort = a.sync + 16;
+  int gen = 0;
   bool failed = false;
-  auto barrier = [&]() {
+  // grid barrier on a monotonic arrival count
+  auto barrier = [&]() __attribute__((always_inline)) {
     cg_complete_stores();
     __syncthreads();
-    target += G;
+    ++gen;
     if (tid == 0) {
-      __hip_atomic_fetch_add(a.sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(arrivals, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       long spins = 0;
       int ok = 1;
-      while (__hip_atomic_load(a.sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen * G) {
+        // the abort word every 64 polls (one round trip per poll otherwise)
+        if ((spins & 63) == 63 &&
+            __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > kCgSpinLimit) {
           __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
@@ -137,129 +197,310 @@ __global__ __launch_bounds__(kBlock) void cg_kernel(CgArgs a) {
     __syncthreads();
     failed = failed || !ok_s;
   };
-  // sum of the grid's shares, the same fixed order in every workgroup
-  auto grid_sum = [&](const double* sh) {
-    double v = 0.0;
-    for (int i = tid; i < G; i += kBlock) v += cload(sh + i);
-    return block_sum(v, red);
+  // sums of the grid's gamma and delta shares, the same fixed order in every
+  // workgroup (both loads in flight together)
+  auto grid_sums = [&](double& sg, double& sd) __attribute__((always_inline)) {
+    double vg = 0.0, vd = 0.0;
+    for (int i = tid; i < G; i += kBlock) {
+      const double x = cload(sh_g + i), y = cload(sh_d + i);
+      vg += x;
+      vd += y;
+    }
+    sg = block_sum(vg, red);
+    sd = block_sum(vd, red);
   };
 
-  // ---- start: h = 0, r = b, p_prev = 0, shares of b.b
-  double part = 0.0;
-  for (int64_t i = tid; i < ne; i += kBlock) {
-    const double bi = a.b[e0 + i];
-    cstore(a.r + e0 + i, bi);
-    cstore(a.pbuf + e0 + i, 0.0);
-    own_h[i] = 0.0;
-    part += bi * bi;
-  }
-  {
-    const double s = block_sum(part, red);
-    if (tid == 0) cstore(sh_rr + w, s);
-  }
-  barrier();
-  const double bb = grid_sum(sh_rr);
-  double rr = bb;
-  double beta = 0.0;
-  int cur = 0;  // pbuf half holding p_prev
-  int it = 0;
-  bool conv = !(bb > 0.0);
-  // tile staging roles: row tid / 4, columns 16 (tid % 4) .. + 16
-  const int srow = tid >> 2, scol = (tid & 3) * 16;
-  while (!conv && !failed && it < a.max_iter) {
-    const double* pprev = a.pbuf + cur * d;
-    double* pnext = a.pbuf + (cur ^ 1) * d;
-    // ---- S: own entries of p, then the tile products
-    for (int64_t i = tid; i < ne; i += kBlock) {
-      const double pv = dir(cload(a.r + e0 + i), beta, cload(pprev + e0 + i));
-      own_p[i] = pv;
-      cstore(pnext + e0 + i, pv);
+  // vector sources of the S phase: r_{i+1} = r - alpha (s + beta w).  At the
+  // start all three are b with alpha = beta = 0, which gives r_0 = b exactly.
+  const double* rsrc = a.b;
+  const double* ssrc = a.b;
+  const double* wsrc = a.b;
+  bool setup = true;
+  double alpha = 0.0, beta = 0.0;
+  // With FULL tiles the loads below are unconditional (a tile index past the
+  // workgroup's range repeats its last tile), so the compiler can keep the
+  // next tiles' loads in flight while the current one is used.
+  auto fetch = [&](TileRegs& R, int64_t tau) __attribute__((always_inline)) {
+    int64_t fi, fj;
+    tile_of(tau, fi, fj);
+    const int64_t r0 = fi * kCt, c0 = fj * kCt;
+    if (FULL) {
+      const int64_t x = tid < kCt ? c0 + tid : r0 + (tid & (kCt - 1));
+      R.r = cload(rsrc + x);  // threads >= 128 load a value they do not use
+      R.s = cload(ssrc + x);
+      R.w = cload(wsrc + x);
     }
-    // tiles t0 .. t1 - 1 in row-major lower order; the next tile's M entries
-    // and r, p_prev values load into registers while the current one is used
-    int64_t ti = 0, tj = 0;
-    if (t0 < t1) {
-      ti = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(t0) + 1.0) - 1.0) * 0.5);
-      while ((ti + 1) * (ti + 2) / 2 <= t0) ++ti;
-      while (ti * (ti + 1) / 2 > t0) --ti;
-      tj = t0 - ti * (ti + 1) / 2;
-    }
-    double v[16];
-    double vr = 0.0, vp = 0.0;
-    auto fetch = [&](int64_t fi, int64_t fj) {
-      const int64_t r0 = fi * kCt, c0 = fj * kCt;
-      const int64_t row = r0 + srow;
-      const double* src = a.M + row * d + c0 + scol;
-      if (fi != fj && row < d && c0 + scol + 16 <= d && (d & 1) == 0) {
+    const int64_t row = r0 + srow;
+    const double* src = a.M + row * d + c0 + scol;
+    if (FULL) {
 #pragma unroll
-        for (int e = 0; e < 16; e += 2) {
-          const double2 x = *reinterpret_cast<const double2*>(src + e);
-          v[e] = x.x;
-          v[e + 1] = x.y;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int64_t col = c0 + scol + e;
-          v[e] = (row < d && col < d && (fi != fj || col <= row)) ? src[e] : 0.0;
-        }
+      for (int e = 0; e < 16; e += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(src + e);
+        R.v[e] = x.x;
+        R.v[e + 1] = x.y;
       }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t col = c0 + scol + e;
+        R.v[e] = (row < d && col < d && (fi != fj || col <= row)) ? src[e] : 0.0;
+      }
+      R.r = R.s = R.w = 0.0;
       if (tid < 2 * kCt) {
         const int64_t x = tid < kCt ? c0 + tid : r0 + tid - kCt;
-        vr = x < d ? cload(a.r + x) : 0.0;
-        vp = x < d ? cload(pprev + x) : 0.0;
+        if (x < d) {
+          R.r = cload(rsrc + x);
+          R.s = cload(ssrc + x);
+          R.w = cload(wsrc + x);
+        }
       }
-    };
-    if (t0 < t1) fetch(ti, tj);
-    for (int64_t tau = t0; tau < t1; ++tau) {
-      const bool diag = ti == tj;
-      if (tid < kCt)
-        pJ[tid] = dir(vr, beta, vp);
-      else if (tid < 2 * kCt)
-        pI[tid - kCt] = dir(vr, beta, vp);
+    }
+  };
+  // one tile; real = false: a stand-in whose partials go to the spare slot
+  auto process = [&](TileRegs& R, int64_t tau, bool real) __attribute__((always_inline)) {
+    int64_t ti, tj;
+    tile_of(tau, ti, tj);
+    const bool diag = ti == tj;
+    vIJ[tid] = next_entry(R.r, R.s, R.w, alpha, beta).r;  // [0, 64): J, [64, 128): I
 #pragma unroll
-      for (int e = 0; e < 16; ++e) tile[srow * kCld + scol + e] = v[e];
-      __syncthreads();
-      // next tile
-      if (++tj > ti) {
-        ++ti;
-        tj = 0;
+    for (int e = 0; e < 16; ++e)
+      tile[srow * kCld + scol + e] = (!FULL || !diag || scol + e <= srow) ? R.v[e] : 0.0;
+    __syncthreads();
+    if (FULL)
+      fetch(R, tau + 2 < t1 ? tau + 2 : t1 - 1);
+    else if (tau + 2 < t1)
+      fetch(R, tau + 2);
+    const int64_t slot = real ? tau : a.ntiles;
+    // row part: sum_c M[row][c] v_J[c] over the 4 threads of the row
+    double rs = 0.0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rs = fma(tile[srow * kCld + scol + e], vIJ[scol + e], rs);
+    rs += __shfl_xor(rs, 1, 64);
+    rs += __shfl_xor(rs, 2, 64);
+    if ((tid & 3) == 0) cstore(a.rowpart + slot * kCt + srow, rs);
+    // column part: sum_row M[row][c] v_I[row] (diagonal tile: rows below c only)
+    {
+      const int c = tid & 63, rg = tid >> 6;
+      double cs = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rw = rg * 16 + i;
+        const double m = (!diag || rw > c) ? tile[rw * kCld + c] : 0.0;
+        cs = fma(m, vIJ[kCt + rw], cs);
       }
-      if (tau + 1 < t1) fetch(ti, tj);
-      // row part: sum_c M[row][c] pJ[c] over the 4 threads of the row
+      csum[rg][c] = cs;
+    }
+    __syncthreads();
+    if (tid < kCt)
+      cstore(a.colpart + slot * kCt + tid,
+             ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid]);
+    __syncthreads();
+  };
+  // ---- resident tiles (RES)
+  double treg[RES ? kResReg : 1][16];
+  if (RES) {
+    // the distinct vector blocks of the workgroup's tiles, and each tile's slots
+    if (tid == 0) {
+      int ns = 0;
+      for (int k = 0; k < nloc; ++k) {
+        int64_t ti, tj;
+        tile_of(t0 + k, ti, tj);
+        int sj = -1, si = -1;
+        for (int q = 0; q < ns; ++q) {
+          if (blk_of[q] == tj) sj = q;
+          if (blk_of[q] == ti) si = q;
+        }
+        if (sj < 0) {
+          blk_of[ns] = tj;
+          sj = ns++;
+        }
+        if (si < 0) {
+          if (ti == tj) {
+            si = sj;
+          } else {
+            blk_of[ns] = ti;
+            si = ns++;
+          }
+        }
+        slot_of[k] = sj;
+        slot_of[kMaxRes + k] = si;
+        diag_of[k] = ti == tj ? 1 : 0;
+      }
+      nslot_s = ns;
+    }
+    __syncthreads();
+  }
+  // this thread's 16 entries of tile tau (diagonal tiles: upper part zero)
+  auto load_tile = [&](double (&v)[16], int64_t tau) {
+    int64_t fi, fj;
+    tile_of(tau, fi, fj);
+    const double* src = a.M + (fi * kCt + srow) * d + fj * kCt + scol;
+#pragma unroll
+    for (int e = 0; e < 16; e += 2) {
+      const double2 x = *reinterpret_cast<const double2*>(src + e);
+      v[e] = (fi != fj || scol + e <= srow) ? x.x : 0.0;
+      v[e + 1] = (fi != fj || scol + e + 1 <= srow) ? x.y : 0.0;
+    }
+  };
+  auto phase_s_res = [&](double* rnext, double* wcur) __attribute__((always_inline)) {
+    for (int64_t i = tid; i < ne; i += kBlock) {
+      const int64_t x = e0 + i;
+      if (!setup) {
+        const double rv = cload(rsrc + x);
+        const Next nx = next_entry(rv, cload(ssrc + x), cload(wsrc + x), alpha, beta);
+        const double pv = fma(beta, own_p[i], rv);  // p_i = r_i + beta p_{i-1}
+        own_p[i] = pv;
+        own_h[i] = fma(alpha, pv, own_h[i]);
+        own_r[i] = nx.r;
+        cstore(wcur + x, nx.w);
+        cstore(rnext + x, nx.r);
+      } else {  // r_0 = b, w_{-1} = 0
+        const double rv = rsrc[x];
+        own_p[i] = 0.0;
+        own_h[i] = 0.0;
+        own_r[i] = rv;
+        cstore(wcur + x, 0.0);
+        cstore(rnext + x, rv);
+      }
+    }
+    // the vector blocks: every load in flight before any value is formed
+    const int nv = nslot_s * kCt;
+    double lr[kVbPer], ls[kVbPer], lw[kVbPer];
+#pragma unroll
+    for (int q = 0; q < kVbPer; ++q) {
+      const int e = tid + kBlock * q;
+      const int ee = e < nv ? e : 0;
+      const int64_t x = blk_of[ee / kCt] * kCt + (ee % kCt);
+      lr[q] = cload(rsrc + x);
+      ls[q] = cload(ssrc + x);
+      lw[q] = cload(wsrc + x);
+    }
+    if (setup) {  // the tiles, once
+#pragma unroll
+      for (int k = 0; k < kResReg; ++k)
+        if (k < nloc) load_tile(treg[k], t0 + k);
+#pragma unroll
+      for (int k = 0; k < kResLds; ++k) {
+        if (kResReg + k < nloc) {
+          double v[16];
+          load_tile(v, t0 + kResReg + k);
+#pragma unroll
+          for (int e = 0; e < 16; ++e) tres[k][srow * kCld + scol + e] = v[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kVbPer; ++q) {
+      const int e = tid + kBlock * q;
+      if (e < nv) vblk[e / kCt][e % kCt] = next_entry(lr[q], ls[q], lw[q], alpha, beta).r;
+    }
+    __syncthreads();
+    // row parts of every tile (registers and the LDS-resident tiles), kept
+    // until the stores at the end
+    double rsv[kMaxRes];
+#pragma unroll
+    for (int k = 0; k < kMaxRes; ++k) {
       double rs = 0.0;
+      if (k < nloc) {
+        const double* vJ = vblk[slot_of[k]];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) rs = fma(tile[srow * kCld + scol + e], pJ[scol + e], rs);
+        for (int e = 0; e < 16; ++e) {
+          const double m = k < kResReg ? treg[k < kResReg ? k : 0][e]
+                                       : tres[k - kResReg][srow * kCld + scol + e];
+          rs = fma(m, vJ[scol + e], rs);
+        }
+      }
       rs += __shfl_xor(rs, 1, 64);
       rs += __shfl_xor(rs, 2, 64);
-      if ((tid & 3) == 0) cstore(a.rowpart + tau * kCt + srow, rs);
-      // column part: sum_row M[row][c] pI[row] (diagonal tile: rows below c only)
-      {
-        const int c = tid & 63, rg = tid >> 6;
+      rsv[k] = rs;
+    }
+    // column parts: register tiles through two alternating LDS buffers, one
+    // barrier per tile
+    const int cc = tid & 63, rg = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < kMaxRes; ++k) {
+      if (k < nloc) {
+        const double* T;
+        if (k < kResReg) {
+          double* buf = (k & 1) ? tile2 : tile;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) buf[srow * kCld + scol + e] = treg[k < kResReg ? k : 0][e];
+          __syncthreads();
+          T = buf;
+        } else {
+          T = tres[k - kResReg];
+        }
+        const double* vI = vblk[slot_of[kMaxRes + k]];
+        const bool dg = diag_of[k] != 0;
         double cs = 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int rr_ = rg * 16 + i;
-          const double m = (!diag || rr_ > c) ? tile[rr_ * kCld + c] : 0.0;
-          cs = fma(m, pI[rr_], cs);
+          const int rw = rg * 16 + i;
+          const double m = (!dg || rw > cc) ? T[rw * kCld + cc] : 0.0;
+          cs = fma(m, vI[rw], cs);
         }
-        csum[rg][c] = cs;
+        csum_all[k][rg][cc] = cs;
       }
-      __syncthreads();
-      if (tid < kCt)
-        cstore(a.colpart + tau * kCt + tid,
-               ((csum[0][tid] + csum[1][tid]) + csum[2][tid]) + csum[3][tid]);
-      __syncthreads();
     }
-    barrier();
-    // ---- R: own entries of q = M p, share of p.q
-    // 16 threads per entry: thread z of entry i sums terms z, z + 16, ... of
-    // [rowpart(I, 0..I), colpart(I..nb-1, I)], then the 16 in a fixed tree
-    part = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMaxRes; ++k) {
+      if (k < nloc) {
+        const int64_t tau = t0 + k;
+        if ((tid & 3) == 0) cstore(a.rowpart + tau * kCt + srow, rsv[k]);
+        if (tid < kCt)
+          cstore(a.colpart + tau * kCt + tid,
+                 ((csum_all[k][0][tid] + csum_all[k][1][tid]) + csum_all[k][2][tid]) +
+                     csum_all[k][3][tid]);
+      }
+    }
+  };
+  // S phase: the owners' updates, then the tile products
+  auto phase_s = [&](double* rnext, double* wcur) __attribute__((always_inline)) {
+    if (RES) {
+      phase_s_res(rnext, wcur);
+      return;
+    }
+    for (int64_t i = tid; i < ne; i += kBlock) {
+      const int64_t x = e0 + i;
+      if (!setup) {
+        const double rv = cload(rsrc + x);
+        const Next nx = next_entry(rv, cload(ssrc + x), cload(wsrc + x), alpha, beta);
+        const double pv = fma(beta, own_p[i], rv);  // p_i = r_i + beta p_{i-1}
+        own_p[i] = pv;
+        own_h[i] = fma(alpha, pv, own_h[i]);
+        own_r[i] = nx.r;
+        cstore(wcur + x, nx.w);
+        cstore(rnext + x, nx.r);
+      } else {  // r_0 = b, w_{-1} = 0
+        const double rv = rsrc[x];
+        own_p[i] = 0.0;
+        own_h[i] = 0.0;
+        own_r[i] = rv;
+        cstore(wcur + x, 0.0);
+        cstore(rnext + x, rv);
+      }
+    }
+    if (t0 >= t1) return;
+    TileRegs A, B;
+    fetch(A, t0);
+    fetch(B, t0 + 1 < t1 ? t0 + 1 : t0);
+    for (int64_t tau = t0; tau < t1; tau += 2) {
+      process(A, tau, true);
+      if (FULL)
+        process(B, tau + 1 < t1 ? tau + 1 : tau, tau + 1 < t1);
+      else if (tau + 1 < t1)
+        process(B, tau + 1, true);
+    }
+  };
+  // R phase: own entries of s = M r (sums of the partials in a fixed order);
+  // 16 threads per entry, thread z summing terms z, z + 16, ... of
+  // [rowpart(I, 0..I), colpart(I..nb-1, I)], then the 16 in a fixed tree
+  auto phase_r = [&](double* snext) __attribute__((always_inline)) {
     for (int64_t base = 0; base < ne; base += kBlock / 16) {
       const int64_t i = base + (tid >> 4);
       const int z = tid & 15;
-      double s = 0.0;
+      double sum = 0.0;
       if (i < ne) {
         const int64_t gi = e0 + i;
         const int64_t I = gi / kCt, o = gi % kCt;
@@ -273,55 +514,103 @@ __global__ __launch_bounds__(kBlock) void cg_kernel(CgArgs a) {
           t[q] = u < nt ? cload(src) : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < kCgTerms; ++q) s += t[q];
+        for (int q = 0; q < kCgTerms; ++q) sum += t[q];
       }
-      s += __shfl_xor(s, 8, 64);
-      s += __shfl_xor(s, 4, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 1, 64);
+      sum += __shfl_xor(sum, 8, 64);
+      sum += __shfl_xor(sum, 4, 64);
+      sum += __shfl_xor(sum, 2, 64);
+      sum += __shfl_xor(sum, 1, 64);
       if (i < ne && z == 0) {
-        own_q[i] = s;
+        own_s[i] = sum;
+        cstore(snext + e0 + i, sum);
       }
     }
     __syncthreads();
-    for (int64_t i = tid; i < ne; i += kBlock) part = fma(own_p[i], own_q[i], part);
-    {
-      const double s = block_sum(part, red);
-      if (tid == 0) cstore(sh_pq + w, s);
-    }
-    barrier();
-    // ---- U: alpha, h and r on own entries, share of r.r
-    const double pq = grid_sum(sh_pq);
-    const double alpha = rr / pq;
-    part = 0.0;
+    double pg = 0.0, pd = 0.0;
     for (int64_t i = tid; i < ne; i += kBlock) {
-      own_h[i] = fma(alpha, own_p[i], own_h[i]);
-      const double rv = fma(-alpha, own_q[i], cload(a.r + e0 + i));
-      cstore(a.r + e0 + i, rv);
-      part = fma(rv, rv, part);
+      pg = fma(own_r[i], own_r[i], pg);
+      pd = fma(own_r[i], own_s[i], pd);
     }
-    {
-      const double s = block_sum(part, red);
-      if (tid == 0) cstore(sh_rr + w, s);
+    const double sg = block_sum(pg, red);
+    const double sd = block_sum(pd, red);
+    if (tid == 0) {
+      cstore(sh_g + wg, sg);
+      cstore(sh_d + wg, sd);
     }
+  };
+
+  // ---- start: s_0 = M b, gamma_0, delta_0
+  phase_s(a.rbuf, a.wbuf + d);  // r_0 -> rbuf[0], w_{-1} = 0 -> wbuf[1]
+  barrier();
+  phase_r(a.sbuf);
+  barrier();
+  double g0, del;
+  grid_sums(g0, del);
+  double gam = g0;
+  alpha = del > 0.0 ? gam / del : 0.0;
+  beta = 0.0;
+  int it = 0;
+  bool conv = !(g0 > 0.0);
+  bool broke = !conv && !(del > 0.0);
+  while (!conv && !broke && !failed && it < a.max_iter) {
+    const int c = it & 1;
+    setup = false;
+    rsrc = a.rbuf + c * d;
+    ssrc = a.sbuf + c * d;
+    wsrc = a.wbuf + (c ^ 1) * d;
+    phase_s(a.rbuf + (c ^ 1) * d, a.wbuf + c * d);
     barrier();
-    const double rr_new = grid_sum(sh_rr);
-    beta = rr_new / rr;
-    rr = rr_new;
-    cur ^= 1;
+    phase_r(a.sbuf + (c ^ 1) * d);
+    barrier();
+    double gn, dn;
+    grid_sums(gn, dn);
     ++it;
-    conv = rr <= kCgTol * kCgTol * bb;
-    if (!(pq > 0.0)) break;  // not positive definite in this direction: leave it to the factorisation
+    const double gprev = gam;
+    gam = gn;
+    conv = gn <= kCgTol * kCgTol * g0;
+    if (conv) break;
+    const double bn = gn / gprev;
+    const double den = dn - bn * gn / alpha;
+    if (!(den > 0.0)) {  // not positive definite in this direction
+      broke = true;
+      break;
+    }
+    beta = bn;
+    alpha = gn / den;
   }
   // ---- finish: h, or b again when the iteration did not converge
   for (int64_t i = tid; i < ne; i += kBlock) a.h[e0 + i] = conv ? own_h[i] : a.b[e0 + i];
-  if (w == 0 && tid == 0) {
+  if (wg == 0 && tid == 0) {
     *a.cg_done = conv ? 1 : 0;
     *a.steps = it;
-    *a.relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    *a.relres = g0 > 0.0 ? sqrt(gam / g0) : 0.0;
     if (conv) *a.min_pivot = 0.0;
   }
   if (failed && tid == 0) atomicMax(a.status, static_cast<int32_t>(TK_E_HIP));
+}
+
+struct CgWS {
+  double* rbuf;
+  double* sbuf;
+  double* wbuf;
+  double* rowpart;
+  double* colpart;
+  double* shares;
+  int32_t* sync;
+  int32_t* done;
+};
+
+void carve_cg(Carver& c, int64_t d, CgWS& w) {
+  const int64_t nb = cdiv(d, kCt);
+  const int64_t nt = nb * (nb + 1) / 2;
+  w.rbuf = c.take<double>(2 * d);
+  w.sbuf = c.take<double>(2 * d);
+  w.wbuf = c.take<double>(2 * d);
+  w.rowpart = c.take<double>((nt + 1) * kCt);  // one spare tile slot
+  w.colpart = c.take<double>((nt + 1) * kCt);
+  w.shares = c.take<double>(2 * 1024);
+  w.sync = c.take<int32_t>(kCgSyncWords);
+  w.done = c.take<int32_t>(1);
 }
 
 }  // namespace
@@ -329,45 +618,52 @@ __global__ __launch_bounds__(kBlock) void cg_kernel(CgArgs a) {
 bool cg_ok(int64_t d) { return d >= 1024 && d <= int64_t(kCgMaxBlocks) * kCt; }
 
 size_t cg_bytes(int64_t d) {
-  const int64_t nb = cdiv(d, kCt);
-  const int64_t nt = nb * (nb + 1) / 2;
   Carver c(nullptr);
-  (void)c.take<double>(2 * d);            // pbuf
-  (void)c.take<double>(nt * kCt);         // rowpart
-  (void)c.take<double>(nt * kCt);         // colpart
-  (void)c.take<double>(2 * 1024);         // shares
-  (void)c.take<int32_t>(64);              // sync words
-  (void)c.take<int32_t>(1);               // done
+  CgWS w;
+  carve_cg(c, d, w);
   return c.used;
 }
 
-void launch_cg(const double* M, int64_t d, const double* b, double* h, double* r, void* ws,
-               int32_t* steps, double* relres, double* min_pivot, int32_t* status,
-               int max_iter, hipStream_t st) {
+void launch_cg(const double* M, int64_t d, const double* b, double* h, void* ws, int32_t* steps,
+               double* relres, double* min_pivot, int32_t* status, int max_iter,
+               hipStream_t st) {
   const int64_t nb = cdiv(d, kCt);
   const int64_t nt = nb * (nb + 1) / 2;
   Carver c(ws);
-  CgArgs a;
-  a.pbuf = c.take<double>(2 * d);
-  a.rowpart = c.take<double>(nt * kCt);
-  a.colpart = c.take<double>(nt * kCt);
-  a.shares = c.take<double>(2 * 1024);
-  a.sync = c.take<int32_t>(64);
-  a.cg_done = c.take<int32_t>(1);
+  CgWS w;
+  carve_cg(c, d, w);
   // one workgroup per compute unit, all resident together (the barriers wait
   // on every workgroup of the launch)
+  const bool full = d % kCt == 0;
+  // the grid: one workgroup per compute unit (all resident together: the
+  // barriers wait on every workgroup), then tiles held on chip when they fit
   int grid = device_cu_count();
-  const int res = resident_grid(reinterpret_cast<const void*>(cg_kernel), kBlock, 0);
-  if (res > 0 && grid > res) grid = res;
+  {
+    const int r1 = resident_grid(reinterpret_cast<const void*>(cg_kernel<true, true>), kBlock, 0);
+    const int r2 = resident_grid(reinterpret_cast<const void*>(cg_kernel<true, false>), kBlock, 0);
+    const int r3 = resident_grid(reinterpret_cast<const void*>(cg_kernel<false, false>), kBlock, 0);
+    int r = r1 < r2 ? r1 : r2;
+    r = r < r3 ? r : r3;
+    if (r > 0 && grid > r) grid = r;
+  }
   if (grid > 1024) grid = 1024;
   if (grid > nt) grid = static_cast<int>(nt);
   int64_t own = cdiv(d, grid);
   if (own > kCgMaxOwn) own = kCgMaxOwn;
   grid = static_cast<int>(cdiv(d, own));
+  const bool resident = full && cdiv(nt, grid) <= kMaxRes;
+  CgArgs a;
   a.M = M;
   a.b = b;
   a.h = h;
-  a.r = r;
+  a.rbuf = w.rbuf;
+  a.sbuf = w.sbuf;
+  a.wbuf = w.wbuf;
+  a.rowpart = w.rowpart;
+  a.colpart = w.colpart;
+  a.shares = w.shares;
+  a.sync = w.sync;
+  a.cg_done = w.done;
   a.steps = steps;
   a.relres = relres;
   a.min_pivot = min_pivot;
@@ -377,20 +673,21 @@ void launch_cg(const double* M, int64_t d, const double* b, double* h, double* r
   a.ntiles = nt;
   a.own = own;
   a.max_iter = max_iter;
-  launch_fill_i32(64, 0, a.sync, st);
-  hipLaunchKernelGGL(cg_kernel, dim3(static_cast<unsigned>(grid)), dim3(kBlock), 0, st, a);
+  launch_fill_i32(kCgSyncWords, 0, w.sync, st);
+  const dim3 gd(static_cast<unsigned>(grid));
+  if (resident)
+    hipLaunchKernelGGL((cg_kernel<true, true>), gd, dim3(kBlock), 0, st, a);
+  else if (full)
+    hipLaunchKernelGGL((cg_kernel<true, false>), gd, dim3(kBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((cg_kernel<false, false>), gd, dim3(kBlock), 0, st, a);
 }
 
 const int32_t* cg_done_word(void* ws, int64_t d) {
-  const int64_t nb = cdiv(d, kCt);
-  const int64_t nt = nb * (nb + 1) / 2;
   Carver c(ws);
-  (void)c.take<double>(2 * d);
-  (void)c.take<double>(nt * kCt);
-  (void)c.take<double>(nt * kCt);
-  (void)c.take<double>(2 * 1024);
-  (void)c.take<int32_t>(64);
-  return c.take<int32_t>(1);
+  CgWS w;
+  carve_cg(c, d, w);
+  return w.done;
 }
 
 }  // namespace tk

@@ -300,15 +300,15 @@ void launch_cholesky(double* M, int64_t d, double* Linv_diag, double* min_pivot,
 // Conjugate-gradient solve of M h = b, M symmetric positive definite given by
 // its lower triangle (tk_cg.hip): one persistent launch with grid barriers, at
 // most max_iter iterations, stopping at ||r|| <= 1e-14 ||b||.  ws: cg_bytes(d)
-// bytes; r: d doubles of scratch.  On convergence h holds the solution, the
+// bytes.  On convergence h holds the solution, the
 // done word (cg_done_word) is 1 and *min_pivot = 0; otherwise h = b and the
 // done word is 0, for a factorisation and triangular solves that follow.
 // steps / relres: iterations and final recursive ||r|| / ||b||.
 bool cg_ok(int64_t d);
 size_t cg_bytes(int64_t d);
-void launch_cg(const double* M, int64_t d, const double* b, double* h, double* r, void* ws,
-               int32_t* steps, double* relres, double* min_pivot, int32_t* status,
-               int max_iter, hipStream_t st);
+void launch_cg(const double* M, int64_t d, const double* b, double* h, void* ws, int32_t* steps,
+               double* relres, double* min_pivot, int32_t* status, int max_iter,
+               hipStream_t st);
 const int32_t* cg_done_word(void* ws, int64_t d);
 // Solve (L L^T) x = b in place on x (x holds b on entry).  flags: int32
 // scratch of 2 * ceil(d/nb) + 2 words.  accum (nullable): accum += x, entry by
