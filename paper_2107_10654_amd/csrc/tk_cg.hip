@@ -110,6 +110,25 @@ __device__ inline Next next_entry(double r, double s, double wprev, double alpha
   return {w, fma(-alpha, w, r)};
 }
 
+// x from another lane of the same 16-lane row (DPP control CTRL).
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
+}
+// Sum over the 16 lanes of a row, in every lane: rotations by 8 and 4, then
+// the quad swaps of 2 and 1 (a fixed order).
+__device__ inline double row16_sum(double x) {
+  x += dpp_f64<0x128>(x);  // row_ror:8
+  x += dpp_f64<0x124>(x);  // row_ror:4
+  x += dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  return x;
+}
+
 // Sum of one value per thread over the workgroup in a fixed tree order.
 __device__ inline double block_sum(double v, double* red) {
   const int tid = threadIdx.x;
@@ -141,10 +160,9 @@ struct TileRegs {
 template <bool FULL, bool RES>
 __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
   __shared__ double tile[kCt * kCld];
-  __shared__ double tile2[RES ? kCt * kCld : 1];  // second column-pass buffer
-  __shared__ double tres[RES ? kResLds : 1][RES ? kCt * kCld : 1];
+  __shared__ double tres[RES ? kResLds : 1][RES ? 16 * kBlock : 1];
   __shared__ double vblk[RES ? kMaxVb : 1][kCt];
-  __shared__ double csum_all[RES ? kMaxRes : 1][4][kCt];
+  __shared__ double csum_all[RES ? kMaxRes : 1][16][kCt];  // per row group of 4 rows
   __shared__ int slot_of[RES ? 2 * kMaxRes : 1];  // [k]: slot of tile k's J block, [kMaxRes + k]: I
   __shared__ int diag_of[RES ? kMaxRes : 1];
   __shared__ int64_t blk_of[RES ? kMaxVb : 1];
@@ -330,16 +348,24 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     }
     __syncthreads();
   }
-  // this thread's 16 entries of tile tau (diagonal tiles: upper part zero)
-  auto load_tile = [&](double (&v)[16], int64_t tau) {
+  // Resident tiles are held in 4 x 4 blocks: thread (rb, cb), rb = 4 wave +
+  // lane / 16 and cb = lane % 16, keeps M[4 rb + i][4 cb + j] at 4 i + j.
+  // Row sums then reduce over the 16 lanes of a row group and column sums over
+  // the wave's 4 row groups (lane shuffles) and the 4 waves (LDS).
+  const int rb = (tid >> 6) * 4 + ((tid >> 4) & 3), cb = tid & 15;
+  // this thread's block of tile tau (diagonal tiles: upper part zero)
+  auto load_tile = [&](double (&v)[16], int64_t tau) __attribute__((always_inline)) {
     int64_t fi, fj;
     tile_of(tau, fi, fj);
-    const double* src = a.M + (fi * kCt + srow) * d + fj * kCt + scol;
+    const double* src = a.M + (fi * kCt + 4 * rb) * d + fj * kCt + 4 * cb;
 #pragma unroll
-    for (int e = 0; e < 16; e += 2) {
-      const double2 x = *reinterpret_cast<const double2*>(src + e);
-      v[e] = (fi != fj || scol + e <= srow) ? x.x : 0.0;
-      v[e + 1] = (fi != fj || scol + e + 1 <= srow) ? x.y : 0.0;
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; j += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(src + i * d + j);
+        v[4 * i + j] = (fi != fj || 4 * cb + j <= 4 * rb + i) ? x.x : 0.0;
+        v[4 * i + j + 1] = (fi != fj || 4 * cb + j + 1 <= 4 * rb + i) ? x.y : 0.0;
+      }
     }
   };
   auto phase_s_res = [&](double* rnext, double* wcur) __attribute__((always_inline)) {
@@ -385,7 +411,7 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
           double v[16];
           load_tile(v, t0 + kResReg + k);
 #pragma unroll
-          for (int e = 0; e < 16; ++e) tres[k][srow * kCld + scol + e] = v[e];
+          for (int e = 0; e < 16; ++e) tres[k][e * kBlock + tid] = v[e];  // this thread's own
         }
       }
     }
@@ -395,51 +421,45 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
       if (e < nv) vblk[e / kCt][e % kCt] = next_entry(lr[q], ls[q], lw[q], alpha, beta).r;
     }
     __syncthreads();
-    // row parts of every tile (registers and the LDS-resident tiles), kept
-    // until the stores at the end
+    // every tile's row and column parts, no workgroup barrier between tiles;
+    // row results stay in registers and column results in LDS until the
+    // stores at the end
     double rsv[kMaxRes];
 #pragma unroll
     for (int k = 0; k < kMaxRes; ++k) {
-      double rs = 0.0;
+      rsv[k] = 0.0;
       if (k < nloc) {
-        const double* vJ = vblk[slot_of[k]];
+        double m[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const double m = k < kResReg ? treg[k < kResReg ? k : 0][e]
-                                       : tres[k - kResReg][srow * kCld + scol + e];
-          rs = fma(m, vJ[scol + e], rs);
+        for (int e = 0; e < 16; ++e)
+          m[e] = k < kResReg ? treg[k < kResReg ? k : 0][e] : tres[k - kResReg][e * kBlock + tid];
+        const double* vJ = vblk[slot_of[k]] + 4 * cb;
+        const double* vI = vblk[slot_of[kMaxRes + k]] + 4 * rb;
+        const bool dg = diag_of[k] != 0 && rb == cb;  // a block on the tile's diagonal
+        double y[4], z[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          y[i] = 0.0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) y[i] = fma(m[4 * i + j], vJ[j], y[i]);
         }
-      }
-      rs += __shfl_xor(rs, 1, 64);
-      rs += __shfl_xor(rs, 2, 64);
-      rsv[k] = rs;
-    }
-    // column parts: register tiles through two alternating LDS buffers, one
-    // barrier per tile
-    const int cc = tid & 63, rg = tid >> 6;
 #pragma unroll
-    for (int k = 0; k < kMaxRes; ++k) {
-      if (k < nloc) {
-        const double* T;
-        if (k < kResReg) {
-          double* buf = (k & 1) ? tile2 : tile;
+        for (int j = 0; j < 4; ++j) {
+          z[j] = 0.0;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) buf[srow * kCld + scol + e] = treg[k < kResReg ? k : 0][e];
-          __syncthreads();
-          T = buf;
-        } else {
-          T = tres[k - kResReg];
+          for (int i = 0; i < 4; ++i) {
+            const double mv = (!dg || i > j) ? m[4 * i + j] : 0.0;  // strictly lower
+            z[j] = fma(mv, vI[i], z[j]);
+          }
         }
-        const double* vI = vblk[slot_of[kMaxRes + k]];
-        const bool dg = diag_of[k] != 0;
-        double cs = 0.0;
+        // rows: over the 16 column blocks of the row group (one 16-lane row)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int rw = rg * 16 + i;
-          const double m = (!dg || rw > cc) ? T[rw * kCld + cc] : 0.0;
-          cs = fma(m, vI[rw], cs);
-        }
-        csum_all[k][rg][cc] = cs;
+        for (int i = 0; i < 4; ++i) y[i] = row16_sum(y[i]);
+        // lane cb < 4 keeps row 4 rb + cb; the column partials of the row
+        // group go to LDS, summed over the 16 row groups at the end
+        rsv[k] = cb == 0 ? y[0] : cb == 1 ? y[1] : cb == 2 ? y[2] : y[3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) csum_all[k][rb][4 * cb + j] = z[j];
       }
     }
     __syncthreads();
@@ -447,11 +467,13 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     for (int k = 0; k < kMaxRes; ++k) {
       if (k < nloc) {
         const int64_t tau = t0 + k;
-        if ((tid & 3) == 0) cstore(a.rowpart + tau * kCt + srow, rsv[k]);
-        if (tid < kCt)
-          cstore(a.colpart + tau * kCt + tid,
-                 ((csum_all[k][0][tid] + csum_all[k][1][tid]) + csum_all[k][2][tid]) +
-                     csum_all[k][3][tid]);
+        if (cb < 4) cstore(a.rowpart + tau * kCt + 4 * rb + cb, rsv[k]);
+        if (tid < kCt) {
+          double c = 0.0;
+#pragma unroll
+          for (int g = 0; g < 16; ++g) c += csum_all[k][g][tid];
+          cstore(a.colpart + tau * kCt + tid, c);
+        }
       }
     }
   };
