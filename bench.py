@@ -7,10 +7,13 @@ Workload (default ``c2``): 512 x 512 x 512 float32 tensor, Tucker rank
 
 One step = one sampled core update, every step of the hot path: factor
 leverage scores and integer CDFs, product-distribution sampling, gather of the
-sampled entries, Kronecker-row Gram on MFMA (BF16 operands, FP32
-accumulation), assembly with lambda P and the FP64 right side, FP64 Cholesky,
-solve, FP64 refinement, and the map back from whitened coordinates.  Inputs
-are resident in HBM before the timed region.  Beside the headline number the
+sampled entries, the sketched Gram plus lambda P and the FP64 right side, the
+solve and its FP64 residual check, and the map back from whitened
+coordinates.  The default precision is FP64: the Gram grouped by the last
+mode's sample index on FP64 MFMA, solved by conjugate gradients (Cholesky as
+fallback).  --precision bf16 / f32 times the stream-K Gram on MFMA with FP32
+accumulation, FP64 Cholesky and FP64 refinement.  Inputs are resident in HBM
+before the timed region.  Beside the headline number the
 script times the exact core update and one ALS iteration (exact factor
 updates plus either core update) on the same data, and the loss each core
 update reaches.
@@ -82,24 +85,37 @@ class HipEvents:
             self.lib.hipEventDestroy(h)
 
 
-GRAM_SOURCES = ("tk_gram_sk.hip", "tk_mfma.h", "tk_internal.h")
+GRAM_SOURCES = {"bf16": ("tk_gram_sk.hip", "tk_mfma.h", "tk_internal.h"),
+                "f32": ("tk_gram_sk.hip", "tk_mfma.h", "tk_internal.h"),
+                "f64": ("tk_gram_grouped.hip", "tk_mfma.h", "tk_internal.h")}
 
 
-def kernel_source_hash():
-    """Hash of the sources the stream-K Gram kernel is built from."""
+def kernel_source_hash(prec):
+    """Hash of the sources the Gram kernels of precision prec are built from."""
     h = hashlib.sha256()
-    for name in GRAM_SOURCES:
+    for name in GRAM_SOURCES[prec]:
         with open(os.path.join(ROOT, "paper_2107_10654_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel, workload):
+def grouped_gram_on(d, s, RL, IL):
+    """Whether the library takes the FP64 Gram grouped by the last mode (its
+    plan: d >= 256, R_L >= 2, and clearly fewer multiply-adds than per sample)."""
+    if d < 256 or RL < 2:
+        return False
+    dp = d // RL
+    pt = -(-dp // 64)
+    tiles = pt * (pt + 1) // 2 * 4096.0
+    return 3.0 * tiles * (s + IL * RL * RL) <= s * d * d * 0.5
+
+
+def read_traffic(kernel, workload, prec):
     """HBM bytes per launch from profiles/traffic.txt, if taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    src = kernel_source_hash()
+    src = kernel_source_hash(prec)
     with open(path) as f:
         for line in f:
             parts = line.split()
@@ -171,7 +187,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--precision", default="f64", choices=["bf16", "f32", "f64"])
     ap.add_argument("--refine-max", type=int, default=8)
     ap.add_argument("--cpu-samples", type=int, default=131072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -283,17 +299,47 @@ def main():
     log(f"[bench] {args.steps} sketched updates: {ms:.3f} ms each; stages (ms): "
         + ", ".join(f"{n} {v:.3f}" for n, v in stage_ms.items()))
 
-    # roofline of the dominant kernel (the sketched Gram)
+    # rooflines of the Gram stage and of the solve; the larger stage is "roofline"
     gram_ms = stage_ms["gram"]
-    flops = float(s) * d * (d + 1)
+    ranks = list(cfg["ranks"])
+    dims = list(cfg["dims"])
+    L = max(n for n in range(len(ranks)) if ranks[n] >= 2)
+    grouped = args.precision == "f64" and grouped_gram_on(d, s, ranks[L], dims[L])
+    if grouped:
+        # lower triangle: each sample adds d'(d'+1)/2 products to its group's
+        # B_k, each group adds d(d+1)/2 to M (one multiply-add = 2 flops)
+        dp = d // ranks[L]
+        flops = float(s) * dp * (dp + 1) + float(dims[L]) * d * (d + 1)
+        kern = ("grouped FP64 Gram (grp_block_kernel and grp_expand_kernel on FP64 MFMA, with "
+                "the sort and sorted-row kernels; time of the Gram stage)")
+    else:
+        flops = float(s) * d * (d + 1)
+        kern = (f"gram_sk_kernel (stream-K Gram, {args.precision} operands, fp32 "
+                "accumulation; time of the Gram stage, with its slot-index kernel)")
     achieved = flops / (gram_ms * 1e-3) / 1e12
     peak = PEAKS_TFLOPS[args.precision]
-    traffic = read_traffic(f"gram_{args.precision}", args.workload)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": f"gram_sk_kernel (stream-K Gram, {args.precision} operands, fp32 "
-                          "accumulation; time of the Gram stage, with its slot-index kernel)",
-                "algorithmic_flops": flops, "kernel_ms": round(gram_ms, 4)}
+    traffic = read_traffic(f"gram_{args.precision}", args.workload, args.precision)
+    gram_roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kern,
+                 "algorithmic_flops": flops, "kernel_ms": round(gram_ms, 4)}
+    solve_roof = None
+    cg_iters = int(info[2].item()) if args.precision == "f64" and info[4].item() == 0.0 else 0
+    if cg_iters > 0:
+        # conjugate gradients: one product with the symmetric M per iteration
+        # plus the start, 2 d^2 flops each, on the FP64 vector units
+        solve_ms = stage_ms["solve"]
+        sflops = 2.0 * d * d * (cg_iters + 1)
+        sach = sflops / (solve_ms * 1e-3) / 1e12
+        solve_roof = {"bound": "alu", "achieved": round(sach, 3), "peak": PEAKS_TFLOPS["f64"],
+                      "unit": "TFLOP/s", "frac": round(sach / PEAKS_TFLOPS["f64"], 4),
+                      "traffic": None,
+                      "kernel": f"cg_kernel (persistent conjugate gradients, {cg_iters} "
+                                "iterations, two grid barriers each; time of the solve stage)",
+                      "algorithmic_flops": sflops, "kernel_ms": round(solve_ms, 4)}
+    if solve_roof is not None and stage_ms["solve"] > gram_ms:
+        roofline, other = solve_roof, gram_roof
+    else:
+        roofline, other = gram_roof, solve_roof
 
     extras = {}
     if not args.no_extras:
@@ -395,9 +441,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
                    "gram_operands": args.precision, "gram_accumulate": "f32" if args.precision != "f64" else "f64",
-                   "solve": "f64 Cholesky + f64 refinement" if args.precision != "f64" else "f64 Cholesky",
+                   "gram": "grouped by the last mode" if grouped else "per sample",
+                   "solve": ("f64 Cholesky + f64 refinement" if args.precision != "f64" else
+                             f"f64 conjugate gradients ({cg_iters} iterations)" if cg_iters else
+                             "f64 Cholesky"),
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "roofline_other_stage": other,
         "cpu_baseline": cpu,
         "oracle_rel_err": oracle_err,
     }
@@ -563,7 +613,10 @@ def bench_microbench(args, tk, workloads, np, torch, dev):
 
 
 def bench_batch(args, tk, workloads, np, torch, dev):
-    """The 64-problem batch: tuner, graph capture, timed graph replays."""
+    """The 64-problem batch: tuner, graph capture, timed graph replays (BF16 or
+    FP32 stream-K Gram; the default FP64 precision selects BF16 here)."""
+    if args.precision == "f64":
+        args.precision = "bf16"
     t_gen = time.perf_counter()
     probs = workloads.batch_problems(seed=4, count=64)
     lam = 1e-3

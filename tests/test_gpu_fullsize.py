@@ -1,5 +1,7 @@
-"""Parity at the full workload sizes, in the launch configuration bench.py times
-(f32 problem, BF16 Gram with FP32 accumulation, FP64 Cholesky and refinement).
+"""Parity at the full workload sizes, in the launch configurations bench.py times:
+FP64 (its default: the Gram grouped by the last mode, conjugate gradients) and
+--precision bf16 (BF16 Gram with FP32 accumulation, FP64 Cholesky and
+refinement), on the f32 problems.
 
 The oracle cannot solve these sizes end to end in seconds, so the checks are
 the parts it computes exactly and properties that hold at any size:
