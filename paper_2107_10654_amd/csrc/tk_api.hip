@@ -214,11 +214,18 @@ bool use_cg(const Geom& g, int64_t s, const tk_sketch_opts* o, int call) {
   return call == TK_CALL_SKETCHED && o->gram_precision == TK_F64 && cg_ok(g.d) && s >= 8 * g.d;
 }
 
+// The sampled update's right side and residual check grouped like the Gram
+// (FP64 grouped Gram; the adjoint keeps the per-sample passes).
+bool grouped_vectors(const GramPlan& pl, int call) {
+  return call == TK_CALL_SKETCHED && grouped_resid_ok(pl.grp);
+}
+
 SketchNeeds sketch_needs(const tk_problem* p, const Geom& g, int64_t s, const tk_sketch_opts* o,
-                         int call) {
+                         int call, const GramPlan& pl) {
   const bool adj = call == TK_CALL_ADJOINT;
   const int32_t prec = o->gram_precision;
-  return {adj || !resid_small_ok(g) || prec == TK_F64,
+  const bool gv = grouped_vectors(pl, call);
+  return {adj || (prec == TK_F64 && !pl.grp.on) || (!resid_small_ok(g) && !gv),
           adj || !core_chain_small_ok(g) || !refine_check_p_ok(g), use_cg(g, s, o, call),
           o->augmented ? make_geom_aug(p).total_q : 0, o->sampling == 1};
 }
@@ -592,7 +599,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call, pl));
       break;
     }
     case TK_CALL_ADJOINT: {
@@ -601,7 +608,7 @@ size_t tucker_workspace_bytes(const tk_problem* p, const tk_sketch_opts* opts, i
       if (s < 1) return 0;
       const GramPlan pl = plan_sketch_gram(p, g, s, opts);
       SketchWS w;
-      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call));
+      carve_sketch(c, g, s, pl, w, sketch_needs(p, g, s, opts, call, pl));
       AdjWS a;
       carve_adjoint(c, g, s, a);
       break;
@@ -798,6 +805,7 @@ struct SketchRun {
   double lam_sys = 0.0;          // lambda of the assembled and refined system
   int chol_grid = 0;             // cap of the Cholesky's workgroups (0: one per CU)
   bool cg = false;               // FP64 solve by conjugate gradients, Cholesky only as fallback
+  bool grp_vec = false;          // right side and residual grouped like the Gram (no sample rows)
   void stage(int k) const {
     if (o->stage_events) (void)hipEventRecord(static_cast<hipEvent_t>(o->stage_events[k]), st);
   }
@@ -868,8 +876,9 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   // 3. sampled entries (x_t, mask) and effective weights; sample rows
   launch_gather(g, p->X, p->dtype, p->mask, R.idx, R.weight, R.s, w.weff, w.xw, w.missing,
                 R.status, st, R.aug ? 1 : 0);
-  launch_pregather(R.ga, R.idx, w.weff, R.s, R.q64s, R.want_rows64 ? w.rows64 : nullptr, w.rows32,
-                   st);
+  if (!R.grp_vec)  // the grouped Gram and vectors stage their own sorted rows
+    launch_pregather(R.ga, R.idx, w.weff, R.s, R.q64s, R.want_rows64 ? w.rows64 : nullptr,
+                     w.rows32, st);
   R.stage(3);
   return TK_OK;
 }
@@ -879,7 +888,9 @@ void sketch_factor(SketchRun& R) {
   const Geom& g = R.g;
   SketchWS& w = R.w;
   // 5. right-hand side sum_t w_t x_t q_t (FP64)
-  if (resid_small_ok(g))
+  if (R.grp_vec)
+    launch_grouped_resid(R.ga, R.pl.grp, R.q64s, w.gpart, nullptr, w.rhs, R.st);
+  else if (resid_small_ok(g))
     launch_resid_small(R.ga, R.idx, R.q64s, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
   else if (resid_big_ok(g))
@@ -897,7 +908,7 @@ void sketch_factor(SketchRun& R) {
 void sketch_gram(SketchRun& R) {
   SketchWS& w = R.w;
   if (R.pl.grp.on) {
-    launch_grouped_gram(R.ga, R.pl.grp, R.idx, R.q64s, w.weff, w.lev.P, R.lam_sys, w.gpart, w.M,
+    launch_grouped_gram(R.ga, R.pl.grp, R.idx, R.q64s, w.weff, w.xw, w.lev.P, R.lam_sys, w.gpart, w.M,
                         R.st);
     R.stage(4);
     return;
@@ -965,7 +976,9 @@ void refined_solve(SketchRun& R, double lambda, const double* b, const double* x
   }
   R.stage(7);
   for (int k = 0; k <= iters; ++k) {
-    if (resid_small_ok(g)) {
+    if (R.grp_vec && xw == w.xw && !refine) {  // one check of the FP64 solve
+      launch_grouped_resid(R.ga, R.pl.grp, R.q64s, w.gpart, h, w.r, st);
+    } else if (resid_small_ok(g)) {
       launch_resid_small(R.ga, R.idx, R.q64s, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
     } else if (resid_big_ok(g)) {
       launch_resid_big(g, w.rows64, xw, w.weff, h, R.s, w.vpart, w.r, w.done, st);
@@ -1007,7 +1020,8 @@ tk_status sketch_carve(SketchRun& R, const tk_problem* p, const tk_sketch_opts* 
   R.o = o;
   R.st = static_cast<hipStream_t>(stream);
   R.pl = plan_sketch_gram(p, R.g, s, o);
-  const SketchNeeds need = sketch_needs(p, R.g, s, o, call);
+  const SketchNeeds need = sketch_needs(p, R.g, s, o, call, R.pl);
+  R.grp_vec = grouped_vectors(R.pl, call);
   R.want_rows64 = need.rows64;
   R.cg = need.cg;
   carve_sketch(c, R.g, s, R.pl, R.w, need, with_partials);
@@ -1202,7 +1216,9 @@ tk_status tucker_sketched_system(const tk_problem* p, const tk_sketch_opts* o,
   const Geom& g = R.g;
   SketchWS& w = R.w;
   sketch_gram(R);
-  if (resid_small_ok(g))
+  if (R.grp_vec)
+    launch_grouped_resid(R.ga, R.pl.grp, R.q64s, w.gpart, nullptr, w.rhs, R.st);
+  else if (resid_small_ok(g))
     launch_resid_small(R.ga, R.idx, R.q64s, w.xw, nullptr, nullptr, R.s, w.vpart, w.rhs, nullptr,
                        R.st);
   else if (resid_big_ok(g))

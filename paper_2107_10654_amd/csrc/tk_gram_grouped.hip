@@ -163,13 +163,16 @@ struct GrpArgs {
 
 // ------------------------------------------------------------------ pass 2: B_k
 // Sorted sample rows: element e = u S' + j holds entry j of the concatenated
-// rows of modes < L of sample t = perm[u]; scs[u] = w_t prod_{n>L} q^(n)_{i_n}[0]^2.
+// rows of modes < L of sample t = perm[u]; with tau_t = prod_{n>L} q^(n)_{i_n}[0]
+// (the modes after L have rank 1), scs[u] = w_t tau_t^2 and xs[u] = (w x)_t tau_t.
 __global__ __launch_bounds__(kBlock) void grp_rows_kernel(Geom g, const int32_t* __restrict__ idx,
                                                           int64_t s, const double* __restrict__ Q64,
                                                           const double* __restrict__ weff,
+                                                          const double* __restrict__ xw,
                                                           const int32_t* __restrict__ perm, int L,
                                                           int sp, double* __restrict__ rows,
-                                                          double* __restrict__ scs) {
+                                                          double* __restrict__ scs,
+                                                          double* __restrict__ xs) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= s * sp) return;
   const int64_t u = e / sp;
@@ -181,14 +184,14 @@ __global__ __launch_bounds__(kBlock) void grp_rows_kernel(Geom g, const int32_t*
   if (i < 0 || i >= g.dims[n]) i = 0;  // flagged by the gather pass (weight 0)
   rows[e] = Q64[g.qoff[n] + static_cast<int64_t>(i) * g.ranks[n] + (j - g.soff[n])];
   if (j == 0) {
-    double sc = weff[t];
+    double tau = 1.0;
     for (int m = L + 1; m < g.order; ++m) {
       int32_t im = idx[static_cast<int64_t>(m) * s + t];
       if (im < 0 || im >= g.dims[m]) im = 0;
-      const double q = Q64[g.qoff[m] + im];  // rank 1
-      sc *= q * q;
+      tau *= Q64[g.qoff[m] + im];  // rank 1
     }
-    scs[u] = sc;
+    scs[u] = weff[t] * (tau * tau);
+    xs[u] = xw[t] * tau;
   }
 }
 
@@ -306,6 +309,424 @@ __global__ __launch_bounds__(kBlock) void grp_block_kernel(Geom g, GrpArgs a) {
         const int col = qb * 32 + j * 16 + (lane & 15);
         out[row * kGt + col] = acc[i][j][v];
       }
+}
+
+// Sample-split form for at most three modes before L (NL): workgroup (group
+// k, lower 64 x 64 tile (ta, tb) of d' x d'); every wave computes the whole
+// tile as 4 x 4 blocks of v_mfma_f64_16x16x4 over its own quarter of each
+// 32-sample chunk (samples 8 w .. 8 w + 7), so each formed operand feeds four
+// products and no wave idles on a diagonal tile (its blocks above the
+// diagonal are skipped).  The four partial tiles are added in wave order
+// through LDS at the end.
+template <int NR, int NL>
+__global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpArgs a) {
+  extern __shared__ double rowbuf[];  // [kGkc][S' + 1], then the 64 x 64 reduction tile
+  __shared__ double ssc[kGkc];
+  const int64_t tau = blockIdx.x % a.ptiles;
+  const int64_t k = blockIdx.x / a.ptiles;
+  int64_t ta, tb;
+  tri_index(tau, ta, tb);
+  const bool diag = ta == tb;
+  const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int SP = a.sp, LD = a.sp + 1;
+  double* red = rowbuf + kGkc * LD;
+  // LDS offsets (within a sample's row) of the digits of this lane's operand rows
+  int oa[4][NL], ob[4][NL];
+  bool va[4], vb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t pa = ta * kGt + i * 16 + (lane & 15), pb = tb * kGt + i * 16 + (lane & 15);
+    va[i] = pa < a.dp;
+    vb[i] = pb < a.dp;
+    int64_t xa = va[i] ? pa : 0, xb = vb[i] ? pb : 0;
+#pragma unroll
+    for (int n = NL - 1; n >= 0; --n) {
+      const int R = g.ranks[n];
+      oa[i][n] = g.soff[n] + static_cast<int>(xa % R);
+      ob[i][n] = g.soff[n] + static_cast<int>(xb % R);
+      xa /= R;
+      xb /= R;
+    }
+  }
+  // staging: element e = tid + 256 i of a chunk -> LDS (e / S') LD + e % S'
+  const int nel = kGkc * SP;
+  int lofs[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int e = tid + kBlock * i;
+    lofs[i] = e < nel ? (e / SP) * LD + e % SP : -1;
+  }
+  double pf[NR];
+  double psc = 0.0;
+  auto fetch = [&](int64_t c0) {
+    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * SP;
+    const double* src = a.rows + c0 * SP;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int e = tid + kBlock * i;
+      pf[i] = e < lim ? src[e] : 0.0;
+    }
+    if (tid < kGkc) psc = c0 + tid < g1 ? a.scs[c0 + tid] : 0.0;
+  };
+  doublex4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  if (g0 < g1) fetch(g0);
+  for (int64_t c0 = g0; c0 < g1; c0 += kGkc) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+      if (lofs[i] >= 0) rowbuf[lofs[i]] = pf[i];
+    if (tid < kGkc) ssc[tid] = psc;
+    __syncthreads();
+    if (c0 + kGkc < g1) fetch(c0 + kGkc);
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int kk = (2 * w + h) * 4 + (lane >> 4);
+      const double* rk = rowbuf + kk * LD;
+      const double sw = ssc[kk];
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double x = sw, y = 1.0;
+#pragma unroll
+        for (int n = 0; n < NL; ++n) {
+          x *= rk[oa[i][n]];
+          y *= rk[ob[i][n]];
+        }
+        av[i] = va[i] ? x : 0.0;
+        bv[i] = vb[i] ? y : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (!diag || i >= j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // ((acc_3 + acc_2) + acc_1) + acc_0 through one LDS tile; accumulator v of
+  // lane l: row l / 16 + 4 v, column l % 16 of its 16 x 16 block
+  for (int src = 3; src >= 0; --src) {
+    if (w == src) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int e = (i * 16 + (lane >> 4) + 4 * v) * kGt + j * 16 + (lane & 15);
+            red[e] = src == 3 ? acc[i][j][v] : red[e] + acc[i][j][v];
+          }
+    }
+    __syncthreads();
+  }
+  double* out = a.B + (k * a.ptiles + tau) * (kGt * kGt);
+  for (int e = tid; e < kGt * kGt; e += kBlock) out[e] = red[e];
+}
+
+// x from another lane of the same 16-lane row (DPP control CTRL); the sum over
+// the 16 lanes of a row, in every lane, in a fixed order.
+template <int CTRL>
+__device__ inline double grp_dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned int>(lo)));
+}
+__device__ inline double row16_sum(double x) {
+  x += grp_dpp<0x128>(x);  // row_ror:8
+  x += grp_dpp<0x124>(x);  // row_ror:4
+  x += grp_dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += grp_dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  return x;
+}
+
+// ------------------------------------------------------------------ right side and residual
+// The same grouping for the vectors of the solve:
+//   sum_t q_t (xw_t - weff_t q_t.h) = sum_k (sum_{t: i_L = k} c_t y_t) (x) e_k,
+//   c_t = xs_t - scs_t (y_t . u_k),  u_k[p] = sum_m h[p R_L + m] e_k[m]
+// (without h: c_t = xs_t, the right side).
+
+// Chunk staging of the vector kernels: the 32 S' doubles of a chunk of sorted
+// rows, four per thread in registers (the rest, for S' > 32, loaded directly),
+// so that the next chunk's loads are in flight while the current one is used.
+struct RowStage {
+  double pf[4];
+  __device__ void fetch(const double* rows, int64_t c0, int64_t g1, int sp) {
+    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * sp;
+    const double* src = rows + c0 * sp;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = threadIdx.x + kBlock * i;
+      pf[i] = e < lim ? src[e] : 0.0;
+    }
+  }
+  __device__ void store(double* rowbuf, const double* rows, int64_t c0, int64_t g1, int sp) {
+    const int ld = sp + 1, nel = kGkc * sp;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = threadIdx.x + kBlock * i;
+      if (e < nel) rowbuf[(e / sp) * ld + e % sp] = pf[i];
+    }
+    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * sp;
+    for (int e = threadIdx.x + 4 * kBlock; e < nel; e += kBlock)
+      rowbuf[(e / sp) * ld + e % sp] = e < lim ? rows[c0 * sp + e] : 0.0;
+  }
+};
+
+// U[k][p] = u_k[p]
+__global__ __launch_bounds__(kBlock) void grp_hvec_kernel(GrpArgs a, const double* __restrict__ h,
+                                                          double* __restrict__ U) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= a.groups * a.dp) return;
+  const int64_t k = e / a.dp, p = e % a.dp;
+  const double* ek = a.E + k * a.RL;
+  const double* hp = h + p * a.RL;
+  double sum = 0.0;
+  for (int m = 0; m < a.RL; ++m) sum = fma(hp[m], ek[m], sum);
+  U[e] = sum;
+}
+
+// V[k][p] = sum_{t in group k} c_t y_t[p], one workgroup per group, the group's
+// samples in their sorted order in chunks of 32 staged in LDS.  A thread keeps
+// the sums of p = tid + 256 i (i < kResPer); the dots y_t . u_k are taken by 8
+// threads per sample over p = z, z + 8, ... and added in a fixed tree.
+constexpr int kResPer = 4;  // d' <= 1024
+template <int NL>
+__global__ __launch_bounds__(kBlock) void grp_resid_kernel(Geom g, GrpArgs a,
+                                                           const double* __restrict__ xs,
+                                                           const double* __restrict__ U,
+                                                           double* __restrict__ V) {
+  extern __shared__ double smem[];  // rows [kGkc][S' + 1], u_k [d'], digit offsets [d'][NL]
+  __shared__ double cfac[kGkc];
+  const int SP = a.sp, LD = a.sp + 1;
+  const int64_t dp = a.dp;
+  double* rowbuf = smem;
+  double* uk = smem + kGkc * LD;
+  int* dig = reinterpret_cast<int*>(uk + dp);
+  const int64_t k = blockIdx.x;
+  const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
+  const int tid = threadIdx.x;
+  for (int64_t p = tid; p < dp; p += kBlock) {
+    if (U) uk[p] = U[k * dp + p];
+    int64_t x = p;
+#pragma unroll
+    for (int n = NL - 1; n >= 0; --n) {
+      const int R = g.ranks[n];
+      dig[p * NL + n] = g.soff[n] + static_cast<int>(x % R);
+      x /= R;
+    }
+  }
+  double v[kResPer];
+  int od[kResPer][NL];  // this thread's digit offsets
+#pragma unroll
+  for (int i = 0; i < kResPer; ++i) {
+    v[i] = 0.0;
+    int64_t x = tid + kBlock * i < dp ? tid + kBlock * i : 0;
+#pragma unroll
+    for (int n = NL - 1; n >= 0; --n) {
+      const int R = g.ranks[n];
+      od[i][n] = g.soff[n] + static_cast<int>(x % R);
+      x /= R;
+    }
+  }
+  const int jd = tid >> 3, zd = tid & 7;  // dot roles: sample jd, p slice zd
+  RowStage stg;
+  if (g0 < g1) stg.fetch(a.rows, g0, g1, SP);
+  for (int64_t c0 = g0; c0 < g1; c0 += kGkc) {
+    __syncthreads();  // previous chunk done (and the tables above written)
+    stg.store(rowbuf, a.rows, c0, g1, SP);
+    __syncthreads();
+    if (c0 + kGkc < g1) stg.fetch(a.rows, c0 + kGkc, g1, SP);
+    // c_j for the chunk's samples
+    double dot = 0.0;
+    if (U) {
+      const double* rj = rowbuf + jd * LD;
+      for (int64_t p = zd; p < dp; p += 8) {
+        double y = 1.0;
+#pragma unroll
+        for (int n = 0; n < NL; ++n) y *= rj[dig[p * NL + n]];
+        dot = fma(y, uk[p], dot);
+      }
+      dot += __shfl_xor(dot, 4, 64);
+      dot += __shfl_xor(dot, 2, 64);
+      dot += __shfl_xor(dot, 1, 64);
+    }
+    if (zd == 0) {
+      const int64_t u = c0 + jd;
+      cfac[jd] = u < g1 ? (U ? fma(-a.scs[u], dot, xs[u]) : xs[u]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kResPer; ++i) {
+      const int64_t p = tid + kBlock * i;
+      if (p < dp) {
+        double acc = v[i];
+#pragma unroll 8
+        for (int j = 0; j < kGkc; ++j) {
+          const double* rj = rowbuf + j * LD;
+          double y = cfac[j];
+#pragma unroll
+          for (int n = 0; n < NL; ++n) y *= rj[od[i][n]];
+          acc += y;
+        }
+        v[i] = acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kResPer; ++i) {
+    const int64_t p = tid + kBlock * i;
+    if (p < dp) V[k * dp + p] = v[i];
+  }
+}
+
+// The same sums on FP64 MFMA, for d'' = prod_{n<L-1} R_n <= 64 and R_{L-1} <= 64.
+// With y_t = o_t (x) b_t (o_t over the modes before L - 1, b_t the row of mode
+// L - 1) and U2_k = u_k as a d'' x R_{L-1} matrix,
+//   y_t . u_k = o_t^T U2_k b_t,  sum_t c_t y_t = vec(sum_t c_t o_t b_t^T),
+// so per chunk of 32 samples Z = O U2 (32 x R_{L-1}) and V2 += O^T diag(c) B
+// (d'' x R_{L-1}) are 16 x 16 block products.  Wave w takes the Z blocks and
+// the V2 blocks congruent to w mod 4; each block's sums run in a fixed order.
+constexpr int kRmMax = 64;
+template <int NL>
+__global__ __launch_bounds__(kBlock) void grp_resid_mfma_kernel(Geom g, GrpArgs a,
+                                                                const double* __restrict__ xs,
+                                                                const double* __restrict__ U,
+                                                                double* __restrict__ V) {
+  extern __shared__ double smem[];  // rows [kGkc][S' + 1], u_k [d'' R1]
+  __shared__ double cfac[kGkc];
+  __shared__ double zpart[kRmMax / 16][kGkc];
+  __shared__ int od[kRmMax][NL > 1 ? NL - 1 : 1];  // row offsets of o's digits
+  const int SP = a.sp, LD = a.sp + 1;
+  const int R1 = g.ranks[NL - 1];
+  const int nd = static_cast<int>(a.dp / R1);  // d''
+  const int nc1 = (R1 + 15) / 16, nr0 = (nd + 15) / 16;
+  const int sb = g.soff[NL - 1];
+  double* rowbuf = smem;
+  double* uk = smem + kGkc * LD;
+  const int64_t k = blockIdx.x;
+  const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (U)
+    for (int e = tid; e < nd * R1; e += kBlock) uk[e] = U[k * a.dp + e];
+  for (int p0 = tid; p0 < nd; p0 += kBlock) {
+    int x = p0;
+#pragma unroll
+    for (int n = NL - 2; n >= 0; --n) {
+      const int R = g.ranks[n];
+      od[p0][n] = g.soff[n] + x % R;
+      x /= R;
+    }
+  }
+  // o_j[p0] from the staged rows (1 when no mode precedes L - 1)
+  auto o_of = [&](int j, int p0) {
+    double x = 1.0;
+    const double* rj = rowbuf + j * LD;
+#pragma unroll
+    for (int n = 0; n < NL - 1; ++n) x *= rj[od[p0][n]];
+    return x;
+  };
+  const int nbv = nr0 * nc1;      // V2 blocks
+  doublex4 accv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) accv[i] = doublex4{0.0, 0.0, 0.0, 0.0};
+  RowStage stg;
+  if (g0 < g1) stg.fetch(a.rows, g0, g1, SP);
+  for (int64_t c0 = g0; c0 < g1; c0 += kGkc) {
+    __syncthreads();  // the previous chunk is done (and the tables above are written)
+    stg.store(rowbuf, a.rows, c0, g1, SP);
+    __syncthreads();
+    if (c0 + kGkc < g1) stg.fetch(a.rows, c0 + kGkc, g1, SP);
+    if (U) {
+      // Z blocks (sample half, column block): dots of o_j^T U2 with b_j
+      for (int zb = w; zb < 2 * nc1; zb += 4) {
+        const int sh = zb & 1, cbk = zb >> 1;
+        doublex4 z = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < (nd + 3) / 4; ++ks) {
+          const int p0 = ks * 4 + (lane >> 4);
+          const int j = sh * 16 + (lane & 15);
+          const int p1 = cbk * 16 + (lane & 15);
+          const double av = p0 < nd ? o_of(j, p0) : 0.0;
+          const double bv = (p0 < nd && p1 < R1) ? uk[p0 * R1 + p1] : 0.0;
+          z = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, z, 0, 0, 0);
+        }
+        // accumulator v: sample sh 16 + lane / 16 + 4 v, column cbk 16 + lane % 16
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = sh * 16 + (lane >> 4) + 4 * v;
+          const int p1 = cbk * 16 + (lane & 15);
+          double t = p1 < R1 ? z[v] * rowbuf[j * LD + sb + p1] : 0.0;
+          t = row16_sum(t);
+          if ((lane & 15) == 0) zpart[cbk][j] = t;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid < kGkc) {
+      const int64_t u = c0 + tid;
+      double dot = 0.0;
+      if (U)
+        for (int c = 0; c < nc1; ++c) dot += zpart[c][tid];
+      cfac[tid] = u < g1 ? (U ? fma(-a.scs[u], dot, xs[u]) : xs[u]) : 0.0;
+    }
+    __syncthreads();
+    // V2 blocks (row block of o, column block of b) over the chunk's 32 samples
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = w + 4 * i;
+      if (b < nbv) {
+        const int rb = b / nc1, cb = b % nc1;
+#pragma unroll 2
+        for (int ks = 0; ks < kGkc / 4; ++ks) {
+          const int j = ks * 4 + (lane >> 4);
+          const int p0 = rb * 16 + (lane & 15);
+          const int p1 = cb * 16 + (lane & 15);
+          const double av = p0 < nd ? cfac[j] * o_of(j, p0) : 0.0;
+          const double bv = p1 < R1 ? rowbuf[j * LD + sb + p1] : 0.0;
+          accv[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accv[i], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = w + 4 * i;
+    if (b < nbv) {
+      const int rb = b / nc1, cb = b % nc1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p0 = rb * 16 + (lane >> 4) + 4 * v;
+        const int p1 = cb * 16 + (lane & 15);
+        if (p0 < nd && p1 < R1) V[k * a.dp + p0 * R1 + p1] = accv[i][v];
+      }
+    }
+  }
+}
+
+// out[p R_L + m] = sum_k V[k][p] e_k[m]: workgroup per 16 outputs, 16 threads
+// per output summing groups z, z + 16, ... then a fixed shuffle tree
+__global__ __launch_bounds__(kBlock) void grp_vec_expand_kernel(GrpArgs a,
+                                                                const double* __restrict__ V,
+                                                                double* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 16 + (threadIdx.x >> 4);
+  const int z = threadIdx.x & 15;
+  double sum = 0.0;
+  if (e < a.dp * a.RL) {
+    const int64_t p = e / a.RL;
+    const int m = static_cast<int>(e % a.RL);
+    for (int64_t k = z; k < a.groups; k += 16) sum = fma(V[k * a.dp + p], a.E[k * a.RL + m], sum);
+  }
+  sum += __shfl_xor(sum, 8, 64);
+  sum += __shfl_xor(sum, 4, 64);
+  sum += __shfl_xor(sum, 2, 64);
+  sum += __shfl_xor(sum, 1, 64);
+  if (e < a.dp * a.RL && z == 0) out[e] = sum;
 }
 
 // ------------------------------------------------------------------ pass 3: M
@@ -442,6 +863,9 @@ struct GrpWS {
   int32_t* part;
   double* rows;
   double* scs;
+  double* xs;
+  double* U;
+  double* V;
   double* B;
 };
 
@@ -452,6 +876,9 @@ void carve_grouped(Carver& c, const GroupedPlan& gp, GrpWS& w) {
   w.part = c.take<int32_t>(gp.nparts);
   w.rows = c.take<double>(static_cast<size_t>(gp.s) * gp.sp);
   w.scs = c.take<double>(gp.s);
+  w.xs = c.take<double>(gp.s);
+  w.U = c.take<double>(static_cast<size_t>(gp.groups) * gp.dp);
+  w.V = c.take<double>(static_cast<size_t>(gp.groups) * gp.dp);
   w.B = c.take<double>(static_cast<size_t>(gp.groups) * gp.ptiles * kGt * kGt);
 }
 
@@ -462,6 +889,23 @@ int expand_ne(int rl) { return rl <= 8 ? 1 : rl <= 16 ? 2 : rl <= 32 ? 4 : 8; }
 template <int NR>
 void launch_block(const Geom& gr, const GrpArgs& a, unsigned grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(grp_block_kernel<NR>, dim3(grid), dim3(kBlock), lds, st, gr, a);
+}
+template <int NR, int NL>
+void launch_block_split(const Geom& gr, const GrpArgs& a, size_t lds, hipStream_t st) {
+  if (lds > 65536)
+    ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL>),
+                   static_cast<int>(lds));
+  hipLaunchKernelGGL((grp_block_split_kernel<NR, NL>),
+                     dim3(static_cast<unsigned>(a.groups * a.ptiles)), dim3(kBlock), lds, st, gr,
+                     a);
+}
+template <int NR>
+void launch_block_split_nl(const Geom& gr, const GrpArgs& a, size_t lds, hipStream_t st) {
+  switch (a.L) {
+    case 1: launch_block_split<NR, 1>(gr, a, lds, st); break;
+    case 2: launch_block_split<NR, 2>(gr, a, lds, st); break;
+    default: launch_block_split<NR, 3>(gr, a, lds, st); break;
+  }
 }
 template <int NE>
 void launch_expand(const Geom& gr, const GrpArgs& a, int64_t nunits, int ncb, hipStream_t st) {
@@ -512,8 +956,8 @@ size_t grouped_bytes(const GroupedPlan& gp) {
 }
 
 void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* idx,
-                         const double* Q64, const double* weff, const double* P, double lambda,
-                         void* ws, double* M, hipStream_t st) {
+                         const double* Q64, const double* weff, const double* xw, const double* P,
+                         double lambda, void* ws, double* M, hipStream_t st) {
   Carver c(ws);
   GrpWS w;
   carve_grouped(c, gp, w);
@@ -530,7 +974,8 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
                      key, gp.s, gp.groups, gp.nb, w.rank, w.cnt, w.perm);
   const int64_t nel = gp.s * gp.sp;
   hipLaunchKernelGGL(grp_rows_kernel, dim3(static_cast<unsigned>(cdiv(nel, kBlock))), dim3(kBlock),
-                     0, st, gr, idx, gp.s, Q64, weff, w.perm, gp.L, gp.sp, w.rows, w.scs);
+                     0, st, gr, idx, gp.s, Q64, weff, xw, w.perm, gp.L, gp.sp, w.rows, w.scs,
+                     w.xs);
   GrpArgs a;
   a.rows = w.rows;
   a.scs = w.scs;
@@ -549,11 +994,21 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
   a.sp = gp.sp;
   const unsigned grid = static_cast<unsigned>(gp.groups * gp.ptiles);
   const size_t lds = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double);
-  switch (block_nr(gp.sp)) {
-    case 2: launch_block<2>(gr, a, grid, lds, st); break;
-    case 4: launch_block<4>(gr, a, grid, lds, st); break;
-    case 8: launch_block<8>(gr, a, grid, lds, st); break;
-    default: launch_block<17>(gr, a, grid, lds, st); break;
+  if (gp.L <= 3) {  // every wave the whole tile over a quarter of each chunk
+    const size_t lds2 = lds + static_cast<size_t>(kGt) * kGt * sizeof(double);
+    switch (block_nr(gp.sp)) {
+      case 2: launch_block_split_nl<2>(gr, a, lds2, st); break;
+      case 4: launch_block_split_nl<4>(gr, a, lds2, st); break;
+      case 8: launch_block_split_nl<8>(gr, a, lds2, st); break;
+      default: launch_block_split_nl<17>(gr, a, lds2, st); break;
+    }
+  } else {
+    switch (block_nr(gp.sp)) {
+      case 2: launch_block<2>(gr, a, grid, lds, st); break;
+      case 4: launch_block<4>(gr, a, grid, lds, st); break;
+      case 8: launch_block<8>(gr, a, grid, lds, st); break;
+      default: launch_block<17>(gr, a, grid, lds, st); break;
+    }
   }
   const int ncb = static_cast<int>(cdiv(static_cast<int64_t>(gp.RL) * gp.RL, kGt));
   const int64_t nunits = gp.ptiles * kGt * ncb;
@@ -563,6 +1018,68 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
     case 4: launch_expand<4>(gr, a, nunits, ncb, st); break;
     default: launch_expand<8>(gr, a, nunits, ncb, st); break;
   }
+}
+
+bool grouped_resid_ok(const GroupedPlan& gp) {
+  return gp.on && gp.L <= 3 && gp.dp <= int64_t(kResPer) * kBlock;
+}
+
+void launch_grouped_resid(const Geom& gr, const GroupedPlan& gp, const double* Q64, void* ws,
+                          const double* h, double* out, hipStream_t st) {
+  Carver c(ws);
+  GrpWS w;
+  carve_grouped(c, gp, w);
+  GrpArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rows = w.rows;
+  a.scs = w.scs;
+  a.cnt = w.cnt;
+  a.E = Q64 + gr.qoff[gp.L];
+  a.nb = gp.nb;
+  a.groups = gp.groups;
+  a.dp = gp.dp;
+  a.L = gp.L;
+  a.RL = gp.RL;
+  a.sp = gp.sp;
+  if (h)
+    hipLaunchKernelGGL(grp_hvec_kernel, dim3(static_cast<unsigned>(cdiv(gp.groups * gp.dp, kBlock))),
+                       dim3(kBlock), 0, st, a, h, w.U);
+  const size_t lds = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double) +
+                     static_cast<size_t>(gp.dp) * sizeof(double) +
+                     static_cast<size_t>(gp.dp) * gp.L * sizeof(int);
+  const dim3 grid(static_cast<unsigned>(gp.groups));
+  const double* U = h ? w.U : nullptr;
+  const int R1 = gr.ranks[gp.L - 1];
+  if (R1 <= kRmMax && gp.dp / R1 <= kRmMax) {
+    const size_t lds_m = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double) +
+                         static_cast<size_t>(gp.dp) * sizeof(double);
+    switch (gp.L) {
+      case 1:
+        hipLaunchKernelGGL(grp_resid_mfma_kernel<1>, grid, dim3(kBlock), lds_m, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+      case 2:
+        hipLaunchKernelGGL(grp_resid_mfma_kernel<2>, grid, dim3(kBlock), lds_m, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+      default:
+        hipLaunchKernelGGL(grp_resid_mfma_kernel<3>, grid, dim3(kBlock), lds_m, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+    }
+  } else switch (gp.L) {
+    case 1:
+      hipLaunchKernelGGL(grp_resid_kernel<1>, grid, dim3(kBlock), lds, st, gr, a, w.xs, U, w.V);
+      break;
+    case 2:
+      hipLaunchKernelGGL(grp_resid_kernel<2>, grid, dim3(kBlock), lds, st, gr, a, w.xs, U, w.V);
+      break;
+    default:
+      hipLaunchKernelGGL(grp_resid_kernel<3>, grid, dim3(kBlock), lds, st, gr, a, w.xs, U, w.V);
+      break;
+  }
+  hipLaunchKernelGGL(grp_vec_expand_kernel, dim3(static_cast<unsigned>(cdiv(gp.dp * gp.RL, 16))),
+                     dim3(kBlock), 0, st, a, w.V, out);
 }
 
 }  // namespace tk

@@ -180,9 +180,15 @@ size_t grouped_bytes(const GroupedPlan& gp);
 // M (d x d, lower triangle) = sum_t weff_t q_t q_t^T + lambda (x)_n P_n from the
 // samples' indices idx ([order][s]) and the row tables Q64 (at gr.qoff);
 // ws: grouped_bytes(gp) bytes.
+// xw: per-sample w_t x_t, kept (sorted) for launch_grouped_resid.
 void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* idx,
-                         const double* Q64, const double* weff, const double* P, double lambda,
-                         void* ws, double* M, hipStream_t st);
+                         const double* Q64, const double* weff, const double* xw, const double* P,
+                         double lambda, void* ws, double* M, hipStream_t st);
+// After launch_grouped_gram on the same ws: out = sum_t q_t (xw_t - weff_t q_t.h), or
+// the right side sum_t xw_t q_t when h is null (FP64, grouped by i_L the same way).
+bool grouped_resid_ok(const GroupedPlan& gp);
+void launch_grouped_resid(const Geom& gr, const GroupedPlan& gp, const double* Q64, void* ws,
+                          const double* h, double* out, hipStream_t st);
 
 struct GramPlan {
   tk_dtype prec;
