@@ -62,6 +62,7 @@ CASES = [
     ((40, 36, 30, 20), (16, 16, 8, 1), 0.3),  # d = 2048, L = 2, masked
     ((70, 64), (64, 8), None),              # order 2, d = 512, d' = 64
     ((30, 28, 26), (12, 12, 12), None),     # d = 1728, d' = 144: ragged tiles
+    ((8, 6, 6, 5, 6), (4, 3, 3, 2, 4), None),  # order 5: four modes before L, d' = 72
 ]
 
 

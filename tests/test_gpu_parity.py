@@ -102,9 +102,16 @@ def _sketch_case(dims, ranks, seed, dtype="f64", missing=None, factor="gaussian"
 
 
 # FP64 shapes with d >= 256 take the Gram grouped by the last mode of rank >= 2
+# The right side and residual are grouped the same way (up to three modes
+# before L): on MFMA when prod_{n<L-1} R_n <= 64 and R_{L-1} <= 64, else on the
+# vector units; with four or more modes before L they stay per sample.
 GROUPED_SHAPES = [
     ((40, 36, 30), (8, 8, 8)),          # d = 512, 30 groups
     ((30, 28, 26, 9), (8, 6, 6, 1)),    # d = 288, trailing rank-1 mode, d' = 48
+    ((40, 16, 8), (24, 12, 1)),         # L = 1: one mode before L, d' = 24
+    ((12, 10, 10, 10), (4, 4, 4, 4)),   # three modes before L, d' = 64
+    ((12, 10, 4, 5), (9, 8, 2, 4)),     # R_0 R_1 = 72 > 64: vector-unit residual
+    ((8, 6, 6, 5, 6), (4, 3, 3, 2, 4)),  # four modes before L: per-sample vectors
 ]
 
 
