@@ -20,7 +20,7 @@
 //   h_{i+1} = h_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i w_i,
 // the same iterates as the textbook form in exact arithmetic.
 //
-// One persistent launch runs every iteration, two grid-wide barriers each:
+// One persistent launch runs every iteration in two phases:
 //   S  each workgroup forms r_{i+1} on the entries its tiles need (from r_i,
 //      s_i, w_{i-1} and the scalars, the same arithmetic as the entries'
 //      owners) and multiplies its lower 64 x 64 tiles M_IJ by it: the row part
@@ -29,11 +29,20 @@
 //      also update h, p, w, r there.  The next tiles' M entries and vector
 //      values load while the current tile is used (two tiles ahead);
 //   R  each workgroup sums the partials of its own entries of s_{i+1} in a
-//      fixed order, and its shares of gamma and delta.
-// Every sum has a fixed order and every workgroup sums the shares alike, so
-// the result does not depend on timing.  Data that other workgroups read is
-// written through to memory and read with agent-scope loads, since the L2 of
-// one XCD does not see another's writes.
+//      fixed order, and publishes its shares of gamma and delta; every
+//      workgroup then adds all shares in the same order.
+// No grid-wide barrier separates the phases: a partial or a share starts as
+// an empty pattern (a signalling NaN that no arithmetic produces) and its
+// reader polls until the value replaces it.  The reader of a partial clears
+// it again after reading; shares rotate over three rounds, a workgroup
+// clearing its slot of round j - 1 once it has every share of round j.  A
+// workgroup publishes its shares only after its other stores of the phase
+// have completed, so a complete set of shares also means that every vector
+// entry of the phase is in memory (the argument is spelled out at
+// share_wait).  Every sum has a fixed order and every workgroup sums the
+// shares alike, so the result does not depend on timing.  Data that other
+// workgroups read is written through to memory and read with agent-scope
+// loads, since the L2 of one XCD does not see another's writes.
 #include <string.h>
 
 #include "tk_internal.h"
@@ -67,7 +76,7 @@ struct CgArgs {
   double* wbuf;      // w_i = M p_i, two halves
   double* rowpart;   // [tile][64], plus a spare slot
   double* colpart;   // [tile][64], plus a spare slot
-  double* shares;    // [2][grid]: gamma and delta shares
+  double* shares;    // [3 rounds][gamma, delta][grid] shares
   int32_t* sync;     // [0] arrivals, [16] abort word
   int32_t* cg_done;  // out: 1 when converged
   int32_t* steps;    // out: iterations taken
@@ -91,6 +100,15 @@ __device__ inline void cg_complete_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// The empty pattern of a partial or share that has not been written yet.
+constexpr unsigned long long kCgEmpty = 0x7FF4C0DE5EED0001ULL;
+__device__ inline bool cg_empty(double v) {
+  return static_cast<unsigned long long>(__double_as_longlong(v)) == kCgEmpty;
+}
+__device__ inline void cg_clear(double* p) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), kCgEmpty, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline int64_t tri(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
 __device__ inline void tile_of(int64_t t, int64_t& i, int64_t& j) {
@@ -129,19 +147,24 @@ __device__ inline double row16_sum(double x) {
   return x;
 }
 
-// Sum of one value per thread over the workgroup in a fixed tree order.
-__device__ inline double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
+// Sums of two values per thread over the workgroup, in a fixed order: lane 0
+// of each wave sums its wave by a butterfly, then the four wave sums are
+// added in wave order (red: 8 doubles).
+__device__ inline void block_sum2(double& x, double& y, double* red) {
 #pragma unroll
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    x += __shfl_xor(x, o, 64);
+    y += __shfl_xor(y, o, 64);
   }
-  const double s = red[0];
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = x;
+    red[4 + (tid >> 6)] = y;
+  }
   __syncthreads();
-  return s;
+  x = ((red[0] + red[1]) + red[2]) + red[3];
+  y = ((red[4] + red[5]) + red[6]) + red[7];
+  __syncthreads();
 }
 
 // One tile's operands in registers: this thread's 16 entries of M_IJ and, for
@@ -172,6 +195,7 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
   __shared__ double csum[4][kCt];
   __shared__ double own_h[kCgMaxOwn], own_p[kCgMaxOwn], own_r[kCgMaxOwn], own_s[kCgMaxOwn];
   __shared__ int ok_s;
+  __shared__ int fail_s;
   const int tid = threadIdx.x;
   const int G = gridDim.x, wg = blockIdx.x;
   const int64_t d = a.d, nb = a.nb;
@@ -181,8 +205,9 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
   const int64_t t0 = wg * a.ntiles / G, t1 = (wg + 1) * a.ntiles / G;
   const int srow = tid >> 2, scol = (tid & 3) * 16;  // tile roles: row, 16 columns
   const int nloc = static_cast<int>(t1 - t0);
-  double* sh_g = a.shares;
-  double* sh_d = a.shares + G;
+  // shares of round rd: gamma at shg(rd)[wg], delta at shd(rd)[wg]
+  auto shg = [&](int rd) { return a.shares + static_cast<int64_t>(2 * rd) * G; };
+  auto shd = [&](int rd) { return a.shares + static_cast<int64_t>(2 * rd + 1) * G; };
   int32_t* arrivals = a.sync;
   int32_t* abort = a.sync + 16;
   int gen = 0;
@@ -215,17 +240,63 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     __syncthreads();
     failed = failed || !ok_s;
   };
-  // sums of the grid's gamma and delta shares, the same fixed order in every
-  // workgroup (both loads in flight together)
-  auto grid_sums = [&](double& sg, double& sd) __attribute__((always_inline)) {
+  // one poll step of a wait: false once the launch is to stop (the abort word
+  // is read every 64 polls; past the spin limit this workgroup raises it)
+  auto poll_on = [&](long& spins) __attribute__((always_inline)) {
+    ++spins;
+    if ((spins & 63) == 0 &&
+        __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      return false;
+    if (spins > kCgSpinLimit) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
+  };
+  // Sums of every workgroup's gamma and delta shares of round rd, the same
+  // fixed order in every workgroup.  Why a complete set orders the phases:
+  // a workgroup publishes its shares of round j only after all its stores of
+  // the phases before have completed (r_{i+1}, w_i, s_{i+1}, the partials it
+  // wrote and the ones it cleared), so once every share of round j is seen,
+  // every vector entry the next S phase reads is in memory; and every other
+  // workgroup has read all shares of round j - 1 (it read them before it
+  // computed the shares of round j), so this workgroup's slot of round j - 1
+  // can be cleared now for round j + 2.  That clear completes before this
+  // workgroup publishes round j + 1, which every reader of round j + 2 has
+  // seen first, so no reader finds a stale share.  The same holds for a
+  // cleared partial: its tile's workgroup writes it again only after seeing
+  // the shares that its reader published after clearing it.
+  auto share_wait = [&](int rd, bool clear_prev, double& sg, double& sd)
+      __attribute__((always_inline)) {
     double vg = 0.0, vd = 0.0;
+    bool bad = false;
     for (int i = tid; i < G; i += kBlock) {
-      const double x = cload(sh_g + i), y = cload(sh_d + i);
+      const double* pg = shg(rd) + i;
+      const double* pd = shd(rd) + i;
+      double x = cload(pg), y = cload(pd);
+      long spins = 0;
+      while (!bad && (cg_empty(x) || cg_empty(y))) {
+        if (!poll_on(spins)) {
+          bad = true;
+          break;
+        }
+        if (cg_empty(x)) x = cload(pg);
+        if (cg_empty(y)) y = cload(pd);
+      }
       vg += x;
       vd += y;
     }
-    sg = block_sum(vg, red);
-    sd = block_sum(vd, red);
+    if (bad) fail_s = 1;
+    block_sum2(vg, vd, red);
+    failed = failed || fail_s != 0;
+    if (clear_prev && tid == 0) {
+      const int pr = (rd + 2) % 3;
+      cg_clear(shg(pr) + wg);
+      cg_clear(shd(pr) + wg);
+    }
+    sg = vg;
+    sd = vd;
   };
 
   // vector sources of the S phase: r_{i+1} = r - alpha (s + beta w).  At the
@@ -369,6 +440,19 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     }
   };
   auto phase_s_res = [&](double* rnext, double* wcur) __attribute__((always_inline)) {
+    // the vector blocks' loads first, so that they and the owned entries'
+    // loads below are in flight together (one round trip)
+    const int nv = nslot_s * kCt;
+    double lr[kVbPer], ls[kVbPer], lw[kVbPer];
+#pragma unroll
+    for (int q = 0; q < kVbPer; ++q) {
+      const int e = tid + kBlock * q;
+      const int ee = e < nv ? e : 0;
+      const int64_t x = blk_of[ee / kCt] * kCt + (ee % kCt);
+      lr[q] = cload(rsrc + x);
+      ls[q] = cload(ssrc + x);
+      lw[q] = cload(wsrc + x);
+    }
     for (int64_t i = tid; i < ne; i += kBlock) {
       const int64_t x = e0 + i;
       if (!setup) {
@@ -388,18 +472,6 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
         cstore(wcur + x, 0.0);
         cstore(rnext + x, rv);
       }
-    }
-    // the vector blocks: every load in flight before any value is formed
-    const int nv = nslot_s * kCt;
-    double lr[kVbPer], ls[kVbPer], lw[kVbPer];
-#pragma unroll
-    for (int q = 0; q < kVbPer; ++q) {
-      const int e = tid + kBlock * q;
-      const int ee = e < nv ? e : 0;
-      const int64_t x = blk_of[ee / kCt] * kCt + (ee % kCt);
-      lr[q] = cload(rsrc + x);
-      ls[q] = cload(ssrc + x);
-      lw[q] = cload(wsrc + x);
     }
     if (setup) {  // the tiles, once
 #pragma unroll
@@ -464,17 +536,15 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kMaxRes; ++k) {
-      if (k < nloc) {
-        const int64_t tau = t0 + k;
-        if (cb < 4) cstore(a.rowpart + tau * kCt + 4 * rb + cb, rsv[k]);
-        if (tid < kCt) {
-          double c = 0.0;
+    for (int k = 0; k < kMaxRes; ++k)
+      if (k < nloc && cb < 4) cstore(a.rowpart + (t0 + k) * kCt + 4 * rb + cb, rsv[k]);
+    // column parts: wave w sums the 16 row groups of tiles w, w + 4, ...
+    for (int k = tid >> 6; k < nloc; k += 4) {
+      const int c = tid & (kCt - 1);
+      double cs = 0.0;
 #pragma unroll
-          for (int g = 0; g < 16; ++g) c += csum_all[k][g][tid];
-          cstore(a.colpart + tau * kCt + tid, c);
-        }
-      }
+      for (int g = 0; g < 16; ++g) cs += csum_all[k][g][c];
+      cstore(a.colpart + (t0 + k) * kCt + c, cs);
     }
   };
   // S phase: the owners' updates, then the tile products
@@ -517,8 +587,15 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
   };
   // R phase: own entries of s = M r (sums of the partials in a fixed order);
   // 16 threads per entry, thread z summing terms z, z + 16, ... of
-  // [rowpart(I, 0..I), colpart(I..nb-1, I)], then the 16 in a fixed tree
-  auto phase_r = [&](double* snext) __attribute__((always_inline)) {
+  // [rowpart(I, 0..I), colpart(I..nb-1, I)], then the 16 in a fixed tree.
+  // Each term is polled until its tile's workgroup has written it and is
+  // cleared after reading.  Ends with this workgroup's shares published in
+  // round rd.
+  auto term = [&](int64_t I, int64_t o, int64_t u) __attribute__((always_inline)) {
+    return u <= I ? a.rowpart + tri(I, u) * kCt + o : a.colpart + tri(u - 1, I) * kCt + o;
+  };
+  auto phase_r = [&](double* snext, int rd) __attribute__((always_inline)) {
+    bool bad = false;
     for (int64_t base = 0; base < ne; base += kBlock / 16) {
       const int64_t i = base + (tid >> 4);
       const int z = tid & 15;
@@ -531,9 +608,28 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
 #pragma unroll
         for (int q = 0; q < kCgTerms; ++q) {
           const int64_t u = z + 16 * q;
-          const double* src = u <= I ? a.rowpart + tri(I, u) * kCt + o
-                                     : a.colpart + tri(I + (u - I - 1), I) * kCt + o;
-          t[q] = u < nt ? cload(src) : 0.0;
+          t[q] = u < nt ? cload(term(I, o, u)) : 0.0;
+        }
+        long spins = 0;
+        for (;;) {
+          bool pend = false;
+#pragma unroll
+          for (int q = 0; q < kCgTerms; ++q) pend = pend || cg_empty(t[q]);
+          if (!pend || bad) break;
+          if (!poll_on(spins)) {
+            bad = true;
+            break;
+          }
+#pragma unroll
+          for (int q = 0; q < kCgTerms; ++q) {
+            const int64_t u = z + 16 * q;
+            if (u < nt && cg_empty(t[q])) t[q] = cload(term(I, o, u));
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kCgTerms; ++q) {
+          const int64_t u = z + 16 * q;
+          if (u < nt) cg_clear(term(I, o, u));
         }
 #pragma unroll
         for (int q = 0; q < kCgTerms; ++q) sum += t[q];
@@ -547,27 +643,39 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
         cstore(snext + e0 + i, sum);
       }
     }
+    if (bad) fail_s = 1;
     __syncthreads();
     double pg = 0.0, pd = 0.0;
     for (int64_t i = tid; i < ne; i += kBlock) {
       pg = fma(own_r[i], own_r[i], pg);
       pd = fma(own_r[i], own_s[i], pd);
     }
-    const double sg = block_sum(pg, red);
-    const double sd = block_sum(pd, red);
-    if (tid == 0) {
-      cstore(sh_g + wg, sg);
-      cstore(sh_d + wg, sd);
+    block_sum2(pg, pd, red);
+    cg_complete_stores();
+    __syncthreads();
+    if (tid == 0 && fail_s == 0) {
+      cstore(shg(rd) + wg, pg);
+      cstore(shd(rd) + wg, pd);
     }
   };
 
-  // ---- start: s_0 = M b, gamma_0, delta_0
+  // ---- start: the partials this workgroup reads and its share slots of
+  // every round empty, then the launch's one grid-wide barrier
+  if (tid == 0) fail_s = 0;
+  for (int64_t x = tid; x < ne * (nb + 1); x += kBlock) {
+    const int64_t gi = e0 + x / (nb + 1), u = x % (nb + 1);
+    cg_clear(term(gi / kCt, gi % kCt, u));
+  }
+  if (tid < 3) {
+    cg_clear(shg(tid) + wg);
+    cg_clear(shd(tid) + wg);
+  }
+  barrier();
+  // ---- s_0 = M b, gamma_0, delta_0 (shares of round 0)
   phase_s(a.rbuf, a.wbuf + d);  // r_0 -> rbuf[0], w_{-1} = 0 -> wbuf[1]
-  barrier();
-  phase_r(a.sbuf);
-  barrier();
+  phase_r(a.sbuf, 0);
   double g0, del;
-  grid_sums(g0, del);
+  share_wait(0, false, g0, del);
   double gam = g0;
   alpha = del > 0.0 ? gam / del : 0.0;
   beta = 0.0;
@@ -580,12 +688,11 @@ __global__ __launch_bounds__(kBlock, 1) void cg_kernel(CgArgs a) {
     rsrc = a.rbuf + c * d;
     ssrc = a.sbuf + c * d;
     wsrc = a.wbuf + (c ^ 1) * d;
+    const int rd = (it + 1) % 3;
     phase_s(a.rbuf + (c ^ 1) * d, a.wbuf + c * d);
-    barrier();
-    phase_r(a.sbuf + (c ^ 1) * d);
-    barrier();
+    phase_r(a.sbuf + (c ^ 1) * d, rd);
     double gn, dn;
-    grid_sums(gn, dn);
+    share_wait(rd, true, gn, dn);
     ++it;
     const double gprev = gam;
     gam = gn;
@@ -630,7 +737,7 @@ void carve_cg(Carver& c, int64_t d, CgWS& w) {
   w.wbuf = c.take<double>(2 * d);
   w.rowpart = c.take<double>((nt + 1) * kCt);  // one spare tile slot
   w.colpart = c.take<double>((nt + 1) * kCt);
-  w.shares = c.take<double>(2 * 1024);
+  w.shares = c.take<double>(3 * 2 * 1024);
   w.sync = c.take<int32_t>(kCgSyncWords);
   w.done = c.take<int32_t>(1);
 }
