@@ -335,7 +335,8 @@ def main():
                       "unit": "TFLOP/s", "frac": round(sach / PEAKS_TFLOPS["f64"], 4),
                       "traffic": None,
                       "kernel": f"cg_kernel (persistent conjugate gradients, {cg_iters} "
-                                "iterations, two grid barriers each; time of the solve stage)",
+                                "iterations, partials and shares polled between workgroups; "
+                                "time of the solve stage)",
                       "algorithmic_flops": sflops, "kernel_ms": round(solve_ms, 4)}
     if solve_roof is not None and stage_ms["solve"] > gram_ms:
         roofline, other = solve_roof, gram_roof

@@ -23,6 +23,8 @@
 //     its epilogue.
 #include <string.h>
 
+#include <type_traits>
+
 #include "tk_mfma.h"
 
 namespace tk {
@@ -314,14 +316,28 @@ __global__ __launch_bounds__(kBlock) void grp_block_kernel(Geom g, GrpArgs a) {
 // Sample-split form for at most three modes before L (NL): workgroup (group
 // k, lower 64 x 64 tile (ta, tb) of d' x d'); every wave computes the whole
 // tile as 4 x 4 blocks of v_mfma_f64_16x16x4 over its own quarter of each
-// 32-sample chunk (samples 8 w .. 8 w + 7), so each formed operand feeds four
-// products and no wave idles on a diagonal tile (its blocks above the
-// diagonal are skipped).  The four partial tiles are added in wave order
-// through LDS at the end.
-template <int NR, int NL>
+// CK-sample chunk (samples w CK / 4 .. (w + 1) CK / 4 - 1, k-steps past the
+// group's end skipped), so each formed operand feeds four products and no
+// wave idles on a diagonal tile (its blocks above the diagonal are skipped).
+// FP64 MFMA and ordinary vector instructions do not overlap on one SIMD, so
+// the operand formation is kept to its multiplies: the chunk sits in LDS
+// transposed, entry j of sample u at j CKP + u, which makes every operand
+// address of a k-step a per-lane base fixed for the launch plus a constant;
+// row S' is all zeros and serves the rows p >= d' of a ragged tile.  The four
+// partial tiles are added in wave order through LDS at the end.
+constexpr int kRld = kGt + 8;  // reduction tile row stride (two rows per bank sweep)
+int split_ck(int sp) { return sp <= 32 ? 64 : 32; }
+// p / R and p % R for p < 2^20, R <= 64: (p + 1/2) / R stays at least 1/(2R)
+// from an integer, far more than the rounding of the float product
+__device__ inline void small_divmod(int p, int R, float rinv, int& q, int& r) {
+  q = static_cast<int>((static_cast<float>(p) + 0.5f) * rinv);
+  r = p - q * R;
+}
+template <int NR, int NL, int CK>
 __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpArgs a) {
-  extern __shared__ double rowbuf[];  // [kGkc][S' + 1], then the 64 x 64 reduction tile
-  __shared__ double ssc[kGkc];
+  constexpr int CKP = CK + 2;       // transposed chunk stride
+  extern __shared__ double rowT[];  // [S' + 1][CKP], then the 64 x kRld reduction tile
+  __shared__ double ssc[CK];
   const int64_t tau = blockIdx.x % a.ptiles;
   const int64_t k = blockIdx.x / a.ptiles;
   int64_t ta, tb;
@@ -329,45 +345,52 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
   const bool diag = ta == tb;
   const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int SP = a.sp, LD = a.sp + 1;
-  double* red = rowbuf + kGkc * LD;
-  // LDS offsets (within a sample's row) of the digits of this lane's operand rows
-  int oa[4][NL], ob[4][NL];
-  bool va[4], vb[4];
+  const int SP = a.sp;
+  double* red = rowT + (SP + 1) * CKP;
+  // this lane's sample within a k-step and its first k-step's sample
+  const int u0 = w * (CK / 4) + (lane >> 4);
+  // LDS indices (at sample u0) of the digits of this lane's operand rows
+  int ia[4][NL], ib[4][NL];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t pa = ta * kGt + i * 16 + (lane & 15), pb = tb * kGt + i * 16 + (lane & 15);
-    va[i] = pa < a.dp;
-    vb[i] = pb < a.dp;
-    int64_t xa = va[i] ? pa : 0, xb = vb[i] ? pb : 0;
+    const int pa = static_cast<int>(ta) * kGt + i * 16 + (lane & 15);
+    const int pb = static_cast<int>(tb) * kGt + i * 16 + (lane & 15);
+    const bool va = pa < a.dp, vb = pb < a.dp;
+    int xa = va ? pa : 0, xb = vb ? pb : 0;
 #pragma unroll
     for (int n = NL - 1; n >= 0; --n) {
       const int R = g.ranks[n];
-      oa[i][n] = g.soff[n] + static_cast<int>(xa % R);
-      ob[i][n] = g.soff[n] + static_cast<int>(xb % R);
-      xa /= R;
-      xb /= R;
+      const float rinv = 1.0f / static_cast<float>(R);
+      int qa, ra, qb, rb;
+      small_divmod(xa, R, rinv, qa, ra);
+      small_divmod(xb, R, rinv, qb, rb);
+      // the zero row for p >= d' (in the first mode: the product is then 0)
+      ia[i][n] = ((n == 0 && !va) ? SP : g.soff[n] + ra) * CKP + u0;
+      ib[i][n] = ((n == 0 && !vb) ? SP : g.soff[n] + rb) * CKP + u0;
+      xa = qa;
+      xb = qb;
     }
   }
-  // staging: element e = tid + 256 i of a chunk -> LDS (e / S') LD + e % S'
-  const int nel = kGkc * SP;
+  // staging: element e = tid + 256 i of a chunk (sample e / S', entry e % S')
+  const int nel = CK * SP;
   int lofs[NR];
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
     const int e = tid + kBlock * i;
-    lofs[i] = e < nel ? (e / SP) * LD + e % SP : -1;
+    lofs[i] = e < nel ? (e % SP) * CKP + e / SP : -1;
   }
+  for (int u = tid; u < CK; u += kBlock) rowT[SP * CKP + u] = 0.0;
   double pf[NR];
   double psc = 0.0;
   auto fetch = [&](int64_t c0) {
-    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * SP;
+    const int64_t lim = ((g1 < c0 + CK ? g1 : c0 + CK) - c0) * SP;
     const double* src = a.rows + c0 * SP;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int e = tid + kBlock * i;
       pf[i] = e < lim ? src[e] : 0.0;
     }
-    if (tid < kGkc) psc = c0 + tid < g1 ? a.scs[c0 + tid] : 0.0;
+    if (tid < CK) psc = c0 + tid < g1 ? a.scs[c0 + tid] : 0.0;
   };
   doublex4 acc[4][4];
 #pragma unroll
@@ -375,36 +398,36 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
   if (g0 < g1) fetch(g0);
-  for (int64_t c0 = g0; c0 < g1; c0 += kGkc) {
+  for (int64_t c0 = g0; c0 < g1; c0 += CK) {
 #pragma unroll
     for (int i = 0; i < NR; ++i)
-      if (lofs[i] >= 0) rowbuf[lofs[i]] = pf[i];
-    if (tid < kGkc) ssc[tid] = psc;
+      if (lofs[i] >= 0) rowT[lofs[i]] = pf[i];
+    if (tid < CK) ssc[tid] = psc;
     __syncthreads();
-    if (c0 + kGkc < g1) fetch(c0 + kGkc);
-#pragma unroll 1
-    for (int h = 0; h < 2; ++h) {
-      const int kk = (2 * w + h) * 4 + (lane >> 4);
-      const double* rk = rowbuf + kk * LD;
-      const double sw = ssc[kk];
-      double av[4], bv[4];
+    if (c0 + CK < g1) fetch(c0 + CK);
+    const int64_t left = g1 - c0 - w * (CK / 4);  // samples of this wave's quarter
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double x = sw, y = 1.0;
+    for (int h = 0; h < CK / 16; ++h) {
+      if (4 * h < left) {
+        double av[4], bv[4];
 #pragma unroll
-        for (int n = 0; n < NL; ++n) {
-          x *= rk[oa[i][n]];
-          y *= rk[ob[i][n]];
+        for (int i = 0; i < 4; ++i) {
+          double x = ssc[u0 + 4 * h], y = 1.0;
+#pragma unroll
+          for (int n = 0; n < NL; ++n) {
+            x *= rowT[ia[i][n] + 4 * h];
+            y *= rowT[ib[i][n] + 4 * h];
+          }
+          av[i] = x;
+          bv[i] = y;
         }
-        av[i] = va[i] ? x : 0.0;
-        bv[i] = vb[i] ? y : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (!diag || i >= j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (!diag || i >= j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -418,14 +441,14 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
         for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int e = (i * 16 + (lane >> 4) + 4 * v) * kGt + j * 16 + (lane & 15);
+            const int e = (i * 16 + (lane >> 4) + 4 * v) * kRld + j * 16 + (lane & 15);
             red[e] = src == 3 ? acc[i][j][v] : red[e] + acc[i][j][v];
           }
     }
     __syncthreads();
   }
   double* out = a.B + (k * a.ptiles + tau) * (kGt * kGt);
-  for (int e = tid; e < kGt * kGt; e += kBlock) out[e] = red[e];
+  for (int e = tid; e < kGt * kGt; e += kBlock) out[e] = red[(e / kGt) * kRld + e % kGt];
 }
 
 // x from another lane of the same 16-lane row (DPP control CTRL); the sum over
@@ -733,16 +756,22 @@ __global__ __launch_bounds__(kBlock) void grp_vec_expand_kernel(GrpArgs a,
 // Workgroup (row a of lower tile tau, block cb of 64 columns c = m R_L + m'):
 // out[b][c] = sum_k B_k[tau][a][b] e_k[m] e_k[m'] for b in [0, 64), the pairs
 // (p, p') = (64 ta + a, 64 tb + b).  Wave w takes quadrant (w / 2, w % 2) of
-// the 64 x 64 output.  Per chunk of 32 groups the B_k entries and the rows e_k
-// go to LDS from registers loaded during the previous chunk's products; each
-// lane forms its e_k[m] e_k[m'] operands from LDS.  Workgroup ids are spread
-// so that the column blocks of one row, which read the same B_k entries, run
-// on one XCD (ids go round-robin over the 8 XCDs).  NE >= R_L / 8.
+// the 64 x 64 output on v_mfma_f64_4x4x4_4b (lane layout as in pass 2): per
+// k-step of 4 groups, 8 row operands (rows b = 4 r .. 4 r + 3 of the
+// quadrant, the same in all four blocks: B_k entries read straight from LDS)
+// and 2 column operands (block q: columns 16 cc + 4 q .. + 3, the products
+// e_k[m] e_k[m'] formed from LDS) feed 16 instructions; on a diagonal tile the
+// rows above a are skipped.  Per chunk of 32 groups the B_k entries and the
+// rows e_k (transposed, with a zero row for the padded columns) go to LDS from
+// registers loaded during the previous chunk's products.  Workgroup ids are
+// spread so that the column blocks of one row, which read the same B_k
+// entries, run on one XCD (ids go round-robin over the 8 XCDs).  NE >= R_L / 8.
 template <int NE>
 __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, int64_t nunits,
                                                             int ncb) {
+  constexpr int kEld = kGkc + 2;  // transposed e_k stride
   __shared__ double as[kGkc][kGld];
-  __shared__ double es[kGkc * kMaxRank];
+  __shared__ double esT[(kMaxRank + 1) * kEld];
   const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
   const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (unit >= nunits) return;
@@ -755,26 +784,46 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
   const int64_t p = ta * kGt + arow;
   if (p >= a.dp) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = (lane >> 2) & 3, l4 = lane & 3, lk = lane >> 4;
   const int RL = a.RL;
   const int rr = RL * RL;
   const int qa = w >> 1, qc = w & 1;
+  const bool diag = ta == tb;
   // quadrant rows b >= 32 qa; on a diagonal tile only b <= arow is stored
-  const bool active = !(ta == tb && qa * 32 > arow) && cb * 64 + qc * 32 < rr;
-  // this lane's two operand columns c -> (m, m')
-  int fm[2], fmp[2];
-  bool fv[2];
+  const bool active = !(diag && qa * 32 > arow) && cb * 64 + qc * 32 < rr;
+  const int blim = diag ? arow : kGt - 1;  // last row b needed
+  // LDS indices (at k-step 0) of this lane's row and column operands
+  int ia[8];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int c = cb * 64 + qc * 32 + j * 16 + (lane & 15);
-    fv[j] = c < rr;
-    fm[j] = fv[j] ? c / RL : 0;
-    fmp[j] = fv[j] ? c % RL : 0;
+  for (int r = 0; r < 8; ++r) ia[r] = lk * kGld + qa * 32 + 4 * r + l4;
+  int im[2], imp[2];
+  const float rlinv = 1.0f / static_cast<float>(RL);
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) {
+    const int c = cb * 64 + qc * 32 + cc * 16 + 4 * q + l4;
+    int m, mp;
+    small_divmod(c, RL, rlinv, m, mp);
+    if (c >= rr) {  // the zero row
+      m = RL;
+      mp = 0;
+    }
+    im[cc] = m * kEld + lk;
+    imp[cc] = mp * kEld + lk;
   }
+  for (int u = tid; u < kGkc; u += kBlock) esT[RL * kEld + u] = 0.0;
   // staging roles: B entries (group tid / 8, entries 8 (tid % 8) .. + 8) and
   // row elements tid + 256 i of the chunk's 32 R_L contiguous e_k entries
   const int skk = tid >> 3, se = (tid & 7) * 8;
   const double* Bsrc = a.B + tau * (kGt * kGt) + static_cast<int64_t>(arow) * kGt + se;
   const int64_t bstride = a.ptiles * (kGt * kGt);
+  int eofs[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = tid + kBlock * i;
+    int kk, m;
+    small_divmod(e, RL, rlinv, kk, m);
+    eofs[i] = e < kGkc * RL ? m * kEld + kk : -1;
+  }
   double pa[8], pe[NE];
   auto fetch = [&](int64_t k0) {
     const bool kv = k0 + skk < a.groups;
@@ -788,71 +837,78 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
       pe[i] = e < lim ? a.E[k0 * RL + e] : 0.0;
     }
   };
-  doublex4 acc[2][2];
+  double acc[8][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < 8; ++r) acc[r][0] = acc[r][1] = 0.0;
   fetch(0);
   for (int64_t k0 = 0; k0 < a.groups; k0 += kGkc) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) as[skk][se + e] = pa[e];
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = tid + kBlock * i;
-      if (e < kGkc * RL) es[e] = pe[i];
-    }
+    for (int i = 0; i < NE; ++i)
+      if (eofs[i] >= 0) esT[eofs[i]] = pe[i];
     __syncthreads();
     if (k0 + kGkc < a.groups) fetch(k0 + kGkc);
-    if (active) {
-#pragma unroll 2
+    // PART: some rows of the quadrant lie above a diagonal tile's row a
+    auto ksteps = [&](auto part) __attribute__((always_inline)) {
+      constexpr bool PART = decltype(part)::value;
+#pragma unroll
       for (int ks = 0; ks < kGkc / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        const double a0 = as[kk][qa * 32 + (lane & 15)];
-        const double a1 = as[kk][qa * 32 + 16 + (lane & 15)];
-        const double* ek = es + kk * RL;
-        const double f0 = fv[0] ? ek[fm[0]] * ek[fmp[0]] : 0.0;
-        const double f1 = fv[1] ? ek[fm[1]] * ek[fmp[1]] : 0.0;
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, f0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, f1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, f0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, f1, acc[1][1], 0, 0, 0);
+        const double f0 = esT[im[0] + 4 * ks] * esT[imp[0] + 4 * ks];
+        const double f1 = esT[im[1] + 4 * ks] * esT[imp[1] + 4 * ks];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          if (PART && qa * 32 + 4 * r > blim) continue;
+          const double av = (&as[0][0])[ia[r] + 4 * ks * kGld];
+          acc[r][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, f0, acc[r][0], 0, 0, 0);
+          acc[r][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, f1, acc[r][1], 0, 0, 0);
+        }
       }
+    };
+    if (active) {
+      if (qa * 32 + 28 <= blim)
+        ksteps(std::false_type{});
+      else
+        ksteps(std::true_type{});
     }
     __syncthreads();
   }
   if (!active) return;
   // epilogue: the pair's ridge term lambda prod_{n != L} P_n[digit_n(p)][digit_n(p')]
-  // (modes after L: their 1 x 1 P_n) times P_L[m][m'], then the lower-triangle store
+  // (modes after L: their 1 x 1 P_n) times P_L[m][m'], then the lower-triangle store;
+  // accumulator lane l: row l / 16, column l % 4 of block (l / 4) % 4
   const int64_t d = g.d;
   const double* PL = a.P + g.roff[a.L];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = qa * 32 + i * 16 + (lane >> 4) + 4 * v;
-      const int64_t pp = tb * kGt + b;
-      if (pp >= a.dp || pp > p) continue;
-      double pr = a.lambda;
-      {
-        int64_t x = p, y = pp;
-        for (int n = g.order - 1; n >= 0; --n) {
-          if (n == a.L) continue;
-          const int R = g.ranks[n];
-          pr *= a.P[g.roff[n] + (x % R) * R + (y % R)];
-          x /= R;
-          y /= R;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = cb * 64 + qc * 32 + j * 16 + (lane & 15);
-        if (c >= rr) continue;
-        const int m = c / RL, mp = c % RL;
-        if (pp == p && mp > m) continue;
-        a.M[(p * RL + m) * d + pp * RL + mp] = fma(pr, PL[m * RL + mp], acc[i][j][v]);
+  for (int r = 0; r < 8; ++r) {
+    const int b = qa * 32 + 4 * r + lk;
+    const int64_t pp = tb * kGt + b;
+    if (pp >= a.dp || pp > p) continue;
+    double pr = a.lambda;
+    {
+      int x = static_cast<int>(p), y = static_cast<int>(pp);
+      for (int n = g.order - 1; n >= 0; --n) {
+        if (n == a.L) continue;
+        const int R = g.ranks[n];
+        const float rinv = 1.0f / static_cast<float>(R);
+        int qx, rx, qy, ry;
+        small_divmod(x, R, rinv, qx, rx);
+        small_divmod(y, R, rinv, qy, ry);
+        pr *= a.P[g.roff[n] + rx * R + ry];
+        x = qx;
+        y = qy;
       }
     }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int c = cb * 64 + qc * 32 + cc * 16 + 4 * q + l4;
+      if (c >= rr) continue;
+      int m, mp;
+      small_divmod(c, RL, rlinv, m, mp);
+      if (pp == p && mp > m) continue;
+      a.M[(p * RL + m) * d + pp * RL + mp] = fma(pr, PL[m * RL + mp], acc[r][cc]);
+    }
+  }
 }
 
 // Carved pieces of the grouped Gram's scratch.
@@ -890,21 +946,23 @@ template <int NR>
 void launch_block(const Geom& gr, const GrpArgs& a, unsigned grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(grp_block_kernel<NR>, dim3(grid), dim3(kBlock), lds, st, gr, a);
 }
-template <int NR, int NL>
-void launch_block_split(const Geom& gr, const GrpArgs& a, size_t lds, hipStream_t st) {
+template <int NR, int NL, int CK>
+void launch_block_split(const Geom& gr, const GrpArgs& a, hipStream_t st) {
+  const size_t lds =
+      (static_cast<size_t>(a.sp + 1) * (CK + 2) + static_cast<size_t>(kGt) * kRld) * sizeof(double);
   if (lds > 65536)
-    ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL>),
+    ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL, CK>),
                    static_cast<int>(lds));
-  hipLaunchKernelGGL((grp_block_split_kernel<NR, NL>),
+  hipLaunchKernelGGL((grp_block_split_kernel<NR, NL, CK>),
                      dim3(static_cast<unsigned>(a.groups * a.ptiles)), dim3(kBlock), lds, st, gr,
                      a);
 }
-template <int NR>
-void launch_block_split_nl(const Geom& gr, const GrpArgs& a, size_t lds, hipStream_t st) {
+template <int NR, int CK>
+void launch_block_split_nl(const Geom& gr, const GrpArgs& a, hipStream_t st) {
   switch (a.L) {
-    case 1: launch_block_split<NR, 1>(gr, a, lds, st); break;
-    case 2: launch_block_split<NR, 2>(gr, a, lds, st); break;
-    default: launch_block_split<NR, 3>(gr, a, lds, st); break;
+    case 1: launch_block_split<NR, 1, CK>(gr, a, st); break;
+    case 2: launch_block_split<NR, 2, CK>(gr, a, st); break;
+    default: launch_block_split<NR, 3, CK>(gr, a, st); break;
   }
 }
 template <int NE>
@@ -934,7 +992,7 @@ GroupedPlan plan_grouped(const Geom& gr, int64_t s, tk_dtype prec) {
   gp.ptiles = pt * (pt + 1) / 2;
   gp.sp = gr.soff[L];
   if (gp.ncnt > (int64_t(1) << 24) || gp.groups * gp.ptiles >= (int64_t(1) << 31) ||
-      s * gp.sp >= (int64_t(1) << 31) || gp.sp > 17 * kBlock / kGkc)
+      s * gp.sp >= (int64_t(1) << 31) || gp.sp > 17 * kBlock / kGkc || gp.dp >= (int64_t(1) << 20))
     return gp;
   // multiply-adds of the two forms (tiles padded to 64): grouped only when
   // clearly fewer, and B_k within 4 GiB
@@ -995,12 +1053,17 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
   const unsigned grid = static_cast<unsigned>(gp.groups * gp.ptiles);
   const size_t lds = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double);
   if (gp.L <= 3) {  // every wave the whole tile over a quarter of each chunk
-    const size_t lds2 = lds + static_cast<size_t>(kGt) * kGt * sizeof(double);
-    switch (block_nr(gp.sp)) {
-      case 2: launch_block_split_nl<2>(gr, a, lds2, st); break;
-      case 4: launch_block_split_nl<4>(gr, a, lds2, st); break;
-      case 8: launch_block_split_nl<8>(gr, a, lds2, st); break;
-      default: launch_block_split_nl<17>(gr, a, lds2, st); break;
+    // staging registers: CK S' / 256 doubles per thread
+    if (split_ck(gp.sp) == 64) {
+      if (gp.sp <= 16)
+        launch_block_split_nl<4, 64>(gr, a, st);
+      else
+        launch_block_split_nl<8, 64>(gr, a, st);
+    } else {
+      if (gp.sp <= 64)
+        launch_block_split_nl<8, 32>(gr, a, st);
+      else
+        launch_block_split_nl<17, 32>(gr, a, st);
     }
   } else {
     switch (block_nr(gp.sp)) {
