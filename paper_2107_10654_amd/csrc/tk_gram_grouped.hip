@@ -475,32 +475,35 @@ __device__ inline double row16_sum(double x) {
 //   c_t = xs_t - scs_t (y_t . u_k),  u_k[p] = sum_m h[p R_L + m] e_k[m]
 // (without h: c_t = xs_t, the right side).
 
-// Chunk staging of the vector kernels: the 32 S' doubles of a chunk of sorted
-// rows, four per thread in registers (the rest, for S' > 32, loaded directly),
-// so that the next chunk's loads are in flight while the current one is used.
-struct RowStage {
-  double pf[4];
+// Chunk staging of the vector kernels: the CK S' doubles of a chunk of sorted
+// rows, NP per thread in registers (the rest, for longer rows, loaded
+// directly), so that the next chunk's loads are in flight while the current
+// one is used.
+template <int CK, int NP>
+struct ChunkStage {
+  double pf[NP];
   __device__ void fetch(const double* rows, int64_t c0, int64_t g1, int sp) {
-    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * sp;
+    const int64_t lim = ((g1 < c0 + CK ? g1 : c0 + CK) - c0) * sp;
     const double* src = rows + c0 * sp;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const int e = threadIdx.x + kBlock * i;
       pf[i] = e < lim ? src[e] : 0.0;
     }
   }
   __device__ void store(double* rowbuf, const double* rows, int64_t c0, int64_t g1, int sp) {
-    const int ld = sp + 1, nel = kGkc * sp;
+    const int ld = sp + 1, nel = CK * sp;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NP; ++i) {
       const int e = threadIdx.x + kBlock * i;
       if (e < nel) rowbuf[(e / sp) * ld + e % sp] = pf[i];
     }
-    const int64_t lim = ((g1 < c0 + kGkc ? g1 : c0 + kGkc) - c0) * sp;
-    for (int e = threadIdx.x + 4 * kBlock; e < nel; e += kBlock)
+    const int64_t lim = ((g1 < c0 + CK ? g1 : c0 + CK) - c0) * sp;
+    for (int e = threadIdx.x + NP * kBlock; e < nel; e += kBlock)
       rowbuf[(e / sp) * ld + e % sp] = e < lim ? rows[c0 * sp + e] : 0.0;
   }
 };
+using RowStage = ChunkStage<kGkc, 4>;
 
 // U[k][p] = u_k[p]
 __global__ __launch_bounds__(kBlock) void grp_hvec_kernel(GrpArgs a, const double* __restrict__ h,
@@ -729,6 +732,147 @@ __global__ __launch_bounds__(kBlock) void grp_resid_mfma_kernel(Geom g, GrpArgs 
         if (p0 < nd && p1 < R1) V[k * a.dp + p0 * R1 + p1] = accv[i][v];
       }
     }
+  }
+}
+
+// The same sums with every wave on its own 32 samples of each 128-sample
+// chunk, for V2 of at most four 16 x 16 blocks: each wave takes the Z blocks
+// and the factors c of its samples and accumulates every V2 block over them,
+// so a chunk needs only the barriers around its staging and its factors (the
+// 32-sample form above keeps one or two waves busy per chunk at d'' = R1 =
+// 16).  The four waves' partial blocks are added in wave order through LDS at
+// the end, so every sum keeps a fixed order.
+constexpr int kRwc = 128;  // samples per chunk
+template <int NL>
+__global__ __launch_bounds__(kBlock) void grp_resid_wave_kernel(Geom g, GrpArgs a,
+                                                                const double* __restrict__ xs,
+                                                                const double* __restrict__ U,
+                                                                double* __restrict__ V) {
+  extern __shared__ double smem[];  // rows [kRwc][S' + 1] (then the reduction), u_k [d'' R1]
+  __shared__ double cfac[kRwc];
+  __shared__ double zpart[kRmMax / 16][kRwc];
+  __shared__ int od[kRmMax][NL > 1 ? NL - 1 : 1];  // row offsets of o's digits
+  const int SP = a.sp, LD = a.sp + 1;
+  const int R1 = g.ranks[NL - 1];
+  const int nd = static_cast<int>(a.dp / R1);  // d''
+  const int nc1 = (R1 + 15) / 16, nr0 = (nd + 15) / 16;
+  const int nbv = nr0 * nc1;  // V2 blocks, at most 4
+  const int sb = g.soff[NL - 1];
+  const int rsz = kRwc * LD > nbv * 256 ? kRwc * LD : nbv * 256;
+  double* rowbuf = smem;
+  double* uk = smem + rsz;
+  const int64_t k = blockIdx.x;
+  const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ws0 = w * 32;  // this wave's first sample in a chunk
+  if (U)
+    for (int e = tid; e < nd * R1; e += kBlock) uk[e] = U[k * a.dp + e];
+  for (int p0 = tid; p0 < nd; p0 += kBlock) {
+    int x = p0;
+#pragma unroll
+    for (int n = NL - 2; n >= 0; --n) {
+      const int R = g.ranks[n];
+      od[p0][n] = g.soff[n] + x % R;
+      x /= R;
+    }
+  }
+  // o_j[p0] from the staged rows (1 when no mode precedes L - 1)
+  auto o_of = [&](int j, int p0) {
+    double x = 1.0;
+    const double* rj = rowbuf + j * LD;
+#pragma unroll
+    for (int n = 0; n < NL - 1; ++n) x *= rj[od[p0][n]];
+    return x;
+  };
+  doublex4 accv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) accv[i] = doublex4{0.0, 0.0, 0.0, 0.0};
+  ChunkStage<kRwc, 16> stg;
+  if (g0 < g1) stg.fetch(a.rows, g0, g1, SP);
+  for (int64_t c0 = g0; c0 < g1; c0 += kRwc) {
+    __syncthreads();  // the previous chunk is done (and the tables above are written)
+    stg.store(rowbuf, a.rows, c0, g1, SP);
+    __syncthreads();
+    if (c0 + kRwc < g1) stg.fetch(a.rows, c0 + kRwc, g1, SP);
+    const int64_t nleft = g1 - c0 - ws0;  // samples of this wave in the chunk
+    if (U && nleft > 0) {
+      // Z blocks (16-sample half of this wave, column block): dots of o_j^T U2 with b_j
+      for (int zb = 0; zb < 2 * nc1; ++zb) {
+        const int sh = zb & 1, cbk = zb >> 1;
+        if (sh * 16 >= nleft) continue;
+        doublex4 z = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < (nd + 3) / 4; ++ks) {
+          const int p0 = ks * 4 + (lane >> 4);
+          const int j = ws0 + sh * 16 + (lane & 15);
+          const int p1 = cbk * 16 + (lane & 15);
+          const double av = p0 < nd ? o_of(j, p0) : 0.0;
+          const double bv = (p0 < nd && p1 < R1) ? uk[p0 * R1 + p1] : 0.0;
+          z = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, z, 0, 0, 0);
+        }
+        // accumulator v: sample ws0 + sh 16 + lane / 16 + 4 v, column cbk 16 + lane % 16
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = ws0 + sh * 16 + (lane >> 4) + 4 * v;
+          const int p1 = cbk * 16 + (lane & 15);
+          double t = p1 < R1 ? z[v] * rowbuf[j * LD + sb + p1] : 0.0;
+          t = row16_sum(t);
+          if ((lane & 15) == 0) zpart[cbk][j] = t;
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < 32) {
+      const int j = ws0 + lane;
+      const int64_t u = c0 + j;
+      double dot = 0.0;
+      if (U)
+        for (int c = 0; c < nc1; ++c) dot += zpart[c][j];
+      cfac[j] = u < g1 ? (U ? fma(-a.scs[u], dot, xs[u]) : xs[u]) : 0.0;
+    }
+    __syncthreads();
+    // V2 blocks (row block of o, column block of b) over this wave's 32 samples
+    if (nleft > 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < nbv) {
+          const int rb = i / nc1, cb = i % nc1;
+#pragma unroll 2
+          for (int ks = 0; ks < 8; ++ks) {
+            if (4 * ks >= nleft) break;
+            const int j = ws0 + ks * 4 + (lane >> 4);
+            const int p0 = rb * 16 + (lane & 15);
+            const int p1 = cb * 16 + (lane & 15);
+            const double av = p0 < nd ? cfac[j] * o_of(j, p0) : 0.0;
+            const double bv = p1 < R1 ? rowbuf[j * LD + sb + p1] : 0.0;
+            accv[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accv[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // ((wave 3 + wave 2) + wave 1) + wave 0 through LDS; accumulator v of lane
+  // l: row l / 16 + 4 v, column l % 16 of its block
+  double* red = smem;
+  __syncthreads();
+  for (int src = 3; src >= 0; --src) {
+    if (w == src) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < nbv) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int e = i * 256 + ((lane >> 4) + 4 * v) * 16 + (lane & 15);
+            red[e] = src == 3 ? accv[i][v] : red[e] + accv[i][v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nbv * 256; e += kBlock) {
+    const int i = e >> 8, rem = e & 255;
+    const int p0 = (i / nc1) * 16 + (rem >> 4), p1 = (i % nc1) * 16 + (rem & 15);
+    if (p0 < nd && p1 < R1) V[k * a.dp + p0 * R1 + p1] = red[e];
   }
 }
 
@@ -1113,7 +1257,34 @@ void launch_grouped_resid(const Geom& gr, const GroupedPlan& gp, const double* Q
   const dim3 grid(static_cast<unsigned>(gp.groups));
   const double* U = h ? w.U : nullptr;
   const int R1 = gr.ranks[gp.L - 1];
-  if (R1 <= kRmMax && gp.dp / R1 <= kRmMax) {
+  const int nd = static_cast<int>(gp.dp / R1);
+  if (R1 <= kRmMax && nd <= kRmMax && ((nd + 15) / 16) * ((R1 + 15) / 16) <= 4) {
+    const size_t rsz = static_cast<size_t>(kRwc) * (gp.sp + 1) > static_cast<size_t>(
+                                                                      ((nd + 15) / 16) * ((R1 + 15) / 16) * 256)
+                           ? static_cast<size_t>(kRwc) * (gp.sp + 1)
+                           : static_cast<size_t>(((nd + 15) / 16) * ((R1 + 15) / 16) * 256);
+    const size_t lds_w = (rsz + static_cast<size_t>(gp.dp)) * sizeof(double);
+    switch (gp.L) {
+      case 1:
+        if (lds_w > 65536)
+          ensure_dyn_lds(reinterpret_cast<const void*>(grp_resid_wave_kernel<1>), static_cast<int>(lds_w));
+        hipLaunchKernelGGL(grp_resid_wave_kernel<1>, grid, dim3(kBlock), lds_w, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+      case 2:
+        if (lds_w > 65536)
+          ensure_dyn_lds(reinterpret_cast<const void*>(grp_resid_wave_kernel<2>), static_cast<int>(lds_w));
+        hipLaunchKernelGGL(grp_resid_wave_kernel<2>, grid, dim3(kBlock), lds_w, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+      default:
+        if (lds_w > 65536)
+          ensure_dyn_lds(reinterpret_cast<const void*>(grp_resid_wave_kernel<3>), static_cast<int>(lds_w));
+        hipLaunchKernelGGL(grp_resid_wave_kernel<3>, grid, dim3(kBlock), lds_w, st, gr, a, w.xs, U,
+                           w.V);
+        break;
+    }
+  } else if (R1 <= kRmMax && nd <= kRmMax) {
     const size_t lds_m = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double) +
                          static_cast<size_t>(gp.dp) * sizeof(double);
     switch (gp.L) {

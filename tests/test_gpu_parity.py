@@ -103,8 +103,9 @@ def _sketch_case(dims, ranks, seed, dtype="f64", missing=None, factor="gaussian"
 
 # FP64 shapes with d >= 256 take the Gram grouped by the last mode of rank >= 2
 # The right side and residual are grouped the same way (up to three modes
-# before L): on MFMA when prod_{n<L-1} R_n <= 64 and R_{L-1} <= 64, else on the
-# vector units; with four or more modes before L they stay per sample.
+# before L): on MFMA when prod_{n<L-1} R_n <= 64 and R_{L-1} <= 64 (each wave
+# on its own samples when that V2 has at most four 16 x 16 blocks), else on
+# the vector units; with four or more modes before L they stay per sample.
 GROUPED_SHAPES = [
     ((40, 36, 30), (8, 8, 8)),          # d = 512, 30 groups
     ((30, 28, 26, 9), (8, 6, 6, 1)),    # d = 288, trailing rank-1 mode, d' = 48
@@ -112,6 +113,7 @@ GROUPED_SHAPES = [
     ((12, 10, 10, 10), (4, 4, 4, 4)),   # three modes before L, d' = 64
     ((12, 10, 4, 5), (9, 8, 2, 4)),     # R_0 R_1 = 72 > 64: vector-unit residual
     ((8, 6, 6, 5, 6), (4, 3, 3, 2, 4)),  # four modes before L: per-sample vectors
+    ((44, 20, 5), (40, 17, 2)),         # d = 1360: V2 of 3 x 2 blocks (32-sample MFMA form)
 ]
 
 
