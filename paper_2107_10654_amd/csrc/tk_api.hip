@@ -837,12 +837,7 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   SketchWS& w = R.w;
   hipStream_t st = R.st;
   R.stage(0);
-  launch_fill_i32(1, 0, R.status, st);
-  launch_fill_i32(1, 0, w.done, st);
-  launch_fill_i32(1, 0, w.steps, st);
-  launch_fill_f64(1, 0.0, w.relres, st);
-  launch_fill_f64(1, 1e308, w.min_pivot, st);
-  launch_fill_u32(1, 0u, w.missing, st);
+  launch_init_words(R.status, w.done, w.steps, w.relres, w.min_pivot, w.missing, st);
 
   // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
   launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,

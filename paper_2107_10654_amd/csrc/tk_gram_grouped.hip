@@ -175,10 +175,11 @@ __global__ __launch_bounds__(kBlock) void grp_rows_kernel(Geom g, const int32_t*
                                                           int sp, double* __restrict__ rows,
                                                           double* __restrict__ scs,
                                                           double* __restrict__ xs) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= s * sp) return;
-  const int64_t u = e / sp;
-  const int j = static_cast<int>(e - u * sp);
+  // s S' < 2^31 (the plan's limit): 32-bit index arithmetic
+  const uint32_t e = blockIdx.x * static_cast<uint32_t>(kBlock) + threadIdx.x;
+  if (static_cast<int64_t>(e) >= s * sp) return;
+  const uint32_t u = e / static_cast<uint32_t>(sp);
+  const int j = static_cast<int>(e - u * static_cast<uint32_t>(sp));
   const int64_t t = perm[u];
   int n = 0;
   while (n + 1 < L && g.soff[n + 1] <= j) ++n;

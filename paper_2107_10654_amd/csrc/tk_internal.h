@@ -347,6 +347,9 @@ void launch_cast_in(int64_t n, const void* x, tk_dtype dt, double* y, hipStream_
 void launch_fill_i32(int64_t n, int32_t v, int32_t* p, hipStream_t st);
 void launch_fill_f64(int64_t n, double v, double* p, hipStream_t st);
 void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st);
+// status, done, steps = 0, relres = 0, min_pivot = 1e308, missing = 0 in one launch
+void launch_init_words(int32_t* status, int32_t* done, int32_t* steps, double* relres,
+                       double* min_pivot, uint32_t* missing, hipStream_t st);
 // Refinement bookkeeping: residual update, relative residual, convergence flag:
 // r <- r + b - lambda ph (b, ph may be NULL); stops (done = 1) once
 // ||r|| <= tol ||rhs||.

@@ -656,6 +656,17 @@ __global__ void fill_kernel(int64_t n, T v, T* __restrict__ p) {
   if (i < n) p[i] = v;
 }
 
+// The per-call words of a sampled update in their starting state.
+__global__ void init_words_kernel(int32_t* status, int32_t* done, int32_t* steps, double* relres,
+                                  double* min_pivot, uint32_t* missing) {
+  *status = 0;
+  *done = 0;
+  *steps = 0;
+  *relres = 0.0;
+  *min_pivot = 1e308;
+  *missing = 0u;
+}
+
 // r <- r - lambda * ph (when ph != null); relres = ||r|| / ||rhs||; done when <= tol.
 __global__ __launch_bounds__(1024) void refine_check_kernel(int64_t d, double* __restrict__ r,
                                                             const double* __restrict__ ph,
@@ -770,6 +781,12 @@ void launch_fill_f64(int64_t n, double v, double* p, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_kernel<double>, dim3(static_cast<unsigned>(cdiv(n, kBlock))),
                      dim3(kBlock), 0, st, n, v, p);
+}
+
+void launch_init_words(int32_t* status, int32_t* done, int32_t* steps, double* relres,
+                       double* min_pivot, uint32_t* missing, hipStream_t st) {
+  hipLaunchKernelGGL(init_words_kernel, dim3(1), dim3(1), 0, st, status, done, steps, relres,
+                     min_pivot, missing);
 }
 
 void launch_fill_u32(int64_t n, uint32_t v, uint32_t* p, hipStream_t st) {
