@@ -761,11 +761,10 @@ void launch_cg(const double* M, int64_t d, const double* b, double* h, void* ws,
   Carver c(ws);
   CgWS w;
   carve_cg(c, d, w);
-  // one workgroup per compute unit, all resident together (the barriers wait
-  // on every workgroup of the launch)
   const bool full = d % kCt == 0;
-  // the grid: one workgroup per compute unit (all resident together: the
-  // barriers wait on every workgroup), then tiles held on chip when they fit
+  // the grid: one workgroup per compute unit, all resident together (every
+  // workgroup waits on data from the others), then tiles held on chip when
+  // they fit
   int grid = device_cu_count();
   {
     const int r1 = resident_grid(reinterpret_cast<const void*>(cg_kernel<true, true>), kBlock, 0);
