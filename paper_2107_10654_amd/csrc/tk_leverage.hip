@@ -26,19 +26,19 @@ __device__ inline double ld(const T* a, int64_t i) {
   return static_cast<double>(a[i]);
 }
 
-// buf[e] = src[e] for e < n (FP64), eight loads in flight per thread (indices
+// buf[e] = src[e] for e < n (FP64), NV loads in flight per thread (indices
 // clamped into range so that the loads issue together)
-template <class T>
+template <int NV, class T>
 __device__ inline void stage_rows(const T* src, int64_t n, double* buf) {
-  for (int64_t e0 = threadIdx.x; e0 < n; e0 += 8 * kBlock) {
-    double v[8];
+  for (int64_t e0 = threadIdx.x; e0 < n; e0 += NV * kBlock) {
+    double v[NV];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NV; ++k) {
       const int64_t e = e0 + k * kBlock;
       v[k] = ld(src, e < n ? e : n - 1);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NV; ++k) {
       const int64_t e = e0 + k * kBlock;
       if (e < n) buf[e] = v[k];
     }
@@ -50,8 +50,11 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp, double* Lg,
                                                           double* Linvg, double* Pg,
                                                           int32_t* status) {
-  __shared__ double bufC[kMaxRank * kMaxRank];  // C, then L (lower) in place
-  __shared__ double bufA[kMaxRank * kMaxRank];  // row chunks of A, then L^{-1}
+  // row chunks of A across both halves; then C and L (lower, in place) in the
+  // first, L^{-1} in the second
+  __shared__ double buf2[2 * kMaxRank * kMaxRank];
+  double* bufC = buf2;
+  double* bufA = buf2 + kMaxRank * kMaxRank;
   __shared__ int bad;
   __shared__ double thr;
 
@@ -74,11 +77,11 @@ __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp,
   double acc[kMaxPer];
 #pragma unroll
   for (int k = 0; k < kMaxPer; ++k) acc[k] = 0.0;
-  const int64_t chunk_rows = (kMaxRank * kMaxRank) / R;
+  const int64_t chunk_rows = (2 * kMaxRank * kMaxRank) / R;
   for (int64_t r0 = 0; r0 < I; r0 += chunk_rows) {
     const int64_t rows = (I - r0 < chunk_rows) ? (I - r0) : chunk_rows;
     __syncthreads();
-    stage_rows(A + r0 * R, rows * R, bufA);
+    stage_rows<32>(A + r0 * R, rows * R, buf2);  // one round trip for a full chunk
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kMaxPer; ++k) {
@@ -89,14 +92,17 @@ __global__ __launch_bounds__(kBlock) void leverage_kernel(Geom g, FactorPtrs fp,
         while ((a + 1) * (a + 2) / 2 <= e) ++a;
         while (a * (a + 1) / 2 > e) --a;
         const int b = e - a * (a + 1) / 2;
-        double s0 = 0.0, s1 = 0.0;
+        // four independent chains over the rows, added in a fixed order
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int64_t i = grp;
-        for (; i + G < rows; i += 2 * G) {
-          s0 = fma(bufA[i * R + a], bufA[i * R + b], s0);
-          s1 = fma(bufA[(i + G) * R + a], bufA[(i + G) * R + b], s1);
+        for (; i + 3 * G < rows; i += 4 * G) {
+          s0 = fma(buf2[i * R + a], buf2[i * R + b], s0);
+          s1 = fma(buf2[(i + G) * R + a], buf2[(i + G) * R + b], s1);
+          s2 = fma(buf2[(i + 2 * G) * R + a], buf2[(i + 2 * G) * R + b], s2);
+          s3 = fma(buf2[(i + 3 * G) * R + a], buf2[(i + 3 * G) * R + b], s3);
         }
-        if (i < rows) s0 = fma(bufA[i * R + a], bufA[i * R + b], s0);
-        acc[k] += s0 + s1;
+        for (; i < rows; i += G) s0 = fma(buf2[i * R + a], buf2[i * R + b], s0);
+        acc[k] += (s0 + s1) + (s2 + s3);
       }
     }
   }
