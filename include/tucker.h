@@ -39,7 +39,9 @@ extern "C" {
 
 #define TK_MAX_ORDER 8     /* largest supported tensor order N */
 #define TK_MAX_RANK 64     /* largest supported per-mode rank R_n */
-#define TK_Q_BITS 24       /* fixed-point bits of the integer sampling weights */
+#define TK_Q_BITS 24       /* fixed-point bits Q of the integer sampling weights (default) */
+#define TK_Q_BITS_MIN 8    /* range of tk_sketch_opts.cdf_bits when it is not 0 */
+#define TK_Q_BITS_MAX 40
 #define TK_INFO_LEN 8      /* doubles written to dev_info by the sketched update */
 #define TK_NUM_STAGE_EVENTS 10 /* stage boundaries of the sketched update (tk_sketch_opts) */
 
@@ -109,6 +111,13 @@ typedef struct {
                               leverage scores of K (Sec. 2 SVD form), a mixture over
                               singular-value tuples (tucker_ridge_tables,
                               tucker_sample_ridge) */
+  int32_t cdf_bits;        /* fixed-point bits Q of the integer sampling weights the call
+                              builds (w = ceil(l 2^Q) for the factor scores, the ridge tuple
+                              and column weights, the augmented coin's 2^Q and ceil(c 2^Q)):
+                              0 selects TK_Q_BITS, else TK_Q_BITS_MIN..TK_Q_BITS_MAX
+                              (TK_E_ARG otherwise).  The entry points that build tables
+                              without options (tucker_leverage_scores, tucker_ridge_tables, the
+                              augmented coin of tucker_sample_augmented) use TK_Q_BITS. */
 } tk_sketch_opts;
 
 /* Which call tucker_workspace_bytes() sizes. */

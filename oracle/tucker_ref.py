@@ -276,16 +276,17 @@ def sample(tables, s, seed, counter, problem=0):
 AUG_BLOCK = 2
 
 
-def coin_weights(d, d_eff_lower):
+def coin_weights(d, d_eff_lower, q_bits=Q_BITS):
     """Integer weights of the two branches of D(l, d'_eff): the data rows
     (total mass d after normalisation) get D = 2^Q, the d ridge rows (total
     mass d c) get C = ceil(c 2^Q), so a draw is a ridge row with probability
     C / (D + C) ~ c / (1 + c)."""
     c = ridge_row_mass(d, d_eff_lower)
-    return 2 ** Q_BITS, int(math.ceil(c * float(2 ** Q_BITS)))
+    return 2 ** q_bits, int(math.ceil(c * float(2 ** q_bits)))
 
 
-def sample_augmented(tables, ranks, s, seed, counter, d_eff_lower=0.0, problem=0):
+def sample_augmented(tables, ranks, s, seed, counter, d_eff_lower=0.0, problem=0,
+                     q_bits=Q_BITS):
     """s i.i.d. draws from the augmented distribution D(l, d'_eff) of Alg. 1.
 
     Each draw first flips the branch coin (Sec. 3: branch on the two index
@@ -302,7 +303,7 @@ def sample_augmented(tables, ranks, s, seed, counter, d_eff_lower=0.0, problem=0
     N = len(tables)
     dims = [len(C) for _, C in tables]
     d = int(np.prod(ranks))
-    D, Cw = coin_weights(d, d_eff_lower)
+    D, Cw = coin_weights(d, d_eff_lower, q_bits)
     idx, acc = _product_draws(tables, s, seed, counter, problem)
     t = np.arange(s, dtype=np.uint64)
     words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(AUG_BLOCK), seed, 0)
@@ -385,7 +386,8 @@ def ridge_mixture_probabilities(tuple_tab, cols, ranks, idx):
     return P
 
 
-def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0, d_eff_lower=None):
+def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0, d_eff_lower=None,
+                 q_bits=Q_BITS):
     """s i.i.d. draws from the ridge-score mixture.
 
     Per draw: the tuple t from the tuple table with word 0 of Philox block
@@ -429,7 +431,7 @@ def sample_ridge(tuple_tab, cols, ranks, s, seed, counter, problem=0, d_eff_lowe
         return idx, weight
     dims = [len(colt[0][1]) for colt in cols]
     d = int(np.prod(ranks))
-    D, Cw = coin_weights(d, d_eff_lower)
+    D, Cw = coin_weights(d, d_eff_lower, q_bits)
     words = philox4x64(t, np.uint64(counter), np.uint64(problem), np.uint64(AUG_BLOCK), seed, 0)
     ridge = mulhi64(words[0], np.uint64(D + Cw)) >= np.uint64(D)
     k = mulhi64(words[1], np.uint64(d)).astype(np.int64)
@@ -529,19 +531,21 @@ def core_update_sketched_augmented(X, factors, lam, idx, weight, mask=None):
 
 
 def fast_core_tensor_update_augmented(X, factors, lam, s, seed, counter, d_eff_lower=0.0,
-                                      mask=None, problem=0):
+                                      mask=None, problem=0, q_bits=Q_BITS):
     """Alg. 3 with Alg. 1 taken literally: factor leverage scores as the
     overestimate, draws from the augmented distribution, solve on S Abar."""
-    tables = [cdf_table(leverage_scores(A)) for A in factors]
+    tables = [cdf_table(leverage_scores(A), q_bits) for A in factors]
     ranks = [A.shape[1] for A in factors]
-    idx, weight = sample_augmented(tables, ranks, s, seed, counter, d_eff_lower, problem)
+    idx, weight = sample_augmented(tables, ranks, s, seed, counter, d_eff_lower, problem, q_bits)
     G = core_update_sketched_augmented(X, factors, lam, idx, weight, mask)
     return G, idx, weight, tables
 
 
-def fast_core_tensor_update(X, factors, lam, s, seed, counter, mask=None, problem=0):
-    """Alg. 3 end to end: factor leverage scores, product sampler, sketched solve."""
-    tables = [cdf_table(leverage_scores(A)) for A in factors]
+def fast_core_tensor_update(X, factors, lam, s, seed, counter, mask=None, problem=0,
+                            q_bits=Q_BITS):
+    """Alg. 3 end to end: factor leverage scores, product sampler, sketched solve
+    (sampling tables with q_bits fixed-point bits)."""
+    tables = [cdf_table(leverage_scores(A), q_bits) for A in factors]
     idx, weight = sample(tables, s, seed, counter, problem)
     G = core_update_sketched(X, factors, lam, idx, weight, mask)
     return G, idx, weight, tables

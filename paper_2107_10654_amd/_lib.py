@@ -54,6 +54,7 @@ class TkSketchOpts(ctypes.Structure):
         ("augmented", ctypes.c_int32),
         ("d_eff_lower", ctypes.c_double),
         ("sampling", ctypes.c_int32),
+        ("cdf_bits", ctypes.c_int32),
     ]
 
 

@@ -104,10 +104,12 @@ double ridge_row_mass(int64_t d, double d_eff_lower) {
 }
 
 // Integer weight C = ceil(c 2^Q) of the ridge branch (the data branch has 2^Q).
-uint64_t ridge_coin_weight(int64_t d, double d_eff_lower) {
-  return static_cast<uint64_t>(
-      ceil(ridge_row_mass(d, d_eff_lower) * static_cast<double>(1ull << TK_Q_BITS)));
+uint64_t ridge_coin_weight(int64_t d, double d_eff_lower, int qbits) {
+  return static_cast<uint64_t>(ceil(ridge_row_mass(d, d_eff_lower) * ldexp(1.0, qbits)));
 }
+
+// Q of a sampled update's integer weights (0 selects TK_Q_BITS).
+int sketch_qbits(const tk_sketch_opts* o) { return o->cdf_bits ? o->cdf_bits : TK_Q_BITS; }
 
 // ---------------------------------------------------------------- workspaces
 struct LevWS {
@@ -155,9 +157,10 @@ void carve_ridge(Carver& c, const Geom& g, RidgeWS& r) {
   r.deff = c.take<double>(1);
 }
 
-void launch_ridge(const Geom& g, const tk_problem* p, RidgeWS& r, hipStream_t st) {
+void launch_ridge(const Geom& g, const tk_problem* p, RidgeWS& r, hipStream_t st,
+                  int qbits = TK_Q_BITS) {
   launch_eig_modes(g, p->factors, p->dtype, r.V, r.lamm, r.W, r.C, st);
-  launch_ridge_tables(g, r.lamm, r.W, p->lambda, r.tcdf, r.ccdf, r.deff, st);
+  launch_ridge_tables(g, r.lamm, r.W, p->lambda, r.tcdf, r.ccdf, r.deff, st, qbits);
 }
 
 struct SketchWS {
@@ -711,7 +714,7 @@ tk_status tucker_sample_ridge(int32_t order, const int64_t* dims, const int32_t*
   const Geom g = make_geom(&p);
   launch_sample_ridge(g, tuple_cdf, col_cdf, s, seed, counter, problem, idx, weight,
                       static_cast<hipStream_t>(stream), augmented,
-                      augmented ? ridge_coin_weight(d, d_eff_lower) : 0);
+                      augmented ? ridge_coin_weight(d, d_eff_lower, TK_Q_BITS) : 0);
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
@@ -771,7 +774,7 @@ tk_status tucker_sample_augmented(int32_t order, const int64_t* dims, const int3
   }
   const Geom g = make_geom(&p);
   launch_sample(g, cdf, s, seed, counter, problem, idx, weight, static_cast<hipStream_t>(stream),
-                1, ridge_coin_weight(d, d_eff_lower));
+                1, ridge_coin_weight(d, d_eff_lower, TK_Q_BITS));
   return hipGetLastError() == hipSuccess ? TK_OK : TK_E_HIP;
 }
 
@@ -822,6 +825,8 @@ tk_status check_sketch_args(const tk_problem* p, const tk_sketch_opts* o, int64_
       if (p->dims[n] > (int64_t(1) << 31) - 1 - kMaxRank) return TK_E_SHAPE;
   }
   if (o->refine_max < 0 || o->refine_max > 1000 || !(o->refine_tol >= 0.0)) return TK_E_ARG;
+  if (o->cdf_bits != 0 && (o->cdf_bits < TK_Q_BITS_MIN || o->cdf_bits > TK_Q_BITS_MAX))
+    return TK_E_ARG;
   const Geom g = make_geom(p);
   s = resolve_samples(o, g.d);
   if (s < 1 || s > (int64_t(1) << 31) - 1) return TK_E_ARG;
@@ -840,8 +845,9 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   launch_init_words(R.status, w.done, w.steps, w.relres, w.min_pivot, w.missing, st);
 
   // 1. factor leverage scores, whitened rows, CDF tables (Alg. 3, first step)
+  const int qbits = sketch_qbits(R.o);
   launch_leverage(g, p->factors, p->dtype, w.lev.scores, w.lev.cdf, w.lev.L, w.lev.Linv, w.lev.P,
-                  w.lev.Q64, w.lev.Q32, R.status, st);
+                  w.lev.Q64, w.lev.Q32, R.status, st, qbits);
   if (R.aug) launch_aug_tables(g, R.ga, w.lev.Q64, w.lev.Linv, p->lambda, w.Q64a, st);
   R.stage(1);
   // 2. samples (Alg. 3 sampler) or the frozen set
@@ -850,14 +856,14 @@ tk_status sketch_pre(SketchRun& R, const tk_problem* p, const int32_t* idx_in,
   if (!idx_in) {
     int32_t* io = idx_out ? idx_out : w.idx;
     double* wo = weight_out ? weight_out : w.weight;
-    const uint64_t coin = R.aug ? ridge_coin_weight(g.d, R.o->d_eff_lower) : 0;
+    const uint64_t coin = R.aug ? ridge_coin_weight(g.d, R.o->d_eff_lower, qbits) : 0;
     if (R.o->sampling == 1) {  // the ridge-score mixture of K
-      launch_ridge(g, p, w.ridge, st);
+      launch_ridge(g, p, w.ridge, st, qbits);
       launch_sample_ridge(g, w.ridge.tcdf, w.ridge.ccdf, R.s, R.o->seed, R.o->counter,
-                          R.o->problem, io, wo, st, R.aug ? 1 : 0, coin);
+                          R.o->problem, io, wo, st, R.aug ? 1 : 0, coin, qbits);
     } else {
       launch_sample(g, w.lev.cdf, R.s, R.o->seed, R.o->counter, R.o->problem, io, wo, st,
-                    R.aug ? 1 : 0, coin);
+                    R.aug ? 1 : 0, coin, qbits);
     }
     R.idx = io;
     R.weight = wo;

@@ -62,9 +62,10 @@ struct Carver {
 // Leverage scores / tables / whitening (tk_leverage.hip).
 // L, Linv and P (= (L^T L)^{-1}) per mode at geom.roff; Q64 / Q32 whitened rows
 // at geom.qoff; scores and cdf at geom.off.
+// qbits: fixed-point bits Q of the integer sampling weights ceil(l 2^Q).
 void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, double* scores,
                      uint64_t* cdf, double* L, double* Linv, double* P, double* Q64, float* Q32,
-                     int32_t* status, hipStream_t st);
+                     int32_t* status, hipStream_t st, int qbits = TK_Q_BITS);
 
 // Rows times a per-mode R_n x R_n FP64 matrix M (at geom.roff):
 // out[i][c] = sum_k A(n)[i][k] M[k][c], or M transposed when trans != 0; out64
@@ -73,14 +74,15 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
 // at geom.off.
 void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, const double* M,
                       int trans, double* out64, float* out32, double* scores, uint64_t* weights,
-                      hipStream_t st);
+                      hipStream_t st, int qbits = TK_Q_BITS);
 
 // Sampler (tk_sample.hip).
 // aug != 0: augmented draws over [K; sqrt(lambda) I] with ridge branch weight
-// coin_c (tk_sample.hip); g.ranks and g.d give the ridge rows' digits.
+// coin_c against the data branch's 2^qbits (tk_sample.hip); g.ranks and g.d
+// give the ridge rows' digits.
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug = 0,
-                   uint64_t coin_c = 0);
+                   uint64_t coin_c = 0, int qbits = TK_Q_BITS);
 
 // Ridge-score mixture of K (tk_leverage.hip, tk_sample.hip): from the
 // eigenpairs of eig_modes (lamm[n * 64 + c], W_n = A(n) V_n rows at qoff) the
@@ -88,10 +90,12 @@ void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed,
 // d_eff = sum_t pi_t (device double); then draws from the mixture (with the
 // augmented coin when aug != 0), weights 1/(s P).
 void launch_ridge_tables(const Geom& g, const double* lamm, const double* W, double lambda,
-                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st);
+                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st,
+                         int qbits = TK_Q_BITS);
 void launch_sample_ridge(const Geom& g, const uint64_t* tcdf, const uint64_t* ccdf, int64_t s,
                          uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
-                         double* weight, hipStream_t st, int aug = 0, uint64_t coin_c = 0);
+                         double* weight, hipStream_t st, int aug = 0, uint64_t coin_c = 0,
+                         int qbits = TK_Q_BITS);
 
 // Whitened row tables of the augmented design (tk_leverage.hip): in the
 // geometry ga (dims I_n + R_n), rows i < I_n of mode n copy Q64's rows and

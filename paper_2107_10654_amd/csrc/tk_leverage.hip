@@ -206,7 +206,8 @@ __host__ __device__ inline int64_t mode_row_blocks(int64_t I) {
 template <class T>
 __global__ __launch_bounds__(kBlock) void mode_rows_kernel(Geom g, FactorPtrs fp, const double* Mg,
                                                            int trans, double* out64, float* out32,
-                                                           double* scores, uint64_t* weights) {
+                                                           double* scores, uint64_t* weights,
+                                                           double qscale) {
   __shared__ double Ms[kMaxRank * kMaxRank];
   __shared__ double As[kModeRows * (kMaxRank + 1)];
   __shared__ double Ss[kModeRows * (kMaxRank + 1)];
@@ -248,8 +249,7 @@ __global__ __launch_bounds__(kBlock) void mode_rows_kernel(Geom g, FactorPtrs fp
     for (int c = 0; c < R; ++c) l += Ss[tid * Rp + c];
     if (scores) scores[g.off[n] + r0 + tid] = l;
     const double lc = l > 0.0 ? l : 0.0;
-    weights[g.off[n] + r0 + tid] =
-        static_cast<uint64_t>(ceil(lc * static_cast<double>(1ull << TK_Q_BITS)));
+    weights[g.off[n] + r0 + tid] = static_cast<uint64_t>(ceil(lc * qscale));
   }
 }
 
@@ -314,7 +314,8 @@ __device__ void block_scan_u64(uint64_t* cd, int64_t len, uint64_t* wsum) {
 // numerically zero eigenvalue (<= R 2^-52 max) gets an all-zero column.
 __global__ __launch_bounds__(kBlock) void ridge_col_kernel(Geom g, const double* __restrict__ lamm,
                                                            const double* __restrict__ W,
-                                                           uint64_t* __restrict__ ccdf) {
+                                                           uint64_t* __restrict__ ccdf,
+                                                           double qscale) {
   __shared__ uint64_t wsum[kBlock / 64];
   int n = 0, c = blockIdx.x;
   while (c >= g.ranks[n]) c -= g.ranks[n++];
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void ridge_col_kernel(Geom g, const double*
   for (int64_t i = threadIdx.x; i < I; i += kBlock) {
     const double v = w[i * R];
     const double u2 = zero ? 0.0 : (v * v) / lc;
-    cd[i] = static_cast<uint64_t>(ceil(u2 * static_cast<double>(1ull << TK_Q_BITS)));
+    cd[i] = static_cast<uint64_t>(ceil(u2 * qscale));
   }
   __syncthreads();
   block_scan_u64(cd, I, wsum);
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(kBlock) void ridge_col_kernel(Geom g, const double*
 __global__ __launch_bounds__(kBlock) void ridge_tuple_kernel(Geom g, const double* __restrict__ lamm,
                                                              double lambda,
                                                              uint64_t* __restrict__ tcdf,
-                                                             double* __restrict__ deff) {
+                                                             double* __restrict__ deff,
+                                                             double qscale) {
   __shared__ uint64_t wsum[kBlock / 64];
   __shared__ double part[kBlock];
   const int tid = threadIdx.x;
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void ridge_tuple_kernel(Geom g, const doubl
     for (int n = 0; n < g.order; ++n) prod = prod * lamm[n * kMaxRank + dig[n]];
     const double pi = prod > 0.0 ? prod / (prod + lambda) : 0.0;
     acc += pi;
-    tcdf[t] = static_cast<uint64_t>(ceil(pi * static_cast<double>(1ull << TK_Q_BITS)));
+    tcdf[t] = static_cast<uint64_t>(ceil(pi * qscale));
   }
   part[tid] = acc;
   __syncthreads();
@@ -398,9 +400,12 @@ __global__ __launch_bounds__(kBlock) void aug_tables_kernel(Geom g, Geom ga,
 }  // namespace
 
 void launch_ridge_tables(const Geom& g, const double* lamm, const double* W, double lambda,
-                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st) {
-  hipLaunchKernelGGL(ridge_col_kernel, dim3(g.sum_r), dim3(kBlock), 0, st, g, lamm, W, ccdf);
-  hipLaunchKernelGGL(ridge_tuple_kernel, dim3(1), dim3(kBlock), 0, st, g, lamm, lambda, tcdf, deff);
+                         uint64_t* tcdf, uint64_t* ccdf, double* deff, hipStream_t st, int qbits) {
+  const double qscale = ldexp(1.0, qbits);
+  hipLaunchKernelGGL(ridge_col_kernel, dim3(g.sum_r), dim3(kBlock), 0, st, g, lamm, W, ccdf,
+                     qscale);
+  hipLaunchKernelGGL(ridge_tuple_kernel, dim3(1), dim3(kBlock), 0, st, g, lamm, lambda, tcdf, deff,
+                     qscale);
 }
 
 void launch_aug_tables(const Geom& g, const Geom& ga, const double* Q64, const double* Linv,
@@ -411,7 +416,7 @@ void launch_aug_tables(const Geom& g, const Geom& ga, const double* Q64, const d
 
 void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, double* scores,
                      uint64_t* cdf, double* L, double* Linv, double* P, double* Q64, float* Q32,
-                     int32_t* status, hipStream_t st) {
+                     int32_t* status, hipStream_t st, int qbits) {
   FactorPtrs fp;
   for (int n = 0; n < kMaxOrder; ++n) fp.p[n] = n < g.order ? factors[n] : nullptr;
   if (dt == TK_F64)
@@ -420,13 +425,14 @@ void launch_leverage(const Geom& g, const void* const* factors, tk_dtype dt, dou
   else
     hipLaunchKernelGGL(leverage_kernel<float>, dim3(g.order), dim3(kBlock), 0, st, g, fp, L, Linv,
                        P, status);
-  launch_mode_rows(g, factors, dt, Linv, 1, Q64, Q32, scores, cdf, st);
+  launch_mode_rows(g, factors, dt, Linv, 1, Q64, Q32, scores, cdf, st, qbits);
   hipLaunchKernelGGL(weight_scan_kernel, dim3(g.order), dim3(kBlock), 0, st, g, cdf);
 }
 
 void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, const double* M,
                       int trans, double* out64, float* out32, double* scores, uint64_t* weights,
-                      hipStream_t st) {
+                      hipStream_t st, int qbits) {
+  const double qscale = ldexp(1.0, qbits);
   FactorPtrs fp;
   int64_t blocks = 0;
   for (int n = 0; n < kMaxOrder; ++n) fp.p[n] = n < g.order ? factors[n] : nullptr;
@@ -434,10 +440,10 @@ void launch_mode_rows(const Geom& g, const void* const* factors, tk_dtype dt, co
   if (blocks == 0) return;
   if (dt == TK_F64)
     hipLaunchKernelGGL(mode_rows_kernel<double>, dim3(blocks), dim3(kBlock), 0, st, g, fp, M,
-                       trans, out64, out32, scores, weights);
+                       trans, out64, out32, scores, weights, qscale);
   else
     hipLaunchKernelGGL(mode_rows_kernel<float>, dim3(blocks), dim3(kBlock), 0, st, g, fp, M, trans,
-                       out64, out32, scores, weights);
+                       out64, out32, scores, weights, qscale);
 }
 
 }  // namespace tk

@@ -50,14 +50,14 @@ __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
 // by every sample's binary searches); the grid strides over the samples.
 constexpr int64_t kSampleLdsRows = 6144;  // 48 KB of uint64 entries
 constexpr uint64_t kAugBlock = 2;          // Philox block of the branch draws (modes use 0, 1)
-constexpr uint64_t kCoinData = 1ull << TK_Q_BITS;
 
 // aug: 0 plain product draws; 1 augmented draws with ridge branch weight coin_c
+// against the data branch's coin_d = 2^Q
 template <bool STAGE>
 __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* __restrict__ cdf,
                                                         int64_t s, uint64_t seed,
                                                         uint64_t counter, uint64_t problem,
-                                                        int aug, uint64_t coin_c,
+                                                        int aug, uint64_t coin_c, uint64_t coin_d,
                                                         int32_t* __restrict__ idx,
                                                         double* __restrict__ weight) {
   extern __shared__ uint64_t cs[];
@@ -114,8 +114,8 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* 
     }
     uint64_t c[4] = {static_cast<uint64_t>(t), counter, problem, kAugBlock};
     philox4x64_10(c, seed, 0ull);
-    const uint64_t tot = kCoinData + coin_c;
-    if (__umul64hi(c[0], tot) >= kCoinData) {
+    const uint64_t tot = coin_d + coin_c;
+    if (__umul64hi(c[0], tot) >= coin_d) {
       // ridge row k of the d rows sqrt(lambda) e_k
       uint64_t k = __umul64hi(c[1], static_cast<uint64_t>(g.d));
       for (int n = N - 1; n >= 0; --n) {
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(Geom g, const uint64_t* 
       const double r = static_cast<double>(tot) / static_cast<double>(coin_c);
       weight[t] = (r * static_cast<double>(g.d)) / static_cast<double>(s);
     } else {
-      const double r = static_cast<double>(tot) / static_cast<double>(kCoinData);
+      const double r = static_cast<double>(tot) / static_cast<double>(coin_d);
       weight[t] = (acc * r) / static_cast<double>(s);
     }
   }
@@ -156,7 +156,7 @@ __device__ inline int64_t upper_search(const uint64_t* __restrict__ C, int64_t l
 
 __global__ __launch_bounds__(kBlock) void ridge_sample_kernel(
     Geom g, const uint64_t* __restrict__ tcdf, const uint64_t* __restrict__ ccdf, int64_t s,
-    uint64_t seed, uint64_t counter, uint64_t problem, int aug, uint64_t coin_c,
+    uint64_t seed, uint64_t counter, uint64_t problem, int aug, uint64_t coin_c, uint64_t coin_d,
     int32_t* __restrict__ idx, double* __restrict__ weight) {
   const int N = g.order;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; t < s;
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void ridge_sample_kernel(
     if (!aug) continue;
     uint64_t ca[4] = {static_cast<uint64_t>(t), counter, problem, kAugBlock};
     philox4x64_10(ca, seed, 0ull);
-    const uint64_t tot = kCoinData + coin_c;
-    if (__umul64hi(ca[0], tot) >= kCoinData) {
+    const uint64_t tot = coin_d + coin_c;
+    if (__umul64hi(ca[0], tot) >= coin_d) {
       uint64_t k = __umul64hi(ca[1], static_cast<uint64_t>(g.d));
       for (int n = N - 1; n >= 0; --n) {
         const uint64_t R = static_cast<uint64_t>(g.ranks[n]);
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void ridge_sample_kernel(
 // sum_r + 2 bufmax doubles.
 __global__ __launch_bounds__(64) void ridge_weight_kernel(
     Geom g, const uint64_t* __restrict__ tcdf, const uint64_t* __restrict__ ccdf,
-    const int32_t* __restrict__ idx, int64_t s, int aug, uint64_t coin_c, int64_t bufmax,
+    const int32_t* __restrict__ idx, int64_t s, int aug, uint64_t coin_c, uint64_t coin_d, int64_t bufmax,
     double* __restrict__ weight) {
   extern __shared__ double sm[];
   double* u = sm;                  // [sum_r]
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64) void ridge_weight_kernel(
       const double num =
           (src ? src[0] : static_cast<double>(tcdf[0])) * scal;  // sum_t w_t prod_n u_n[t_n]
       double w = Wt / num;
-      if (aug) w = w * (static_cast<double>(kCoinData + coin_c) / static_cast<double>(kCoinData));
+      if (aug) w = w * (static_cast<double>(coin_d + coin_c) / static_cast<double>(coin_d));
       weight[t] = w / static_cast<double>(s);
     }
     __syncthreads();
@@ -275,13 +275,15 @@ __global__ __launch_bounds__(64) void ridge_weight_kernel(
 
 void launch_sample_ridge(const Geom& g, const uint64_t* tcdf, const uint64_t* ccdf, int64_t s,
                          uint64_t seed, uint64_t counter, uint64_t problem, int32_t* idx,
-                         double* weight, hipStream_t st, int aug, uint64_t coin_c) {
+                         double* weight, hipStream_t st, int aug, uint64_t coin_c, int qbits) {
+  const uint64_t coin_d = 1ull << qbits;
   if (s <= 0) return;
   const int64_t want = cdiv(s, kBlock);
   const int64_t res =
       resident_grid(reinterpret_cast<const void*>(&ridge_sample_kernel), kBlock, 0);
   hipLaunchKernelGGL(ridge_sample_kernel, dim3(static_cast<unsigned>(want < res ? want : res)),
                      dim3(kBlock), 0, st, g, tcdf, ccdf, s, seed, counter, problem, aug, coin_c,
+                     coin_d,
                      idx, weight);
   // the largest intermediate of the contraction: d over the last rank >= 2
   int64_t bufmax = 1;
@@ -294,12 +296,13 @@ void launch_sample_ridge(const Geom& g, const uint64_t* tcdf, const uint64_t* cc
   ensure_dyn_lds(reinterpret_cast<const void*>(&ridge_weight_kernel), static_cast<int>(lds));
   const int64_t grid = s < 65536 ? s : 65536;
   hipLaunchKernelGGL(ridge_weight_kernel, dim3(static_cast<unsigned>(grid)), dim3(64), lds, st, g,
-                     tcdf, ccdf, idx, s, aug, coin_c, bufmax, weight);
+                     tcdf, ccdf, idx, s, aug, coin_c, coin_d, bufmax, weight);
 }
 
 void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed, uint64_t counter,
                    uint64_t problem, int32_t* idx, double* weight, hipStream_t st, int aug,
-                   uint64_t coin_c) {
+                   uint64_t coin_c, int qbits) {
+  const uint64_t coin_d = 1ull << qbits;
   if (s <= 0) return;
   if (g.total_rows <= kSampleLdsRows) {
     // as many workgroups as are resident at once (each stages the tables)
@@ -309,10 +312,11 @@ void launch_sample(const Geom& g, const uint64_t* cdf, int64_t s, uint64_t seed,
         resident_grid(reinterpret_cast<const void*>(&sample_kernel<true>), kBlock, lds);
     const unsigned grid = static_cast<unsigned>(want < res ? want : res);
     hipLaunchKernelGGL(sample_kernel<true>, dim3(grid), dim3(kBlock), lds, st, g, cdf, s, seed,
-                       counter, problem, aug, coin_c, idx, weight);
+                       counter, problem, aug, coin_c, coin_d, idx, weight);
   } else {
     hipLaunchKernelGGL(sample_kernel<false>, dim3(static_cast<unsigned>(cdiv(s, kBlock))),
-                       dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, aug, coin_c, idx,
+                       dim3(kBlock), 0, st, g, cdf, s, seed, counter, problem, aug, coin_c, coin_d,
+                       idx,
                        weight);
   }
 }

@@ -112,8 +112,9 @@ SAMPLINGS = {"leverage": 0, "ridge": 1}
 
 
 def _opts(samples, seed, counter, problem, precision, refine_max, refine_tol, eps=0.1, delta=0.1,
-          stage_events=None, augmented=False, d_eff_lower=0.0, sampling="leverage"):
+          stage_events=None, augmented=False, d_eff_lower=0.0, sampling="leverage", cdf_bits=0):
     o = L.TkSketchOpts()
+    o.cdf_bits = int(cdf_bits)
     o.augmented = 1 if augmented else 0
     o.d_eff_lower = float(d_eff_lower)
     o.sampling = SAMPLINGS[sampling]
@@ -276,7 +277,7 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
                          mask=None, idx=None, weight=None, refine_max=20, refine_tol=1e-13,
                          return_samples=False, return_info=False, check=True, out=None,
                          stage_events=None, status=None, augmented=False, d_eff_lower=0.0,
-                         sampling="leverage"):
+                         sampling="leverage", cdf_bits=0):
     """Sampled core update (Alg. 3 with Alg. 1); returns the core (and optionally samples/info).
 
     stage_events: optional address of an array of NUM_STAGE_EVENTS hipEvent_t
@@ -287,12 +288,14 @@ def core_update_sketched(X, factors, lam, samples, seed=0, counter=0, problem=0,
     of the effective dimension) and solve on the sampled rows of [K; sqrt(lam) I].
     sampling: "leverage" (product of the factor leverage scores) or "ridge" (the
     lambda-ridge leverage scores of K, a mixture over singular-value tuples).
+    cdf_bits: fixed-point bits Q of the integer sampling weights ceil(l 2^Q)
+    (0: the library default, TK_Q_BITS = 24; else 8..40).
     """
     lib = L.load()
     p = make_problem(X, factors, lam, mask)
     o = _opts(samples, seed, counter, problem, precision, refine_max, refine_tol,
               stage_events=stage_events, augmented=augmented, d_eff_lower=d_eff_lower,
-              sampling=sampling)
+              sampling=sampling, cdf_bits=cdf_bits)
     dev = X.device
     N = len(factors)
     d = int(torch.tensor([A.shape[1] for A in factors]).prod())

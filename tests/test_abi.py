@@ -47,8 +47,9 @@ def test_struct_layouts_match_header(lib):
     # 8 pointers, double -> natural alignment
     assert ctypes.sizeof(L.TkProblem) == 4 + 4 + 64 + 32 + 4 + 4 + 8 + 8 + 64 + 8
     # ... int32 gram_precision, int32 refine_max, double, pointer, int32 augmented
-    # (+4 padding), double d_eff_lower, int32 sampling (+4 padding)
+    # (+4 padding), double d_eff_lower, int32 sampling, int32 cdf_bits
     assert ctypes.sizeof(L.TkSketchOpts) == 8 * 6 + 4 + 4 + 8 + 8 + 8 + 8 + 8
+    assert L.TkSketchOpts.sampling.offset == 88 and L.TkSketchOpts.cdf_bits.offset == 92
 
 
 def _problem(dims, ranks, dtype=L.TK_F32, lam=1e-2):
@@ -117,6 +118,12 @@ def test_host_argument_errors(lib):
     # idx without weights
     assert f(ctypes.byref(p), ctypes.byref(o), ctypes.c_void_p(0x10), None, None, None, core,
              None, None, ws, 16, st) == 1
+    # fixed-point bits of the sampling weights outside 8..40 (0 selects the default)
+    for q in (7, 41, -1):
+        oq = _opts()
+        oq.cdf_bits = q
+        assert f(ctypes.byref(p), ctypes.byref(oq), None, None, None, None, core, None, None,
+                 ws, 16, st) == 1
     # bad order / dtype / lambda
     bad = _problem((64, 64, 64), (4, 4, 4))
     bad.order = 0

@@ -101,6 +101,22 @@ def test_augmented_update_matches_oracle(tk, dims, ranks, s, missing, precision)
     assert elem_err(G.cpu().numpy(), Gr) <= (1e-10 if precision == "f64" else 1e-9)
 
 
+def test_augmented_cdf_bits_matches_oracle(tk):
+    # the factor tables and the branch coin with Q = 20 fixed-point bits
+    dims, ranks, s, q = (41, 37, 29), (5, 6, 7), 9000, 20
+    p, F = _case(dims, ranks, 31)
+    lam, deff = 2e-2, float(np.prod(ranks)) - 0.6
+    G, idx, w = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=7, counter=5,
+                                        precision="f64", augmented=True, d_eff_lower=deff,
+                                        return_samples=True, cdf_bits=q)
+    tabs = [oracle.cdf_table(oracle.leverage_scores(A), q) for A in F]
+    ridx, rw = oracle.sample_augmented(tabs, ranks, s, 7, 5, deff, q_bits=q)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(w.cpu().numpy(), rw)
+    Gr = oracle.core_update_sketched_augmented(p["X"], F, lam, ridx, rw)
+    assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
+
+
 def test_augmented_frozen_set_and_adjoint_refusal(tk):
     p, F = _case((20, 18, 16), (3, 4, 2), 32)
     lam, s = 5e-2, 2500

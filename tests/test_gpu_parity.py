@@ -129,6 +129,24 @@ def test_sketched_f64_matches_oracle(tk, dims, ranks):
     assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
 
 
+# tk_sketch_opts.cdf_bits: the integer sampling weights ceil(l 2^Q) with another
+# Q; the draws must stay bit-exact with the oracle's tables of the same Q (and
+# differ from the default Q's, so the option reaches the sampler).
+@pytest.mark.parametrize("q", [12, 32])
+def test_sketched_cdf_bits_matches_oracle(tk, q):
+    dims, ranks = (41, 37, 29), (5, 6, 7)
+    p, F = _sketch_case(dims, ranks, 3)
+    lam, s = 1e-3, 3001
+    G, idx, w = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=11, counter=2,
+                                        precision="f64", return_samples=True, cdf_bits=q)
+    Gr, ridx, rw, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 11, 2, q_bits=q)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(w.cpu().numpy(), rw)
+    assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
+    _, ridx24, rw24, _ = oracle.fast_core_tensor_update(p["X"], F, lam, s, 11, 2)
+    assert not np.array_equal(rw24, rw)
+
+
 # FP64 with d >= 1024 and s >= 8 d solves by conjugate gradients (one
 # persistent launch; the Cholesky runs only when they do not converge).
 # info[2] = iterations, info[4] = 0 (no factorisation ran), info[3] the

@@ -138,3 +138,23 @@ def test_update_with_ridge_sampling_matches_oracle(tk, dims, ranks, s, aug, prec
     if precision != "f64":
         assert info[3].item() <= 1e-13, info
     assert elem_err(G.cpu().numpy(), Gr) <= (1e-10 if precision == "f64" else 1e-9)
+
+
+def test_ridge_sampling_cdf_bits(tk):
+    # tables of the ridge mixture with Q = 20: the update solves its own draws
+    # (checked against the oracle's solve) and they differ from the default Q's
+    dims, ranks, s = (23, 19, 17), (3, 4, 5), 6000
+    p = workloads.tucker_tensor(dims, ranks, 13, "f64", factor="gaussian", noise=("sigma", 0.1))
+    rng = np.random.default_rng(14)
+    F = [A + 0.1 * rng.standard_normal(A.shape) for A in p["factors_true"]]
+    lam = 0.5
+    X, FF = T(p["X"]), [T(A) for A in F]
+    G, idx, w = tk.core_update_sketched(X, FF, lam, s, seed=3, counter=1, precision="f64",
+                                        sampling="ridge", return_samples=True, cdf_bits=20)
+    _, idx0, w0 = tk.core_update_sketched(X, FF, lam, s, seed=3, counter=1, precision="f64",
+                                          sampling="ridge", return_samples=True)
+    assert not torch.equal(w, w0)
+    ii, ww = idx.cpu().numpy(), w.cpu().numpy()
+    assert all((ii[n] >= 0).all() and (ii[n] < dims[n]).all() for n in range(3))
+    Gr = oracle.core_update_sketched(p["X"], F, lam, ii, ww)
+    assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
