@@ -15,12 +15,14 @@
 //     each sample's rank among the block's samples of its key and a count
 //     table [key][block], an exclusive scan of that table, a scatter;
 //  2. B_k on v_mfma_f64_16x16x4, one workgroup per (group, lower 64 x 64
-//     tile of d' x d'), y_t formed in LDS per chunk of 32 samples of the
-//     group (in their original order, so every sum has a fixed order);
+//     tile of d' x d'), y_t formed from LDS per chunk of 32 or 64 samples of
+//     the group (in their original order, so every sum has a fixed order);
 //  3. M[p R_L + m][p' R_L + m'] = sum_k B_k[p][p'] e_k[m] e_k[m']
 //     + lambda prod_n P_n[..][..] on the lower triangle: a GEMM over the
-//     groups on the same MFMA, with the ridge term's Kronecker product in
-//     its epilogue.
+//     groups on v_mfma_f64_4x4x4_4b, with the ridge term's Kronecker product
+//     in its epilogue.
+// The right side and the residual of the solve are grouped the same way
+// (the vector kernels below).
 #include <string.h>
 
 #include <type_traits>
@@ -31,7 +33,7 @@ namespace tk {
 namespace {
 
 constexpr int kGt = 64;        // tile edge over d' (pass 2) and q-row block (pass 3)
-constexpr int kGkc = 32;       // samples (pass 2) or groups (pass 3) per LDS chunk
+constexpr int kGkc = 32;       // samples (quadrant pass 2, vectors) or groups (pass 3) per chunk
 constexpr int kGld = kGt + 1;  // padded LDS row
 constexpr int kScanPer = 16 * kBlock;  // count-table entries per scan workgroup
 
