@@ -129,6 +129,26 @@ def test_sketched_f64_matches_oracle(tk, dims, ranks):
     assert elem_err(G.cpu().numpy(), Gr) <= 1e-10
 
 
+# d = 6144, a multiple of 64 with more tiles per workgroup than stay on chip:
+# the CG kernel streams its tiles from memory every iteration.  The core must
+# solve its normal equations (the oracle's matrix-free residual on the same
+# samples) with CG converged and no factorisation run.
+def test_sketched_f64_cg_streamed_tiles(tk):
+    dims, ranks = (24, 24, 30), (16, 16, 24)
+    p, F = _sketch_case(dims, ranks, 8)
+    lam, d = 1e-3, 16 * 16 * 24
+    s = 8 * d
+    print(f"[cg streamed] dims {dims} ranks {ranks} s {s}", flush=True)
+    G, idx, w, info = tk.core_update_sketched(T(p["X"]), [T(A) for A in F], lam, s, seed=17,
+                                              counter=3, precision="f64", return_samples=True,
+                                              return_info=True)
+    info = info.cpu().numpy()
+    assert 1 <= info[2] < 64 and info[4] == 0.0 and info[3] <= 1e-12, info
+    res = oracle.normal_equation_residual(p["X"], F, lam, idx.cpu().numpy(), w.cpu().numpy(),
+                                          G.cpu().numpy())
+    assert res <= 1e-10, res
+
+
 # tk_sketch_opts.cdf_bits: the integer sampling weights ceil(l 2^Q) with another
 # Q; the draws must stay bit-exact with the oracle's tables of the same Q (and
 # differ from the default Q's, so the option reaches the sampler).
