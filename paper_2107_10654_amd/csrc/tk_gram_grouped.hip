@@ -337,12 +337,18 @@ __device__ inline void small_divmod(int p, int R, float rinv, int& q, int& r) {
   r = p - q * R;
 }
 template <int NR, int NL, int CK>
-__global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpArgs a) {
+__global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpArgs a,
+                                                                    int64_t nunits) {
   constexpr int CKP = CK + 2;       // transposed chunk stride
   extern __shared__ double rowT[];  // [S' + 1][CKP], then the 64 x kRld reduction tile
   __shared__ double ssc[CK];
-  const int64_t tau = blockIdx.x % a.ptiles;
-  const int64_t k = blockIdx.x / a.ptiles;
+  // workgroup ids go round-robin over the 8 XCDs; consecutive units (one
+  // group's tiles, which read the same sorted rows) are kept on one XCD
+  const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
+  const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (unit >= nunits) return;
+  const int64_t tau = unit % a.ptiles;
+  const int64_t k = unit / a.ptiles;
   int64_t ta, tb;
   tri_index(tau, ta, tb);
   const bool diag = ta == tb;
@@ -1100,9 +1106,10 @@ void launch_block_split(const Geom& gr, const GrpArgs& a, hipStream_t st) {
   if (lds > 65536)
     ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL, CK>),
                    static_cast<int>(lds));
+  const int64_t nunits = a.groups * a.ptiles;
   hipLaunchKernelGGL((grp_block_split_kernel<NR, NL, CK>),
-                     dim3(static_cast<unsigned>(a.groups * a.ptiles)), dim3(kBlock), lds, st, gr,
-                     a);
+                     dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)), dim3(kBlock), lds, st, gr,
+                     a, nunits);
 }
 template <int NR, int CK>
 void launch_block_split_nl(const Geom& gr, const GrpArgs& a, hipStream_t st) {
