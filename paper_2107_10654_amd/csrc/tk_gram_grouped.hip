@@ -906,9 +906,11 @@ __global__ __launch_bounds__(kBlock) void grp_vec_expand_kernel(GrpArgs a,
 }
 
 // ------------------------------------------------------------------ pass 3: M
-// Workgroup (row a of lower tile tau, block cb of 64 columns c = m R_L + m'):
-// out[b][c] = sum_k B_k[tau][a][b] e_k[m] e_k[m'] for b in [0, 64), the pairs
-// (p, p') = (64 ta + a, 64 tb + b).  Wave w takes quadrant (w / 2, w % 2) of
+// Workgroup (row a of lower tile tau, block cb of 64 columns c = m (m + 1) / 2 + m',
+// m' <= m): out[b][c] = sum_k B_k[tau][a][b] e_k[m] e_k[m'] for b in [0, 64), the
+// pairs (p, p') = (64 ta + a, 64 tb + b).  The sum is symmetric in (m, m'), so only
+// m' <= m is formed and, for p' < p, stored at both (p R_L + m, p' R_L + m') and
+// (p R_L + m', p' R_L + m).  Wave w takes quadrant (w / 2, w % 2) of
 // the 64 x 64 output on v_mfma_f64_4x4x4_4b (lane layout as in pass 2): per
 // k-step of 4 groups, 8 row operands (rows b = 4 r .. 4 r + 3 of the
 // quadrant, the same in all four blocks: B_k entries read straight from LDS)
@@ -919,6 +921,15 @@ __global__ __launch_bounds__(kBlock) void grp_vec_expand_kernel(GrpArgs a,
 // registers loaded during the previous chunk's products.  Workgroup ids are
 // spread so that the column blocks of one row, which read the same B_k
 // entries, run on one XCD (ids go round-robin over the 8 XCDs).  NE >= R_L / 8.
+// (m, m') with c = m (m + 1) / 2 + m', 0 <= m' <= m, for c < 2^20
+__device__ inline void pair_of(int c, int& m, int& mp) {
+  int i = static_cast<int>((sqrtf(8.0f * static_cast<float>(c) + 1.0f) - 1.0f) * 0.5f);
+  if ((i + 1) * (i + 2) / 2 <= c) ++i;
+  if (i * (i + 1) / 2 > c) --i;
+  m = i;
+  mp = c - i * (i + 1) / 2;
+}
+
 template <int NE>
 __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, int64_t nunits,
                                                             int ncb) {
@@ -939,11 +950,11 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int q = (lane >> 2) & 3, l4 = lane & 3, lk = lane >> 4;
   const int RL = a.RL;
-  const int rr = RL * RL;
+  const int nc = RL * (RL + 1) / 2;  // column pairs m' <= m
   const int qa = w >> 1, qc = w & 1;
   const bool diag = ta == tb;
   // quadrant rows b >= 32 qa; on a diagonal tile only b <= arow is stored
-  const bool active = !(diag && qa * 32 > arow) && cb * 64 + qc * 32 < rr;
+  const bool active = !(diag && qa * 32 > arow) && cb * 64 + qc * 32 < nc;
   const int blim = diag ? arow : kGt - 1;  // last row b needed
   // LDS indices (at k-step 0) of this lane's row and column operands
   int ia[8];
@@ -954,12 +965,8 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
 #pragma unroll
   for (int cc = 0; cc < 2; ++cc) {
     const int c = cb * 64 + qc * 32 + cc * 16 + 4 * q + l4;
-    int m, mp;
-    small_divmod(c, RL, rlinv, m, mp);
-    if (c >= rr) {  // the zero row
-      m = RL;
-      mp = 0;
-    }
+    int m = RL, mp = 0;  // the zero row past the last pair
+    if (c < nc) pair_of(c, m, mp);
     im[cc] = m * kEld + lk;
     imp[cc] = mp * kEld + lk;
   }
@@ -1002,27 +1009,37 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
       if (eofs[i] >= 0) esT[eofs[i]] = pe[i];
     __syncthreads();
     if (k0 + kGkc < a.groups) fetch(k0 + kGkc);
-    // PART: some rows of the quadrant lie above a diagonal tile's row a
-    auto ksteps = [&](auto part) __attribute__((always_inline)) {
+    // PART: some rows of the quadrant lie above a diagonal tile's row a;
+    // ONE: the quadrant's second 16 columns lie past the last pair
+    auto ksteps = [&](auto part, auto one) __attribute__((always_inline)) {
       constexpr bool PART = decltype(part)::value;
+      constexpr bool ONE = decltype(one)::value;
 #pragma unroll
       for (int ks = 0; ks < kGkc / 4; ++ks) {
         const double f0 = esT[im[0] + 4 * ks] * esT[imp[0] + 4 * ks];
-        const double f1 = esT[im[1] + 4 * ks] * esT[imp[1] + 4 * ks];
+        const double f1 = ONE ? 0.0 : esT[im[1] + 4 * ks] * esT[imp[1] + 4 * ks];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           if (PART && qa * 32 + 4 * r > blim) continue;
           const double av = (&as[0][0])[ia[r] + 4 * ks * kGld];
           acc[r][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, f0, acc[r][0], 0, 0, 0);
-          acc[r][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, f1, acc[r][1], 0, 0, 0);
+          if (!ONE) acc[r][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, f1, acc[r][1], 0, 0, 0);
         }
       }
     };
     if (active) {
-      if (qa * 32 + 28 <= blim)
-        ksteps(std::false_type{});
-      else
-        ksteps(std::true_type{});
+      const bool part = qa * 32 + 28 > blim;
+      if (cb * 64 + qc * 32 + 16 < nc) {
+        if (part)
+          ksteps(std::true_type{}, std::false_type{});
+        else
+          ksteps(std::false_type{}, std::false_type{});
+      } else {
+        if (part)
+          ksteps(std::true_type{}, std::true_type{});
+        else
+          ksteps(std::false_type{}, std::true_type{});
+      }
     }
     __syncthreads();
   }
@@ -1055,11 +1072,12 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc) {
       const int c = cb * 64 + qc * 32 + cc * 16 + 4 * q + l4;
-      if (c >= rr) continue;
+      if (c >= nc) continue;
       int m, mp;
-      small_divmod(c, RL, rlinv, m, mp);
-      if (pp == p && mp > m) continue;
+      pair_of(c, m, mp);
       a.M[(p * RL + m) * d + pp * RL + mp] = fma(pr, PL[m * RL + mp], acc[r][cc]);
+      if (pp < p && mp < m)
+        a.M[(p * RL + mp) * d + pp * RL + m] = fma(pr, PL[mp * RL + m], acc[r][cc]);
     }
   }
 }
@@ -1227,7 +1245,7 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
       default: launch_block<17>(gr, a, grid, lds, st); break;
     }
   }
-  const int ncb = static_cast<int>(cdiv(static_cast<int64_t>(gp.RL) * gp.RL, kGt));
+  const int ncb = static_cast<int>(cdiv(static_cast<int64_t>(gp.RL) * (gp.RL + 1) / 2, kGt));
   const int64_t nunits = gp.ptiles * kGt * ncb;
   switch (expand_ne(gp.RL)) {
     case 1: launch_expand<1>(gr, a, nunits, ncb, st); break;
