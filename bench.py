@@ -310,9 +310,10 @@ def main():
         # B_k, each group adds d(d+1)/2 to M (one multiply-add = 2 flops)
         dp = d // ranks[L]
         flops = float(s) * dp * (dp + 1) + float(dims[L]) * d * (d + 1)
-        kern = ("grouped FP64 Gram (grp_block_split_kernel, or grp_block_kernel beyond three "
-                "modes before the grouping mode, and grp_expand_kernel on FP64 MFMA, with the "
-                "sort and sorted-row kernels; time of the Gram stage)")
+        kern = ("grouped FP64 Gram (grp_block_split_kernel, in its pair form when two modes "
+                "precede the grouping mode, or grp_block_kernel beyond three, and "
+                "grp_expand_kernel on FP64 MFMA, with the sort and sorted-row kernels; time of "
+                "the Gram stage; flops counted as the algorithm's, not as executed)")
     else:
         flops = float(s) * d * (d + 1)
         kern = (f"gram_sk_kernel (stream-K Gram, {args.precision} operands, fp32 "

@@ -163,6 +163,7 @@ struct GrpArgs {
   double* M;            // d x d, lower triangle written
   int64_t nb, groups, dp, ptiles;
   int32_t L, RL, sp;    // sp = S' = sum_{n<L} R_n
+  int32_t tcn, n0, n1;  // pair form: column tiles, pairs of modes 0 and 1
 };
 
 // ------------------------------------------------------------------ pass 2: B_k
@@ -336,9 +337,24 @@ __device__ inline void small_divmod(int p, int R, float rinv, int& q, int& r) {
   q = static_cast<int>((static_cast<float>(p) + 0.5f) * rinv);
   r = p - q * R;
 }
-template <int NR, int NL, int CK>
+// (m, m') with c = m (m + 1) / 2 + m', 0 <= m' <= m, for c < 2^20
+__device__ inline void pair_of(int c, int& m, int& mp) {
+  int i = static_cast<int>((sqrtf(8.0f * static_cast<float>(c) + 1.0f) - 1.0f) * 0.5f);
+  if ((i + 1) * (i + 2) / 2 <= c) ++i;
+  if (i * (i + 1) / 2 > c) --i;
+  m = i;
+  mp = c - i * (i + 1) / 2;
+}
+
+// PAIR (NL = 2): with y_t = a_t (x) b_t (rows of modes 0 and 1), B_k[(r, s)][(r', s')]
+// = C_k[i0][i1] = sum_t w_t a_t[r] a_t[r'] b_t[s] b_t[s'] depends only on the
+// unordered pairs i0 = {r, r'} and i1 = {s, s'}, so the pass forms the n0 x n1
+// matrix C_k (no symmetry left) in tiles (tr, tc) = (tau / tcn, tau % tcn): the
+// operands are products of two entries of one mode instead of one of each mode.
+template <int NR, int NL, int CK, bool PAIR>
 __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpArgs a,
                                                                     int64_t nunits) {
+  static_assert(!PAIR || NL == 2, "the pair form takes two modes before L");
   constexpr int CKP = CK + 2;       // transposed chunk stride
   extern __shared__ double rowT[];  // [S' + 1][CKP], then the 64 x kRld reduction tile
   __shared__ double ssc[CK];
@@ -350,8 +366,13 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
   const int64_t tau = unit % a.ptiles;
   const int64_t k = unit / a.ptiles;
   int64_t ta, tb;
-  tri_index(tau, ta, tb);
-  const bool diag = ta == tb;
+  if (PAIR) {
+    ta = tau / a.tcn;
+    tb = tau % a.tcn;
+  } else {
+    tri_index(tau, ta, tb);
+  }
+  const bool diag = !PAIR && ta == tb;
   const int64_t g0 = a.cnt[k * a.nb], g1 = a.cnt[(k + 1) * a.nb];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int SP = a.sp;
@@ -360,8 +381,29 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
   const int u0 = w * (CK / 4) + (lane >> 4);
   // LDS indices (at sample u0) of the digits of this lane's operand rows
   int ia[4][NL], ib[4][NL];
+  // pair form: 16-row blocks of the tile that hold pairs
+  int nbi = 4, nbj = 4;
+  if (PAIR) {
+    const int li = a.n0 - static_cast<int>(ta) * kGt, lj = a.n1 - static_cast<int>(tb) * kGt;
+    nbi = li >= kGt ? 4 : (li + 15) / 16;
+    nbj = lj >= kGt ? 4 : (lj + 15) / 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int i0 = static_cast<int>(ta) * kGt + i * 16 + (lane & 15);
+      const int i1 = static_cast<int>(tb) * kGt + i * 16 + (lane & 15);
+      int r = 0, rp = 0, s2 = 0, sp2 = 0;
+      if (i0 < a.n0) pair_of(i0, r, rp);
+      if (i1 < a.n1) pair_of(i1, s2, sp2);
+      // the zero row past the last pair
+      ia[i][0] = (i0 < a.n0 ? g.soff[0] + r : SP) * CKP + u0;
+      ia[i][NL - 1] = (i0 < a.n0 ? g.soff[0] + rp : SP) * CKP + u0;
+      ib[i][0] = (i1 < a.n1 ? g.soff[1] + s2 : SP) * CKP + u0;
+      ib[i][NL - 1] = (i1 < a.n1 ? g.soff[1] + sp2 : SP) * CKP + u0;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    if (PAIR) break;
     const int pa = static_cast<int>(ta) * kGt + i * 16 + (lane & 15);
     const int pb = static_cast<int>(tb) * kGt + i * 16 + (lane & 15);
     const bool va = pa < a.dp, vb = pb < a.dp;
@@ -434,7 +476,7 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (!diag || i >= j)
+            if (PAIR ? (i < nbi && j < nbj) : (!diag || i >= j))
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
       }
     }
@@ -920,42 +962,49 @@ __global__ __launch_bounds__(kBlock) void grp_vec_expand_kernel(GrpArgs a,
 // rows e_k (transposed, with a zero row for the padded columns) go to LDS from
 // registers loaded during the previous chunk's products.  Workgroup ids are
 // spread so that the column blocks of one row, which read the same B_k
-// entries, run on one XCD (ids go round-robin over the 8 XCDs).  NE >= R_L / 8.
-// (m, m') with c = m (m + 1) / 2 + m', 0 <= m' <= m, for c < 2^20
-__device__ inline void pair_of(int c, int& m, int& mp) {
-  int i = static_cast<int>((sqrtf(8.0f * static_cast<float>(c) + 1.0f) - 1.0f) * 0.5f);
-  if ((i + 1) * (i + 2) / 2 <= c) ++i;
-  if (i * (i + 1) / 2 > c) --i;
-  m = i;
-  mp = c - i * (i + 1) / 2;
-}
-
-template <int NE>
-__global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, int64_t nunits,
-                                                            int ncb) {
+// entries, run on one XCD (ids go round-robin over the 8 XCDs), and each XCD
+// takes its rows in order.  NE >= R_L / 8.
+// PAIR: the B_k are the pair form's C_k; row a of tile (tr, tc) is the pair i0 =
+// {r >= r'} of mode 0 and the 64 operand rows b the pairs i1 = {s >= s'} of mode 1,
+// all needed (no triangle), and each sum, symmetric in s <-> s' and m <-> m', goes
+// to the up to four places (r, s1, m1; r', s2, m2) of M's lower triangle.
+template <int NE, bool PAIR>
+__global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, int ncb) {
   constexpr int kEld = kGkc + 2;  // transposed e_k stride
   __shared__ double as[kGkc][kGld];
   __shared__ double esT[(kMaxRank + 1) * kEld];
-  const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
-  const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (unit >= nunits) return;
-  const int cb = static_cast<int>(unit % ncb);
-  const int64_t qrow = unit / ncb;
-  const int64_t tau = qrow / kGt;
-  const int arow = static_cast<int>(qrow % kGt);
+  // ids go round-robin over the 8 XCDs: XCD x takes the rows q = x mod 8 in
+  // order, each with its ncb column blocks in a row
+  const int64_t j = blockIdx.x / 8;
+  const int cb = static_cast<int>(j % ncb);
+  const int64_t qrow = (j / ncb) * 8 + blockIdx.x % 8;
+  if (qrow >= a.ptiles * kGt) return;
   int64_t ta, tb;
-  tri_index(tau, ta, tb);
-  const int64_t p = ta * kGt + arow;
-  if (p >= a.dp) return;
+  int arow;
+  if (PAIR) {  // column-tile major: the ragged last column tile's rows come last
+    const int64_t trn = a.ptiles / a.tcn;
+    tb = qrow / (trn * kGt);
+    const int64_t rem = qrow % (trn * kGt);
+    ta = rem / kGt;
+    arow = static_cast<int>(rem % kGt);
+  } else {
+    tri_index(qrow / kGt, ta, tb);
+    arow = static_cast<int>(qrow % kGt);
+  }
+  const int64_t tau = PAIR ? ta * a.tcn + tb : qrow / kGt;
+  const int64_t p = ta * kGt + arow;  // PAIR: the pair index i0
+  if (p >= (PAIR ? a.n0 : a.dp)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int q = (lane >> 2) & 3, l4 = lane & 3, lk = lane >> 4;
   const int RL = a.RL;
   const int nc = RL * (RL + 1) / 2;  // column pairs m' <= m
   const int qa = w >> 1, qc = w & 1;
-  const bool diag = ta == tb;
-  // quadrant rows b >= 32 qa; on a diagonal tile only b <= arow is stored
-  const bool active = !(diag && qa * 32 > arow) && cb * 64 + qc * 32 < nc;
-  const int blim = diag ? arow : kGt - 1;  // last row b needed
+  const bool diag = !PAIR && ta == tb;
+  // last row b needed: on a diagonal tile b <= arow; in the pair form the pairs
+  const int blim = PAIR ? min(kGt - 1, a.n1 - 1 - static_cast<int>(tb) * kGt)
+                        : diag ? arow : kGt - 1;
+  // quadrant rows b >= 32 qa
+  const bool active = qa * 32 <= blim && cb * 64 + qc * 32 < nc;
   // LDS indices (at k-step 0) of this lane's row and column operands
   int ia[8];
 #pragma unroll
@@ -1049,6 +1098,40 @@ __global__ __launch_bounds__(kBlock) void grp_expand_kernel(Geom g, GrpArgs a, i
   // accumulator lane l: row l / 16, column l % 4 of block (l / 4) % 4
   const int64_t d = g.d;
   const double* PL = a.P + g.roff[a.L];
+  if (PAIR) {
+    const int R0 = g.ranks[0], R1 = g.ranks[1];
+    int r0, r0p;
+    pair_of(static_cast<int>(p), r0, r0p);
+    double lam = a.lambda;  // the modes after L: 1 x 1 P_n
+    for (int n = a.L + 1; n < g.order; ++n) lam *= a.P[g.roff[n]];
+    lam *= a.P[g.roff[0] + r0 * R0 + r0p];
+    const double* P1 = a.P + g.roff[1];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int i1 = static_cast<int>(tb) * kGt + qa * 32 + 4 * r + lk;
+      if (i1 >= a.n1) continue;
+      int s1, s1p;
+      pair_of(i1, s1, s1p);
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int c = cb * 64 + qc * 32 + cc * 16 + 4 * q + l4;
+        if (c >= nc) continue;
+        int m, mp;
+        pair_of(c, m, mp);
+        for (int o1 = 0; o1 < (s1 == s1p ? 1 : 2); ++o1) {
+          const int sa = o1 ? s1p : s1, sb = o1 ? s1 : s1p;
+          for (int o2 = 0; o2 < (m == mp ? 1 : 2); ++o2) {
+            const int ma = o2 ? mp : m, mb = o2 ? m : mp;
+            const int64_t row = static_cast<int64_t>(r0 * R1 + sa) * RL + ma;
+            const int64_t col = static_cast<int64_t>(r0p * R1 + sb) * RL + mb;
+            if (row < col) continue;
+            a.M[row * d + col] = fma(lam * P1[sa * R1 + sb], PL[ma * RL + mb], acc[r][cc]);
+          }
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int b = qa * 32 + 4 * r + lk;
@@ -1117,15 +1200,15 @@ template <int NR>
 void launch_block(const Geom& gr, const GrpArgs& a, unsigned grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL(grp_block_kernel<NR>, dim3(grid), dim3(kBlock), lds, st, gr, a);
 }
-template <int NR, int NL, int CK>
+template <int NR, int NL, int CK, bool PAIR = false>
 void launch_block_split(const Geom& gr, const GrpArgs& a, hipStream_t st) {
   const size_t lds =
       (static_cast<size_t>(a.sp + 1) * (CK + 2) + static_cast<size_t>(kGt) * kRld) * sizeof(double);
   if (lds > 65536)
-    ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL, CK>),
+    ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL, CK, PAIR>),
                    static_cast<int>(lds));
   const int64_t nunits = a.groups * a.ptiles;
-  hipLaunchKernelGGL((grp_block_split_kernel<NR, NL, CK>),
+  hipLaunchKernelGGL((grp_block_split_kernel<NR, NL, CK, PAIR>),
                      dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)), dim3(kBlock), lds, st, gr,
                      a, nunits);
 }
@@ -1133,14 +1216,22 @@ template <int NR, int CK>
 void launch_block_split_nl(const Geom& gr, const GrpArgs& a, hipStream_t st) {
   switch (a.L) {
     case 1: launch_block_split<NR, 1, CK>(gr, a, st); break;
-    case 2: launch_block_split<NR, 2, CK>(gr, a, st); break;
+    case 2:
+      if (a.tcn > 0)
+        launch_block_split<NR, 2, CK, true>(gr, a, st);
+      else
+        launch_block_split<NR, 2, CK>(gr, a, st);
+      break;
     default: launch_block_split<NR, 3, CK>(gr, a, st); break;
   }
 }
 template <int NE>
-void launch_expand(const Geom& gr, const GrpArgs& a, int64_t nunits, int ncb, hipStream_t st) {
-  hipLaunchKernelGGL(grp_expand_kernel<NE>, dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)),
-                     dim3(kBlock), 0, st, gr, a, nunits, ncb);
+void launch_expand(const Geom& gr, const GrpArgs& a, int ncb, bool pair, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(cdiv(a.ptiles * kGt, 8) * 8 * ncb));
+  if (pair)
+    hipLaunchKernelGGL((grp_expand_kernel<NE, true>), grid, dim3(kBlock), 0, st, gr, a, ncb);
+  else
+    hipLaunchKernelGGL((grp_expand_kernel<NE, false>), grid, dim3(kBlock), 0, st, gr, a, ncb);
 }
 
 }  // namespace
@@ -1174,6 +1265,17 @@ GroupedPlan plan_grouped(const Geom& gr, int64_t s, tk_dtype prec) {
   const double grouped = tile * (static_cast<double>(s) + static_cast<double>(gp.groups) * RL * RL);
   const double bbytes = tile * static_cast<double>(gp.groups) * 8.0;
   if (grouped * 3.0 > plain || bbytes > 4.0 * 1024 * 1024 * 1024) return gp;
+  if (L == 2) {  // the pair form, where it takes no more tiles
+    const int n0 = gr.ranks[0] * (gr.ranks[0] + 1) / 2, n1 = gr.ranks[1] * (gr.ranks[1] + 1) / 2;
+    const int64_t t0 = cdiv(n0, kGt), t1 = cdiv(n1, kGt);
+    if (t0 * t1 <= gp.ptiles) {
+      gp.pair = 1;
+      gp.n0 = n0;
+      gp.n1 = n1;
+      gp.tcn = static_cast<int32_t>(t1);
+      gp.ptiles = t0 * t1;
+    }
+  }
   gp.on = 1;
   return gp;
 }
@@ -1222,6 +1324,9 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
   a.L = gp.L;
   a.RL = gp.RL;
   a.sp = gp.sp;
+  a.tcn = gp.pair ? gp.tcn : 0;
+  a.n0 = gp.n0;
+  a.n1 = gp.n1;
   const unsigned grid = static_cast<unsigned>(gp.groups * gp.ptiles);
   const size_t lds = static_cast<size_t>(kGkc) * (gp.sp + 1) * sizeof(double);
   if (gp.L <= 3) {  // every wave the whole tile over a quarter of each chunk
@@ -1246,12 +1351,11 @@ void launch_grouped_gram(const Geom& gr, const GroupedPlan& gp, const int32_t* i
     }
   }
   const int ncb = static_cast<int>(cdiv(static_cast<int64_t>(gp.RL) * (gp.RL + 1) / 2, kGt));
-  const int64_t nunits = gp.ptiles * kGt * ncb;
   switch (expand_ne(gp.RL)) {
-    case 1: launch_expand<1>(gr, a, nunits, ncb, st); break;
-    case 2: launch_expand<2>(gr, a, nunits, ncb, st); break;
-    case 4: launch_expand<4>(gr, a, nunits, ncb, st); break;
-    default: launch_expand<8>(gr, a, nunits, ncb, st); break;
+    case 1: launch_expand<1>(gr, a, ncb, gp.pair != 0, st); break;
+    case 2: launch_expand<2>(gr, a, ncb, gp.pair != 0, st); break;
+    case 4: launch_expand<4>(gr, a, ncb, gp.pair != 0, st); break;
+    default: launch_expand<8>(gr, a, ncb, gp.pair != 0, st); break;
   }
 }
 

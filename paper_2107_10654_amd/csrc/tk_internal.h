@@ -175,6 +175,9 @@ struct GroupedPlan {
   int64_t nparts;  // scan partials of the count table
   int64_t ptiles;  // lower 64 x 64 tiles of d' x d'
   int32_t sp;      // S' = sum_{n<L} R_n: length of a sample's rows of the modes before L
+  // pair form (two modes before L): B_k kept as C_k[i0][i1], i0 and i1 the index
+  // pairs r >= r' of modes 0 and 1 (n0, n1 of them), in ptiles = tiles0 tcn tiles
+  int32_t pair, tcn, n0, n1;
 };
 // On for FP64 when d >= 256, R_L >= 2 and the grouped form needs clearly
 // fewer multiply-adds; gr is the row geometry (the augmented one for
