@@ -58,10 +58,13 @@ CASES = [
     ((18, 13, 11, 8), (10, 8, 7, 4), None),  # order 4, d = 2240: 256 tiles, ragged
     # FP64 Gram grouped by the last mode of rank >= 2 (d >= 256): d' = d / R_L
     # in 64-tiles; a trailing rank-1 mode with a mask, an order-2 problem with
-    # one d' tile and 64 groups, and R_L^2 = 144 over three 64-column blocks
-    ((40, 36, 30, 20), (16, 16, 8, 1), 0.3),  # d = 2048, L = 2, masked
+    # one d' tile and 64 groups, and R_L (R_L + 1) / 2 = 78 column pairs over
+    # two 64-column blocks.  Two modes before L take the pair form of B_k (pairs
+    # r >= r' of each mode) unless it needs more tiles than the lower triangle.
+    ((40, 36, 30, 20), (16, 16, 8, 1), 0.3),  # d = 2048, L = 2, masked, pair form
     ((70, 64), (64, 8), None),              # order 2, d = 512, d' = 64
-    ((30, 28, 26), (12, 12, 12), None),     # d = 1728, d' = 144: ragged tiles
+    ((30, 28, 26), (12, 12, 12), None),     # d = 1728, pair form: 78 x 78 pairs, ragged
+    ((40, 6, 30), (32, 2, 8), None),        # d = 512, 528 x 3 pairs: lower-triangle form
     ((8, 6, 6, 5, 6), (4, 3, 3, 2, 4), None),  # order 5: four modes before L, d' = 72
 ]
 
