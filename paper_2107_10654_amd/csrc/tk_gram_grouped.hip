@@ -358,18 +358,41 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
   constexpr int CKP = CK + 2;       // transposed chunk stride
   extern __shared__ double rowT[];  // [S' + 1][CKP], then the 64 x kRld reduction tile
   __shared__ double ssc[CK];
-  // workgroup ids go round-robin over the 8 XCDs; consecutive units (one
-  // group's tiles, which read the same sorted rows) are kept on one XCD
-  const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
-  const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (unit >= nunits) return;
-  const int64_t tau = unit % a.ptiles;
-  const int64_t k = unit / a.ptiles;
-  int64_t ta, tb;
+  // workgroup ids go round-robin over the 8 XCDs
+  int64_t k, tau, ta, tb;
   if (PAIR) {
-    ta = tau / a.tcn;
-    tb = tau % a.tcn;
+    // XCD x takes the groups k = x mod 8 (their sorted rows stay in its L2),
+    // tile by tile: the full tiles first, then those of the ragged last row or
+    // column tile, so that the light workgroups fill the end
+    const int64_t x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int64_t gx = (a.groups - x + 7) / 8;
+    if (j >= gx * a.ptiles) return;
+    const int64_t rk = j / gx;
+    k = x + 8 * (j % gx);
+    const int64_t tcn = a.tcn, trn = a.ptiles / a.tcn;
+    const int64_t h = (trn - 1) * (tcn - 1);
+    if (rk < h) {
+      ta = rk / (tcn - 1);
+      tb = rk % (tcn - 1);
+    } else if (rk < h + trn - 1) {
+      ta = rk - h;
+      tb = tcn - 1;
+    } else if (rk < h + trn - 1 + tcn - 1) {
+      ta = trn - 1;
+      tb = rk - h - (trn - 1);
+    } else {
+      ta = trn - 1;
+      tb = tcn - 1;
+    }
+    tau = ta * tcn + tb;
   } else {
+    // consecutive units (one group's tiles, which read the same sorted rows)
+    // are kept on one XCD
+    const int64_t per_xcd = static_cast<int64_t>(gridDim.x) / 8;
+    const int64_t unit = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (unit >= nunits) return;
+    tau = unit % a.ptiles;
+    k = unit / a.ptiles;
     tri_index(tau, ta, tb);
   }
   const bool diag = !PAIR && ta == tb;
@@ -484,22 +507,29 @@ __global__ __launch_bounds__(kBlock, 2) void grp_block_split_kernel(Geom g, GrpA
   }
   // ((acc_3 + acc_2) + acc_1) + acc_0 through one LDS tile; accumulator v of
   // lane l: row l / 16 + 4 v, column l % 16 of its 16 x 16 block
+  // (pair form: only the blocks that hold pairs; the expand pass reads no other)
   for (int src = 3; src >= 0; --src) {
     if (w == src) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+          if (PAIR && (i >= nbi || j >= nbj)) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int e = (i * 16 + (lane >> 4) + 4 * v) * kRld + j * 16 + (lane & 15);
             red[e] = src == 3 ? acc[i][j][v] : red[e] + acc[i][j][v];
           }
+        }
     }
     __syncthreads();
   }
   double* out = a.B + (k * a.ptiles + tau) * (kGt * kGt);
-  for (int e = tid; e < kGt * kGt; e += kBlock) out[e] = red[(e / kGt) * kRld + e % kGt];
+  const int nrow = 16 * nbi, ncol = 16 * nbj;
+  for (int e = tid; e < kGt * kGt; e += kBlock) {
+    const int r = e / kGt, c = e % kGt;
+    if (!PAIR || (r < nrow && c < ncol)) out[e] = red[r * kRld + c];
+  }
 }
 
 // x from another lane of the same 16-lane row (DPP control CTRL); the sum over
@@ -1208,9 +1238,10 @@ void launch_block_split(const Geom& gr, const GrpArgs& a, hipStream_t st) {
     ensure_dyn_lds(reinterpret_cast<const void*>(grp_block_split_kernel<NR, NL, CK, PAIR>),
                    static_cast<int>(lds));
   const int64_t nunits = a.groups * a.ptiles;
+  // the pair form's grid: 8 XCDs x (groups k = x mod 8) x tiles
+  const int64_t nwg = PAIR ? 8 * cdiv(a.groups, 8) * a.ptiles : cdiv(nunits, 8) * 8;
   hipLaunchKernelGGL((grp_block_split_kernel<NR, NL, CK, PAIR>),
-                     dim3(static_cast<unsigned>(cdiv(nunits, 8) * 8)), dim3(kBlock), lds, st, gr,
-                     a, nunits);
+                     dim3(static_cast<unsigned>(nwg)), dim3(kBlock), lds, st, gr, a, nunits);
 }
 template <int NR, int CK>
 void launch_block_split_nl(const Geom& gr, const GrpArgs& a, hipStream_t st) {
