@@ -115,6 +115,7 @@ GROUPED_SHAPES = [
     ((8, 6, 6, 5, 6), (4, 3, 3, 2, 4)),  # four modes before L: per-sample vectors
     ((44, 20, 5), (40, 17, 2)),         # d = 1360: V2 of 3 x 2 blocks (32-sample MFMA form)
     ((40, 6, 30), (32, 2, 8)),          # two modes before L, 528 x 3 pairs: lower-triangle B_k
+    ((20, 14, 10), (16, 12, 4)),        # pair form, 136 x 78 pairs: full and ragged tiles
 ]
 
 
